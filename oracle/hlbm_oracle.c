@@ -1,0 +1,1138 @@
+/*
+ * hlbm_oracle.c -- plain FP64 CPU oracle of the moving-grid hybrid lattice
+ * Boltzmann method (MG-HLBM), Di Ilio et al., arXiv 2006.13631.
+ *
+ * TEST INFRASTRUCTURE ONLY: see hlbm_oracle.h. Nothing here is tuned; every
+ * function is a direct, loop-by-loop statement of the passage it cites.
+ *
+ * Units: lattice spacing and structured time step are 1 (Delta x_s = Delta
+ * t_s = 1), reference density 1. D2Q9 with c_s^2 = 1/3 (Sec. 3, below
+ * Eq.(ulbe)); the paper does not print the weights, the standard D2Q9 set is
+ * used.
+ */
+#include "hlbm_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------ */
+/* D2Q9 velocity set: rest, 4 axis, 4 diagonal directions              */
+/* ------------------------------------------------------------------ */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double WT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                             1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double CS2 = 1.0 / 3.0; /* lattice speed of sound squared */
+
+void or_d2q9(int32_t cx[9], int32_t cy[9], double w[9]) {
+  for (int i = 0; i < 9; ++i) {
+    cx[i] = CX[i];
+    cy[i] = CY[i];
+    w[i] = WT[i];
+  }
+}
+
+/* Eq.(local_eq): second-order polynomial equilibrium. */
+void or_feq(double rho, double ux, double uy, double feq[9]) {
+  const double uu = ux * ux + uy * uy;
+  for (int i = 0; i < 9; ++i) {
+    const double cu = CX[i] * ux + CY[i] * uy;
+    feq[i] = WT[i] * rho *
+             (1.0 + cu / CS2 + (cu * cu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  }
+}
+
+/* density and velocity: the first two moments of f (text after Eq.(local_eq)) */
+static void moments(const double f[9], double *rho, double *ux, double *uy) {
+  double r = 0.0, mx = 0.0, my = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    r += f[i];
+    mx += CX[i] * f[i];
+    my += CY[i] * f[i];
+  }
+  *rho = r;
+  *ux = mx / r;
+  *uy = my / r;
+}
+
+/* ------------------------------------------------------------------ */
+/* Structured lattice, Eq.(LBE)                                        */
+/* ------------------------------------------------------------------ */
+static size_t lidx(int nx, int ny, int q, int x, int y) {
+  return ((size_t)q * (size_t)ny + (size_t)y) * (size_t)nx + (size_t)x;
+}
+
+static int wrap(int a, int n) { return ((a % n) + n) % n; }
+
+/* Streaming (left side of Eq.(LBE)) written in pull form: the population
+ * arriving at (x,y) along c_i left x - c_i one step earlier. Across a y wall
+ * (bc 0) it is the opposite population of the same node, reflected halfway;
+ * a wall moving with x-velocity uw adds 2 w_i rho0 c_i.u_w / c_s^2. */
+static void pull_node(const double *A, int nx, int ny, int bc, int x, int y,
+                      double u_bot, double u_top, double f[9]) {
+  for (int i = 0; i < 9; ++i) {
+    const int xs = wrap(x - CX[i], nx);
+    int ys = y - CY[i];
+    if (bc == OR_BC_PERIODIC) {
+      ys = wrap(ys, ny);
+    } else if (ys < 0 || ys >= ny) {
+      const double uw = (ys < 0) ? u_bot : u_top;
+      f[i] = A[lidx(nx, ny, OPP[i], x, y)] + 2.0 * WT[i] * 1.0 * (CX[i] * uw) / CS2;
+      continue;
+    }
+    f[i] = A[lidx(nx, ny, i, xs, ys)];
+  }
+}
+
+void or_lattice_step(const double *A, double *B, int32_t nx, int32_t ny,
+                     int32_t bc, double tau, double u_bot, double u_top,
+                     const uint8_t *disc) {
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      if (disc && !disc[(size_t)y * nx + x]) {
+        for (int i = 0; i < 9; ++i) B[lidx(nx, ny, i, x, y)] = A[lidx(nx, ny, i, x, y)];
+        continue;
+      }
+      double f[9], feq[9], rho, ux, uy;
+      pull_node(A, nx, ny, bc, x, y, u_bot, u_top, f);
+      moments(f, &rho, &ux, &uy);
+      or_feq(rho, ux, uy, feq);
+      /* Eq.(LBE) with Delta t_s = 1: relax toward equilibrium */
+      for (int i = 0; i < 9; ++i)
+        B[lidx(nx, ny, i, x, y)] = f[i] - (1.0 / tau) * (f[i] - feq[i]);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Triangular body-fitted grid and its finite-volume matrices          */
+/* ------------------------------------------------------------------ */
+#define KCAP 16 /* neighbour slots per node (self included) */
+
+struct or_mesh {
+  int nnode, ntri;
+  double *x, *y; /* node coordinates, local frame */
+  int *type;     /* OR_NODE_* */
+  int *tri;      /* [ntri][3] */
+  double *txy;   /* [ntri][3][2] vertex coordinates (unwrapped) */
+  /* stencil: per node up to KCAP neighbours, slot 0 = the node itself */
+  int *nk;       /* [nnode] */
+  int *nbr;      /* [nnode][KCAP] */
+  double *S;     /* [nnode][9][KCAP] streaming matrix S_ik */
+  double *C;     /* [nnode][KCAP] collision matrix C_ik */
+  double *V;     /* [nnode] control-volume area */
+  /* wall edges (force) */
+  int nwe;
+  int *we;       /* [nwe][2] */
+  double *wn;    /* [nwe][2] unit normal pointing out of the body */
+  double *wl;    /* [nwe] length */
+  /* bucket grid for point location */
+  double bx0, by0, bh;
+  int bnx, bny;
+  int *bstart, *blist;
+  /* lamina geometry (local frame) */
+  double b, T;
+};
+
+static void *xcalloc(size_t n, size_t sz) { return calloc(n ? n : 1, sz); }
+
+void or_mesh_free(or_mesh *m) {
+  if (!m) return;
+  free(m->x); free(m->y); free(m->type); free(m->tri); free(m->txy);
+  free(m->nk); free(m->nbr); free(m->S); free(m->C); free(m->V);
+  free(m->we); free(m->wn); free(m->wl); free(m->bstart); free(m->blist);
+  free(m);
+}
+
+int32_t or_mesh_nnode(const or_mesh *m) { return m->nnode; }
+int32_t or_mesh_ntri(const or_mesh *m) { return m->ntri; }
+int32_t or_mesh_kmax(const or_mesh *m) {
+  int k = 0;
+  for (int p = 0; p < m->nnode; ++p)
+    if (m->nk[p] > k) k = m->nk[p];
+  return k;
+}
+
+void or_mesh_nodes(const or_mesh *m, double *x, double *y, int32_t *type) {
+  for (int p = 0; p < m->nnode; ++p) {
+    if (x) x[p] = m->x[p];
+    if (y) y[p] = m->y[p];
+    if (type) type[p] = m->type[p];
+  }
+}
+
+void or_mesh_triangles(const or_mesh *m, int32_t *tri, double *txy) {
+  for (int t = 0; t < m->ntri; ++t)
+    for (int a = 0; a < 3; ++a) {
+      if (tri) tri[3 * t + a] = m->tri[3 * t + a];
+      if (txy) {
+        txy[6 * t + 2 * a] = m->txy[6 * t + 2 * a];
+        txy[6 * t + 2 * a + 1] = m->txy[6 * t + 2 * a + 1];
+      }
+    }
+}
+
+/* barycentric coordinates of (px,py) in the triangle with vertices v[3][2] */
+static void bary(const double *v, double px, double py, double lam[3]) {
+  const double x0 = v[0], y0 = v[1], x1 = v[2], y1 = v[3], x2 = v[4], y2 = v[5];
+  const double d = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
+  lam[1] = ((px - x0) * (y2 - y0) - (x2 - x0) * (py - y0)) / d;
+  lam[2] = ((x1 - x0) * (py - y0) - (px - x0) * (y1 - y0)) / d;
+  lam[0] = 1.0 - lam[1] - lam[2];
+}
+
+typedef struct { int lo, hi, slot; } edge_t;
+
+static int edge_cmp(const void *x, const void *y) {
+  const edge_t *a = (const edge_t *)x, *b = (const edge_t *)y;
+  if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+  if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+  return a->slot < b->slot ? -1 : (a->slot > b->slot);
+}
+
+static int slot_of(or_mesh *m, int p, int q) {
+  for (int k = 0; k < m->nk[p]; ++k)
+    if (m->nbr[p * KCAP + k] == q) return k;
+  return -1;
+}
+
+static int add_nbr(or_mesh *m, int p, int q) {
+  int s = slot_of(m, p, q);
+  if (s >= 0) return s;
+  if (m->nk[p] >= KCAP) return -1;
+  m->nbr[p * KCAP + m->nk[p]] = q;
+  return m->nk[p]++;
+}
+
+/* Median-dual control volume of each node (centroids joined to edge
+ * midpoints; closed by half-edges where the grid ends), f linear on each
+ * triangle. Reading of S_ik and C_ik, which the paper cites but does not give
+ * (Sec. 3, after Eq.(ulbe)):
+ *   S_ik = -(1/V_P) * (coefficient of f(P_k) in the outflow of population i
+ *           through the boundary of the control volume of P),
+ *   C_ik =  (1/V_P) * integral over the control volume of the linear shape
+ *           function of P_k.
+ * Both integrals are exact for piecewise-linear f. */
+static int assemble(or_mesh *m) {
+  const int N = m->nnode;
+  m->nk = xcalloc(N, sizeof(int));
+  m->nbr = xcalloc((size_t)N * KCAP, sizeof(int));
+  m->S = xcalloc((size_t)N * 9 * KCAP, sizeof(double));
+  m->C = xcalloc((size_t)N * KCAP, sizeof(double));
+  m->V = xcalloc(N, sizeof(double));
+  if (!m->nk || !m->nbr || !m->S || !m->C || !m->V) return OR_E_NOMEM;
+  for (int p = 0; p < N; ++p) {
+    for (int k = 0; k < KCAP; ++k) m->nbr[p * KCAP + k] = -1;
+    add_nbr(m, p, p); /* slot 0: the pivotal node itself (k = 0 in Eq.(ulbe)) */
+  }
+  for (int t = 0; t < m->ntri; ++t)
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c)
+        if (add_nbr(m, m->tri[3 * t + a], m->tri[3 * t + c]) < 0) return OR_E_ARG;
+
+  double *Sacc = m->S, *Cacc = m->C;
+  for (int t = 0; t < m->ntri; ++t) {
+    const int *v = &m->tri[3 * t];
+    const double *p = &m->txy[6 * t];
+    const double area = 0.5 * ((p[2] - p[0]) * (p[5] - p[1]) - (p[4] - p[0]) * (p[3] - p[1]));
+    if (!(area > 0.0)) return OR_E_ARG;
+    const double gx = (p[0] + p[2] + p[4]) / 3.0, gy = (p[1] + p[3] + p[5]) / 3.0;
+    for (int a = 0; a < 3; ++a) m->V[v[a]] += area / 3.0;
+
+    /* collision matrix: integrate each shape function over the part of the
+     * control volume of vertex a inside this triangle, the quadrilateral
+     * (a, mid(a,b), centroid, mid(a,c)), split into two triangles. A linear
+     * function integrates to area * mean of its vertex values. */
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      const double ax = p[2 * a], ay = p[2 * a + 1];
+      const double mbx = 0.5 * (ax + p[2 * b]), mby = 0.5 * (ay + p[2 * b + 1]);
+      const double mcx = 0.5 * (ax + p[2 * c]), mcy = 0.5 * (ay + p[2 * c + 1]);
+      const double sub[2][6] = {{ax, ay, mbx, mby, gx, gy}, {ax, ay, gx, gy, mcx, mcy}};
+      for (int s = 0; s < 2; ++s) {
+        const double *q = sub[s];
+        const double sa = 0.5 * fabs((q[2] - q[0]) * (q[5] - q[1]) - (q[4] - q[0]) * (q[3] - q[1]));
+        double lsum[3] = {0.0, 0.0, 0.0};
+        for (int r = 0; r < 3; ++r) {
+          double lam[3];
+          bary(p, q[2 * r], q[2 * r + 1], lam);
+          for (int j = 0; j < 3; ++j) lsum[j] += lam[j];
+        }
+        for (int j = 0; j < 3; ++j)
+          Cacc[v[a] * KCAP + slot_of(m, v[a], v[j])] += sa * lsum[j] / 3.0;
+      }
+    }
+
+    /* streaming matrix, interior faces: the face between the control volumes
+     * of vertices a and b inside this triangle runs from mid(a,b) to the
+     * centroid. Outflow of population i from the volume of a through it is
+     * (c_i . n) * length * f(face midpoint), n pointing from a toward b. */
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3;
+      const double mx = 0.5 * (p[2 * a] + p[2 * b]), my = 0.5 * (p[2 * a + 1] + p[2 * b + 1]);
+      double nlx = gy - my, nly = -(gx - mx); /* normal scaled by face length */
+      if (nlx * (p[2 * b] - p[2 * a]) + nly * (p[2 * b + 1] - p[2 * a + 1]) < 0.0) {
+        nlx = -nlx;
+        nly = -nly;
+      }
+      double lam[3];
+      bary(p, 0.5 * (mx + gx), 0.5 * (my + gy), lam);
+      for (int i = 0; i < 9; ++i) {
+        const double cn = CX[i] * nlx + CY[i] * nly;
+        for (int j = 0; j < 3; ++j) {
+          Sacc[((size_t)v[a] * 9 + i) * KCAP + slot_of(m, v[a], v[j])] -= cn * lam[j];
+          Sacc[((size_t)v[b] * 9 + i) * KCAP + slot_of(m, v[b], v[j])] += cn * lam[j];
+        }
+      }
+    }
+  }
+
+  /* boundary faces: an edge that belongs to one triangle only ends the grid.
+   * Each of its end nodes closes its control volume with the half of the edge
+   * next to it; f along it is linear between the two end nodes. */
+  int nwe = 0;
+  int *edge_count = xcalloc((size_t)m->ntri * 3, sizeof(int));
+  edge_t *edges = xcalloc((size_t)m->ntri * 3, sizeof(edge_t));
+  if (!edge_count || !edges) return OR_E_NOMEM;
+  for (int t = 0; t < m->ntri; ++t)
+    for (int e = 0; e < 3; ++e) {
+      const int a = m->tri[3 * t + e], b = m->tri[3 * t + (e + 1) % 3];
+      edge_t *E = &edges[3 * t + e];
+      E->lo = a < b ? a : b;
+      E->hi = a < b ? b : a;
+      E->slot = 3 * t + e;
+    }
+  qsort(edges, (size_t)m->ntri * 3, sizeof(edge_t), edge_cmp);
+  for (size_t r = 0; r < (size_t)m->ntri * 3;) {
+    size_t q = r;
+    while (q < (size_t)m->ntri * 3 && edges[q].lo == edges[r].lo && edges[q].hi == edges[r].hi) ++q;
+    for (size_t u = r; u < q; ++u) edge_count[edges[u].slot] = (int)(q - r - 1);
+    r = q;
+  }
+  free(edges);
+  for (int t = 0; t < m->ntri; ++t)
+    for (int e = 0; e < 3; ++e) {
+      const int a = m->tri[3 * t + e], b = m->tri[3 * t + (e + 1) % 3];
+      if (edge_count[3 * t + e] == 0 && m->type[a] == OR_NODE_WALL && m->type[b] == OR_NODE_WALL) ++nwe;
+    }
+  m->nwe = nwe;
+  m->we = xcalloc((size_t)2 * nwe, sizeof(int));
+  m->wn = xcalloc((size_t)2 * nwe, sizeof(double));
+  m->wl = xcalloc(nwe, sizeof(double));
+  int w = 0;
+  for (int t = 0; t < m->ntri; ++t) {
+    const double *p = &m->txy[6 * t];
+    for (int e = 0; e < 3; ++e) {
+      if (edge_count[3 * t + e] != 0) continue;
+      const int ea = e, eb = (e + 1) % 3, ec = (e + 2) % 3;
+      const int a = m->tri[3 * t + ea], b = m->tri[3 * t + eb];
+      const double ex = p[2 * eb] - p[2 * ea], ey = p[2 * eb + 1] - p[2 * ea + 1];
+      double nlx = ey, nly = -ex; /* outward normal of the grid, scaled by length */
+      if (nlx * (p[2 * ec] - p[2 * ea]) + nly * (p[2 * ec + 1] - p[2 * ea + 1]) > 0.0) {
+        nlx = -nlx;
+        nly = -nly;
+      }
+      const int ends[2] = {ea, eb};
+      for (int s = 0; s < 2; ++s) {
+        const int me = ends[s], other = ends[1 - s];
+        const int node = m->tri[3 * t + me];
+        /* half edge from this end to the edge midpoint; its midpoint sits at
+         * 3/4 of the way from the other end */
+        double lam[3];
+        bary(p, 0.75 * p[2 * me] + 0.25 * p[2 * other], 0.75 * p[2 * me + 1] + 0.25 * p[2 * other + 1], lam);
+        for (int i = 0; i < 9; ++i) {
+          const double cn = 0.5 * (CX[i] * nlx + CY[i] * nly);
+          for (int j = 0; j < 3; ++j)
+            Sacc[((size_t)node * 9 + i) * KCAP + slot_of(m, node, m->tri[3 * t + j])] -= cn * lam[j];
+        }
+      }
+      if (m->type[a] == OR_NODE_WALL && m->type[b] == OR_NODE_WALL) {
+        const double len = sqrt(ex * ex + ey * ey);
+        m->we[2 * w] = a;
+        m->we[2 * w + 1] = b;
+        m->wn[2 * w] = -nlx / len; /* the body lies outside the grid */
+        m->wn[2 * w + 1] = -nly / len;
+        m->wl[w] = len;
+        ++w;
+      }
+    }
+  }
+  free(edge_count);
+
+  for (int p = 0; p < N; ++p) {
+    if (!(m->V[p] > 0.0)) return OR_E_ARG;
+    for (int k = 0; k < m->nk[p]; ++k) {
+      m->C[p * KCAP + k] /= m->V[p];
+      for (int i = 0; i < 9; ++i) m->S[((size_t)p * 9 + i) * KCAP + k] /= m->V[p];
+    }
+  }
+  return OR_OK;
+}
+
+/* bucket grid: each triangle is listed in every unit bucket its bounding box
+ * touches, in increasing triangle order */
+static int build_buckets(or_mesh *m) {
+  double x0 = 1e300, y0 = 1e300, x1 = -1e300, y1 = -1e300;
+  for (int t = 0; t < m->ntri; ++t)
+    for (int a = 0; a < 3; ++a) {
+      const double px = m->txy[6 * t + 2 * a], py = m->txy[6 * t + 2 * a + 1];
+      if (px < x0) x0 = px;
+      if (px > x1) x1 = px;
+      if (py < y0) y0 = py;
+      if (py > y1) y1 = py;
+    }
+  m->bh = 1.0;
+  m->bx0 = x0;
+  m->by0 = y0;
+  m->bnx = (int)floor((x1 - x0) / m->bh) + 1;
+  m->bny = (int)floor((y1 - y0) / m->bh) + 1;
+  const size_t nb = (size_t)m->bnx * m->bny;
+  int *count = xcalloc(nb + 1, sizeof(int));
+  m->bstart = xcalloc(nb + 1, sizeof(int));
+  if (!count || !m->bstart) return OR_E_NOMEM;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      m->bstart[0] = 0;
+      for (size_t i = 0; i < nb; ++i) m->bstart[i + 1] = m->bstart[i] + count[i];
+      m->blist = xcalloc((size_t)m->bstart[nb], sizeof(int));
+      if (!m->blist) return OR_E_NOMEM;
+      memset(count, 0, nb * sizeof(int));
+    }
+    for (int t = 0; t < m->ntri; ++t) {
+      double tx0 = 1e300, ty0 = 1e300, tx1 = -1e300, ty1 = -1e300;
+      for (int a = 0; a < 3; ++a) {
+        const double px = m->txy[6 * t + 2 * a], py = m->txy[6 * t + 2 * a + 1];
+        if (px < tx0) tx0 = px;
+        if (px > tx1) tx1 = px;
+        if (py < ty0) ty0 = py;
+        if (py > ty1) ty1 = py;
+      }
+      int i0 = (int)floor((tx0 - m->bx0) / m->bh) - 1, i1 = (int)floor((tx1 - m->bx0) / m->bh) + 1;
+      int j0 = (int)floor((ty0 - m->by0) / m->bh) - 1, j1 = (int)floor((ty1 - m->by0) / m->bh) + 1;
+      if (i0 < 0) i0 = 0;
+      if (j0 < 0) j0 = 0;
+      if (i1 >= m->bnx) i1 = m->bnx - 1;
+      if (j1 >= m->bny) j1 = m->bny - 1;
+      for (int j = j0; j <= j1; ++j)
+        for (int i = i0; i <= i1; ++i) {
+          const size_t bi = (size_t)j * m->bnx + i;
+          if (pass == 1) m->blist[m->bstart[bi] + count[bi]] = t;
+          ++count[bi];
+        }
+    }
+  }
+  free(count);
+  return OR_OK;
+}
+
+/* Point location with a closed inside test; a point on a shared edge goes to
+ * the lowest-numbered triangle (triangles are numbered by cell, row-major,
+ * lower triangle first). Interpolation is continuous, so the choice only
+ * changes rounding. */
+int32_t or_mesh_locate(const or_mesh *m, double px, double py, double lam[3]) {
+  const double tol = 1e-12;
+  const int bi = (int)floor((px - m->bx0) / m->bh), bj = (int)floor((py - m->by0) / m->bh);
+  if (bi < 0 || bj < 0 || bi >= m->bnx || bj >= m->bny) return -1;
+  const size_t b = (size_t)bj * m->bnx + bi;
+  for (int s = m->bstart[b]; s < m->bstart[b + 1]; ++s) {
+    const int t = m->blist[s];
+    double l[3];
+    bary(&m->txy[6 * t], px, py, l);
+    if (l[0] >= -tol && l[1] >= -tol && l[2] >= -tol) {
+      lam[0] = l[0];
+      lam[1] = l[1];
+      lam[2] = l[2];
+      return t;
+    }
+  }
+  return -1;
+}
+
+/* quad split into two triangles; the diagonal direction is mirrored about the
+ * vertical centre line of the grid so the grid is left-right symmetric */
+static void add_cell(or_mesh *m, int *nt, int n00, int n10, int n01, int n11,
+                     double x0, double y0, double h, int diag_up) {
+  const double X[4] = {x0, x0 + h, x0, x0 + h}, Y[4] = {y0, y0, y0 + h, y0 + h};
+  const int id[4] = {n00, n10, n01, n11};
+  int tris[2][3];
+  if (diag_up) { /* diagonal from (0,0) to (1,1) */
+    tris[0][0] = 0; tris[0][1] = 1; tris[0][2] = 3;
+    tris[1][0] = 0; tris[1][1] = 3; tris[1][2] = 2;
+  } else { /* diagonal from (1,0) to (0,1) */
+    tris[0][0] = 0; tris[0][1] = 1; tris[0][2] = 2;
+    tris[1][0] = 1; tris[1][1] = 3; tris[1][2] = 2;
+  }
+  for (int s = 0; s < 2; ++s) {
+    for (int a = 0; a < 3; ++a) {
+      m->tri[3 * (*nt) + a] = id[tris[s][a]];
+      m->txy[6 * (*nt) + 2 * a] = X[tris[s][a]];
+      m->txy[6 * (*nt) + 2 * a + 1] = Y[tris[s][a]];
+    }
+    ++(*nt);
+  }
+}
+
+static or_mesh *mesh_alloc(int nnode, int maxtri) {
+  or_mesh *m = xcalloc(1, sizeof(or_mesh));
+  if (!m) return NULL;
+  m->nnode = nnode;
+  m->x = xcalloc(nnode, sizeof(double));
+  m->y = xcalloc(nnode, sizeof(double));
+  m->type = xcalloc(nnode, sizeof(int));
+  m->tri = xcalloc((size_t)3 * maxtri, sizeof(int));
+  m->txy = xcalloc((size_t)6 * maxtri, sizeof(double));
+  if (!m->x || !m->y || !m->type || !m->tri || !m->txy) {
+    or_mesh_free(m);
+    return NULL;
+  }
+  return m;
+}
+
+static or_mesh *mesh_finish(or_mesh *m) {
+  if (assemble(m) != OR_OK || build_buckets(m) != OR_OK) {
+    or_mesh_free(m);
+    return NULL;
+  }
+  return m;
+}
+
+/* Body-fitted grid around the lamina: nux*nuy nodes with spacing h; node
+ * (i,j) at local x = (i - nux/2) h, y = (j - (nuy-1)/2) h (lamina centre at
+ * the origin). The lamina, of width b and thickness h, fills the slot between
+ * rows nuy/2-1 and nuy/2 for |x| <= b/2; those cells are not meshed. Nodes on
+ * the slot boundary are wall nodes, nodes on the outer boundary are
+ * interpolation nodes (Sec. Refill procedure), the rest discretization. */
+or_mesh *or_mesh_lamina(int32_t nux, int32_t nuy, double h, double b) {
+  if (nux < 4 || nuy < 4 || (nuy % 2) != 0 || !(h > 0.0) || b < 0.0) return NULL;
+  or_mesh *m = mesh_alloc(nux * nuy, 2 * (nux - 1) * (nuy - 1));
+  if (!m) return NULL;
+  m->b = b;
+  m->T = (b > 0.0) ? h : 0.0;
+  const double half = 0.5 * b + 1e-9 * h;
+  for (int j = 0; j < nuy; ++j)
+    for (int i = 0; i < nux; ++i) {
+      const int p = j * nux + i;
+      m->x[p] = (double)(i - nux / 2) * h;
+      m->y[p] = ((double)j - 0.5 * (double)(nuy - 1)) * h;
+      if (b > 0.0 && (j == nuy / 2 - 1 || j == nuy / 2) && fabs(m->x[p]) <= half)
+        m->type[p] = OR_NODE_WALL;
+      else if (i == 0 || j == 0 || i == nux - 1 || j == nuy - 1)
+        m->type[p] = OR_NODE_INTERFACE;
+      else
+        m->type[p] = OR_NODE_INTERIOR;
+    }
+  int nt = 0;
+  for (int cj = 0; cj < nuy - 1; ++cj)
+    for (int ci = 0; ci < nux - 1; ++ci) {
+      const double x0 = (double)(ci - nux / 2) * h, y0 = ((double)cj - 0.5 * (double)(nuy - 1)) * h;
+      if (b > 0.0 && cj == nuy / 2 - 1 && x0 >= -half && x0 + h <= half) continue; /* inside the lamina */
+      const int n00 = cj * nux + ci;
+      add_cell(m, &nt, n00, n00 + 1, n00 + nux, n00 + nux + 1, x0, y0, h, (x0 + 0.5 * h) < 0.0);
+    }
+  m->ntri = nt;
+  return mesh_finish(m);
+}
+
+or_mesh *or_mesh_periodic(int32_t nx, int32_t ny, double h) {
+  if (nx < 3 || ny < 3 || !(h > 0.0)) return NULL;
+  or_mesh *m = mesh_alloc(nx * ny, 2 * nx * ny);
+  if (!m) return NULL;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      m->x[j * nx + i] = i * h;
+      m->y[j * nx + i] = j * h;
+      m->type[j * nx + i] = OR_NODE_INTERIOR;
+    }
+  int nt = 0;
+  for (int cj = 0; cj < ny; ++cj)
+    for (int ci = 0; ci < nx; ++ci) {
+      const int i1 = (ci + 1) % nx, j1 = (cj + 1) % ny;
+      add_cell(m, &nt, cj * nx + ci, cj * nx + i1, j1 * nx + ci, j1 * nx + i1, ci * h, cj * h, h,
+               (ci + 0.5) < 0.5 * nx);
+    }
+  m->ntri = nt;
+  return mesh_finish(m);
+}
+
+or_mesh *or_mesh_channel(int32_t nx, int32_t ny, double h) {
+  if (nx < 3 || ny < 3 || !(h > 0.0)) return NULL;
+  or_mesh *m = mesh_alloc(nx * ny, 2 * nx * (ny - 1));
+  if (!m) return NULL;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      m->x[j * nx + i] = i * h;
+      m->y[j * nx + i] = j * h;
+      m->type[j * nx + i] = (j == 0 || j == ny - 1) ? OR_NODE_WALL : OR_NODE_INTERIOR;
+    }
+  int nt = 0;
+  for (int cj = 0; cj < ny - 1; ++cj)
+    for (int ci = 0; ci < nx; ++ci) {
+      const int i1 = (ci + 1) % nx;
+      add_cell(m, &nt, cj * nx + ci, cj * nx + i1, (cj + 1) * nx + ci, (cj + 1) * nx + i1, ci * h,
+               cj * h, h, (ci + 0.5) < 0.5 * nx);
+    }
+  m->ntri = nt;
+  return mesh_finish(m);
+}
+
+void or_mesh_stencil(const or_mesh *m, int32_t kmax, int32_t *nbr, double *S,
+                     double *C, double *V) {
+  for (int p = 0; p < m->nnode; ++p) {
+    for (int k = 0; k < kmax; ++k) {
+      const int in = k < m->nk[p] && k < KCAP;
+      if (nbr) nbr[p * kmax + k] = in ? m->nbr[p * KCAP + k] : -1;
+      if (C) C[p * kmax + k] = in ? m->C[p * KCAP + k] : 0.0;
+      for (int i = 0; i < 9; ++i)
+        if (S) S[((size_t)p * 9 + i) * kmax + k] = in ? m->S[((size_t)p * 9 + i) * KCAP + k] : 0.0;
+    }
+    if (V) V[p] = m->V[p];
+  }
+}
+
+/* Eq.(ulbe) for discretization and wall nodes, Eq.(postcollision2_u) for
+ * interpolation (interface) nodes, one forward-Euler sub-step of dt_u with all
+ * right-hand sides at the old level (Jacobi: fout is a separate buffer).
+ *
+ * Eq.(postcollision2_u): the star quantities are the structured-derived ones
+ * (f^eq,s and (1 - 1/(2 tau_s)) f^neq,s, passed in star_eq / star_neq) when
+ * the neighbour is an interpolation node, and the grid's own f^eq, f^neq
+ * otherwise; the leading term is the star value of the node itself.
+ *
+ * Wall nodes (reading; the paper states the rule for the refill only, Sec.
+ * Refill procedure): after the Eq.(ulbe) update over the control volume closed
+ * along the wall, the velocity is set to the wall velocity while the density
+ * and the non-equilibrium part are kept: f <- f^eq(rho, u_w) + (f - f^eq(rho, u)). */
+void or_fv_substep(const or_mesh *m, const double *f, const double *star_eq,
+                   const double *star_neq, double *fout, double tau_u,
+                   double dt_u, const double *uwx, const double *uwy) {
+  const int N = m->nnode;
+  double *feq = malloc((size_t)9 * N * sizeof(double));
+  for (int p = 0; p < N; ++p) {
+    double fp[9], e[9], rho, ux, uy;
+    for (int i = 0; i < 9; ++i) fp[i] = f[(size_t)i * N + p];
+    moments(fp, &rho, &ux, &uy);
+    or_feq(rho, ux, uy, e);
+    for (int i = 0; i < 9; ++i) feq[(size_t)i * N + p] = e[i];
+  }
+  for (int p = 0; p < N; ++p) {
+    const int iface = (m->type[p] == OR_NODE_INTERFACE);
+    double out[9];
+    for (int i = 0; i < 9; ++i) {
+      double sum_s = 0.0, sum_c = 0.0, self;
+      if (iface) self = star_eq[(size_t)i * N + p] + star_neq[(size_t)i * N + p];
+      else self = f[(size_t)i * N + p];
+      for (int k = 0; k < m->nk[p]; ++k) {
+        const int q = m->nbr[p * KCAP + k];
+        double fq, nq;
+        if (iface && m->type[q] == OR_NODE_INTERFACE) {
+          fq = star_eq[(size_t)i * N + q] + star_neq[(size_t)i * N + q];
+          nq = star_neq[(size_t)i * N + q];
+        } else {
+          fq = f[(size_t)i * N + q];
+          nq = f[(size_t)i * N + q] - feq[(size_t)i * N + q];
+        }
+        sum_s += m->S[((size_t)p * 9 + i) * KCAP + k] * fq;
+        sum_c += m->C[p * KCAP + k] * nq;
+      }
+      out[i] = self + dt_u * sum_s - (dt_u / tau_u) * sum_c;
+    }
+    if (m->type[p] == OR_NODE_WALL) {
+      double rho, ux, uy, e[9], ew[9];
+      moments(out, &rho, &ux, &uy);
+      or_feq(rho, ux, uy, e);
+      or_feq(rho, uwx[p], uwy[p], ew);
+      for (int i = 0; i < 9; ++i) out[i] = ew[i] + (out[i] - e[i]);
+    }
+    for (int i = 0; i < 9; ++i) fout[(size_t)i * N + p] = out[i];
+  }
+  free(feq);
+}
+
+/* Force on the body per unit depth (reading: the paper computes it on the
+ * grid nodes lying on the body surface but gives no formula). Traction
+ * t = -p' n + sigma' n with p' = c_s^2 (rho - 1) and the viscous stress of
+ * the finite-volume populations sigma'_ab = -sum_i c_ia c_ib f_i^neq; the
+ * grid's f^neq already carries the structured factor (1 - 1/(2 tau_s)) by
+ * Eq.(continuity_stresses). n points out of the body; each wall edge is
+ * integrated with the trapezoid rule. */
+void or_mesh_force(const or_mesh *m, const double *f, double F[2]) {
+  const int N = m->nnode;
+  F[0] = 0.0;
+  F[1] = 0.0;
+  for (int e = 0; e < m->nwe; ++e) {
+    const double nx = m->wn[2 * e], ny = m->wn[2 * e + 1];
+    double tx = 0.0, ty = 0.0;
+    for (int s = 0; s < 2; ++s) {
+      const int p = m->we[2 * e + s];
+      double fp[9], eq[9], rho, ux, uy;
+      for (int i = 0; i < 9; ++i) fp[i] = f[(size_t)i * N + p];
+      moments(fp, &rho, &ux, &uy);
+      or_feq(rho, ux, uy, eq);
+      double sxx = 0.0, sxy = 0.0, syy = 0.0;
+      for (int i = 0; i < 9; ++i) {
+        const double fn = fp[i] - eq[i];
+        sxx -= CX[i] * CX[i] * fn;
+        sxy -= CX[i] * CY[i] * fn;
+        syy -= CY[i] * CY[i] * fn;
+      }
+      const double pp = CS2 * (rho - 1.0);
+      tx += -pp * nx + sxx * nx + sxy * ny;
+      ty += -pp * ny + sxy * nx + syy * ny;
+    }
+    F[0] += 0.5 * m->wl[e] * tx;
+    F[1] += 0.5 * m->wl[e] * ty;
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* The hybrid method                                                   */
+/* ------------------------------------------------------------------ */
+struct or_sim {
+  int nx, ny, nux, nuy, bc, n;
+  double h, b, T, tau_s, tau_u, nu, A, omega, dt_u, xc, yc, margin;
+  double kc, beta;
+  double body_b; /* width of the meshed-out lamina slot (0: no body) */
+  int64_t k;
+  double *fA, *fB;          /* lattice [9][ny][nx] */
+  uint8_t *disc;            /* lattice discretization flags of this step */
+  or_mesh *m;
+  double *fu, *fu2;         /* grid populations [9][nnode] */
+  double *star_eq, *star_neq;
+  double *uwx, *uwy;
+  double *hist;
+  int64_t hist_cap, hist_n;
+  int64_t nt1, nt2, nt3;
+};
+
+/* prescribed motion y(t) = A sin(omega t) (Sec. Problem statement), t = k */
+static double motion_y(const or_sim *s, int64_t k) { return s->A * sin(s->omega * (double)k); }
+
+/* Fictitious curve (reading: the paper draws it inside the grid boundary but
+ * gives no construction): the axis-aligned rectangle of the grid's node
+ * bounding box at offset y, inset by a margin of 2 lattice units. */
+typedef struct { double x0, x1, y0, y1; } rect_t;
+
+static rect_t rect_at(const or_sim *s, double y) {
+  rect_t r;
+  r.x0 = s->xc + (double)(0 - s->nux / 2) * s->h + s->margin;
+  r.x1 = s->xc + (double)(s->nux - 1 - s->nux / 2) * s->h - s->margin;
+  r.y0 = s->yc + y + (0.0 - 0.5 * (double)(s->nuy - 1)) * s->h + s->margin;
+  r.y1 = s->yc + y + ((double)(s->nuy - 1) - 0.5 * (double)(s->nuy - 1)) * s->h - s->margin;
+  return r;
+}
+
+static int inside_rect(const rect_t *r, int x, int y) {
+  return (double)x >= r->x0 && (double)x <= r->x1 && (double)y >= r->y0 && (double)y <= r->y1;
+}
+
+/* Node classes of the lattice (Sec. Refill procedure): nodes inside the
+ * fictitious curve are unused, unless one of their eight lattice neighbours is
+ * a discretization node, which makes them interpolation nodes. */
+static int lattice_status(const rect_t *r, int x, int y) {
+  if (!inside_rect(r, x, y)) return 0;
+  for (int i = 1; i < 9; ++i)
+    if (!inside_rect(r, x + CX[i], y + CY[i])) return 1;
+  return 2;
+}
+
+int32_t or_lattice_status(const or_sim *s, int64_t k, int32_t x, int32_t y) {
+  if (!s->m) return 0;
+  rect_t r = rect_at(s, motion_y(s, k));
+  return lattice_status(&r, x, y);
+}
+
+static void free_sim(or_sim *s) {
+  if (!s) return;
+  free(s->fA); free(s->fB); free(s->disc); or_mesh_free(s->m);
+  free(s->fu); free(s->fu2); free(s->star_eq); free(s->star_neq);
+  free(s->uwx); free(s->uwy); free(s->hist);
+  free(s);
+}
+
+void or_destroy(or_sim *s) { free_sim(s); }
+
+int or_create(const or_config *c, or_sim **out) {
+  if (!c || !out) return OR_E_ARG;
+  *out = NULL;
+  if (c->nx < 3 || c->ny < 3 || !(c->tau > 0.5) || c->max_steps < 0) return OR_E_ARG;
+  if (c->bc != OR_BC_PERIODIC_X_WALLS_Y && c->bc != OR_BC_PERIODIC) return OR_E_ARG;
+  const int has_mesh = (c->nux > 0 || c->nuy > 0);
+  const int body = has_mesh && c->b > 0.0 && !(c->flags & OR_FLAG_NO_BODY);
+  or_sim *s = xcalloc(1, sizeof(or_sim));
+  if (!s) return OR_E_NOMEM;
+  s->nx = c->nx;
+  s->ny = c->ny;
+  s->nux = c->nux;
+  s->nuy = c->nuy;
+  s->bc = c->bc;
+  s->h = (c->h_u > 0.0) ? c->h_u : 1.0;
+  s->b = c->b;
+  s->body_b = body ? c->b : 0.0;
+  s->kc = c->kc;
+  s->beta = c->beta;
+  s->tau_s = c->tau;
+  /* viscosity matching (Sec. 3): nu = c_s^2 (tau_s - 1/2) on the lattice and
+   * nu = c_s^2 tau_u on the grid, hence tau_u = tau_s - 1/2 */
+  s->nu = (c->tau - 0.5) / 3.0;
+  s->tau_u = c->tau - 0.5;
+  /* Sec. Problem statement: KC = 2 pi eps = 2 pi A / L, beta = omega L^2 / (2 pi nu) */
+  if (has_mesh && c->b > 0.0) {
+    s->A = c->kc * c->b / (2.0 * M_PI);
+    s->omega = 2.0 * M_PI * s->nu * c->beta / (c->b * c->b);
+  } else {
+    s->A = 0.0;
+    s->omega = 0.0;
+  }
+  /* sub-steps: Delta t_s = n Delta t_u; automatic n keeps Delta t_u <= tau_u,
+   * half the explicit stability bound Delta t < 2 tau (Sec. Numerical
+   * performance) */
+  if (c->n_sub > 0) s->n = c->n_sub;
+  else {
+    int n = (int)ceil(1.0 / s->tau_u - 1e-9);
+    s->n = n < 2 ? 2 : n;
+  }
+  s->dt_u = 1.0 / (double)s->n;
+  s->xc = (double)(c->nx / 2);
+  s->yc = 0.5 * (double)(c->ny - 1);
+  s->margin = 2.0;
+  s->hist_cap = c->max_steps;
+  const size_t L = (size_t)9 * c->nx * c->ny;
+  s->fA = malloc(L * sizeof(double));
+  s->fB = malloc(L * sizeof(double));
+  s->disc = malloc((size_t)c->nx * c->ny);
+  s->hist = xcalloc((size_t)2 * (c->max_steps > 0 ? c->max_steps : 1), sizeof(double));
+  if (!s->fA || !s->fB || !s->disc || !s->hist) {
+    free_sim(s);
+    return OR_E_NOMEM;
+  }
+  /* initial state (reading): fluid at rest with unit density everywhere */
+  for (int i = 0; i < 9; ++i)
+    for (size_t p = 0; p < (size_t)c->nx * c->ny; ++p) {
+      s->fA[(size_t)i * c->nx * c->ny + p] = WT[i];
+      s->fB[(size_t)i * c->nx * c->ny + p] = WT[i];
+    }
+  if (has_mesh) {
+    if (body && fabs(c->thickness - s->h) > 1e-12 * s->h) { free_sim(s); return OR_E_ARG; }
+    if (c->n_sub < 0) { free_sim(s); return OR_E_ARG; }
+    /* explicit stability of the grid scheme, Delta t_u < 2 tau_u */
+    if (!(s->dt_u < 2.0 * s->tau_u)) { free_sim(s); return OR_E_ARG; }
+    s->m = or_mesh_lamina(c->nux, c->nuy, s->h, s->body_b);
+    if (!s->m) { free_sim(s); return OR_E_ARG; }
+    s->T = s->m->T;
+    /* geometric requirements: the grid and the lattice donors of its outer
+     * nodes stay inside the lattice; the fictitious rectangle holds the body
+     * with a one-unit gap; a node moves less than one lattice unit per step */
+    const double hx = (double)(c->nux / 2) * s->h, hxr = (double)(c->nux - 1 - c->nux / 2) * s->h;
+    const double hy = 0.5 * (double)(c->nuy - 1) * s->h;
+    if (s->xc - hx < 1.0 || s->xc + hxr > (double)c->nx - 2.0) { free_sim(s); return OR_E_ARG; }
+    if (c->bc == OR_BC_PERIODIC_X_WALLS_Y &&
+        (s->yc - hy - fabs(s->A) < 1.0 || s->yc + hy + fabs(s->A) > (double)c->ny - 2.0)) {
+      free_sim(s);
+      return OR_E_ARG;
+    }
+    if (body && (0.5 * c->b + 1.0 > hx - s->margin - 1.0 || 0.5 * c->b + 1.0 > hxr - s->margin - 1.0 ||
+                       0.5 * s->h + 1.0 > hy - s->margin - 1.0)) {
+      free_sim(s);
+      return OR_E_ARG;
+    }
+    if (!(fabs(s->A * s->omega) < 1.0)) { free_sim(s); return OR_E_ARG; }
+    const int N = s->m->nnode;
+    s->fu = malloc((size_t)9 * N * sizeof(double));
+    s->fu2 = malloc((size_t)9 * N * sizeof(double));
+    s->star_eq = xcalloc((size_t)9 * N, sizeof(double));
+    s->star_neq = xcalloc((size_t)9 * N, sizeof(double));
+    s->uwx = xcalloc(N, sizeof(double));
+    s->uwy = xcalloc(N, sizeof(double));
+    if (!s->fu || !s->fu2 || !s->star_eq || !s->star_neq || !s->uwx || !s->uwy) {
+      free_sim(s);
+      return OR_E_NOMEM;
+    }
+    for (int i = 0; i < 9; ++i)
+      for (int p = 0; p < N; ++p) s->fu[(size_t)i * N + p] = WT[i];
+  }
+  *out = s;
+  return OR_OK;
+}
+
+/* lattice populations arriving at node (x,y) at t_{k+1}: pulled from the
+ * post-collision buffer of t_k (the pre-collision f of Eq.(LBE)'s left side) */
+static void lattice_pre(const or_sim *s, int x, int y, double f[9]) {
+  pull_node(s->fA, s->nx, s->ny, s->bc, wrap(x, s->nx), s->bc == OR_BC_PERIODIC ? wrap(y, s->ny) : y,
+            0.0, 0.0, f);
+}
+
+/* Bilinear Lagrange interpolation over the four lattice nodes of the cell
+ * enclosing (X,Y) (Sec. Refill procedure, type 1): density, velocity and the
+ * non-equilibrium part f^neq,s = f - f^eq(rho, u) of the pre-collision
+ * populations at t_{k+1}. */
+static void lattice_bilinear(const or_sim *s, double X, double Y, double *rho,
+                             double *ux, double *uy, double fneq[9]) {
+  const double fx = floor(X), fy = floor(Y);
+  const int x0 = (int)fx, y0 = (int)fy;
+  const double a = X - fx, bb = Y - fy;
+  const double wgt[4] = {(1.0 - a) * (1.0 - bb), a * (1.0 - bb), (1.0 - a) * bb, a * bb};
+  const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
+  *rho = 0.0;
+  *ux = 0.0;
+  *uy = 0.0;
+  for (int i = 0; i < 9; ++i) fneq[i] = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    double f[9], e[9], r, vx, vy;
+    lattice_pre(s, x0 + dx[d], y0 + dy[d], f);
+    moments(f, &r, &vx, &vy);
+    or_feq(r, vx, vy, e);
+    *rho += wgt[d] * r;
+    *ux += wgt[d] * vx;
+    *uy += wgt[d] * vy;
+    for (int i = 0; i < 9; ++i) fneq[i] += wgt[d] * (f[i] - e[i]);
+  }
+}
+
+/* Eq.(postcollision2_s) at lattice node (x,y) from the grid at offset y_k:
+ * barycentric interpolation of rho, u and f^neq,u over the enclosing triangle,
+ * f^eq rebuilt from the interpolated moments. */
+static int lattice_from_grid(or_sim *s, int x, int y, double yk) {
+  const or_mesh *m = s->m;
+  const int N = m->nnode;
+  double lam[3];
+  const int t = or_mesh_locate(m, (double)x - s->xc, (double)y - (s->yc + yk), lam);
+  if (t < 0) return OR_E_STATE;
+  double rho = 0.0, ux = 0.0, uy = 0.0, fneq[9] = {0};
+  for (int a = 0; a < 3; ++a) {
+    const int p = m->tri[3 * t + a];
+    double f[9], e[9], r, vx, vy;
+    for (int i = 0; i < 9; ++i) f[i] = s->fu[(size_t)i * N + p];
+    moments(f, &r, &vx, &vy);
+    or_feq(r, vx, vy, e);
+    rho += lam[a] * r;
+    ux += lam[a] * vx;
+    uy += lam[a] * vy;
+    for (int i = 0; i < 9; ++i) fneq[i] += lam[a] * (f[i] - e[i]);
+  }
+  double e[9];
+  or_feq(rho, ux, uy, e);
+  const double g = 2.0 * (s->tau_s - 1.0) / (2.0 * s->tau_s - 1.0);
+  for (int i = 0; i < 9; ++i) s->fA[lidx(s->nx, s->ny, i, x, y)] = e[i] + g * fneq[i];
+  return OR_OK;
+}
+
+/* Refill after the move from y_k to y_k1 (Sec. Refill procedure). */
+static void refill(or_sim *s, double yk, double yk1) {
+  const or_mesh *m = s->m;
+  const int N = m->nnode;
+  const double kneq = 1.0 - 1.0 / (2.0 * s->tau_s); /* Eq.(continuity_stresses) */
+  for (int p = 0; p < N; ++p) {
+    double out[9];
+    if (m->type[p] == OR_NODE_WALL) {
+      /* wall nodes keep density and populations; their velocity is imposed
+       * during the sub-steps */
+      for (int i = 0; i < 9; ++i) out[i] = s->fu[(size_t)i * N + p];
+    } else {
+      const double X = s->xc + m->x[p];
+      const double Ynew = (s->yc + yk1) + m->y[p];
+      double lam[3];
+      const int t = or_mesh_locate(m, X - s->xc, Ynew - (s->yc + yk), lam);
+      if (t >= 0) {
+        /* type 3: barycentric interpolation in the old triangle */
+        for (int i = 0; i < 9; ++i) {
+          out[i] = 0.0;
+          for (int a = 0; a < 3; ++a) out[i] += lam[a] * s->fu[(size_t)i * N + m->tri[3 * t + a]];
+        }
+        s->nt3++;
+      } else if (s->body_b > 0.0 && fabs(X - s->xc) < 0.5 * s->body_b && fabs(Ynew - (s->yc + yk)) < 0.5 * s->T) {
+        /* type 2: inside the old body, keep the previous values */
+        for (int i = 0; i < 9; ++i) out[i] = s->fu[(size_t)i * N + p];
+        s->nt2++;
+      } else {
+        /* type 1: outside the old grid, from the lattice */
+        double rho, ux, uy, fneq[9], e[9];
+        lattice_bilinear(s, X, Ynew, &rho, &ux, &uy, fneq);
+        or_feq(rho, ux, uy, e);
+        for (int i = 0; i < 9; ++i) out[i] = e[i] + kneq * fneq[i];
+        s->nt1++;
+      }
+    }
+    for (int i = 0; i < 9; ++i) s->fu2[(size_t)i * N + p] = out[i];
+  }
+  double *tmp = s->fu;
+  s->fu = s->fu2;
+  s->fu2 = tmp;
+}
+
+int or_step(or_sim *s, int64_t nsteps) {
+  if (!s || nsteps < 0) return OR_E_ARG;
+  if (s->m && s->hist_n + nsteps > s->hist_cap) return OR_E_ARG;
+  const int nx = s->nx, ny = s->ny;
+  for (int64_t it = 0; it < nsteps; ++it) {
+    const int64_t k = s->k;
+    if (!s->m) {
+      or_lattice_step(s->fA, s->fB, nx, ny, s->bc, s->tau_s, 0.0, 0.0, NULL);
+    } else {
+      const or_mesh *m = s->m;
+      const int N = m->nnode;
+      const double yk = motion_y(s, k);
+      const double yprev = (k > 0) ? motion_y(s, k - 1) : yk;
+      const double yk1 = motion_y(s, k + 1);
+      const rect_t R = rect_at(s, yk), Rp = rect_at(s, yprev);
+      /* 1. lattice interpolation nodes, plus nodes the moving fictitious line
+       *    has just uncovered (Sec. Refill procedure, last paragraphs), get
+       *    Eq.(postcollision2_s) from the grid at y_k */
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int st = lattice_status(&R, x, y), sp = lattice_status(&Rp, x, y);
+          s->disc[(size_t)y * nx + x] = (st == 0);
+          if (st == 1 || (st == 0 && sp != 0))
+            if (lattice_from_grid(s, x, y, yk) != OR_OK) return OR_E_STATE;
+        }
+      /* 2. Eq.(LBE) on the discretization nodes */
+      or_lattice_step(s->fA, s->fB, nx, ny, s->bc, s->tau_s, 0.0, 0.0, s->disc);
+      /* 3. structured-derived values at the grid's outer nodes, from the
+       *    lattice at t_{k+1} (pre-collision), held over the n sub-steps */
+      const double kneq = 1.0 - 1.0 / (2.0 * s->tau_s);
+      for (int p = 0; p < N; ++p) {
+        if (m->type[p] != OR_NODE_INTERFACE) continue;
+        double rho, ux, uy, fneq[9], e[9];
+        lattice_bilinear(s, s->xc + m->x[p], (s->yc + yk) + m->y[p], &rho, &ux, &uy, fneq);
+        or_feq(rho, ux, uy, e);
+        for (int i = 0; i < 9; ++i) {
+          s->star_eq[(size_t)i * N + p] = e[i];
+          s->star_neq[(size_t)i * N + p] = kneq * fneq[i];
+        }
+      }
+      /* 4. n sub-steps of the grid scheme, Delta t_s = n Delta t_u; the wall
+       *    moves with the lamina, u_w = A omega cos(omega t) at the end of
+       *    each sub-step */
+      for (int sub = 0; sub < s->n; ++sub) {
+        const double t = (double)k + (double)(sub + 1) / (double)s->n;
+        const double uw = s->A * s->omega * cos(s->omega * t);
+        for (int p = 0; p < N; ++p) {
+          s->uwx[p] = 0.0;
+          s->uwy[p] = uw;
+        }
+        or_fv_substep(m, s->fu, s->star_eq, s->star_neq, s->fu2, s->tau_u, s->dt_u, s->uwx, s->uwy);
+        double *tmp = s->fu;
+        s->fu = s->fu2;
+        s->fu2 = tmp;
+      }
+      /* 5. force on the lamina at t_{k+1} */
+      double F[2];
+      or_mesh_force(m, s->fu, F);
+      s->hist[2 * s->hist_n] = F[0];
+      s->hist[2 * s->hist_n + 1] = F[1];
+      s->hist_n++;
+      if (!isfinite(F[0]) || !isfinite(F[1])) return OR_E_UNSTABLE;
+      /* 6. move the grid to y_{k+1} and refill it */
+      refill(s, yk, yk1);
+    }
+    double *tmp = s->fA;
+    s->fA = s->fB;
+    s->fB = tmp;
+    s->k = k + 1;
+  }
+  /* unstable if any density is not finite and positive */
+  const size_t L = (size_t)nx * ny;
+  for (size_t p = 0; p < L; ++p) {
+    double r = 0.0;
+    for (int i = 0; i < 9; ++i) r += s->fA[(size_t)i * L + p];
+    if (!(r > 0.0) || !isfinite(r)) return OR_E_UNSTABLE;
+  }
+  return OR_OK;
+}
+
+int or_info_get(const or_sim *s, or_info *o) {
+  if (!s || !o) return OR_E_ARG;
+  memset(o, 0, sizeof(*o));
+  o->nu = s->nu;
+  o->tau_u = s->tau_u;
+  o->dt_u = s->dt_u;
+  o->A = s->A;
+  o->omega = s->omega;
+  o->period = (s->omega > 0.0) ? 2.0 * M_PI / s->omega : 0.0;
+  o->u_max = s->A * s->omega;
+  o->mach = o->u_max * sqrt(3.0);
+  o->reynolds = (s->nu > 0.0) ? o->u_max * s->b / s->nu : 0.0;
+  o->eps = (s->b > 0.0) ? s->A / s->b : 0.0;
+  o->beta_limit_ok = (o->eps > 0.0) ? (s->beta < 2.6 * pow(o->eps, -1.6)) : 1;
+  o->n_sub = s->n;
+  o->step = s->k;
+  o->y = motion_y(s, s->k);
+  o->n_type1 = s->nt1;
+  o->n_type2 = s->nt2;
+  o->n_type3 = s->nt3;
+  if (s->m) {
+    o->nnode = s->m->nnode;
+    o->ntri = s->m->ntri;
+    o->n_wall_edges = s->m->nwe;
+    for (int p = 0; p < s->m->nnode; ++p) {
+      o->n_interface += s->m->type[p] == OR_NODE_INTERFACE;
+      o->n_wall += s->m->type[p] == OR_NODE_WALL;
+    }
+  }
+  return OR_OK;
+}
+
+const or_mesh *or_sim_mesh(const or_sim *s) { return s->m; }
+
+int or_get_lattice(const or_sim *s, double *out) {
+  memcpy(out, s->fA, (size_t)9 * s->nx * s->ny * sizeof(double));
+  return OR_OK;
+}
+int or_set_lattice(or_sim *s, const double *in) {
+  memcpy(s->fA, in, (size_t)9 * s->nx * s->ny * sizeof(double));
+  return OR_OK;
+}
+int or_get_mesh(const or_sim *s, double *out) {
+  if (!s->m) return OR_E_STATE;
+  memcpy(out, s->fu, (size_t)9 * s->m->nnode * sizeof(double));
+  return OR_OK;
+}
+int or_set_mesh(or_sim *s, const double *in) {
+  if (!s->m) return OR_E_STATE;
+  memcpy(s->fu, in, (size_t)9 * s->m->nnode * sizeof(double));
+  return OR_OK;
+}
+int64_t or_history(const or_sim *s, double *out, int64_t cap) {
+  const int64_t n = s->hist_n < cap ? s->hist_n : cap;
+  if (out) memcpy(out, s->hist, (size_t)2 * n * sizeof(double));
+  return s->hist_n;
+}
+
+/* Single-harmonic least-squares fit F(t) = F0 sin(omega t + phi) with omega
+ * given, over the window [t0, t1) periods (the paper discards the first cycle
+ * and uses three: [1, 4)), written as F = a_s sin + a_c cos; by
+ * Eq.(force_phasor) F0 e^{i phi} = a_s + i a_c = (pi/4) rho omega^2 L^2 Theta A. */
+int or_fit_theta(const double *hist, int64_t n, double omega, double A,
+                 double b, double t0, double t1, double theta[2]) {
+  if (!(omega > 0.0) || !(A != 0.0) || !(b > 0.0)) return OR_E_ARG;
+  const double T = 2.0 * M_PI / omega;
+  double ss = 0.0, sc = 0.0, cc = 0.0, sf = 0.0, cf = 0.0;
+  int64_t cnt = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double t = (double)(k + 1);
+    if (t < t0 * T || t >= t1 * T) continue;
+    const double sn = sin(omega * t), cs = cos(omega * t), F = hist[2 * k + 1];
+    ss += sn * sn;
+    sc += sn * cs;
+    cc += cs * cs;
+    sf += sn * F;
+    cf += cs * F;
+    ++cnt;
+  }
+  if (cnt < 2) return OR_E_ARG;
+  const double det = ss * cc - sc * sc;
+  if (!(fabs(det) > 0.0)) return OR_E_ARG;
+  const double as = (sf * cc - cf * sc) / det;
+  const double ac = (cf * ss - sf * sc) / det;
+  const double norm = 0.25 * M_PI * 1.0 * omega * omega * b * b * A;
+  theta[0] = as / norm;
+  theta[1] = ac / norm;
+  return OR_OK;
+}

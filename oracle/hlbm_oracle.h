@@ -1,0 +1,142 @@
+/*
+ * hlbm_oracle.h -- plain FP64 CPU oracle of the moving-grid hybrid lattice
+ * Boltzmann method (MG-HLBM) of Di Ilio, Chiappini, Ubertini, Bella and Succi,
+ * "A moving-grid approach for fluid-structure interaction problems with hybrid
+ * lattice Boltzmann method" (arXiv 2006.13631).
+ *
+ * TEST INFRASTRUCTURE. This library exists only to check the GPU library.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it. It shares no code, header, table or helper with the
+ * GPU path and is never a fallback for it.
+ *
+ * Everything is FP64, single-threaded, written as plain loops in the order the
+ * paper states the method. Where the paper leaves a point open, the reading
+ * taken is stated next to the code that takes it.
+ */
+#ifndef HLBM_ORACLE_H
+#define HLBM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* boundary conditions of the background lattice */
+#define OR_BC_PERIODIC_X_WALLS_Y 0 /* periodic in x, halfway bounce-back walls at y=-1/2, ny-1/2 */
+#define OR_BC_PERIODIC 1           /* periodic in x and y */
+
+/* mesh node roles (Sec. Refill procedure) */
+#define OR_NODE_INTERIOR 0  /* discretization node of the body-fitted grid      */
+#define OR_NODE_INTERFACE 1 /* outer boundary: interpolation node                */
+#define OR_NODE_WALL 2      /* on the solid wall of the lamina                   */
+
+/* error codes */
+#define OR_OK 0
+#define OR_E_ARG -1
+#define OR_E_NOMEM -2
+#define OR_E_STATE -5
+#define OR_E_UNSTABLE -4
+
+typedef struct or_config {
+  int32_t nx, ny;   /* background lattice nodes                         */
+  int32_t nux, nuy; /* body-fitted grid nodes (0,0: lattice only)       */
+  double h_u;       /* grid spacing (lattice units)                     */
+  double b;         /* lamina width L (0: no body)                      */
+  double thickness; /* lamina thickness T (must equal h_u)              */
+  double tau;       /* structured relaxation time tau_s                 */
+  double kc;        /* Keulegan-Carpenter number 2 pi A / L             */
+  double beta;      /* frequency parameter omega L^2 / (2 pi nu)        */
+  int32_t n_sub;    /* sub-steps per structured step; 0: automatic      */
+  int32_t bc;       /* OR_BC_*                                          */
+  int32_t flags;    /* OR_FLAG_*                                        */
+  int64_t max_steps;/* capacity of the force history                    */
+} or_config;
+
+/* grid without the lamina slot (b still sets A and omega); for invariance
+ * checks of the moving-grid coupling */
+#define OR_FLAG_NO_BODY 1
+
+typedef struct or_info {
+  double nu, tau_u, dt_u, A, omega, period, u_max, mach, reynolds, eps;
+  int32_t n_sub, nnode, ntri, n_interface, n_wall, n_wall_edges;
+  int32_t beta_limit_ok; /* 1 if beta < 2.6 eps^-1.6 (Eq. betalimit) */
+  int64_t step;
+  double y;              /* current lamina offset y(t_k)             */
+  int64_t n_type1, n_type2, n_type3; /* refill counts, summed over steps */
+} or_info;
+
+typedef struct or_sim or_sim;
+typedef struct or_mesh or_mesh;
+
+/* ---- equilibrium, Eq.(local_eq) ------------------------------------- */
+void or_feq(double rho, double ux, double uy, double feq[9]);
+void or_d2q9(int32_t cx[9], int32_t cy[9], double w[9]);
+
+/* ---- structured lattice, Eq.(LBE) ------------------------------------ */
+/* One pull stream + BGK collide from A (post-collision t) to B (post-collision
+ * t+1) over an nx*ny lattice stored [9][ny][nx]. disc: per-node flag (NULL =
+ * every node computes); non-computing nodes copy A to B. Walls (bc 0) may move
+ * tangentially with x-velocities u_bot, u_top. */
+void or_lattice_step(const double *A, double *B, int32_t nx, int32_t ny,
+                     int32_t bc, double tau, double u_bot, double u_top,
+                     const uint8_t *disc);
+
+/* ---- finite-volume mesh, Eq.(ulbe) ----------------------------------- */
+/* lamina grid: nux*nuy nodes, spacing h, lamina slot of width b (0: none) */
+or_mesh *or_mesh_lamina(int32_t nux, int32_t nuy, double h, double b);
+/* doubly periodic nx*ny grid of spacing h, every node interior */
+or_mesh *or_mesh_periodic(int32_t nx, int32_t ny, double h);
+/* channel periodic in x, rows 0 and ny-1 are walls */
+or_mesh *or_mesh_channel(int32_t nx, int32_t ny, double h);
+void or_mesh_free(or_mesh *m);
+int32_t or_mesh_nnode(const or_mesh *m);
+int32_t or_mesh_ntri(const or_mesh *m);
+int32_t or_mesh_kmax(const or_mesh *m);
+/* node coordinates (local frame) and types */
+void or_mesh_nodes(const or_mesh *m, double *x, double *y, int32_t *type);
+/* triangles: [ntri][3] node ids and [ntri][3][2] vertex coordinates */
+void or_mesh_triangles(const or_mesh *m, int32_t *tri, double *txy);
+/* dense stencil export: nbr [nnode][kmax] (-1 padded, self first),
+ * S [nnode][9][kmax], C [nnode][kmax], V [nnode] */
+void or_mesh_stencil(const or_mesh *m, int32_t kmax, int32_t *nbr, double *S,
+                     double *C, double *V);
+/* point location: triangle containing (px,py) in the local frame, or -1;
+ * lam gets the barycentric coordinates */
+int32_t or_mesh_locate(const or_mesh *m, double px, double py, double lam[3]);
+/* One sub-step of Eq.(ulbe) (interior / wall nodes) and Eq.(postcollision2_u)
+ * (interface nodes). f, fout: [9][nnode]. star_eq / star_neq: [9][nnode],
+ * read at interface nodes only (may be NULL when there are none). uwx, uwy:
+ * per-node wall velocity, read at wall nodes only (may be NULL if no walls). */
+void or_fv_substep(const or_mesh *m, const double *f, const double *star_eq,
+                   const double *star_neq, double *fout, double tau_u,
+                   double dt_u, const double *uwx, const double *uwy);
+/* wall force: sum over wall edges, trapezoid rule; f [9][nnode] */
+void or_mesh_force(const or_mesh *m, const double *f, double F[2]);
+
+/* ---- the hybrid method ----------------------------------------------- */
+int or_create(const or_config *cfg, or_sim **out);
+void or_destroy(or_sim *s);
+int or_step(or_sim *s, int64_t nsteps);
+int or_info_get(const or_sim *s, or_info *out);
+const or_mesh *or_sim_mesh(const or_sim *s);
+/* lattice [9][ny][nx] (post-collision at t_k), mesh [9][nnode] at t_k */
+int or_get_lattice(const or_sim *s, double *out);
+int or_set_lattice(or_sim *s, const double *in);
+int or_get_mesh(const or_sim *s, double *out);
+int or_set_mesh(or_sim *s, const double *in);
+/* force history: entry k holds (Fx, Fy) at t = k+1; returns count */
+int64_t or_history(const or_sim *s, double *out, int64_t cap);
+/* status of lattice node (x,y) at step k: 0 disc, 1 interpolation, 2 unused */
+int32_t or_lattice_status(const or_sim *s, int64_t k, int32_t x, int32_t y);
+
+/* ---- hydrodynamic function fit (Sec. Hydrodynamic function extraction) -- */
+/* hist: (Fx,Fy) pairs, entry k at t=k+1. Window [t0, t1) in periods.
+ * Returns 0 and theta = (Re, Im), or OR_E_ARG if the window holds < 2 samples. */
+int or_fit_theta(const double *hist, int64_t n, double omega, double A,
+                 double b, double t0, double t1, double theta[2]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,275 @@
+"""ctypes binding of the FP64 CPU oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE: only the test suite, the smoke check and the CPU-baseline
+leg of the benchmark import this module. It never backs the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hlbm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BC_PERIODIC_X_WALLS_Y = 0
+BC_PERIODIC = 1
+FLAG_NO_BODY = 1
+NODE_INTERIOR, NODE_INTERFACE, NODE_WALL = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no contraction of a*b+c)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-fPIC",
+               "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nux", C.c_int32), ("nuy", C.c_int32),
+                ("h_u", C.c_double), ("b", C.c_double), ("thickness", C.c_double),
+                ("tau", C.c_double), ("kc", C.c_double), ("beta", C.c_double),
+                ("n_sub", C.c_int32), ("bc", C.c_int32), ("flags", C.c_int32),
+                ("max_steps", C.c_int64)]
+
+
+class Info(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("nu", "tau_u", "dt_u", "A", "omega", "period", "u_max", "mach", "reynolds", "eps")] + \
+               [(n, C.c_int32) for n in
+                ("n_sub", "nnode", "ntri", "n_interface", "n_wall", "n_wall_edges", "beta_limit_ok")] + \
+               [("step", C.c_int64), ("y", C.c_double),
+                ("n_type1", C.c_int64), ("n_type2", C.c_int64), ("n_type3", C.c_int64)]
+
+
+_lib = None
+_D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_I = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_U8 = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        vp = C.c_void_p
+        L.or_feq.argtypes = [C.c_double, C.c_double, C.c_double, _D]
+        L.or_d2q9.argtypes = [_I, _I, _D]
+        L.or_lattice_step.argtypes = [_D, _D, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                      C.c_double, C.c_double, vp]
+        for f in ("or_mesh_lamina",):
+            getattr(L, f).argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double]
+            getattr(L, f).restype = vp
+        for f in ("or_mesh_periodic", "or_mesh_channel"):
+            getattr(L, f).argtypes = [C.c_int32, C.c_int32, C.c_double]
+            getattr(L, f).restype = vp
+        L.or_mesh_free.argtypes = [vp]
+        for f in ("or_mesh_nnode", "or_mesh_ntri", "or_mesh_kmax"):
+            getattr(L, f).argtypes = [vp]
+            getattr(L, f).restype = C.c_int32
+        L.or_mesh_nodes.argtypes = [vp, _D, _D, _I]
+        L.or_mesh_triangles.argtypes = [vp, _I, _D]
+        L.or_mesh_stencil.argtypes = [vp, C.c_int32, _I, _D, _D, _D]
+        L.or_mesh_locate.argtypes = [vp, C.c_double, C.c_double, _D]
+        L.or_mesh_locate.restype = C.c_int32
+        L.or_fv_substep.argtypes = [vp, _D, vp, vp, _D, C.c_double, C.c_double, vp, vp]
+        L.or_mesh_force.argtypes = [vp, _D, _D]
+        L.or_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.or_destroy.argtypes = [vp]
+        L.or_step.argtypes = [vp, C.c_int64]
+        L.or_info_get.argtypes = [vp, C.POINTER(Info)]
+        L.or_sim_mesh.argtypes = [vp]
+        L.or_sim_mesh.restype = vp
+        for f in ("or_get_lattice", "or_set_lattice", "or_get_mesh", "or_set_mesh"):
+            getattr(L, f).argtypes = [vp, _D]
+        L.or_history.argtypes = [vp, _D, C.c_int64]
+        L.or_history.restype = C.c_int64
+        L.or_lattice_status.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32]
+        L.or_lattice_status.restype = C.c_int32
+        L.or_fit_theta.argtypes = [_D, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                   C.c_double, C.c_double, _D]
+        _lib = L
+    return _lib
+
+
+def d2q9():
+    cx = np.zeros(9, np.int32)
+    cy = np.zeros(9, np.int32)
+    w = np.zeros(9)
+    lib().or_d2q9(cx, cy, w)
+    return cx, cy, w
+
+
+def feq(rho: float, ux: float, uy: float) -> np.ndarray:
+    out = np.zeros(9)
+    lib().or_feq(rho, ux, uy, out)
+    return out
+
+
+def lattice_step(A: np.ndarray, tau: float, bc: int = BC_PERIODIC, u_bot: float = 0.0,
+                 u_top: float = 0.0, disc: np.ndarray | None = None) -> np.ndarray:
+    """One Eq.(LBE) step on a [9][ny][nx] array; returns the new array."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    _, ny, nx = A.shape
+    B = np.empty_like(A)
+    dptr = None
+    if disc is not None:
+        disc = np.ascontiguousarray(disc, dtype=np.uint8)
+        dptr = disc.ctypes.data_as(C.c_void_p)
+    lib().or_lattice_step(A, B, nx, ny, bc, tau, u_bot, u_top, dptr)
+    return B
+
+
+class Mesh:
+    """A triangular grid with its finite-volume matrices."""
+
+    def __init__(self, ptr, owned=True):
+        if not ptr:
+            raise ValueError("mesh construction rejected its arguments")
+        self.ptr = ptr
+        self.owned = owned
+        L = lib()
+        self.nnode = L.or_mesh_nnode(ptr)
+        self.ntri = L.or_mesh_ntri(ptr)
+        self.kmax = L.or_mesh_kmax(ptr)
+
+    @classmethod
+    def lamina(cls, nux, nuy, h=1.0, b=0.0):
+        return cls(lib().or_mesh_lamina(nux, nuy, h, b))
+
+    @classmethod
+    def periodic(cls, nx, ny, h=1.0):
+        return cls(lib().or_mesh_periodic(nx, ny, h))
+
+    @classmethod
+    def channel(cls, nx, ny, h=1.0):
+        return cls(lib().or_mesh_channel(nx, ny, h))
+
+    def __del__(self):
+        if getattr(self, "owned", False) and self.ptr and _lib is not None:
+            _lib.or_mesh_free(self.ptr)
+            self.ptr = None
+
+    def nodes(self):
+        x = np.zeros(self.nnode)
+        y = np.zeros(self.nnode)
+        t = np.zeros(self.nnode, np.int32)
+        lib().or_mesh_nodes(self.ptr, x, y, t)
+        return x, y, t
+
+    def triangles(self):
+        tri = np.zeros((self.ntri, 3), np.int32)
+        txy = np.zeros((self.ntri, 3, 2))
+        lib().or_mesh_triangles(self.ptr, tri, txy)
+        return tri, txy
+
+    def stencil(self):
+        k = self.kmax
+        nbr = np.zeros((self.nnode, k), np.int32)
+        S = np.zeros((self.nnode, 9, k))
+        Cm = np.zeros((self.nnode, k))
+        V = np.zeros(self.nnode)
+        lib().or_mesh_stencil(self.ptr, k, nbr, S, Cm, V)
+        return nbr, S, Cm, V
+
+    def locate(self, px, py):
+        lam = np.zeros(3)
+        t = lib().or_mesh_locate(self.ptr, px, py, lam)
+        return t, lam
+
+    def substep(self, f, tau_u, dt_u, star_eq=None, star_neq=None, uwx=None, uwy=None):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.empty_like(f)
+        keep = []
+
+        def p(a):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            keep.append(a)
+            return a.ctypes.data_as(C.c_void_p)
+        lib().or_fv_substep(self.ptr, f, p(star_eq), p(star_neq), out, tau_u, dt_u, p(uwx), p(uwy))
+        return out
+
+    def force(self, f):
+        F = np.zeros(2)
+        lib().or_mesh_force(self.ptr, np.ascontiguousarray(f, dtype=np.float64), F)
+        return F
+
+
+class Sim:
+    """The hybrid method, advanced step by step on the CPU."""
+
+    def __init__(self, nx, ny, nux=0, nuy=0, h_u=1.0, b=0.0, thickness=1.0, tau=0.8, kc=0.0,
+                 beta=0.0, n_sub=0, bc=BC_PERIODIC_X_WALLS_Y, flags=0, max_steps=0):
+        self.cfg = Config(nx, ny, nux, nuy, h_u, b, thickness, tau, kc, beta, n_sub, bc, flags,
+                          max_steps)
+        h = C.c_void_p()
+        rc = lib().or_create(C.byref(self.cfg), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"or_create rejected the configuration (code {rc})")
+        self.ptr = h
+        self.nx, self.ny = nx, ny
+        inf = self.info()
+        self.nnode = inf.nnode
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.or_destroy(self.ptr)
+            self.ptr = None
+
+    def step(self, n=1):
+        rc = lib().or_step(self.ptr, n)
+        if rc != 0:
+            raise RuntimeError(f"or_step failed (code {rc})")
+
+    def info(self) -> Info:
+        i = Info()
+        lib().or_info_get(self.ptr, C.byref(i))
+        return i
+
+    def mesh(self) -> Mesh:
+        return Mesh(lib().or_sim_mesh(self.ptr), owned=False)
+
+    def lattice(self):
+        out = np.zeros((9, self.ny, self.nx))
+        lib().or_get_lattice(self.ptr, out)
+        return out
+
+    def set_lattice(self, f):
+        lib().or_set_lattice(self.ptr, np.ascontiguousarray(f, dtype=np.float64))
+
+    def grid(self):
+        out = np.zeros((9, self.nnode))
+        lib().or_get_mesh(self.ptr, out)
+        return out
+
+    def set_grid(self, f):
+        lib().or_set_mesh(self.ptr, np.ascontiguousarray(f, dtype=np.float64))
+
+    def history(self):
+        n = lib().or_history(self.ptr, np.zeros(2), 0)
+        out = np.zeros((max(n, 1), 2))
+        lib().or_history(self.ptr, out, n)
+        return out[:n]
+
+    def status(self, k):
+        return np.array([[lib().or_lattice_status(self.ptr, k, x, y) for x in range(self.nx)]
+                         for y in range(self.ny)], dtype=np.int32)
+
+
+def fit_theta(hist, omega, A, b, t0=1.0, t1=4.0):
+    hist = np.ascontiguousarray(hist, dtype=np.float64).reshape(-1, 2)
+    out = np.zeros(2)
+    rc = lib().or_fit_theta(hist, hist.shape[0], omega, A, b, t0, t1, out)
+    if rc != 0:
+        raise ValueError("fit window holds fewer than two samples")
+    return complex(out[0], out[1])

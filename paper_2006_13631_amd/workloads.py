@@ -1,0 +1,77 @@
+"""Seeded synthetic workloads: named lamina configurations and random fields.
+
+This module only states sizes, parameters and seeded random numbers. It holds
+none of the method's arithmetic, so both the GPU library's tests and the CPU
+oracle can take their inputs from it.
+
+The configurations follow the problem statement of the paper (Sec. Problem
+statement): a lamina of width ``b`` and thickness 1 in a D2Q9 lattice, moving
+as y = A sin(omega t) with KC = 2 pi A / b and beta = omega b^2 / (2 pi nu).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# name -> parameters (lattice nx*ny, body-fitted grid nux*nuy, lamina width b,
+# relaxation time tau, KC, beta, number of structured steps)
+PRESETS = {
+    # plain run with oracle parity: 256x128 lattice, 64x32 grid, 2000 steps
+    "lamina_256x128": dict(nx=256, ny=128, nux=64, nuy=32, h_u=1.0, b=32.0, thickness=1.0,
+                           tau=0.8, kc=0.5, beta=100.0, steps=2000),
+    # sweep scale: 2048^2 lattice, 512x128 grid, 20000 steps
+    "lamina_2048": dict(nx=2048, ny=2048, nux=512, nuy=128, h_u=1.0, b=128.0, thickness=1.0,
+                        tau=0.55, kc=1.0, beta=1000.0, steps=20000),
+    # differentiation case: 1024^2 lattice, 256x64 grid, 4000 steps, window 200
+    "lamina_1024": dict(nx=1024, ny=1024, nux=256, nuy=64, h_u=1.0, b=64.0, thickness=1.0,
+                        tau=0.6, kc=0.8, beta=500.0, steps=4000, ckpt_every=200),
+    # 128x64 copy of the differentiation case (same KC, tau and lamina speed)
+    "lamina_128x64": dict(nx=128, ny=64, nux=64, nuy=16, h_u=1.0, b=16.0, thickness=1.0,
+                          tau=0.6, kc=0.8, beta=125.0, steps=4000, ckpt_every=200),
+    # precision at scale: 4096^2 lattice, 1024x256 grid, 100000 steps
+    "lamina_4096": dict(nx=4096, ny=4096, nux=1024, nuy=256, h_u=1.0, b=256.0, thickness=1.0,
+                        tau=0.52, kc=3.0, beta=2000.0, steps=100000),
+    # small cases for tests: several tiles, ragged sizes, odd grid width
+    "tiny_ragged": dict(nx=77, ny=45, nux=33, nuy=16, h_u=1.0, b=12.0, thickness=1.0,
+                        tau=0.7, kc=0.6, beta=40.0, steps=60),
+    # grid spacing 0.2 below the largest per-step displacement (0.225): some
+    # nodes land inside the old lamina
+    "tiny_fine_grid": dict(nx=48, ny=48, nux=90, nuy=44, h_u=0.2, b=8.0, thickness=0.2,
+                           tau=0.8, kc=1.8, beta=10.0, n_sub=32, steps=40),
+}
+
+
+def preset(name: str, **overrides) -> dict:
+    cfg = dict(PRESETS[name])
+    cfg.update(overrides)
+    return cfg
+
+
+def batch_cases(seed: int = 0, n_kc: int = 8, n_beta: int = 8):
+    """64 (KC, beta) cases on a log grid, KC in [0.1, 4], beta in [50, 5000],
+    each with a lattice edge drawn uniformly from {256, 512, 768, 1024} and a
+    lamina of width edge/8 in a 4b x b grid."""
+    rng = np.random.default_rng(seed)
+    kcs = np.geomspace(0.1, 4.0, n_kc)
+    betas = np.geomspace(50.0, 5000.0, n_beta)
+    sizes = rng.choice([256, 512, 768, 1024], n_kc * n_beta)
+    cases = []
+    for i, kc in enumerate(kcs):
+        for j, beta in enumerate(betas):
+            n = int(sizes[i * n_beta + j])
+            b = n // 8
+            cases.append(dict(nx=n, ny=n, nux=4 * b, nuy=b, h_u=1.0, b=float(b), thickness=1.0,
+                              kc=float(kc), beta=float(beta)))
+    return cases
+
+
+def random_populations(shape, seed: int, base: np.ndarray, spread: float = 0.02) -> np.ndarray:
+    """base * (1 + u), u uniform in [-spread, spread]; base broadcasts over the
+    trailing axes of ``shape`` (first axis = population index)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-spread, spread, size=shape)
+    b = np.asarray(base, dtype=np.float64).reshape((shape[0],) + (1,) * (len(shape) - 1))
+    return b * (1.0 + u)
+
+
+def random_field(shape, seed: int, lo: float, hi: float) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(lo, hi, size=shape)
