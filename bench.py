@@ -1,0 +1,130 @@
+"""Benchmark of the MG-HLBM step on one MI355X.
+
+A step is one structured time step of the whole hot path: lattice
+interpolation nodes from the grid, lattice stream-collide, the grid's
+interface donors and n finite-volume sub-steps, move + refill, wall force.
+Default workload: the 2048^2 lamina case (512 x 128 grid, tau 0.55, KC 1,
+beta 1000), FP64, its full 20000-step run.
+
+Prints one JSON line: lattice MLUPS (whole job), a roofline entry for the
+dominant kernel (lattice stream-collide, HBM bound, 18 s bytes per node
+update, timed with HIP events on its stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES = {"f64": 8, "f32": 4, "f16dev": 2}
+
+
+def cpu_baseline(cfg, steps):
+    """The oracle as it stands, single-threaded, on `steps` steps."""
+    from oracle import oracle as O
+    c = dict(cfg)
+    c.pop("steps", None)
+    c.pop("ckpt_every", None)
+    s = O.Sim(max_steps=steps, **c)
+    t0 = time.perf_counter()
+    s.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": c["nx"] * c["ny"] * steps / dt / 1e6, "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {steps} steps of the same workload, FP64, one thread ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="lamina_2048")
+    ap.add_argument("--storage", default="f64", choices=list(BYTES))
+    ap.add_argument("--timing-steps", type=int, default=400)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.workloads import preset
+
+    cfg = preset(args.workload)
+    steps = args.steps if args.steps is not None else cfg["steps"]
+    W = args.warmup
+    total = W + steps + args.timing_steps
+    torch.cuda.set_device(0)
+    case = H.case_from_preset(cfg, storage=args.storage, max_steps=total)
+    info = case.info()
+    print(f"# workload {args.workload} storage {args.storage} n_sub {info.n_sub} "
+          f"grid nodes {info.nnode} warmup {W} steps {steps}", file=sys.stderr, flush=True)
+
+    case.step(W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    chunk = max(1, steps // 10)
+    while done < steps:
+        n = min(chunk, steps - done)
+        case.step(n)
+        done += n
+        print(f"# {done}/{steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nx, ny = cfg["nx"], cfg["ny"]
+    mlups = nx * ny * steps / dt / 1e6
+
+    # per-kernel HIP-event timing on each kernel's own stream
+    case.timing(True)
+    case.step(args.timing_steps)
+    ms_k1, n_k1 = case.timing_get(H.K_STREAM_COLLIDE)
+    kern = {}
+    for name, kid in (("stream_collide", H.K_STREAM_COLLIDE), ("lattice_from_grid", H.K_LATTICE_FROM_GRID),
+                      ("grid_substeps", H.K_GRID_SUBSTEPS), ("refill", H.K_REFILL), ("force", H.K_FORCE),
+                      ("step", H.K_STEP)):
+        ms, cnt = case.timing_get(kid)
+        kern[name] = round(1000.0 * ms / max(cnt, 1), 3)
+    case.timing(False)
+    avg_s = ms_k1 / 1000.0 / max(n_k1, 1)
+    alg_bytes = 18 * BYTES[args.storage] * nx * ny
+    achieved = alg_bytes / avg_s / 1e9
+    th = None
+    try:
+        th = case.theta()
+    except H.HlbmError:
+        pass
+
+    out = {
+        "metric": "lattice MLUPS (whole MG-HLBM step) + HBM roofline fraction of the stream-collide kernel",
+        "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": W,
+        "ms_per_step": round(1000.0 * dt / steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": args.workload, "nx": nx, "ny": ny, "nux": cfg["nux"], "nuy": cfg["nuy"],
+                   "b": cfg["b"], "tau": cfg["tau"], "kc": cfg["kc"], "beta": cfg["beta"],
+                   "n_sub": info.n_sub, "storage": args.storage},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_stream_collide", "avg_us": round(avg_s * 1e6, 3),
+                     "bytes_per_launch": alg_bytes},
+        "kernel_avg_us": kern,
+        "mlups_total": round((nx * ny + info.n_sub * info.nnode) * steps / dt / 1e6, 2),
+        "theta": None if th is None else [th.real, th.imag],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

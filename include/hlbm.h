@@ -1,0 +1,180 @@
+/*
+ * hlbm.h -- C ABI of the MI355X (gfx950) library for the moving-grid hybrid
+ * lattice Boltzmann method (MG-HLBM) of Di Ilio, Chiappini, Ubertini, Bella
+ * and Succi, "A moving-grid approach for fluid-structure interaction problems
+ * with hybrid lattice Boltzmann method" (arXiv 2006.13631).
+ *
+ * The library advances a thin rigid lamina oscillating as y(t) = A sin(omega t)
+ * in a fluid at rest (Sec. Problem statement): a D2Q9 BGK background lattice
+ * (Eq.(LBE), Eq.(local_eq)), a body-fitted triangular grid that moves with the
+ * lamina and is advanced with the cell-vertex finite-volume scheme Eq.(ulbe)
+ * in n sub-steps per lattice step, the two-way exchange of Eqs.
+ * (postcollision2_s) and (postcollision2_u), the refill of the moved grid
+ * (Sec. Refill procedure), and the force on the lamina from which the
+ * hydrodynamic function Theta of Eq.(force_phasor) is fitted (Sec. 2.1).
+ *
+ * Conventions for every call:
+ *  - Return 0 on success or a negative HLBM_E_* code; no exception or signal
+ *    crosses the ABI. Output arguments are written only on success.
+ *  - Host pointers belong to the caller and are only read or written during
+ *    the call. Device memory belongs to the library (allocated in
+ *    hlbm_create, released in hlbm_destroy).
+ *  - A handle is used by one host thread at a time. Results are
+ *    deterministic: the same configuration and call sequence give the same
+ *    bits on the same GPU.
+ *  - Lattice units: lattice spacing and structured time step are 1, reference
+ *    density 1, c_s^2 = 1/3.
+ */
+#ifndef HLBM_H
+#define HLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define HLBM_OK 0
+#define HLBM_E_ARG -1         /* invalid argument or configuration          */
+#define HLBM_E_NOMEM -2       /* device or host allocation failed           */
+#define HLBM_E_HIP -3         /* HIP runtime error (text in hlbm_last_error) */
+#define HLBM_E_UNSTABLE -4    /* a non-finite force or density was detected  */
+#define HLBM_E_STATE -5       /* call not valid in the handle's state        */
+#define HLBM_E_UNSUPPORTED -6 /* option not implemented in this build        */
+
+/* ---- background lattice boundaries ------------------------------------ */
+#define HLBM_BC_PERIODIC_X_WALLS_Y 0 /* periodic in x; halfway bounce-back walls
+                                        at rest at y = -1/2 and y = ny - 1/2 */
+#define HLBM_BC_PERIODIC 1           /* periodic in x and y                  */
+
+/* ---- storage of the lattice populations ------------------------------- */
+#define HLBM_FP64 0     /* FP64 storage and arithmetic                          */
+#define HLBM_FP32 1     /* FP32 storage and arithmetic                          */
+#define HLBM_FP16_DEV 2 /* FP16 storage of f_i - w_i, FP32 arithmetic           */
+
+/* ---- flags ------------------------------------------------------------- */
+#define HLBM_FLAG_NO_BODY 1 /* grid without the lamina slot; b still sets A and
+                               omega (used to check the moving-grid coupling) */
+
+/* ---- state selectors for hlbm_get_state / hlbm_set_state --------------- */
+#define HLBM_STATE_LATTICE 0 /* double [9][ny][nx]: post-collision f at t_k     */
+#define HLBM_STATE_GRID 1    /* double [9][nux*nuy]: grid f at t_k, node
+                                index j*nux + i                              */
+
+/* Problem and discretisation (Sec. Problem statement, Sec. HLBM).
+ * Grid node (i, j) sits at x = nx/2 + (i - nux/2) h_u (integer division) and
+ * y = (ny-1)/2 + y(t) + (j - (nuy-1)/2) h_u; the lamina of width b and
+ * thickness h_u fills the slot between rows nuy/2-1 and nuy/2 for
+ * |x - nx/2| <= b/2. Derived quantities:
+ *   nu = (tau - 1/2)/3, tau_u = tau - 1/2, A = kc b / (2 pi),
+ *   omega = 2 pi nu beta / b^2, n = n_sub, or when n_sub = 0
+ *   n = max(2, ceil(1/tau_u - 1e-9)), Delta t_u = 1/n. */
+typedef struct hlbm_config {
+  int32_t nx, ny;     /* background lattice nodes                         */
+  int32_t nux, nuy;   /* body-fitted grid nodes; nuy even                 */
+  double h_u;         /* grid spacing in lattice units (0: 1)             */
+  double b;           /* lamina width L                                   */
+  double thickness;   /* lamina thickness T; must equal h_u               */
+  double tau;         /* structured relaxation time tau_s (> 1/2)         */
+  double kc;          /* Keulegan-Carpenter number 2 pi A / L             */
+  double beta;        /* frequency parameter omega L^2 / (2 pi nu)        */
+  int32_t n_sub;      /* grid sub-steps per lattice step (0: automatic)   */
+  int32_t bc;         /* HLBM_BC_*                                        */
+  int32_t storage;    /* HLBM_FP64 | HLBM_FP32 | HLBM_FP16_DEV            */
+  int32_t flags;      /* HLBM_FLAG_*                                      */
+  int32_t ckpt_every; /* adjoint checkpoint window (0: no adjoint)        */
+  int32_t reserved;   /* must be 0                                        */
+  int64_t max_steps;  /* capacity of the force history (steps)           */
+} hlbm_config;
+
+/* Derived parameters and counters of a case. */
+typedef struct hlbm_info {
+  double nu, tau_u, dt_u, A, omega, period, u_max, mach, reynolds, eps;
+  int32_t n_sub, nnode, ntri, n_interface, n_wall, n_wall_edges;
+  int32_t beta_limit_ok; /* 1 if beta < 2.6 eps^-1.6, Eq.(betalimit) */
+  int32_t n_classes;     /* distinct finite-volume stencils on the grid */
+  int64_t step;          /* structured steps taken                      */
+  double y;              /* lamina offset y(t_k)                         */
+  int64_t n_type1, n_type2, n_type3; /* refill counts, summed over steps */
+  int64_t lattice_bytes; /* device bytes of one lattice buffer          */
+} hlbm_info;
+
+typedef struct hlbm hlbm_t;
+
+/* Create a case: validate the configuration, build the grid and its
+ * finite-volume matrices S_ik, C_ik (median-dual control volumes, Eq.(ulbe)),
+ * allocate device buffers and set both grids to rest (f = w_i).
+ * ncases must be 1. Errors: HLBM_E_ARG (invalid configuration: tau <= 1/2,
+ * Delta t_u >= 2 tau_u, grid or its motion leaving the lattice, lamina not
+ * inside the fictitious rectangle, |A omega| >= 1), HLBM_E_NOMEM, HLBM_E_HIP.
+ * On error *out is set to NULL. */
+int hlbm_create(const hlbm_config *cfg, int32_t ncases, hlbm_t **out);
+
+/* Advance nsteps structured steps t_k -> t_{k+1} (Sec. HLBM and Sec. Refill
+ * procedure): lattice interpolation nodes from the grid (Eq.
+ * (postcollision2_s)), lattice stream-collide (Eq.(LBE)), n grid sub-steps
+ * (Eq.(ulbe), Eq.(postcollision2_u)), force, move and refill. Blocks until
+ * the steps are done. HLBM_E_ARG if the force history would overflow
+ * max_steps; HLBM_E_UNSTABLE if a non-finite force appeared. */
+int hlbm_step(hlbm_t *h, int64_t nsteps);
+
+/* Force history and hydrodynamic function (Sec. 2.1, Eq.(force_phasor)).
+ * hist_xy (may be NULL) receives up to cap (Fx, Fy) pairs, entry k at
+ * t = k+1; *n_out (may be NULL) gets the number of entries. If theta is not
+ * NULL, F_y is fitted as a_s sin(omega t) + a_c cos(omega t) over
+ * win_t0 <= t/T < win_t1 (T = 2 pi/omega; the paper uses [1, 4)) and
+ * theta = (a_s, a_c) / ((pi/4) omega^2 b^2 A). HLBM_E_ARG if the window
+ * holds fewer than two samples. */
+int hlbm_force(hlbm_t *h, int32_t case_id, double *hist_xy, int64_t cap,
+               int64_t *n_out, double win_t0, double win_t1, double theta[2]);
+
+/* Discrete adjoint: gradient of J = sum_k dJ_dFy[k] F_y(t_{k+1}) with respect
+ * to (A, omega, tau). Not available in this build: returns
+ * HLBM_E_UNSUPPORTED. */
+int hlbm_adjoint(hlbm_t *h, int32_t case_id, const double *dJ_dFy, int64_t n,
+                 double grad_A_omega_tau[3]);
+
+/* Copy a state array to or from host memory, converted to or from FP64.
+ * which = HLBM_STATE_LATTICE or HLBM_STATE_GRID; bytes must equal the
+ * array size in doubles times 8 (HLBM_E_ARG otherwise). */
+int hlbm_get_state(hlbm_t *h, int32_t case_id, int32_t which, void *host_buf,
+                   size_t bytes);
+int hlbm_set_state(hlbm_t *h, int32_t case_id, int32_t which,
+                   const void *host_buf, size_t bytes);
+
+/* Derived parameters and counters. */
+int hlbm_info_get(hlbm_t *h, int32_t case_id, hlbm_info *out);
+
+/* The grid's finite-volume matrices as assembled for the GPU, dense per node:
+ * nbr [nnode][kmax] (-1 padded, slot 0 = the node itself), S [nnode][9][kmax]
+ * streaming matrix S_ik, C [nnode][kmax] collision matrix C_ik (Eq.(ulbe)).
+ * HLBM_E_ARG if kmax is smaller than the largest stencil. */
+int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
+                     double *C);
+
+/* Per-kernel timing with HIP events recorded on the stream each kernel is
+ * launched on. hlbm_timing(h, 1) clears the accumulators and turns event
+ * recording on for later hlbm_step calls; 0 turns it off. hlbm_timing_get
+ * returns for kernel id (HLBM_K_*) the summed milliseconds and launch count. */
+#define HLBM_K_STREAM_COLLIDE 0 /* lattice stream-collide, Eq.(LBE)            */
+#define HLBM_K_LATTICE_FROM_GRID 1 /* Eq.(postcollision2_s)                    */
+#define HLBM_K_GRID_SUBSTEPS 2  /* donors + n sub-steps, Eqs.(ulbe),(postcollision2_u) */
+#define HLBM_K_REFILL 3         /* move + refill                               */
+#define HLBM_K_FORCE 4          /* wall force                                  */
+#define HLBM_K_STEP 5           /* whole structured step                       */
+int hlbm_timing(hlbm_t *h, int32_t on);
+int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count);
+
+/* Release the device memory and streams of the handle (NULL is a no-op). */
+void hlbm_destroy(hlbm_t *h);
+
+/* Text of the last error on this handle, or of the last failed
+ * hlbm_create when h is NULL. Valid until the next call on the handle. */
+const char *hlbm_last_error(const hlbm_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,668 @@
+// Host runtime and C ABI of the gfx950 HLBM library (see include/hlbm.h).
+//
+// One case owns: two lattice buffers (ping-pong), two grid buffers, the
+// structured-derived interface values, the stencil classes of the grid, a
+// per-step table of FP64 scalars computed here (motion, fictitious-rectangle
+// bounds, wall velocity at each sub-step) and the force history. A step runs
+// the lattice update and the grid path on two HIP streams of default
+// priority: within a step the grid path reads only the lattice buffer of
+// t_k, which the lattice kernel only reads, so the two proceed concurrently.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hlbm.h"
+#include "kernels.h"
+
+namespace mghlbm {
+namespace {
+
+std::string g_create_error;
+
+constexpr double kMargin = 2.0;  // inset of the fictitious rectangle (lattice units)
+
+struct Derived {
+  double nu, tau_u, A, omega, xc, yc;
+  int n;
+};
+
+// Derived quantities (Sec. Problem statement; viscosity matching of Sec. 3).
+Derived derive(const hlbm_config &c) {
+  Derived d;
+  d.nu = (c.tau - 0.5) / 3.0;
+  d.tau_u = c.tau - 0.5;
+  const bool has_grid = c.nux > 0 || c.nuy > 0;
+  if (has_grid && c.b > 0.0) {
+    d.A = c.kc * c.b / (2.0 * M_PI);
+    d.omega = 2.0 * M_PI * d.nu * c.beta / (c.b * c.b);
+  } else {
+    d.A = 0.0;
+    d.omega = 0.0;
+  }
+  if (c.n_sub > 0) {
+    d.n = c.n_sub;
+  } else {
+    const int n = (int)std::ceil(1.0 / d.tau_u - 1e-9);
+    d.n = n < 2 ? 2 : n;
+  }
+  d.xc = (double)(c.nx / 2);
+  d.yc = 0.5 * (double)(c.ny - 1);
+  return d;
+}
+
+class CaseBase {
+ public:
+  virtual ~CaseBase() = default;
+  virtual int step(int64_t n) = 0;
+  virtual int get_state(int which, void *buf, size_t bytes) = 0;
+  virtual int set_state(int which, const void *buf, size_t bytes) = 0;
+  virtual int force(double *hist, int64_t cap, int64_t *n_out, double t0, double t1, double th[2]) = 0;
+  virtual int info(hlbm_info *o) = 0;
+  virtual int stencil(int kmax, int32_t *nbr, double *S, double *C) = 0;
+  virtual int timing(int on) = 0;
+  virtual int timing_get(int kernel, double *ms, int64_t *count) = 0;
+  std::string err;
+};
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      err = std::string(#expr) + ": " + hipGetErrorString(e_);                         \
+      return HLBM_E_HIP;                                                              \
+    }                                                                                 \
+  } while (0)
+
+template <class T, class R>
+class Case final : public CaseBase {
+ public:
+  ~Case() override { release(); }
+
+  int init(const hlbm_config &c) {
+    cfg_ = c;
+    d_ = derive(c);
+    h_ = c.h_u > 0.0 ? c.h_u : 1.0;
+    has_grid_ = c.nux > 0 || c.nuy > 0;
+    body_ = has_grid_ && c.b > 0.0 && !(c.flags & HLBM_FLAG_NO_BODY);
+    plane_ = (size_t)c.nx * c.ny;
+    if (has_grid_) {
+      std::string e;
+      if (!build_grid(c.nux, c.nuy, h_, c.b, body_, &grid_, &e)) {
+        err = e;
+        return HLBM_E_ARG;
+      }
+    }
+    HIPCHK(hipStreamCreateWithFlags(&s_main_, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&s_grid_, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+    HIPCHK(alloc(&lat_[0], 9 * plane_ * sizeof(T)));
+    HIPCHK(alloc(&lat_[1], 9 * plane_ * sizeof(T)));
+    const int64_t cap = std::max<int64_t>(c.max_steps, 1);
+    HIPCHK(alloc(&hist_, 2 * cap * sizeof(double)));
+    HIPCHK(alloc(&dk_, sizeof(int64_t)));
+    HIPCHK(alloc(&flag_, sizeof(int)));
+    HIPCHK(alloc(&counts_, 2 * sizeof(unsigned long long)));
+    HIPCHK(hipMemset(dk_, 0, sizeof(int64_t)));
+    HIPCHK(hipMemset(flag_, 0, sizeof(int)));
+    HIPCHK(hipMemset(counts_, 0, 2 * sizeof(unsigned long long)));
+    HIPCHK(hipMemset(hist_, 0, 2 * cap * sizeof(double)));
+    const int N = has_grid_ ? grid_.nnode : 0;
+    if (has_grid_) {
+      for (int i = 0; i < 2; ++i) HIPCHK(alloc(&gbuf_[i], 9 * (size_t)N * sizeof(R)));
+      HIPCHK(alloc(&star_f_, 9 * (size_t)N * sizeof(R)));
+      HIPCHK(alloc(&star_n_, 9 * (size_t)N * sizeof(R)));
+      HIPCHK(hipMemset(star_f_, 0, 9 * (size_t)N * sizeof(R)));
+      HIPCHK(hipMemset(star_n_, 0, 9 * (size_t)N * sizeof(R)));
+      std::vector<GridClass<R>> tab(grid_.classes.size());
+      for (size_t i = 0; i < tab.size(); ++i) {
+        const GridClass<double> &g = grid_.classes[i];
+        GridClass<R> &t = tab[i];
+        std::memset(&t, 0, sizeof(t));
+        t.k = g.k;
+        t.type = g.type;
+        for (int s = 0; s < KMAX; ++s) {
+          t.off[s] = g.off[s];
+          t.C[s] = (R)g.C[s];
+          for (int q = 0; q < 9; ++q) t.S[q][s] = (R)g.S[q][s];
+        }
+      }
+      HIPCHK(upload(&tab_, tab.data(), tab.size() * sizeof(GridClass<R>)));
+      HIPCHK(upload(&cls_, grid_.cls.data(), grid_.cls.size() * sizeof(int)));
+      HIPCHK(upload(&iface_, grid_.iface.data(), grid_.iface.size() * sizeof(int)));
+      HIPCHK(upload(&wall_, grid_.wall.data(), grid_.wall.size() * sizeof(WallEdge)));
+      // per-step scalars for k = 0 .. max_steps, wall velocity per sub-step
+      std::vector<StepParams> P(cap + 1);
+      for (int64_t k = 0; k <= cap; ++k) P[k] = params_at(k);
+      HIPCHK(upload(&params_, P.data(), P.size() * sizeof(StepParams)));
+      std::vector<R> uw((size_t)cap * d_.n);
+      for (int64_t k = 0; k < cap; ++k)
+        for (int m = 0; m < d_.n; ++m) {
+          const double t = (double)k + (double)(m + 1) / (double)d_.n;
+          uw[(size_t)k * d_.n + m] = (R)(d_.A * d_.omega * std::cos(d_.omega * t));
+        }
+      HIPCHK(upload(&uw_, uw.data(), uw.size() * sizeof(R)));
+      int x0 = P[0].ix0, x1 = P[0].ix1;
+      k2_x0_ = x0;
+      k2_w_ = std::max(1, x1 - x0 + 1);
+      int hmax = 1;
+      for (int64_t k = 0; k <= cap; ++k)
+        hmax = std::max(hmax, std::max(P[k].iy1, P[k].piy1) - std::min(P[k].iy0, P[k].piy0) + 1);
+      k2_h_ = hmax;
+    }
+    Kernels<T, R>::fill_rest((T *)lat_[0], plane_, has_grid_ ? (R *)gbuf_[0] : nullptr, N, s_main_);
+    Kernels<T, R>::fill_rest((T *)lat_[1], plane_, has_grid_ ? (R *)gbuf_[1] : nullptr, N, s_main_);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s_main_));
+    return HLBM_OK;
+  }
+
+  int step(int64_t nsteps) override {
+    if (nsteps < 0) return fail(HLBM_E_ARG, "nsteps < 0");
+    if (has_grid_ && k_ + nsteps > cfg_.max_steps) return fail(HLBM_E_ARG, "force history would exceed max_steps");
+    for (int64_t it = 0; it < nsteps; ++it) {
+      CaseView<T, R> v = view();
+      if (timing_) HIPCHK(hipEventRecord(tev_[0], s_main_));
+      if (has_grid_) {
+        const R *g = (const R *)gbuf_[gcur_];
+        Kernels<T, R>::lattice_from_grid(v, g, s_main_);
+        if (timing_) HIPCHK(hipEventRecord(tev_[1], s_main_));
+        HIPCHK(hipEventRecord(ev_fork_, s_main_));
+        HIPCHK(hipStreamWaitEvent(s_grid_, ev_fork_, 0));
+        Kernels<T, R>::stream_collide(v, s_main_);
+        if (timing_) HIPCHK(hipEventRecord(tev_[2], s_main_));
+        // grid path
+        if (timing_) HIPCHK(hipEventRecord(tev_[3], s_grid_));
+        Kernels<T, R>::interface_donors(v, s_grid_);
+        int cur = gcur_;
+        for (int m = 0; m < d_.n; ++m) {
+          Kernels<T, R>::grid_substep(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, s_grid_);
+          cur = 1 - cur;
+        }
+        if (timing_) HIPCHK(hipEventRecord(tev_[4], s_grid_));
+        Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
+        if (timing_) HIPCHK(hipEventRecord(tev_[5], s_grid_));
+        Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_);
+        if (timing_) HIPCHK(hipEventRecord(tev_[6], s_grid_));
+        gcur_ = 1 - cur;
+        HIPCHK(hipEventRecord(ev_join_, s_grid_));
+        HIPCHK(hipStreamWaitEvent(s_main_, ev_join_, 0));
+      } else {
+        if (timing_) HIPCHK(hipEventRecord(tev_[1], s_main_));
+        Kernels<T, R>::stream_collide(v, s_main_);
+        if (timing_) HIPCHK(hipEventRecord(tev_[2], s_main_));
+      }
+      if (timing_) HIPCHK(hipEventRecord(tev_[7], s_main_));
+      HIPCHK(hipGetLastError());
+      std::swap(lat_[0], lat_[1]);
+      ++k_;
+      if (timing_) HIPCHK(harvest());
+    }
+    HIPCHK(hipStreamSynchronize(s_main_));
+    if (has_grid_) {
+      int flag = 0;
+      HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
+      if (flag) return fail(HLBM_E_UNSTABLE, "non-finite force on the lamina");
+    }
+    return HLBM_OK;
+  }
+
+  int get_state(int which, void *buf, size_t bytes) override {
+    HIPCHK(hipStreamSynchronize(s_main_));
+    if (which == HLBM_STATE_LATTICE) {
+      if (bytes != 9 * plane_ * sizeof(double)) return fail(HLBM_E_ARG, "lattice state size mismatch");
+      double *tmp = nullptr;
+      HIPCHK(hipMalloc(&tmp, bytes));
+      Kernels<T, R>::lattice_to_f64((const T *)lat_[0], tmp, plane_, s_main_);
+      hipError_t e = hipMemcpyAsync(buf, tmp, bytes, hipMemcpyDeviceToHost, s_main_);
+      if (e == hipSuccess) e = hipStreamSynchronize(s_main_);
+      (void)hipFree(tmp);
+      HIPCHK(e);
+      return HLBM_OK;
+    }
+    if (which == HLBM_STATE_GRID) {
+      if (!has_grid_) return fail(HLBM_E_STATE, "case has no grid");
+      const size_t n = 9 * (size_t)grid_.nnode;
+      if (bytes != n * sizeof(double)) return fail(HLBM_E_ARG, "grid state size mismatch");
+      std::vector<R> tmp(n);
+      HIPCHK(hipMemcpy(tmp.data(), gbuf_[gcur_], n * sizeof(R), hipMemcpyDeviceToHost));
+      double *out = (double *)buf;
+      for (size_t i = 0; i < n; ++i) out[i] = (double)tmp[i];
+      return HLBM_OK;
+    }
+    return fail(HLBM_E_ARG, "unknown state selector");
+  }
+
+  int set_state(int which, const void *buf, size_t bytes) override {
+    HIPCHK(hipStreamSynchronize(s_main_));
+    if (which == HLBM_STATE_LATTICE) {
+      if (bytes != 9 * plane_ * sizeof(double)) return fail(HLBM_E_ARG, "lattice state size mismatch");
+      double *tmp = nullptr;
+      HIPCHK(hipMalloc(&tmp, bytes));
+      hipError_t e = hipMemcpyAsync(tmp, buf, bytes, hipMemcpyHostToDevice, s_main_);
+      if (e == hipSuccess) {
+        Kernels<T, R>::lattice_from_f64(tmp, (T *)lat_[0], plane_, s_main_);
+        e = hipStreamSynchronize(s_main_);
+      }
+      (void)hipFree(tmp);
+      HIPCHK(e);
+      return HLBM_OK;
+    }
+    if (which == HLBM_STATE_GRID) {
+      if (!has_grid_) return fail(HLBM_E_STATE, "case has no grid");
+      const size_t n = 9 * (size_t)grid_.nnode;
+      if (bytes != n * sizeof(double)) return fail(HLBM_E_ARG, "grid state size mismatch");
+      std::vector<R> tmp(n);
+      const double *in = (const double *)buf;
+      for (size_t i = 0; i < n; ++i) tmp[i] = (R)in[i];
+      HIPCHK(hipMemcpy(gbuf_[gcur_], tmp.data(), n * sizeof(R), hipMemcpyHostToDevice));
+      return HLBM_OK;
+    }
+    return fail(HLBM_E_ARG, "unknown state selector");
+  }
+
+  // Single-harmonic least-squares fit of F_y (Sec. 2.1) and Theta from
+  // Eq.(force_phasor): a_s + i a_c = (pi/4) rho omega^2 L^2 A Theta, rho = 1.
+  int force(double *hist, int64_t cap, int64_t *n_out, double t0, double t1, double th[2]) override {
+    HIPCHK(hipStreamSynchronize(s_main_));
+    const int64_t n = has_grid_ ? k_ : 0;
+    std::vector<double> hbuf(2 * std::max<int64_t>(n, 1));
+    if (n > 0) HIPCHK(hipMemcpy(hbuf.data(), hist_, 2 * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (th) {
+      if (!(d_.omega > 0.0)) return fail(HLBM_E_ARG, "no oscillation to fit");
+      const double period = 2.0 * M_PI / d_.omega;
+      double ss = 0, sc = 0, cc = 0, sf = 0, cf = 0;
+      int64_t cnt = 0;
+      for (int64_t k = 0; k < n; ++k) {
+        const double t = (double)(k + 1);
+        if (t < t0 * period || t >= t1 * period) continue;
+        const double sn = std::sin(d_.omega * t), cs = std::cos(d_.omega * t), F = hbuf[2 * k + 1];
+        ss += sn * sn;
+        sc += sn * cs;
+        cc += cs * cs;
+        sf += sn * F;
+        cf += cs * F;
+        ++cnt;
+      }
+      const double det = ss * cc - sc * sc;
+      if (cnt < 2 || !(std::fabs(det) > 0.0)) return fail(HLBM_E_ARG, "fit window holds fewer than two samples");
+      const double norm = 0.25 * M_PI * d_.omega * d_.omega * cfg_.b * cfg_.b * d_.A;
+      th[0] = (sf * cc - cf * sc) / det / norm;
+      th[1] = (cf * ss - sf * sc) / det / norm;
+    }
+    if (hist) std::memcpy(hist, hbuf.data(), 2 * std::min(cap, n) * sizeof(double));
+    if (n_out) *n_out = n;
+    return HLBM_OK;
+  }
+
+  int info(hlbm_info *o) override {
+    std::memset(o, 0, sizeof(*o));
+    o->nu = d_.nu;
+    o->tau_u = d_.tau_u;
+    o->dt_u = 1.0 / (double)d_.n;
+    o->A = d_.A;
+    o->omega = d_.omega;
+    o->period = d_.omega > 0.0 ? 2.0 * M_PI / d_.omega : 0.0;
+    o->u_max = d_.A * d_.omega;
+    o->mach = o->u_max * std::sqrt(3.0);
+    o->reynolds = d_.nu > 0.0 ? o->u_max * cfg_.b / d_.nu : 0.0;
+    o->eps = cfg_.b > 0.0 ? d_.A / cfg_.b : 0.0;
+    o->beta_limit_ok = o->eps > 0.0 ? (cfg_.beta < 2.6 * std::pow(o->eps, -1.6)) : 1;
+    o->n_sub = d_.n;
+    o->step = k_;
+    o->y = d_.A * std::sin(d_.omega * (double)k_);
+    o->lattice_bytes = (int64_t)(9 * plane_ * sizeof(T));
+    if (has_grid_) {
+      o->nnode = grid_.nnode;
+      o->ntri = grid_.ntri;
+      o->n_interface = (int)grid_.iface.size();
+      o->n_wall_edges = (int)grid_.wall.size();
+      o->n_classes = (int)grid_.classes.size();
+      for (int t : grid_.type) o->n_wall += (t == NODE_WALL);
+      unsigned long long cnt[2];
+      HIPCHK(hipStreamSynchronize(s_main_));
+      HIPCHK(hipMemcpy(cnt, counts_, sizeof(cnt), hipMemcpyDeviceToHost));
+      o->n_type1 = (int64_t)cnt[0];
+      o->n_type2 = (int64_t)cnt[1];
+      o->n_type3 = k_ * (int64_t)(grid_.nnode - o->n_wall) - o->n_type1 - o->n_type2;
+    }
+    return HLBM_OK;
+  }
+
+  int stencil(int kmax, int32_t *nbr, double *S, double *C) override {
+    if (!has_grid_) return fail(HLBM_E_STATE, "case has no grid");
+    int need = 0;
+    for (const auto &c : grid_.classes) need = std::max(need, c.k);
+    if (kmax < need) return fail(HLBM_E_ARG, "kmax smaller than the largest stencil");
+    for (int p = 0; p < grid_.nnode; ++p) {
+      const GridClass<double> &c = grid_.classes[grid_.cls[p]];
+      for (int s = 0; s < kmax; ++s) {
+        const bool in = s < c.k;
+        if (nbr) nbr[(size_t)p * kmax + s] = in ? p + c.off[s] : -1;
+        if (C) C[(size_t)p * kmax + s] = in ? c.C[s] : 0.0;
+        if (S)
+          for (int q = 0; q < 9; ++q) S[((size_t)p * 9 + q) * kmax + s] = in ? c.S[q][s] : 0.0;
+      }
+    }
+    return HLBM_OK;
+  }
+
+  int timing(int on) override {
+    HIPCHK(hipStreamSynchronize(s_main_));
+    if (on && !tev_[0])
+      for (auto &e : tev_) HIPCHK(hipEventCreate(&e));
+    for (int i = 0; i < 6; ++i) {
+      tms_[i] = 0.0;
+      tcount_[i] = 0;
+    }
+    timing_ = on != 0;
+    return HLBM_OK;
+  }
+
+  int timing_get(int kernel, double *ms, int64_t *count) override {
+    if (kernel < 0 || kernel > 5) return fail(HLBM_E_ARG, "unknown kernel id");
+    if (ms) *ms = tms_[kernel];
+    if (count) *count = tcount_[kernel];
+    return HLBM_OK;
+  }
+
+ private:
+  template <class P>
+  hipError_t alloc(P **p, size_t bytes) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 256));
+    if (e == hipSuccess) owned_.push_back(q);
+    *p = (P *)q;
+    return e;
+  }
+  template <class P>
+  hipError_t upload(P **p, const void *src, size_t bytes) {
+    hipError_t e = alloc(p, bytes);
+    if (e == hipSuccess && bytes && src) e = hipMemcpy((void *)*p, src, bytes, hipMemcpyHostToDevice);
+    return e;
+  }
+  void release() {
+    if (s_main_) (void)hipStreamSynchronize(s_main_);
+    if (s_grid_) (void)hipStreamSynchronize(s_grid_);
+    for (void *p : owned_) (void)hipFree(p);
+    owned_.clear();
+    for (auto &e : tev_)
+      if (e) (void)hipEventDestroy(e);
+    if (ev_fork_) (void)hipEventDestroy(ev_fork_);
+    if (ev_join_) (void)hipEventDestroy(ev_join_);
+    if (s_main_) (void)hipStreamDestroy(s_main_);
+    if (s_grid_) (void)hipStreamDestroy(s_grid_);
+  }
+  int fail(int code, const char *msg) {
+    err = msg;
+    return code;
+  }
+
+  double motion(int64_t k) const { return d_.A * std::sin(d_.omega * (double)k); }
+
+  // Fictitious rectangle: the grid's node bounding box at offset y, inset by
+  // two lattice units; lattice node (i, j) is inside when the closed
+  // rectangle holds it, i.e. ceil(x0) <= i <= floor(x1), same in y.
+  void rect(double y, int &ix0, int &ix1, int &iy0, int &iy1) const {
+    const double rx0 = d_.xc + (double)(0 - cfg_.nux / 2) * h_ + kMargin;
+    const double rx1 = d_.xc + (double)(cfg_.nux - 1 - cfg_.nux / 2) * h_ - kMargin;
+    const double ry0 = d_.yc + y + (0.0 - 0.5 * (double)(cfg_.nuy - 1)) * h_ + kMargin;
+    const double ry1 = d_.yc + y + ((double)(cfg_.nuy - 1) - 0.5 * (double)(cfg_.nuy - 1)) * h_ - kMargin;
+    ix0 = (int)std::ceil(rx0);
+    ix1 = (int)std::floor(rx1);
+    iy0 = (int)std::ceil(ry0);
+    iy1 = (int)std::floor(ry1);
+  }
+
+  StepParams params_at(int64_t k) const {
+    StepParams P;
+    P.y = motion(k);
+    P.y1 = motion(k + 1);
+    const double yp = k > 0 ? motion(k - 1) : P.y;
+    P.ybase = d_.yc + P.y;
+    P.ybase1 = d_.yc + P.y1;
+    rect(P.y, P.ix0, P.ix1, P.iy0, P.iy1);
+    rect(yp, P.pix0, P.pix1, P.piy0, P.piy1);
+    return P;
+  }
+
+  CaseView<T, R> view() const {
+    CaseView<T, R> v{};
+    v.A = (const T *)lat_[0];
+    v.B = (T *)lat_[1];
+    v.nx = cfg_.nx;
+    v.ny = cfg_.ny;
+    v.periodic_y = cfg_.bc == HLBM_BC_PERIODIC;
+    v.inv_tau = (R)(1.0 / cfg_.tau);
+    v.g_post = (R)(2.0 * (cfg_.tau - 1.0) / (2.0 * cfg_.tau - 1.0));
+    v.k_neq = (R)(1.0 - 1.0 / (2.0 * cfg_.tau));
+    v.has_grid = has_grid_;
+    if (has_grid_) {
+      v.nux = cfg_.nux;
+      v.nuy = cfg_.nuy;
+      v.nnode = grid_.nnode;
+      v.n_iface = (int)grid_.iface.size();
+      v.n_wall_edges = (int)grid_.wall.size();
+      v.n_sub = d_.n;
+      v.h = h_;
+      v.xc = d_.xc;
+      v.yc = d_.yc;
+      v.half_b = 0.5 * grid_.b;
+      v.half_T = 0.5 * grid_.T;
+      v.body = body_;
+      v.cls = cls_;
+      v.tab = tab_;
+      v.iface = iface_;
+      v.wall = wall_;
+      v.star_f = star_f_;
+      v.star_n = star_n_;
+      v.dt_u = (R)(1.0 / (double)d_.n);
+      v.dt_over_tau_u = (R)((1.0 / (double)d_.n) / d_.tau_u);
+      v.uw = uw_;
+      v.params = params_;
+      v.dk = dk_;
+      v.hist = hist_;
+      v.flag = flag_;
+      v.counts = counts_;
+      v.k2_x0 = k2_x0_;
+      v.k2_w = k2_w_;
+      v.k2_h = k2_h_;
+    }
+    return v;
+  }
+
+  hipError_t harvest() {
+    hipError_t e = hipEventSynchronize(tev_[7]);
+    if (e != hipSuccess) return e;
+    auto add = [&](int id, hipEvent_t a, hipEvent_t b) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+        tms_[id] += ms;
+        tcount_[id] += 1;
+      }
+    };
+    add(HLBM_K_STREAM_COLLIDE, tev_[1], tev_[2]);
+    if (has_grid_) {
+      add(HLBM_K_LATTICE_FROM_GRID, tev_[0], tev_[1]);
+      add(HLBM_K_GRID_SUBSTEPS, tev_[3], tev_[4]);
+      add(HLBM_K_REFILL, tev_[4], tev_[5]);
+      add(HLBM_K_FORCE, tev_[5], tev_[6]);
+    }
+    add(HLBM_K_STEP, tev_[0], tev_[7]);
+    return hipSuccess;
+  }
+
+  hlbm_config cfg_{};
+  Derived d_{};
+  double h_ = 1.0;
+  bool has_grid_ = false, body_ = false;
+  size_t plane_ = 0;
+  HostGrid grid_;
+  hipStream_t s_main_ = nullptr, s_grid_ = nullptr;
+  hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+  hipEvent_t tev_[8] = {};
+  bool timing_ = false;
+  double tms_[6] = {};
+  int64_t tcount_[6] = {};
+  std::vector<void *> owned_;
+  void *lat_[2] = {nullptr, nullptr};
+  void *gbuf_[2] = {nullptr, nullptr};
+  int gcur_ = 0;
+  R *star_f_ = nullptr, *star_n_ = nullptr;
+  GridClass<R> *tab_ = nullptr;
+  int *cls_ = nullptr, *iface_ = nullptr;
+  WallEdge *wall_ = nullptr;
+  StepParams *params_ = nullptr;
+  R *uw_ = nullptr;
+  double *hist_ = nullptr;
+  int64_t *dk_ = nullptr;
+  int *flag_ = nullptr;
+  unsigned long long *counts_ = nullptr;
+  int k2_x0_ = 0, k2_w_ = 1, k2_h_ = 1;
+  int64_t k_ = 0;
+};
+
+// Configuration checks shared by all storage types (mirrors the geometric
+// requirements stated in hlbm.h).
+int validate(const hlbm_config &c, std::string *err) {
+  if (c.nx < 3 || c.ny < 3) { *err = "lattice needs nx, ny >= 3"; return HLBM_E_ARG; }
+  if (!(c.tau > 0.5)) { *err = "tau must exceed 1/2"; return HLBM_E_ARG; }
+  if (c.bc != HLBM_BC_PERIODIC_X_WALLS_Y && c.bc != HLBM_BC_PERIODIC) { *err = "unknown bc"; return HLBM_E_ARG; }
+  if (c.storage < HLBM_FP64 || c.storage > HLBM_FP16_DEV) { *err = "unknown storage"; return HLBM_E_ARG; }
+  if (c.max_steps < 0 || c.n_sub < 0 || c.reserved != 0) { *err = "invalid counts"; return HLBM_E_ARG; }
+  if (c.flags & ~HLBM_FLAG_NO_BODY) { *err = "unknown flags"; return HLBM_E_ARG; }
+  const bool has_grid = c.nux > 0 || c.nuy > 0;
+  if (!has_grid) return HLBM_OK;
+  const Derived d = derive(c);
+  const double h = c.h_u > 0.0 ? c.h_u : 1.0;
+  const bool body = c.b > 0.0 && !(c.flags & HLBM_FLAG_NO_BODY);
+  if (body && std::fabs(c.thickness - h) > 1e-12 * h) { *err = "lamina thickness must equal h_u"; return HLBM_E_ARG; }
+  if (!(1.0 / (double)d.n < 2.0 * d.tau_u)) { *err = "grid sub-step violates Delta t_u < 2 tau_u"; return HLBM_E_ARG; }
+  if (c.nux < 4 || c.nuy < 4 || (c.nuy % 2)) { *err = "grid needs nux >= 4 and even nuy >= 4"; return HLBM_E_ARG; }
+  const double hx = (double)(c.nux / 2) * h, hxr = (double)(c.nux - 1 - c.nux / 2) * h;
+  const double hy = 0.5 * (double)(c.nuy - 1) * h;
+  if (d.xc - hx < 1.0 || d.xc + hxr > (double)c.nx - 2.0) { *err = "grid leaves the lattice in x"; return HLBM_E_ARG; }
+  if (c.bc == HLBM_BC_PERIODIC_X_WALLS_Y &&
+      (d.yc - hy - std::fabs(d.A) < 1.0 || d.yc + hy + std::fabs(d.A) > (double)c.ny - 2.0)) {
+    *err = "grid motion leaves the lattice in y";
+    return HLBM_E_ARG;
+  }
+  if (body && (0.5 * c.b + 1.0 > hx - kMargin - 1.0 || 0.5 * c.b + 1.0 > hxr - kMargin - 1.0 ||
+               0.5 * h + 1.0 > hy - kMargin - 1.0)) {
+    *err = "lamina does not fit inside the fictitious rectangle";
+    return HLBM_E_ARG;
+  }
+  if (!(std::fabs(d.A * d.omega) < 1.0)) { *err = "lamina speed must stay below one lattice unit per step"; return HLBM_E_ARG; }
+  return HLBM_OK;
+}
+
+}  // namespace
+}  // namespace mghlbm
+
+struct hlbm {
+  std::unique_ptr<mghlbm::CaseBase> c;
+};
+
+extern "C" {
+
+int hlbm_create(const hlbm_config *cfg, int32_t ncases, hlbm_t **out) {
+  using namespace mghlbm;
+  if (out) *out = nullptr;
+  if (!cfg || !out) { g_create_error = "null argument"; return HLBM_E_ARG; }
+  if (ncases != 1) { g_create_error = "only ncases = 1 is supported"; return HLBM_E_UNSUPPORTED; }
+  std::string e;
+  int rc = validate(*cfg, &e);
+  if (rc != HLBM_OK) { g_create_error = e; return rc; }
+  std::unique_ptr<CaseBase> c;
+  try {
+    if (cfg->storage == HLBM_FP64) {
+      auto p = std::make_unique<Case<double, double>>();
+      rc = p->init(*cfg);
+      c = std::move(p);
+    } else if (cfg->storage == HLBM_FP32) {
+      auto p = std::make_unique<Case<float, float>>();
+      rc = p->init(*cfg);
+      c = std::move(p);
+    } else {
+      auto p = std::make_unique<Case<__half, float>>();
+      rc = p->init(*cfg);
+      c = std::move(p);
+    }
+  } catch (const std::bad_alloc &) {
+    g_create_error = "host allocation failed";
+    return HLBM_E_NOMEM;
+  }
+  if (rc != HLBM_OK) {
+    g_create_error = c->err;
+    return rc == HLBM_E_HIP && g_create_error.find("out of memory") != std::string::npos ? HLBM_E_NOMEM : rc;
+  }
+  hlbm_t *h = new (std::nothrow) hlbm_t;
+  if (!h) { g_create_error = "host allocation failed"; return HLBM_E_NOMEM; }
+  h->c = std::move(c);
+  *out = h;
+  return HLBM_OK;
+}
+
+int hlbm_step(hlbm_t *h, int64_t nsteps) {
+  if (!h) return HLBM_E_ARG;
+  return h->c->step(nsteps);
+}
+
+int hlbm_force(hlbm_t *h, int32_t case_id, double *hist_xy, int64_t cap, int64_t *n_out, double win_t0,
+               double win_t1, double theta[2]) {
+  if (!h || case_id != 0 || cap < 0) return HLBM_E_ARG;
+  return h->c->force(hist_xy, cap, n_out, win_t0, win_t1, theta);
+}
+
+int hlbm_adjoint(hlbm_t *h, int32_t case_id, const double *dJ_dFy, int64_t n, double grad[3]) {
+  (void)case_id;
+  (void)dJ_dFy;
+  (void)n;
+  (void)grad;
+  if (!h) return HLBM_E_ARG;
+  h->c->err = "adjoint not available in this build";
+  return HLBM_E_UNSUPPORTED;
+}
+
+int hlbm_get_state(hlbm_t *h, int32_t case_id, int32_t which, void *buf, size_t bytes) {
+  if (!h || case_id != 0 || !buf) return HLBM_E_ARG;
+  return h->c->get_state(which, buf, bytes);
+}
+
+int hlbm_set_state(hlbm_t *h, int32_t case_id, int32_t which, const void *buf, size_t bytes) {
+  if (!h || case_id != 0 || !buf) return HLBM_E_ARG;
+  return h->c->set_state(which, buf, bytes);
+}
+
+int hlbm_info_get(hlbm_t *h, int32_t case_id, hlbm_info *out) {
+  if (!h || case_id != 0 || !out) return HLBM_E_ARG;
+  return h->c->info(out);
+}
+
+int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S, double *C) {
+  if (!h || kmax <= 0) return HLBM_E_ARG;
+  return h->c->stencil(kmax, nbr, S, C);
+}
+
+int hlbm_timing(hlbm_t *h, int32_t on) {
+  if (!h) return HLBM_E_ARG;
+  return h->c->timing(on);
+}
+
+int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count) {
+  if (!h) return HLBM_E_ARG;
+  return h->c->timing_get(kernel, total_ms, count);
+}
+
+void hlbm_destroy(hlbm_t *h) { delete h; }
+
+const char *hlbm_last_error(const hlbm_t *h) {
+  if (!h) return mghlbm::g_create_error.c_str();
+  return h->c->err.c_str();
+}
+
+}  // extern "C"

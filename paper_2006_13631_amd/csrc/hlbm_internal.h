@@ -1,0 +1,65 @@
+// Internal declarations of the gfx950 HLBM library: device-side data layouts
+// shared by the host runtime and the kernels. Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mghlbm {
+
+constexpr int KMAX = 8;  // finite-volume stencil slots per grid node (self first)
+
+enum NodeType : int { NODE_INTERIOR = 0, NODE_INTERFACE = 1, NODE_WALL = 2 };
+
+// Per-structured-step scalars, computed once on the host in FP64 so the
+// discrete decisions (node status, donor cells) use the same bits as any
+// other FP64 implementation of the same formulas.
+struct StepParams {
+  double y;      // lamina offset y(t_k) = A sin(omega k)
+  double y1;     // y(t_{k+1})
+  double ybase;  // yc + y(t_k): absolute y of the grid centre line at t_k
+  double ybase1; // yc + y(t_{k+1})
+  int ix0, ix1, iy0, iy1;      // lattice nodes inside the fictitious rectangle at t_k
+  int pix0, pix1, piy0, piy1;  // same at t_{k-1} (t_0 for k = 0)
+};
+
+// One finite-volume stencil shared by every grid node with the same
+// neighbourhood geometry and role (Eq.(ulbe) coefficients).
+template <class R>
+struct GridClass {
+  int k;            // used slots
+  int type;         // NodeType
+  int off[KMAX];    // neighbour node-index offsets (slot 0 = 0)
+  R S[9][KMAX];     // streaming matrix S_ik
+  R C[KMAX];        // collision matrix C_ik
+};
+
+struct WallEdge {
+  int a, b;         // node indices
+  double nx, ny;    // unit normal pointing out of the body
+  double len;
+};
+
+// Host-side body-fitted grid (built independently of any other
+// implementation from the definition of the lamina grid).
+struct HostGrid {
+  int nux = 0, nuy = 0;
+  double h = 1.0, b = 0.0, T = 0.0;
+  bool body = false;
+  int nnode = 0, ntri = 0;
+  std::vector<int> type;                 // NodeType per node
+  std::vector<int> cls;                  // class id per node
+  std::vector<GridClass<double>> classes;
+  std::vector<int> iface;                // interface (outer ring) node ids
+  std::vector<WallEdge> wall;            // body polygon edges
+};
+
+// Builds the grid, its median-dual finite-volume matrices and stencil
+// classes. Returns false with a message on invalid geometry.
+bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, std::string *err);
+
+}  // namespace mghlbm

@@ -1,0 +1,59 @@
+// Launch interface of the gfx950 HLBM kernels (internal to the library).
+#pragma once
+
+#include "hlbm_internal.h"
+
+namespace mghlbm {
+
+// Everything a kernel of one case needs, by value. Pointers are device
+// pointers; the lattice pointers are swapped by the host between steps.
+template <class T, class R>
+struct CaseView {
+  // lattice
+  const T *A;      // post-collision populations at t_k, [9][ny][nx]
+  T *B;            // post-collision populations at t_{k+1}
+  int nx, ny;
+  int periodic_y;  // 1: periodic in y, 0: halfway bounce-back walls
+  R inv_tau;       // 1 / tau_s
+  R g_post;        // 2 (tau_s - 1) / (2 tau_s - 1), Eq.(postcollision2_s)
+  R k_neq;         // 1 - 1/(2 tau_s), Eq.(continuity_stresses)
+  int has_grid;
+  // grid
+  int nux, nuy, nnode, n_iface, n_wall_edges, n_sub;
+  double h, xc, yc, half_b, half_T;
+  int body;
+  const int *cls;
+  const GridClass<R> *tab;
+  const int *iface;
+  const WallEdge *wall;
+  R *star_f;       // [9][nnode] structured-derived f* at interface nodes
+  R *star_n;       // [9][nnode] structured-derived f^neq* at interface nodes
+  R dt_u, dt_over_tau_u;
+  const R *uw;     // wall velocity table [max_steps][n_sub]
+  const StepParams *params;  // [max_steps + 1]
+  int64_t *dk;     // device step counter
+  double *hist;    // [max_steps][2]
+  int *flag;       // non-finite force seen
+  unsigned long long *counts;  // refill type 1 and type 2 counters
+  // lattice rows and columns the interpolation kernel must cover
+  int k2_x0, k2_w, k2_h;
+};
+
+template <class T, class R>
+struct Kernels {
+  static void fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStream_t s);
+  static void stream_collide(const CaseView<T, R> &v, hipStream_t s);
+  static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
+  static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
+  static void grid_substep(const CaseView<T, R> &v, const R *f, R *fout, int m, hipStream_t s);
+  static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
+  static void force(const CaseView<T, R> &v, const R *f, hipStream_t s);
+  static void lattice_to_f64(const T *src, double *dst, size_t plane, hipStream_t s);
+  static void lattice_from_f64(const double *src, T *dst, size_t plane, hipStream_t s);
+};
+
+extern template struct Kernels<double, double>;
+extern template struct Kernels<float, float>;
+extern template struct Kernels<__half, float>;
+
+}  // namespace mghlbm

@@ -1,0 +1,547 @@
+// gfx950 kernels of the moving-grid hybrid lattice Boltzmann step.
+//
+// Storage: structure of arrays, one plane per D2Q9 population, [9][ny][nx]
+// for the lattice and [9][nnode] for the body-fitted grid. T is the storage
+// type of the lattice and R the arithmetic type (FP64/FP64, FP32/FP32,
+// FP16 holding f_i - w_i / FP32). The grid is kept in R.
+//
+// D2Q9 ordering: rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1),
+// (1,-1); weights 4/9, 1/9 (axis), 1/36 (diagonal); c_s^2 = 1/3.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace mghlbm {
+namespace {
+
+constexpr int CXd[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CYd[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+template <class R>
+__device__ __forceinline__ R wgt(int q) {
+  return q == 0 ? R(4.0 / 9.0) : (q < 5 ? R(1.0 / 9.0) : R(1.0 / 36.0));
+}
+
+// ---- storage traits --------------------------------------------------------
+template <class T>
+struct Stor;
+template <>
+struct Stor<double> {
+  static __device__ __forceinline__ double ld(const double *p, size_t i, int) { return p[i]; }
+  static __device__ __forceinline__ void st(double *p, size_t i, int, double v) { p[i] = v; }
+};
+template <>
+struct Stor<float> {
+  static __device__ __forceinline__ float ld(const float *p, size_t i, int) { return p[i]; }
+  static __device__ __forceinline__ void st(float *p, size_t i, int, float v) { p[i] = v; }
+};
+template <>
+struct Stor<__half> {  // deviation from the rest equilibrium w_i
+  static __device__ __forceinline__ float ld(const __half *p, size_t i, int q) {
+    return __half2float(p[i]) + wgt<float>(q);
+  }
+  static __device__ __forceinline__ void st(__half *p, size_t i, int q, float v) {
+    p[i] = __float2half_rn(v - wgt<float>(q));
+  }
+};
+
+// ---- D2Q9 helpers -------------------------------------------------------------
+// Eq.(local_eq) with c_s^2 = 1/3: w rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
+template <class R>
+__device__ __forceinline__ void equilibrium(R rho, R ux, R uy, R e[9]) {
+  const R uu = R(1.5) * (ux * ux + uy * uy);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const R cu = R(CXd[q]) * ux + R(CYd[q]) * uy;
+    e[q] = wgt<R>(q) * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - uu);
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void moments(const R f[9], R &rho, R &ux, R &uy) {
+  rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const R mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const R my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  const R inv = R(1) / rho;
+  ux = mx * inv;
+  uy = my * inv;
+}
+
+// Populations arriving at lattice node (x, y) at t_{k+1}: pulled from the
+// post-collision buffer of t_k (left side of Eq.(LBE)); across a resting y
+// wall, halfway bounce-back returns the opposite population of the node.
+template <class T, class R>
+__device__ __forceinline__ void pull(const T *__restrict__ A, int nx, int ny, int periodic_y, int x,
+                                     int y, R f[9]) {
+  const size_t plane = (size_t)nx * ny;
+  const int xm = x == 0 ? nx - 1 : x - 1;
+  const int xp = x == nx - 1 ? 0 : x + 1;
+  int ym = y - 1, yp = y + 1;
+  bool lo = false, hi = false;
+  if (periodic_y) {
+    ym = y == 0 ? ny - 1 : ym;
+    yp = y == ny - 1 ? 0 : yp;
+  } else {
+    lo = (y == 0);
+    hi = (y == ny - 1);
+  }
+  const size_t r = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
+  const size_t c = r + x;
+  f[0] = Stor<T>::ld(A, c, 0);
+  f[1] = Stor<T>::ld(A, 1 * plane + r + xm, 1);
+  f[3] = Stor<T>::ld(A, 3 * plane + r + xp, 3);
+  if (lo) {
+    f[2] = Stor<T>::ld(A, 4 * plane + c, 4);
+    f[5] = Stor<T>::ld(A, 7 * plane + c, 7);
+    f[6] = Stor<T>::ld(A, 8 * plane + c, 8);
+  } else {
+    f[2] = Stor<T>::ld(A, 2 * plane + rm + x, 2);
+    f[5] = Stor<T>::ld(A, 5 * plane + rm + xm, 5);
+    f[6] = Stor<T>::ld(A, 6 * plane + rm + xp, 6);
+  }
+  if (hi) {
+    f[4] = Stor<T>::ld(A, 2 * plane + c, 2);
+    f[7] = Stor<T>::ld(A, 5 * plane + c, 5);
+    f[8] = Stor<T>::ld(A, 6 * plane + c, 6);
+  } else {
+    f[4] = Stor<T>::ld(A, 4 * plane + rp + x, 4);
+    f[7] = Stor<T>::ld(A, 7 * plane + rp + xp, 7);
+    f[8] = Stor<T>::ld(A, 8 * plane + rp + xm, 8);
+  }
+}
+
+// Bilinear Lagrange interpolation over the lattice cell around (X, Y) of
+// density, velocity and f^neq = f - f^eq of the pre-collision populations at
+// t_{k+1} (refill type 1 and the grid's interface donors).
+template <class T, class R>
+__device__ __forceinline__ void bilinear_donors(const CaseView<T, R> &v, double X, double Y, R &rho,
+                                                R &ux, R &uy, R fneq[9]) {
+  const double fx = floor(X), fy = floor(Y);
+  const double a = X - fx, b = Y - fy;
+  int x0 = (int)fx, y0 = (int)fy;
+  const double w4[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+  rho = ux = uy = R(0);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) fneq[q] = R(0);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    int xd = x0 + (d & 1), yd = y0 + (d >> 1);
+    xd = xd >= v.nx ? xd - v.nx : (xd < 0 ? xd + v.nx : xd);
+    if (v.periodic_y) yd = yd >= v.ny ? yd - v.ny : (yd < 0 ? yd + v.ny : yd);
+    R f[9], e[9], r, vx, vy;
+    pull<T, R>(v.A, v.nx, v.ny, v.periodic_y, xd, yd, f);
+    moments<R>(f, r, vx, vy);
+    equilibrium<R>(r, vx, vy, e);
+    const R w = R(w4[d]);
+    rho += w * r;
+    ux += w * vx;
+    uy += w * vy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fneq[q] += w * (f[q] - e[q]);
+  }
+}
+
+// Triangle of the grid cell (ci, cj) containing local cell coordinates
+// (a, b) in [0,1]^2 and its barycentric weights. Cells left of the centre
+// line are cut by the rising diagonal, cells right of it by the falling one.
+__device__ __forceinline__ void cell_triangle(int ci, int cj, int nux, double a, double b,
+                                              int node[3], double lam[3]) {
+  const int n00 = cj * nux + ci, n10 = n00 + 1, n01 = n00 + nux, n11 = n01 + 1;
+  if (2 * ci + 1 < nux) {
+    if (b <= a) {  // (n00, n10, n11)
+      node[0] = n00; node[1] = n10; node[2] = n11;
+      lam[0] = 1.0 - a; lam[1] = a - b; lam[2] = b;
+    } else {       // (n00, n11, n01)
+      node[0] = n00; node[1] = n11; node[2] = n01;
+      lam[0] = 1.0 - b; lam[1] = a; lam[2] = b - a;
+    }
+  } else {
+    if (a + b <= 1.0) {  // (n00, n10, n01)
+      node[0] = n00; node[1] = n10; node[2] = n01;
+      lam[0] = 1.0 - a - b; lam[1] = a; lam[2] = b;
+    } else {             // (n10, n11, n01)
+      node[0] = n10; node[1] = n11; node[2] = n01;
+      lam[0] = 1.0 - b; lam[1] = a + b - 1.0; lam[2] = 1.0 - a;
+    }
+  }
+}
+
+// ---- K1: fused pull stream + BGK collide, Eq.(LBE) -------------------------
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_stream_collide(CaseView<T, R> v) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= v.nx) return;
+  const size_t plane = (size_t)v.nx * v.ny, c = (size_t)y * v.nx + x;
+  bool inside = false;
+  if (v.has_grid) {
+    const StepParams &P = v.params[*v.dk];
+    inside = x >= P.ix0 && x <= P.ix1 && y >= P.iy0 && y <= P.iy1;
+  }
+  if (inside) {  // unused and interpolation nodes carry their values
+#pragma unroll
+    for (int q = 0; q < 9; ++q) v.B[q * plane + c] = v.A[q * plane + c];
+    return;
+  }
+  R f[9], e[9], rho, ux, uy;
+  pull<T, R>(v.A, v.nx, v.ny, v.periodic_y, x, y, f);
+  moments<R>(f, rho, ux, uy);
+  equilibrium<R>(rho, ux, uy, e);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Stor<T>::st(v.B, q * plane + c, q, f[q] - v.inv_tau * (f[q] - e[q]));
+}
+
+// ---- K2: lattice interpolation nodes from the grid, Eq.(postcollision2_s) ----
+// Targets: nodes inside the fictitious rectangle with a neighbour outside it
+// (interpolation nodes), and nodes the moving rectangle uncovered since the
+// previous step. Barycentric interpolation of rho, u and f^neq,u over the
+// grid triangle at t_k; f^eq rebuilt from the interpolated moments.
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_lattice_from_grid(CaseView<T, R> v, const R *__restrict__ g) {
+  const StepParams &P = v.params[*v.dk];
+  const int x = v.k2_x0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = min(P.iy0, P.piy0) + (int)blockIdx.y;
+  if (x >= v.k2_x0 + v.k2_w || y > max(P.iy1, P.piy1)) return;
+  const bool in_k = x >= P.ix0 && x <= P.ix1 && y >= P.iy0 && y <= P.iy1;
+  const bool in_p = x >= P.pix0 && x <= P.pix1 && y >= P.piy0 && y <= P.piy1;
+  const bool interp = in_k && (x == P.ix0 || x == P.ix1 || y == P.iy0 || y == P.iy1);
+  if (!(interp || (!in_k && in_p))) return;
+  const double X0 = v.xc + (double)(0 - v.nux / 2) * v.h;
+  const double Y0 = P.ybase + (0.0 - 0.5 * (double)(v.nuy - 1)) * v.h;
+  const double s = ((double)x - X0) / v.h, t = ((double)y - Y0) / v.h;
+  const int ci = min(max((int)floor(s), 0), v.nux - 2), cj = min(max((int)floor(t), 0), v.nuy - 2);
+  int node[3];
+  double lam[3];
+  cell_triangle(ci, cj, v.nux, s - ci, t - cj, node, lam);
+  R rho = 0, ux = 0, uy = 0, fneq[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) fneq[q] = R(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R f[9], e[9], r, vx, vy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = g[(size_t)q * v.nnode + node[a]];
+    moments<R>(f, r, vx, vy);
+    equilibrium<R>(r, vx, vy, e);
+    const R l = R(lam[a]);
+    rho += l * r;
+    ux += l * vx;
+    uy += l * vy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fneq[q] += l * (f[q] - e[q]);
+  }
+  R e[9];
+  equilibrium<R>(rho, ux, uy, e);
+  const size_t plane = (size_t)v.nx * v.ny, c = (size_t)y * v.nx + x;
+  T *A = const_cast<T *>(v.A);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Stor<T>::st(A, q * plane + c, q, e[q] + v.g_post * fneq[q]);
+}
+
+// ---- K4 prologue: structured-derived values at the grid's outer nodes ----------
+// f* = f^eq,s + (1 - 1/(2 tau_s)) f^neq,s and f^neq* from the lattice at t_{k+1}
+// (pre-collision), held over the n sub-steps (Eq.(postcollision2_u)).
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_interface_donors(CaseView<T, R> v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= v.n_iface) return;
+  const StepParams &P = v.params[*v.dk];
+  const int p = v.iface[t];
+  const int i = p % v.nux, j = p / v.nux;
+  const double X = v.xc + (double)(i - v.nux / 2) * v.h;
+  const double Y = P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
+  R rho, ux, uy, fneq[9], e[9];
+  bilinear_donors<T, R>(v, X, Y, rho, ux, uy, fneq);
+  equilibrium<R>(rho, ux, uy, e);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const R n = v.k_neq * fneq[q];
+    v.star_n[(size_t)q * v.nnode + p] = n;
+    v.star_f[(size_t)q * v.nnode + p] = e[q] + n;
+  }
+}
+
+// ---- K3/K4: one sub-step of the grid scheme ---------------------------------
+// Eq.(ulbe) at discretization and wall nodes; Eq.(postcollision2_u) at the
+// outer interpolation nodes, where the node itself and every interpolation
+// neighbour contribute their structured-derived values. Wall nodes then take
+// the lamina velocity while keeping density and non-equilibrium part.
+template <class R>
+__global__ __launch_bounds__(256) void k_grid_substep(const R *__restrict__ f,
+                                                      R *__restrict__ fout, const R *__restrict__ star_f,
+                                                      const R *__restrict__ star_n, const int *__restrict__ cls,
+                                                      const GridClass<R> *__restrict__ tab, int nnode, int nux,
+                                                      int nuy, R dt, R dt_tau, const R *__restrict__ uw,
+                                                      const int64_t *__restrict__ dk, int n_sub, int m) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnode) return;
+  const GridClass<R> &c = tab[cls[p]];
+  const bool iface = c.type == NODE_INTERFACE;
+  R ss[9], sc[9], out[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) ss[q] = sc[q] = R(0);
+  for (int s = 0; s < c.k; ++s) {
+    const int nb = p + c.off[s];
+    R fq[9], nq[9];
+    bool star = false;
+    if (iface) {
+      const int iq = nb % nux, jq = nb / nux;
+      star = (iq == 0 || jq == 0 || iq == nux - 1 || jq == nuy - 1);
+    }
+    if (star) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        fq[q] = star_f[(size_t)q * nnode + nb];
+        nq[q] = star_n[(size_t)q * nnode + nb];
+      }
+    } else {
+      R e[9], r, vx, vy;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) fq[q] = f[(size_t)q * nnode + nb];
+      moments<R>(fq, r, vx, vy);
+      equilibrium<R>(r, vx, vy, e);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) nq[q] = fq[q] - e[q];
+    }
+    const R cs = c.C[s];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      ss[q] += c.S[q][s] * fq[q];
+      sc[q] += cs * nq[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const R self = iface ? star_f[(size_t)q * nnode + p] : f[(size_t)q * nnode + p];
+    out[q] = self + dt * ss[q] - dt_tau * sc[q];
+  }
+  if (c.type == NODE_WALL) {
+    R e[9], ew[9], r, vx, vy;
+    moments<R>(out, r, vx, vy);
+    equilibrium<R>(r, vx, vy, e);
+    equilibrium<R>(r, R(0), uw[*dk * n_sub + m], ew);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] = ew[q] + (out[q] - e[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) fout[(size_t)q * nnode + p] = out[q];
+}
+
+// ---- K5: move the grid from y_k to y_{k+1} and refill it ---------------------
+// Each non-wall node is located, at its new position, in the grid of t_k:
+// inside a triangle -> type 3 (barycentric interpolation of f); inside the
+// old lamina -> type 2 (keep f); otherwise -> type 1 (bilinear lattice
+// donors, f^neq,u = (1 - 1/(2 tau_s)) f^neq,s, Eq.(continuity_stresses)).
+// Wall nodes keep f (their velocity is imposed during the sub-steps).
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_refill(CaseView<T, R> v, const R *__restrict__ fo, R *__restrict__ fn) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= v.nnode) return;
+  const int i = p % v.nux, j = p / v.nux;
+  const size_t N = (size_t)v.nnode;
+  R out[9];
+  const GridClass<R> &c = v.tab[v.cls[p]];
+  if (c.type == NODE_WALL) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fn[q * N + p] = fo[q * N + p];
+    return;
+  }
+  const StepParams &P = v.params[*v.dk];
+  const double tol = 1e-12;
+  const double xrel = (double)(i - v.nux / 2) * v.h;
+  const double Ynew = P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
+  const double Y0 = P.ybase + (0.0 - 0.5 * (double)(v.nuy - 1)) * v.h;
+  const double s = (double)i, t = (Ynew - Y0) / v.h;
+  const int slot_row = v.nuy / 2 - 1;
+  const double half = v.half_b + 1e-9 * v.h;
+  auto body_cell = [&](int ci, int cj) {
+    return v.body && cj == slot_row && (double)(ci - v.nux / 2) * v.h >= -half &&
+           (double)(ci + 1 - v.nux / 2) * v.h <= half;
+  };
+  int kind = 1;
+  int ci = 0, cj = 0;
+  double a = 0, b = 0;
+  if (t >= -tol && t <= (double)(v.nuy - 1) + tol) {
+    cj = min(max((int)floor(t), 0), v.nuy - 2);
+    ci = min(max((int)floor(s), 0), v.nux - 2);
+    b = t - cj;
+    a = s - ci;
+    kind = 3;
+    if (body_cell(ci, cj)) {
+      if (b <= tol && cj > 0 && !body_cell(ci, cj - 1)) { cj -= 1; b += 1.0; }
+      else if (b >= 1.0 - tol && cj < v.nuy - 2 && !body_cell(ci, cj + 1)) { cj += 1; b -= 1.0; }
+      else if (a <= tol && ci > 0 && !body_cell(ci - 1, cj)) { ci -= 1; a += 1.0; }
+      else if (a >= 1.0 - tol && ci < v.nux - 2 && !body_cell(ci + 1, cj)) { ci += 1; a -= 1.0; }
+      else kind = 0;
+    }
+  } else {
+    kind = 0;
+  }
+  if (kind == 3) {
+    int node[3];
+    double lam[3];
+    cell_triangle(ci, cj, v.nux, a, b, node, lam);
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      out[q] = R(lam[0]) * fo[q * N + node[0]] + R(lam[1]) * fo[q * N + node[1]] + R(lam[2]) * fo[q * N + node[2]];
+  } else if (v.body && fabs(xrel) < v.half_b && fabs(Ynew - P.ybase) < v.half_T) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] = fo[q * N + p];
+    atomicAdd(&v.counts[1], 1ull);
+  } else {
+    R rho, ux, uy, fneq[9], e[9];
+    bilinear_donors<T, R>(v, v.xc + xrel, Ynew, rho, ux, uy, fneq);
+    equilibrium<R>(rho, ux, uy, e);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] = e[q] + v.k_neq * fneq[q];
+    atomicAdd(&v.counts[0], 1ull);
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) fn[q * N + p] = out[q];
+}
+
+// ---- K6: force on the lamina, then advance the step counter ------------------
+// Traction -p' n + sigma' n on each wall edge (trapezoid rule), p' = c_s^2
+// (rho - 1), sigma'_ab = -sum_i c_ia c_ib f_i^neq; FP64 accumulation, wave64
+// shuffle reduction and one LDS pass across the four waves.
+template <class R>
+__global__ __launch_bounds__(256) void k_force(const R *__restrict__ f, const WallEdge *__restrict__ wall,
+                                               int n_wall_edges, int nnode, int64_t *dk, double *hist, int *flag) {
+  __shared__ double red[2][4];
+  double Fx = 0.0, Fy = 0.0;
+  for (int e = threadIdx.x; e < n_wall_edges; e += blockDim.x) {
+    const WallEdge w = wall[e];
+    double tx = 0.0, ty = 0.0;
+    for (int s = 0; s < 2; ++s) {
+      const int p = s ? w.b : w.a;
+      R fp[9], eq[9], r, vx, vy;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) fp[q] = f[(size_t)q * nnode + p];
+      moments<R>(fp, r, vx, vy);
+      equilibrium<R>(r, vx, vy, eq);
+      double sxx = 0.0, sxy = 0.0, syy = 0.0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const double fn = (double)fp[q] - (double)eq[q];
+        sxx -= double(CXd[q] * CXd[q]) * fn;
+        sxy -= double(CXd[q] * CYd[q]) * fn;
+        syy -= double(CYd[q] * CYd[q]) * fn;
+      }
+      const double pp = ((double)r - 1.0) / 3.0;
+      tx += -pp * w.nx + sxx * w.nx + sxy * w.ny;
+      ty += -pp * w.ny + sxy * w.nx + syy * w.ny;
+    }
+    Fx += 0.5 * w.len * tx;
+    Fy += 0.5 * w.len * ty;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    Fx += __shfl_xor(Fx, o, 64);
+    Fy += __shfl_xor(Fy, o, 64);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    red[0][wave] = Fx;
+    red[1][wave] = Fy;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < nw; ++i) {
+      sx += red[0][i];
+      sy += red[1][i];
+    }
+    const int64_t k = *dk;
+    hist[2 * k] = sx;
+    hist[2 * k + 1] = sy;
+    if (!isfinite(sx) || !isfinite(sy)) *flag = 1;
+    *dk = k + 1;
+  }
+}
+
+template <class T, class R>
+__global__ void k_fill_rest(T *lat, size_t plane, R *grid, int nnode) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < plane)
+    for (int q = 0; q < 9; ++q) Stor<T>::st(lat, q * plane + i, q, wgt<R>(q));
+  if (i < (size_t)nnode)
+    for (int q = 0; q < 9; ++q) grid[(size_t)q * nnode + i] = wgt<R>(q);
+}
+
+template <class T>
+__global__ void k_to_f64(const T *src, double *dst, size_t plane) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= plane) return;
+  for (int q = 0; q < 9; ++q) dst[q * plane + i] = (double)Stor<T>::ld(src, q * plane + i, q);
+}
+
+template <class T>
+__global__ void k_from_f64(const double *src, T *dst, size_t plane) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= plane) return;
+  for (int q = 0; q < 9; ++q) {
+    const double x = src[q * plane + i];
+    if constexpr (sizeof(T) == 8) Stor<T>::st(dst, q * plane + i, q, x);
+    else Stor<T>::st(dst, q * plane + i, q, (float)x);
+  }
+}
+
+inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+template <class T, class R>
+void Kernels<T, R>::fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStream_t s) {
+  const size_t n = plane > (size_t)nnode ? plane : (size_t)nnode;
+  hipLaunchKernelGGL((k_fill_rest<T, R>), dim3(blocks(n, 256)), dim3(256), 0, s, lat, plane, grid, nnode);
+}
+
+template <class T, class R>
+void Kernels<T, R>::stream_collide(const CaseView<T, R> &v, hipStream_t s) {
+  hipLaunchKernelGGL((k_stream_collide<T, R>), dim3(blocks(v.nx, 256), v.ny), dim3(256), 0, s, v);
+}
+
+template <class T, class R>
+void Kernels<T, R>::lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_lattice_from_grid<T, R>), dim3(blocks(v.k2_w, 256), v.k2_h), dim3(256), 0, s, v, grid);
+}
+
+template <class T, class R>
+void Kernels<T, R>::interface_donors(const CaseView<T, R> &v, hipStream_t s) {
+  hipLaunchKernelGGL((k_interface_donors<T, R>), dim3(blocks(v.n_iface, 256)), dim3(256), 0, s, v);
+}
+
+template <class T, class R>
+void Kernels<T, R>::grid_substep(const CaseView<T, R> &v, const R *f, R *fout, int m, hipStream_t s) {
+  hipLaunchKernelGGL((k_grid_substep<R>), dim3(blocks(v.nnode, 256)), dim3(256), 0, s, f, fout,
+                     (const R *)v.star_f, (const R *)v.star_n, v.cls, v.tab, v.nnode, v.nux, v.nuy, v.dt_u,
+                     v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m);
+}
+
+template <class T, class R>
+void Kernels<T, R>::refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s) {
+  hipLaunchKernelGGL((k_refill<T, R>), dim3(blocks(v.nnode, 256)), dim3(256), 0, s, v, fold, fnew);
+}
+
+template <class T, class R>
+void Kernels<T, R>::force(const CaseView<T, R> &v, const R *f, hipStream_t s) {
+  hipLaunchKernelGGL((k_force<R>), dim3(1), dim3(256), 0, s, f, v.wall, v.n_wall_edges, v.nnode, v.dk, v.hist,
+                     v.flag);
+}
+
+template <class T, class R>
+void Kernels<T, R>::lattice_to_f64(const T *src, double *dst, size_t plane, hipStream_t s) {
+  hipLaunchKernelGGL((k_to_f64<T>), dim3(blocks(plane, 256)), dim3(256), 0, s, src, dst, plane);
+}
+
+template <class T, class R>
+void Kernels<T, R>::lattice_from_f64(const double *src, T *dst, size_t plane, hipStream_t s) {
+  hipLaunchKernelGGL((k_from_f64<T>), dim3(blocks(plane, 256)), dim3(256), 0, s, src, dst, plane);
+}
+
+template struct Kernels<double, double>;
+template struct Kernels<float, float>;
+template struct Kernels<__half, float>;
+
+}  // namespace mghlbm

@@ -1,0 +1,189 @@
+"""Thin ctypes binding of ``libhlbm.so`` (include/hlbm.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels. There is no fallback; a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhlbm.so")
+
+OK, E_ARG, E_NOMEM, E_HIP, E_UNSTABLE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+BC_PERIODIC_X_WALLS_Y, BC_PERIODIC = 0, 1
+FP64, FP32, FP16_DEV = 0, 1, 2
+FLAG_NO_BODY = 1
+STATE_LATTICE, STATE_GRID = 0, 1
+K_STREAM_COLLIDE, K_LATTICE_FROM_GRID, K_GRID_SUBSTEPS, K_REFILL, K_FORCE, K_STEP = range(6)
+STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV}
+
+EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_state",
+           "hlbm_set_state", "hlbm_info_get", "hlbm_get_stencil", "hlbm_timing",
+           "hlbm_timing_get", "hlbm_destroy", "hlbm_last_error")
+
+
+class HlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nux", C.c_int32), ("nuy", C.c_int32),
+                ("h_u", C.c_double), ("b", C.c_double), ("thickness", C.c_double),
+                ("tau", C.c_double), ("kc", C.c_double), ("beta", C.c_double),
+                ("n_sub", C.c_int32), ("bc", C.c_int32), ("storage", C.c_int32),
+                ("flags", C.c_int32), ("ckpt_every", C.c_int32), ("reserved", C.c_int32),
+                ("max_steps", C.c_int64)]
+
+
+class Info(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("nu", "tau_u", "dt_u", "A", "omega", "period", "u_max", "mach", "reynolds", "eps")] + \
+               [(n, C.c_int32) for n in
+                ("n_sub", "nnode", "ntri", "n_interface", "n_wall", "n_wall_edges", "beta_limit_ok",
+                 "n_classes")] + \
+               [("step", C.c_int64), ("y", C.c_double), ("n_type1", C.c_int64),
+                ("n_type2", C.c_int64), ("n_type3", C.c_int64), ("lattice_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with paper_2006_13631_amd/build.py")
+    L = C.CDLL(path)
+    vp, d, i32, i64 = C.c_void_p, C.c_double, C.c_int32, C.c_int64
+    dp = C.POINTER(C.c_double)
+    L.hlbm_create.argtypes = [C.POINTER(Config), i32, C.POINTER(vp)]
+    L.hlbm_step.argtypes = [vp, i64]
+    L.hlbm_force.argtypes = [vp, i32, dp, i64, C.POINTER(i64), d, d, dp]
+    L.hlbm_adjoint.argtypes = [vp, i32, dp, i64, dp]
+    L.hlbm_get_state.argtypes = [vp, i32, i32, vp, C.c_size_t]
+    L.hlbm_set_state.argtypes = [vp, i32, i32, vp, C.c_size_t]
+    L.hlbm_info_get.argtypes = [vp, i32, C.POINTER(Info)]
+    L.hlbm_get_stencil.argtypes = [vp, i32, C.POINTER(C.c_int32), dp, dp]
+    L.hlbm_timing.argtypes = [vp, i32]
+    L.hlbm_timing_get.argtypes = [vp, i32, dp, C.POINTER(i64)]
+    L.hlbm_destroy.argtypes = [vp]
+    L.hlbm_destroy.restype = None
+    L.hlbm_last_error.argtypes = [vp]
+    L.hlbm_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(a, t=C.c_double):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+class Case:
+    """One lamina case on the GPU."""
+
+    def __init__(self, nx, ny, nux=0, nuy=0, h_u=1.0, b=0.0, thickness=1.0, tau=0.8, kc=0.0,
+                 beta=0.0, n_sub=0, bc=BC_PERIODIC_X_WALLS_Y, storage=FP64, flags=0,
+                 ckpt_every=0, max_steps=0):
+        L = load()
+        if isinstance(storage, str):
+            storage = STORAGE[storage]
+        self.cfg = Config(nx, ny, nux, nuy, h_u, b, thickness, tau, kc, beta, n_sub, bc, storage,
+                          flags, ckpt_every, 0, max_steps)
+        h = C.c_void_p()
+        rc = L.hlbm_create(C.byref(self.cfg), 1, C.byref(h))
+        if rc != 0:
+            raise HlbmError(rc, L.hlbm_last_error(None).decode())
+        self.h = h
+        self.nx, self.ny = nx, ny
+        self.nnode = self.info().nnode
+
+    def _check(self, rc):
+        if rc != 0:
+            raise HlbmError(rc, load().hlbm_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().hlbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        self._check(load().hlbm_step(self.h, n))
+
+    def info(self) -> Info:
+        i = Info()
+        self._check(load().hlbm_info_get(self.h, 0, C.byref(i)))
+        return i
+
+    def lattice(self):
+        out = np.zeros((9, self.ny, self.nx))
+        self._check(load().hlbm_get_state(self.h, 0, STATE_LATTICE, out.ctypes.data, out.nbytes))
+        return out
+
+    def set_lattice(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self._check(load().hlbm_set_state(self.h, 0, STATE_LATTICE, f.ctypes.data, f.nbytes))
+
+    def grid(self):
+        out = np.zeros((9, self.nnode))
+        self._check(load().hlbm_get_state(self.h, 0, STATE_GRID, out.ctypes.data, out.nbytes))
+        return out
+
+    def set_grid(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self._check(load().hlbm_set_state(self.h, 0, STATE_GRID, f.ctypes.data, f.nbytes))
+
+    def history(self):
+        n = C.c_int64()
+        self._check(load().hlbm_force(self.h, 0, None, 0, C.byref(n), 0.0, 0.0, None))
+        out = np.zeros((max(n.value, 1), 2))
+        self._check(load().hlbm_force(self.h, 0, _ptr(out), n.value, C.byref(n), 0.0, 0.0, None))
+        return out[:n.value]
+
+    def theta(self, t0=1.0, t1=4.0):
+        th = np.zeros(2)
+        self._check(load().hlbm_force(self.h, 0, None, 0, None, t0, t1, _ptr(th)))
+        return complex(th[0], th[1])
+
+    def stencil(self, kmax=8):
+        nbr = np.zeros((self.nnode, kmax), np.int32)
+        S = np.zeros((self.nnode, 9, kmax))
+        Cm = np.zeros((self.nnode, kmax))
+        self._check(load().hlbm_get_stencil(self.h, kmax, _ptr(nbr, C.c_int32), _ptr(S), _ptr(Cm)))
+        return nbr, S, Cm
+
+    def timing(self, on=True):
+        self._check(load().hlbm_timing(self.h, 1 if on else 0))
+
+    def timing_get(self, kernel):
+        ms = C.c_double()
+        cnt = C.c_int64()
+        self._check(load().hlbm_timing_get(self.h, kernel, C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
+    def adjoint(self, dJ_dFy):
+        g = np.zeros(3)
+        dJ = np.ascontiguousarray(dJ_dFy, dtype=np.float64)
+        self._check(load().hlbm_adjoint(self.h, 0, _ptr(dJ), dJ.size, _ptr(g)))
+        return g
+
+
+def case_from_preset(cfg: dict, **overrides) -> Case:
+    c = dict(cfg)
+    c.update(overrides)
+    steps = c.pop("steps", 0)
+    c.setdefault("max_steps", steps)
+    return Case(**c)

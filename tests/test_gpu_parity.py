@@ -1,0 +1,180 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 CPU oracle.
+
+Both sides start from the same seeded inputs (workloads module) and are
+compared element by element. FP64 bar (the parity norm of the design notes):
+    max|f_gpu - f_oracle| / max|f_oracle| <= 1e-12 over lattice and grid, and
+    max_k|F_gpu - F_oracle| / max_k|F_oracle| <= 1e-12 over the force history.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2006_13631_amd import hlbm
+from paper_2006_13631_amd.workloads import preset, random_populations
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _pair(oracle, cfg, steps=None, storage=hlbm.FP64, **kw):
+    c = dict(cfg)
+    c.update(kw)
+    n = c.pop("steps")
+    c.pop("ckpt_every", None)
+    cap = steps if steps is not None else n
+    o = oracle.Sim(max_steps=cap, **c)
+    g = hlbm.Case(max_steps=cap, storage=storage, **c)
+    return o, g, cap
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _check_state(o, g, tol=TOL, hist=True):
+    errs = {"lattice": _rel(g.lattice(), o.lattice())}
+    if o.nnode:
+        errs["grid"] = _rel(g.grid(), o.grid())
+        if hist:
+            ho, hg = o.history(), g.history()
+            assert ho.shape == hg.shape
+            errs["force"] = _rel(hg, ho)
+    _say("parity errors", errs)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+    return errs
+
+
+def _sparse(nbr, M):
+    N = nbr.shape[0]
+    rows = np.repeat(np.arange(N), nbr.shape[1])
+    cols = nbr.ravel()
+    keep = cols >= 0
+    return sp.csr_matrix((M.ravel()[keep], (rows[keep], cols[keep])), shape=(N, N))
+
+
+@pytest.mark.parametrize("name", ["lamina_256x128", "tiny_ragged", "tiny_fine_grid", "lamina_128x64"])
+def test_stencil_matches_oracle(oracle, name):
+    _say("stencil", name)
+    cfg = preset(name)
+    o, g, _ = _pair(oracle, cfg, steps=1)
+    nbr_g, S_g, C_g = g.stencil(8)
+    nbr_o, S_o, C_o, _ = o.mesh().stencil()
+    assert abs(_sparse(nbr_g, C_g) - _sparse(nbr_o, C_o)).max() < 1e-13
+    smax = np.abs(S_o).max()  # S scales as 1/h_u
+    for q in range(9):
+        assert abs(_sparse(nbr_g, S_g[:, q, :]) - _sparse(nbr_o, S_o[:, q, :])).max() < 1e-13 * smax
+    assert g.info().n_classes < 200
+
+
+@pytest.mark.parametrize("bc", [hlbm.BC_PERIODIC_X_WALLS_Y, hlbm.BC_PERIODIC])
+def test_lattice_only_random_state(oracle, bc):
+    """Eq.(LBE) alone on a ragged 77 x 45 lattice from a random state."""
+    _say("lattice only bc", bc)
+    nx, ny = 77, 45
+    _, _, w = oracle.d2q9()
+    f0 = random_populations((9, ny, nx), seed=5, base=w, spread=0.05)
+    g = hlbm.Case(nx, ny, tau=0.62, bc=bc)
+    g.set_lattice(f0)
+    g.step(25)
+    f = f0
+    for _ in range(25):
+        f = oracle.lattice_step(f, 0.62, bc=bc)
+    assert _rel(g.lattice(), f) <= TOL
+
+
+def test_lamina_256x128_full_run(oracle):
+    """The 256 x 128 lamina case, 2000 steps: force history and final
+    distributions of both grids."""
+    _say("lamina_256x128 2000 steps")
+    o, g, n = _pair(oracle, preset("lamina_256x128"))
+    for _ in range(4):
+        o.step(n // 4)
+        g.step(n // 4)
+        _check_state(o, g)
+    io, ig = o.info(), g.info()
+    assert (ig.n_type1, ig.n_type2, ig.n_type3) == (io.n_type1, io.n_type2, io.n_type3)
+    th_o = oracle.fit_theta(o.history(), io.omega, io.A, 32.0)
+    th_g = g.theta()
+    _say("theta", th_g, th_o)
+    assert abs(th_g - th_o) <= 1e-11 * abs(th_o)
+
+
+def test_ragged_random_state(oracle):
+    """Odd grid width, ragged lattice, random start on both grids."""
+    _say("tiny_ragged random state")
+    cfg = preset("tiny_ragged")
+    o, g, n = _pair(oracle, cfg)
+    _, _, w = oracle.d2q9()
+    fl = random_populations((9, cfg["ny"], cfg["nx"]), seed=21, base=w, spread=0.01)
+    fg = random_populations((9, o.nnode), seed=22, base=w, spread=0.01)
+    for s in (o, g):
+        s.set_lattice(fl)
+        s.set_grid(fg)
+    o.step(n)
+    g.step(n)
+    _check_state(o, g)
+
+
+def test_fine_grid_with_type2_refill(oracle):
+    """Grid spacing 0.2 below the per-step displacement: type-2 refill."""
+    _say("tiny_fine_grid")
+    o, g, n = _pair(oracle, preset("tiny_fine_grid"))
+    o.step(n)
+    g.step(n)
+    _check_state(o, g)
+    assert g.info().n_type2 == o.info().n_type2 > 0
+
+
+def test_periodic_lattice_with_body(oracle):
+    _say("periodic bc with lamina")
+    o, g, n = _pair(oracle, preset("tiny_ragged"), bc=hlbm.BC_PERIODIC)
+    o.step(n)
+    g.step(n)
+    _check_state(o, g)
+
+
+def test_uniform_flow_no_body_invariant(oracle):
+    """GPU alone: uniform flow stays uniform with an oscillating grid."""
+    _say("uniform flow")
+    g = hlbm.Case(64, 48, 24, 16, 1.0, 8.0, 1.0, 0.7, 1.0, 20.0, bc=hlbm.BC_PERIODIC,
+                  flags=hlbm.FLAG_NO_BODY, max_steps=40)
+    e = oracle.feq(1.0, 0.03, -0.02)
+    g.set_lattice(np.broadcast_to(e[:, None, None], (9, 48, 64)).copy())
+    g.set_grid(np.broadcast_to(e[:, None], (9, g.nnode)).copy())
+    g.step(40)
+    assert np.max(np.abs(g.lattice() - e[:, None, None])) < 1e-14
+    assert np.max(np.abs(g.grid() - e[:, None])) < 1e-14
+
+
+@pytest.mark.timeout(600)
+def test_lamina_2048_first_steps(oracle):
+    """The 2048^2 lamina case at full size, in the configuration the
+    benchmark times, over its first steps (whole-array comparison)."""
+    _say("lamina_2048 3 steps")
+    o, g, _ = _pair(oracle, preset("lamina_2048"), steps=3)
+    o.step(3)
+    g.step(3)
+    _check_state(o, g)
+
+
+@pytest.mark.parametrize("storage,tol", [(hlbm.FP32, 2e-3), (hlbm.FP16_DEV, 3e-2)])
+def test_reduced_precision_theta(storage, tol):
+    """FP32 and FP16-deviation storage against the FP64 run of the
+    256 x 128 lamina case: relative error of Theta."""
+    _say("precision", storage)
+    cfg = preset("lamina_256x128")
+    ref = hlbm.case_from_preset(cfg)
+    ref.step(cfg["steps"])
+    low = hlbm.case_from_preset(cfg, storage=storage)
+    low.step(cfg["steps"])
+    t64, tlo = ref.theta(), low.theta()
+    _say("theta f64", t64, "reduced", tlo, "rel", abs(tlo - t64) / abs(t64))
+    assert abs(tlo - t64) <= tol * abs(t64)
