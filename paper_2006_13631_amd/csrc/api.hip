@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -24,6 +25,7 @@ namespace {
 std::string g_create_error;
 
 constexpr double kMargin = 2.0;  // inset of the fictitious rectangle (lattice units)
+constexpr int kGraphSteps = 8;   // structured steps per captured HIP graph (even)
 
 struct Derived {
   double nu, tau_u, A, omega, xc, yc;
@@ -96,12 +98,16 @@ class Case final : public CaseBase {
         return HLBM_E_ARG;
       }
     }
+    HIPCHK((Kernels<T, R>::prepare()));
     HIPCHK(hipStreamCreateWithFlags(&s_main_, hipStreamNonBlocking));
-    HIPCHK(hipStreamCreateWithFlags(&s_grid_, hipStreamNonBlocking));
+    if (std::getenv("HLBM_ONE_STREAM")) s_grid_ = s_main_;
+    else HIPCHK(hipStreamCreateWithFlags(&s_grid_, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
     HIPCHK(alloc(&lat_[0], 9 * plane_ * sizeof(T)));
     HIPCHK(alloc(&lat_[1], 9 * plane_ * sizeof(T)));
+    lat_base_ = lat_[0];
+    use_graphs_ = std::getenv("HLBM_NO_GRAPHS") == nullptr;
     const int64_t cap = std::max<int64_t>(c.max_steps, 1);
     HIPCHK(alloc(&hist_, 2 * cap * sizeof(double)));
     HIPCHK(alloc(&dk_, sizeof(int64_t)));
@@ -123,10 +129,8 @@ class Case final : public CaseBase {
         const GridClass<double> &g = grid_.classes[i];
         GridClass<R> &t = tab[i];
         std::memset(&t, 0, sizeof(t));
-        t.k = g.k;
         t.type = g.type;
-        for (int s = 0; s < KMAX; ++s) {
-          t.off[s] = g.off[s];
+        for (int s = 0; s < NSLOT; ++s) {
           t.C[s] = (R)g.C[s];
           for (int q = 0; q < 9; ++q) t.S[q][s] = (R)g.S[q][s];
         }
@@ -161,45 +165,108 @@ class Case final : public CaseBase {
     return HLBM_OK;
   }
 
+  // Enqueue one structured step t_k -> t_{k+1} (host bookkeeping included).
+  hipError_t enqueue_step() {
+    hipError_t e = hipSuccess;
+#define ENQ(expr)                  \
+  do {                             \
+    e = (expr);                    \
+    if (e != hipSuccess) return e; \
+  } while (0)
+    CaseView<T, R> v = view();
+    if (timing_) ENQ(hipEventRecord(tev_[0], s_main_));
+    if (has_grid_) {
+      // 1. lattice interpolation nodes from the grid at t_k, Eq.(postcollision2_s)
+      Kernels<T, R>::lattice_from_grid(v, (const R *)gbuf_[gcur_], s_main_);
+      if (timing_) ENQ(hipEventRecord(tev_[1], s_main_));
+      if (s_grid_ != s_main_) {
+        ENQ(hipEventRecord(ev_fork_, s_main_));
+        ENQ(hipStreamWaitEvent(s_grid_, ev_fork_, 0));
+      }
+      // 2. lattice stream-collide, Eq.(LBE)
+      Kernels<T, R>::stream_collide(v, s_main_);
+      if (timing_) ENQ(hipEventRecord(tev_[2], s_main_));
+      // 3.-6. grid path: donors, n sub-steps, refill, force
+      if (timing_) ENQ(hipEventRecord(tev_[3], s_grid_));
+      Kernels<T, R>::interface_donors(v, s_grid_);
+      int cur = gcur_;
+      for (int m = 0; m < d_.n; ++m) {
+        Kernels<T, R>::grid_substep(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, s_grid_);
+        cur = 1 - cur;
+      }
+      if (timing_) ENQ(hipEventRecord(tev_[4], s_grid_));
+      Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
+      if (timing_) ENQ(hipEventRecord(tev_[5], s_grid_));
+      Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_);
+      if (timing_) ENQ(hipEventRecord(tev_[6], s_grid_));
+      gcur_ = 1 - cur;
+      if (s_grid_ != s_main_) {
+        ENQ(hipEventRecord(ev_join_, s_grid_));
+        ENQ(hipStreamWaitEvent(s_main_, ev_join_, 0));
+      }
+    } else {
+      if (timing_) ENQ(hipEventRecord(tev_[1], s_main_));
+      Kernels<T, R>::stream_collide(v, s_main_);
+      if (timing_) ENQ(hipEventRecord(tev_[2], s_main_));
+    }
+    if (timing_) ENQ(hipEventRecord(tev_[7], s_main_));
+    ENQ(hipGetLastError());
+    std::swap(lat_[0], lat_[1]);
+    ++k_;
+#undef ENQ
+    return hipSuccess;
+  }
+
+  // kGraphSteps steps (even) captured as one HIP graph per buffer
+  // arrangement: after an even number of steps the lattice and grid buffers
+  // are back in place, so the graph can be replayed; kernels read the step
+  // index from device memory.
+  hipError_t graph_for_current_layout(hipGraphExec_t *out) {
+    const int key = (lat_[0] == lat_base_ ? 0 : 1) + 2 * gcur_;
+    if (gexec_[key]) {
+      *out = gexec_[key];
+      return hipSuccess;
+    }
+    void *l0 = lat_[0], *l1 = lat_[1];
+    const int g0 = gcur_;
+    const int64_t k0 = k_;
+    hipError_t e = hipStreamBeginCapture(s_main_, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e2 = hipSuccess;
+    for (int i = 0; i < kGraphSteps && e2 == hipSuccess; ++i) e2 = enqueue_step();
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s_main_, &g);
+    lat_[0] = l0;
+    lat_[1] = l1;
+    gcur_ = g0;
+    k_ = k0;
+    if (e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return e2;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&gexec_[key], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    *out = gexec_[key];
+    return hipSuccess;
+  }
+
   int step(int64_t nsteps) override {
     if (nsteps < 0) return fail(HLBM_E_ARG, "nsteps < 0");
     if (has_grid_ && k_ + nsteps > cfg_.max_steps) return fail(HLBM_E_ARG, "force history would exceed max_steps");
-    for (int64_t it = 0; it < nsteps; ++it) {
-      CaseView<T, R> v = view();
-      if (timing_) HIPCHK(hipEventRecord(tev_[0], s_main_));
-      if (has_grid_) {
-        const R *g = (const R *)gbuf_[gcur_];
-        Kernels<T, R>::lattice_from_grid(v, g, s_main_);
-        if (timing_) HIPCHK(hipEventRecord(tev_[1], s_main_));
-        HIPCHK(hipEventRecord(ev_fork_, s_main_));
-        HIPCHK(hipStreamWaitEvent(s_grid_, ev_fork_, 0));
-        Kernels<T, R>::stream_collide(v, s_main_);
-        if (timing_) HIPCHK(hipEventRecord(tev_[2], s_main_));
-        // grid path
-        if (timing_) HIPCHK(hipEventRecord(tev_[3], s_grid_));
-        Kernels<T, R>::interface_donors(v, s_grid_);
-        int cur = gcur_;
-        for (int m = 0; m < d_.n; ++m) {
-          Kernels<T, R>::grid_substep(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, s_grid_);
-          cur = 1 - cur;
-        }
-        if (timing_) HIPCHK(hipEventRecord(tev_[4], s_grid_));
-        Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
-        if (timing_) HIPCHK(hipEventRecord(tev_[5], s_grid_));
-        Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_);
-        if (timing_) HIPCHK(hipEventRecord(tev_[6], s_grid_));
-        gcur_ = 1 - cur;
-        HIPCHK(hipEventRecord(ev_join_, s_grid_));
-        HIPCHK(hipStreamWaitEvent(s_main_, ev_join_, 0));
-      } else {
-        if (timing_) HIPCHK(hipEventRecord(tev_[1], s_main_));
-        Kernels<T, R>::stream_collide(v, s_main_);
-        if (timing_) HIPCHK(hipEventRecord(tev_[2], s_main_));
+    int64_t done = 0;
+    if (!timing_ && use_graphs_) {
+      for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
+        hipGraphExec_t ge = nullptr;
+        HIPCHK(graph_for_current_layout(&ge));
+        HIPCHK(hipGraphLaunch(ge, s_main_));
+        // same buffer layout, kGraphSteps steps further
+        k_ += kGraphSteps;
       }
-      if (timing_) HIPCHK(hipEventRecord(tev_[7], s_main_));
-      HIPCHK(hipGetLastError());
-      std::swap(lat_[0], lat_[1]);
-      ++k_;
+    }
+    for (; done < nsteps; ++done) {
+      HIPCHK(enqueue_step());
       if (timing_) HIPCHK(harvest());
     }
     HIPCHK(hipStreamSynchronize(s_main_));
@@ -336,16 +403,27 @@ class Case final : public CaseBase {
   int stencil(int kmax, int32_t *nbr, double *S, double *C) override {
     if (!has_grid_) return fail(HLBM_E_STATE, "case has no grid");
     int need = 0;
-    for (const auto &c : grid_.classes) need = std::max(need, c.k);
+    for (const auto &c : grid_.classes) {
+      int k = 0;
+      for (int s = 0; s < NSLOT; ++s) k += c.C[s] != 0.0;
+      need = std::max(need, k);
+    }
     if (kmax < need) return fail(HLBM_E_ARG, "kmax smaller than the largest stencil");
     for (int p = 0; p < grid_.nnode; ++p) {
       const GridClass<double> &c = grid_.classes[grid_.cls[p]];
-      for (int s = 0; s < kmax; ++s) {
-        const bool in = s < c.k;
-        if (nbr) nbr[(size_t)p * kmax + s] = in ? p + c.off[s] : -1;
-        if (C) C[(size_t)p * kmax + s] = in ? c.C[s] : 0.0;
+      // slot order: the node itself, then the neighbours by node index
+      int order[NSLOT], k = 0;
+      order[k++] = SELF_SLOT;
+      for (int s = 0; s < NSLOT; ++s)
+        if (s != SELF_SLOT && c.C[s] != 0.0) order[k++] = s;
+      for (int u = 0; u < kmax; ++u) {
+        const bool in = u < k;
+        const int s = in ? order[u] : 0;
+        const int q = p + (s % 3 - 1) + (s / 3 - 1) * cfg_.nux;
+        if (nbr) nbr[(size_t)p * kmax + u] = in ? q : -1;
+        if (C) C[(size_t)p * kmax + u] = in ? c.C[s] : 0.0;
         if (S)
-          for (int q = 0; q < 9; ++q) S[((size_t)p * 9 + q) * kmax + s] = in ? c.S[q][s] : 0.0;
+          for (int r = 0; r < 9; ++r) S[((size_t)p * 9 + r) * kmax + u] = in ? c.S[r][s] : 0.0;
       }
     }
     return HLBM_OK;
@@ -387,15 +465,17 @@ class Case final : public CaseBase {
   }
   void release() {
     if (s_main_) (void)hipStreamSynchronize(s_main_);
-    if (s_grid_) (void)hipStreamSynchronize(s_grid_);
+    if (s_grid_ && s_grid_ != s_main_) (void)hipStreamSynchronize(s_grid_);
+    for (auto &g : gexec_)
+      if (g) (void)hipGraphExecDestroy(g);
     for (void *p : owned_) (void)hipFree(p);
     owned_.clear();
     for (auto &e : tev_)
       if (e) (void)hipEventDestroy(e);
     if (ev_fork_) (void)hipEventDestroy(ev_fork_);
     if (ev_join_) (void)hipEventDestroy(ev_join_);
+    if (s_grid_ && s_grid_ != s_main_) (void)hipStreamDestroy(s_grid_);
     if (s_main_) (void)hipStreamDestroy(s_main_);
-    if (s_grid_) (void)hipStreamDestroy(s_grid_);
   }
   int fail(int code, const char *msg) {
     err = msg;
@@ -524,6 +604,9 @@ class Case final : public CaseBase {
   unsigned long long *counts_ = nullptr;
   int k2_x0_ = 0, k2_w_ = 1, k2_h_ = 1;
   int64_t k_ = 0;
+  bool use_graphs_ = true;
+  void *lat_base_ = nullptr;
+  hipGraphExec_t gexec_[4] = {};
 };
 
 // Configuration checks shared by all storage types (mirrors the geometric

@@ -17,7 +17,6 @@
 // and the consistent collision matrix is
 //     C_ik = (1/V_P) sum_{T} integral over (CV_P in T) of phi_k,
 // which is 11/54 |T| for k = P and 7/108 |T| for the other two vertices.
-#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -92,14 +91,7 @@ bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, st
     for (int i = 0; i < nux; ++i) {
       const int p = j * nux + i;
       double V = 0.0;
-      std::vector<int> nb = {0};  // offsets; 0 = the node itself
-      std::vector<double> S(9 * 16, 0.0), C(16, 0.0);
-      auto slot = [&](int off) {
-        for (size_t s = 0; s < nb.size(); ++s)
-          if (nb[s] == off) return (int)s;
-        nb.push_back(off);
-        return (int)nb.size() - 1;
-      };
+      double S[9][NSLOT] = {}, C[NSLOT] = {};
       for (int dj = -1; dj <= 0; ++dj)
         for (int di = -1; di <= 0; ++di) {
           const int ci = i + di, cj = j + dj;
@@ -122,33 +114,23 @@ bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, st
               const double gx = -(py[qc] - py[qb]) / (2.0 * area);
               const double gy = (px[qc] - px[qb]) / (2.0 * area);
               const int cq = t.v[q];
-              const int off = ((cq & 1) - (me & 1)) + ((cq >> 1) - (me >> 1)) * nux;
-              const int s = slot(off);
-              if (s >= 16) {
-                *err = "stencil too large";
-                return false;
-              }
-              for (int c = 0; c < 9; ++c) S[c * 16 + s] -= (area / 3.0) * (CX[c] * gx + CY[c] * gy);
+              const int sdi = (cq & 1) - (me & 1), sdj = (cq >> 1) - (me >> 1);
+              const int s = (sdj + 1) * 3 + (sdi + 1);
+              for (int c = 0; c < 9; ++c) S[c][s] -= (area / 3.0) * (CX[c] * gx + CY[c] * gy);
               C[s] += area * (q == a ? 11.0 / 54.0 : 7.0 / 108.0);
             }
           }
         }
-      if (!(V > 0.0) || (int)nb.size() > KMAX) {
-        *err = "grid node without control volume or with too many neighbours";
+      if (!(V > 0.0)) {
+        *err = "grid node without control volume";
         return false;
       }
-      // canonical slot order: self first, then increasing offset
-      std::vector<int> order(nb.size());
-      for (size_t s = 0; s < nb.size(); ++s) order[s] = (int)s;
-      std::sort(order.begin() + 1, order.end(), [&](int u, int v) { return nb[u] < nb[v]; });
       GridClass<double> gc;
       std::memset(&gc, 0, sizeof(gc));
-      gc.k = (int)nb.size();
       gc.type = g->type[p];
-      for (int s = 0; s < gc.k; ++s) {
-        gc.off[s] = nb[order[s]];
-        gc.C[s] = C[order[s]] / V;
-        for (int c = 0; c < 9; ++c) gc.S[c][s] = S[c * 16 + order[s]] / V;
+      for (int s = 0; s < NSLOT; ++s) {
+        gc.C[s] = C[s] / V;
+        for (int c = 0; c < 9; ++c) gc.S[c][s] = S[c][s] / V;
       }
       std::vector<uint64_t> key(sizeof(gc) / 8 + 1, 0);
       std::memcpy(key.data(), &gc, sizeof(gc));

@@ -11,7 +11,11 @@
 
 namespace mghlbm {
 
-constexpr int KMAX = 8;  // finite-volume stencil slots per grid node (self first)
+// The grid is a split-quad mesh, so every finite-volume stencil lies in the
+// 3 x 3 node neighbourhood; stencils are stored densely over its nine slots,
+// slot = (dj + 1) * 3 + (di + 1); slot 4 is the node itself.
+constexpr int NSLOT = 9;
+constexpr int SELF_SLOT = 4;
 
 enum NodeType : int { NODE_INTERIOR = 0, NODE_INTERFACE = 1, NODE_WALL = 2 };
 
@@ -28,14 +32,14 @@ struct StepParams {
 };
 
 // One finite-volume stencil shared by every grid node with the same
-// neighbourhood geometry and role (Eq.(ulbe) coefficients).
+// neighbourhood geometry and role (Eq.(ulbe) coefficients). A slot holds a
+// neighbour exactly when its C entry is non-zero (C_ik > 0 for neighbours).
 template <class R>
 struct GridClass {
-  int k;            // used slots
+  R S[9][NSLOT];    // streaming matrix S_ik, [population][slot]
+  R C[NSLOT];       // collision matrix C_ik
   int type;         // NodeType
-  int off[KMAX];    // neighbour node-index offsets (slot 0 = 0)
-  R S[9][KMAX];     // streaming matrix S_ik
-  R C[KMAX];        // collision matrix C_ik
+  int pad;
 };
 
 struct WallEdge {

@@ -41,6 +41,7 @@ struct CaseView {
 
 template <class T, class R>
 struct Kernels {
+  static hipError_t prepare();  // one-time launch attributes (dynamic LDS of the sub-step)
   static void fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStream_t s);
   static void stream_collide(const CaseView<T, R> &v, hipStream_t s);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);

@@ -240,22 +240,53 @@ __global__ __launch_bounds__(256) void k_lattice_from_grid(CaseView<T, R> v, con
 
 // ---- K4 prologue: structured-derived values at the grid's outer nodes ----------
 // f* = f^eq,s + (1 - 1/(2 tau_s)) f^neq,s and f^neq* from the lattice at t_{k+1}
-// (pre-collision), held over the n sub-steps (Eq.(postcollision2_u)).
+// (pre-collision), held over the n sub-steps (Eq.(postcollision2_u)). Four
+// consecutive lanes take the four bilinear donors of one node and combine
+// their weighted moments with two shuffles.
 template <class T, class R>
 __global__ __launch_bounds__(256) void k_interface_donors(CaseView<T, R> v) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= v.n_iface) return;
-  const StepParams &P = v.params[*v.dk];
-  const int p = v.iface[t];
-  const int i = p % v.nux, j = p / v.nux;
-  const double X = v.xc + (double)(i - v.nux / 2) * v.h;
-  const double Y = P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
-  R rho, ux, uy, fneq[9], e[9];
-  bilinear_donors<T, R>(v, X, Y, rho, ux, uy, fneq);
-  equilibrium<R>(rho, ux, uy, e);
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = gt >> 2, d = gt & 3;
+  const bool valid = t < v.n_iface;
+  R acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = R(0);
+  int p = 0;
+  if (valid) {
+    const StepParams &P = v.params[*v.dk];
+    p = v.iface[t];
+    const int i = p % v.nux, j = p / v.nux;
+    const double X = v.xc + (double)(i - v.nux / 2) * v.h;
+    const double Y = P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
+    const double fx = floor(X), fy = floor(Y);
+    const double a = X - fx, b = Y - fy;
+    const double w = (d & 1 ? a : 1.0 - a) * (d >> 1 ? b : 1.0 - b);
+    int xd = (int)fx + (d & 1), yd = (int)fy + (d >> 1);
+    xd = xd >= v.nx ? xd - v.nx : (xd < 0 ? xd + v.nx : xd);
+    if (v.periodic_y) yd = yd >= v.ny ? yd - v.ny : (yd < 0 ? yd + v.ny : yd);
+    R f[9], e[9], r, vx, vy;
+    pull<T, R>(v.A, v.nx, v.ny, v.periodic_y, xd, yd, f);
+    moments<R>(f, r, vx, vy);
+    equilibrium<R>(r, vx, vy, e);
+    const R wr = R(w);
+    acc[0] = wr * r;
+    acc[1] = wr * vx;
+    acc[2] = wr * vy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[3 + q] = wr * (f[q] - e[q]);
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    acc[k] += __shfl_xor(acc[k], 1, 64);
+    acc[k] += __shfl_xor(acc[k], 2, 64);
+  }
+  if (!valid) return;
+  R e[9];
+  equilibrium<R>(acc[0], acc[1], acc[2], e);
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    const R n = v.k_neq * fneq[q];
+    if ((q & 3) != d) continue;
+    const R n = v.k_neq * acc[3 + q];
     v.star_n[(size_t)q * v.nnode + p] = n;
     v.star_f[(size_t)q * v.nnode + p] = e[q] + n;
   }
@@ -266,65 +297,159 @@ __global__ __launch_bounds__(256) void k_interface_donors(CaseView<T, R> v) {
 // outer interpolation nodes, where the node itself and every interpolation
 // neighbour contribute their structured-derived values. Wall nodes then take
 // the lamina velocity while keeping density and non-equilibrium part.
+//
+// A workgroup owns a 64 x 4 tile of the grid. It stages f and f^neq of the
+// tile and a one-node halo in LDS (each node's moments computed once), then
+// every lane sums its 3 x 3 stencil from LDS. Lanes of a wave are served one
+// stencil class at a time (usually one), so the coefficients are wave-uniform
+// scalar loads. Tiles are dealt to the eight XCDs in contiguous bands so a
+// band's halo rows stay in one L2.
+constexpr int TX = 64, TY = 4, LX = TX + 2, LY = TY + 2, LN = LX * LY;
+constexpr int NRING = 2 * LX + 2 * LY;  // tile positions that can lie on the grid's outer ring
+
+// position of tile-local node (lx, ly) in the ring arrays, or -1 when the
+// node is not on the grid's outer ring
+__device__ __forceinline__ int ring_slot(int gi, int gj, int lx, int ly, int nux, int nuy) {
+  if (gj == 0) return lx;
+  if (gj == nuy - 1) return LX + lx;
+  if (gi == 0) return 2 * LX + ly;
+  if (gi == nux - 1) return 2 * LX + LY + ly;
+  return -1;
+}
+
 template <class R>
-__global__ __launch_bounds__(256) void k_grid_substep(const R *__restrict__ f,
-                                                      R *__restrict__ fout, const R *__restrict__ star_f,
-                                                      const R *__restrict__ star_n, const int *__restrict__ cls,
-                                                      const GridClass<R> *__restrict__ tab, int nnode, int nux,
-                                                      int nuy, R dt, R dt_tau, const R *__restrict__ uw,
-                                                      const int64_t *__restrict__ dk, int n_sub, int m) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nnode) return;
-  const GridClass<R> &c = tab[cls[p]];
-  const bool iface = c.type == NODE_INTERFACE;
-  R ss[9], sc[9], out[9];
+__global__ __launch_bounds__(256) void k_grid_substep(const R *__restrict__ f, R *__restrict__ fout,
+                                                      const R *__restrict__ star_f, const R *__restrict__ star_n,
+                                                      const int *__restrict__ cls, const GridClass<R> *__restrict__ tab,
+                                                      int nux, int nuy, int tiles_x, int ntiles, R dt, R dt_tau,
+                                                      const R *__restrict__ uw, const int64_t *__restrict__ dk,
+                                                      int n_sub, int m) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  R(*sf)[LN] = reinterpret_cast<R(*)[LN]>(lds_raw);   // grid f
+  R(*sn)[LN] = sf + 9;                                 // grid f^neq
+  R(*rf)[NRING] = reinterpret_cast<R(*)[NRING]>(sn + 9);  // f* on the outer ring
+  R(*rn)[NRING] = rf + 9;                              // f^neq* on the outer ring
+  const int b = blockIdx.x;
+  const int t = (ntiles % 8 == 0) ? (b % 8) * (ntiles / 8) + (b / 8) : b;
+  const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
+  const bool touches_ring = x0 == 0 || y0 == 0 || x0 + TX >= nux - 1 || y0 + TY >= nuy - 1;
+  const size_t N = (size_t)nux * nuy;
+  for (int idx = threadIdx.x; idx < LN; idx += blockDim.x) {
+    const int lx = idx % LX, ly = idx / LX;
+    const int gi = x0 - 1 + lx, gj = y0 - 1 + ly;
+    if (gi >= 0 && gi < nux && gj >= 0 && gj < nuy) {
+      const size_t p = (size_t)gj * nux + gi;
+      R v[9], e[9], r, vx, vy;
 #pragma unroll
-  for (int q = 0; q < 9; ++q) ss[q] = sc[q] = R(0);
-  for (int s = 0; s < c.k; ++s) {
-    const int nb = p + c.off[s];
-    R fq[9], nq[9];
-    bool star = false;
-    if (iface) {
-      const int iq = nb % nux, jq = nb / nux;
-      star = (iq == 0 || jq == 0 || iq == nux - 1 || jq == nuy - 1);
-    }
-    if (star) {
+      for (int q = 0; q < 9; ++q) v[q] = f[q * N + p];
+      if (touches_ring) {
+        const int rs = ring_slot(gi, gj, lx, ly, nux, nuy);
+        if (rs >= 0) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        fq[q] = star_f[(size_t)q * nnode + nb];
-        nq[q] = star_n[(size_t)q * nnode + nb];
+          for (int q = 0; q < 9; ++q) {
+            rf[q][rs] = star_f[q * N + p];
+            rn[q][rs] = star_n[q * N + p];
+          }
+        }
       }
-    } else {
-      R e[9], r, vx, vy;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) fq[q] = f[(size_t)q * nnode + nb];
-      moments<R>(fq, r, vx, vy);
+      moments<R>(v, r, vx, vy);
       equilibrium<R>(r, vx, vy, e);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) nq[q] = fq[q] - e[q];
+      for (int q = 0; q < 9; ++q) {
+        sf[q][idx] = v[q];
+        sn[q][idx] = v[q] - e[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) sf[q][idx] = sn[q][idx] = R(0);
     }
-    const R cs = c.C[s];
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int gi = x0 + tx, gj = y0 + ty;
+  const bool valid = gi < nux && gj < nuy;
+  const int p = gj * nux + gi;
+  const int mine = valid ? cls[p] : -1;
+  const int ci = (ty + 1) * LX + (tx + 1);
+  const R uw_now = uw[*dk * n_sub + m];
+  R out[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      ss[q] += c.S[q][s] * fq[q];
-      sc[q] += cs * nq[q];
+  for (int q = 0; q < 9; ++q) out[q] = R(0);
+  unsigned long long pending = __ballot(valid);
+  while (pending) {
+    // one stencil class per pass; its coefficients are wave-uniform, read
+    // in uniform control flow so they come through the scalar cache
+    const int lead = __ffsll(pending) - 1;
+    const int c0 = __builtin_amdgcn_readfirstlane(__shfl(mine, lead, 64));
+    const bool take = valid && mine == c0;
+    const GridClass<R> *__restrict__ Cp = tab + c0;
+    const int type = Cp->type;
+    R cc[NSLOT];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) cc[s] = Cp->C[s];
+    if (type != NODE_INTERFACE) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        R sq[NSLOT];
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) sq[s] = Cp->S[q][s];
+        R ss = R(0), sc = R(0);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+          if (cc[s] == R(0)) continue;
+          const int li = ci + (s / 3 - 1) * LX + (s % 3 - 1);
+          ss += sq[s] * sf[q][li];
+          sc += cc[s] * sn[q][li];
+        }
+        if (take) out[q] = sf[q][ci] + dt * ss - dt_tau * sc;
+      }
+    } else {
+      // outer interpolation nodes, Eq.(postcollision2_u): neighbours on the
+      // outer ring (and the node itself) contribute structured-derived values
+      int rsl[NSLOT];
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s)
+        rsl[s] = ring_slot(gi + s % 3 - 1, gj + s / 3 - 1, tx + 1 + s % 3 - 1, ty + 1 + s / 3 - 1, nux, nuy);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        R sq[NSLOT];
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) sq[s] = Cp->S[q][s];
+        R ss = R(0), sc = R(0);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+          if (cc[s] == R(0)) continue;
+          const int li = ci + (s / 3 - 1) * LX + (s % 3 - 1);
+          const int rs = take ? rsl[s] : -1;
+          const R fq = rs >= 0 ? rf[q][rs] : sf[q][li];
+          const R nq = rs >= 0 ? rn[q][rs] : sn[q][li];
+          ss += sq[s] * fq;
+          sc += cc[s] * nq;
+        }
+        const int r0 = take ? rsl[SELF_SLOT] : -1;
+        if (take) out[q] = (r0 >= 0 ? rf[q][r0] : sf[q][ci]) + dt * ss - dt_tau * sc;
+      }
     }
-  }
+    if (type == NODE_WALL && take) {
+      // wall nodes: impose the lamina velocity, keep rho and f^neq
+      R e[9], ew[9], r, vx, vy;
+      moments<R>(out, r, vx, vy);
+      equilibrium<R>(r, vx, vy, e);
+      equilibrium<R>(r, R(0), uw_now, ew);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const R self = iface ? star_f[(size_t)q * nnode + p] : f[(size_t)q * nnode + p];
-    out[q] = self + dt * ss[q] - dt_tau * sc[q];
+      for (int q = 0; q < 9; ++q) out[q] = ew[q] + (out[q] - e[q]);
+    }
+    pending &= ~__ballot(take);
   }
-  if (c.type == NODE_WALL) {
-    R e[9], ew[9], r, vx, vy;
-    moments<R>(out, r, vx, vy);
-    equilibrium<R>(r, vx, vy, e);
-    equilibrium<R>(r, R(0), uw[*dk * n_sub + m], ew);
+  if (valid) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) out[q] = ew[q] + (out[q] - e[q]);
+    for (int q = 0; q < 9; ++q) fout[q * N + p] = out[q];
   }
-#pragma unroll
-  for (int q = 0; q < 9; ++q) fout[(size_t)q * nnode + p] = out[q];
+}
+
+template <class R>
+constexpr size_t substep_lds_bytes() {
+  return sizeof(R) * (size_t)(2 * 9 * LN + 2 * 9 * NRING);
 }
 
 // ---- K5: move the grid from y_k to y_{k+1} and refill it ---------------------
@@ -340,8 +465,7 @@ __global__ __launch_bounds__(256) void k_refill(CaseView<T, R> v, const R *__res
   const int i = p % v.nux, j = p / v.nux;
   const size_t N = (size_t)v.nnode;
   R out[9];
-  const GridClass<R> &c = v.tab[v.cls[p]];
-  if (c.type == NODE_WALL) {
+  if (v.tab[v.cls[p]].type == NODE_WALL) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) fn[q * N + p] = fo[q * N + p];
     return;
@@ -492,6 +616,12 @@ inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b
 }  // namespace
 
 template <class T, class R>
+hipError_t Kernels<T, R>::prepare() {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_grid_substep<R>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)substep_lds_bytes<R>());
+}
+
+template <class T, class R>
 void Kernels<T, R>::fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStream_t s) {
   const size_t n = plane > (size_t)nnode ? plane : (size_t)nnode;
   hipLaunchKernelGGL((k_fill_rest<T, R>), dim3(blocks(n, 256)), dim3(256), 0, s, lat, plane, grid, nnode);
@@ -509,14 +639,15 @@ void Kernels<T, R>::lattice_from_grid(const CaseView<T, R> &v, const R *grid, hi
 
 template <class T, class R>
 void Kernels<T, R>::interface_donors(const CaseView<T, R> &v, hipStream_t s) {
-  hipLaunchKernelGGL((k_interface_donors<T, R>), dim3(blocks(v.n_iface, 256)), dim3(256), 0, s, v);
+  hipLaunchKernelGGL((k_interface_donors<T, R>), dim3(blocks((size_t)4 * v.n_iface, 256)), dim3(256), 0, s, v);
 }
 
 template <class T, class R>
 void Kernels<T, R>::grid_substep(const CaseView<T, R> &v, const R *f, R *fout, int m, hipStream_t s) {
-  hipLaunchKernelGGL((k_grid_substep<R>), dim3(blocks(v.nnode, 256)), dim3(256), 0, s, f, fout,
-                     (const R *)v.star_f, (const R *)v.star_n, v.cls, v.tab, v.nnode, v.nux, v.nuy, v.dt_u,
-                     v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m);
+  const int tiles_x = (v.nux + TX - 1) / TX, tiles_y = (v.nuy + TY - 1) / TY;
+  hipLaunchKernelGGL((k_grid_substep<R>), dim3(tiles_x * tiles_y), dim3(TX * TY), substep_lds_bytes<R>(), s, f, fout,
+                     (const R *)v.star_f, (const R *)v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x,
+                     tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m);
 }
 
 template <class T, class R>
