@@ -132,7 +132,8 @@ class Case final : public CaseBase {
         t.type = g.type;
         for (int s = 0; s < NSLOT; ++s) {
           t.C[s] = (R)g.C[s];
-          for (int q = 0; q < 9; ++q) t.S[q][s] = (R)g.S[q][s];
+          t.Gx[s] = (R)g.Gx[s];
+          t.Gy[s] = (R)g.Gy[s];
         }
       }
       HIPCHK(upload(&tab_, tab.data(), tab.size() * sizeof(GridClass<R>)));
@@ -190,8 +191,9 @@ class Case final : public CaseBase {
       if (timing_) ENQ(hipEventRecord(tev_[3], s_grid_));
       Kernels<T, R>::interface_donors(v, s_grid_);
       int cur = gcur_;
-      for (int m = 0; m < d_.n; ++m) {
-        Kernels<T, R>::grid_substep(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, s_grid_);
+      for (int m = 0; m < d_.n; m += kSubstepBlock) {
+        const int cnt = std::min(kSubstepBlock, d_.n - m);
+        Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_);
         cur = 1 - cur;
       }
       if (timing_) ENQ(hipEventRecord(tev_[4], s_grid_));
@@ -422,8 +424,10 @@ class Case final : public CaseBase {
         const int q = p + (s % 3 - 1) + (s / 3 - 1) * cfg_.nux;
         if (nbr) nbr[(size_t)p * kmax + u] = in ? q : -1;
         if (C) C[(size_t)p * kmax + u] = in ? c.C[s] : 0.0;
+        static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
         if (S)
-          for (int r = 0; r < 9; ++r) S[((size_t)p * 9 + r) * kmax + u] = in ? c.S[r][s] : 0.0;
+          for (int r = 0; r < 9; ++r)
+            S[((size_t)p * 9 + r) * kmax + u] = in ? cx[r] * c.Gx[s] + cy[r] * c.Gy[s] : 0.0;
       }
     }
     return HLBM_OK;

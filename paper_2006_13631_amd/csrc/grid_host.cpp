@@ -13,7 +13,8 @@
 // each vertex) with f linear on every triangle. For such f the outflow of
 // population i through the closed control-volume boundary equals, by the
 // divergence theorem, the integral of c_i . grad f over the volume, so
-//     S_ik = -(1/V_P) sum_{T contains P} (|T|/3) c_i . grad(phi_k on T),
+//     S_ik = -(1/V_P) sum_{T contains P} (|T|/3) c_i . grad(phi_k on T)
+//          = c_ix Gx_k + c_iy Gy_k,
 // and the consistent collision matrix is
 //     C_ik = (1/V_P) sum_{T} integral over (CV_P in T) of phi_k,
 // which is 11/54 |T| for k = P and 7/108 |T| for the other two vertices.
@@ -25,9 +26,6 @@
 
 namespace mghlbm {
 namespace {
-
-constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 struct Tri {
   int v[3];         // corner ids within the cell: 0=(0,0) 1=(1,0) 2=(0,1) 3=(1,1)
@@ -91,7 +89,7 @@ bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, st
     for (int i = 0; i < nux; ++i) {
       const int p = j * nux + i;
       double V = 0.0;
-      double S[9][NSLOT] = {}, C[NSLOT] = {};
+      double Gx[NSLOT] = {}, Gy[NSLOT] = {}, C[NSLOT] = {};
       for (int dj = -1; dj <= 0; ++dj)
         for (int di = -1; di <= 0; ++di) {
           const int ci = i + di, cj = j + dj;
@@ -116,7 +114,8 @@ bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, st
               const int cq = t.v[q];
               const int sdi = (cq & 1) - (me & 1), sdj = (cq >> 1) - (me >> 1);
               const int s = (sdj + 1) * 3 + (sdi + 1);
-              for (int c = 0; c < 9; ++c) S[c][s] -= (area / 3.0) * (CX[c] * gx + CY[c] * gy);
+              Gx[s] -= (area / 3.0) * gx;
+              Gy[s] -= (area / 3.0) * gy;
               C[s] += area * (q == a ? 11.0 / 54.0 : 7.0 / 108.0);
             }
           }
@@ -130,7 +129,8 @@ bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, st
       gc.type = g->type[p];
       for (int s = 0; s < NSLOT; ++s) {
         gc.C[s] = C[s] / V;
-        for (int c = 0; c < 9; ++c) gc.S[c][s] = S[c][s] / V;
+        gc.Gx[s] = Gx[s] / V;
+        gc.Gy[s] = Gy[s] / V;
       }
       std::vector<uint64_t> key(sizeof(gc) / 8 + 1, 0);
       std::memcpy(key.data(), &gc, sizeof(gc));

@@ -32,11 +32,15 @@ struct StepParams {
 };
 
 // One finite-volume stencil shared by every grid node with the same
-// neighbourhood geometry and role (Eq.(ulbe) coefficients). A slot holds a
-// neighbour exactly when its C entry is non-zero (C_ik > 0 for neighbours).
+// neighbourhood geometry and role (Eq.(ulbe) coefficients). The streaming
+// matrix factors as S_ik = c_ix Gx_k + c_iy Gy_k, where (Gx, Gy)_k are the
+// weights of the control-volume gradient, G_k = -(1/V_P) sum_T (|T|/3)
+// grad(phi_k on T); so a stencil is 27 numbers. A slot holds a neighbour
+// exactly when its C entry is non-zero (C_ik > 0 for neighbours).
 template <class R>
 struct GridClass {
-  R S[9][NSLOT];    // streaming matrix S_ik, [population][slot]
+  R Gx[NSLOT];      // x weights of the streaming matrix
+  R Gy[NSLOT];      // y weights of the streaming matrix
   R C[NSLOT];       // collision matrix C_ik
   int type;         // NodeType
   int pad;

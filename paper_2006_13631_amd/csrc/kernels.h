@@ -39,6 +39,9 @@ struct CaseView {
   int k2_x0, k2_w, k2_h;
 };
 
+// grid sub-steps advanced per launch (temporal blocking depth)
+constexpr int kSubstepBlock = 4;
+
 template <class T, class R>
 struct Kernels {
   static hipError_t prepare();  // one-time launch attributes (dynamic LDS of the sub-step)
@@ -46,7 +49,8 @@ struct Kernels {
   static void stream_collide(const CaseView<T, R> &v, hipStream_t s);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
   static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
-  static void grid_substep(const CaseView<T, R> &v, const R *f, R *fout, int m, hipStream_t s);
+  // sub-steps m0 .. m0+count-1 (count <= kSubstepBlock) in one launch
+  static void grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s);
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
   static void force(const CaseView<T, R> &v, const R *f, hipStream_t s);
   static void lattice_to_f64(const T *src, double *dst, size_t plane, hipStream_t s);

@@ -292,164 +292,211 @@ __global__ __launch_bounds__(256) void k_interface_donors(CaseView<T, R> v) {
   }
 }
 
-// ---- K3/K4: one sub-step of the grid scheme ---------------------------------
+// ---- K3/K4: sub-steps of the grid scheme ------------------------------------
 // Eq.(ulbe) at discretization and wall nodes; Eq.(postcollision2_u) at the
 // outer interpolation nodes, where the node itself and every interpolation
 // neighbour contribute their structured-derived values. Wall nodes then take
 // the lamina velocity while keeping density and non-equilibrium part.
 //
-// A workgroup owns a 64 x 4 tile of the grid. It stages f and f^neq of the
-// tile and a one-node halo in LDS (each node's moments computed once), then
-// every lane sums its 3 x 3 stencil from LDS. Lanes of a wave are served one
-// stencil class at a time (usually one), so the coefficients are wave-uniform
-// scalar loads. Tiles are dealt to the eight XCDs in contiguous bands so a
-// band's halo rows stay in one L2.
-constexpr int TX = 64, TY = 4, LX = TX + 2, LY = TY + 2, LN = LX * LY;
-constexpr int NRING = 2 * LX + 2 * LY;  // tile positions that can lie on the grid's outer ring
+// One launch advances `count` <= H sub-steps (temporal blocking). A
+// workgroup owns a 64 x 4 tile and stages the tile plus an H-node halo in
+// LDS, node-major (f then f^neq, stride 19 so wave64 reads are free of bank
+// conflicts): every node's moments are computed once per sub-step. It also
+// keeps the structured-derived values of nodes on the grid's outer ring and
+// the stencil class of each node. Sub-step s updates the region grown by
+// count-1-s around the tile, so after `count` sub-steps the tile is exact
+// and only it is written back. A lane keeps its region nodes and their 27
+// stencil coefficients in registers for the whole launch. Tiles are dealt to
+// the eight XCDs in contiguous bands.
+constexpr int TX = 64, TY = 4;
+constexpr int NS = 19;  // LDS doubles (or floats) per node: f[9], f^neq[9], pad
 
-// position of tile-local node (lx, ly) in the ring arrays, or -1 when the
-// node is not on the grid's outer ring
-__device__ __forceinline__ int ring_slot(int gi, int gj, int lx, int ly, int nux, int nuy) {
-  if (gj == 0) return lx;
-  if (gj == nuy - 1) return LX + lx;
-  if (gi == 0) return 2 * LX + ly;
-  if (gi == nux - 1) return 2 * LX + LY + ly;
+template <int H>
+struct Region {
+  static constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RN = RX * RY;
+  static constexpr int NRING = 2 * RX + 2 * RY;  // region nodes that can lie on the outer ring
+};
+
+// slot of region node (rx, ry) (global (gi, gj)) in the ring array, or -1
+// when the node is not a grid node on the outer ring
+template <int H>
+__device__ __forceinline__ int ring_slot(int gi, int gj, int rx, int ry, int nux, int nuy) {
+  using G = Region<H>;
+  if (gi < 0 || gj < 0 || gi >= nux || gj >= nuy) return -1;
+  if (gj == 0) return rx;
+  if (gj == nuy - 1) return G::RX + rx;
+  if (gi == 0) return 2 * G::RX + ry;
+  if (gi == nux - 1) return 2 * G::RX + G::RY + ry;
   return -1;
 }
 
-template <class R>
-__global__ __launch_bounds__(256) void k_grid_substep(const R *__restrict__ f, R *__restrict__ fout,
-                                                      const R *__restrict__ star_f, const R *__restrict__ star_n,
-                                                      const int *__restrict__ cls, const GridClass<R> *__restrict__ tab,
-                                                      int nux, int nuy, int tiles_x, int ntiles, R dt, R dt_tau,
-                                                      const R *__restrict__ uw, const int64_t *__restrict__ dk,
-                                                      int n_sub, int m) {
+template <class R, int H>
+constexpr size_t substeps_lds_bytes() {
+  using G = Region<H>;
+  return sizeof(R) * (size_t)(NS * G::RN + NS * G::NRING) + sizeof(int) * (size_t)G::RN;
+}
+
+constexpr int kSubstepThreads = 512;  // 8 waves share one tile's LDS
+
+template <class R, int H>
+__global__ __launch_bounds__(kSubstepThreads) void k_grid_substeps(
+    const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
+    const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int ntiles,
+    R dt, R dt_tau, const R *__restrict__ uw, const int64_t *__restrict__ dk, int n_sub, int m0, int count) {
+  using G = Region<H>;
+  constexpr int RX = G::RX, RN = G::RN;
+  constexpr int NT = kSubstepThreads, PER = (RN + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  R(*sf)[LN] = reinterpret_cast<R(*)[LN]>(lds_raw);   // grid f
-  R(*sn)[LN] = sf + 9;                                 // grid f^neq
-  R(*rf)[NRING] = reinterpret_cast<R(*)[NRING]>(sn + 9);  // f* on the outer ring
-  R(*rn)[NRING] = rf + 9;                              // f^neq* on the outer ring
+  R *sl = reinterpret_cast<R *>(lds_raw);   // [RN][NS] grid f, f^neq
+  R *rl = sl + NS * RN;                     // [NRING][NS] f*, f^neq* on the outer ring
+  int *scls = reinterpret_cast<int *>(rl + NS * G::NRING);  // stencil class, -1 outside the grid
   const int b = blockIdx.x;
   const int t = (ntiles % 8 == 0) ? (b % 8) * (ntiles / 8) + (b / 8) : b;
-  const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
-  const bool touches_ring = x0 == 0 || y0 == 0 || x0 + TX >= nux - 1 || y0 + TY >= nuy - 1;
+  const int x0 = (t % tiles_x) * TX - H, y0 = (t / tiles_x) * TY - H;  // region origin
+  const bool touches_ring = x0 <= 0 || y0 <= 0 || x0 + RX >= nux || y0 + G::RY >= nuy;
   const size_t N = (size_t)nux * nuy;
-  for (int idx = threadIdx.x; idx < LN; idx += blockDim.x) {
-    const int lx = idx % LX, ly = idx / LX;
-    const int gi = x0 - 1 + lx, gj = y0 - 1 + ly;
-    if (gi >= 0 && gi < nux && gj >= 0 && gj < nuy) {
-      const size_t p = (size_t)gj * nux + gi;
-      R v[9], e[9], r, vx, vy;
+
+  // stage the region; a lane's loads are issued together
+  {
+    R v[PER][9];
+    bool inside[PER];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) v[q] = f[q * N + p];
-      if (touches_ring) {
-        const int rs = ring_slot(gi, gj, lx, ly, nux, nuy);
+    for (int u = 0; u < PER; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      const int gi = x0 + idx % RX, gj = y0 + idx / RX;
+      const bool in = idx < RN && gi >= 0 && gi < nux && gj >= 0 && gj < nuy;
+      inside[u] = in;
+      const size_t p = in ? (size_t)gj * nux + gi : 0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) v[u][q] = in ? f[q * N + p] : R(0);
+      if (idx < RN) scls[idx] = in ? cls[p] : -1;
+      if (touches_ring && in) {
+        const int rs = ring_slot<H>(gi, gj, idx % RX, idx / RX, nux, nuy);
         if (rs >= 0) {
 #pragma unroll
           for (int q = 0; q < 9; ++q) {
-            rf[q][rs] = star_f[q * N + p];
-            rn[q][rs] = star_n[q * N + p];
+            rl[rs * NS + q] = star_f[q * N + p];
+            rl[rs * NS + 9 + q] = star_n[q * N + p];
           }
         }
       }
-      moments<R>(v, r, vx, vy);
-      equilibrium<R>(r, vx, vy, e);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      if (idx >= RN) continue;
+      R e[9], r, vx, vy;
+      if (inside[u]) {
+        moments<R>(v[u], r, vx, vy);
+        equilibrium<R>(r, vx, vy, e);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) e[q] = v[u][q];
+      }
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
-        sf[q][idx] = v[q];
-        sn[q][idx] = v[q] - e[q];
+        sl[idx * NS + q] = v[u][q];
+        sl[idx * NS + 9 + q] = v[u][q] - e[q];
       }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) sf[q][idx] = sn[q][idx] = R(0);
     }
   }
   __syncthreads();
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int gi = x0 + tx, gj = y0 + ty;
-  const bool valid = gi < nux && gj < nuy;
-  const int p = gj * nux + gi;
-  const int mine = valid ? cls[p] : -1;
-  const int ci = (ty + 1) * LX + (tx + 1);
-  const R uw_now = uw[*dk * n_sub + m];
-  R out[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) out[q] = R(0);
-  unsigned long long pending = __ballot(valid);
-  while (pending) {
-    // one stencil class per pass; its coefficients are wave-uniform, read
-    // in uniform control flow so they come through the scalar cache
-    const int lead = __ffsll(pending) - 1;
-    const int c0 = __builtin_amdgcn_readfirstlane(__shfl(mine, lead, 64));
-    const bool take = valid && mine == c0;
-    const GridClass<R> *__restrict__ Cp = tab + c0;
-    const int type = Cp->type;
-    R cc[NSLOT];
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) cc[s] = Cp->C[s];
-    if (type != NODE_INTERFACE) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        R sq[NSLOT];
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s) sq[s] = Cp->S[q][s];
-        R ss = R(0), sc = R(0);
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s) {
-          if (cc[s] == R(0)) continue;
-          const int li = ci + (s / 3 - 1) * LX + (s % 3 - 1);
-          ss += sq[s] * sf[q][li];
-          sc += cc[s] * sn[q][li];
-        }
-        if (take) out[q] = sf[q][ci] + dt * ss - dt_tau * sc;
-      }
-    } else {
-      // outer interpolation nodes, Eq.(postcollision2_u): neighbours on the
-      // outer ring (and the node itself) contribute structured-derived values
-      int rsl[NSLOT];
-#pragma unroll
-      for (int s = 0; s < NSLOT; ++s)
-        rsl[s] = ring_slot(gi + s % 3 - 1, gj + s / 3 - 1, tx + 1 + s % 3 - 1, ty + 1 + s / 3 - 1, nux, nuy);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        R sq[NSLOT];
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s) sq[s] = Cp->S[q][s];
-        R ss = R(0), sc = R(0);
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s) {
-          if (cc[s] == R(0)) continue;
-          const int li = ci + (s / 3 - 1) * LX + (s % 3 - 1);
-          const int rs = take ? rsl[s] : -1;
-          const R fq = rs >= 0 ? rf[q][rs] : sf[q][li];
-          const R nq = rs >= 0 ? rn[q][rs] : sn[q][li];
-          ss += sq[s] * fq;
-          sc += cc[s] * nq;
-        }
-        const int r0 = take ? rsl[SELF_SLOT] : -1;
-        if (take) out[q] = (r0 >= 0 ? rf[q][r0] : sf[q][ci]) + dt * ss - dt_tau * sc;
-      }
-    }
-    if (type == NODE_WALL && take) {
-      // wall nodes: impose the lamina velocity, keep rho and f^neq
-      R e[9], ew[9], r, vx, vy;
-      moments<R>(out, r, vx, vy);
-      equilibrium<R>(r, vx, vy, e);
-      equilibrium<R>(r, R(0), uw_now, ew);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) out[q] = ew[q] + (out[q] - e[q]);
-    }
-    pending &= ~__ballot(take);
-  }
-  if (valid) {
-#pragma unroll
-    for (int q = 0; q < 9; ++q) fout[q * N + p] = out[q];
-  }
-}
 
-template <class R>
-constexpr size_t substep_lds_bytes() {
-  return sizeof(R) * (size_t)(2 * 9 * LN + 2 * 9 * NRING);
+  // each lane keeps the same region nodes for all sub-steps, with their
+  // stencil coefficients in registers (27 per node: Gx, Gy, C)
+  R gx[PER][NSLOT], gy[PER][NSLOT], cc[PER][NSLOT];
+  int typ[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int idx = threadIdx.x + u * NT;
+    const int c = idx < RN ? scls[idx] : -1;
+    typ[u] = c >= 0 ? tab[c].type : -1;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      gx[u][s] = c >= 0 ? tab[c].Gx[s] : R(0);
+      gy[u][s] = c >= 0 ? tab[c].Gy[s] : R(0);
+      cc[u][s] = c >= 0 ? tab[c].C[s] : R(0);
+    }
+  }
+
+  for (int sub = 0; sub < count; ++sub) {
+    const int ex = count - 1 - sub;  // region growth still exact after this sub-step
+    const R uw_now = uw[*dk * n_sub + m0 + sub];
+    R out[PER][9];
+    bool upd[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      const int rx = idx % RX, ry = idx / RX;
+      upd[u] = idx < RN && typ[u] >= 0 && rx >= H - ex && rx < H + TX + ex && ry >= H - ex && ry < H + TY + ex;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) out[u][q] = R(0);
+      if (__ballot(upd[u]) == 0) continue;  // nothing to update in this wave
+      const int gi = x0 + rx, gj = y0 + ry;
+      // LDS row (offset from the LDS base) of each stencil slot; on the outer
+      // ring an interpolation node reads structured-derived values instead
+      // (Eq.(postcollision2_u)). Absent neighbours have zero weights.
+      int row[NSLOT];
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s) {
+        const int di = s % 3 - 1, dj = s / 3 - 1;
+        const int cidx = upd[u] ? idx + dj * RX + di : idx;
+        row[s] = cidx * NS;
+        if (typ[u] == NODE_INTERFACE && upd[u]) {
+          const int rs = ring_slot<H>(gi + di, gj + dj, rx + di, ry + dj, nux, nuy);
+          if (rs >= 0) row[s] = NS * RN + rs * NS;
+        }
+      }
+      // streaming c_q . sum_s G_s f_q,s and collision sum_s C_s f^neq_q,s
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        R ax = R(0), ay = R(0), sc = R(0);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+          const R fq = sl[row[s] + q];
+          if (CXd[q] != 0) ax += gx[u][s] * fq;
+          if (CYd[q] != 0) ay += gy[u][s] * fq;
+          sc += cc[u][s] * sl[row[s] + 9 + q];
+        }
+        out[u][q] = sl[row[SELF_SLOT] + q] + dt * (R(CXd[q]) * ax + R(CYd[q]) * ay) - dt_tau * sc;
+      }
+      if (typ[u] == NODE_WALL && upd[u]) {
+        // wall nodes: impose the lamina velocity, keep rho and f^neq
+        R e[9], ew[9], r, vx, vy;
+        moments<R>(out[u], r, vx, vy);
+        equilibrium<R>(r, vx, vy, e);
+        equilibrium<R>(r, R(0), uw_now, ew);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) out[u][q] = ew[q] + (out[u][q] - e[q]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      if (!upd[u]) continue;
+      const int idx = threadIdx.x + u * NT;
+      R e[9], r, vx, vy;
+      moments<R>(out[u], r, vx, vy);
+      equilibrium<R>(r, vx, vy, e);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        sl[idx * NS + q] = out[u][q];
+        sl[idx * NS + 9 + q] = out[u][q] - e[q];
+      }
+    }
+    __syncthreads();
+  }
+
+  // the tile is exact: write it back
+  for (int j = threadIdx.x; j < TX * TY; j += NT) {
+    const int rx = H + j % TX, ry = H + j / TX;
+    const int gi = x0 + rx, gj = y0 + ry;
+    if (gi >= nux || gj >= nuy) continue;
+    const int ci = ry * RX + rx;
+    const size_t p = (size_t)gj * nux + gi;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fout[q * N + p] = sl[ci * NS + q];
+  }
 }
 
 // ---- K5: move the grid from y_k to y_{k+1} and refill it ---------------------
@@ -617,8 +664,9 @@ inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b
 
 template <class T, class R>
 hipError_t Kernels<T, R>::prepare() {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_grid_substep<R>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)substep_lds_bytes<R>());
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_grid_substeps<R, kSubstepBlock>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)substeps_lds_bytes<R, kSubstepBlock>());
 }
 
 template <class T, class R>
@@ -643,11 +691,12 @@ void Kernels<T, R>::interface_donors(const CaseView<T, R> &v, hipStream_t s) {
 }
 
 template <class T, class R>
-void Kernels<T, R>::grid_substep(const CaseView<T, R> &v, const R *f, R *fout, int m, hipStream_t s) {
+void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s) {
   const int tiles_x = (v.nux + TX - 1) / TX, tiles_y = (v.nuy + TY - 1) / TY;
-  hipLaunchKernelGGL((k_grid_substep<R>), dim3(tiles_x * tiles_y), dim3(TX * TY), substep_lds_bytes<R>(), s, f, fout,
-                     (const R *)v.star_f, (const R *)v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x,
-                     tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m);
+  hipLaunchKernelGGL((k_grid_substeps<R, kSubstepBlock>), dim3(tiles_x * tiles_y), dim3(kSubstepThreads),
+                     (substeps_lds_bytes<R, kSubstepBlock>()), s, f, fout, (const R *)v.star_f, (const R *)v.star_n,
+                     v.cls, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw,
+                     (const int64_t *)v.dk, v.n_sub, m0, count);
 }
 
 template <class T, class R>

@@ -178,3 +178,17 @@ def test_reduced_precision_theta(storage, tol):
     t64, tlo = ref.theta(), low.theta()
     _say("theta f64", t64, "reduced", tlo, "rel", abs(tlo - t64) / abs(t64))
     assert abs(tlo - t64) <= tol * abs(t64)
+
+
+@pytest.mark.parametrize("storage,tol", [(hlbm.FP32, 2e-6), (hlbm.FP16_DEV, 2e-4)])
+@pytest.mark.parametrize("name", ["tiny_ragged", "lamina_256x128"])
+def test_reduced_precision_state(oracle, storage, tol, name):
+    """FP32 and FP16-deviation storage against the FP64 oracle over the first
+    steps: largest deviation of either grid relative to max|f|."""
+    _say("reduced precision state", name, storage)
+    o, g, _ = _pair(oracle, preset(name), steps=20, storage=storage)
+    o.step(20)
+    g.step(20)
+    errs = {"lattice": _rel(g.lattice(), o.lattice()), "grid": _rel(g.grid(), o.grid())}
+    _say("errors", errs)
+    assert max(errs.values()) <= tol, errs
