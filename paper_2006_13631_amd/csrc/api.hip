@@ -100,8 +100,12 @@ class Case final : public CaseBase {
     }
     HIPCHK((Kernels<T, R>::prepare()));
     HIPCHK(hipStreamCreateWithFlags(&s_main_, hipStreamNonBlocking));
-    if (std::getenv("HLBM_ONE_STREAM")) s_grid_ = s_main_;
-    else HIPCHK(hipStreamCreateWithFlags(&s_grid_, hipStreamNonBlocking));
+    // The grid path may run on a second stream, concurrently with the
+    // lattice update; measured on MI355X it is faster on the same stream
+    // (the latency-bound sub-steps slow down under the lattice kernel's HBM
+    // traffic), so a second stream is opt-in.
+    if (std::getenv("HLBM_TWO_STREAMS")) HIPCHK(hipStreamCreateWithFlags(&s_grid_, hipStreamNonBlocking));
+    else s_grid_ = s_main_;
     HIPCHK(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
     HIPCHK(alloc(&lat_[0], 9 * plane_ * sizeof(T)));
@@ -185,8 +189,7 @@ class Case final : public CaseBase {
         ENQ(hipStreamWaitEvent(s_grid_, ev_fork_, 0));
       }
       // 2. lattice stream-collide, Eq.(LBE)
-      Kernels<T, R>::stream_collide(v, s_main_);
-      if (timing_) ENQ(hipEventRecord(tev_[2], s_main_));
+      Kernels<T, R>::stream_collide(v, s_main_, timing_ ? tev_[8] : nullptr, timing_ ? tev_[2] : nullptr);
       // 3.-6. grid path: donors, n sub-steps, refill, force
       if (timing_) ENQ(hipEventRecord(tev_[3], s_grid_));
       Kernels<T, R>::interface_donors(v, s_grid_);
@@ -208,8 +211,7 @@ class Case final : public CaseBase {
       }
     } else {
       if (timing_) ENQ(hipEventRecord(tev_[1], s_main_));
-      Kernels<T, R>::stream_collide(v, s_main_);
-      if (timing_) ENQ(hipEventRecord(tev_[2], s_main_));
+      Kernels<T, R>::stream_collide(v, s_main_, timing_ ? tev_[8] : nullptr, timing_ ? tev_[2] : nullptr);
     }
     if (timing_) ENQ(hipEventRecord(tev_[7], s_main_));
     ENQ(hipGetLastError());
@@ -569,7 +571,7 @@ class Case final : public CaseBase {
         tcount_[id] += 1;
       }
     };
-    add(HLBM_K_STREAM_COLLIDE, tev_[1], tev_[2]);
+    add(HLBM_K_STREAM_COLLIDE, tev_[8], tev_[2]);
     if (has_grid_) {
       add(HLBM_K_LATTICE_FROM_GRID, tev_[0], tev_[1]);
       add(HLBM_K_GRID_SUBSTEPS, tev_[3], tev_[4]);
@@ -588,7 +590,7 @@ class Case final : public CaseBase {
   HostGrid grid_;
   hipStream_t s_main_ = nullptr, s_grid_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
-  hipEvent_t tev_[8] = {};
+  hipEvent_t tev_[9] = {};
   bool timing_ = false;
   double tms_[6] = {};
   int64_t tcount_[6] = {};

@@ -46,7 +46,9 @@ template <class T, class R>
 struct Kernels {
   static hipError_t prepare();  // one-time launch attributes (dynamic LDS of the sub-step)
   static void fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStream_t s);
-  static void stream_collide(const CaseView<T, R> &v, hipStream_t s);
+  // start/stop (optional): events recorded at the kernel's own start and end
+  static void stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start = nullptr,
+                             hipEvent_t stop = nullptr);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
   static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
   // sub-steps m0 .. m0+count-1 (count <= kSubstepBlock) in one launch

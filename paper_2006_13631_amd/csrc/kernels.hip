@@ -7,6 +7,8 @@
 //
 // D2Q9 ordering: rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1),
 // (1,-1); weights 4/9, 1/9 (axis), 1/36 (diagonal); c_s^2 = 1/3.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 #include "kernels.h"
@@ -25,15 +27,23 @@ __device__ __forceinline__ R wgt(int q) {
 // ---- storage traits --------------------------------------------------------
 template <class T>
 struct Stor;
+// st_stream: store of a value that is not read again in this kernel; the
+// lattice output is streamed with non-temporal stores.
 template <>
 struct Stor<double> {
   static __device__ __forceinline__ double ld(const double *p, size_t i, int) { return p[i]; }
   static __device__ __forceinline__ void st(double *p, size_t i, int, double v) { p[i] = v; }
+  static __device__ __forceinline__ void st_stream(double *p, size_t i, int, double v) {
+    __builtin_nontemporal_store(v, p + i);
+  }
 };
 template <>
 struct Stor<float> {
   static __device__ __forceinline__ float ld(const float *p, size_t i, int) { return p[i]; }
   static __device__ __forceinline__ void st(float *p, size_t i, int, float v) { p[i] = v; }
+  static __device__ __forceinline__ void st_stream(float *p, size_t i, int, float v) {
+    __builtin_nontemporal_store(v, p + i);
+  }
 };
 template <>
 struct Stor<__half> {  // deviation from the rest equilibrium w_i
@@ -42,6 +52,11 @@ struct Stor<__half> {  // deviation from the rest equilibrium w_i
   }
   static __device__ __forceinline__ void st(__half *p, size_t i, int q, float v) {
     p[i] = __float2half_rn(v - wgt<float>(q));
+  }
+  static __device__ __forceinline__ void st_stream(__half *p, size_t i, int q, float v) {
+    const __half h = __float2half_rn(v - wgt<float>(q));
+    __builtin_nontemporal_store(*reinterpret_cast<const unsigned short *>(&h),
+                                reinterpret_cast<unsigned short *>(p + i));
   }
 };
 
@@ -188,7 +203,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(CaseView<T, R> v) {
   moments<R>(f, rho, ux, uy);
   equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) Stor<T>::st(v.B, q * plane + c, q, f[q] - v.inv_tau * (f[q] - e[q]));
+  for (int q = 0; q < 9; ++q) Stor<T>::st_stream(v.B, q * plane + c, q, f[q] - v.inv_tau * (f[q] - e[q]));
 }
 
 // ---- K2: lattice interpolation nodes from the grid, Eq.(postcollision2_s) ----
@@ -676,8 +691,13 @@ void Kernels<T, R>::fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStrea
 }
 
 template <class T, class R>
-void Kernels<T, R>::stream_collide(const CaseView<T, R> &v, hipStream_t s) {
-  hipLaunchKernelGGL((k_stream_collide<T, R>), dim3(blocks(v.nx, 256), v.ny), dim3(256), 0, s, v);
+void Kernels<T, R>::stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  if (start) {  // events taken by the command processor at the kernel's own start and end
+    hipExtLaunchKernelGGL((k_stream_collide<T, R>), dim3(blocks(v.nx, 256), v.ny), dim3(256), 0, s, start, stop, 0,
+                          v);
+  } else {
+    hipLaunchKernelGGL((k_stream_collide<T, R>), dim3(blocks(v.nx, 256), v.ny), dim3(256), 0, s, v);
+  }
 }
 
 template <class T, class R>

@@ -1,0 +1,112 @@
+"""Summaries of rocprofv3 CSV output (kernel statistics and HBM counters).
+
+    python -m paper_2006_13631_amd.profiling stats KERNEL_STATS_CSV --out FILE --command CMD
+    python -m paper_2006_13631_amd.profiling traffic --fetch PMC_CSV --write PMC_CSV \
+        --kernel k_stream_collide --copy-bytes N --out FILE --command CMD
+
+`traffic` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch) of
+a kernel into bytes per launch, each scaled by what the same counter reads
+for a plain device copy of known size recorded in the same run, and stores
+the SHA-256 of the kernel source so a later benchmark can tell whether the
+counters still describe the kernel it runs.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+COPY_KERNEL = "copyBuffer"
+
+
+def source_sha256(path: str = KERNEL_SOURCE) -> str:
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def _short(name: str) -> str:
+    name = name.replace("mghlbm::(anonymous namespace)::", "")
+    return name.split("(")[0].replace("void ", "")
+
+
+def stats_table(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    lines = [f"{'kernel':46s} {'calls':>7s} {'avg_us':>10s} {'min_us':>9s} {'max_us':>9s} {'pct':>7s}"]
+    for r in rows:
+        lines.append(f"{_short(r['Name'])[:46]:46s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.3f} "
+                     f"{float(r['MinNs']) / 1e3:9.3f} {float(r['MaxNs']) / 1e3:9.3f} {float(r['Percentage']):7.2f}")
+    return "\n".join(lines)
+
+
+def _per_dispatch(path: str, counter: str):
+    """{kernel: [value per dispatch]} for one counter (summed over its
+    instances within a dispatch)."""
+    rows = list(csv.DictReader(open(path)))
+    acc = collections.defaultdict(float)
+    names = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        acc[d] += float(r["Counter_Value"])
+        names[d] = r["Kernel_Name"]
+    out = collections.defaultdict(list)
+    for d, v in acc.items():
+        out[names[d]].append(v)
+    return out
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dict:
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        per = _per_dispatch(path, counter)
+        kv = [v for n, vs in per.items() if kernel in n for v in vs]
+        cv = [v for n, vs in per.items() if COPY_KERNEL in n for v in vs]
+        if not kv or not cv:
+            raise SystemExit(f"{counter}: no dispatch of {kernel!r} or of the copy kernel in {path}")
+        copy_kib = max(cv)  # the calibration copy is the largest copy of the run
+        scale = (copy_bytes / 1024.0) / copy_kib
+        res[counter] = {"kernel_kib_per_dispatch": sum(kv) / len(kv), "dispatches": len(kv),
+                        "copy_kib": copy_kib, "copy_scale": scale,
+                        "bytes_per_launch": sum(kv) / len(kv) * 1024.0 * scale}
+    res["bytes_per_launch"] = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--out", required=True)
+    s.add_argument("--command", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--storage", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--command", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        text = f"# rocprofv3 kernel statistics\n# command: {a.command}\n" + stats_table(a.csv) + "\n"
+        open(a.out, "w").write(text)
+        print(text)
+    else:
+        res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes)
+        res.update({"kernel": a.kernel, "workload": a.workload, "storage": a.storage,
+                    "source_sha256": source_sha256(), "command": a.command})
+        json.dump(res, open(a.out, "w"), indent=1)
+        print(json.dumps(res, indent=1))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
