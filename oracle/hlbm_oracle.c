@@ -21,6 +21,25 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+/* Scalar of every quantity that depends on the physical parameters. The
+ * default build uses double. Built with -DOR_COMPLEX_STEP it uses
+ * double _Complex: A, omega and tau can then carry an imaginary perturbation
+ * i h, and Im(output)/h is the exact derivative of the discrete method
+ * (complex-step differentiation; every decision uses the real part). The
+ * grid geometry and its matrices stay double. */
+#ifdef OR_COMPLEX_STEP
+#include <complex.h>
+typedef double _Complex real;
+#define RE(x) creal(x)
+#define RSIN csin
+#define RCOS ccos
+#else
+typedef double real;
+#define RE(x) (x)
+#define RSIN sin
+#define RCOS cos
+#endif
+
 /* ------------------------------------------------------------------ */
 /* D2Q9 velocity set: rest, 4 axis, 4 diagonal directions              */
 /* ------------------------------------------------------------------ */
@@ -41,18 +60,22 @@ void or_d2q9(int32_t cx[9], int32_t cy[9], double w[9]) {
 }
 
 /* Eq.(local_eq): second-order polynomial equilibrium. */
-void or_feq(double rho, double ux, double uy, double feq[9]) {
-  const double uu = ux * ux + uy * uy;
+static void feq_r(real rho, real ux, real uy, real feq[9]) {
+  const real uu = ux * ux + uy * uy;
   for (int i = 0; i < 9; ++i) {
-    const double cu = CX[i] * ux + CY[i] * uy;
+    const real cu = CX[i] * ux + CY[i] * uy;
     feq[i] = WT[i] * rho *
              (1.0 + cu / CS2 + (cu * cu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
   }
 }
 
+#ifndef OR_COMPLEX_STEP
+void or_feq(double rho, double ux, double uy, double feq[9]) { feq_r(rho, ux, uy, feq); }
+#endif
+
 /* density and velocity: the first two moments of f (text after Eq.(local_eq)) */
-static void moments(const double f[9], double *rho, double *ux, double *uy) {
-  double r = 0.0, mx = 0.0, my = 0.0;
+static void moments(const real f[9], real *rho, real *ux, real *uy) {
+  real r = 0.0, mx = 0.0, my = 0.0;
   for (int i = 0; i < 9; ++i) {
     r += f[i];
     mx += CX[i] * f[i];
@@ -76,15 +99,15 @@ static int wrap(int a, int n) { return ((a % n) + n) % n; }
  * arriving at (x,y) along c_i left x - c_i one step earlier. Across a y wall
  * (bc 0) it is the opposite population of the same node, reflected halfway;
  * a wall moving with x-velocity uw adds 2 w_i rho0 c_i.u_w / c_s^2. */
-static void pull_node(const double *A, int nx, int ny, int bc, int x, int y,
-                      double u_bot, double u_top, double f[9]) {
+static void pull_node(const real *A, int nx, int ny, int bc, int x, int y,
+                      real u_bot, real u_top, real f[9]) {
   for (int i = 0; i < 9; ++i) {
     const int xs = wrap(x - CX[i], nx);
     int ys = y - CY[i];
     if (bc == OR_BC_PERIODIC) {
       ys = wrap(ys, ny);
     } else if (ys < 0 || ys >= ny) {
-      const double uw = (ys < 0) ? u_bot : u_top;
+      const real uw = (ys < 0) ? u_bot : u_top;
       f[i] = A[lidx(nx, ny, OPP[i], x, y)] + 2.0 * WT[i] * 1.0 * (CX[i] * uw) / CS2;
       continue;
     }
@@ -92,25 +115,33 @@ static void pull_node(const double *A, int nx, int ny, int bc, int x, int y,
   }
 }
 
-void or_lattice_step(const double *A, double *B, int32_t nx, int32_t ny,
-                     int32_t bc, double tau, double u_bot, double u_top,
-                     const uint8_t *disc) {
+static void lattice_step_r(const real *A, real *B, int32_t nx, int32_t ny,
+                           int32_t bc, real tau, real u_bot, real u_top,
+                           const uint8_t *disc) {
   for (int y = 0; y < ny; ++y) {
     for (int x = 0; x < nx; ++x) {
       if (disc && !disc[(size_t)y * nx + x]) {
         for (int i = 0; i < 9; ++i) B[lidx(nx, ny, i, x, y)] = A[lidx(nx, ny, i, x, y)];
         continue;
       }
-      double f[9], feq[9], rho, ux, uy;
+      real f[9], feq[9], rho, ux, uy;
       pull_node(A, nx, ny, bc, x, y, u_bot, u_top, f);
       moments(f, &rho, &ux, &uy);
-      or_feq(rho, ux, uy, feq);
+      feq_r(rho, ux, uy, feq);
       /* Eq.(LBE) with Delta t_s = 1: relax toward equilibrium */
       for (int i = 0; i < 9; ++i)
         B[lidx(nx, ny, i, x, y)] = f[i] - (1.0 / tau) * (f[i] - feq[i]);
     }
   }
 }
+
+#ifndef OR_COMPLEX_STEP
+void or_lattice_step(const double *A, double *B, int32_t nx, int32_t ny,
+                     int32_t bc, double tau, double u_bot, double u_top,
+                     const uint8_t *disc) {
+  lattice_step_r(A, B, nx, ny, bc, tau, u_bot, u_top, disc);
+}
+#endif
 
 /* ------------------------------------------------------------------ */
 /* Triangular body-fitted grid and its finite-volume matrices          */
@@ -182,6 +213,15 @@ void or_mesh_triangles(const or_mesh *m, int32_t *tri, double *txy) {
 
 /* barycentric coordinates of (px,py) in the triangle with vertices v[3][2] */
 static void bary(const double *v, double px, double py, double lam[3]) {
+  const double x0 = v[0], y0 = v[1], x1 = v[2], y1 = v[3], x2 = v[4], y2 = v[5];
+  const double d = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
+  lam[1] = ((px - x0) * (y2 - y0) - (x2 - x0) * (py - y0)) / d;
+  lam[2] = ((x1 - x0) * (py - y0) - (px - x0) * (y1 - y0)) / d;
+  lam[0] = 1.0 - lam[1] - lam[2];
+}
+
+/* same, for a point whose coordinates may carry a perturbation */
+static void bary_r(const double *v, real px, real py, real lam[3]) {
   const double x0 = v[0], y0 = v[1], x1 = v[2], y1 = v[3], x2 = v[4], y2 = v[5];
   const double d = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
   lam[1] = ((px - x0) * (y2 - y0) - (x2 - x0) * (py - y0)) / d;
@@ -610,28 +650,28 @@ void or_mesh_stencil(const or_mesh *m, int32_t kmax, int32_t *nbr, double *S,
  * Refill procedure): after the Eq.(ulbe) update over the control volume closed
  * along the wall, the velocity is set to the wall velocity while the density
  * and the non-equilibrium part are kept: f <- f^eq(rho, u_w) + (f - f^eq(rho, u)). */
-void or_fv_substep(const or_mesh *m, const double *f, const double *star_eq,
-                   const double *star_neq, double *fout, double tau_u,
-                   double dt_u, const double *uwx, const double *uwy) {
+static void fv_substep_r(const or_mesh *m, const real *f, const real *star_eq,
+                         const real *star_neq, real *fout, real tau_u,
+                         double dt_u, const real *uwx, const real *uwy) {
   const int N = m->nnode;
-  double *feq = malloc((size_t)9 * N * sizeof(double));
+  real *feq = malloc((size_t)9 * N * sizeof(real));
   for (int p = 0; p < N; ++p) {
-    double fp[9], e[9], rho, ux, uy;
+    real fp[9], e[9], rho, ux, uy;
     for (int i = 0; i < 9; ++i) fp[i] = f[(size_t)i * N + p];
     moments(fp, &rho, &ux, &uy);
-    or_feq(rho, ux, uy, e);
+    feq_r(rho, ux, uy, e);
     for (int i = 0; i < 9; ++i) feq[(size_t)i * N + p] = e[i];
   }
   for (int p = 0; p < N; ++p) {
     const int iface = (m->type[p] == OR_NODE_INTERFACE);
-    double out[9];
+    real out[9];
     for (int i = 0; i < 9; ++i) {
-      double sum_s = 0.0, sum_c = 0.0, self;
+      real sum_s = 0.0, sum_c = 0.0, self;
       if (iface) self = star_eq[(size_t)i * N + p] + star_neq[(size_t)i * N + p];
       else self = f[(size_t)i * N + p];
       for (int k = 0; k < m->nk[p]; ++k) {
         const int q = m->nbr[p * KCAP + k];
-        double fq, nq;
+        real fq, nq;
         if (iface && m->type[q] == OR_NODE_INTERFACE) {
           fq = star_eq[(size_t)i * N + q] + star_neq[(size_t)i * N + q];
           nq = star_neq[(size_t)i * N + q];
@@ -645,16 +685,24 @@ void or_fv_substep(const or_mesh *m, const double *f, const double *star_eq,
       out[i] = self + dt_u * sum_s - (dt_u / tau_u) * sum_c;
     }
     if (m->type[p] == OR_NODE_WALL) {
-      double rho, ux, uy, e[9], ew[9];
+      real rho, ux, uy, e[9], ew[9];
       moments(out, &rho, &ux, &uy);
-      or_feq(rho, ux, uy, e);
-      or_feq(rho, uwx[p], uwy[p], ew);
+      feq_r(rho, ux, uy, e);
+      feq_r(rho, uwx[p], uwy[p], ew);
       for (int i = 0; i < 9; ++i) out[i] = ew[i] + (out[i] - e[i]);
     }
     for (int i = 0; i < 9; ++i) fout[(size_t)i * N + p] = out[i];
   }
   free(feq);
 }
+
+#ifndef OR_COMPLEX_STEP
+void or_fv_substep(const or_mesh *m, const double *f, const double *star_eq,
+                   const double *star_neq, double *fout, double tau_u,
+                   double dt_u, const double *uwx, const double *uwy) {
+  fv_substep_r(m, f, star_eq, star_neq, fout, tau_u, dt_u, uwx, uwy);
+}
+#endif
 
 /* Force on the body per unit depth (reading: the paper computes it on the
  * grid nodes lying on the body surface but gives no formula). Traction
@@ -663,27 +711,27 @@ void or_fv_substep(const or_mesh *m, const double *f, const double *star_eq,
  * grid's f^neq already carries the structured factor (1 - 1/(2 tau_s)) by
  * Eq.(continuity_stresses). n points out of the body; each wall edge is
  * integrated with the trapezoid rule. */
-void or_mesh_force(const or_mesh *m, const double *f, double F[2]) {
+static void mesh_force_r(const or_mesh *m, const real *f, real F[2]) {
   const int N = m->nnode;
   F[0] = 0.0;
   F[1] = 0.0;
   for (int e = 0; e < m->nwe; ++e) {
     const double nx = m->wn[2 * e], ny = m->wn[2 * e + 1];
-    double tx = 0.0, ty = 0.0;
+    real tx = 0.0, ty = 0.0;
     for (int s = 0; s < 2; ++s) {
       const int p = m->we[2 * e + s];
-      double fp[9], eq[9], rho, ux, uy;
+      real fp[9], eq[9], rho, ux, uy;
       for (int i = 0; i < 9; ++i) fp[i] = f[(size_t)i * N + p];
       moments(fp, &rho, &ux, &uy);
-      or_feq(rho, ux, uy, eq);
-      double sxx = 0.0, sxy = 0.0, syy = 0.0;
+      feq_r(rho, ux, uy, eq);
+      real sxx = 0.0, sxy = 0.0, syy = 0.0;
       for (int i = 0; i < 9; ++i) {
-        const double fn = fp[i] - eq[i];
+        const real fn = fp[i] - eq[i];
         sxx -= CX[i] * CX[i] * fn;
         sxy -= CX[i] * CY[i] * fn;
         syy -= CY[i] * CY[i] * fn;
       }
-      const double pp = CS2 * (rho - 1.0);
+      const real pp = CS2 * (rho - 1.0);
       tx += -pp * nx + sxx * nx + sxy * ny;
       ty += -pp * ny + sxy * nx + syy * ny;
     }
@@ -692,28 +740,33 @@ void or_mesh_force(const or_mesh *m, const double *f, double F[2]) {
   }
 }
 
+#ifndef OR_COMPLEX_STEP
+void or_mesh_force(const or_mesh *m, const double *f, double F[2]) { mesh_force_r(m, f, F); }
+#endif
+
 /* ------------------------------------------------------------------ */
 /* The hybrid method                                                   */
 /* ------------------------------------------------------------------ */
 struct or_sim {
   int nx, ny, nux, nuy, bc, n;
-  double h, b, T, tau_s, tau_u, nu, A, omega, dt_u, xc, yc, margin;
+  double h, b, T, nu, dt_u, xc, yc, margin;
+  real tau_s, tau_u, A, omega;  /* the differentiable parameters */
   double kc, beta;
   double body_b; /* width of the meshed-out lamina slot (0: no body) */
   int64_t k;
-  double *fA, *fB;          /* lattice [9][ny][nx] */
+  real *fA, *fB;            /* lattice [9][ny][nx] */
   uint8_t *disc;            /* lattice discretization flags of this step */
   or_mesh *m;
-  double *fu, *fu2;         /* grid populations [9][nnode] */
-  double *star_eq, *star_neq;
-  double *uwx, *uwy;
-  double *hist;
+  real *fu, *fu2;           /* grid populations [9][nnode] */
+  real *star_eq, *star_neq;
+  real *uwx, *uwy;
+  real *hist;
   int64_t hist_cap, hist_n;
   int64_t nt1, nt2, nt3;
 };
 
 /* prescribed motion y(t) = A sin(omega t) (Sec. Problem statement), t = k */
-static double motion_y(const or_sim *s, int64_t k) { return s->A * sin(s->omega * (double)k); }
+static real motion_y(const or_sim *s, int64_t k) { return s->A * RSIN(s->omega * (double)k); }
 
 /* Fictitious curve (reading: the paper draws it inside the grid boundary but
  * gives no construction): the axis-aligned rectangle of the grid's node
@@ -745,7 +798,7 @@ static int lattice_status(const rect_t *r, int x, int y) {
 
 int32_t or_lattice_status(const or_sim *s, int64_t k, int32_t x, int32_t y) {
   if (!s->m) return 0;
-  rect_t r = rect_at(s, motion_y(s, k));
+  rect_t r = rect_at(s, RE(motion_y(s, k)));
   return lattice_status(&r, x, y);
 }
 
@@ -796,7 +849,7 @@ int or_create(const or_config *c, or_sim **out) {
    * performance) */
   if (c->n_sub > 0) s->n = c->n_sub;
   else {
-    int n = (int)ceil(1.0 / s->tau_u - 1e-9);
+    int n = (int)ceil(1.0 / RE(s->tau_u) - 1e-9);
     s->n = n < 2 ? 2 : n;
   }
   s->dt_u = 1.0 / (double)s->n;
@@ -805,10 +858,10 @@ int or_create(const or_config *c, or_sim **out) {
   s->margin = 2.0;
   s->hist_cap = c->max_steps;
   const size_t L = (size_t)9 * c->nx * c->ny;
-  s->fA = malloc(L * sizeof(double));
-  s->fB = malloc(L * sizeof(double));
+  s->fA = malloc(L * sizeof(real));
+  s->fB = malloc(L * sizeof(real));
   s->disc = malloc((size_t)c->nx * c->ny);
-  s->hist = xcalloc((size_t)2 * (c->max_steps > 0 ? c->max_steps : 1), sizeof(double));
+  s->hist = xcalloc((size_t)2 * (c->max_steps > 0 ? c->max_steps : 1), sizeof(real));
   if (!s->fA || !s->fB || !s->disc || !s->hist) {
     free_sim(s);
     return OR_E_NOMEM;
@@ -823,7 +876,7 @@ int or_create(const or_config *c, or_sim **out) {
     if (body && fabs(c->thickness - s->h) > 1e-12 * s->h) { free_sim(s); return OR_E_ARG; }
     if (c->n_sub < 0) { free_sim(s); return OR_E_ARG; }
     /* explicit stability of the grid scheme, Delta t_u < 2 tau_u */
-    if (!(s->dt_u < 2.0 * s->tau_u)) { free_sim(s); return OR_E_ARG; }
+    if (!(s->dt_u < 2.0 * RE(s->tau_u))) { free_sim(s); return OR_E_ARG; }
     s->m = or_mesh_lamina(c->nux, c->nuy, s->h, s->body_b);
     if (!s->m) { free_sim(s); return OR_E_ARG; }
     s->T = s->m->T;
@@ -834,7 +887,7 @@ int or_create(const or_config *c, or_sim **out) {
     const double hy = 0.5 * (double)(c->nuy - 1) * s->h;
     if (s->xc - hx < 1.0 || s->xc + hxr > (double)c->nx - 2.0) { free_sim(s); return OR_E_ARG; }
     if (c->bc == OR_BC_PERIODIC_X_WALLS_Y &&
-        (s->yc - hy - fabs(s->A) < 1.0 || s->yc + hy + fabs(s->A) > (double)c->ny - 2.0)) {
+        (s->yc - hy - fabs(RE(s->A)) < 1.0 || s->yc + hy + fabs(RE(s->A)) > (double)c->ny - 2.0)) {
       free_sim(s);
       return OR_E_ARG;
     }
@@ -843,14 +896,14 @@ int or_create(const or_config *c, or_sim **out) {
       free_sim(s);
       return OR_E_ARG;
     }
-    if (!(fabs(s->A * s->omega) < 1.0)) { free_sim(s); return OR_E_ARG; }
+    if (!(fabs(RE(s->A * s->omega)) < 1.0)) { free_sim(s); return OR_E_ARG; }
     const int N = s->m->nnode;
-    s->fu = malloc((size_t)9 * N * sizeof(double));
-    s->fu2 = malloc((size_t)9 * N * sizeof(double));
-    s->star_eq = xcalloc((size_t)9 * N, sizeof(double));
-    s->star_neq = xcalloc((size_t)9 * N, sizeof(double));
-    s->uwx = xcalloc(N, sizeof(double));
-    s->uwy = xcalloc(N, sizeof(double));
+    s->fu = malloc((size_t)9 * N * sizeof(real));
+    s->fu2 = malloc((size_t)9 * N * sizeof(real));
+    s->star_eq = xcalloc((size_t)9 * N, sizeof(real));
+    s->star_neq = xcalloc((size_t)9 * N, sizeof(real));
+    s->uwx = xcalloc(N, sizeof(real));
+    s->uwy = xcalloc(N, sizeof(real));
     if (!s->fu || !s->fu2 || !s->star_eq || !s->star_neq || !s->uwx || !s->uwy) {
       free_sim(s);
       return OR_E_NOMEM;
@@ -864,7 +917,7 @@ int or_create(const or_config *c, or_sim **out) {
 
 /* lattice populations arriving at node (x,y) at t_{k+1}: pulled from the
  * post-collision buffer of t_k (the pre-collision f of Eq.(LBE)'s left side) */
-static void lattice_pre(const or_sim *s, int x, int y, double f[9]) {
+static void lattice_pre(const or_sim *s, int x, int y, real f[9]) {
   pull_node(s->fA, s->nx, s->ny, s->bc, wrap(x, s->nx), s->bc == OR_BC_PERIODIC ? wrap(y, s->ny) : y,
             0.0, 0.0, f);
 }
@@ -873,22 +926,22 @@ static void lattice_pre(const or_sim *s, int x, int y, double f[9]) {
  * enclosing (X,Y) (Sec. Refill procedure, type 1): density, velocity and the
  * non-equilibrium part f^neq,s = f - f^eq(rho, u) of the pre-collision
  * populations at t_{k+1}. */
-static void lattice_bilinear(const or_sim *s, double X, double Y, double *rho,
-                             double *ux, double *uy, double fneq[9]) {
-  const double fx = floor(X), fy = floor(Y);
+static void lattice_bilinear(const or_sim *s, double X, real Y, real *rho,
+                             real *ux, real *uy, real fneq[9]) {
+  const double fx = floor(X), fy = floor(RE(Y));
   const int x0 = (int)fx, y0 = (int)fy;
-  const double a = X - fx, bb = Y - fy;
-  const double wgt[4] = {(1.0 - a) * (1.0 - bb), a * (1.0 - bb), (1.0 - a) * bb, a * bb};
+  const real a = X - fx, bb = Y - fy;
+  const real wgt[4] = {(1.0 - a) * (1.0 - bb), a * (1.0 - bb), (1.0 - a) * bb, a * bb};
   const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
   *rho = 0.0;
   *ux = 0.0;
   *uy = 0.0;
   for (int i = 0; i < 9; ++i) fneq[i] = 0.0;
   for (int d = 0; d < 4; ++d) {
-    double f[9], e[9], r, vx, vy;
+    real f[9], e[9], r, vx, vy;
     lattice_pre(s, x0 + dx[d], y0 + dy[d], f);
     moments(f, &r, &vx, &vy);
-    or_feq(r, vx, vy, e);
+    feq_r(r, vx, vy, e);
     *rho += wgt[d] * r;
     *ux += wgt[d] * vx;
     *uy += wgt[d] * vy;
@@ -899,47 +952,53 @@ static void lattice_bilinear(const or_sim *s, double X, double Y, double *rho,
 /* Eq.(postcollision2_s) at lattice node (x,y) from the grid at offset y_k:
  * barycentric interpolation of rho, u and f^neq,u over the enclosing triangle,
  * f^eq rebuilt from the interpolated moments. */
-static int lattice_from_grid(or_sim *s, int x, int y, double yk) {
+static int lattice_from_grid(or_sim *s, int x, int y, real yk) {
   const or_mesh *m = s->m;
   const int N = m->nnode;
-  double lam[3];
-  const int t = or_mesh_locate(m, (double)x - s->xc, (double)y - (s->yc + yk), lam);
+  double lam0[3];
+  const real px = (double)x - s->xc, py = (double)y - (s->yc + yk);
+  const int t = or_mesh_locate(m, RE(px), RE(py), lam0);
   if (t < 0) return OR_E_STATE;
-  double rho = 0.0, ux = 0.0, uy = 0.0, fneq[9] = {0};
+  real lam[3];
+  bary_r(&m->txy[6 * t], px, py, lam);
+  real rho = 0.0, ux = 0.0, uy = 0.0, fneq[9] = {0};
   for (int a = 0; a < 3; ++a) {
     const int p = m->tri[3 * t + a];
-    double f[9], e[9], r, vx, vy;
+    real f[9], e[9], r, vx, vy;
     for (int i = 0; i < 9; ++i) f[i] = s->fu[(size_t)i * N + p];
     moments(f, &r, &vx, &vy);
-    or_feq(r, vx, vy, e);
+    feq_r(r, vx, vy, e);
     rho += lam[a] * r;
     ux += lam[a] * vx;
     uy += lam[a] * vy;
     for (int i = 0; i < 9; ++i) fneq[i] += lam[a] * (f[i] - e[i]);
   }
-  double e[9];
-  or_feq(rho, ux, uy, e);
-  const double g = 2.0 * (s->tau_s - 1.0) / (2.0 * s->tau_s - 1.0);
+  real e[9];
+  feq_r(rho, ux, uy, e);
+  const real g = 2.0 * (s->tau_s - 1.0) / (2.0 * s->tau_s - 1.0);
   for (int i = 0; i < 9; ++i) s->fA[lidx(s->nx, s->ny, i, x, y)] = e[i] + g * fneq[i];
   return OR_OK;
 }
 
 /* Refill after the move from y_k to y_k1 (Sec. Refill procedure). */
-static void refill(or_sim *s, double yk, double yk1) {
+static void refill(or_sim *s, real yk, real yk1) {
   const or_mesh *m = s->m;
   const int N = m->nnode;
-  const double kneq = 1.0 - 1.0 / (2.0 * s->tau_s); /* Eq.(continuity_stresses) */
+  const real kneq = 1.0 - 1.0 / (2.0 * s->tau_s); /* Eq.(continuity_stresses) */
   for (int p = 0; p < N; ++p) {
-    double out[9];
+    real out[9];
     if (m->type[p] == OR_NODE_WALL) {
       /* wall nodes keep density and populations; their velocity is imposed
        * during the sub-steps */
       for (int i = 0; i < 9; ++i) out[i] = s->fu[(size_t)i * N + p];
     } else {
       const double X = s->xc + m->x[p];
-      const double Ynew = (s->yc + yk1) + m->y[p];
-      double lam[3];
-      const int t = or_mesh_locate(m, X - s->xc, Ynew - (s->yc + yk), lam);
+      const real Ynew = (s->yc + yk1) + m->y[p];
+      const real py = Ynew - (s->yc + yk);
+      double lam0[3];
+      real lam[3];
+      const int t = or_mesh_locate(m, X - s->xc, RE(py), lam0);
+      if (t >= 0) bary_r(&m->txy[6 * t], X - s->xc, py, lam);
       if (t >= 0) {
         /* type 3: barycentric interpolation in the old triangle */
         for (int i = 0; i < 9; ++i) {
@@ -947,22 +1006,22 @@ static void refill(or_sim *s, double yk, double yk1) {
           for (int a = 0; a < 3; ++a) out[i] += lam[a] * s->fu[(size_t)i * N + m->tri[3 * t + a]];
         }
         s->nt3++;
-      } else if (s->body_b > 0.0 && fabs(X - s->xc) < 0.5 * s->body_b && fabs(Ynew - (s->yc + yk)) < 0.5 * s->T) {
+      } else if (s->body_b > 0.0 && fabs(X - s->xc) < 0.5 * s->body_b && fabs(RE(py)) < 0.5 * s->T) {
         /* type 2: inside the old body, keep the previous values */
         for (int i = 0; i < 9; ++i) out[i] = s->fu[(size_t)i * N + p];
         s->nt2++;
       } else {
         /* type 1: outside the old grid, from the lattice */
-        double rho, ux, uy, fneq[9], e[9];
+        real rho, ux, uy, fneq[9], e[9];
         lattice_bilinear(s, X, Ynew, &rho, &ux, &uy, fneq);
-        or_feq(rho, ux, uy, e);
+        feq_r(rho, ux, uy, e);
         for (int i = 0; i < 9; ++i) out[i] = e[i] + kneq * fneq[i];
         s->nt1++;
       }
     }
     for (int i = 0; i < 9; ++i) s->fu2[(size_t)i * N + p] = out[i];
   }
-  double *tmp = s->fu;
+  real *tmp = s->fu;
   s->fu = s->fu2;
   s->fu2 = tmp;
 }
@@ -974,14 +1033,14 @@ int or_step(or_sim *s, int64_t nsteps) {
   for (int64_t it = 0; it < nsteps; ++it) {
     const int64_t k = s->k;
     if (!s->m) {
-      or_lattice_step(s->fA, s->fB, nx, ny, s->bc, s->tau_s, 0.0, 0.0, NULL);
+      lattice_step_r(s->fA, s->fB, nx, ny, s->bc, s->tau_s, 0.0, 0.0, NULL);
     } else {
       const or_mesh *m = s->m;
       const int N = m->nnode;
-      const double yk = motion_y(s, k);
-      const double yprev = (k > 0) ? motion_y(s, k - 1) : yk;
-      const double yk1 = motion_y(s, k + 1);
-      const rect_t R = rect_at(s, yk), Rp = rect_at(s, yprev);
+      const real yk = motion_y(s, k);
+      const real yprev = (k > 0) ? motion_y(s, k - 1) : yk;
+      const real yk1 = motion_y(s, k + 1);
+      const rect_t R = rect_at(s, RE(yk)), Rp = rect_at(s, RE(yprev));
       /* 1. lattice interpolation nodes, plus nodes the moving fictitious line
        *    has just uncovered (Sec. Refill procedure, last paragraphs), get
        *    Eq.(postcollision2_s) from the grid at y_k */
@@ -993,15 +1052,15 @@ int or_step(or_sim *s, int64_t nsteps) {
             if (lattice_from_grid(s, x, y, yk) != OR_OK) return OR_E_STATE;
         }
       /* 2. Eq.(LBE) on the discretization nodes */
-      or_lattice_step(s->fA, s->fB, nx, ny, s->bc, s->tau_s, 0.0, 0.0, s->disc);
+      lattice_step_r(s->fA, s->fB, nx, ny, s->bc, s->tau_s, 0.0, 0.0, s->disc);
       /* 3. structured-derived values at the grid's outer nodes, from the
        *    lattice at t_{k+1} (pre-collision), held over the n sub-steps */
-      const double kneq = 1.0 - 1.0 / (2.0 * s->tau_s);
+      const real kneq = 1.0 - 1.0 / (2.0 * s->tau_s);
       for (int p = 0; p < N; ++p) {
         if (m->type[p] != OR_NODE_INTERFACE) continue;
-        double rho, ux, uy, fneq[9], e[9];
+        real rho, ux, uy, fneq[9], e[9];
         lattice_bilinear(s, s->xc + m->x[p], (s->yc + yk) + m->y[p], &rho, &ux, &uy, fneq);
-        or_feq(rho, ux, uy, e);
+        feq_r(rho, ux, uy, e);
         for (int i = 0; i < 9; ++i) {
           s->star_eq[(size_t)i * N + p] = e[i];
           s->star_neq[(size_t)i * N + p] = kneq * fneq[i];
@@ -1012,27 +1071,27 @@ int or_step(or_sim *s, int64_t nsteps) {
        *    each sub-step */
       for (int sub = 0; sub < s->n; ++sub) {
         const double t = (double)k + (double)(sub + 1) / (double)s->n;
-        const double uw = s->A * s->omega * cos(s->omega * t);
+        const real uw = s->A * s->omega * RCOS(s->omega * t);
         for (int p = 0; p < N; ++p) {
           s->uwx[p] = 0.0;
           s->uwy[p] = uw;
         }
-        or_fv_substep(m, s->fu, s->star_eq, s->star_neq, s->fu2, s->tau_u, s->dt_u, s->uwx, s->uwy);
-        double *tmp = s->fu;
+        fv_substep_r(m, s->fu, s->star_eq, s->star_neq, s->fu2, s->tau_u, s->dt_u, s->uwx, s->uwy);
+        real *tmp = s->fu;
         s->fu = s->fu2;
         s->fu2 = tmp;
       }
       /* 5. force on the lamina at t_{k+1} */
-      double F[2];
-      or_mesh_force(m, s->fu, F);
+      real F[2];
+      mesh_force_r(m, s->fu, F);
       s->hist[2 * s->hist_n] = F[0];
       s->hist[2 * s->hist_n + 1] = F[1];
       s->hist_n++;
-      if (!isfinite(F[0]) || !isfinite(F[1])) return OR_E_UNSTABLE;
+      if (!isfinite(RE(F[0])) || !isfinite(RE(F[1]))) return OR_E_UNSTABLE;
       /* 6. move the grid to y_{k+1} and refill it */
       refill(s, yk, yk1);
     }
-    double *tmp = s->fA;
+    real *tmp = s->fA;
     s->fA = s->fB;
     s->fB = tmp;
     s->k = k + 1;
@@ -1041,7 +1100,7 @@ int or_step(or_sim *s, int64_t nsteps) {
   const size_t L = (size_t)nx * ny;
   for (size_t p = 0; p < L; ++p) {
     double r = 0.0;
-    for (int i = 0; i < 9; ++i) r += s->fA[(size_t)i * L + p];
+    for (int i = 0; i < 9; ++i) r += RE(s->fA[(size_t)i * L + p]);
     if (!(r > 0.0) || !isfinite(r)) return OR_E_UNSTABLE;
   }
   return OR_OK;
@@ -1050,20 +1109,21 @@ int or_step(or_sim *s, int64_t nsteps) {
 int or_info_get(const or_sim *s, or_info *o) {
   if (!s || !o) return OR_E_ARG;
   memset(o, 0, sizeof(*o));
+  const double A = RE(s->A), omega = RE(s->omega);
   o->nu = s->nu;
-  o->tau_u = s->tau_u;
+  o->tau_u = RE(s->tau_u);
   o->dt_u = s->dt_u;
-  o->A = s->A;
-  o->omega = s->omega;
-  o->period = (s->omega > 0.0) ? 2.0 * M_PI / s->omega : 0.0;
-  o->u_max = s->A * s->omega;
+  o->A = A;
+  o->omega = omega;
+  o->period = (omega > 0.0) ? 2.0 * M_PI / omega : 0.0;
+  o->u_max = A * omega;
   o->mach = o->u_max * sqrt(3.0);
   o->reynolds = (s->nu > 0.0) ? o->u_max * s->b / s->nu : 0.0;
-  o->eps = (s->b > 0.0) ? s->A / s->b : 0.0;
+  o->eps = (s->b > 0.0) ? A / s->b : 0.0;
   o->beta_limit_ok = (o->eps > 0.0) ? (s->beta < 2.6 * pow(o->eps, -1.6)) : 1;
   o->n_sub = s->n;
   o->step = s->k;
-  o->y = motion_y(s, s->k);
+  o->y = RE(motion_y(s, s->k));
   o->n_type1 = s->nt1;
   o->n_type2 = s->nt2;
   o->n_type3 = s->nt3;
@@ -1081,6 +1141,7 @@ int or_info_get(const or_sim *s, or_info *o) {
 
 const or_mesh *or_sim_mesh(const or_sim *s) { return s->m; }
 
+#ifndef OR_COMPLEX_STEP
 int or_get_lattice(const or_sim *s, double *out) {
   memcpy(out, s->fA, (size_t)9 * s->nx * s->ny * sizeof(double));
   return OR_OK;
@@ -1104,6 +1165,48 @@ int64_t or_history(const or_sim *s, double *out, int64_t cap) {
   if (out) memcpy(out, s->hist, (size_t)2 * n * sizeof(double));
   return s->hist_n;
 }
+#else
+/* complex-step build: add i h to A, omega and tau_s (tau_u follows) */
+int or_cs_perturb(or_sim *s, double hA, double homega, double htau) {
+  s->A += I * hA;
+  s->omega += I * homega;
+  s->tau_s += I * htau;
+  s->tau_u = s->tau_s - 0.5;
+  return OR_OK;
+}
+static void split(const real *src, size_t n, double *re, double *im) {
+  for (size_t i = 0; i < n; ++i) {
+    if (re) re[i] = creal(src[i]);
+    if (im) im[i] = cimag(src[i]);
+  }
+}
+static void join(real *dst, size_t n, const double *re, const double *im) {
+  for (size_t i = 0; i < n; ++i) dst[i] = re[i] + I * (im ? im[i] : 0.0);
+}
+int or_cs_get_lattice(const or_sim *s, double *re, double *im) {
+  split(s->fA, (size_t)9 * s->nx * s->ny, re, im);
+  return OR_OK;
+}
+int or_cs_set_lattice(or_sim *s, const double *re, const double *im) {
+  join(s->fA, (size_t)9 * s->nx * s->ny, re, im);
+  return OR_OK;
+}
+int or_cs_get_mesh(const or_sim *s, double *re, double *im) {
+  if (!s->m) return OR_E_STATE;
+  split(s->fu, (size_t)9 * s->m->nnode, re, im);
+  return OR_OK;
+}
+int or_cs_set_mesh(or_sim *s, const double *re, const double *im) {
+  if (!s->m) return OR_E_STATE;
+  join(s->fu, (size_t)9 * s->m->nnode, re, im);
+  return OR_OK;
+}
+int64_t or_cs_history(const or_sim *s, double *re, double *im, int64_t cap) {
+  const int64_t n = s->hist_n < cap ? s->hist_n : cap;
+  split(s->hist, (size_t)2 * n, re, im);
+  return s->hist_n;
+}
+#endif
 
 /* Single-harmonic least-squares fit F(t) = F0 sin(omega t + phi) with omega
  * given, over the window [t0, t1) periods (the paper discards the first cycle

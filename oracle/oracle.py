@@ -1,7 +1,14 @@
-"""ctypes binding of the FP64 CPU oracle (``liboracle.so``).
+"""ctypes binding of the FP64 CPU oracle (``liboracle.so``) and of its
+complex-step build (``liboracle_cs.so``).
 
 TEST INFRASTRUCTURE: only the test suite, the smoke check and the CPU-baseline
 leg of the benchmark import this module. It never backs the GPU library.
+
+The complex-step build runs the same source with every quantity that depends
+continuously on (A, omega, tau) held as a complex number. Adding i*h to one
+parameter gives Im(output)/h = d(output)/d(parameter) with no cancellation
+error (Squire and Trapp, SIAM Review 40, 1998), while every discrete decision
+(cells, triangles, refill types, node status) follows the real part.
 """
 from __future__ import annotations
 
@@ -14,6 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hlbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_CS = os.path.join(_HERE, "liboracle_cs.so")
 
 BC_PERIODIC_X_WALLS_Y = 0
 BC_PERIODIC = 1
@@ -22,12 +30,14 @@ NODE_INTERIOR, NODE_INTERFACE, NODE_WALL = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no contraction of a*b+c)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-fPIC",
-               "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle with gcc (FP64, no contraction of a*b+c), once as
+    plain doubles and once as the complex-step variant."""
+    for out, extra in ((_LIB, []), (_LIB_CS, ["-DOR_COMPLEX_STEP"])):
+        if force or not os.path.exists(out):
+            cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-fPIC", *extra,
+                   "-shared", "-o", out + ".tmp", _SRC, "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(out + ".tmp", out)
     return _LIB
 
 
@@ -98,6 +108,31 @@ def lib():
                                    C.c_double, C.c_double, _D]
         _lib = L
     return _lib
+
+
+_lib_cs = None
+
+
+def lib_cs():
+    global _lib_cs
+    if _lib_cs is None:
+        if not os.path.exists(_LIB_CS):
+            build()
+        L = C.CDLL(_LIB_CS)
+        vp = C.c_void_p
+        L.or_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.or_destroy.argtypes = [vp]
+        L.or_step.argtypes = [vp, C.c_int64]
+        L.or_info_get.argtypes = [vp, C.POINTER(Info)]
+        L.or_cs_perturb.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+        for f in ("or_cs_get_lattice", "or_cs_get_mesh"):
+            getattr(L, f).argtypes = [vp, _D, _D]
+        for f in ("or_cs_set_lattice", "or_cs_set_mesh"):
+            getattr(L, f).argtypes = [vp, _D, vp]
+        L.or_cs_history.argtypes = [vp, _D, _D, C.c_int64]
+        L.or_cs_history.restype = C.c_int64
+        _lib_cs = L
+    return _lib_cs
 
 
 def d2q9():
@@ -264,6 +299,76 @@ class Sim:
     def status(self, k):
         return np.array([[lib().or_lattice_status(self.ptr, k, x, y) for x in range(self.nx)]
                          for y in range(self.ny)], dtype=np.int32)
+
+
+class SimCS:
+    """The complex-step build of :class:`Sim`.
+
+    ``SimCS(h_A, h_omega, h_tau, **cfg)`` adds i*h to A, omega and tau_s
+    (tau_u = tau_s - 1/2 follows). After ``step``, ``history()`` returns the
+    real force history and its imaginary part; divided by h the latter is
+    the exact derivative of the history along that direction."""
+
+    def __init__(self, h_A=0.0, h_omega=0.0, h_tau=0.0, *, nx, ny, nux=0, nuy=0, h_u=1.0,
+                 b=0.0, thickness=1.0, tau=0.8, kc=0.0, beta=0.0, n_sub=0,
+                 bc=BC_PERIODIC_X_WALLS_Y, flags=0, max_steps=0):
+        self.cfg = Config(nx, ny, nux, nuy, h_u, b, thickness, tau, kc, beta, n_sub, bc, flags,
+                          max_steps)
+        h = C.c_void_p()
+        rc = lib_cs().or_create(C.byref(self.cfg), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"or_create rejected the configuration (code {rc})")
+        self.ptr = h
+        self.nx, self.ny = nx, ny
+        lib_cs().or_cs_perturb(self.ptr, h_A, h_omega, h_tau)
+        i = Info()
+        lib_cs().or_info_get(self.ptr, C.byref(i))
+        self.nnode = i.nnode
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib_cs is not None:
+            _lib_cs.or_destroy(self.ptr)
+            self.ptr = None
+
+    def step(self, n=1):
+        rc = lib_cs().or_step(self.ptr, n)
+        if rc != 0:
+            raise RuntimeError(f"or_step failed (code {rc})")
+
+    def info(self) -> Info:
+        i = Info()
+        lib_cs().or_info_get(self.ptr, C.byref(i))
+        return i
+
+    def history(self):
+        z = np.zeros(2)
+        n = lib_cs().or_cs_history(self.ptr, z, z, 0)
+        re = np.zeros((max(n, 1), 2))
+        im = np.zeros((max(n, 1), 2))
+        lib_cs().or_cs_history(self.ptr, re, im, n)
+        return re[:n], im[:n]
+
+    def lattice(self):
+        re = np.zeros((9, self.ny, self.nx))
+        im = np.zeros_like(re)
+        lib_cs().or_cs_get_lattice(self.ptr, re, im)
+        return re, im
+
+    def grid(self):
+        re = np.zeros((9, self.nnode))
+        im = np.zeros_like(re)
+        lib_cs().or_cs_get_mesh(self.ptr, re, im)
+        return re, im
+
+    def set_lattice(self, re, im=None):
+        im = None if im is None else np.ascontiguousarray(im, dtype=np.float64)
+        lib_cs().or_cs_set_lattice(self.ptr, np.ascontiguousarray(re, dtype=np.float64),
+                                   None if im is None else im.ctypes.data_as(C.c_void_p))
+
+    def set_grid(self, re, im=None):
+        im = None if im is None else np.ascontiguousarray(im, dtype=np.float64)
+        lib_cs().or_cs_set_mesh(self.ptr, np.ascontiguousarray(re, dtype=np.float64),
+                                None if im is None else im.ctypes.data_as(C.c_void_p))
 
 
 def fit_theta(hist, omega, A, b, t0=1.0, t1=4.0):

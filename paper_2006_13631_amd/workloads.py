@@ -33,6 +33,11 @@ PRESETS = {
     # small cases for tests: several tiles, ragged sizes, odd grid width
     "tiny_ragged": dict(nx=77, ny=45, nux=33, nuy=16, h_u=1.0, b=12.0, thickness=1.0,
                         tau=0.7, kc=0.6, beta=40.0, steps=60),
+    # tiny_ragged with beta 41: its period (52.7 steps) is not an even
+    # integer, so no step has y_{k+1} = y_k exactly and the force history is
+    # smooth in A, omega and tau at this point (derivative tests)
+    "tiny_adjoint": dict(nx=77, ny=45, nux=33, nuy=16, h_u=1.0, b=12.0, thickness=1.0,
+                         tau=0.7, kc=0.6, beta=41.0, n_sub=5, steps=60),
     # grid spacing 0.2 below the largest per-step displacement (0.225): some
     # nodes land inside the old lamina
     "tiny_fine_grid": dict(nx=48, ny=48, nux=90, nuy=44, h_u=0.2, b=8.0, thickness=0.2,
