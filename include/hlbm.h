@@ -62,6 +62,10 @@ extern "C" {
 #define HLBM_STATE_LATTICE 0 /* double [9][ny][nx]: post-collision f at t_k     */
 #define HLBM_STATE_GRID 1    /* double [9][nux*nuy]: grid f at t_k, node
                                 index j*nux + i                              */
+#define HLBM_STATE_ADJ_LATTICE 2 /* get only, double [9][ny][nx]: dJ/d(lattice
+                                    at t_0) from the last hlbm_adjoint       */
+#define HLBM_STATE_ADJ_GRID 3    /* get only, double [9][nux*nuy]: dJ/d(grid at
+                                    t_0) from the last hlbm_adjoint          */
 
 /* Problem and discretisation (Sec. Problem statement, Sec. HLBM).
  * Grid node (i, j) sits at x = nx/2 + (i - nux/2) h_u (integer division) and
@@ -130,15 +134,33 @@ int hlbm_step(hlbm_t *h, int64_t nsteps);
 int hlbm_force(hlbm_t *h, int32_t case_id, double *hist_xy, int64_t cap,
                int64_t *n_out, double win_t0, double win_t1, double theta[2]);
 
-/* Discrete adjoint: gradient of J = sum_k dJ_dFy[k] F_y(t_{k+1}) with respect
- * to (A, omega, tau). Not available in this build: returns
- * HLBM_E_UNSUPPORTED. */
-int hlbm_adjoint(hlbm_t *h, int32_t case_id, const double *dJ_dFy, int64_t n,
+/* Discrete adjoint of the whole run (reverse mode over the steps taken so
+ * far, every step of the method differentiated as the forward computed it).
+ * For J = sum_k (dJ_dF[2k] F_x(t_{k+1}) + dJ_dF[2k+1] F_y(t_{k+1})), n = the
+ * number of steps taken since creation, grad_A_omega_tau receives dJ/dA,
+ * dJ/domega and dJ/dtau with A, omega and tau = tau_s independent (tau_u =
+ * tau_s - 1/2 follows tau_s; kc and beta are only the way the configuration
+ * names A and omega). The discrete decisions of the run (node status, donor
+ * cells, triangles, refill types, n) are held fixed, so the result is the
+ * derivative of the piecewise-smooth J on the run's piece.
+ * Uses the checkpoints taken every ckpt_every steps during hlbm_step and
+ * recomputes each window of steps into a device tape of
+ * (ckpt_every + 1) lattice and ckpt_every (n + 1) + 1 grid arrays before
+ * running it backwards; the adjoint of the initial state is kept for
+ * hlbm_get_state (HLBM_STATE_ADJ_*). Blocks until done; the forward state
+ * is left as it was. Errors: HLBM_E_STATE (no grid, ckpt_every = 0, or the
+ * state was replaced by hlbm_set_state after step 0), HLBM_E_ARG (n is not
+ * the number of steps taken, or NULL pointers), HLBM_E_UNSUPPORTED (the
+ * lattice donors of the grid wrap across a periodic y boundary),
+ * HLBM_E_NOMEM (the tape does not fit: use a smaller ckpt_every). */
+int hlbm_adjoint(hlbm_t *h, int32_t case_id, const double *dJ_dF, int64_t n,
                  double grad_A_omega_tau[3]);
 
 /* Copy a state array to or from host memory, converted to or from FP64.
- * which = HLBM_STATE_LATTICE or HLBM_STATE_GRID; bytes must equal the
- * array size in doubles times 8 (HLBM_E_ARG otherwise). */
+ * which = HLBM_STATE_* (the adjoint states can only be read, after
+ * hlbm_adjoint; HLBM_E_STATE before); bytes must equal the array size in
+ * doubles times 8 (HLBM_E_ARG otherwise). Setting a state after step 0
+ * invalidates the checkpoints of a case created with ckpt_every > 0. */
 int hlbm_get_state(hlbm_t *h, int32_t case_id, int32_t which, void *host_buf,
                    size_t bytes);
 int hlbm_set_state(hlbm_t *h, int32_t case_id, int32_t which,
@@ -164,6 +186,8 @@ int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
 #define HLBM_K_REFILL 3         /* move + refill                               */
 #define HLBM_K_FORCE 4          /* wall force                                  */
 #define HLBM_K_STEP 5           /* whole structured step                       */
+#define HLBM_K_ADJ_STREAM_COLLIDE 6 /* adjoint of the lattice stream-collide   */
+#define HLBM_K_ADJOINT 7        /* whole hlbm_adjoint call (count = steps)     */
 int hlbm_timing(hlbm_t *h, int32_t on);
 int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count);
 

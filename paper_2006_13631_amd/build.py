@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhlbm.so")
-SOURCES = ["api.hip", "kernels.hip", "grid_host.cpp"]
+SOURCES = ["api.hip", "kernels.hip", "adjoint.hip", "grid_host.cpp"]
 ARCH = os.environ.get("HLBM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -31,7 +31,7 @@ def build(verbose: bool = False) -> str:
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        contract = "-ffp-contract=fast" if src == "kernels.hip" else "-ffp-contract=off"
+        contract = "-ffp-contract=fast" if src in ("kernels.hip", "adjoint.hip") else "-ffp-contract=off"
         cmd = [hipcc(), "-x", "hip", f"--offload-arch={ARCH}",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                *common, contract, "-c", os.path.join(CSRC, src), "-o", obj]

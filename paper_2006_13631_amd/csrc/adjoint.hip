@@ -1,0 +1,729 @@
+// gfx950 discrete-adjoint kernels of the moving-grid hybrid step.
+//
+// Reverse of one structured step k (forward order: grid-to-lattice writes,
+// lattice stream-collide, interface donors, n grid sub-steps, refill, force):
+//
+//   star        recompute f*, f^neq* (forward arithmetic) and keep the
+//               interpolated moments of every interface node
+//   refill      per grid node: adjoint of its own type-1 refill (Z1), then a
+//               gather of every refill that read it (type 3 barycentric in
+//               its column, type 2 and wall copies) plus the force adjoint
+//   wall        per wall node and sub-step: adjoint of the imposed lamina
+//               velocity (the forward output is recomputed from the tape)
+//   substep     per grid node: transposed finite-volume stencil, gathered
+//               from the 3 x 3 neighbours through LDS; structured-derived
+//               adjoints accumulate at interface nodes; the last sub-step
+//               turns them into the donor adjoint (Z2)
+//   donor gather per lattice node near the grid: the bilinear weights of every
+//               interface donor and type-1 refill that read it, folded with
+//               its own moments into E = dJ/d f_pre
+//   stream_collide  per lattice node: BGK adjoint plus E, pushed to the
+//               addresses the forward pull read (a permutation: no atomics)
+//   from_grid   per lattice node set from the grid: adjoint of
+//               Eq.(postcollision2_s) (Z3); the node's tape value is dead
+//   from_grid gather  per grid node: barycentric weights of every such
+//               lattice node whose triangle holds it
+//
+// Every scatter of the forward is a gather here, so each output element is
+// written by one thread in a fixed order and the gradient is bitwise
+// reproducible. Parameter derivatives (A and omega through the grid
+// position y_k = A sin(omega k) and the lamina velocity u_w = A omega
+// cos(omega t), tau through 1/tau_s, the Eq.(postcollision2_s) factor, the
+// Eq.(continuity_stresses) factor and dt_u / tau_u) are summed per block into
+// fixed slots and reduced once at the end.
+#include <hip/hip_ext.h>
+
+#include "adjoint.h"
+
+namespace mghlbm {
+namespace {
+
+using namespace dev;
+
+constexpr int NT = 256;
+
+inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+// Adds this block's (a, b, c) to slot[0..2]; all NT threads must call it.
+__device__ __forceinline__ void block_accum3(double a, double b, double c, double *slot) {
+  __shared__ double red[3][NT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  if (lane == 0) {
+    red[0][wave] = a;
+    red[1][wave] = b;
+    red[2][wave] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      s0 += red[0][w];
+      s1 += red[1][w];
+      s2 += red[2][w];
+    }
+    slot[0] += s0;
+    slot[1] += s1;
+    slot[2] += s2;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ double dot12(const R z[12], R rho, R ux, R uy, const R fneq[9]) {
+  double s = (double)z[0] * (double)rho + (double)z[1] * (double)ux + (double)z[2] * (double)uy;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) s += (double)z[3 + q] * (double)fneq[q];
+  return s;
+}
+
+// x coordinate of grid column i and y coordinate of grid row j at base yb
+__device__ __forceinline__ double grid_x(const GridGeom &g, int i) { return g.xc + (double)(i - g.nux / 2) * g.h; }
+__device__ __forceinline__ double grid_y(const GridGeom &g, double yb, int j) {
+  return yb + ((double)j - 0.5 * (double)(g.nuy - 1)) * g.h;
+}
+
+// ---- star: f*, f^neq* of step k and the interpolated moments ----------------
+template <class T, class R>
+__global__ __launch_bounds__(NT) void k_adj_star(AdjCtx<T, R> c) {
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = gt >> 2, d = gt & 3;
+  const bool valid = t < c.n_iface;
+  R acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = R(0);
+  int p = 0;
+  if (valid) {
+    p = c.iface[t];
+    const int i = p % c.gg.nux, j = p / c.gg.nux;
+    donor_corner<T, R>(c.Lt, c.nx, c.ny, c.periodic_y, grid_x(c.gg, i), grid_y(c.gg, c.P.ybase, j), d, acc);
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    acc[k] += __shfl_xor(acc[k], 1, 64);
+    acc[k] += __shfl_xor(acc[k], 2, 64);
+  }
+  if (!valid) return;
+  R e[9];
+  equilibrium<R>(acc[0], acc[1], acc[2], e);
+  const size_t N = (size_t)c.nnode;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    if ((q & 3) != d) continue;
+    const R n = c.k_neq * acc[3 + q];
+    c.star_n[q * N + p] = n;
+    c.star_f[q * N + p] = e[q] + n;
+  }
+  if (d < 3) c.M2[d * N + p] = acc[d];
+}
+
+// ---- refill and force adjoint -------------------------------------------------
+template <class T, class R>
+__global__ __launch_bounds__(NT) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
+  const int q = blockIdx.x * NT + threadIdx.x;
+  const size_t N = (size_t)c.nnode;
+  const GridGeom &g = c.gg;
+  double pA = 0.0, pW = 0.0, pT = 0.0;
+  if (q < c.nnode) {
+    const int i = q % g.nux, j = q / g.nux;
+    const int tq = c.tab[c.cls[q]].type;
+    // (a) this node's own type-1 refill: adjoint of the interpolated moments
+    R z[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) z[k] = R(0);
+    unsigned char flag = tq == NODE_INTERFACE ? 2 : 0;
+    int kind = 0;
+    if (tq != NODE_WALL) kind = refill_cell(g, c.P.ybase, c.P.ybase1, i, j).kind;
+    R ub[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) ub[s] = c.Ub_next[s * N + q];
+    if (kind == 1) {
+      R rho, ux, uy, fneq[9];
+      lattice_bilinear<T, R>(c.Lt, c.nx, c.ny, c.periodic_y, grid_x(g, i), grid_y(g, c.P.ybase1, j), rho, ux, uy,
+                             fneq);
+      equilibrium_vjp<R>(rho, ux, uy, ub, z[0], z[1], z[2]);
+      double sn = 0.0;
+#pragma unroll
+      for (int s = 0; s < 9; ++s) {
+        z[3 + s] = c.k_neq * ub[s];
+        sn += (double)ub[s] * (double)fneq[s];
+      }
+      pT += sn / (2.0 * c.tau * c.tau);  // d(1 - 1/(2 tau))/d tau
+      flag |= 1;
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c.Z1[k * N + q] = z[k];
+    c.zf[q] = flag;
+    // (b) every refill that read this node of the old grid
+    R acc[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) acc[s] = (tq == NODE_WALL || kind == 2) ? ub[s] : R(0);
+    R un[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) un[s] = c.Un[s * N + q];
+    double dsum = 0.0;
+    const double delta = (c.P.ybase1 - c.P.ybase) / g.h;
+    const int jc = j - (int)floor(delta);
+    for (int jj = max(jc - 4, 0); jj <= min(jc + 3, g.nuy - 1); ++jj) {
+      for (int ii = max(i - 1, 0); ii <= min(i + 1, g.nux - 1); ++ii) {
+        const int p = jj * g.nux + ii;
+        if (c.tab[c.cls[p]].type == NODE_WALL) continue;
+        const RefillCell r = refill_cell(g, c.P.ybase, c.P.ybase1, ii, jj);
+        if (r.kind != 3) continue;
+        int node[3];
+        double lam[3], dl[3];
+        cell_triangle(r.ci, r.cj, g.nux, r.a, r.b, node, lam, dl);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (node[a] != q) continue;
+          const R l = R(lam[a]);
+          double d = 0.0;
+#pragma unroll
+          for (int s = 0; s < 9; ++s) {
+            const R u = c.Ub_next[s * N + p];
+            acc[s] += l * u;
+            d += (double)u * (double)un[s];
+          }
+          dsum += dl[a] * d;
+        }
+      }
+    }
+    // the new node's old-grid coordinate t = (y_{k+1} - y_k)/h + const
+    pA += dsum * (c.dyA1 - c.dyA) / g.h;
+    pW += dsum * (c.dyW1 - c.dyW) / g.h;
+    // (c) force on the lamina at t_{k+1}
+    if (tq == NODE_WALL) {
+      const double nx = c.wall_nrm[q], ny = c.wall_nrm[N + q];
+      R rho, ux, uy;
+      moments<R>(un, rho, ux, uy);
+      R gb[9], fb[9];
+#pragma unroll
+      for (int s = 0; s < 9; ++s) {
+        const double cx = CXd[s], cy = CYd[s];
+        gb[s] = R(-(cx * cx * c.wfx * nx + cx * cy * (c.wfx * ny + c.wfy * nx) + cy * cy * c.wfy * ny));
+      }
+      const R rb = R(-(c.wfx * nx + c.wfy * ny) / 3.0);
+      node_chain<R>(rho, ux, uy, rb, R(0), R(0), gb, fb);
+#pragma unroll
+      for (int s = 0; s < 9; ++s) acc[s] += fb[s];
+    }
+#pragma unroll
+    for (int s = 0; s < 9; ++s) c.Ubn[s * N + q] = acc[s];
+  }
+  block_accum3(pA, pW, pT, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+}
+
+// ---- one sub-step backwards -----------------------------------------------------
+// Wall nodes: the forward output o of Eq.(ulbe) is mapped to
+// W(o) = o + f^eq(rho(o), (0, u_w)) - f^eq(rho(o), u(o)); ub <- W'(o)^T ub.
+template <class T, class R>
+__global__ __launch_bounds__(NT) void k_adj_wall(AdjCtx<T, R> c, const R *__restrict__ Um, R *__restrict__ ub,
+                                                 R uw, double duwA, double duwW, int slot0) {
+  const int t = blockIdx.x * NT + threadIdx.x;
+  const size_t N = (size_t)c.nnode;
+  const GridGeom &g = c.gg;
+  double pA = 0.0, pW = 0.0;
+  if (t < c.n_wall) {
+    const int p = c.wall_nodes[t];
+    const int i = p % g.nux, j = p / g.nux;
+    const GridClass<R> &cl = c.tab[c.cls[p]];
+    R ax[9], ay[9], sc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ax[q] = ay[q] = sc[q] = R(0);
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const int ii = i + s % 3 - 1, jj = j + s / 3 - 1;
+      if (ii < 0 || jj < 0 || ii >= g.nux || jj >= g.nuy) continue;
+      const size_t pq = (size_t)jj * g.nux + ii;
+      R f[9], e[9], r, vx, vy;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) f[q] = Um[q * N + pq];
+      moments<R>(f, r, vx, vy);
+      equilibrium<R>(r, vx, vy, e);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        ax[q] += cl.Gx[s] * f[q];
+        ay[q] += cl.Gy[s] * f[q];
+        sc[q] += cl.C[s] * (f[q] - e[q]);
+      }
+    }
+    R o[9], u[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      o[q] = Um[q * N + p] + c.dt * (R(CXd[q]) * ax[q] + R(CYd[q]) * ay[q]) - c.dt_tau * sc[q];
+      u[q] = ub[q * N + p];
+    }
+    R rho, ux, uy;
+    moments<R>(o, rho, ux, uy);
+    R ar, axx, ayy, arw, axw, ayw;
+    equilibrium_vjp<R>(rho, ux, uy, u, ar, axx, ayy);
+    equilibrium_vjp<R>(rho, R(0), uw, u, arw, axw, ayw);
+    const R inv = R(1) / rho;
+    const R bx = -axx * inv, by = -ayy * inv;
+    const R base = arw - ar - bx * ux - by * uy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ub[q * N + p] = u[q] + base + bx * R(CXd[q]) + by * R(CYd[q]);
+    pA += (double)ayw * duwA;
+    pW += (double)ayw * duwW;
+  }
+  block_accum3(pA, pW, 0.0, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+}
+
+// Transposed Eq.(ulbe)/Eq.(postcollision2_u) stencil. A workgroup owns a
+// 64 x 4 tile and stages the adjoint of the whole 66 x 6 region (tile plus
+// one-node halo) with the neighbours' stencil classes in LDS. Node q gathers
+// from each neighbour p the coefficient p applied to q's slot (the mirror of
+// q's slot for p).
+constexpr int ATX = 64, ATY = 4, ARX = ATX + 2, ARY = ATY + 2, ARN = ARX * ARY;
+
+template <class T, class R>
+__global__ __launch_bounds__(NT) void k_adj_substep(AdjCtx<T, R> c, const R *__restrict__ Um,
+                                                    const R *__restrict__ ub, R *__restrict__ ub_out, int first,
+                                                    int last, int slot0) {
+  __shared__ R sob[ARN * 9];
+  __shared__ int scls[ARN];
+  const GridGeom &g = c.gg;
+  const size_t N = (size_t)c.nnode;
+  const int tiles_x = (g.nux + ATX - 1) / ATX;
+  const int x0 = (blockIdx.x % tiles_x) * ATX - 1, y0 = (blockIdx.x / tiles_x) * ATY - 1;
+  for (int idx = threadIdx.x; idx < ARN; idx += NT) {
+    const int gi = x0 + idx % ARX, gj = y0 + idx / ARX;
+    const bool in = gi >= 0 && gj >= 0 && gi < g.nux && gj < g.nuy;
+    const size_t p = in ? (size_t)gj * g.nux + gi : 0;
+    scls[idx] = in ? c.cls[p] : -1;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sob[idx * 9 + q] = in ? ub[q * N + p] : R(0);
+  }
+  __syncthreads();
+  double pT = 0.0;
+  const int tx = threadIdx.x % ATX, ty = threadIdx.x / ATX;
+  const int gi = x0 + 1 + tx, gj = y0 + 1 + ty;
+  if (gi < g.nux && gj < g.nuy) {
+    const int ci = (ty + 1) * ARX + (tx + 1);
+    const size_t q = (size_t)gj * g.nux + gi;
+    const int tq = c.tab[scls[ci]].type;
+    R accF[9], accN[9], sf[9], sn[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) accF[s] = accN[s] = sf[s] = sn[s] = R(0);
+#pragma unroll
+    for (int sp = 0; sp < NSLOT; ++sp) {
+      const int ri = ci + (sp / 3 - 1) * ARX + (sp % 3 - 1);
+      const int cp = scls[ri];
+      if (cp < 0) continue;
+      const GridClass<R> &cl = c.tab[cp];
+      const int s = NSLOT - 1 - sp;  // p's slot that holds q
+      const R gx = cl.Gx[s], gy = cl.Gy[s], cc = cl.C[s];
+      const bool star = cl.type == NODE_INTERFACE && tq == NODE_INTERFACE;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const R o = sob[ri * 9 + k];
+        const R st = c.dt * (R(CXd[k]) * gx + R(CYd[k]) * gy) * o;
+        const R ct = -c.dt_tau * cc * o;
+        if (star) {
+          sf[k] += st;
+          sn[k] += ct;
+        } else {
+          accF[k] += st;
+          accN[k] += ct;
+        }
+      }
+    }
+    // the node's own value: its f, or f* at an interface node
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if (tq == NODE_INTERFACE) sf[k] += sob[ci * 9 + k];
+      else accF[k] += sob[ci * 9 + k];
+    }
+    R f[9], e[9], rho, ux, uy, fb[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) f[k] = Um[k * N + q];
+    moments<R>(f, rho, ux, uy);
+    equilibrium<R>(rho, ux, uy, e);
+    node_chain<R>(rho, ux, uy, R(0), R(0), R(0), accN, fb);
+    double dn = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      ub_out[k * N + q] = accF[k] + fb[k];
+      dn += (double)accN[k] * (double)(f[k] - e[k]);
+    }
+    if (tq == NODE_INTERFACE) {
+      double ds = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const R stn = c.star_n[k * N + q];
+        ds += (double)sn[k] * (double)stn;
+        if (!first) {
+          sf[k] += c.sbf[k * N + q];
+          sn[k] += c.sbn[k * N + q];
+        }
+        c.sbf[k * N + q] = sf[k];
+        c.sbn[k * N + q] = sn[k];
+      }
+      dn += ds;
+      if (last) {
+        // donor adjoint: f* = f^eq(rho, u) + k f^neq, f^neq* = k f^neq
+        R z[12], tot[9];
+        double dk = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          tot[k] = sf[k] + sn[k];
+          dk += (double)tot[k] * (double)c.star_n[k * N + q];
+        }
+        equilibrium_vjp<R>(c.M2[q], c.M2[N + q], c.M2[2 * N + q], sf, z[0], z[1], z[2]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) z[3 + k] = c.k_neq * tot[k];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) c.Z2[k * N + q] = z[k];
+        // d f^neq*/d tau = (d k/d tau) f^neq = (d k/d tau)/k f^neq*
+        pT += dk * (1.0 / (2.0 * c.tau * c.tau)) / (double)c.k_neq;
+      }
+    }
+    // d(dt_u/tau_u)/d tau = -dt_u/tau_u^2: the collision adjoints carry -dt_u/tau_u
+    pT += dn * (-1.0 / c.tau_u);
+  }
+  block_accum3(0.0, 0.0, pT, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+}
+
+// ---- donor gather: dJ/d f_pre at lattice nodes read by bilinear donors ------------
+template <class T, class R>
+__global__ __launch_bounds__(NT) void k_adj_donor_gather(AdjCtx<T, R> c, int slot0) {
+  const int x = c.ex0 + blockIdx.x * NT + threadIdx.x;
+  const int y = c.ey0 + blockIdx.y;
+  const GridGeom &g = c.gg;
+  const size_t N = (size_t)c.nnode;
+  double pA = 0.0, pW = 0.0;
+  if (x < c.ex0 + c.ew) {
+    R Eo[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Eo[k] = R(0);
+    const bool inside = x >= c.P.ix0 && x <= c.P.ix1 && y >= c.P.iy0 && y <= c.P.iy1;
+    if (!inside) {  // donors are discretization nodes
+      R zs[12], zA[12], zW[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) zs[k] = zA[k] = zW[k] = R(0);
+      bool any = false;
+      const int ilo = max(0, (int)floor(((double)x - 1.0 - g.xc) / g.h) + g.nux / 2 - 1);
+      const int ihi = min(g.nux - 1, (int)ceil(((double)x + 1.0 - g.xc) / g.h) + g.nux / 2 + 1);
+      for (int i = ilo; i <= ihi; ++i) {
+        const double X = grid_x(g, i);
+        const int fx = (int)floor(X);
+        if (fx != x && fx + 1 != x) continue;
+        for (int pos = 0; pos < 2; ++pos) {  // 0: interface donors at y_k, 1: type-1 refill at y_{k+1}
+          const double yb = pos ? c.P.ybase1 : c.P.ybase;
+          const double dyA = pos ? c.dyA1 : c.dyA, dyW = pos ? c.dyW1 : c.dyW;
+          const double j0 = ((double)y - yb) / g.h + 0.5 * (double)(g.nuy - 1);
+          const int jlo = max(0, (int)floor(j0 - 1.0 / g.h) - 1), jhi = min(g.nuy - 1, (int)ceil(j0 + 1.0 / g.h) + 1);
+          const unsigned char need = pos ? 1 : 2;
+          const R *Z = pos ? c.Z1 : c.Z2;
+          for (int j = jlo; j <= jhi; ++j) {
+            const int p = j * g.nux + i;
+            if (!(c.zf[p] & need)) continue;
+            const double Y = grid_y(g, yb, j);
+            const int fy = (int)floor(Y);
+            if (fy != y && fy + 1 != y) continue;
+            int xd, yd;
+            double w, dw;
+            bilinear_corner(X, Y, (x - fx) + 2 * (y - fy), xd, yd, w, dw);
+            const R wr = R(w), wa = R(dw * dyA), ww = R(dw * dyW);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+              const R z = Z[k * N + p];
+              zs[k] += wr * z;
+              zA[k] += wa * z;
+              zW[k] += ww * z;
+            }
+            any = true;
+          }
+        }
+      }
+      if (any) {
+        R f[9], e[9], rho, ux, uy, fneq[9];
+        pull<T, R>(c.Lt, c.nx, c.ny, c.periodic_y, x, y, f);
+        moments<R>(f, rho, ux, uy);
+        equilibrium<R>(rho, ux, uy, e);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) fneq[k] = f[k] - e[k];
+        node_chain<R>(rho, ux, uy, zs[0], zs[1], zs[2], zs + 3, Eo);
+        pA += dot12<R>(zA, rho, ux, uy, fneq);
+        pW += dot12<R>(zW, rho, ux, uy, fneq);
+      }
+    }
+    const size_t plane = (size_t)c.ew * c.eh, at = (size_t)(y - c.ey0) * c.ew + (x - c.ex0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c.E[k * plane + at] = Eo[k];
+  }
+  block_accum3(pA, pW, 0.0, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// ---- lattice stream-collide adjoint ---------------------------------------------
+// Forward at a discretization node: f_post = f - (f - f^eq(f))/tau, f pulled
+// from L'_k. Backward: v = (1 - 1/tau) l + (1/tau) (d f^eq/d f)^T l + E, then
+// v_q is stored at the address the forward pull read f_q from. Inside the
+// fictitious rectangle the forward copied the value, and the copy is never
+// read again (such nodes are overwritten from the grid before any
+// discretization node reads them), so zeros are pushed.
+template <class T, class R>
+__global__ __launch_bounds__(NT) void k_adj_stream_collide(AdjCtx<T, R> c, int slot0) {
+  const int x = blockIdx.x * NT + threadIdx.x;
+  const int y = blockIdx.y;
+  double pT = 0.0;
+  if (x < c.nx) {
+    const size_t plane = (size_t)c.nx * c.ny, cc = (size_t)y * c.nx + x;
+    size_t idx[9];
+    pull_index(c.nx, c.ny, c.periodic_y, x, y, idx);
+    const bool inside = c.has_grid && x >= c.P.ix0 && x <= c.P.ix1 && y >= c.P.iy0 && y <= c.P.iy1;
+    R v[9];
+    if (inside) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) v[q] = R(0);
+    } else {
+      R f[9], e[9], l[9], rho, ux, uy;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) f[q] = Stor<T>::ld(c.Lt, idx[q], q);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) l[q] = c.Lb_next[q * plane + cc];
+      moments<R>(f, rho, ux, uy);
+      equilibrium<R>(rho, ux, uy, e);
+      R ar, ax, ay;
+      equilibrium_vjp<R>(rho, ux, uy, l, ar, ax, ay);
+      const R inv = R(1) / rho;
+      const R bx = ax * inv, by = ay * inv, base = ar - bx * ux - by * uy;
+      double dt = 0.0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        v[q] = (R(1) - c.inv_tau) * l[q] + c.inv_tau * (base + bx * R(CXd[q]) + by * R(CYd[q]));
+        dt += (double)l[q] * (double)(f[q] - e[q]);
+      }
+      pT += dt / (c.tau * c.tau);
+      if (c.has_grid && x >= c.ex0 && x < c.ex0 + c.ew && y >= c.ey0 && y < c.ey0 + c.eh) {
+        const size_t eplane = (size_t)c.ew * c.eh, at = (size_t)(y - c.ey0) * c.ew + (x - c.ex0);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v[q] += c.E[q * eplane + at];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) c.Lb[idx[q]] = v[q];
+  }
+  block_accum3(0.0, 0.0, pT, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// ---- grid-to-lattice adjoint, lattice side ---------------------------------------
+// Forward: L'(x) = f^eq(rho, u) + g f^neq with barycentric (rho, u, f^neq) from
+// the grid at t_k, g = 2 (tau - 1)/(2 tau - 1). Z3 holds the adjoint of the
+// interpolated (rho, u, f^neq); the node's incoming adjoint is consumed.
+template <class T, class R>
+__global__ __launch_bounds__(NT) void k_adj_from_grid(AdjCtx<T, R> c, int slot0) {
+  const int x = c.k2_x0 + blockIdx.x * NT + threadIdx.x;
+  const int ybot = min(c.P.iy0, c.P.piy0);
+  const int y = ybot + (int)blockIdx.y;
+  double pT = 0.0;
+  if (x < c.k2_x0 + c.k2_w) {
+    R z[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) z[k] = R(0);
+    if (y <= max(c.P.iy1, c.P.piy1) && from_grid_target(c.P, x, y)) {
+      int ci, cj, node[3];
+      double a, b, lam[3], dl[3];
+      lattice_node_cell(c.gg, c.P.ybase, x, y, ci, cj, a, b);
+      cell_triangle(ci, cj, c.gg.nux, a, b, node, lam, dl);
+      R rho, ux, uy, fneq[9];
+      grid_barycentric<R>(c.U0, c.nnode, node, lam, rho, ux, uy, fneq);
+      const size_t plane = (size_t)c.nx * c.ny, cc = (size_t)y * c.nx + x;
+      R lb[9];
+      double dg = 0.0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        lb[q] = c.Lb[q * plane + cc];
+        c.Lb[q * plane + cc] = R(0);
+        z[3 + q] = c.g_post * lb[q];
+        dg += (double)lb[q] * (double)fneq[q];
+      }
+      equilibrium_vjp<R>(rho, ux, uy, lb, z[0], z[1], z[2]);
+      const double tm = 2.0 * c.tau - 1.0;
+      pT += dg * 2.0 / (tm * tm);  // d g / d tau
+    }
+    const size_t zp = (size_t)c.k2_w * c.k2_h, at = (size_t)blockIdx.y * c.k2_w + (x - c.k2_x0);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c.Z3[k * zp + at] = z[k];
+  }
+  block_accum3(0.0, 0.0, pT, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// ---- grid-to-lattice adjoint, grid side -------------------------------------------
+template <class T, class R>
+__global__ __launch_bounds__(NT) void k_adj_from_grid_gather(AdjCtx<T, R> c, R *__restrict__ ub, int slot0) {
+  const int q = blockIdx.x * NT + threadIdx.x;
+  const GridGeom &g = c.gg;
+  const size_t N = (size_t)c.nnode;
+  double pA = 0.0, pW = 0.0;
+  if (q < c.nnode) {
+    const int i = q % g.nux, j = q / g.nux;
+    const double X0 = grid_x(g, 0), Y0 = grid_y(g, c.P.ybase, 0);
+    const int ybot = min(c.P.iy0, c.P.piy0), ytop = min(max(c.P.iy1, c.P.piy1), ybot + c.k2_h - 1);
+    const int xlo = max((int)floor(X0 + (double)(i - 1) * g.h) - 1, c.k2_x0);
+    const int xhi = min((int)ceil(X0 + (double)(i + 1) * g.h) + 1, c.k2_x0 + c.k2_w - 1);
+    const int ylo = max((int)floor(Y0 + (double)(j - 1) * g.h) - 1, ybot);
+    const int yhi = min((int)ceil(Y0 + (double)(j + 1) * g.h) + 1, ytop);
+    R zs[12], zd[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) zs[k] = zd[k] = R(0);
+    bool any = false;
+    const size_t zp = (size_t)c.k2_w * c.k2_h;
+    for (int yl = ylo; yl <= yhi; ++yl) {
+      for (int xl = xlo; xl <= xhi; ++xl) {
+        if (!from_grid_target(c.P, xl, yl)) continue;
+        int ci, cj, node[3];
+        double a, b, lam[3], dl[3];
+        lattice_node_cell(g, c.P.ybase, xl, yl, ci, cj, a, b);
+        cell_triangle(ci, cj, g.nux, a, b, node, lam, dl);
+        const size_t at = (size_t)(yl - ybot) * c.k2_w + (xl - c.k2_x0);
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+          if (node[n] != q) continue;
+          const R l = R(lam[n]), d = R(dl[n]);
+#pragma unroll
+          for (int k = 0; k < 12; ++k) {
+            const R z = c.Z3[k * zp + at];
+            zs[k] += l * z;
+            zd[k] += d * z;
+          }
+          any = true;
+        }
+      }
+    }
+    if (any) {
+      R f[9], e[9], rho, ux, uy, fneq[9], fb[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) f[k] = c.U0[k * N + q];
+      moments<R>(f, rho, ux, uy);
+      equilibrium<R>(rho, ux, uy, e);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) fneq[k] = f[k] - e[k];
+      node_chain<R>(rho, ux, uy, zs[0], zs[1], zs[2], zs + 3, fb);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) ub[k * N + q] += fb[k];
+      // the lattice node's grid coordinate t = (y - y_k)/h + const
+      const double dsum = dot12<R>(zd, rho, ux, uy, fneq);
+      pA += dsum * (-c.dyA / g.h);
+      pW += dsum * (-c.dyW / g.h);
+    }
+  }
+  block_accum3(pA, pW, 0.0, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+}
+
+__global__ __launch_bounds__(NT) void k_adj_reduce(const double *__restrict__ part, int nslots, double *out) {
+  __shared__ double red[3][NT];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nslots; i += NT)
+    for (int k = 0; k < 3; ++k) s[k] += part[3 * (size_t)i + k];
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) {
+      double t = 0.0;
+      for (int i = 0; i < NT; ++i) t += red[k][i];
+      out[k] = t;
+    }
+  }
+}
+
+__global__ void k_set_counter(int64_t *dk, int64_t k) { *dk = k; }
+
+}  // namespace
+
+template <class T, class R>
+void AdjKernels<T, R>::star(const AdjCtx<T, R> &c, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_star<T, R>), dim3(blocks((size_t)4 * c.n_iface, NT)), dim3(NT), 0, s, c);
+}
+
+template <class T, class R>
+int AdjKernels<T, R>::refill_slots(const AdjCtx<T, R> &c) {
+  return (int)blocks(c.nnode, NT);
+}
+template <class T, class R>
+void AdjKernels<T, R>::refill(const AdjCtx<T, R> &c, int slot0, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_refill<T, R>), dim3(refill_slots(c)), dim3(NT), 0, s, c, slot0);
+}
+
+template <class T, class R>
+int AdjKernels<T, R>::wall_slots(const AdjCtx<T, R> &c) {
+  return (int)blocks(c.n_wall > 0 ? c.n_wall : 1, NT);
+}
+template <class T, class R>
+void AdjKernels<T, R>::wall(const AdjCtx<T, R> &c, const R *Um, R *ub, R uw, double duwA, double duwW, int slot0,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_wall<T, R>), dim3(wall_slots(c)), dim3(NT), 0, s, c, Um, ub, uw, duwA, duwW, slot0);
+}
+
+template <class T, class R>
+int AdjKernels<T, R>::substep_slots(const AdjCtx<T, R> &c) {
+  return ((c.gg.nux + ATX - 1) / ATX) * ((c.gg.nuy + ATY - 1) / ATY);
+}
+template <class T, class R>
+void AdjKernels<T, R>::substep(const AdjCtx<T, R> &c, const R *Um, const R *ub, R *ub_out, int first, int last,
+                               int slot0, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_substep<T, R>), dim3(substep_slots(c)), dim3(NT), 0, s, c, Um, ub, ub_out, first, last,
+                     slot0);
+}
+
+template <class T, class R>
+int AdjKernels<T, R>::donor_gather_slots(const AdjCtx<T, R> &c) {
+  return (int)blocks(c.ew, NT) * c.eh;
+}
+template <class T, class R>
+void AdjKernels<T, R>::donor_gather(const AdjCtx<T, R> &c, int slot0, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_donor_gather<T, R>), dim3(blocks(c.ew, NT), c.eh), dim3(NT), 0, s, c, slot0);
+}
+
+template <class T, class R>
+int AdjKernels<T, R>::stream_collide_slots(const AdjCtx<T, R> &c) {
+  return (int)blocks(c.nx, NT) * c.ny;
+}
+template <class T, class R>
+void AdjKernels<T, R>::stream_collide(const AdjCtx<T, R> &c, int slot0, hipStream_t s, hipEvent_t start,
+                                      hipEvent_t stop) {
+  if (start) {
+    hipExtLaunchKernelGGL((k_adj_stream_collide<T, R>), dim3(blocks(c.nx, NT), c.ny), dim3(NT), 0, s, start, stop, 0,
+                          c, slot0);
+  } else {
+    hipLaunchKernelGGL((k_adj_stream_collide<T, R>), dim3(blocks(c.nx, NT), c.ny), dim3(NT), 0, s, c, slot0);
+  }
+}
+
+template <class T, class R>
+int AdjKernels<T, R>::from_grid_slots(const AdjCtx<T, R> &c) {
+  return (int)blocks(c.k2_w, NT) * c.k2_h;
+}
+template <class T, class R>
+void AdjKernels<T, R>::from_grid(const AdjCtx<T, R> &c, int slot0, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_from_grid<T, R>), dim3(blocks(c.k2_w, NT), c.k2_h), dim3(NT), 0, s, c, slot0);
+}
+
+template <class T, class R>
+int AdjKernels<T, R>::from_grid_gather_slots(const AdjCtx<T, R> &c) {
+  return (int)blocks(c.nnode, NT);
+}
+template <class T, class R>
+void AdjKernels<T, R>::from_grid_gather(const AdjCtx<T, R> &c, R *ub, int slot0, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_from_grid_gather<T, R>), dim3(from_grid_gather_slots(c)), dim3(NT), 0, s, c, ub, slot0);
+}
+
+void adj_reduce(const double *part, int nslots, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(NT), 0, s, part, nslots, out);
+}
+
+void set_step_counter(int64_t *dk, int64_t k, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, s, dk, k);
+}
+
+template struct AdjKernels<double, double>;
+template struct AdjKernels<float, float>;
+template struct AdjKernels<__half, float>;
+
+}  // namespace mghlbm

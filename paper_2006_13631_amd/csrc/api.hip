@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "hlbm.h"
 #include "kernels.h"
 
@@ -67,6 +68,7 @@ class CaseBase {
   virtual int stencil(int kmax, int32_t *nbr, double *S, double *C) = 0;
   virtual int timing(int on) = 0;
   virtual int timing_get(int kernel, double *ms, int64_t *count) = 0;
+  virtual int adjoint(const double *dJ, int64_t n, double grad[3]) = 0;
   std::string err;
 };
 
@@ -145,7 +147,8 @@ class Case final : public CaseBase {
       HIPCHK(upload(&iface_, grid_.iface.data(), grid_.iface.size() * sizeof(int)));
       HIPCHK(upload(&wall_, grid_.wall.data(), grid_.wall.size() * sizeof(WallEdge)));
       // per-step scalars for k = 0 .. max_steps, wall velocity per sub-step
-      std::vector<StepParams> P(cap + 1);
+      std::vector<StepParams> &P = P_host_;
+      P.resize(cap + 1);
       for (int64_t k = 0; k <= cap; ++k) P[k] = params_at(k);
       HIPCHK(upload(&params_, P.data(), P.size() * sizeof(StepParams)));
       std::vector<R> uw((size_t)cap * d_.n);
@@ -162,6 +165,15 @@ class Case final : public CaseBase {
       for (int64_t k = 0; k <= cap; ++k)
         hmax = std::max(hmax, std::max(P[k].iy1, P[k].piy1) - std::min(P[k].iy0, P[k].piy0) + 1);
       k2_h_ = hmax;
+      if (c.ckpt_every > 0) {
+        // checkpoints of (lattice, grid) at every multiple of ckpt_every
+        ckW_ = c.ckpt_every;
+        nck_ = cap / ckW_ + 1;
+        ck_lat_bytes_ = 9 * plane_ * sizeof(T);
+        ck_grid_bytes_ = 9 * (size_t)N * sizeof(R);
+        HIPCHK(alloc(&ck_lat_, (size_t)nck_ * ck_lat_bytes_));
+        HIPCHK(alloc(&ck_grid_, (size_t)nck_ * ck_grid_bytes_));
+      }
     }
     Kernels<T, R>::fill_rest((T *)lat_[0], plane_, has_grid_ ? (R *)gbuf_[0] : nullptr, N, s_main_);
     Kernels<T, R>::fill_rest((T *)lat_[1], plane_, has_grid_ ? (R *)gbuf_[1] : nullptr, N, s_main_);
@@ -260,18 +272,30 @@ class Case final : public CaseBase {
     if (nsteps < 0) return fail(HLBM_E_ARG, "nsteps < 0");
     if (has_grid_ && k_ + nsteps > cfg_.max_steps) return fail(HLBM_E_ARG, "force history would exceed max_steps");
     int64_t done = 0;
-    if (!timing_ && use_graphs_) {
-      for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
+    while (done < nsteps) {
+      int64_t room = nsteps - done;
+      if (ckW_ > 0) {
+        if (k_ % ckW_ == 0 && k_ / ckW_ < nck_) {
+          const size_t w = (size_t)(k_ / ckW_);
+          HIPCHK(hipMemcpyAsync((char *)ck_lat_ + w * ck_lat_bytes_, lat_[0], ck_lat_bytes_,
+                                hipMemcpyDeviceToDevice, s_main_));
+          HIPCHK(hipMemcpyAsync((char *)ck_grid_ + w * ck_grid_bytes_, gbuf_[gcur_], ck_grid_bytes_,
+                                hipMemcpyDeviceToDevice, s_main_));
+        }
+        room = std::min<int64_t>(room, ckW_ - k_ % ckW_);
+      }
+      if (!timing_ && use_graphs_ && room >= kGraphSteps) {
         hipGraphExec_t ge = nullptr;
         HIPCHK(graph_for_current_layout(&ge));
         HIPCHK(hipGraphLaunch(ge, s_main_));
         // same buffer layout, kGraphSteps steps further
         k_ += kGraphSteps;
+        done += kGraphSteps;
+      } else {
+        HIPCHK(enqueue_step());
+        if (timing_) HIPCHK(harvest());
+        ++done;
       }
-    }
-    for (; done < nsteps; ++done) {
-      HIPCHK(enqueue_step());
-      if (timing_) HIPCHK(harvest());
     }
     HIPCHK(hipStreamSynchronize(s_main_));
     if (has_grid_) {
@@ -305,11 +329,25 @@ class Case final : public CaseBase {
       for (size_t i = 0; i < n; ++i) out[i] = (double)tmp[i];
       return HLBM_OK;
     }
+    if (which == HLBM_STATE_ADJ_LATTICE || which == HLBM_STATE_ADJ_GRID) {
+      if (!adj_done_) return fail(HLBM_E_STATE, "no adjoint has been run");
+      const bool lat = which == HLBM_STATE_ADJ_LATTICE;
+      const size_t n = lat ? 9 * plane_ : 9 * (size_t)grid_.nnode;
+      if (bytes != n * sizeof(double)) return fail(HLBM_E_ARG, "adjoint state size mismatch");
+      std::vector<R> tmp(n);
+      HIPCHK(hipMemcpy(tmp.data(), lat ? (void *)alat_[adj_lc_] : (void *)agrid_[adj_gc_], n * sizeof(R),
+                       hipMemcpyDeviceToHost));
+      double *out = (double *)buf;
+      for (size_t i = 0; i < n; ++i) out[i] = (double)tmp[i];
+      return HLBM_OK;
+    }
     return fail(HLBM_E_ARG, "unknown state selector");
   }
 
   int set_state(int which, const void *buf, size_t bytes) override {
     HIPCHK(hipStreamSynchronize(s_main_));
+    if (which != HLBM_STATE_LATTICE && which != HLBM_STATE_GRID) return fail(HLBM_E_ARG, "state cannot be set");
+    if (k_ > 0) ck_valid_ = false;
     if (which == HLBM_STATE_LATTICE) {
       if (bytes != 9 * plane_ * sizeof(double)) return fail(HLBM_E_ARG, "lattice state size mismatch");
       double *tmp = nullptr;
@@ -439,7 +477,7 @@ class Case final : public CaseBase {
     HIPCHK(hipStreamSynchronize(s_main_));
     if (on && !tev_[0])
       for (auto &e : tev_) HIPCHK(hipEventCreate(&e));
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 8; ++i) {
       tms_[i] = 0.0;
       tcount_[i] = 0;
     }
@@ -448,9 +486,53 @@ class Case final : public CaseBase {
   }
 
   int timing_get(int kernel, double *ms, int64_t *count) override {
-    if (kernel < 0 || kernel > 5) return fail(HLBM_E_ARG, "unknown kernel id");
+    if (kernel < 0 || kernel > 7) return fail(HLBM_E_ARG, "unknown kernel id");
     if (ms) *ms = tms_[kernel];
     if (count) *count = tcount_[kernel];
+    return HLBM_OK;
+  }
+
+  // Reverse mode over all steps taken: windows of ckpt_every steps from the
+  // last to the first; each window is recomputed from its checkpoint into the
+  // tape, then run backwards step by step.
+  int adjoint(const double *dJ, int64_t n, double grad[3]) override {
+    if (!dJ || !grad) return fail(HLBM_E_ARG, "null argument");
+    if (!has_grid_) return fail(HLBM_E_STATE, "case has no grid, so no force to differentiate");
+    if (ckW_ <= 0) return fail(HLBM_E_STATE, "case was created with ckpt_every = 0");
+    if (!ck_valid_) return fail(HLBM_E_STATE, "state was replaced after step 0; the checkpoints no longer hold");
+    if (n != k_ || n <= 0) return fail(HLBM_E_ARG, "the cotangent must cover every step taken (n = steps)");
+    HIPCHK(hipStreamSynchronize(s_main_));
+    int rc = adjoint_setup();
+    if (rc != HLBM_OK) return rc;
+    const size_t lat_r = 9 * plane_ * sizeof(R), grid_r = 9 * (size_t)grid_.nnode * sizeof(R);
+    HIPCHK(hipMemsetAsync(alat_[0], 0, lat_r, s_main_));
+    HIPCHK(hipMemsetAsync(agrid_[0], 0, grid_r, s_main_));
+    HIPCHK(hipMemsetAsync(part_, 0, (size_t)nslots_ * 3 * sizeof(double), s_main_));
+    if (timing_) HIPCHK(hipEventRecord(tev_adj_[2], s_main_));
+    int lc = 0, gc = 0;
+    const int64_t nwin = (n + ckW_ - 1) / ckW_;
+    for (int64_t w = nwin - 1; w >= 0; --w) {
+      const int64_t k0 = w * ckW_, k1 = std::min<int64_t>(n, k0 + ckW_);
+      HIPCHK(recompute(w, k0, k1));
+      for (int64_t k = k1 - 1; k >= k0; --k) HIPCHK(reverse_step(k, k0, dJ, lc, gc));
+    }
+    adj_reduce(part_, nslots_, grad_dev_, s_main_);
+    set_step_counter(dk_, k_, s_main_);
+    HIPCHK(hipGetLastError());
+    if (timing_) HIPCHK(hipEventRecord(tev_adj_[3], s_main_));
+    double g[3];
+    HIPCHK(hipMemcpyAsync(g, grad_dev_, sizeof(g), hipMemcpyDeviceToHost, s_main_));
+    HIPCHK(hipStreamSynchronize(s_main_));
+    if (timing_) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, tev_adj_[2], tev_adj_[3]));
+      tms_[HLBM_K_ADJOINT] += ms;
+      tcount_[HLBM_K_ADJOINT] += n;
+    }
+    for (int i = 0; i < 3; ++i) grad[i] = g[i];
+    adj_lc_ = lc;
+    adj_gc_ = gc;
+    adj_done_ = true;
     return HLBM_OK;
   }
 
@@ -477,6 +559,8 @@ class Case final : public CaseBase {
     for (void *p : owned_) (void)hipFree(p);
     owned_.clear();
     for (auto &e : tev_)
+      if (e) (void)hipEventDestroy(e);
+    for (auto &e : tev_adj_)
       if (e) (void)hipEventDestroy(e);
     if (ev_fork_) (void)hipEventDestroy(ev_fork_);
     if (ev_join_) (void)hipEventDestroy(ev_join_);
@@ -582,6 +666,207 @@ class Case final : public CaseBase {
     return hipSuccess;
   }
 
+
+  // ---- adjoint workspace ------------------------------------------------------
+  size_t tape_grid_elems() const { return 9 * (size_t)grid_.nnode; }
+  T *tape_lat(int64_t j) const { return (T *)tape_lat_ + (size_t)j * 9 * plane_; }
+  R *tape_grid(int64_t j, int m) const { return tape_grid_ + ((size_t)j * (d_.n + 1) + m) * tape_grid_elems(); }
+
+  // Allocates the tape and the adjoint buffers on first use and fills the
+  // step-independent part of the kernels' context.
+  int adjoint_setup() {
+    if (adj_ready_) return HLBM_OK;
+    const int N = grid_.nnode;
+    // lattice rows and columns that can be bilinear donors: the grid's
+    // bounding box over the whole motion, one node wider
+    const double hx0 = (double)(0 - cfg_.nux / 2) * h_, hx1 = (double)(cfg_.nux - 1 - cfg_.nux / 2) * h_;
+    const double hy = 0.5 * (double)(cfg_.nuy - 1) * h_;
+    double ymin = 1e300, ymax = -1e300;
+    for (const StepParams &P : P_host_) {
+      ymin = std::min(ymin, std::min(P.ybase, P.ybase1));
+      ymax = std::max(ymax, std::max(P.ybase, P.ybase1));
+    }
+    ex0_ = (int)std::floor(d_.xc + hx0);
+    ew_ = (int)std::floor(d_.xc + hx1) + 2 - ex0_;
+    ey0_ = (int)std::floor(ymin - hy);
+    eh_ = (int)std::floor(ymax + hy) + 2 - ey0_;
+    if (ex0_ < 0 || ex0_ + ew_ > cfg_.nx || ey0_ < 0 || ey0_ + eh_ > cfg_.ny)
+      return fail(HLBM_E_UNSUPPORTED, "lattice donors of the grid wrap across a periodic boundary");
+    const size_t tape_lat_bytes = (size_t)(ckW_ + 1) * 9 * plane_ * sizeof(T);
+    const size_t tape_grid_bytes = ((size_t)ckW_ * (d_.n + 1) + 1) * tape_grid_elems() * sizeof(R);
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    const size_t need = tape_lat_bytes + tape_grid_bytes + 2 * 9 * plane_ * sizeof(R) + ((size_t)64 << 20);
+    if (need > free_b) return fail(HLBM_E_NOMEM, "adjoint tape does not fit in device memory: use a smaller ckpt_every");
+    HIPCHK(alloc(&tape_lat_, tape_lat_bytes));
+    HIPCHK(alloc(&tape_grid_, tape_grid_bytes));
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(alloc(&alat_[i], 9 * plane_ * sizeof(R)));
+      HIPCHK(alloc(&agrid_[i], 9 * (size_t)N * sizeof(R)));
+    }
+    HIPCHK(alloc(&M2_, 3 * (size_t)N * sizeof(R)));
+    HIPCHK(alloc(&sbf_, 9 * (size_t)N * sizeof(R)));
+    HIPCHK(alloc(&sbn_, 9 * (size_t)N * sizeof(R)));
+    HIPCHK(alloc(&Z1_, 12 * (size_t)N * sizeof(R)));
+    HIPCHK(alloc(&Z2_, 12 * (size_t)N * sizeof(R)));
+    HIPCHK(alloc(&zf_, (size_t)N));
+    HIPCHK(alloc(&Z3_, 12 * (size_t)k2_w_ * k2_h_ * sizeof(R)));
+    HIPCHK(alloc(&E_, 9 * (size_t)ew_ * eh_ * sizeof(R)));
+    HIPCHK(alloc(&grad_dev_, 3 * sizeof(double)));
+    HIPCHK(alloc(&counts_scratch_, 2 * sizeof(unsigned long long)));
+    HIPCHK(hipMemset(Z2_, 0, 12 * (size_t)N * sizeof(R)));
+    // wall nodes and, per node, the sum over its wall edges of (len/2) n
+    std::vector<int> wn;
+    std::vector<double> nrm(2 * (size_t)N, 0.0);
+    for (int p = 0; p < N; ++p)
+      if (grid_.type[p] == NODE_WALL) wn.push_back(p);
+    for (const WallEdge &e : grid_.wall)
+      for (int s = 0; s < 2; ++s) {
+        const int p = s ? e.b : e.a;
+        nrm[p] += 0.5 * e.len * e.nx;
+        nrm[N + p] += 0.5 * e.len * e.ny;
+      }
+    HIPCHK(upload(&wall_nodes_, wn.data(), wn.size() * sizeof(int)));
+    HIPCHK(upload(&wall_nrm_, nrm.data(), nrm.size() * sizeof(double)));
+    AdjCtx<T, R> &c = actx_;
+    std::memset(&c, 0, sizeof(c));
+    c.nx = cfg_.nx;
+    c.ny = cfg_.ny;
+    c.periodic_y = cfg_.bc == HLBM_BC_PERIODIC;
+    c.has_grid = 1;
+    c.tau = cfg_.tau;
+    c.tau_u = d_.tau_u;
+    const CaseView<T, R> v = view();
+    c.inv_tau = v.inv_tau;
+    c.g_post = v.g_post;
+    c.k_neq = v.k_neq;
+    c.dt = v.dt_u;
+    c.dt_tau = v.dt_over_tau_u;
+    c.gg = dev::GridGeom{cfg_.nux, cfg_.nuy, h_, d_.xc, v.half_b, v.half_T, (int)body_};
+    c.nnode = N;
+    c.n_iface = (int)grid_.iface.size();
+    c.n_wall = (int)wn.size();
+    c.cls = cls_;
+    c.tab = tab_;
+    c.iface = iface_;
+    c.wall_nodes = wall_nodes_;
+    c.wall_nrm = wall_nrm_;
+    c.star_f = star_f_;
+    c.star_n = star_n_;
+    c.M2 = M2_;
+    c.sbf = sbf_;
+    c.sbn = sbn_;
+    c.Z1 = Z1_;
+    c.Z2 = Z2_;
+    c.zf = zf_;
+    c.Z3 = Z3_;
+    c.k2_x0 = k2_x0_;
+    c.k2_w = k2_w_;
+    c.k2_h = k2_h_;
+    c.E = E_;
+    c.ex0 = ex0_;
+    c.ey0 = ey0_;
+    c.ew = ew_;
+    c.eh = eh_;
+    using AK = AdjKernels<T, R>;
+    slot_refill_ = 0;
+    slot_wall_ = slot_refill_ + AK::refill_slots(c);
+    slot_sub_ = slot_wall_ + AK::wall_slots(c);
+    slot_eg_ = slot_sub_ + AK::substep_slots(c);
+    slot_sc_ = slot_eg_ + AK::donor_gather_slots(c);
+    slot_fg_ = slot_sc_ + AK::stream_collide_slots(c);
+    slot_fgg_ = slot_fg_ + AK::from_grid_slots(c);
+    nslots_ = slot_fgg_ + AK::from_grid_gather_slots(c);
+    HIPCHK(alloc(&part_, (size_t)nslots_ * 3 * sizeof(double)));
+    c.part = part_;
+    for (auto &e : tev_adj_)
+      if (!e) HIPCHK(hipEventCreate(&e));
+    adj_ready_ = true;
+    return HLBM_OK;
+  }
+
+  // Forward steps k0 .. k1-1 from checkpoint w, keeping every lattice after
+  // its grid-to-lattice writes and every grid state of every sub-step.
+  hipError_t recompute(int64_t w, int64_t k0, int64_t k1) {
+    hipError_t e = hipMemcpyAsync(tape_lat(0), (char *)ck_lat_ + (size_t)w * ck_lat_bytes_, ck_lat_bytes_,
+                                  hipMemcpyDeviceToDevice, s_main_);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(tape_grid(0, 0), (char *)ck_grid_ + (size_t)w * ck_grid_bytes_, ck_grid_bytes_,
+                       hipMemcpyDeviceToDevice, s_main_);
+    if (e != hipSuccess) return e;
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t j = k - k0;
+      set_step_counter(dk_, k, s_main_);
+      CaseView<T, R> v = view();
+      v.A = tape_lat(j);
+      v.B = tape_lat(j + 1);
+      v.counts = counts_scratch_;
+      Kernels<T, R>::lattice_from_grid(v, tape_grid(j, 0), s_main_);
+      Kernels<T, R>::stream_collide(v, s_main_);
+      Kernels<T, R>::interface_donors(v, s_main_);
+      for (int m = 0; m < d_.n; ++m) Kernels<T, R>::grid_substeps(v, tape_grid(j, m), tape_grid(j, m + 1), m, 1, s_main_);
+      Kernels<T, R>::refill(v, tape_grid(j, d_.n), tape_grid(j + 1, 0), s_main_);
+    }
+    return hipGetLastError();
+  }
+
+  // One structured step backwards: (alat_[lc], agrid_[gc]) hold the adjoints
+  // of the lattice and grid at t_{k+1} on entry and of those at t_k on exit.
+  hipError_t reverse_step(int64_t k, int64_t k0, const double *dJ, int &lc, int &gc) {
+    using AK = AdjKernels<T, R>;
+    const int64_t j = k - k0;
+    AdjCtx<T, R> c = actx_;
+    c.Lt = tape_lat(j);
+    c.Lb_next = alat_[lc];
+    c.Lb = alat_[1 - lc];
+    c.P = P_host_[k];
+    const double A = d_.A, om = d_.omega;
+    c.dyA = std::sin(om * (double)k);
+    c.dyW = A * (double)k * std::cos(om * (double)k);
+    c.dyA1 = std::sin(om * (double)(k + 1));
+    c.dyW1 = A * (double)(k + 1) * std::cos(om * (double)(k + 1));
+    c.wfx = dJ[2 * k];
+    c.wfy = dJ[2 * k + 1];
+    c.U0 = tape_grid(j, 0);
+    c.Un = tape_grid(j, d_.n);
+    c.Ub_next = agrid_[gc];
+    c.Ubn = agrid_[1 - gc];
+    AK::star(c, s_main_);
+    AK::refill(c, slot_refill_, s_main_);
+    int gin = 1 - gc;  // holds the adjoint of the grid after sub-step m+1
+    for (int m = d_.n - 1; m >= 0; --m) {
+      const double t = (double)k + (double)(m + 1) / (double)d_.n;
+      const R uw = (R)(A * om * std::cos(om * t));
+      const double duwA = om * std::cos(om * t);
+      const double duwW = A * std::cos(om * t) - A * om * t * std::sin(om * t);
+      AK::wall(c, tape_grid(j, m), agrid_[gin], uw, duwA, duwW, slot_wall_, s_main_);
+      AK::substep(c, tape_grid(j, m), agrid_[gin], agrid_[1 - gin], m == d_.n - 1, m == 0, slot_sub_, s_main_);
+      gin = 1 - gin;
+    }
+    AK::donor_gather(c, slot_eg_, s_main_);
+    if (timing_) {
+      AK::stream_collide(c, slot_sc_, s_main_, tev_adj_[0], tev_adj_[1]);
+    } else {
+      AK::stream_collide(c, slot_sc_, s_main_);
+    }
+    AK::from_grid(c, slot_fg_, s_main_);
+    AK::from_grid_gather(c, agrid_[gin], slot_fgg_, s_main_);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (timing_) {
+      e = hipEventSynchronize(tev_adj_[1]);
+      if (e != hipSuccess) return e;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, tev_adj_[0], tev_adj_[1]) == hipSuccess) {
+        tms_[HLBM_K_ADJ_STREAM_COLLIDE] += ms;
+        tcount_[HLBM_K_ADJ_STREAM_COLLIDE] += 1;
+      }
+    }
+    lc = 1 - lc;
+    gc = gin;
+    return hipSuccess;
+  }
+
   hlbm_config cfg_{};
   Derived d_{};
   double h_ = 1.0;
@@ -592,8 +877,8 @@ class Case final : public CaseBase {
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
   hipEvent_t tev_[9] = {};
   bool timing_ = false;
-  double tms_[6] = {};
-  int64_t tcount_[6] = {};
+  double tms_[8] = {};
+  int64_t tcount_[8] = {};
   std::vector<void *> owned_;
   void *lat_[2] = {nullptr, nullptr};
   void *gbuf_[2] = {nullptr, nullptr};
@@ -613,6 +898,29 @@ class Case final : public CaseBase {
   bool use_graphs_ = true;
   void *lat_base_ = nullptr;
   hipGraphExec_t gexec_[4] = {};
+  std::vector<StepParams> P_host_;
+  // checkpoints
+  int ckW_ = 0;
+  int64_t nck_ = 0;
+  size_t ck_lat_bytes_ = 0, ck_grid_bytes_ = 0;
+  void *ck_lat_ = nullptr, *ck_grid_ = nullptr;
+  bool ck_valid_ = true;
+  // adjoint
+  bool adj_ready_ = false, adj_done_ = false;
+  AdjCtx<T, R> actx_{};
+  void *tape_lat_ = nullptr;
+  R *tape_grid_ = nullptr;
+  R *alat_[2] = {nullptr, nullptr}, *agrid_[2] = {nullptr, nullptr};
+  int adj_lc_ = 0, adj_gc_ = 0;
+  R *M2_ = nullptr, *sbf_ = nullptr, *sbn_ = nullptr, *Z1_ = nullptr, *Z2_ = nullptr, *Z3_ = nullptr, *E_ = nullptr;
+  unsigned char *zf_ = nullptr;
+  int *wall_nodes_ = nullptr;
+  double *wall_nrm_ = nullptr, *part_ = nullptr, *grad_dev_ = nullptr;
+  unsigned long long *counts_scratch_ = nullptr;
+  int ex0_ = 0, ey0_ = 0, ew_ = 1, eh_ = 1;
+  int slot_refill_ = 0, slot_wall_ = 0, slot_sub_ = 0, slot_eg_ = 0, slot_sc_ = 0, slot_fg_ = 0, slot_fgg_ = 0,
+      nslots_ = 0;
+  hipEvent_t tev_adj_[4] = {};
 };
 
 // Configuration checks shared by all storage types (mirrors the geometric
@@ -622,7 +930,7 @@ int validate(const hlbm_config &c, std::string *err) {
   if (!(c.tau > 0.5)) { *err = "tau must exceed 1/2"; return HLBM_E_ARG; }
   if (c.bc != HLBM_BC_PERIODIC_X_WALLS_Y && c.bc != HLBM_BC_PERIODIC) { *err = "unknown bc"; return HLBM_E_ARG; }
   if (c.storage < HLBM_FP64 || c.storage > HLBM_FP16_DEV) { *err = "unknown storage"; return HLBM_E_ARG; }
-  if (c.max_steps < 0 || c.n_sub < 0 || c.reserved != 0) { *err = "invalid counts"; return HLBM_E_ARG; }
+  if (c.max_steps < 0 || c.n_sub < 0 || c.reserved != 0 || c.ckpt_every < 0) { *err = "invalid counts"; return HLBM_E_ARG; }
   if (c.flags & ~HLBM_FLAG_NO_BODY) { *err = "unknown flags"; return HLBM_E_ARG; }
   const bool has_grid = c.nux > 0 || c.nuy > 0;
   if (!has_grid) return HLBM_OK;
@@ -707,14 +1015,9 @@ int hlbm_force(hlbm_t *h, int32_t case_id, double *hist_xy, int64_t cap, int64_t
   return h->c->force(hist_xy, cap, n_out, win_t0, win_t1, theta);
 }
 
-int hlbm_adjoint(hlbm_t *h, int32_t case_id, const double *dJ_dFy, int64_t n, double grad[3]) {
-  (void)case_id;
-  (void)dJ_dFy;
-  (void)n;
-  (void)grad;
-  if (!h) return HLBM_E_ARG;
-  h->c->err = "adjoint not available in this build";
-  return HLBM_E_UNSUPPORTED;
+int hlbm_adjoint(hlbm_t *h, int32_t case_id, const double *dJ_dF, int64_t n, double grad[3]) {
+  if (!h || case_id != 0) return HLBM_E_ARG;
+  return h->c->adjoint(dJ_dF, n, grad);
 }
 
 int hlbm_get_state(hlbm_t *h, int32_t case_id, int32_t which, void *buf, size_t bytes) {

@@ -4,182 +4,17 @@
 // for the lattice and [9][nnode] for the body-fitted grid. T is the storage
 // type of the lattice and R the arithmetic type (FP64/FP64, FP32/FP32,
 // FP16 holding f_i - w_i / FP32). The grid is kept in R.
-//
-// D2Q9 ordering: rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1),
-// (1,-1); weights 4/9, 1/9 (axis), 1/36 (diagonal); c_s^2 = 1/3.
 #include <hip/hip_ext.h>
 
 #include <cmath>
 
+#include "device_common.h"
 #include "kernels.h"
 
 namespace mghlbm {
 namespace {
 
-constexpr int CXd[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-constexpr int CYd[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-
-template <class R>
-__device__ __forceinline__ R wgt(int q) {
-  return q == 0 ? R(4.0 / 9.0) : (q < 5 ? R(1.0 / 9.0) : R(1.0 / 36.0));
-}
-
-// ---- storage traits --------------------------------------------------------
-template <class T>
-struct Stor;
-// st_stream: store of a value that is not read again in this kernel; the
-// lattice output is streamed with non-temporal stores.
-template <>
-struct Stor<double> {
-  static __device__ __forceinline__ double ld(const double *p, size_t i, int) { return p[i]; }
-  static __device__ __forceinline__ void st(double *p, size_t i, int, double v) { p[i] = v; }
-  static __device__ __forceinline__ void st_stream(double *p, size_t i, int, double v) {
-    __builtin_nontemporal_store(v, p + i);
-  }
-};
-template <>
-struct Stor<float> {
-  static __device__ __forceinline__ float ld(const float *p, size_t i, int) { return p[i]; }
-  static __device__ __forceinline__ void st(float *p, size_t i, int, float v) { p[i] = v; }
-  static __device__ __forceinline__ void st_stream(float *p, size_t i, int, float v) {
-    __builtin_nontemporal_store(v, p + i);
-  }
-};
-template <>
-struct Stor<__half> {  // deviation from the rest equilibrium w_i
-  static __device__ __forceinline__ float ld(const __half *p, size_t i, int q) {
-    return __half2float(p[i]) + wgt<float>(q);
-  }
-  static __device__ __forceinline__ void st(__half *p, size_t i, int q, float v) {
-    p[i] = __float2half_rn(v - wgt<float>(q));
-  }
-  static __device__ __forceinline__ void st_stream(__half *p, size_t i, int q, float v) {
-    const __half h = __float2half_rn(v - wgt<float>(q));
-    __builtin_nontemporal_store(*reinterpret_cast<const unsigned short *>(&h),
-                                reinterpret_cast<unsigned short *>(p + i));
-  }
-};
-
-// ---- D2Q9 helpers -------------------------------------------------------------
-// Eq.(local_eq) with c_s^2 = 1/3: w rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
-template <class R>
-__device__ __forceinline__ void equilibrium(R rho, R ux, R uy, R e[9]) {
-  const R uu = R(1.5) * (ux * ux + uy * uy);
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const R cu = R(CXd[q]) * ux + R(CYd[q]) * uy;
-    e[q] = wgt<R>(q) * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - uu);
-  }
-}
-
-template <class R>
-__device__ __forceinline__ void moments(const R f[9], R &rho, R &ux, R &uy) {
-  rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-  const R mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-  const R my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-  const R inv = R(1) / rho;
-  ux = mx * inv;
-  uy = my * inv;
-}
-
-// Populations arriving at lattice node (x, y) at t_{k+1}: pulled from the
-// post-collision buffer of t_k (left side of Eq.(LBE)); across a resting y
-// wall, halfway bounce-back returns the opposite population of the node.
-template <class T, class R>
-__device__ __forceinline__ void pull(const T *__restrict__ A, int nx, int ny, int periodic_y, int x,
-                                     int y, R f[9]) {
-  const size_t plane = (size_t)nx * ny;
-  const int xm = x == 0 ? nx - 1 : x - 1;
-  const int xp = x == nx - 1 ? 0 : x + 1;
-  int ym = y - 1, yp = y + 1;
-  bool lo = false, hi = false;
-  if (periodic_y) {
-    ym = y == 0 ? ny - 1 : ym;
-    yp = y == ny - 1 ? 0 : yp;
-  } else {
-    lo = (y == 0);
-    hi = (y == ny - 1);
-  }
-  const size_t r = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
-  const size_t c = r + x;
-  f[0] = Stor<T>::ld(A, c, 0);
-  f[1] = Stor<T>::ld(A, 1 * plane + r + xm, 1);
-  f[3] = Stor<T>::ld(A, 3 * plane + r + xp, 3);
-  if (lo) {
-    f[2] = Stor<T>::ld(A, 4 * plane + c, 4);
-    f[5] = Stor<T>::ld(A, 7 * plane + c, 7);
-    f[6] = Stor<T>::ld(A, 8 * plane + c, 8);
-  } else {
-    f[2] = Stor<T>::ld(A, 2 * plane + rm + x, 2);
-    f[5] = Stor<T>::ld(A, 5 * plane + rm + xm, 5);
-    f[6] = Stor<T>::ld(A, 6 * plane + rm + xp, 6);
-  }
-  if (hi) {
-    f[4] = Stor<T>::ld(A, 2 * plane + c, 2);
-    f[7] = Stor<T>::ld(A, 5 * plane + c, 5);
-    f[8] = Stor<T>::ld(A, 6 * plane + c, 6);
-  } else {
-    f[4] = Stor<T>::ld(A, 4 * plane + rp + x, 4);
-    f[7] = Stor<T>::ld(A, 7 * plane + rp + xp, 7);
-    f[8] = Stor<T>::ld(A, 8 * plane + rp + xm, 8);
-  }
-}
-
-// Bilinear Lagrange interpolation over the lattice cell around (X, Y) of
-// density, velocity and f^neq = f - f^eq of the pre-collision populations at
-// t_{k+1} (refill type 1 and the grid's interface donors).
-template <class T, class R>
-__device__ __forceinline__ void bilinear_donors(const CaseView<T, R> &v, double X, double Y, R &rho,
-                                                R &ux, R &uy, R fneq[9]) {
-  const double fx = floor(X), fy = floor(Y);
-  const double a = X - fx, b = Y - fy;
-  int x0 = (int)fx, y0 = (int)fy;
-  const double w4[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
-  rho = ux = uy = R(0);
-#pragma unroll
-  for (int q = 0; q < 9; ++q) fneq[q] = R(0);
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    int xd = x0 + (d & 1), yd = y0 + (d >> 1);
-    xd = xd >= v.nx ? xd - v.nx : (xd < 0 ? xd + v.nx : xd);
-    if (v.periodic_y) yd = yd >= v.ny ? yd - v.ny : (yd < 0 ? yd + v.ny : yd);
-    R f[9], e[9], r, vx, vy;
-    pull<T, R>(v.A, v.nx, v.ny, v.periodic_y, xd, yd, f);
-    moments<R>(f, r, vx, vy);
-    equilibrium<R>(r, vx, vy, e);
-    const R w = R(w4[d]);
-    rho += w * r;
-    ux += w * vx;
-    uy += w * vy;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) fneq[q] += w * (f[q] - e[q]);
-  }
-}
-
-// Triangle of the grid cell (ci, cj) containing local cell coordinates
-// (a, b) in [0,1]^2 and its barycentric weights. Cells left of the centre
-// line are cut by the rising diagonal, cells right of it by the falling one.
-__device__ __forceinline__ void cell_triangle(int ci, int cj, int nux, double a, double b,
-                                              int node[3], double lam[3]) {
-  const int n00 = cj * nux + ci, n10 = n00 + 1, n01 = n00 + nux, n11 = n01 + 1;
-  if (2 * ci + 1 < nux) {
-    if (b <= a) {  // (n00, n10, n11)
-      node[0] = n00; node[1] = n10; node[2] = n11;
-      lam[0] = 1.0 - a; lam[1] = a - b; lam[2] = b;
-    } else {       // (n00, n11, n01)
-      node[0] = n00; node[1] = n11; node[2] = n01;
-      lam[0] = 1.0 - b; lam[1] = a; lam[2] = b - a;
-    }
-  } else {
-    if (a + b <= 1.0) {  // (n00, n10, n01)
-      node[0] = n00; node[1] = n10; node[2] = n01;
-      lam[0] = 1.0 - a - b; lam[1] = a; lam[2] = b;
-    } else {             // (n10, n11, n01)
-      node[0] = n10; node[1] = n11; node[2] = n01;
-      lam[0] = 1.0 - b; lam[1] = a + b - 1.0; lam[2] = 1.0 - a;
-    }
-  }
-}
+using namespace dev;
 
 // ---- K1: fused pull stream + BGK collide, Eq.(LBE) -------------------------
 template <class T, class R>
@@ -217,34 +52,14 @@ __global__ __launch_bounds__(256) void k_lattice_from_grid(CaseView<T, R> v, con
   const int x = v.k2_x0 + blockIdx.x * blockDim.x + threadIdx.x;
   const int y = min(P.iy0, P.piy0) + (int)blockIdx.y;
   if (x >= v.k2_x0 + v.k2_w || y > max(P.iy1, P.piy1)) return;
-  const bool in_k = x >= P.ix0 && x <= P.ix1 && y >= P.iy0 && y <= P.iy1;
-  const bool in_p = x >= P.pix0 && x <= P.pix1 && y >= P.piy0 && y <= P.piy1;
-  const bool interp = in_k && (x == P.ix0 || x == P.ix1 || y == P.iy0 || y == P.iy1);
-  if (!(interp || (!in_k && in_p))) return;
-  const double X0 = v.xc + (double)(0 - v.nux / 2) * v.h;
-  const double Y0 = P.ybase + (0.0 - 0.5 * (double)(v.nuy - 1)) * v.h;
-  const double s = ((double)x - X0) / v.h, t = ((double)y - Y0) / v.h;
-  const int ci = min(max((int)floor(s), 0), v.nux - 2), cj = min(max((int)floor(t), 0), v.nuy - 2);
-  int node[3];
-  double lam[3];
-  cell_triangle(ci, cj, v.nux, s - ci, t - cj, node, lam);
-  R rho = 0, ux = 0, uy = 0, fneq[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) fneq[q] = R(0);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    R f[9], e[9], r, vx, vy;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) f[q] = g[(size_t)q * v.nnode + node[a]];
-    moments<R>(f, r, vx, vy);
-    equilibrium<R>(r, vx, vy, e);
-    const R l = R(lam[a]);
-    rho += l * r;
-    ux += l * vx;
-    uy += l * vy;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) fneq[q] += l * (f[q] - e[q]);
-  }
+  if (!from_grid_target(P, x, y)) return;
+  const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body};
+  int ci, cj, node[3];
+  double a, b, lam[3], dlam[3];
+  lattice_node_cell(gg, P.ybase, x, y, ci, cj, a, b);
+  cell_triangle(ci, cj, v.nux, a, b, node, lam, dlam);
+  R rho, ux, uy, fneq[9];
+  grid_barycentric<R>(g, v.nnode, node, lam, rho, ux, uy, fneq);
   R e[9];
   equilibrium<R>(rho, ux, uy, e);
   const size_t plane = (size_t)v.nx * v.ny, c = (size_t)y * v.nx + x;
@@ -273,22 +88,7 @@ __global__ __launch_bounds__(256) void k_interface_donors(CaseView<T, R> v) {
     const int i = p % v.nux, j = p / v.nux;
     const double X = v.xc + (double)(i - v.nux / 2) * v.h;
     const double Y = P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
-    const double fx = floor(X), fy = floor(Y);
-    const double a = X - fx, b = Y - fy;
-    const double w = (d & 1 ? a : 1.0 - a) * (d >> 1 ? b : 1.0 - b);
-    int xd = (int)fx + (d & 1), yd = (int)fy + (d >> 1);
-    xd = xd >= v.nx ? xd - v.nx : (xd < 0 ? xd + v.nx : xd);
-    if (v.periodic_y) yd = yd >= v.ny ? yd - v.ny : (yd < 0 ? yd + v.ny : yd);
-    R f[9], e[9], r, vx, vy;
-    pull<T, R>(v.A, v.nx, v.ny, v.periodic_y, xd, yd, f);
-    moments<R>(f, r, vx, vy);
-    equilibrium<R>(r, vx, vy, e);
-    const R wr = R(w);
-    acc[0] = wr * r;
-    acc[1] = wr * vx;
-    acc[2] = wr * vy;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) acc[3 + q] = wr * (f[q] - e[q]);
+    donor_corner<T, R>(v.A, v.nx, v.ny, v.periodic_y, X, Y, d, acc);
   }
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
@@ -351,16 +151,21 @@ constexpr size_t substeps_lds_bytes() {
   return sizeof(R) * (size_t)(NS * G::RN + NS * G::NRING) + sizeof(int) * (size_t)G::RN;
 }
 
-constexpr int kSubstepThreads = 512;  // 8 waves share one tile's LDS
+// workgroup size: FP64 nodes need the register room of 512 threads, FP32
+// nodes fit 1024 (16 waves on one tile's LDS)
+template <class R>
+constexpr int substep_threads() {
+  return sizeof(R) == 8 ? 512 : 1024;
+}
 
 template <class R, int H>
-__global__ __launch_bounds__(kSubstepThreads) void k_grid_substeps(
+__global__ __launch_bounds__(substep_threads<R>()) void k_grid_substeps(
     const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
     const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int ntiles,
     R dt, R dt_tau, const R *__restrict__ uw, const int64_t *__restrict__ dk, int n_sub, int m0, int count) {
   using G = Region<H>;
   constexpr int RX = G::RX, RN = G::RN;
-  constexpr int NT = kSubstepThreads, PER = (RN + NT - 1) / NT;
+  constexpr int NT = substep_threads<R>(), PER = (RN + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   R *sl = reinterpret_cast<R *>(lds_raw);   // [RN][NS] grid f, f^neq
   R *rl = sl + NS * RN;                     // [NRING][NS] f*, f^neq* on the outer ring
@@ -533,50 +338,24 @@ __global__ __launch_bounds__(256) void k_refill(CaseView<T, R> v, const R *__res
     return;
   }
   const StepParams &P = v.params[*v.dk];
-  const double tol = 1e-12;
-  const double xrel = (double)(i - v.nux / 2) * v.h;
-  const double Ynew = P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
-  const double Y0 = P.ybase + (0.0 - 0.5 * (double)(v.nuy - 1)) * v.h;
-  const double s = (double)i, t = (Ynew - Y0) / v.h;
-  const int slot_row = v.nuy / 2 - 1;
-  const double half = v.half_b + 1e-9 * v.h;
-  auto body_cell = [&](int ci, int cj) {
-    return v.body && cj == slot_row && (double)(ci - v.nux / 2) * v.h >= -half &&
-           (double)(ci + 1 - v.nux / 2) * v.h <= half;
-  };
-  int kind = 1;
-  int ci = 0, cj = 0;
-  double a = 0, b = 0;
-  if (t >= -tol && t <= (double)(v.nuy - 1) + tol) {
-    cj = min(max((int)floor(t), 0), v.nuy - 2);
-    ci = min(max((int)floor(s), 0), v.nux - 2);
-    b = t - cj;
-    a = s - ci;
-    kind = 3;
-    if (body_cell(ci, cj)) {
-      if (b <= tol && cj > 0 && !body_cell(ci, cj - 1)) { cj -= 1; b += 1.0; }
-      else if (b >= 1.0 - tol && cj < v.nuy - 2 && !body_cell(ci, cj + 1)) { cj += 1; b -= 1.0; }
-      else if (a <= tol && ci > 0 && !body_cell(ci - 1, cj)) { ci -= 1; a += 1.0; }
-      else if (a >= 1.0 - tol && ci < v.nux - 2 && !body_cell(ci + 1, cj)) { ci += 1; a -= 1.0; }
-      else kind = 0;
-    }
-  } else {
-    kind = 0;
-  }
-  if (kind == 3) {
+  const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body};
+  const RefillCell rc = refill_cell(gg, P.ybase, P.ybase1, i, j);
+  if (rc.kind == 3) {
     int node[3];
-    double lam[3];
-    cell_triangle(ci, cj, v.nux, a, b, node, lam);
+    double lam[3], dlam[3];
+    cell_triangle(rc.ci, rc.cj, v.nux, rc.a, rc.b, node, lam, dlam);
 #pragma unroll
     for (int q = 0; q < 9; ++q)
       out[q] = R(lam[0]) * fo[q * N + node[0]] + R(lam[1]) * fo[q * N + node[1]] + R(lam[2]) * fo[q * N + node[2]];
-  } else if (v.body && fabs(xrel) < v.half_b && fabs(Ynew - P.ybase) < v.half_T) {
+  } else if (rc.kind == 2) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = fo[q * N + p];
     atomicAdd(&v.counts[1], 1ull);
   } else {
+    const double X = v.xc + (double)(i - v.nux / 2) * v.h;
+    const double Ynew = P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
     R rho, ux, uy, fneq[9], e[9];
-    bilinear_donors<T, R>(v, v.xc + xrel, Ynew, rho, ux, uy, fneq);
+    lattice_bilinear<T, R>(v.A, v.nx, v.ny, v.periodic_y, X, Ynew, rho, ux, uy, fneq);
     equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = e[q] + v.k_neq * fneq[q];
@@ -713,7 +492,7 @@ void Kernels<T, R>::interface_donors(const CaseView<T, R> &v, hipStream_t s) {
 template <class T, class R>
 void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s) {
   const int tiles_x = (v.nux + TX - 1) / TX, tiles_y = (v.nuy + TY - 1) / TY;
-  hipLaunchKernelGGL((k_grid_substeps<R, kSubstepBlock>), dim3(tiles_x * tiles_y), dim3(kSubstepThreads),
+  hipLaunchKernelGGL((k_grid_substeps<R, kSubstepBlock>), dim3(tiles_x * tiles_y), dim3(substep_threads<R>()),
                      (substeps_lds_bytes<R, kSubstepBlock>()), s, f, fout, (const R *)v.star_f, (const R *)v.star_n,
                      v.cls, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw,
                      (const int64_t *)v.dk, v.n_sub, m0, count);

@@ -17,8 +17,9 @@ OK, E_ARG, E_NOMEM, E_HIP, E_UNSTABLE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -
 BC_PERIODIC_X_WALLS_Y, BC_PERIODIC = 0, 1
 FP64, FP32, FP16_DEV = 0, 1, 2
 FLAG_NO_BODY = 1
-STATE_LATTICE, STATE_GRID = 0, 1
-K_STREAM_COLLIDE, K_LATTICE_FROM_GRID, K_GRID_SUBSTEPS, K_REFILL, K_FORCE, K_STEP = range(6)
+STATE_LATTICE, STATE_GRID, STATE_ADJ_LATTICE, STATE_ADJ_GRID = 0, 1, 2, 3
+(K_STREAM_COLLIDE, K_LATTICE_FROM_GRID, K_GRID_SUBSTEPS, K_REFILL, K_FORCE, K_STEP,
+ K_ADJ_STREAM_COLLIDE, K_ADJOINT) = range(8)
 STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV}
 
 EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_state",
@@ -174,11 +175,25 @@ class Case:
         self._check(load().hlbm_timing_get(self.h, kernel, C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
 
-    def adjoint(self, dJ_dFy):
+    def adjoint(self, dJ_dF):
+        """dJ/d(A, omega, tau) for J = sum_k dJ_dF[k] . F(t_{k+1}); dJ_dF has
+        one (x, y) row per step taken."""
         g = np.zeros(3)
-        dJ = np.ascontiguousarray(dJ_dFy, dtype=np.float64)
-        self._check(load().hlbm_adjoint(self.h, 0, _ptr(dJ), dJ.size, _ptr(g)))
+        dJ = np.ascontiguousarray(dJ_dF, dtype=np.float64).reshape(-1, 2)
+        self._check(load().hlbm_adjoint(self.h, 0, _ptr(dJ), dJ.shape[0], _ptr(g)))
         return g
+
+    def adjoint_lattice(self):
+        """dJ/d(lattice at t_0) from the last adjoint."""
+        out = np.zeros((9, self.ny, self.nx))
+        self._check(load().hlbm_get_state(self.h, 0, STATE_ADJ_LATTICE, out.ctypes.data, out.nbytes))
+        return out
+
+    def adjoint_grid(self):
+        """dJ/d(grid at t_0) from the last adjoint."""
+        out = np.zeros((9, self.nnode))
+        self._check(load().hlbm_get_state(self.h, 0, STATE_ADJ_GRID, out.ctypes.data, out.nbytes))
+        return out
 
 
 def case_from_preset(cfg: dict, **overrides) -> Case:
