@@ -13,11 +13,19 @@ Prints one JSON line: lattice MLUPS (whole job), a roofline entry for the
 dominant kernel (lattice stream-collide, HBM bound, 18 s bytes per node
 update, timed with HIP events on its stream) and the CPU oracle timed on a
 bounded sample of the same workload.
+
+The "adjoint" entry times the differentiation case (1024^2 lattice, 256 x 64
+grid, FP32, 4000 steps, checkpoints every 200 steps): the forward run with
+checkpoints, then the discrete adjoint for the cotangent of Re Theta (window
+[1, 4) periods), their time ratio, the adjoint lattice kernel against its
+algorithmic bytes, and central differences of Re Theta at relative step
+1e-4 in (KC, beta, tau) against the adjoint's gradient.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -58,6 +66,78 @@ def cpu_baseline(cfg, steps):
             "sample": f"first {steps} steps of the same workload, FP64, one thread ({dt:.1f} s)"}
 
 
+def adjoint_leg(workload, storage, W_ckpt, fd_step, steps=None):
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.autograd import theta
+    from paper_2006_13631_amd.workloads import preset
+    cfg = preset(workload)
+    full = cfg.pop("steps")
+    steps = steps or full
+    cfg.pop("ckpt_every", None)
+    W = W_ckpt
+    case = H.Case(max_steps=steps, storage=storage, ckpt_every=W, **cfg)
+    info = case.info()
+    print(f"# adjoint leg {workload} {storage} steps {steps} window {W}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    case.step(steps)
+    t_fwd = time.perf_counter() - t0
+    hist = torch.from_numpy(case.history()).requires_grad_(True)
+    A = torch.tensor(info.A, dtype=torch.float64)
+    om = torch.tensor(info.omega, dtype=torch.float64)
+    th = theta(hist, A, om, cfg["b"])
+    th.real.backward()
+    w = hist.grad.numpy().copy()
+    g = case.adjoint(w)  # first call allocates the tape
+    print("# adjoint warm-up done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    g = case.adjoint(w)
+    t_adj = time.perf_counter() - t0
+    case.timing(True)
+    case.adjoint(w)
+    ms, cnt = case.timing_get(H.K_ADJ_STREAM_COLLIDE)
+    case.timing(False)
+    sT = BYTES[{H.FP64: "f64", H.FP32: "f32", H.FP16_DEV: "f16dev"}[storage]]
+    sR = 8 if storage == H.FP64 else 4
+    nodes = cfg["nx"] * cfg["ny"]
+    k1_bytes = (9 * sT + 18 * sR) * nodes
+    k1_avg = ms / 1000.0 / max(cnt, 1)
+    # total derivative of Re Theta in (KC, beta, tau): A = KC b/(2 pi) and
+    # omega = 2 pi nu beta / b^2 with nu = (tau - 1/2)/3, so tau also moves
+    # omega; Theta's explicit dependence on A and omega comes from torch
+    Ag = torch.tensor(info.A, dtype=torch.float64, requires_grad=True)
+    omg = torch.tensor(info.omega, dtype=torch.float64, requires_grad=True)
+    theta(torch.from_numpy(case.history()), Ag, omg, cfg["b"]).real.backward()
+    dA, dW, dT = g[0] + Ag.grad.item(), g[1] + omg.grad.item(), g[2]
+    b, tau = cfg["b"], cfg["tau"]
+    adj_cfg = {"kc": dA * b / (2 * math.pi), "beta": dW * info.omega / cfg["beta"],
+               "tau": dT + dW * info.omega / (tau - 0.5)}
+    fd = {}
+    for key in (("kc", "beta", "tau") if fd_step else ()):
+        vals = []
+        for sgn in (1, -1):
+            c2 = dict(cfg)
+            c2[key] = cfg[key] * (1 + sgn * fd_step)
+            cc = H.Case(max_steps=steps, storage=storage, **c2)
+            cc.step(steps)
+            vals.append(cc.theta().real)
+        fd[key] = (vals[0] - vals[1]) / (2 * fd_step * cfg[key])
+        print(f"# fd {key}: {fd[key]:.6e} adjoint {adj_cfg[key]:.6e}", file=sys.stderr, flush=True)
+    return {
+        "workload": workload, "storage": {H.FP64: "f64", H.FP32: "f32", H.FP16_DEV: "f16dev"}[storage],
+        "steps": steps, "ckpt_every": W, "objective": "Re Theta, window [1,4) periods",
+        "forward_s": round(t_fwd, 4), "adjoint_s": round(t_adj, 4), "ratio": round(t_adj / t_fwd, 3),
+        "adjoint_mlups": round(nodes * steps / t_adj / 1e6, 1),
+        "grad_A_omega_tau": [float(v) for v in g],
+        "dRe_theta_dKC_beta_tau": {k: float(v) for k, v in adj_cfg.items()},
+        "fd_rel_step": fd_step or None, "fd": {k: float(v) for k, v in fd.items()},
+        "fd_rel_err": {k: float(abs(fd[k] - adj_cfg[k]) / abs(adj_cfg[k])) for k in fd},
+        "kernel": "k_adj_stream_collide", "kernel_avg_us": round(k1_avg * 1e6, 3),
+        "kernel_bytes_per_launch": k1_bytes, "kernel_gbs": round(k1_bytes / k1_avg / 1e9, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +148,12 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--adjoint-workload", default="lamina_1024")
+    ap.add_argument("--adjoint-storage", default="f32", choices=list(BYTES))
+    ap.add_argument("--adjoint-window", type=int, default=200)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=None)
+    ap.add_argument("--no-fd", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
@@ -146,6 +232,9 @@ def main():
         "mlups_total": round((nx * ny + info.n_sub * info.nnode) * steps / dt / 1e6, 2),
         "theta": None if th is None else [th.real, th.imag],
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(args.adjoint_workload, H.STORAGE[args.adjoint_storage], args.adjoint_window,
+                                     0.0 if args.no_fd else 1e-4, args.adjoint_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -27,7 +27,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     objs = []
-    common = ["-O3", "-std=c++17", "-fPIC", "-Wall",
+    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wshadow",
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")

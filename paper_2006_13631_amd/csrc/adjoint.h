@@ -12,6 +12,20 @@
 
 namespace mghlbm {
 
+// The transposed stencil of a grid node q: slot s holds the coefficients its
+// neighbour p (at slot s of q) applies to q, i.e. p's own slot 8 - s; bit s
+// of star is set when p reads q's structured-derived value instead of q's f
+// (both on the outer ring, Eq.(postcollision2_u)). Nodes with equal
+// transposed stencils share one class.
+template <class R>
+struct AdjClass {
+  R Gx[NSLOT];
+  R Gy[NSLOT];
+  R C[NSLOT];
+  int star;
+  int type;  // NodeType of q
+};
+
 // Everything the adjoint kernels of one reverse step read, by value.
 template <class T, class R>
 struct AdjCtx {
@@ -35,7 +49,12 @@ struct AdjCtx {
   const GridClass<R> *tab;
   const int *iface;
   const int *wall_nodes;    // ids of the wall nodes
+  const int *widx;          // per grid node: its index among the wall nodes, -1 otherwise
+  const unsigned char *ntype;  // per grid node: NodeType
+  const int *acls;          // per grid node: transposed stencil class
+  const AdjClass<R> *atab;
   const double *wall_nrm;   // [2][nnode]: sum over a wall node's edges of (len/2) n
+  const R *wt;              // [n][3][n_wall] wall-node moments before the velocity is imposed
   const R *U0;              // grid state U_k
   const R *Un;              // grid state after the n sub-steps of step k
   R *star_f, *star_n;       // structured-derived values of step k (recomputed)
@@ -59,12 +78,11 @@ struct AdjKernels {
   static void star(const AdjCtx<T, R> &c, hipStream_t s);
   // refill and force adjoints: Ubn from Ub_next; Z1 and zf
   static void refill(const AdjCtx<T, R> &c, int slot0, hipStream_t s);
-  // one sub-step backwards: wall-velocity adjoint in place on ub, then the
-  // transposed stencil ub -> ub_out; first/last: m = n-1 / m = 0
-  static void wall(const AdjCtx<T, R> &c, const R *Um, R *ub, R uw, double duwA, double duwW, int slot0,
-                   hipStream_t s);
-  static void substep(const AdjCtx<T, R> &c, const R *Um, const R *ub, R *ub_out, int first, int last, int slot0,
-                      hipStream_t s);
+  // one sub-step backwards: wall-velocity adjoint (lamina velocity uw of
+  // this sub-step and its A, omega derivatives), then the transposed
+  // stencil ub -> ub_out; first/last: m = n-1 / m = 0
+  static void substep(const AdjCtx<T, R> &c, const R *Um, const R *ub, R *ub_out, int m, R uw, double duwA,
+                      double duwW, int first, int last, int slot0, hipStream_t s);
   // lattice side: donor gather E, stream-collide adjoint, grid-to-lattice adjoint
   static void donor_gather(const AdjCtx<T, R> &c, int slot0, hipStream_t s);
   static void stream_collide(const AdjCtx<T, R> &c, int slot0, hipStream_t s, hipEvent_t start = nullptr,
@@ -74,7 +92,6 @@ struct AdjKernels {
   static void from_grid_gather(const AdjCtx<T, R> &c, R *ub, int slot0, hipStream_t s);
   // partial-sum slots each launcher uses
   static int refill_slots(const AdjCtx<T, R> &c);
-  static int wall_slots(const AdjCtx<T, R> &c);
   static int substep_slots(const AdjCtx<T, R> &c);
   static int donor_gather_slots(const AdjCtx<T, R> &c);
   static int stream_collide_slots(const AdjCtx<T, R> &c);

@@ -8,10 +8,10 @@
 //   refill      per grid node: adjoint of its own type-1 refill (Z1), then a
 //               gather of every refill that read it (type 3 barycentric in
 //               its column, type 2 and wall copies) plus the force adjoint
-//   wall        per wall node and sub-step: adjoint of the imposed lamina
-//               velocity (the forward output is recomputed from the tape)
-//   substep     per grid node: transposed finite-volume stencil, gathered
-//               from the 3 x 3 neighbours through LDS; structured-derived
+//   substep     per sub-step: wall nodes first pulled back through the
+//               imposed lamina velocity (from moments the recompute taped),
+//               then per grid node its transposed finite-volume stencil
+//               class applied to the 3 x 3 neighbours in LDS; structured-derived
 //               adjoints accumulate at interface nodes; the last sub-step
 //               turns them into the donor adjoint (Z2)
 //   donor gather per lattice node near the grid: the bilinear weights of every
@@ -40,13 +40,16 @@ namespace {
 
 using namespace dev;
 
-constexpr int NT = 256;
+constexpr int NT = 256;  // lattice-sized kernels
+constexpr int NG = 64;   // grid-sized kernels: one wave per workgroup spreads the few
+                         // thousand grid nodes over all compute units
 
 inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
-// Adds this block's (a, b, c) to slot[0..2]; all NT threads must call it.
+// Adds this block's (a, b, c) to slot[0..2]; all BT threads must call it.
+template <int BT>
 __device__ __forceinline__ void block_accum3(double a, double b, double c, double *slot) {
-  __shared__ double red[3][NT / 64];
+  __shared__ double red[3][BT / 64];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     a += __shfl_xor(a, o, 64);
@@ -64,7 +67,7 @@ __device__ __forceinline__ void block_accum3(double a, double b, double c, doubl
   if (tid == 0) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
-    for (int w = 0; w < NT / 64; ++w) {
+    for (int w = 0; w < BT / 64; ++w) {
       s0 += red[0][w];
       s1 += red[1][w];
       s2 += red[2][w];
@@ -91,7 +94,7 @@ __device__ __forceinline__ double grid_y(const GridGeom &g, double yb, int j) {
 
 // ---- star: f*, f^neq* of step k and the interpolated moments ----------------
 template <class T, class R>
-__global__ __launch_bounds__(NT) void k_adj_star(AdjCtx<T, R> c) {
+__global__ __launch_bounds__(NG) void k_adj_star(AdjCtx<T, R> c) {
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = gt >> 2, d = gt & 3;
   const bool valid = t < c.n_iface;
@@ -125,8 +128,8 @@ __global__ __launch_bounds__(NT) void k_adj_star(AdjCtx<T, R> c) {
 
 // ---- refill and force adjoint -------------------------------------------------
 template <class T, class R>
-__global__ __launch_bounds__(NT) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
-  const int q = blockIdx.x * NT + threadIdx.x;
+__global__ __launch_bounds__(NG) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
+  const int q = blockIdx.x * NG + threadIdx.x;
   const size_t N = (size_t)c.nnode;
   const GridGeom &g = c.gg;
   double pA = 0.0, pW = 0.0, pT = 0.0;
@@ -168,9 +171,12 @@ __global__ __launch_bounds__(NT) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
 #pragma unroll
     for (int s = 0; s < 9; ++s) un[s] = c.Un[s * N + q];
     double dsum = 0.0;
+    // a new node jj lands near old row jj + delta; its triangle's rows are
+    // within one (two next to the lamina) of that
     const double delta = (c.P.ybase1 - c.P.ybase) / g.h;
-    const int jc = j - (int)floor(delta);
-    for (int jj = max(jc - 4, 0); jj <= min(jc + 3, g.nuy - 1); ++jj) {
+    const int jlo = max((int)ceil((double)j - 2.0 - delta) - 1, 0);
+    const int jhi = min((int)ceil((double)j + 2.0 - delta), g.nuy - 1);
+    for (int jj = jlo; jj <= jhi; ++jj) {
       for (int ii = max(i - 1, 0); ii <= min(i + 1, g.nux - 1); ++ii) {
         const int p = jj * g.nux + ii;
         if (c.tab[c.cls[p]].type == NODE_WALL) continue;
@@ -216,116 +222,87 @@ __global__ __launch_bounds__(NT) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
 #pragma unroll
     for (int s = 0; s < 9; ++s) c.Ubn[s * N + q] = acc[s];
   }
-  block_accum3(pA, pW, pT, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+  block_accum3<NG>(pA, pW, pT, c.part + 3 * (size_t)(slot0 + blockIdx.x));
 }
 
 // ---- one sub-step backwards -----------------------------------------------------
 // Wall nodes: the forward output o of Eq.(ulbe) is mapped to
-// W(o) = o + f^eq(rho(o), (0, u_w)) - f^eq(rho(o), u(o)); ub <- W'(o)^T ub.
-template <class T, class R>
-__global__ __launch_bounds__(NT) void k_adj_wall(AdjCtx<T, R> c, const R *__restrict__ Um, R *__restrict__ ub,
-                                                 R uw, double duwA, double duwW, int slot0) {
-  const int t = blockIdx.x * NT + threadIdx.x;
-  const size_t N = (size_t)c.nnode;
-  const GridGeom &g = c.gg;
-  double pA = 0.0, pW = 0.0;
-  if (t < c.n_wall) {
-    const int p = c.wall_nodes[t];
-    const int i = p % g.nux, j = p / g.nux;
-    const GridClass<R> &cl = c.tab[c.cls[p]];
-    R ax[9], ay[9], sc[9];
+// W(o) = o + f^eq(rho(o), (0, u_w)) - f^eq(rho(o), u(o)); the adjoint of the
+// new state is pulled back through W'(o)^T (which needs only the moments of
+// o, taped by the recompute) before the stencil.
+template <class R>
+__device__ __forceinline__ void wall_vjp(R rho, R ux, R uy, R uw, R u[9], R &d_uw) {
+  R ar, axx, ayy, arw, axw, ayw;
+  equilibrium_vjp<R>(rho, ux, uy, u, ar, axx, ayy);
+  equilibrium_vjp<R>(rho, R(0), uw, u, arw, axw, ayw);
+  const R inv = R(1) / rho;
+  const R bx = -axx * inv, by = -ayy * inv;
+  const R base = arw - ar - bx * ux - by * uy;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) ax[q] = ay[q] = sc[q] = R(0);
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-      const int ii = i + s % 3 - 1, jj = j + s / 3 - 1;
-      if (ii < 0 || jj < 0 || ii >= g.nux || jj >= g.nuy) continue;
-      const size_t pq = (size_t)jj * g.nux + ii;
-      R f[9], e[9], r, vx, vy;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) f[q] = Um[q * N + pq];
-      moments<R>(f, r, vx, vy);
-      equilibrium<R>(r, vx, vy, e);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        ax[q] += cl.Gx[s] * f[q];
-        ay[q] += cl.Gy[s] * f[q];
-        sc[q] += cl.C[s] * (f[q] - e[q]);
-      }
-    }
-    R o[9], u[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      o[q] = Um[q * N + p] + c.dt * (R(CXd[q]) * ax[q] + R(CYd[q]) * ay[q]) - c.dt_tau * sc[q];
-      u[q] = ub[q * N + p];
-    }
-    R rho, ux, uy;
-    moments<R>(o, rho, ux, uy);
-    R ar, axx, ayy, arw, axw, ayw;
-    equilibrium_vjp<R>(rho, ux, uy, u, ar, axx, ayy);
-    equilibrium_vjp<R>(rho, R(0), uw, u, arw, axw, ayw);
-    const R inv = R(1) / rho;
-    const R bx = -axx * inv, by = -ayy * inv;
-    const R base = arw - ar - bx * ux - by * uy;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) ub[q * N + p] = u[q] + base + bx * R(CXd[q]) + by * R(CYd[q]);
-    pA += (double)ayw * duwA;
-    pW += (double)ayw * duwW;
-  }
-  block_accum3(pA, pW, 0.0, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+  for (int q = 0; q < 9; ++q) u[q] = u[q] + base + bx * R(CXd[q]) + by * R(CYd[q]);
+  d_uw = ayw;
 }
 
-// Transposed Eq.(ulbe)/Eq.(postcollision2_u) stencil. A workgroup owns a
-// 64 x 4 tile and stages the adjoint of the whole 66 x 6 region (tile plus
-// one-node halo) with the neighbours' stencil classes in LDS. Node q gathers
-// from each neighbour p the coefficient p applied to q's slot (the mirror of
-// q's slot for p).
-constexpr int ATX = 64, ATY = 4, ARX = ATX + 2, ARY = ATY + 2, ARN = ARX * ARY;
+// Transposed Eq.(ulbe)/Eq.(postcollision2_u) stencil. A workgroup (one
+// wave) owns a 16 x 4 tile and stages the adjoint of the 18 x 6 region (tile
+// plus one-node halo, zeros outside the grid) in LDS, wall nodes already
+// pulled back through the velocity imposition. Node q applies its transposed
+// stencil class to the nine region values around it.
+constexpr int ATX = 16, ATY = 4, ARX = ATX + 2, ARY = ATY + 2, ARN = ARX * ARY;
 
 template <class T, class R>
-__global__ __launch_bounds__(NT) void k_adj_substep(AdjCtx<T, R> c, const R *__restrict__ Um,
-                                                    const R *__restrict__ ub, R *__restrict__ ub_out, int first,
-                                                    int last, int slot0) {
+__global__ __launch_bounds__(NG) void k_adj_substep(AdjCtx<T, R> c, const R *__restrict__ Um,
+                                                    const R *__restrict__ ub, R *__restrict__ ub_out, int m, R uw,
+                                                    double duwA, double duwW, int first, int last, int slot0) {
   __shared__ R sob[ARN * 9];
-  __shared__ int scls[ARN];
   const GridGeom &g = c.gg;
   const size_t N = (size_t)c.nnode;
   const int tiles_x = (g.nux + ATX - 1) / ATX;
   const int x0 = (blockIdx.x % tiles_x) * ATX - 1, y0 = (blockIdx.x / tiles_x) * ATY - 1;
-  for (int idx = threadIdx.x; idx < ARN; idx += NT) {
-    const int gi = x0 + idx % ARX, gj = y0 + idx / ARX;
+  double pA = 0.0, pW = 0.0, pT = 0.0;
+  for (int idx = threadIdx.x; idx < ARN; idx += NG) {
+    const int rx = idx % ARX, ry = idx / ARX;
+    const int gi = x0 + rx, gj = y0 + ry;
     const bool in = gi >= 0 && gj >= 0 && gi < g.nux && gj < g.nuy;
-    const size_t p = in ? (size_t)gj * g.nux + gi : 0;
-    scls[idx] = in ? c.cls[p] : -1;
+    const int p = in ? gj * g.nux + gi : 0;
+    R u[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) sob[idx * 9 + q] = in ? ub[q * N + p] : R(0);
+    for (int q = 0; q < 9; ++q) u[q] = in ? ub[q * N + p] : R(0);
+    if (in && c.ntype[p] == NODE_WALL) {
+      const R *wt = c.wt + (size_t)m * 3 * c.n_wall;
+      const int w = c.widx[p];
+      R d_uw;
+      wall_vjp<R>(wt[w], wt[c.n_wall + w], wt[2 * c.n_wall + w], uw, u, d_uw);
+      if (rx >= 1 && rx <= ATX && ry >= 1 && ry <= ATY) {  // count each wall node once
+        pA += (double)d_uw * duwA;
+        pW += (double)d_uw * duwW;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sob[idx * 9 + q] = u[q];
   }
   __syncthreads();
-  double pT = 0.0;
   const int tx = threadIdx.x % ATX, ty = threadIdx.x / ATX;
   const int gi = x0 + 1 + tx, gj = y0 + 1 + ty;
   if (gi < g.nux && gj < g.nuy) {
     const int ci = (ty + 1) * ARX + (tx + 1);
     const size_t q = (size_t)gj * g.nux + gi;
-    const int tq = c.tab[scls[ci]].type;
+    const AdjClass<R> &cl = c.atab[c.acls[q]];
+    const int tq = cl.type, star = cl.star;
     R accF[9], accN[9], sf[9], sn[9];
 #pragma unroll
-    for (int s = 0; s < 9; ++s) accF[s] = accN[s] = sf[s] = sn[s] = R(0);
+    for (int k = 0; k < 9; ++k) accF[k] = accN[k] = sf[k] = sn[k] = R(0);
 #pragma unroll
-    for (int sp = 0; sp < NSLOT; ++sp) {
-      const int ri = ci + (sp / 3 - 1) * ARX + (sp % 3 - 1);
-      const int cp = scls[ri];
-      if (cp < 0) continue;
-      const GridClass<R> &cl = c.tab[cp];
-      const int s = NSLOT - 1 - sp;  // p's slot that holds q
+    for (int s = 0; s < NSLOT; ++s) {
+      const int ri = ci + (s / 3 - 1) * ARX + (s % 3 - 1);
       const R gx = cl.Gx[s], gy = cl.Gy[s], cc = cl.C[s];
-      const bool star = cl.type == NODE_INTERFACE && tq == NODE_INTERFACE;
+      const bool st_s = (star >> s) & 1;
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
         const R o = sob[ri * 9 + k];
         const R st = c.dt * (R(CXd[k]) * gx + R(CYd[k]) * gy) * o;
         const R ct = -c.dt_tau * cc * o;
-        if (star) {
+        if (st_s) {
           sf[k] += st;
           sn[k] += ct;
         } else {
@@ -387,13 +364,13 @@ __global__ __launch_bounds__(NT) void k_adj_substep(AdjCtx<T, R> c, const R *__r
     // d(dt_u/tau_u)/d tau = -dt_u/tau_u^2: the collision adjoints carry -dt_u/tau_u
     pT += dn * (-1.0 / c.tau_u);
   }
-  block_accum3(0.0, 0.0, pT, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+  block_accum3<NG>(pA, pW, pT, c.part + 3 * (size_t)(slot0 + blockIdx.x));
 }
 
 // ---- donor gather: dJ/d f_pre at lattice nodes read by bilinear donors ------------
 template <class T, class R>
-__global__ __launch_bounds__(NT) void k_adj_donor_gather(AdjCtx<T, R> c, int slot0) {
-  const int x = c.ex0 + blockIdx.x * NT + threadIdx.x;
+__global__ __launch_bounds__(NG) void k_adj_donor_gather(AdjCtx<T, R> c, int slot0) {
+  const int x = c.ex0 + blockIdx.x * NG + threadIdx.x;
   const int y = c.ey0 + blockIdx.y;
   const GridGeom &g = c.gg;
   const size_t N = (size_t)c.nnode;
@@ -458,7 +435,7 @@ __global__ __launch_bounds__(NT) void k_adj_donor_gather(AdjCtx<T, R> c, int slo
 #pragma unroll
     for (int k = 0; k < 9; ++k) c.E[k * plane + at] = Eo[k];
   }
-  block_accum3(pA, pW, 0.0, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
+  block_accum3<NG>(pA, pW, 0.0, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // ---- lattice stream-collide adjoint ---------------------------------------------
@@ -510,7 +487,7 @@ __global__ __launch_bounds__(NT) void k_adj_stream_collide(AdjCtx<T, R> c, int s
 #pragma unroll
     for (int q = 0; q < 9; ++q) c.Lb[idx[q]] = v[q];
   }
-  block_accum3(0.0, 0.0, pT, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
+  block_accum3<NT>(0.0, 0.0, pT, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // ---- grid-to-lattice adjoint, lattice side ---------------------------------------
@@ -552,13 +529,13 @@ __global__ __launch_bounds__(NT) void k_adj_from_grid(AdjCtx<T, R> c, int slot0)
 #pragma unroll
     for (int k = 0; k < 12; ++k) c.Z3[k * zp + at] = z[k];
   }
-  block_accum3(0.0, 0.0, pT, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
+  block_accum3<NT>(0.0, 0.0, pT, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // ---- grid-to-lattice adjoint, grid side -------------------------------------------
 template <class T, class R>
-__global__ __launch_bounds__(NT) void k_adj_from_grid_gather(AdjCtx<T, R> c, R *__restrict__ ub, int slot0) {
-  const int q = blockIdx.x * NT + threadIdx.x;
+__global__ __launch_bounds__(NG) void k_adj_from_grid_gather(AdjCtx<T, R> c, R *__restrict__ ub, int slot0) {
+  const int q = blockIdx.x * NG + threadIdx.x;
   const GridGeom &g = c.gg;
   const size_t N = (size_t)c.nnode;
   double pA = 0.0, pW = 0.0;
@@ -575,7 +552,13 @@ __global__ __launch_bounds__(NT) void k_adj_from_grid_gather(AdjCtx<T, R> c, R *
     for (int k = 0; k < 12; ++k) zs[k] = zd[k] = R(0);
     bool any = false;
     const size_t zp = (size_t)c.k2_w * c.k2_h;
-    for (int yl = ylo; yl <= yhi; ++yl) {
+    // no candidate can be set from the grid when all of them lie strictly
+    // inside the rectangle (not on its edge) or outside both rectangles
+    const StepParams &P = c.P;
+    const bool deep = xlo > P.ix0 && xhi < P.ix1 && ylo > P.iy0 && yhi < P.iy1;
+    const bool away = xhi < min(P.ix0, P.pix0) || xlo > max(P.ix1, P.pix1) || yhi < min(P.iy0, P.piy0) ||
+                      ylo > max(P.iy1, P.piy1);
+    for (int yl = (deep || away) ? yhi + 1 : ylo; yl <= yhi; ++yl) {
       for (int xl = xlo; xl <= xhi; ++xl) {
         if (!from_grid_target(c.P, xl, yl)) continue;
         int ci, cj, node[3];
@@ -614,7 +597,7 @@ __global__ __launch_bounds__(NT) void k_adj_from_grid_gather(AdjCtx<T, R> c, R *
       pW += dsum * (-c.dyW / g.h);
     }
   }
-  block_accum3(pA, pW, 0.0, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+  block_accum3<NG>(pA, pW, 0.0, c.part + 3 * (size_t)(slot0 + blockIdx.x));
 }
 
 __global__ __launch_bounds__(NT) void k_adj_reduce(const double *__restrict__ part, int nslots, double *out) {
@@ -639,26 +622,16 @@ __global__ void k_set_counter(int64_t *dk, int64_t k) { *dk = k; }
 
 template <class T, class R>
 void AdjKernels<T, R>::star(const AdjCtx<T, R> &c, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_star<T, R>), dim3(blocks((size_t)4 * c.n_iface, NT)), dim3(NT), 0, s, c);
+  hipLaunchKernelGGL((k_adj_star<T, R>), dim3(blocks((size_t)4 * c.n_iface, NG)), dim3(NG), 0, s, c);
 }
 
 template <class T, class R>
 int AdjKernels<T, R>::refill_slots(const AdjCtx<T, R> &c) {
-  return (int)blocks(c.nnode, NT);
+  return (int)blocks(c.nnode, NG);
 }
 template <class T, class R>
 void AdjKernels<T, R>::refill(const AdjCtx<T, R> &c, int slot0, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_refill<T, R>), dim3(refill_slots(c)), dim3(NT), 0, s, c, slot0);
-}
-
-template <class T, class R>
-int AdjKernels<T, R>::wall_slots(const AdjCtx<T, R> &c) {
-  return (int)blocks(c.n_wall > 0 ? c.n_wall : 1, NT);
-}
-template <class T, class R>
-void AdjKernels<T, R>::wall(const AdjCtx<T, R> &c, const R *Um, R *ub, R uw, double duwA, double duwW, int slot0,
-                            hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_wall<T, R>), dim3(wall_slots(c)), dim3(NT), 0, s, c, Um, ub, uw, duwA, duwW, slot0);
+  hipLaunchKernelGGL((k_adj_refill<T, R>), dim3(refill_slots(c)), dim3(NG), 0, s, c, slot0);
 }
 
 template <class T, class R>
@@ -666,19 +639,19 @@ int AdjKernels<T, R>::substep_slots(const AdjCtx<T, R> &c) {
   return ((c.gg.nux + ATX - 1) / ATX) * ((c.gg.nuy + ATY - 1) / ATY);
 }
 template <class T, class R>
-void AdjKernels<T, R>::substep(const AdjCtx<T, R> &c, const R *Um, const R *ub, R *ub_out, int first, int last,
-                               int slot0, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_substep<T, R>), dim3(substep_slots(c)), dim3(NT), 0, s, c, Um, ub, ub_out, first, last,
-                     slot0);
+void AdjKernels<T, R>::substep(const AdjCtx<T, R> &c, const R *Um, const R *ub, R *ub_out, int m, R uw, double duwA,
+                               double duwW, int first, int last, int slot0, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_substep<T, R>), dim3(substep_slots(c)), dim3(NG), 0, s, c, Um, ub, ub_out, m, uw, duwA,
+                     duwW, first, last, slot0);
 }
 
 template <class T, class R>
 int AdjKernels<T, R>::donor_gather_slots(const AdjCtx<T, R> &c) {
-  return (int)blocks(c.ew, NT) * c.eh;
+  return (int)blocks(c.ew, NG) * c.eh;
 }
 template <class T, class R>
 void AdjKernels<T, R>::donor_gather(const AdjCtx<T, R> &c, int slot0, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_donor_gather<T, R>), dim3(blocks(c.ew, NT), c.eh), dim3(NT), 0, s, c, slot0);
+  hipLaunchKernelGGL((k_adj_donor_gather<T, R>), dim3(blocks(c.ew, NG), c.eh), dim3(NG), 0, s, c, slot0);
 }
 
 template <class T, class R>
@@ -707,11 +680,11 @@ void AdjKernels<T, R>::from_grid(const AdjCtx<T, R> &c, int slot0, hipStream_t s
 
 template <class T, class R>
 int AdjKernels<T, R>::from_grid_gather_slots(const AdjCtx<T, R> &c) {
-  return (int)blocks(c.nnode, NT);
+  return (int)blocks(c.nnode, NG);
 }
 template <class T, class R>
 void AdjKernels<T, R>::from_grid_gather(const AdjCtx<T, R> &c, R *ub, int slot0, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_from_grid_gather<T, R>), dim3(from_grid_gather_slots(c)), dim3(NT), 0, s, c, ub, slot0);
+  hipLaunchKernelGGL((k_adj_from_grid_gather<T, R>), dim3(from_grid_gather_slots(c)), dim3(NG), 0, s, c, ub, slot0);
 }
 
 void adj_reduce(const double *part, int nslots, double *out, hipStream_t s) {

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -191,19 +192,19 @@ class Case final : public CaseBase {
     if (e != hipSuccess) return e; \
   } while (0)
     CaseView<T, R> v = view();
-    if (timing_) ENQ(hipEventRecord(tev_[0], s_main_));
+    if (timing_) ENQ(hipEventRecord(tev_[tslot_][0], s_main_));
     if (has_grid_) {
       // 1. lattice interpolation nodes from the grid at t_k, Eq.(postcollision2_s)
       Kernels<T, R>::lattice_from_grid(v, (const R *)gbuf_[gcur_], s_main_);
-      if (timing_) ENQ(hipEventRecord(tev_[1], s_main_));
+      if (timing_) ENQ(hipEventRecord(tev_[tslot_][1], s_main_));
       if (s_grid_ != s_main_) {
         ENQ(hipEventRecord(ev_fork_, s_main_));
         ENQ(hipStreamWaitEvent(s_grid_, ev_fork_, 0));
       }
       // 2. lattice stream-collide, Eq.(LBE)
-      Kernels<T, R>::stream_collide(v, s_main_, timing_ ? tev_[8] : nullptr, timing_ ? tev_[2] : nullptr);
+      Kernels<T, R>::stream_collide(v, s_main_, timing_ ? tev_[tslot_][8] : nullptr, timing_ ? tev_[tslot_][2] : nullptr);
       // 3.-6. grid path: donors, n sub-steps, refill, force
-      if (timing_) ENQ(hipEventRecord(tev_[3], s_grid_));
+      if (timing_) ENQ(hipEventRecord(tev_[tslot_][3], s_grid_));
       Kernels<T, R>::interface_donors(v, s_grid_);
       int cur = gcur_;
       for (int m = 0; m < d_.n; m += kSubstepBlock) {
@@ -211,21 +212,22 @@ class Case final : public CaseBase {
         Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_);
         cur = 1 - cur;
       }
-      if (timing_) ENQ(hipEventRecord(tev_[4], s_grid_));
+      if (timing_) ENQ(hipEventRecord(tev_[tslot_][4], s_grid_));
       Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
-      if (timing_) ENQ(hipEventRecord(tev_[5], s_grid_));
+      if (timing_) ENQ(hipEventRecord(tev_[tslot_][5], s_grid_));
       Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_);
-      if (timing_) ENQ(hipEventRecord(tev_[6], s_grid_));
+      if (timing_) ENQ(hipEventRecord(tev_[tslot_][6], s_grid_));
       gcur_ = 1 - cur;
       if (s_grid_ != s_main_) {
         ENQ(hipEventRecord(ev_join_, s_grid_));
         ENQ(hipStreamWaitEvent(s_main_, ev_join_, 0));
       }
     } else {
-      if (timing_) ENQ(hipEventRecord(tev_[1], s_main_));
-      Kernels<T, R>::stream_collide(v, s_main_, timing_ ? tev_[8] : nullptr, timing_ ? tev_[2] : nullptr);
+      if (timing_) ENQ(hipEventRecord(tev_[tslot_][1], s_main_));
+      Kernels<T, R>::stream_collide(v, s_main_, timing_ ? tev_[tslot_][8] : nullptr, timing_ ? tev_[tslot_][2] : nullptr);
     }
-    if (timing_) ENQ(hipEventRecord(tev_[7], s_main_));
+    if (timing_) ENQ(hipEventRecord(tev_[tslot_][7], s_main_));
+    if (timing_) ++tslot_;
     ENQ(hipGetLastError());
     std::swap(lat_[0], lat_[1]);
     ++k_;
@@ -293,10 +295,11 @@ class Case final : public CaseBase {
         done += kGraphSteps;
       } else {
         HIPCHK(enqueue_step());
-        if (timing_) HIPCHK(harvest());
+        if (timing_ && tslot_ == kTimingRing) HIPCHK(harvest());
         ++done;
       }
     }
+    if (timing_ && tslot_ > 0) HIPCHK(harvest());
     HIPCHK(hipStreamSynchronize(s_main_));
     if (has_grid_) {
       int flag = 0;
@@ -475,8 +478,10 @@ class Case final : public CaseBase {
 
   int timing(int on) override {
     HIPCHK(hipStreamSynchronize(s_main_));
-    if (on && !tev_[0])
-      for (auto &e : tev_) HIPCHK(hipEventCreate(&e));
+    if (on && !tev_[0][0])
+      for (auto &ring : tev_)
+        for (auto &e : ring) HIPCHK(hipEventCreate(&e));
+    tslot_ = 0;
     for (int i = 0; i < 8; ++i) {
       tms_[i] = 0.0;
       tcount_[i] = 0;
@@ -508,14 +513,51 @@ class Case final : public CaseBase {
     HIPCHK(hipMemsetAsync(alat_[0], 0, lat_r, s_main_));
     HIPCHK(hipMemsetAsync(agrid_[0], 0, grid_r, s_main_));
     HIPCHK(hipMemsetAsync(part_, 0, (size_t)nslots_ * 3 * sizeof(double), s_main_));
+    aslot_ = 0;
     if (timing_) HIPCHK(hipEventRecord(tev_adj_[2], s_main_));
     int lc = 0, gc = 0;
     const int64_t nwin = (n + ckW_ - 1) / ckW_;
-    for (int64_t w = nwin - 1; w >= 0; --w) {
-      const int64_t k0 = w * ckW_, k1 = std::min<int64_t>(n, k0 + ckW_);
-      HIPCHK(recompute(w, k0, k1));
-      for (int64_t k = k1 - 1; k >= k0; --k) HIPCHK(reverse_step(k, k0, dJ, lc, gc));
+    auto tape_of = [&](int64_t w) { return (int)(w % ntapes_); };
+    auto window = [&](int64_t w, int64_t &k0, int64_t &k1) {
+      k0 = w * ckW_;
+      k1 = std::min<int64_t>(n, k0 + ckW_);
+    };
+    // the recompute of window w-1 (stream s_aux_) runs while window w is
+    // reversed (s_main_); a tape is rewritten only after its reverse ended
+    HIPCHK(hipEventRecord(ev_rev_[0], s_main_));
+    HIPCHK(hipEventRecord(ev_rev_[1], s_main_));
+    HIPCHK(hipStreamWaitEvent(s_aux_, ev_rev_[0], 0));
+    {
+      int64_t k0, k1;
+      window(nwin - 1, k0, k1);
+      HIPCHK(recompute(tape_of(nwin - 1), nwin - 1, k0, k1, s_aux_));
+      HIPCHK(hipEventRecord(ev_rec_[tape_of(nwin - 1)], s_aux_));
     }
+    for (int64_t w = nwin - 1; w >= 0; --w) {
+      const int t = tape_of(w);
+      int64_t k0, k1;
+      if (w > 0 && ntapes_ == 2) {
+        const int tp = tape_of(w - 1);
+        window(w - 1, k0, k1);
+        HIPCHK(hipStreamWaitEvent(s_aux_, ev_rev_[tp], 0));
+        HIPCHK(recompute(tp, w - 1, k0, k1, s_aux_));
+        HIPCHK(hipEventRecord(ev_rec_[tp], s_aux_));
+      }
+      window(w, k0, k1);
+      HIPCHK(hipStreamWaitEvent(s_main_, ev_rec_[t], 0));
+      for (int64_t k = k1 - 1; k >= k0; --k) HIPCHK(reverse_step(t, k, k0, dJ, lc, gc));
+      HIPCHK(hipEventRecord(ev_rev_[t], s_main_));
+      if (w > 0 && ntapes_ == 1) {
+        window(w - 1, k0, k1);
+        HIPCHK(hipStreamWaitEvent(s_aux_, ev_rev_[t], 0));
+        HIPCHK(recompute(t, w - 1, k0, k1, s_aux_));
+        HIPCHK(hipEventRecord(ev_rec_[t], s_aux_));
+      }
+    }
+    // restore the forward's step counter after the last recompute
+    HIPCHK(hipStreamWaitEvent(s_main_, ev_rec_[0], 0));
+    if (ntapes_ == 2) HIPCHK(hipStreamWaitEvent(s_main_, ev_rec_[1], 0));
+    if (timing_) HIPCHK(harvest_adjoint());
     adj_reduce(part_, nslots_, grad_dev_, s_main_);
     set_step_counter(dk_, k_, s_main_);
     HIPCHK(hipGetLastError());
@@ -552,18 +594,28 @@ class Case final : public CaseBase {
     return e;
   }
   void release() {
+    if (s_aux_) (void)hipStreamSynchronize(s_aux_);
     if (s_main_) (void)hipStreamSynchronize(s_main_);
     if (s_grid_ && s_grid_ != s_main_) (void)hipStreamSynchronize(s_grid_);
     for (auto &g : gexec_)
       if (g) (void)hipGraphExecDestroy(g);
     for (void *p : owned_) (void)hipFree(p);
     owned_.clear();
-    for (auto &e : tev_)
-      if (e) (void)hipEventDestroy(e);
+    for (auto &ring : tev_)
+      for (auto &e : ring)
+        if (e) (void)hipEventDestroy(e);
     for (auto &e : tev_adj_)
       if (e) (void)hipEventDestroy(e);
+    for (auto &pr : tev_adj_ring_)
+      for (auto &e : pr)
+        if (e) (void)hipEventDestroy(e);
     if (ev_fork_) (void)hipEventDestroy(ev_fork_);
     if (ev_join_) (void)hipEventDestroy(ev_join_);
+    for (auto &e : ev_rec_)
+      if (e) (void)hipEventDestroy(e);
+    for (auto &e : ev_rev_)
+      if (e) (void)hipEventDestroy(e);
+    if (s_aux_) (void)hipStreamDestroy(s_aux_);
     if (s_grid_ && s_grid_ != s_main_) (void)hipStreamDestroy(s_grid_);
     if (s_main_) (void)hipStreamDestroy(s_main_);
   }
@@ -645,32 +697,55 @@ class Case final : public CaseBase {
     return v;
   }
 
-  hipError_t harvest() {
-    hipError_t e = hipEventSynchronize(tev_[7]);
+  hipError_t harvest_adjoint() {
+    if (aslot_ == 0) return hipSuccess;
+    hipError_t e = hipEventSynchronize(tev_adj_ring_[aslot_ - 1][1]);
     if (e != hipSuccess) return e;
-    auto add = [&](int id, hipEvent_t a, hipEvent_t b) {
+    for (int i = 0; i < aslot_; ++i) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
-        tms_[id] += ms;
-        tcount_[id] += 1;
+      if (hipEventElapsedTime(&ms, tev_adj_ring_[i][0], tev_adj_ring_[i][1]) == hipSuccess) {
+        tms_[HLBM_K_ADJ_STREAM_COLLIDE] += ms;
+        tcount_[HLBM_K_ADJ_STREAM_COLLIDE] += 1;
       }
-    };
-    add(HLBM_K_STREAM_COLLIDE, tev_[8], tev_[2]);
-    if (has_grid_) {
-      add(HLBM_K_LATTICE_FROM_GRID, tev_[0], tev_[1]);
-      add(HLBM_K_GRID_SUBSTEPS, tev_[3], tev_[4]);
-      add(HLBM_K_REFILL, tev_[4], tev_[5]);
-      add(HLBM_K_FORCE, tev_[5], tev_[6]);
     }
-    add(HLBM_K_STEP, tev_[0], tev_[7]);
+    aslot_ = 0;
     return hipSuccess;
   }
 
+  // Accumulates the timings of the steps recorded in the event ring (the
+  // steps ran back to back; only here does the host wait for them).
+  hipError_t harvest() {
+    hipError_t e = hipEventSynchronize(tev_[tslot_ - 1][7]);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < tslot_; ++i) {
+      hipEvent_t *t = tev_[i];
+      auto add = [&](int id, hipEvent_t a, hipEvent_t b) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+          tms_[id] += ms;
+          tcount_[id] += 1;
+        }
+      };
+      add(HLBM_K_STREAM_COLLIDE, t[8], t[2]);
+      if (has_grid_) {
+        add(HLBM_K_LATTICE_FROM_GRID, t[0], t[1]);
+        add(HLBM_K_GRID_SUBSTEPS, t[3], t[4]);
+        add(HLBM_K_REFILL, t[4], t[5]);
+        add(HLBM_K_FORCE, t[5], t[6]);
+      }
+      add(HLBM_K_STEP, t[0], t[7]);
+    }
+    tslot_ = 0;
+    return hipSuccess;
+  }
 
   // ---- adjoint workspace ------------------------------------------------------
   size_t tape_grid_elems() const { return 9 * (size_t)grid_.nnode; }
-  T *tape_lat(int64_t j) const { return (T *)tape_lat_ + (size_t)j * 9 * plane_; }
-  R *tape_grid(int64_t j, int m) const { return tape_grid_ + ((size_t)j * (d_.n + 1) + m) * tape_grid_elems(); }
+  T *tape_lat(int t, int64_t j) const { return (T *)tape_lat_[t] + (size_t)j * 9 * plane_; }
+  R *tape_grid(int t, int64_t j, int m) const {
+    return tape_grid_[t] + ((size_t)j * (d_.n + 1) + m) * tape_grid_elems();
+  }
+  R *tape_wall(int t, int64_t j) const { return wtape_[t] + (size_t)j * d_.n * 3 * std::max(n_wall_, 1); }
 
   // Allocates the tape and the adjoint buffers on first use and fills the
   // step-independent part of the kernels' context.
@@ -696,10 +771,26 @@ class Case final : public CaseBase {
     const size_t tape_grid_bytes = ((size_t)ckW_ * (d_.n + 1) + 1) * tape_grid_elems() * sizeof(R);
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
-    const size_t need = tape_lat_bytes + tape_grid_bytes + 2 * 9 * plane_ * sizeof(R) + ((size_t)64 << 20);
-    if (need > free_b) return fail(HLBM_E_NOMEM, "adjoint tape does not fit in device memory: use a smaller ckpt_every");
-    HIPCHK(alloc(&tape_lat_, tape_lat_bytes));
-    HIPCHK(alloc(&tape_grid_, tape_grid_bytes));
+    n_wall_ = (int)std::count(grid_.type.begin(), grid_.type.end(), (int)NODE_WALL);
+    const size_t tape_wall_bytes = (size_t)ckW_ * d_.n * 3 * std::max(n_wall_, 1) * sizeof(R);
+    const size_t one = tape_lat_bytes + tape_grid_bytes + tape_wall_bytes;
+    const size_t fixed = 2 * 9 * plane_ * sizeof(R) + ((size_t)256 << 20);
+    // two tapes let the recompute of the previous window run on a second
+    // stream while this window is reversed; one tape runs them in turn
+    if (one + fixed > free_b) return fail(HLBM_E_NOMEM, "adjoint tape does not fit in device memory: use a smaller ckpt_every");
+    ntapes_ = (2 * one + fixed <= free_b && !std::getenv("HLBM_ONE_TAPE")) ? 2 : 1;
+    for (int t = 0; t < ntapes_; ++t) {
+      HIPCHK(alloc(&tape_lat_[t], tape_lat_bytes));
+      HIPCHK(alloc(&tape_grid_[t], tape_grid_bytes));
+      HIPCHK(alloc(&wtape_[t], tape_wall_bytes));
+    }
+    HIPCHK(alloc(&astar_f_, 9 * (size_t)N * sizeof(R)));
+    HIPCHK(alloc(&astar_n_, 9 * (size_t)N * sizeof(R)));
+    HIPCHK(hipStreamCreateWithFlags(&s_aux_, hipStreamNonBlocking));
+    for (int t = 0; t < 2; ++t) {
+      HIPCHK(hipEventCreateWithFlags(&ev_rec_[t], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ev_rev_[t], hipEventDisableTiming));
+    }
     for (int i = 0; i < 2; ++i) {
       HIPCHK(alloc(&alat_[i], 9 * plane_ * sizeof(R)));
       HIPCHK(alloc(&agrid_[i], 9 * (size_t)N * sizeof(R)));
@@ -728,6 +819,57 @@ class Case final : public CaseBase {
       }
     HIPCHK(upload(&wall_nodes_, wn.data(), wn.size() * sizeof(int)));
     HIPCHK(upload(&wall_nrm_, nrm.data(), nrm.size() * sizeof(double)));
+    std::vector<int> widx(N, -1);
+    for (size_t w = 0; w < wn.size(); ++w) widx[wn[w]] = (int)w;
+    std::vector<unsigned char> ntype(N);
+    for (int p = 0; p < N; ++p) ntype[p] = (unsigned char)grid_.type[p];
+    HIPCHK(upload(&widx_, widx.data(), widx.size() * sizeof(int)));
+    HIPCHK(upload(&ntype_, ntype.data(), ntype.size()));
+    n_wall_ = (int)wn.size();
+    // transposed stencils: slot s of node q holds what its neighbour at slot
+    // s applies to q (the neighbour's slot 8 - s), deduplicated into classes
+    {
+      std::vector<AdjClass<double>> atab;
+      std::vector<int> acls(N);
+      std::map<std::string, int> seen;
+      for (int q = 0; q < N; ++q) {
+        const int i = q % cfg_.nux, j = q / cfg_.nux;
+        AdjClass<double> a;
+        std::memset(&a, 0, sizeof(a));
+        a.type = grid_.type[q];
+        for (int s = 0; s < NSLOT; ++s) {
+          const int ii = i + s % 3 - 1, jj = j + s / 3 - 1;
+          if (ii < 0 || jj < 0 || ii >= cfg_.nux || jj >= cfg_.nuy) continue;
+          const int p = jj * cfg_.nux + ii;
+          const GridClass<double> &cp = grid_.classes[grid_.cls[p]];
+          a.Gx[s] = cp.Gx[NSLOT - 1 - s];
+          a.Gy[s] = cp.Gy[NSLOT - 1 - s];
+          a.C[s] = cp.C[NSLOT - 1 - s];
+          if (grid_.type[p] == NODE_INTERFACE && grid_.type[q] == NODE_INTERFACE) a.star |= 1 << s;
+        }
+        const std::string key((const char *)&a, sizeof(a));
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+          it = seen.emplace(key, (int)atab.size()).first;
+          atab.push_back(a);
+        }
+        acls[q] = it->second;
+      }
+      std::vector<AdjClass<R>> at(atab.size());
+      for (size_t k = 0; k < atab.size(); ++k) {
+        std::memset(&at[k], 0, sizeof(at[k]));
+        for (int s = 0; s < NSLOT; ++s) {
+          at[k].Gx[s] = (R)atab[k].Gx[s];
+          at[k].Gy[s] = (R)atab[k].Gy[s];
+          at[k].C[s] = (R)atab[k].C[s];
+        }
+        at[k].star = atab[k].star;
+        at[k].type = atab[k].type;
+      }
+      HIPCHK(upload(&atab_, at.data(), at.size() * sizeof(AdjClass<R>)));
+      HIPCHK(upload(&acls_, acls.data(), acls.size() * sizeof(int)));
+      n_adj_classes_ = (int)at.size();
+    }
     AdjCtx<T, R> &c = actx_;
     std::memset(&c, 0, sizeof(c));
     c.nx = cfg_.nx;
@@ -750,9 +892,13 @@ class Case final : public CaseBase {
     c.tab = tab_;
     c.iface = iface_;
     c.wall_nodes = wall_nodes_;
+    c.widx = widx_;
+    c.ntype = ntype_;
+    c.acls = acls_;
+    c.atab = atab_;
     c.wall_nrm = wall_nrm_;
-    c.star_f = star_f_;
-    c.star_n = star_n_;
+    c.star_f = astar_f_;
+    c.star_n = astar_n_;
     c.M2 = M2_;
     c.sbf = sbf_;
     c.sbn = sbn_;
@@ -770,8 +916,7 @@ class Case final : public CaseBase {
     c.eh = eh_;
     using AK = AdjKernels<T, R>;
     slot_refill_ = 0;
-    slot_wall_ = slot_refill_ + AK::refill_slots(c);
-    slot_sub_ = slot_wall_ + AK::wall_slots(c);
+    slot_sub_ = slot_refill_ + AK::refill_slots(c);
     slot_eg_ = slot_sub_ + AK::substep_slots(c);
     slot_sc_ = slot_eg_ + AK::donor_gather_slots(c);
     slot_fg_ = slot_sc_ + AK::stream_collide_slots(c);
@@ -781,42 +926,52 @@ class Case final : public CaseBase {
     c.part = part_;
     for (auto &e : tev_adj_)
       if (!e) HIPCHK(hipEventCreate(&e));
+    for (auto &pr : tev_adj_ring_)
+      for (auto &e : pr)
+        if (!e) HIPCHK(hipEventCreate(&e));
     adj_ready_ = true;
     return HLBM_OK;
   }
 
-  // Forward steps k0 .. k1-1 from checkpoint w, keeping every lattice after
-  // its grid-to-lattice writes and every grid state of every sub-step.
-  hipError_t recompute(int64_t w, int64_t k0, int64_t k1) {
-    hipError_t e = hipMemcpyAsync(tape_lat(0), (char *)ck_lat_ + (size_t)w * ck_lat_bytes_, ck_lat_bytes_,
-                                  hipMemcpyDeviceToDevice, s_main_);
+  // Forward steps k0 .. k1-1 from checkpoint w into tape t on stream st,
+  // keeping every lattice after its grid-to-lattice writes, every grid state
+  // of every sub-step and the wall moments the adjoint needs.
+  hipError_t recompute(int t, int64_t w, int64_t k0, int64_t k1, hipStream_t st) {
+    if (t < 0 || t >= ntapes_ || w < 0 || w >= nck_ || k1 - k0 > ckW_) return hipErrorInvalidValue;
+    hipError_t e = hipMemcpyAsync(tape_lat(t, 0), (char *)ck_lat_ + (size_t)w * ck_lat_bytes_, ck_lat_bytes_,
+                                  hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(tape_grid(0, 0), (char *)ck_grid_ + (size_t)w * ck_grid_bytes_, ck_grid_bytes_,
-                       hipMemcpyDeviceToDevice, s_main_);
+    e = hipMemcpyAsync(tape_grid(t, 0, 0), (char *)ck_grid_ + (size_t)w * ck_grid_bytes_, ck_grid_bytes_,
+                       hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
     for (int64_t k = k0; k < k1; ++k) {
       const int64_t j = k - k0;
-      set_step_counter(dk_, k, s_main_);
+      set_step_counter(dk_, k, st);
       CaseView<T, R> v = view();
-      v.A = tape_lat(j);
-      v.B = tape_lat(j + 1);
+      v.A = tape_lat(t, j);
+      v.B = tape_lat(t, j + 1);
       v.counts = counts_scratch_;
-      Kernels<T, R>::lattice_from_grid(v, tape_grid(j, 0), s_main_);
-      Kernels<T, R>::stream_collide(v, s_main_);
-      Kernels<T, R>::interface_donors(v, s_main_);
-      for (int m = 0; m < d_.n; ++m) Kernels<T, R>::grid_substeps(v, tape_grid(j, m), tape_grid(j, m + 1), m, 1, s_main_);
-      Kernels<T, R>::refill(v, tape_grid(j, d_.n), tape_grid(j + 1, 0), s_main_);
+      Kernels<T, R>::lattice_from_grid(v, tape_grid(t, j, 0), st);
+      Kernels<T, R>::stream_collide(v, st);
+      Kernels<T, R>::interface_donors(v, st);
+      for (int m = 0; m < d_.n; m += kSubstepBlock) {
+        const int cnt = std::min(kSubstepBlock, d_.n - m);
+        Kernels<T, R>::grid_substeps(v, tape_grid(t, j, m), tape_grid(t, j, m + cnt), m, cnt, st, tape_grid(t, j, 0),
+                                     tape_wall(t, j), widx_, std::max(n_wall_, 1));
+      }
+      Kernels<T, R>::refill(v, tape_grid(t, j, d_.n), tape_grid(t, j + 1, 0), st);
     }
     return hipGetLastError();
   }
 
   // One structured step backwards: (alat_[lc], agrid_[gc]) hold the adjoints
   // of the lattice and grid at t_{k+1} on entry and of those at t_k on exit.
-  hipError_t reverse_step(int64_t k, int64_t k0, const double *dJ, int &lc, int &gc) {
+  hipError_t reverse_step(int tape, int64_t k, int64_t k0, const double *dJ, int &lc, int &gc) {
     using AK = AdjKernels<T, R>;
     const int64_t j = k - k0;
+    if (tape < 0 || tape >= ntapes_ || j < 0 || j >= ckW_) return hipErrorInvalidValue;
     AdjCtx<T, R> c = actx_;
-    c.Lt = tape_lat(j);
+    c.Lt = tape_lat(tape, j);
     c.Lb_next = alat_[lc];
     c.Lb = alat_[1 - lc];
     c.P = P_host_[k];
@@ -827,25 +982,26 @@ class Case final : public CaseBase {
     c.dyW1 = A * (double)(k + 1) * std::cos(om * (double)(k + 1));
     c.wfx = dJ[2 * k];
     c.wfy = dJ[2 * k + 1];
-    c.U0 = tape_grid(j, 0);
-    c.Un = tape_grid(j, d_.n);
+    c.U0 = tape_grid(tape, j, 0);
+    c.Un = tape_grid(tape, j, d_.n);
+    c.wt = tape_wall(tape, j);
     c.Ub_next = agrid_[gc];
     c.Ubn = agrid_[1 - gc];
     AK::star(c, s_main_);
     AK::refill(c, slot_refill_, s_main_);
     int gin = 1 - gc;  // holds the adjoint of the grid after sub-step m+1
     for (int m = d_.n - 1; m >= 0; --m) {
-      const double t = (double)k + (double)(m + 1) / (double)d_.n;
-      const R uw = (R)(A * om * std::cos(om * t));
-      const double duwA = om * std::cos(om * t);
-      const double duwW = A * std::cos(om * t) - A * om * t * std::sin(om * t);
-      AK::wall(c, tape_grid(j, m), agrid_[gin], uw, duwA, duwW, slot_wall_, s_main_);
-      AK::substep(c, tape_grid(j, m), agrid_[gin], agrid_[1 - gin], m == d_.n - 1, m == 0, slot_sub_, s_main_);
+      const double tm = (double)k + (double)(m + 1) / (double)d_.n;
+      const R uw = (R)(A * om * std::cos(om * tm));
+      const double duwA = om * std::cos(om * tm);
+      const double duwW = A * std::cos(om * tm) - A * om * tm * std::sin(om * tm);
+      AK::substep(c, tape_grid(tape, j, m), agrid_[gin], agrid_[1 - gin], m, uw, duwA, duwW, m == d_.n - 1, m == 0,
+                  slot_sub_, s_main_);
       gin = 1 - gin;
     }
     AK::donor_gather(c, slot_eg_, s_main_);
     if (timing_) {
-      AK::stream_collide(c, slot_sc_, s_main_, tev_adj_[0], tev_adj_[1]);
+      AK::stream_collide(c, slot_sc_, s_main_, tev_adj_ring_[aslot_][0], tev_adj_ring_[aslot_][1]);
     } else {
       AK::stream_collide(c, slot_sc_, s_main_);
     }
@@ -853,14 +1009,9 @@ class Case final : public CaseBase {
     AK::from_grid_gather(c, agrid_[gin], slot_fgg_, s_main_);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (timing_) {
-      e = hipEventSynchronize(tev_adj_[1]);
+    if (timing_ && ++aslot_ == kTimingRing) {
+      e = harvest_adjoint();
       if (e != hipSuccess) return e;
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, tev_adj_[0], tev_adj_[1]) == hipSuccess) {
-        tms_[HLBM_K_ADJ_STREAM_COLLIDE] += ms;
-        tcount_[HLBM_K_ADJ_STREAM_COLLIDE] += 1;
-      }
     }
     lc = 1 - lc;
     gc = gin;
@@ -875,7 +1026,9 @@ class Case final : public CaseBase {
   HostGrid grid_;
   hipStream_t s_main_ = nullptr, s_grid_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
-  hipEvent_t tev_[9] = {};
+  static constexpr int kTimingRing = 64;  // steps recorded between harvests
+  hipEvent_t tev_[kTimingRing][9] = {};
+  int tslot_ = 0;
   bool timing_ = false;
   double tms_[8] = {};
   int64_t tcount_[8] = {};
@@ -908,19 +1061,29 @@ class Case final : public CaseBase {
   // adjoint
   bool adj_ready_ = false, adj_done_ = false;
   AdjCtx<T, R> actx_{};
-  void *tape_lat_ = nullptr;
-  R *tape_grid_ = nullptr;
+  void *tape_lat_[2] = {nullptr, nullptr};
+  R *tape_grid_[2] = {nullptr, nullptr};
+  int ntapes_ = 1;
+  hipStream_t s_aux_ = nullptr;
+  hipEvent_t ev_rec_[2] = {}, ev_rev_[2] = {};
+  R *astar_f_ = nullptr, *astar_n_ = nullptr;
   R *alat_[2] = {nullptr, nullptr}, *agrid_[2] = {nullptr, nullptr};
   int adj_lc_ = 0, adj_gc_ = 0;
   R *M2_ = nullptr, *sbf_ = nullptr, *sbn_ = nullptr, *Z1_ = nullptr, *Z2_ = nullptr, *Z3_ = nullptr, *E_ = nullptr;
   unsigned char *zf_ = nullptr;
-  int *wall_nodes_ = nullptr;
+  int *wall_nodes_ = nullptr, *widx_ = nullptr, *acls_ = nullptr;
+  unsigned char *ntype_ = nullptr;
+  AdjClass<R> *atab_ = nullptr;
+  R *wtape_[2] = {nullptr, nullptr};
+  int n_wall_ = 0, n_adj_classes_ = 0;
   double *wall_nrm_ = nullptr, *part_ = nullptr, *grad_dev_ = nullptr;
   unsigned long long *counts_scratch_ = nullptr;
   int ex0_ = 0, ey0_ = 0, ew_ = 1, eh_ = 1;
-  int slot_refill_ = 0, slot_wall_ = 0, slot_sub_ = 0, slot_eg_ = 0, slot_sc_ = 0, slot_fg_ = 0, slot_fgg_ = 0,
+  int slot_refill_ = 0, slot_sub_ = 0, slot_eg_ = 0, slot_sc_ = 0, slot_fg_ = 0, slot_fgg_ = 0,
       nslots_ = 0;
   hipEvent_t tev_adj_[4] = {};
+  hipEvent_t tev_adj_ring_[kTimingRing][2] = {};
+  int aslot_ = 0;
 };
 
 // Configuration checks shared by all storage types (mirrors the geometric

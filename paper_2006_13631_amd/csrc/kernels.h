@@ -51,8 +51,13 @@ struct Kernels {
                              hipEvent_t stop = nullptr);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
   static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
-  // sub-steps m0 .. m0+count-1 (count <= kSubstepBlock) in one launch
-  static void grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s);
+  // sub-steps m0 .. m0+count-1 (count <= kSubstepBlock) in one launch; with
+  // a tape, the grid after sub-step m (m0 < m < m0+count) is also stored at
+  // tape + m * 9 * nnode, and the moments (rho, u_x, u_y) of every wall node
+  // before its velocity is imposed in sub-step m at wtape + (3 m + c) nwall
+  // + widx[node]
+  static void grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
+                            R *tape = nullptr, R *wtape = nullptr, const int *widx = nullptr, int nwall = 0);
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
   static void force(const CaseView<T, R> &v, const R *f, hipStream_t s);
   static void lattice_to_f64(const T *src, double *dst, size_t plane, hipStream_t s);

@@ -162,7 +162,8 @@ template <class R, int H>
 __global__ __launch_bounds__(substep_threads<R>()) void k_grid_substeps(
     const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
     const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int ntiles,
-    R dt, R dt_tau, const R *__restrict__ uw, const int64_t *__restrict__ dk, int n_sub, int m0, int count) {
+    R dt, R dt_tau, const R *__restrict__ uw, const int64_t *__restrict__ dk, int n_sub, int m0, int count,
+    R *__restrict__ tape, R *__restrict__ wtape, const int *__restrict__ widx, int nwall) {
   using G = Region<H>;
   constexpr int RX = G::RX, RN = G::RN;
   constexpr int NT = substep_threads<R>(), PER = (RN + NT - 1) / NT;
@@ -284,6 +285,14 @@ __global__ __launch_bounds__(substep_threads<R>()) void k_grid_substeps(
         // wall nodes: impose the lamina velocity, keep rho and f^neq
         R e[9], ew[9], r, vx, vy;
         moments<R>(out[u], r, vx, vy);
+        if (wtape && rx >= H && rx < H + TX && ry >= H && ry < H + TY) {
+          // taped for the adjoint: the moments before the velocity is imposed
+          R *wt = wtape + (size_t)(m0 + sub) * 3 * nwall;
+          const int w = widx[(size_t)gj * nux + gi];
+          wt[w] = r;
+          wt[nwall + w] = vx;
+          wt[2 * nwall + w] = vy;
+        }
         equilibrium<R>(r, vx, vy, e);
         equilibrium<R>(r, R(0), uw_now, ew);
 #pragma unroll
@@ -305,6 +314,19 @@ __global__ __launch_bounds__(substep_threads<R>()) void k_grid_substeps(
       }
     }
     __syncthreads();
+    // the tile is exact after every sub-step: a tape keeps the intermediate ones
+    if (tape && sub + 1 < count) {
+      R *dst = tape + (size_t)(m0 + sub + 1) * 9 * N;
+      for (int jn = threadIdx.x; jn < TX * TY; jn += NT) {
+        const int rx = H + jn % TX, ry = H + jn / TX;
+        const int gi = x0 + rx, gj = y0 + ry;
+        if (gi >= nux || gj >= nuy) continue;
+        const int ci = ry * RX + rx;
+        const size_t p = (size_t)gj * nux + gi;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dst[q * N + p] = sl[ci * NS + q];
+      }
+    }
   }
 
   // the tile is exact: write it back
@@ -490,12 +512,13 @@ void Kernels<T, R>::interface_donors(const CaseView<T, R> &v, hipStream_t s) {
 }
 
 template <class T, class R>
-void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s) {
+void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
+                                  R *tape, R *wtape, const int *widx, int nwall) {
   const int tiles_x = (v.nux + TX - 1) / TX, tiles_y = (v.nuy + TY - 1) / TY;
   hipLaunchKernelGGL((k_grid_substeps<R, kSubstepBlock>), dim3(tiles_x * tiles_y), dim3(substep_threads<R>()),
                      (substeps_lds_bytes<R, kSubstepBlock>()), s, f, fout, (const R *)v.star_f, (const R *)v.star_n,
                      v.cls, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw,
-                     (const int64_t *)v.dk, v.n_sub, m0, count);
+                     (const int64_t *)v.dk, v.n_sub, m0, count, tape, wtape, widx, nwall);
 }
 
 template <class T, class R>
