@@ -103,17 +103,41 @@ typedef struct hlbm_info {
   double y;              /* lamina offset y(t_k)                         */
   int64_t n_type1, n_type2, n_type3; /* refill counts, summed over steps */
   int64_t lattice_bytes; /* device bytes of one lattice buffer          */
+  int32_t status;        /* HLBM_STATUS_*                               */
+  int32_t reserved;
 } hlbm_info;
+
+#define HLBM_STATUS_RUNNING 0  /* steps left                                  */
+#define HLBM_STATUS_DONE 1     /* max_steps reached                            */
+#define HLBM_STATUS_UNSTABLE 2 /* a non-finite force appeared; the case stopped */
+
+/* Schedule of a batched handle (ncases > 1), chosen by hlbm_tune. None of
+ * the choices changes any result: every case computes the same bits. */
+typedef struct hlbm_tuning {
+  int32_t steps_per_graph; /* structured steps captured in one HIP graph     */
+  int32_t lattice_threads; /* workgroup size of the batched stream-collide   */
+  int32_t substep_threads; /* workgroup size of the batched grid sub-steps   */
+  int32_t order;           /* 0: work lists case by case; 1: dealt to the 8
+                              XCDs in contiguous chunks                     */
+  double ms_per_step;      /* measured for the chosen schedule (output)      */
+} hlbm_tuning;
 
 typedef struct hlbm hlbm_t;
 
 /* Create a case: validate the configuration, build the grid and its
  * finite-volume matrices S_ik, C_ik (median-dual control volumes, Eq.(ulbe)),
  * allocate device buffers and set both grids to rest (f = w_i).
- * ncases must be 1. Errors: HLBM_E_ARG (invalid configuration: tau <= 1/2,
- * Delta t_u >= 2 tau_u, grid or its motion leaving the lattice, lamina not
- * inside the fictitious rectangle, |A omega| >= 1), HLBM_E_NOMEM, HLBM_E_HIP.
- * On error *out is set to NULL. */
+ * ncases > 1 creates a batch: cfg points to ncases configurations (sizes,
+ * KC, beta, tau, n_sub may all differ; storage must be the same, ckpt_every
+ * 0, every case with a grid), advanced together by case-batched kernels.
+ * In a batch, case_id selects the case in hlbm_force, hlbm_info_get and
+ * hlbm_get/set_state; hlbm_step advances every running case and lets each
+ * stop at its own max_steps (or when its force becomes non-finite, status
+ * HLBM_STATUS_UNSTABLE) instead of failing. Errors: HLBM_E_ARG (invalid
+ * configuration: tau <= 1/2, Delta t_u >= 2 tau_u, grid or its motion
+ * leaving the lattice, lamina not inside the fictitious rectangle,
+ * |A omega| >= 1; in a batch, mixed storage or ckpt_every != 0),
+ * HLBM_E_NOMEM, HLBM_E_HIP. On error *out is set to NULL. */
 int hlbm_create(const hlbm_config *cfg, int32_t ncases, hlbm_t **out);
 
 /* Advance nsteps structured steps t_k -> t_{k+1} (Sec. HLBM and Sec. Refill
@@ -190,6 +214,15 @@ int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
 #define HLBM_K_ADJOINT 7        /* whole hlbm_adjoint call (count = steps)     */
 int hlbm_timing(hlbm_t *h, int32_t on);
 int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count);
+
+/* Autotuner of a batched handle: before its first step, time every
+ * candidate schedule (steps per graph 4/8/16, lattice workgroup 128/256,
+ * sub-step workgroup, work-list order) for trial_steps steps of the whole
+ * batch, keep the fastest and restore the initial state. trial_steps = 0
+ * applies *t as given instead. *t receives the schedule in use. Errors:
+ * HLBM_E_UNSUPPORTED (single case), HLBM_E_STATE (steps already taken),
+ * HLBM_E_ARG (invalid schedule). */
+int hlbm_tune(hlbm_t *h, int32_t trial_steps, hlbm_tuning *t);
 
 /* Release the device memory and streams of the handle (NULL is a no-op). */
 void hlbm_destroy(hlbm_t *h);

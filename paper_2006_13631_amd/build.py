@@ -1,8 +1,10 @@
 """Build ``libhlbm.so`` (gfx950) in-tree with hipcc.
 
-Host code is built without contraction of a*b+c (the FP64 scalars that decide
-node classes and donor cells must follow their written formulas); device
-kernels may use FMA. Packed FP32 instructions are disabled.
+Host code and the forward kernels are built without contraction of a*b+c
+(the FP64 scalars that decide node classes and donor cells must follow their
+written formulas, and a forward expression must round identically in every
+kernel that inlines it); the adjoint kernels may use FMA. Packed FP32
+instructions are disabled.
 """
 from __future__ import annotations
 
@@ -31,7 +33,10 @@ def build(verbose: bool = False) -> str:
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        contract = "-ffp-contract=fast" if src in ("kernels.hip", "adjoint.hip") else "-ffp-contract=off"
+        # forward kernels: no contraction of a*b+c, so an expression rounds the
+        # same wherever it is inlined (single-case and case-batched kernels
+        # compute identical bits); the adjoint kernels may contract
+        contract = "-ffp-contract=fast" if src == "adjoint.hip" else "-ffp-contract=off"
         cmd = [hipcc(), "-x", "hip", f"--offload-arch={ARCH}",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                *common, contract, "-c", os.path.join(CSRC, src), "-o", obj]

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -70,6 +71,14 @@ class CaseBase {
   virtual int timing(int on) = 0;
   virtual int timing_get(int kernel, double *ms, int64_t *count) = 0;
   virtual int adjoint(const double *dJ, int64_t n, double grad[3]) = 0;
+  // case `id` of a handle (the handle itself for a single case)
+  virtual CaseBase *sub(int id) { return id == 0 ? this : nullptr; }
+  virtual int tune(int trial_steps, hlbm_tuning *t) {
+    (void)trial_steps;
+    (void)t;
+    err = "tuning applies to batched handles (ncases > 1)";
+    return HLBM_E_UNSUPPORTED;
+  }
   std::string err;
 };
 
@@ -428,6 +437,11 @@ class Case final : public CaseBase {
     o->step = k_;
     o->y = d_.A * std::sin(d_.omega * (double)k_);
     o->lattice_bytes = (int64_t)(9 * plane_ * sizeof(T));
+    {
+      int flag = 0;
+      if (has_grid_) HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
+      o->status = flag ? HLBM_STATUS_UNSTABLE : (has_grid_ && k_ >= cfg_.max_steps ? HLBM_STATUS_DONE : HLBM_STATUS_RUNNING);
+    }
     if (has_grid_) {
       o->nnode = grid_.nnode;
       o->ntri = grid_.ntri;
@@ -694,8 +708,45 @@ class Case final : public CaseBase {
       v.k2_w = k2_w_;
       v.k2_h = k2_h_;
     }
+    v.lat[0] = (T *)lat_base_;
+    v.lat[1] = (T *)(lat_base_ == lat_[0] ? lat_[1] : lat_[0]);
+    v.grid[0] = (R *)gbuf_[0];
+    v.grid[1] = (R *)gbuf_[1];
+    v.max_steps = cfg_.max_steps;
     return v;
   }
+
+ public:
+  // ---- hooks for a batch that advances this case with case-batched kernels
+  CaseView<T, R> batched_view() const { return view(); }
+  int64_t steps_taken() const { return k_; }
+  int64_t max_steps() const { return cfg_.max_steps; }
+  int n_sub() const { return d_.n; }
+  int64_t *step_counter() const { return dk_; }
+  int *flag() const { return flag_; }
+  // host bookkeeping after m steps done on the device by batched kernels
+  void advance_host(int64_t m) {
+    const int launches = (d_.n + kSubstepBlock - 1) / kSubstepBlock;
+    if (m & 1) {
+      std::swap(lat_[0], lat_[1]);
+      if ((launches + 1) & 1) gcur_ = 1 - gcur_;
+    }
+    k_ += m;
+  }
+  // every lattice and grid buffer, for snapshots
+  void buffers(void **lat, void **grid, size_t *lat_bytes, size_t *grid_bytes) const {
+    lat[0] = lat_[0];
+    lat[1] = lat_[1];
+    grid[0] = gbuf_[0];
+    grid[1] = gbuf_[1];
+    *lat_bytes = 9 * plane_ * sizeof(T);
+    *grid_bytes = has_grid_ ? 9 * (size_t)grid_.nnode * sizeof(R) : 0;
+  }
+  unsigned long long *refill_counters() const { return counts_; }
+  int64_t lattice_nodes() const { return (int64_t)plane_; }
+  int64_t grid_nodes() const { return has_grid_ ? grid_.nnode : 0; }
+
+ private:
 
   hipError_t harvest_adjoint() {
     if (aslot_ == 0) return hipSuccess;
@@ -1120,6 +1171,320 @@ int validate(const hlbm_config &c, std::string *err) {
   return HLBM_OK;
 }
 
+
+// Many cases advanced together. Every phase of the structured step is one
+// launch over the work list of all running cases (case-batched kernels pick
+// each case's buffers from its step counter), and steps_per_graph steps are
+// captured as one HIP graph. Cases stop at their own max_steps; a case whose
+// force becomes non-finite stops at once (the kernels skip it) and is retired
+// at the next host check. Lists and graphs are rebuilt when the set of
+// running cases changes.
+template <class T, class R>
+class Batch final : public CaseBase {
+ public:
+  ~Batch() override { release(); }
+
+  int init(const hlbm_config *cfgs, int n) {
+    for (int i = 0; i < n; ++i) {
+      auto c = std::make_unique<Case<T, R>>();
+      const int rc = c->init(cfgs[i]);
+      if (rc != HLBM_OK) {
+        err = "case " + std::to_string(i) + ": " + c->err;
+        return rc;
+      }
+      cases_.push_back(std::move(c));
+    }
+    HIPCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    HIPCHK(hipEventCreate(&ev0_));
+    HIPCHK(hipEventCreate(&ev1_));
+    std::vector<CaseView<T, R>> v(n);
+    for (int i = 0; i < n; ++i) v[i] = cases_[i]->batched_view();
+    HIPCHK(hipMalloc(&views_, n * sizeof(CaseView<T, R>)));
+    HIPCHK(hipMemcpy(views_, v.data(), n * sizeof(CaseView<T, R>), hipMemcpyHostToDevice));
+    tuning_ = {8, 256, 0, 0, 0.0};
+    return HLBM_OK;
+  }
+
+  CaseBase *sub(int id) override {
+    return id >= 0 && id < (int)cases_.size() ? cases_[id].get() : nullptr;
+  }
+
+  int step(int64_t nsteps) override {
+    if (nsteps < 0) return fail(HLBM_E_ARG, "nsteps < 0");
+    int64_t done = 0;
+    while (done < nsteps) {
+      std::vector<int> act;
+      int64_t room = nsteps - done;
+      for (int i = 0; i < (int)cases_.size(); ++i) {
+        if (retired_.count(i)) continue;
+        const int64_t left = cases_[i]->max_steps() - cases_[i]->steps_taken();
+        if (left <= 0) continue;
+        act.push_back(i);
+        room = std::min(room, left);
+      }
+      if (act.empty()) break;
+      int rc = run(act, room);
+      if (rc != HLBM_OK) return rc;
+      done += room;
+    }
+    return HLBM_OK;
+  }
+
+  int tune(int trial_steps, hlbm_tuning *t) override {
+    if (!t || trial_steps < 0) return fail(HLBM_E_ARG, "invalid tuning request");
+    for (auto &c : cases_)
+      if (c->steps_taken() != 0) return fail(HLBM_E_STATE, "tuning must precede the first step");
+    if (trial_steps == 0) {
+      if (t->steps_per_graph < 1 || t->steps_per_graph > 64 || t->lattice_threads < 64 || t->lattice_threads > 256 ||
+          t->lattice_threads % 64 || (t->substep_threads != 0 && t->substep_threads != 512) || t->order < 0 ||
+          t->order > 1)
+        return fail(HLBM_E_ARG, "invalid schedule");
+      tuning_ = *t;
+      tuning_.ms_per_step = 0.0;
+      invalidate();
+      *t = tuning_;
+      return HLBM_OK;
+    }
+    // snapshot of every case's state at step 0
+    std::vector<void *> snap;
+    for (auto &c : cases_) {
+      void *lat[2], *grid[2];
+      size_t lb, gb;
+      c->buffers(lat, grid, &lb, &gb);
+      void *p = nullptr;
+      HIPCHK(hipMalloc(&p, lb + gb));
+      snap.push_back(p);
+      HIPCHK(hipMemcpy(p, lat[0], lb, hipMemcpyDeviceToDevice));
+      HIPCHK(hipMemcpy((char *)p + lb, grid[0], gb, hipMemcpyDeviceToDevice));
+    }
+    std::vector<int> all;
+    for (int i = 0; i < (int)cases_.size(); ++i)
+      if (cases_[i]->max_steps() >= trial_steps) all.push_back(i);
+    hlbm_tuning best = tuning_;
+    double best_ms = 1e300;
+    const int nsub_opts = sizeof(R) == 8 ? 1 : 2;
+    int rc = HLBM_OK;
+    for (int g : {4, 8, 16})
+      for (int lt : {128, 256})
+        for (int so = 0; so < nsub_opts && rc == HLBM_OK; ++so)
+          for (int ord = 0; ord < 2 && rc == HLBM_OK; ++ord) {
+            tuning_ = {g, lt, so ? 512 : 0, ord, 0.0};
+            invalidate();
+            float ms = 0.f;
+            rc = timed_trial(all, trial_steps, &ms);
+            if (rc == HLBM_OK) rc = restore(snap);
+            if (rc == HLBM_OK && ms / trial_steps < best_ms) {
+              best_ms = ms / trial_steps;
+              best = tuning_;
+            }
+          }
+    for (void *p : snap) (void)hipFree(p);
+    if (rc != HLBM_OK) return rc;
+    tuning_ = best;
+    tuning_.ms_per_step = best_ms;
+    invalidate();
+    *t = tuning_;
+    return HLBM_OK;
+  }
+
+  int get_state(int, void *, size_t) override { return fail(HLBM_E_ARG, "select a case"); }
+  int set_state(int, const void *, size_t) override { return fail(HLBM_E_ARG, "select a case"); }
+  int force(double *, int64_t, int64_t *, double, double, double *) override {
+    return fail(HLBM_E_ARG, "select a case");
+  }
+  int info(hlbm_info *) override { return fail(HLBM_E_ARG, "select a case"); }
+  int stencil(int, int32_t *, double *, double *) override {
+    return fail(HLBM_E_UNSUPPORTED, "stencils are per case: create the case alone");
+  }
+  int timing(int) override { return fail(HLBM_E_UNSUPPORTED, "per-kernel timing is per single case"); }
+  int timing_get(int, double *, int64_t *) override {
+    return fail(HLBM_E_UNSUPPORTED, "per-kernel timing is per single case");
+  }
+  int adjoint(const double *, int64_t, double *) override {
+    return fail(HLBM_E_UNSUPPORTED, "the adjoint runs on single cases");
+  }
+
+ private:
+  struct List {
+    int4 *d = nullptr;
+    int n = 0;
+  };
+
+  int fail(int code, const std::string &msg) {
+    err = msg;
+    return code;
+  }
+
+  void invalidate() {
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    gexec_ = nullptr;
+    listed_.clear();
+  }
+
+  void release() {
+    if (s_) (void)hipStreamSynchronize(s_);
+    invalidate();
+    for (auto &l : lists_)
+      if (l.d) (void)hipFree(l.d);
+    lists_.clear();
+    if (views_) (void)hipFree(views_);
+    if (ev0_) (void)hipEventDestroy(ev0_);
+    if (ev1_) (void)hipEventDestroy(ev1_);
+    if (s_) (void)hipStreamDestroy(s_);
+    cases_.clear();
+  }
+
+  // reorders a work list so that XCD x (workgroup b runs on XCD b % 8) gets
+  // a contiguous chunk of it
+  static void deal_to_xcds(std::vector<int4> &v) {
+    const size_t n = v.size(), per = (n + 7) / 8;
+    std::vector<int4> out;
+    out.reserve(n);
+    for (size_t b = 0; b < 8 * per; ++b) {
+      const size_t src = (b % 8) * per + b / 8;
+      if (src < n) out.push_back(v[src]);
+    }
+    v.swap(out);
+  }
+
+  hipError_t upload_list(std::vector<int4> &v, List &l) {
+    if (tuning_.order == 1) deal_to_xcds(v);
+    l.n = (int)v.size();
+    if (l.d) (void)hipFree(l.d);
+    l.d = nullptr;
+    if (v.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(&l.d, v.size() * sizeof(int4));
+    if (e == hipSuccess) e = hipMemcpy(l.d, v.data(), v.size() * sizeof(int4), hipMemcpyHostToDevice);
+    return e;
+  }
+
+  // work lists of the running cases: stream-collide, lattice-from-grid,
+  // donors, refill, force, then one per sub-step launch
+  hipError_t build_lists(const std::vector<int> &act) {
+    for (auto &l : lists_)
+      if (l.d) (void)hipFree(l.d);
+    lists_.assign(5, List{});
+    int lmax = 0;
+    std::vector<int4> k1, k2, dn, rf, fo;
+    const int lt = tuning_.lattice_threads;
+    for (int c : act) {
+      const CaseView<T, R> v = cases_[c]->batched_view();
+      for (int y = 0; y < v.ny; ++y)
+        for (int bx = 0; bx < (v.nx + lt - 1) / lt; ++bx) k1.push_back(make_int4(c, bx, y, 0));
+      for (int by = 0; by < v.k2_h; ++by)
+        for (int bx = 0; bx < (v.k2_w + 255) / 256; ++bx) k2.push_back(make_int4(c, bx, by, 0));
+      for (int bx = 0; bx < (4 * v.n_iface + 255) / 256; ++bx) dn.push_back(make_int4(c, bx, 0, 0));
+      for (int bx = 0; bx < (v.nnode + 255) / 256; ++bx) rf.push_back(make_int4(c, bx, 0, 0));
+      fo.push_back(make_int4(c, 0, 0, 0));
+      lmax = std::max(lmax, (v.n_sub + kSubstepBlock - 1) / kSubstepBlock);
+    }
+    hipError_t e = upload_list(k1, lists_[0]);
+    if (e == hipSuccess) e = upload_list(k2, lists_[1]);
+    if (e == hipSuccess) e = upload_list(dn, lists_[2]);
+    if (e == hipSuccess) e = upload_list(rf, lists_[3]);
+    if (e == hipSuccess) e = upload_list(fo, lists_[4]);
+    for (int i = 0; i < lmax && e == hipSuccess; ++i) {
+      std::vector<int4> sl;
+      for (int c : act) {
+        const CaseView<T, R> v = cases_[c]->batched_view();
+        if ((v.n_sub + kSubstepBlock - 1) / kSubstepBlock <= i) continue;
+        const int tiles = ((v.nux + 63) / 64) * ((v.nuy + 3) / 4);
+        for (int t = 0; t < tiles; ++t) sl.push_back(make_int4(c, t, 0, 0));
+      }
+      lists_.push_back(List{});
+      e = upload_list(sl, lists_.back());
+    }
+    listed_ = act;
+    return e;
+  }
+
+  void enqueue_step() {
+    using K = Kernels<T, R>;
+    K::batched(BatchKernel::LatticeFromGrid, views_, lists_[1].d, lists_[1].n, 0, 256, s_);
+    K::batched(BatchKernel::StreamCollide, views_, lists_[0].d, lists_[0].n, 0, tuning_.lattice_threads, s_);
+    K::batched(BatchKernel::InterfaceDonors, views_, lists_[2].d, lists_[2].n, 0, 256, s_);
+    for (size_t i = 5; i < lists_.size(); ++i)
+      K::batched(BatchKernel::GridSubsteps, views_, lists_[i].d, lists_[i].n, (int)(i - 5) * kSubstepBlock,
+                 tuning_.substep_threads, s_);
+    K::batched(BatchKernel::Refill, views_, lists_[3].d, lists_[3].n, 0, 256, s_);
+    K::batched(BatchKernel::Force, views_, lists_[4].d, lists_[4].n, 0, 256, s_);
+  }
+
+  hipError_t ensure_graph(const std::vector<int> &act) {
+    if (gexec_ && act == listed_) return hipSuccess;
+    invalidate();
+    hipError_t e = build_lists(act);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < tuning_.steps_per_graph; ++i) enqueue_step();
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s_, &g);
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+  }
+
+  // m steps of the running cases act (none of them ends before m steps)
+  int run(const std::vector<int> &act, int64_t m) {
+    HIPCHK(ensure_graph(act));
+    int64_t s = 0;
+    for (; s + tuning_.steps_per_graph <= m; s += tuning_.steps_per_graph) HIPCHK(hipGraphLaunch(gexec_, s_));
+    for (; s < m; ++s) enqueue_step();
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s_));
+    for (int c : act) {
+      int64_t k = 0;
+      HIPCHK(hipMemcpy(&k, cases_[c]->step_counter(), sizeof(k), hipMemcpyDeviceToHost));
+      const int64_t adv = k - cases_[c]->steps_taken();
+      cases_[c]->advance_host(adv);
+      if (adv != m) retired_.insert(c);  // stopped early: non-finite force
+    }
+    return HLBM_OK;
+  }
+
+  int timed_trial(const std::vector<int> &act, int steps, float *ms) {
+    HIPCHK(ensure_graph(act));
+    // one untimed graph launch, then the timed steps
+    HIPCHK(hipGraphLaunch(gexec_, s_));
+    HIPCHK(hipEventRecord(ev0_, s_));
+    int s = 0;
+    for (; s + tuning_.steps_per_graph <= steps; s += tuning_.steps_per_graph) HIPCHK(hipGraphLaunch(gexec_, s_));
+    for (; s < steps; ++s) enqueue_step();
+    HIPCHK(hipEventRecord(ev1_, s_));
+    HIPCHK(hipEventSynchronize(ev1_));
+    HIPCHK(hipEventElapsedTime(ms, ev0_, ev1_));
+    return HLBM_OK;
+  }
+
+  // back to the snapshot taken at step 0
+  int restore(const std::vector<void *> &snap) {
+    HIPCHK(hipStreamSynchronize(s_));
+    for (size_t i = 0; i < cases_.size(); ++i) {
+      void *lat[2], *grid[2];
+      size_t lb, gb;
+      cases_[i]->buffers(lat, grid, &lb, &gb);
+      HIPCHK(hipMemcpy(lat[0], snap[i], lb, hipMemcpyDeviceToDevice));
+      HIPCHK(hipMemcpy(grid[0], (char *)snap[i] + lb, gb, hipMemcpyDeviceToDevice));
+      HIPCHK(hipMemset(cases_[i]->step_counter(), 0, sizeof(int64_t)));
+      HIPCHK(hipMemset(cases_[i]->flag(), 0, sizeof(int)));
+      HIPCHK(hipMemset(cases_[i]->refill_counters(), 0, 2 * sizeof(unsigned long long)));
+    }
+    return HLBM_OK;
+  }
+
+  std::vector<std::unique_ptr<Case<T, R>>> cases_;
+  std::set<int> retired_;
+  CaseView<T, R> *views_ = nullptr;
+  std::vector<List> lists_;
+  std::vector<int> listed_;
+  hipGraphExec_t gexec_ = nullptr;
+  hipStream_t s_ = nullptr;
+  hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+  hlbm_tuning tuning_{};
+};
+
 }  // namespace
 }  // namespace mghlbm
 
@@ -1132,14 +1497,35 @@ extern "C" {
 int hlbm_create(const hlbm_config *cfg, int32_t ncases, hlbm_t **out) {
   using namespace mghlbm;
   if (out) *out = nullptr;
-  if (!cfg || !out) { g_create_error = "null argument"; return HLBM_E_ARG; }
-  if (ncases != 1) { g_create_error = "only ncases = 1 is supported"; return HLBM_E_UNSUPPORTED; }
+  if (!cfg || !out || ncases < 1) { g_create_error = "null argument or ncases < 1"; return HLBM_E_ARG; }
   std::string e;
-  int rc = validate(*cfg, &e);
-  if (rc != HLBM_OK) { g_create_error = e; return rc; }
+  for (int i = 0; i < ncases; ++i) {
+    int rc = validate(cfg[i], &e);
+    if (rc != HLBM_OK) { g_create_error = (ncases > 1 ? "case " + std::to_string(i) + ": " : "") + e; return rc; }
+    if (ncases > 1) {
+      if (cfg[i].storage != cfg[0].storage) { g_create_error = "a batch needs one storage type"; return HLBM_E_ARG; }
+      if (cfg[i].ckpt_every != 0) { g_create_error = "a batch takes no checkpoints"; return HLBM_E_ARG; }
+      if (cfg[i].nux <= 0 || cfg[i].nuy <= 0) { g_create_error = "every batched case needs a grid"; return HLBM_E_ARG; }
+    }
+  }
   std::unique_ptr<CaseBase> c;
+  int rc = HLBM_OK;
   try {
-    if (cfg->storage == HLBM_FP64) {
+    if (ncases > 1) {
+      if (cfg->storage == HLBM_FP64) {
+        auto p = std::make_unique<Batch<double, double>>();
+        rc = p->init(cfg, ncases);
+        c = std::move(p);
+      } else if (cfg->storage == HLBM_FP32) {
+        auto p = std::make_unique<Batch<float, float>>();
+        rc = p->init(cfg, ncases);
+        c = std::move(p);
+      } else {
+        auto p = std::make_unique<Batch<__half, float>>();
+        rc = p->init(cfg, ncases);
+        c = std::move(p);
+      }
+    } else if (cfg->storage == HLBM_FP64) {
       auto p = std::make_unique<Case<double, double>>();
       rc = p->init(*cfg);
       c = std::move(p);
@@ -1172,30 +1558,59 @@ int hlbm_step(hlbm_t *h, int64_t nsteps) {
   return h->c->step(nsteps);
 }
 
+static mghlbm::CaseBase *pick(hlbm_t *h, int32_t case_id) {
+  mghlbm::CaseBase *c = h->c->sub(case_id);
+  if (!c) h->c->err = "case_id out of range";
+  return c;
+}
+
 int hlbm_force(hlbm_t *h, int32_t case_id, double *hist_xy, int64_t cap, int64_t *n_out, double win_t0,
                double win_t1, double theta[2]) {
-  if (!h || case_id != 0 || cap < 0) return HLBM_E_ARG;
-  return h->c->force(hist_xy, cap, n_out, win_t0, win_t1, theta);
+  if (!h || cap < 0) return HLBM_E_ARG;
+  mghlbm::CaseBase *c = pick(h, case_id);
+  if (!c) return HLBM_E_ARG;
+  const int rc = c->force(hist_xy, cap, n_out, win_t0, win_t1, theta);
+  if (rc != HLBM_OK && c != h->c.get()) h->c->err = c->err;
+  return rc;
 }
 
 int hlbm_adjoint(hlbm_t *h, int32_t case_id, const double *dJ_dF, int64_t n, double grad[3]) {
-  if (!h || case_id != 0) return HLBM_E_ARG;
+  if (!h) return HLBM_E_ARG;
+  if (h->c->sub(1)) return h->c->adjoint(dJ_dF, n, grad);  // a batch: unsupported
+  if (case_id != 0) return HLBM_E_ARG;
   return h->c->adjoint(dJ_dF, n, grad);
 }
 
 int hlbm_get_state(hlbm_t *h, int32_t case_id, int32_t which, void *buf, size_t bytes) {
-  if (!h || case_id != 0 || !buf) return HLBM_E_ARG;
-  return h->c->get_state(which, buf, bytes);
+  if (!h || !buf) return HLBM_E_ARG;
+  mghlbm::CaseBase *c = pick(h, case_id);
+  if (!c) return HLBM_E_ARG;
+  const int rc = c->get_state(which, buf, bytes);
+  if (rc != HLBM_OK && c != h->c.get()) h->c->err = c->err;
+  return rc;
 }
 
 int hlbm_set_state(hlbm_t *h, int32_t case_id, int32_t which, const void *buf, size_t bytes) {
-  if (!h || case_id != 0 || !buf) return HLBM_E_ARG;
-  return h->c->set_state(which, buf, bytes);
+  if (!h || !buf) return HLBM_E_ARG;
+  mghlbm::CaseBase *c = pick(h, case_id);
+  if (!c) return HLBM_E_ARG;
+  const int rc = c->set_state(which, buf, bytes);
+  if (rc != HLBM_OK && c != h->c.get()) h->c->err = c->err;
+  return rc;
 }
 
 int hlbm_info_get(hlbm_t *h, int32_t case_id, hlbm_info *out) {
-  if (!h || case_id != 0 || !out) return HLBM_E_ARG;
-  return h->c->info(out);
+  if (!h || !out) return HLBM_E_ARG;
+  mghlbm::CaseBase *c = pick(h, case_id);
+  if (!c) return HLBM_E_ARG;
+  const int rc = c->info(out);
+  if (rc != HLBM_OK && c != h->c.get()) h->c->err = c->err;
+  return rc;
+}
+
+int hlbm_tune(hlbm_t *h, int32_t trial_steps, hlbm_tuning *t) {
+  if (!h) return HLBM_E_ARG;
+  return h->c->tune(trial_steps, t);
 }
 
 int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S, double *C) {

@@ -37,7 +37,14 @@ struct CaseView {
   unsigned long long *counts;  // refill type 1 and type 2 counters
   // lattice rows and columns the interpolation kernel must cover
   int k2_x0, k2_w, k2_h;
+  // case-batched kernels pick their buffers from the step counter:
+  // lattice lat[k & 1] -> lat[(k + 1) & 1], grid buffers by flip parity
+  T *lat[2];
+  R *grid[2];
+  int64_t max_steps;  // a batched case stops here
 };
+
+enum class BatchKernel { StreamCollide, LatticeFromGrid, InterfaceDonors, GridSubsteps, Refill, Force };
 
 // grid sub-steps advanced per launch (temporal blocking depth)
 constexpr int kSubstepBlock = 4;
@@ -61,6 +68,12 @@ struct Kernels {
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
   static void force(const CaseView<T, R> &v, const R *f, hipStream_t s);
   static void lattice_to_f64(const T *src, double *dst, size_t plane, hipStream_t s);
+  // one launch of a case-batched step over a work list of int4 items
+  // (case, block x, block y, 0); GridSubsteps: (case, tile) for sub-steps
+  // m0 .. m0+3 of every listed case; threads: stream-collide workgroup size
+  // (<= 256) or grid sub-step workgroup size (512 or the default)
+  static void batched(BatchKernel which, const CaseView<T, R> *views, const int4 *items, int nitems, int m0,
+                      int threads, hipStream_t s);
   static void lattice_from_f64(const double *src, T *dst, size_t plane, hipStream_t s);
 };
 

@@ -16,29 +16,61 @@ namespace {
 
 using namespace dev;
 
+// Each kernel body is a per-workgroup device function; a single-case kernel
+// takes its block coordinates from the grid, a case-batched kernel takes
+// (case, block) from a work list and picks the case's buffers from its step
+// counter (lattice buffers alternate every step; the grid buffers flip once
+// per sub-step launch and once in the refill).
+template <class T, class R>
+__device__ __forceinline__ bool batched_case(const CaseView<T, R> &v, int64_t &k) {
+  k = *v.dk;
+  return k < v.max_steps && *v.flag == 0;
+}
+template <class T, class R>
+__device__ __forceinline__ int grid_cur(const CaseView<T, R> &v, int64_t k) {
+  const int launches = (v.n_sub + kSubstepBlock - 1) / kSubstepBlock;
+  return ((launches + 1) & 1) ? (int)(k & 1) : 0;
+}
+
 // ---- K1: fused pull stream + BGK collide, Eq.(LBE) -------------------------
 template <class T, class R>
-__global__ __launch_bounds__(256) void k_stream_collide(CaseView<T, R> v) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
+__device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, const T *__restrict__ A,
+                                                     T *__restrict__ B, int64_t k, int bx, int by) {
+  const int x = bx * blockDim.x + threadIdx.x;
+  const int y = by;
   if (x >= v.nx) return;
   const size_t plane = (size_t)v.nx * v.ny, c = (size_t)y * v.nx + x;
   bool inside = false;
   if (v.has_grid) {
-    const StepParams &P = v.params[*v.dk];
+    const StepParams &P = v.params[k];
     inside = x >= P.ix0 && x <= P.ix1 && y >= P.iy0 && y <= P.iy1;
   }
   if (inside) {  // unused and interpolation nodes carry their values
 #pragma unroll
-    for (int q = 0; q < 9; ++q) v.B[q * plane + c] = v.A[q * plane + c];
+    for (int q = 0; q < 9; ++q) B[q * plane + c] = A[q * plane + c];
     return;
   }
   R f[9], e[9], rho, ux, uy;
-  pull<T, R>(v.A, v.nx, v.ny, v.periodic_y, x, y, f);
+  pull<T, R>(A, v.nx, v.ny, v.periodic_y, x, y, f);
   moments<R>(f, rho, ux, uy);
   equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) Stor<T>::st_stream(v.B, q * plane + c, q, f[q] - v.inv_tau * (f[q] - e[q]));
+  for (int q = 0; q < 9; ++q) Stor<T>::st_stream(B, q * plane + c, q, f[q] - v.inv_tau * (f[q] - e[q]));
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_stream_collide(CaseView<T, R> v) {
+  stream_collide_block<T, R>(v, v.A, v.B, v.has_grid ? *v.dk : 0, blockIdx.x, blockIdx.y);
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void kb_stream_collide(const CaseView<T, R> *__restrict__ views,
+                                                         const int4 *__restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const CaseView<T, R> &v = views[it.x];
+  int64_t k;
+  if (!batched_case(v, k)) return;
+  stream_collide_block<T, R>(v, v.lat[k & 1], v.lat[(k + 1) & 1], k, it.y, it.z);
 }
 
 // ---- K2: lattice interpolation nodes from the grid, Eq.(postcollision2_s) ----
@@ -47,10 +79,11 @@ __global__ __launch_bounds__(256) void k_stream_collide(CaseView<T, R> v) {
 // previous step. Barycentric interpolation of rho, u and f^neq,u over the
 // grid triangle at t_k; f^eq rebuilt from the interpolated moments.
 template <class T, class R>
-__global__ __launch_bounds__(256) void k_lattice_from_grid(CaseView<T, R> v, const R *__restrict__ g) {
-  const StepParams &P = v.params[*v.dk];
-  const int x = v.k2_x0 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = min(P.iy0, P.piy0) + (int)blockIdx.y;
+__device__ __forceinline__ void lattice_from_grid_block(const CaseView<T, R> &v, T *__restrict__ A,
+                                                        const R *__restrict__ g, int64_t k, int bx, int by) {
+  const StepParams &P = v.params[k];
+  const int x = v.k2_x0 + bx * blockDim.x + threadIdx.x;
+  const int y = min(P.iy0, P.piy0) + by;
   if (x >= v.k2_x0 + v.k2_w || y > max(P.iy1, P.piy1)) return;
   if (!from_grid_target(P, x, y)) return;
   const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body};
@@ -63,9 +96,23 @@ __global__ __launch_bounds__(256) void k_lattice_from_grid(CaseView<T, R> v, con
   R e[9];
   equilibrium<R>(rho, ux, uy, e);
   const size_t plane = (size_t)v.nx * v.ny, c = (size_t)y * v.nx + x;
-  T *A = const_cast<T *>(v.A);
 #pragma unroll
   for (int q = 0; q < 9; ++q) Stor<T>::st(A, q * plane + c, q, e[q] + v.g_post * fneq[q]);
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_lattice_from_grid(CaseView<T, R> v, const R *__restrict__ g) {
+  lattice_from_grid_block<T, R>(v, const_cast<T *>(v.A), g, *v.dk, blockIdx.x, blockIdx.y);
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void kb_lattice_from_grid(const CaseView<T, R> *__restrict__ views,
+                                                            const int4 *__restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const CaseView<T, R> &v = views[it.x];
+  int64_t k;
+  if (!batched_case(v, k)) return;
+  lattice_from_grid_block<T, R>(v, v.lat[k & 1], v.grid[grid_cur(v, k)], k, it.y, it.z);
 }
 
 // ---- K4 prologue: structured-derived values at the grid's outer nodes ----------
@@ -74,26 +121,27 @@ __global__ __launch_bounds__(256) void k_lattice_from_grid(CaseView<T, R> v, con
 // consecutive lanes take the four bilinear donors of one node and combine
 // their weighted moments with two shuffles.
 template <class T, class R>
-__global__ __launch_bounds__(256) void k_interface_donors(CaseView<T, R> v) {
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void interface_donors_block(const CaseView<T, R> &v, const T *__restrict__ A, int64_t k,
+                                                       int bx) {
+  const int gt = bx * blockDim.x + threadIdx.x;
   const int t = gt >> 2, d = gt & 3;
   const bool valid = t < v.n_iface;
   R acc[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = R(0);
+  for (int r = 0; r < 12; ++r) acc[r] = R(0);
   int p = 0;
   if (valid) {
-    const StepParams &P = v.params[*v.dk];
+    const StepParams &P = v.params[k];
     p = v.iface[t];
     const int i = p % v.nux, j = p / v.nux;
     const double X = v.xc + (double)(i - v.nux / 2) * v.h;
     const double Y = P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
-    donor_corner<T, R>(v.A, v.nx, v.ny, v.periodic_y, X, Y, d, acc);
+    donor_corner<T, R>(A, v.nx, v.ny, v.periodic_y, X, Y, d, acc);
   }
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    acc[k] += __shfl_xor(acc[k], 1, 64);
-    acc[k] += __shfl_xor(acc[k], 2, 64);
+  for (int r = 0; r < 12; ++r) {
+    acc[r] += __shfl_xor(acc[r], 1, 64);
+    acc[r] += __shfl_xor(acc[r], 2, 64);
   }
   if (!valid) return;
   R e[9];
@@ -105,6 +153,21 @@ __global__ __launch_bounds__(256) void k_interface_donors(CaseView<T, R> v) {
     v.star_n[(size_t)q * v.nnode + p] = n;
     v.star_f[(size_t)q * v.nnode + p] = e[q] + n;
   }
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_interface_donors(CaseView<T, R> v) {
+  interface_donors_block<T, R>(v, v.A, *v.dk, blockIdx.x);
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void kb_interface_donors(const CaseView<T, R> *__restrict__ views,
+                                                           const int4 *__restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const CaseView<T, R> &v = views[it.x];
+  int64_t k;
+  if (!batched_case(v, k)) return;
+  interface_donors_block<T, R>(v, v.lat[k & 1], k, it.y);
 }
 
 // ---- K3/K4: sub-steps of the grid scheme ------------------------------------
@@ -152,27 +215,26 @@ constexpr size_t substeps_lds_bytes() {
 }
 
 // workgroup size: FP64 nodes need the register room of 512 threads, FP32
-// nodes fit 1024 (16 waves on one tile's LDS)
+// nodes fit 1024 (16 waves on one tile's LDS); a batch may choose others
 template <class R>
 constexpr int substep_threads() {
   return sizeof(R) == 8 ? 512 : 1024;
 }
 
-template <class R, int H>
-__global__ __launch_bounds__(substep_threads<R>()) void k_grid_substeps(
+// Advances tile t of a grid by `count` sub-steps m0 .. m0+count-1 of step k.
+template <class R, int H, int NT>
+__device__ __forceinline__ void grid_substeps_block(
     const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
-    const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int ntiles,
-    R dt, R dt_tau, const R *__restrict__ uw, const int64_t *__restrict__ dk, int n_sub, int m0, int count,
+    const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int t,
+    R dt, R dt_tau, const R *__restrict__ uw, int64_t k, int n_sub, int m0, int count,
     R *__restrict__ tape, R *__restrict__ wtape, const int *__restrict__ widx, int nwall) {
   using G = Region<H>;
   constexpr int RX = G::RX, RN = G::RN;
-  constexpr int NT = substep_threads<R>(), PER = (RN + NT - 1) / NT;
+  constexpr int PER = (RN + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   R *sl = reinterpret_cast<R *>(lds_raw);   // [RN][NS] grid f, f^neq
   R *rl = sl + NS * RN;                     // [NRING][NS] f*, f^neq* on the outer ring
   int *scls = reinterpret_cast<int *>(rl + NS * G::NRING);  // stencil class, -1 outside the grid
-  const int b = blockIdx.x;
-  const int t = (ntiles % 8 == 0) ? (b % 8) * (ntiles / 8) + (b / 8) : b;
   const int x0 = (t % tiles_x) * TX - H, y0 = (t / tiles_x) * TY - H;  // region origin
   const bool touches_ring = x0 <= 0 || y0 <= 0 || x0 + RX >= nux || y0 + G::RY >= nuy;
   const size_t N = (size_t)nux * nuy;
@@ -242,7 +304,7 @@ __global__ __launch_bounds__(substep_threads<R>()) void k_grid_substeps(
 
   for (int sub = 0; sub < count; ++sub) {
     const int ex = count - 1 - sub;  // region growth still exact after this sub-step
-    const R uw_now = uw[*dk * n_sub + m0 + sub];
+    const R uw_now = uw[k * n_sub + m0 + sub];
     R out[PER][9];
     bool upd[PER];
 #pragma unroll
@@ -341,6 +403,33 @@ __global__ __launch_bounds__(substep_threads<R>()) void k_grid_substeps(
   }
 }
 
+template <class R, int H, int NT>
+__global__ __launch_bounds__(NT) void k_grid_substeps(
+    const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
+    const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int ntiles,
+    R dt, R dt_tau, const R *__restrict__ uw, const int64_t *__restrict__ dk, int n_sub, int m0, int count,
+    R *__restrict__ tape, R *__restrict__ wtape, const int *__restrict__ widx, int nwall) {
+  const int b = blockIdx.x;  // tiles are dealt to the eight XCDs in contiguous bands
+  const int t = (ntiles % 8 == 0) ? (b % 8) * (ntiles / 8) + (b / 8) : b;
+  grid_substeps_block<R, H, NT>(f, fout, star_f, star_n, cls, tab, nux, nuy, tiles_x, t, dt, dt_tau, uw, *dk, n_sub,
+                                m0, count, tape, wtape, widx, nwall);
+}
+
+// launch m0 / kSubstepBlock of a batched step: item = (case, tile)
+template <class T, class R, int H, int NT>
+__global__ __launch_bounds__(NT) void kb_grid_substeps(const CaseView<T, R> *__restrict__ views,
+                                                       const int4 *__restrict__ items, int m0) {
+  const int4 it = items[blockIdx.x];
+  const CaseView<T, R> &v = views[it.x];
+  int64_t k;
+  if (!batched_case(v, k)) return;
+  const int cur = grid_cur(v, k), i = m0 / kSubstepBlock;
+  const int tiles_x = (v.nux + TX - 1) / TX;
+  grid_substeps_block<R, H, NT>(v.grid[cur ^ (i & 1)], v.grid[cur ^ ((i + 1) & 1)], v.star_f, v.star_n, v.cls,
+                                v.tab, v.nux, v.nuy, tiles_x, it.y, v.dt_u, v.dt_over_tau_u, v.uw, k, v.n_sub, m0,
+                                min(kSubstepBlock, v.n_sub - m0), nullptr, nullptr, nullptr, 0);
+}
+
 // ---- K5: move the grid from y_k to y_{k+1} and refill it ---------------------
 // Each non-wall node is located, at its new position, in the grid of t_k:
 // inside a triangle -> type 3 (barycentric interpolation of f); inside the
@@ -348,8 +437,9 @@ __global__ __launch_bounds__(substep_threads<R>()) void k_grid_substeps(
 // donors, f^neq,u = (1 - 1/(2 tau_s)) f^neq,s, Eq.(continuity_stresses)).
 // Wall nodes keep f (their velocity is imposed during the sub-steps).
 template <class T, class R>
-__global__ __launch_bounds__(256) void k_refill(CaseView<T, R> v, const R *__restrict__ fo, R *__restrict__ fn) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *__restrict__ A,
+                                             const R *__restrict__ fo, R *__restrict__ fn, int64_t k, int bx) {
+  const int p = bx * blockDim.x + threadIdx.x;
   if (p >= v.nnode) return;
   const int i = p % v.nux, j = p / v.nux;
   const size_t N = (size_t)v.nnode;
@@ -359,7 +449,7 @@ __global__ __launch_bounds__(256) void k_refill(CaseView<T, R> v, const R *__res
     for (int q = 0; q < 9; ++q) fn[q * N + p] = fo[q * N + p];
     return;
   }
-  const StepParams &P = v.params[*v.dk];
+  const StepParams &P = v.params[k];
   const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body};
   const RefillCell rc = refill_cell(gg, P.ybase, P.ybase1, i, j);
   if (rc.kind == 3) {
@@ -377,7 +467,7 @@ __global__ __launch_bounds__(256) void k_refill(CaseView<T, R> v, const R *__res
     const double X = v.xc + (double)(i - v.nux / 2) * v.h;
     const double Ynew = P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
     R rho, ux, uy, fneq[9], e[9];
-    lattice_bilinear<T, R>(v.A, v.nx, v.ny, v.periodic_y, X, Ynew, rho, ux, uy, fneq);
+    lattice_bilinear<T, R>(A, v.nx, v.ny, v.periodic_y, X, Ynew, rho, ux, uy, fneq);
     equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = e[q] + v.k_neq * fneq[q];
@@ -387,13 +477,29 @@ __global__ __launch_bounds__(256) void k_refill(CaseView<T, R> v, const R *__res
   for (int q = 0; q < 9; ++q) fn[q * N + p] = out[q];
 }
 
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_refill(CaseView<T, R> v, const R *__restrict__ fo, R *__restrict__ fn) {
+  refill_block<T, R>(v, v.A, fo, fn, *v.dk, blockIdx.x);
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void kb_refill(const CaseView<T, R> *__restrict__ views,
+                                                 const int4 *__restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const CaseView<T, R> &v = views[it.x];
+  int64_t k;
+  if (!batched_case(v, k)) return;
+  const int cur = grid_cur(v, k), L = (v.n_sub + kSubstepBlock - 1) / kSubstepBlock;
+  refill_block<T, R>(v, v.lat[k & 1], v.grid[cur ^ (L & 1)], v.grid[cur ^ ((L + 1) & 1)], k, it.y);
+}
+
 // ---- K6: force on the lamina, then advance the step counter ------------------
 // Traction -p' n + sigma' n on each wall edge (trapezoid rule), p' = c_s^2
 // (rho - 1), sigma'_ab = -sum_i c_ia c_ib f_i^neq; FP64 accumulation, wave64
 // shuffle reduction and one LDS pass across the four waves.
 template <class R>
-__global__ __launch_bounds__(256) void k_force(const R *__restrict__ f, const WallEdge *__restrict__ wall,
-                                               int n_wall_edges, int nnode, int64_t *dk, double *hist, int *flag) {
+__device__ __forceinline__ void force_block(const R *__restrict__ f, const WallEdge *__restrict__ wall,
+                                            int n_wall_edges, int nnode, int64_t *dk, double *hist, int *flag) {
   __shared__ double red[2][4];
   double Fx = 0.0, Fy = 0.0;
   for (int e = threadIdx.x; e < n_wall_edges; e += blockDim.x) {
@@ -447,6 +553,24 @@ __global__ __launch_bounds__(256) void k_force(const R *__restrict__ f, const Wa
   }
 }
 
+template <class R>
+__global__ __launch_bounds__(256) void k_force(const R *__restrict__ f, const WallEdge *__restrict__ wall,
+                                               int n_wall_edges, int nnode, int64_t *dk, double *hist, int *flag) {
+  force_block<R>(f, wall, n_wall_edges, nnode, dk, hist, flag);
+}
+
+// one workgroup per case: item = (case)
+template <class T, class R>
+__global__ __launch_bounds__(256) void kb_force(const CaseView<T, R> *__restrict__ views,
+                                                const int4 *__restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const CaseView<T, R> &v = views[it.x];
+  int64_t k;
+  if (!batched_case(v, k)) return;
+  const int cur = grid_cur(v, k), L = (v.n_sub + kSubstepBlock - 1) / kSubstepBlock;
+  force_block<R>(v.grid[cur ^ (L & 1)], v.wall, v.n_wall_edges, v.nnode, v.dk, v.hist, v.flag);
+}
+
 template <class T, class R>
 __global__ void k_fill_rest(T *lat, size_t plane, R *grid, int nnode) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -480,9 +604,16 @@ inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b
 
 template <class T, class R>
 hipError_t Kernels<T, R>::prepare() {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_grid_substeps<R, kSubstepBlock>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)substeps_lds_bytes<R, kSubstepBlock>());
+  constexpr int NTd = substep_threads<R>();
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_grid_substeps<R, kSubstepBlock, NTd>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)substeps_lds_bytes<R, kSubstepBlock>());
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_grid_substeps<T, R, kSubstepBlock, NTd>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)substeps_lds_bytes<R, kSubstepBlock>());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_grid_substeps<T, R, kSubstepBlock, 512>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)substeps_lds_bytes<R, kSubstepBlock>());
 }
 
 template <class T, class R>
@@ -515,7 +646,8 @@ template <class T, class R>
 void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
                                   R *tape, R *wtape, const int *widx, int nwall) {
   const int tiles_x = (v.nux + TX - 1) / TX, tiles_y = (v.nuy + TY - 1) / TY;
-  hipLaunchKernelGGL((k_grid_substeps<R, kSubstepBlock>), dim3(tiles_x * tiles_y), dim3(substep_threads<R>()),
+  hipLaunchKernelGGL((k_grid_substeps<R, kSubstepBlock, substep_threads<R>()>), dim3(tiles_x * tiles_y),
+                     dim3(substep_threads<R>()),
                      (substeps_lds_bytes<R, kSubstepBlock>()), s, f, fout, (const R *)v.star_f, (const R *)v.star_n,
                      v.cls, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw,
                      (const int64_t *)v.dk, v.n_sub, m0, count, tape, wtape, widx, nwall);
@@ -540,6 +672,38 @@ void Kernels<T, R>::lattice_to_f64(const T *src, double *dst, size_t plane, hipS
 template <class T, class R>
 void Kernels<T, R>::lattice_from_f64(const double *src, T *dst, size_t plane, hipStream_t s) {
   hipLaunchKernelGGL((k_from_f64<T>), dim3(blocks(plane, 256)), dim3(256), 0, s, src, dst, plane);
+}
+
+template <class T, class R>
+void Kernels<T, R>::batched(BatchKernel which, const CaseView<T, R> *views, const int4 *items, int nitems, int m0,
+                            int threads, hipStream_t s) {
+  if (nitems <= 0) return;
+  const dim3 g(nitems);
+  switch (which) {
+    case BatchKernel::StreamCollide:
+      hipLaunchKernelGGL((kb_stream_collide<T, R>), g, dim3(threads), 0, s, views, items);
+      break;
+    case BatchKernel::LatticeFromGrid:
+      hipLaunchKernelGGL((kb_lattice_from_grid<T, R>), g, dim3(256), 0, s, views, items);
+      break;
+    case BatchKernel::InterfaceDonors:
+      hipLaunchKernelGGL((kb_interface_donors<T, R>), g, dim3(256), 0, s, views, items);
+      break;
+    case BatchKernel::GridSubsteps:
+      if (threads == 512 && substep_threads<R>() != 512)
+        hipLaunchKernelGGL((kb_grid_substeps<T, R, kSubstepBlock, 512>), g, dim3(512),
+                           (substeps_lds_bytes<R, kSubstepBlock>()), s, views, items, m0);
+      else
+        hipLaunchKernelGGL((kb_grid_substeps<T, R, kSubstepBlock, substep_threads<R>()>), g,
+                           dim3(substep_threads<R>()), (substeps_lds_bytes<R, kSubstepBlock>()), s, views, items, m0);
+      break;
+    case BatchKernel::Refill:
+      hipLaunchKernelGGL((kb_refill<T, R>), g, dim3(256), 0, s, views, items);
+      break;
+    case BatchKernel::Force:
+      hipLaunchKernelGGL((kb_force<T, R>), g, dim3(256), 0, s, views, items);
+      break;
+  }
 }
 
 template struct Kernels<double, double>;

@@ -24,7 +24,8 @@ STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV}
 
 EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_state",
            "hlbm_set_state", "hlbm_info_get", "hlbm_get_stencil", "hlbm_timing",
-           "hlbm_timing_get", "hlbm_destroy", "hlbm_last_error")
+           "hlbm_timing_get", "hlbm_tune", "hlbm_destroy", "hlbm_last_error")
+STATUS_RUNNING, STATUS_DONE, STATUS_UNSTABLE = 0, 1, 2
 
 
 class HlbmError(RuntimeError):
@@ -49,7 +50,16 @@ class Info(C.Structure):
                 ("n_sub", "nnode", "ntri", "n_interface", "n_wall", "n_wall_edges", "beta_limit_ok",
                  "n_classes")] + \
                [("step", C.c_int64), ("y", C.c_double), ("n_type1", C.c_int64),
-                ("n_type2", C.c_int64), ("n_type3", C.c_int64), ("lattice_bytes", C.c_int64)]
+                ("n_type2", C.c_int64), ("n_type3", C.c_int64), ("lattice_bytes", C.c_int64),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("steps_per_graph", C.c_int32), ("lattice_threads", C.c_int32),
+                ("substep_threads", C.c_int32), ("order", C.c_int32), ("ms_per_step", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -75,6 +85,7 @@ def load(path: str = LIB_PATH):
     L.hlbm_get_stencil.argtypes = [vp, i32, C.POINTER(C.c_int32), dp, dp]
     L.hlbm_timing.argtypes = [vp, i32]
     L.hlbm_timing_get.argtypes = [vp, i32, dp, C.POINTER(i64)]
+    L.hlbm_tune.argtypes = [vp, i32, C.POINTER(Tuning)]
     L.hlbm_destroy.argtypes = [vp]
     L.hlbm_destroy.restype = None
     L.hlbm_last_error.argtypes = [vp]
@@ -194,6 +205,114 @@ class Case:
         out = np.zeros((9, self.nnode))
         self._check(load().hlbm_get_state(self.h, 0, STATE_ADJ_GRID, out.ctypes.data, out.nbytes))
         return out
+
+
+class _Member:
+    """One case of a batch (reads and writes go to that case)."""
+
+    def __init__(self, batch, cid, nx, ny, nnode):
+        self.batch, self.cid, self.nx, self.ny, self.nnode = batch, cid, nx, ny, nnode
+
+    def _check(self, rc):
+        self.batch._check(rc)
+
+    def info(self) -> Info:
+        i = Info()
+        self._check(load().hlbm_info_get(self.batch.h, self.cid, C.byref(i)))
+        return i
+
+    def history(self):
+        n = C.c_int64()
+        h = self.batch.h
+        self._check(load().hlbm_force(h, self.cid, None, 0, C.byref(n), 0.0, 0.0, None))
+        out = np.zeros((max(n.value, 1), 2))
+        self._check(load().hlbm_force(h, self.cid, _ptr(out), n.value, C.byref(n), 0.0, 0.0, None))
+        return out[:n.value]
+
+    def theta(self, t0=1.0, t1=4.0):
+        th = np.zeros(2)
+        self._check(load().hlbm_force(self.batch.h, self.cid, None, 0, None, t0, t1, _ptr(th)))
+        return complex(th[0], th[1])
+
+    def lattice(self):
+        out = np.zeros((9, self.ny, self.nx))
+        self._check(load().hlbm_get_state(self.batch.h, self.cid, STATE_LATTICE, out.ctypes.data, out.nbytes))
+        return out
+
+    def grid(self):
+        out = np.zeros((9, self.nnode))
+        self._check(load().hlbm_get_state(self.batch.h, self.cid, STATE_GRID, out.ctypes.data, out.nbytes))
+        return out
+
+    def set_lattice(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self._check(load().hlbm_set_state(self.batch.h, self.cid, STATE_LATTICE, f.ctypes.data, f.nbytes))
+
+    def set_grid(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self._check(load().hlbm_set_state(self.batch.h, self.cid, STATE_GRID, f.ctypes.data, f.nbytes))
+
+
+class Batch:
+    """Many lamina cases advanced together by the case-batched kernels.
+    ``configs``: list of keyword dicts as for :class:`Case` (each with its
+    own max_steps); all share one storage type."""
+
+    def __init__(self, configs, storage=FP64):
+        L = load()
+        if isinstance(storage, str):
+            storage = STORAGE[storage]
+        arr = (Config * len(configs))()
+        for i, c in enumerate(configs):
+            c = dict(c)
+            arr[i] = Config(c["nx"], c["ny"], c.get("nux", 0), c.get("nuy", 0), c.get("h_u", 1.0),
+                            c.get("b", 0.0), c.get("thickness", 1.0), c.get("tau", 0.8), c.get("kc", 0.0),
+                            c.get("beta", 0.0), c.get("n_sub", 0), c.get("bc", BC_PERIODIC_X_WALLS_Y),
+                            storage, c.get("flags", 0), 0, 0, c.get("max_steps", 0))
+        h = C.c_void_p()
+        rc = L.hlbm_create(arr, len(configs), C.byref(h))
+        if rc != 0:
+            raise HlbmError(rc, L.hlbm_last_error(None).decode())
+        self.h = h
+        self.cases = []
+        for i, c in enumerate(configs):
+            m = _Member(self, i, c["nx"], c["ny"], 0)
+            m.nnode = m.info().nnode
+            self.cases.append(m)
+
+    def _check(self, rc):
+        if rc != 0:
+            raise HlbmError(rc, load().hlbm_last_error(self.h).decode())
+
+    def __len__(self):
+        return len(self.cases)
+
+    def __getitem__(self, i):
+        return self.cases[i]
+
+    def step(self, n):
+        self._check(load().hlbm_step(self.h, n))
+
+    def tune(self, trial_steps=16, schedule=None):
+        """Autotune (trial_steps > 0) or apply ``schedule`` (dict) as given."""
+        t = Tuning()
+        if schedule:
+            for k, v in schedule.items():
+                setattr(t, k, v)
+            trial_steps = 0
+        self._check(load().hlbm_tune(self.h, trial_steps, C.byref(t)))
+        return t.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().hlbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def case_from_preset(cfg: dict, **overrides) -> Case:

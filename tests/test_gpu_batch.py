@@ -1,0 +1,115 @@
+"""The case-batched path (hlbm_create with ncases > 1) against single cases.
+
+Every case of a batch must compute exactly the bits it computes alone (the
+single-case path is parity-tested against the oracle), whatever schedule the
+autotuner picks; cases stop at their own max_steps; a case whose force turns
+non-finite stops and is reported while the others carry on.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2006_13631_amd import hlbm
+from paper_2006_13631_amd.workloads import preset
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _cases():
+    a = preset("tiny_ragged")
+    a["max_steps"] = a.pop("steps")                      # 60 steps, odd grid width
+    b = preset("tiny_fine_grid")
+    b["max_steps"] = b.pop("steps")                      # 40 steps, h_u = 0.2, n = 32
+    c = preset("lamina_128x64")
+    c.pop("ckpt_every")
+    c.pop("steps")
+    c["max_steps"] = 90                                  # n = 10
+    d = preset("tiny_adjoint", bc=hlbm.BC_PERIODIC)
+    d.pop("steps")
+    d["max_steps"] = 75
+    return [a, b, c, d]
+
+
+def _solo(cfg, storage):
+    g = hlbm.Case(storage=storage, **cfg)
+    g.step(cfg["max_steps"])
+    return g
+
+
+def _same(batch_member, solo):
+    assert np.array_equal(batch_member.history(), solo.history())
+    assert np.array_equal(batch_member.lattice(), solo.lattice())
+    assert np.array_equal(batch_member.grid(), solo.grid())
+
+
+@pytest.mark.parametrize("storage", [hlbm.FP64, hlbm.FP32, hlbm.FP16_DEV])
+def test_batch_matches_single_cases_bitwise(storage):
+    _say("batch vs single, storage", storage)
+    cfgs = _cases()
+    batch = hlbm.Batch(cfgs, storage=storage)
+    batch.step(max(c["max_steps"] for c in cfgs))
+    for i, c in enumerate(cfgs):
+        inf = batch[i].info()
+        assert inf.step == c["max_steps"] and inf.status == hlbm.STATUS_DONE
+        _same(batch[i], _solo(c, storage))
+
+
+@pytest.mark.parametrize("schedule", [
+    dict(steps_per_graph=4, lattice_threads=128, substep_threads=0, order=1),
+    dict(steps_per_graph=16, lattice_threads=256, substep_threads=512, order=0),
+    dict(steps_per_graph=1, lattice_threads=64, substep_threads=0, order=1),
+])
+def test_schedules_do_not_change_results(schedule):
+    _say("schedule", schedule)
+    cfgs = _cases()
+    batch = hlbm.Batch(cfgs, storage=hlbm.FP32)
+    got = batch.tune(schedule=schedule)
+    assert got["steps_per_graph"] == schedule["steps_per_graph"]
+    # several calls, stopping in the middle of graphs
+    for n in (7, 33, 100):
+        batch.step(n)
+    for i, c in enumerate(cfgs):
+        _same(batch[i], _solo(c, hlbm.FP32))
+
+
+def test_autotune_then_run():
+    _say("autotune")
+    cfgs = _cases()
+    batch = hlbm.Batch(cfgs, storage=hlbm.FP32)
+    t = batch.tune(trial_steps=8)
+    _say("chosen", t)
+    assert t["steps_per_graph"] in (4, 8, 16) and t["ms_per_step"] > 0
+    for m in batch.cases:
+        assert m.info().step == 0
+    batch.step(200)
+    for i, c in enumerate(cfgs):
+        _same(batch[i], _solo(c, hlbm.FP32))
+    with pytest.raises(hlbm.HlbmError) as e:
+        batch.tune(trial_steps=4)
+    assert e.value.code == hlbm.E_STATE
+
+
+def test_unstable_case_stops_alone():
+    _say("unstable member")
+    cfgs = _cases()
+    batch = hlbm.Batch(cfgs, storage=hlbm.FP64)
+    g = batch[1].grid()
+    g[:] = np.nan                         # the first force of case 1 is not finite
+    batch[1].set_grid(g)
+    batch.step(100)
+    inf = batch[1].info()
+    assert inf.status == hlbm.STATUS_UNSTABLE and inf.step < cfgs[1]["max_steps"]
+    for i in (0, 2, 3):
+        assert batch[i].info().status == hlbm.STATUS_DONE
+        _same(batch[i], _solo(cfgs[i], hlbm.FP64))
+
+
+def test_batch_has_no_adjoint():
+    b = hlbm.Batch(_cases()[:2])
+    rc = hlbm.load().hlbm_adjoint(b.h, 0, hlbm._ptr(np.zeros(2)), 1, hlbm._ptr(np.zeros(3)))
+    assert rc == hlbm.E_UNSUPPORTED
