@@ -26,6 +26,8 @@ from __future__ import annotations
 import argparse
 import json
 import math
+
+import numpy as np
 import os
 import sys
 import time
@@ -138,6 +140,98 @@ def adjoint_leg(workload, storage, W_ckpt, fd_step, steps=None):
     }
 
 
+def sweep_leg(seed=0, periods=10.0, loop=True, tune_steps=8, chunk=4000, only=None):
+    """The (KC, beta) sweep: all cases as one FP32 batch (autotuned schedule)
+    against the plain FP64 loop over the same cases one by one; Theta of each
+    case compared at the 1e-3 relative bar."""
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.workloads import sweep_cases
+    cases, flagged = sweep_cases(seed, periods)
+    if only:
+        cases = [cases[i] for i in only]
+        flagged = [flagged[i] for i in only]
+    # a lamina faster than one lattice unit per step cannot run on the
+    # lattice at all (the library rejects it): counted, not run
+    speed = [c["kc"] * (c["tau"] - 0.5) / 3.0 * c["beta"] / c["b"] for c in cases]
+    rejected = sum(1 for u in speed if u >= 1.0)
+    keep = [i for i, u in enumerate(speed) if u < 1.0]
+    cases = [cases[i] for i in keep]
+    flagged = [flagged[i] for i in keep]
+    n = len(cases)
+    lat = sum(c["nx"] * c["ny"] * c["max_steps"] for c in cases)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch = H.Batch(cases, storage=H.FP32)
+    t_create = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tuning = batch.tune(trial_steps=tune_steps)
+    t_tune = time.perf_counter() - t0
+    print(f"# sweep: {n} cases, FP32 batch, schedule {tuning}", file=sys.stderr, flush=True)
+    longest = max(c["max_steps"] for c in cases)
+    t0 = time.perf_counter()
+    done = 0
+    while done < longest:
+        m = min(chunk, longest - done)
+        batch.step(m)
+        done += m
+        running = sum(1 for k in range(n) if batch[k].info().status == H.STATUS_RUNNING)
+        print(f"# batch step {done}/{longest}, running {running}, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+    t_batch = time.perf_counter() - t0
+
+    def theta_of(member):
+        try:
+            return member.theta()
+        except H.HlbmError as e:  # fit window holds fewer than two samples
+            if e.code != H.E_ARG:
+                raise
+            return None
+    th32 = [theta_of(batch[k]) if batch[k].info().status == H.STATUS_DONE else None for k in range(n)]
+    st32 = [batch[k].info().status for k in range(n)]
+    batch.close()
+    out = {"metric": "parametric sweep throughput at equal force accuracy", "unit": "cases/hour",
+           "higher_is_better": True, "cases": n, "rejected_speed_above_1": rejected,
+           "flagged_mach": int(sum(flagged)),
+           "workload": f"{n} (KC, beta) cases, seed {seed}, {periods:g} periods each, lattice 256^2..1024^2, "
+                       f"grid 4b x b, b = size/8",
+           "lattice_node_steps": lat,
+           "batch": {"storage": "f32", "schedule": tuning, "create_s": round(t_create, 2),
+                     "tune_s": round(t_tune, 2), "run_s": round(t_batch, 2),
+                     "cases_per_hour": round(n / ((t_create + t_tune + t_batch) / 3600.0), 1),
+                     "cases_per_hour_run_only": round(n / (t_batch / 3600.0), 1),
+                     "diverged": int(sum(1 for x in st32 if x == H.STATUS_UNSTABLE))}}
+    out["value"] = out["batch"]["cases_per_hour"]
+    if loop:
+        th64, st64, t_loop = [], [], 0.0
+        for k, c in enumerate(cases):
+            t0 = time.perf_counter()
+            g = H.Case(storage=H.FP64, **c)
+            try:
+                g.step(c["max_steps"])
+                st64.append(H.STATUS_DONE)
+            except H.HlbmError as e:
+                if e.code != H.E_UNSTABLE:
+                    raise
+                st64.append(H.STATUS_UNSTABLE)
+            th64.append(theta_of(g) if st64[-1] == H.STATUS_DONE else None)
+            g.close()
+            t_loop += time.perf_counter() - t0
+            print(f"# fp64 loop case {k + 1}/{n} ({c['nx']}^2, {c['max_steps']} steps): {t_loop:.1f} s",
+                  file=sys.stderr, flush=True)
+        errs = [abs(a - b) / abs(b) for a, b in zip(th32, th64) if a is not None and b is not None]
+        finite64 = sum(1 for b in th64 if b is not None)
+        out["loop"] = {"storage": "f64", "run_s": round(t_loop, 2),
+                       "cases_per_hour": round(n / (t_loop / 3600.0), 1),
+                       "diverged": int(sum(1 for x in st64 if x == H.STATUS_UNSTABLE))}
+        out["speedup"] = round(out["value"] / out["loop"]["cases_per_hour"], 3)
+        out["theta"] = {"finite_in_f64": finite64,
+                        "within_1e-3": int(sum(1 for e in errs if e <= 1e-3)),
+                        "max_rel_err": max(errs) if errs else None,
+                        "median_rel_err": float(np.median(errs)) if errs else None}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +248,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=None)
     ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run only the parametric sweep (FP32 batch vs FP64 per-case loop) and print its line")
+    ap.add_argument("--sweep-periods", type=float, default=10.0)
+    ap.add_argument("--sweep-no-loop", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
@@ -162,6 +260,11 @@ def main():
     import torch
     from paper_2006_13631_amd import hlbm as H
     from paper_2006_13631_amd.workloads import preset
+
+    if args.sweep:
+        torch.cuda.set_device(0)
+        print(json.dumps(sweep_leg(periods=args.sweep_periods, loop=not args.sweep_no_loop)), flush=True)
+        return
 
     cfg = preset(args.workload)
     steps = args.steps if args.steps is not None else min(cfg["steps"], 1000)

@@ -10,6 +10,8 @@ as y = A sin(omega t) with KC = 2 pi A / b and beta = omega b^2 / (2 pi nu).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 # name -> parameters (lattice nx*ny, body-fitted grid nux*nuy, lamina width b,
@@ -67,6 +69,29 @@ def batch_cases(seed: int = 0, n_kc: int = 8, n_beta: int = 8):
             cases.append(dict(nx=n, ny=n, nux=4 * b, nuy=b, h_u=1.0, b=float(b), thickness=1.0,
                               kc=float(kc), beta=float(beta)))
     return cases
+
+
+def sweep_cases(seed: int = 0, periods: float = 10.0, mach: float = 0.05):
+    """The parametric sweep as runnable configurations: batch_cases(seed) with
+    tau chosen to hold the lattice Mach number U sqrt(3) at ``mach``, where
+    U = A omega = KC nu beta / b, i.e. tau = min(0.9, 1/2 + 3 nu*) with
+    nu* = (mach / sqrt(3)) b / (KC beta), but not below 0.52 (such cases run
+    above ``mach`` and are flagged), and ``periods`` oscillation periods of
+    T = b^2 / (nu beta) steps each. Returns (configs, flagged)."""
+    out, flagged = [], []
+    u_star = mach / math.sqrt(3.0)
+    for c in batch_cases(seed):
+        nu_star = u_star * c["b"] / (c["kc"] * c["beta"])
+        tau = min(0.9, 0.5 + 3.0 * nu_star)
+        flag = tau < 0.52
+        if flag:
+            tau = 0.52
+        nu = (tau - 0.5) / 3.0
+        period = c["b"] ** 2 / (nu * c["beta"])
+        cfg = dict(c, tau=tau, max_steps=int(math.ceil(periods * period)))
+        out.append(cfg)
+        flagged.append(flag)
+    return out, flagged
 
 
 def random_populations(shape, seed: int, base: np.ndarray, spread: float = 0.02) -> np.ndarray:
