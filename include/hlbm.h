@@ -201,9 +201,13 @@ int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
                      double *C);
 
 /* Per-kernel timing with HIP events recorded on the stream each kernel is
- * launched on. hlbm_timing(h, 1) clears the accumulators and turns event
- * recording on for later hlbm_step calls; 0 turns it off. hlbm_timing_get
- * returns for kernel id (HLBM_K_*) the summed milliseconds and launch count. */
+ * launched on. hlbm_timing(h, level) clears the accumulators and, for later
+ * hlbm_step and hlbm_adjoint calls, records: level 1, every kernel of the
+ * step (events between all kernels); level 2, the stream-collide alone, by
+ * events taken at that kernel's own start and end and nothing else in the
+ * step; 0 turns recording off. Timed steps are launched one by one instead
+ * of as graphs. hlbm_timing_get returns for kernel id (HLBM_K_*) the summed
+ * milliseconds and launch count. */
 #define HLBM_K_STREAM_COLLIDE 0 /* lattice stream-collide, Eq.(LBE)            */
 #define HLBM_K_LATTICE_FROM_GRID 1 /* Eq.(postcollision2_s)                    */
 #define HLBM_K_GRID_SUBSTEPS 2  /* donors + n sub-steps, Eqs.(ulbe),(postcollision2_u) */

@@ -193,6 +193,16 @@ class Case final : public CaseBase {
   }
 
   // Enqueue one structured step t_k -> t_{k+1} (host bookkeeping included).
+  // Stream-collide with its own start and end events when timing is on
+  // (the events are taken at the kernel's own start and end on its stream).
+  void stream_collide_timed(const CaseView<T, R> &v) {
+    if (timing_) {
+      Kernels<T, R>::stream_collide(v, s_main_, tev_[tslot_][8], tev_[tslot_][2]);
+    } else {
+      Kernels<T, R>::stream_collide(v, s_main_);
+    }
+  }
+
   hipError_t enqueue_step() {
     hipError_t e = hipSuccess;
 #define ENQ(expr)                  \
@@ -201,19 +211,19 @@ class Case final : public CaseBase {
     if (e != hipSuccess) return e; \
   } while (0)
     CaseView<T, R> v = view();
-    if (timing_) ENQ(hipEventRecord(tev_[tslot_][0], s_main_));
+    if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][0], s_main_));
     if (has_grid_) {
       // 1. lattice interpolation nodes from the grid at t_k, Eq.(postcollision2_s)
       Kernels<T, R>::lattice_from_grid(v, (const R *)gbuf_[gcur_], s_main_);
-      if (timing_) ENQ(hipEventRecord(tev_[tslot_][1], s_main_));
+      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][1], s_main_));
       if (s_grid_ != s_main_) {
         ENQ(hipEventRecord(ev_fork_, s_main_));
         ENQ(hipStreamWaitEvent(s_grid_, ev_fork_, 0));
       }
       // 2. lattice stream-collide, Eq.(LBE)
-      Kernels<T, R>::stream_collide(v, s_main_, timing_ ? tev_[tslot_][8] : nullptr, timing_ ? tev_[tslot_][2] : nullptr);
+      stream_collide_timed(v);
       // 3.-6. grid path: donors, n sub-steps, refill, force
-      if (timing_) ENQ(hipEventRecord(tev_[tslot_][3], s_grid_));
+      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][3], s_grid_));
       Kernels<T, R>::interface_donors(v, s_grid_);
       int cur = gcur_;
       for (int m = 0; m < d_.n; m += kSubstepBlock) {
@@ -221,21 +231,21 @@ class Case final : public CaseBase {
         Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_);
         cur = 1 - cur;
       }
-      if (timing_) ENQ(hipEventRecord(tev_[tslot_][4], s_grid_));
+      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][4], s_grid_));
       Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
-      if (timing_) ENQ(hipEventRecord(tev_[tslot_][5], s_grid_));
+      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][5], s_grid_));
       Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_);
-      if (timing_) ENQ(hipEventRecord(tev_[tslot_][6], s_grid_));
+      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][6], s_grid_));
       gcur_ = 1 - cur;
       if (s_grid_ != s_main_) {
         ENQ(hipEventRecord(ev_join_, s_grid_));
         ENQ(hipStreamWaitEvent(s_main_, ev_join_, 0));
       }
     } else {
-      if (timing_) ENQ(hipEventRecord(tev_[tslot_][1], s_main_));
-      Kernels<T, R>::stream_collide(v, s_main_, timing_ ? tev_[tslot_][8] : nullptr, timing_ ? tev_[tslot_][2] : nullptr);
+      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][1], s_main_));
+      stream_collide_timed(v);
     }
-    if (timing_) ENQ(hipEventRecord(tev_[tslot_][7], s_main_));
+    if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][7], s_main_));
     if (timing_) ++tslot_;
     ENQ(hipGetLastError());
     std::swap(lat_[0], lat_[1]);
@@ -500,7 +510,8 @@ class Case final : public CaseBase {
       tms_[i] = 0.0;
       tcount_[i] = 0;
     }
-    timing_ = on != 0;
+    if (on < 0 || on > 2) return fail(HLBM_E_ARG, "timing level must be 0, 1 or 2");
+    timing_ = on;
     return HLBM_OK;
   }
 
@@ -766,7 +777,8 @@ class Case final : public CaseBase {
   // Accumulates the timings of the steps recorded in the event ring (the
   // steps ran back to back; only here does the host wait for them).
   hipError_t harvest() {
-    hipError_t e = hipEventSynchronize(tev_[tslot_ - 1][7]);
+    hipError_t e = hipEventSynchronize(tev_[tslot_ - 1][2]);
+    if (e == hipSuccess) e = hipStreamSynchronize(s_main_);
     if (e != hipSuccess) return e;
     for (int i = 0; i < tslot_; ++i) {
       hipEvent_t *t = tev_[i];
@@ -778,6 +790,7 @@ class Case final : public CaseBase {
         }
       };
       add(HLBM_K_STREAM_COLLIDE, t[8], t[2]);
+      if (timing_ != 1) continue;
       if (has_grid_) {
         add(HLBM_K_LATTICE_FROM_GRID, t[0], t[1]);
         add(HLBM_K_GRID_SUBSTEPS, t[3], t[4]);
@@ -1080,7 +1093,7 @@ class Case final : public CaseBase {
   static constexpr int kTimingRing = 64;  // steps recorded between harvests
   hipEvent_t tev_[kTimingRing][9] = {};
   int tslot_ = 0;
-  bool timing_ = false;
+  int timing_ = 0;  // 1: every kernel, 2: the stream-collide only
   double tms_[8] = {};
   int64_t tcount_[8] = {};
   std::vector<void *> owned_;

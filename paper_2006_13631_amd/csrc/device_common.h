@@ -59,15 +59,21 @@ struct Stor<__half> {  // deviation from the rest equilibrium w_i
   }
 };
 
+// Fused multiply-add written out: the kernels are compiled without implicit
+// contraction, so every fusion is explicit and rounds the same wherever the
+// expression is inlined.
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // ---- D2Q9 equilibrium and moments ------------------------------------------
 // Eq.(local_eq) with c_s^2 = 1/3: w rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
 template <class R>
 __device__ __forceinline__ void equilibrium(R rho, R ux, R uy, R e[9]) {
-  const R uu = R(1.5) * (ux * ux + uy * uy);
+  const R one_uu = fmad(R(-1.5), fmad(ux, ux, uy * uy), R(1));
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    const R cu = R(CXd[q]) * ux + R(CYd[q]) * uy;
-    e[q] = wgt<R>(q) * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - uu);
+    const R cu = R(CXd[q]) * ux + R(CYd[q]) * uy;  // c components are 0 or +-1: exact
+    e[q] = wgt<R>(q) * rho * fmad(R(4.5) * cu, cu, fmad(R(3), cu, one_uu));
   }
 }
 

@@ -55,7 +55,7 @@ __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, co
   moments<R>(f, rho, ux, uy);
   equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) Stor<T>::st_stream(B, q * plane + c, q, f[q] - v.inv_tau * (f[q] - e[q]));
+  for (int q = 0; q < 9; ++q) Stor<T>::st_stream(B, q * plane + c, q, fmad(-v.inv_tau, f[q] - e[q], f[q]));
 }
 
 template <class T, class R>
@@ -337,11 +337,11 @@ __device__ __forceinline__ void grid_substeps_block(
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
           const R fq = sl[row[s] + q];
-          if (CXd[q] != 0) ax += gx[u][s] * fq;
-          if (CYd[q] != 0) ay += gy[u][s] * fq;
-          sc += cc[u][s] * sl[row[s] + 9 + q];
+          if (CXd[q] != 0) ax = fmad(gx[u][s], fq, ax);
+          if (CYd[q] != 0) ay = fmad(gy[u][s], fq, ay);
+          sc = fmad(cc[u][s], sl[row[s] + 9 + q], sc);
         }
-        out[u][q] = sl[row[SELF_SLOT] + q] + dt * (R(CXd[q]) * ax + R(CYd[q]) * ay) - dt_tau * sc;
+        out[u][q] = fmad(-dt_tau, sc, fmad(dt, R(CXd[q]) * ax + R(CYd[q]) * ay, sl[row[SELF_SLOT] + q]));
       }
       if (typ[u] == NODE_WALL && upd[u]) {
         // wall nodes: impose the lamina velocity, keep rho and f^neq

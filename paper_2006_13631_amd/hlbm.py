@@ -177,8 +177,9 @@ class Case:
         self._check(load().hlbm_get_stencil(self.h, kmax, _ptr(nbr, C.c_int32), _ptr(S), _ptr(Cm)))
         return nbr, S, Cm
 
-    def timing(self, on=True):
-        self._check(load().hlbm_timing(self.h, 1 if on else 0))
+    def timing(self, level=1):
+        """1: every kernel of the step; 2: the stream-collide alone; 0: off."""
+        self._check(load().hlbm_timing(self.h, int(level)))
 
     def timing_get(self, kernel):
         ms = C.c_double()

@@ -1,6 +1,7 @@
 """Summaries of rocprofv3 CSV output (kernel statistics and HBM counters).
 
-    python -m paper_2006_13631_amd.profiling stats KERNEL_STATS_CSV --out FILE --command CMD
+    python -m paper_2006_13631_amd.profiling stats KERNEL_STATS_CSV --out FILE --command CMD \
+        [--trace KERNEL_TRACE_CSV --kernel NAME --windows A:B,C:D]
     python -m paper_2006_13631_amd.profiling traffic --fetch PMC_CSV --write PMC_CSV \
         --kernel k_stream_collide --copy-bytes N --out FILE --command CMD
 
@@ -42,6 +43,21 @@ def stats_table(path: str) -> str:
         lines.append(f"{_short(r['Name'])[:46]:46s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.3f} "
                      f"{float(r['MinNs']) / 1e3:9.3f} {float(r['MaxNs']) / 1e3:9.3f} {float(r['Percentage']):7.2f}")
     return "\n".join(lines)
+
+
+def window_table(trace: str, kernel: str, windows: str) -> str:
+    """Mean duration of a kernel's launches in index windows [a, b) of the
+    trace (launches in the order they ran)."""
+    rows = [r for r in csv.DictReader(open(trace)) if kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
+    out = [f"{kernel}: mean duration by launch window (launch index, in order)"]
+    for w in windows.split(","):
+        a, b = (int(x) for x in w.split(":"))
+        seg = d[a:b]
+        if seg:
+            out.append(f"  launches {a:6d}..{b - 1:6d}: {len(seg):5d} launches, avg {sum(seg) / len(seg):9.3f} us")
+    return "\n".join(out)
 
 
 def _per_dispatch(path: str, counter: str):
@@ -86,6 +102,10 @@ def main(argv=None):
     s.add_argument("csv")
     s.add_argument("--out", required=True)
     s.add_argument("--command", required=True)
+    s.add_argument("--trace")
+    s.add_argument("--kernel", default="k_stream_collide")
+    s.add_argument("--windows")
+    s.add_argument("--note", default="")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -98,6 +118,10 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         text = f"# rocprofv3 kernel statistics\n# command: {a.command}\n" + stats_table(a.csv) + "\n"
+        if a.trace and a.windows:
+            text += "\n" + window_table(a.trace, a.kernel, a.windows) + "\n"
+        if a.note:
+            text += "".join(f"# {line}\n" for line in a.note.split("\n"))
         open(a.out, "w").write(text)
         print(text)
     else:
