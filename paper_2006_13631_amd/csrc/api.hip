@@ -228,7 +228,8 @@ class Case final : public CaseBase {
       int cur = gcur_;
       for (int m = 0; m < d_.n; m += kSubstepBlock) {
         const int cnt = std::min(kSubstepBlock, d_.n - m);
-        Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_);
+        Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_, nullptr, nullptr,
+                                     nullptr, 0, substep_variant_);
         cur = 1 - cur;
       }
       if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][4], s_grid_));
@@ -512,6 +513,52 @@ class Case final : public CaseBase {
     }
     if (on < 0 || on > 2) return fail(HLBM_E_ARG, "timing level must be 0, 1 or 2");
     timing_ = on;
+    return HLBM_OK;
+  }
+
+  // Time the sub-step variants on the current grid: every launch reads
+  // gbuf_[gcur_] (never written here) and writes the free buffer, which the
+  // next step overwrites before reading, so the state is untouched.
+  int tune(int trial_steps, hlbm_tuning *t) override {
+    if (!t || trial_steps < 0) return fail(HLBM_E_ARG, "invalid tuning request");
+    if (!has_grid_) return fail(HLBM_E_UNSUPPORTED, "a case without a grid has nothing to tune");
+    if (trial_steps == 0) {
+      if (t->substep_variant < -1 || t->substep_variant >= kSubstepVariants)
+        return fail(HLBM_E_ARG, "invalid sub-step variant");
+      substep_variant_ = t->substep_variant;
+      *t = hlbm_tuning{0, 0, substep_variant_, 0, 0.0};
+      return HLBM_OK;
+    }
+    HIPCHK(hipDeviceSynchronize());
+    const CaseView<T, R> v = view();
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = default_substep_variant<R>();
+    float best_ms = 3e38f;
+    hipError_t e = hipSuccess;
+    for (int sv = 0; sv < kSubstepVariants && e == hipSuccess; ++sv) {
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first pass warms up
+        e = hipEventRecord(e0, s_grid_);
+        for (int i = 0; i < trial_steps; ++i)
+          for (int m = 0; m < d_.n; m += kSubstepBlock)
+            Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[gcur_], (R *)gbuf_[1 - gcur_], m,
+                                         std::min(kSubstepBlock, d_.n - m), s_grid_, nullptr, nullptr, nullptr, 0, sv);
+        if (e == hipSuccess) e = hipEventRecord(e1, s_grid_);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && rep == 1 && ms < best_ms) {
+          best_ms = ms;
+          best = sv;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(e);
+    substep_variant_ = best;
+    *t = hlbm_tuning{0, 0, best, 0, (double)best_ms / trial_steps};
     return HLBM_OK;
   }
 
@@ -1021,7 +1068,7 @@ class Case final : public CaseBase {
       for (int m = 0; m < d_.n; m += kSubstepBlock) {
         const int cnt = std::min(kSubstepBlock, d_.n - m);
         Kernels<T, R>::grid_substeps(v, tape_grid(t, j, m), tape_grid(t, j, m + cnt), m, cnt, st, tape_grid(t, j, 0),
-                                     tape_wall(t, j), widx_, std::max(n_wall_, 1));
+                                     tape_wall(t, j), widx_, std::max(n_wall_, 1), substep_variant_);
       }
       Kernels<T, R>::refill(v, tape_grid(t, j, d_.n), tape_grid(t, j + 1, 0), st);
     }
@@ -1094,6 +1141,7 @@ class Case final : public CaseBase {
   hipEvent_t tev_[kTimingRing][9] = {};
   int tslot_ = 0;
   int timing_ = 0;  // 1: every kernel, 2: the stream-collide only
+  int substep_variant_ = -1;  // grid sub-step kernel variant (-1: the default for R)
   double tms_[8] = {};
   int64_t tcount_[8] = {};
   std::vector<void *> owned_;
@@ -1214,7 +1262,7 @@ class Batch final : public CaseBase {
     for (int i = 0; i < n; ++i) v[i] = cases_[i]->batched_view();
     HIPCHK(hipMalloc(&views_, n * sizeof(CaseView<T, R>)));
     HIPCHK(hipMemcpy(views_, v.data(), n * sizeof(CaseView<T, R>), hipMemcpyHostToDevice));
-    tuning_ = {8, 256, 0, 0, 0.0};
+    tuning_ = {8, 256, -1, 0, 0.0};
     return HLBM_OK;
   }
 
@@ -1249,7 +1297,7 @@ class Batch final : public CaseBase {
       if (c->steps_taken() != 0) return fail(HLBM_E_STATE, "tuning must precede the first step");
     if (trial_steps == 0) {
       if (t->steps_per_graph < 1 || t->steps_per_graph > 64 || t->lattice_threads < 64 || t->lattice_threads > 256 ||
-          t->lattice_threads % 64 || (t->substep_threads != 0 && t->substep_threads != 512) || t->order < 0 ||
+          t->lattice_threads % 64 || t->substep_variant < -1 || t->substep_variant >= kSubstepVariants || t->order < 0 ||
           t->order > 1)
         return fail(HLBM_E_ARG, "invalid schedule");
       tuning_ = *t;
@@ -1275,13 +1323,12 @@ class Batch final : public CaseBase {
       if (cases_[i]->max_steps() >= trial_steps) all.push_back(i);
     hlbm_tuning best = tuning_;
     double best_ms = 1e300;
-    const int nsub_opts = sizeof(R) == 8 ? 1 : 2;
     int rc = HLBM_OK;
     for (int g : {4, 8, 16})
       for (int lt : {128, 256})
-        for (int so = 0; so < nsub_opts && rc == HLBM_OK; ++so)
+        for (int sv = 0; sv < kSubstepVariants && rc == HLBM_OK; ++sv)
           for (int ord = 0; ord < 2 && rc == HLBM_OK; ++ord) {
-            tuning_ = {g, lt, so ? 512 : 0, ord, 0.0};
+            tuning_ = {g, lt, sv, ord, 0.0};
             invalidate();
             float ms = 0.f;
             rc = timed_trial(all, trial_steps, &ms);
@@ -1401,7 +1448,9 @@ class Batch final : public CaseBase {
       for (int c : act) {
         const CaseView<T, R> v = cases_[c]->batched_view();
         if ((v.n_sub + kSubstepBlock - 1) / kSubstepBlock <= i) continue;
-        const int tiles = ((v.nux + 63) / 64) * ((v.nuy + 3) / 4);
+        int tx, ty;
+        substep_tile(tuning_.substep_variant < 0 ? default_substep_variant<R>() : tuning_.substep_variant, &tx, &ty);
+        const int tiles = ((v.nux + tx - 1) / tx) * ((v.nuy + ty - 1) / ty);
         for (int t = 0; t < tiles; ++t) sl.push_back(make_int4(c, t, 0, 0));
       }
       lists_.push_back(List{});
@@ -1418,7 +1467,7 @@ class Batch final : public CaseBase {
     K::batched(BatchKernel::InterfaceDonors, views_, lists_[2].d, lists_[2].n, 0, 256, s_);
     for (size_t i = 5; i < lists_.size(); ++i)
       K::batched(BatchKernel::GridSubsteps, views_, lists_[i].d, lists_[i].n, (int)(i - 5) * kSubstepBlock,
-                 tuning_.substep_threads, s_);
+                 tuning_.substep_variant, s_);
     K::batched(BatchKernel::Refill, views_, lists_[3].d, lists_[3].n, 0, 256, s_);
     K::batched(BatchKernel::Force, views_, lists_[4].d, lists_[4].n, 0, 256, s_);
   }

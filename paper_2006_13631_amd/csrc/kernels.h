@@ -49,6 +49,18 @@ enum class BatchKernel { StreamCollide, LatticeFromGrid, InterfaceDonors, GridSu
 // grid sub-steps advanced per launch (temporal blocking depth)
 constexpr int kSubstepBlock = 4;
 
+// Variants of the grid sub-step kernel (tile of grid nodes per workgroup,
+// workgroup size):
+//   0: 16 x 16, 576 threads   1: 32 x 8, 640 threads
+//   2: 64 x 4, 896 threads    3: 16 x 8, 384 threads
+constexpr int kSubstepVariants = 4;
+template <class R>
+constexpr int default_substep_variant() {
+  return sizeof(R) == 8 ? 1 : 3;  // fastest at the 512 x 128 grid (hlbm_tune measures)
+}
+// tile shape of a sub-step variant (work lists of the batched kernel)
+void substep_tile(int variant, int *tx, int *ty);
+
 template <class T, class R>
 struct Kernels {
   static hipError_t prepare();  // one-time launch attributes (dynamic LDS of the sub-step)
@@ -64,14 +76,18 @@ struct Kernels {
   // before its velocity is imposed in sub-step m at wtape + (3 m + c) nwall
   // + widx[node]
   static void grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
-                            R *tape = nullptr, R *wtape = nullptr, const int *widx = nullptr, int nwall = 0);
+                            R *tape = nullptr, R *wtape = nullptr, const int *widx = nullptr, int nwall = 0,
+                            int variant = -1);
+  template <int V>
+  static void grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
+                              R *tape, R *wtape, const int *widx, int nwall);
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
   static void force(const CaseView<T, R> &v, const R *f, hipStream_t s);
   static void lattice_to_f64(const T *src, double *dst, size_t plane, hipStream_t s);
   // one launch of a case-batched step over a work list of int4 items
   // (case, block x, block y, 0); GridSubsteps: (case, tile) for sub-steps
   // m0 .. m0+3 of every listed case; threads: stream-collide workgroup size
-  // (<= 256) or grid sub-step workgroup size (512 or the default)
+  // (<= 256), or for GridSubsteps the sub-step variant (-1: default)
   static void batched(BatchKernel which, const CaseView<T, R> *views, const int4 *items, int nitems, int m0,
                       int threads, hipStream_t s);
   static void lattice_from_f64(const double *src, T *dst, size_t plane, hipStream_t s);

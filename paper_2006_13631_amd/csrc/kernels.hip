@@ -177,29 +177,32 @@ __global__ __launch_bounds__(256) void kb_interface_donors(const CaseView<T, R> 
 // the lamina velocity while keeping density and non-equilibrium part.
 //
 // One launch advances `count` <= H sub-steps (temporal blocking). A
-// workgroup owns a 64 x 4 tile and stages the tile plus an H-node halo in
+// workgroup owns a TX x TY tile and stages the tile plus an H-node halo in
 // LDS, node-major (f then f^neq, stride 19 so wave64 reads are free of bank
 // conflicts): every node's moments are computed once per sub-step. It also
 // keeps the structured-derived values of nodes on the grid's outer ring and
-// the stencil class of each node. Sub-step s updates the region grown by
-// count-1-s around the tile, so after `count` sub-steps the tile is exact
-// and only it is written back. A lane keeps its region nodes and their 27
-// stencil coefficients in registers for the whole launch. Tiles are dealt to
+// the stencil class and type of each node. Sub-step s updates the region
+// grown by count-1-s around the tile, so after `count` sub-steps the tile is
+// exact and only it is written back. In every sub-step the lanes are dealt
+// afresh over that shrinking rectangle, so no wave works on nodes outside
+// it; stencil coefficients are read from the class table (interior nodes
+// share one class, so the reads are cache broadcasts). Tiles are dealt to
 // the eight XCDs in contiguous bands.
-constexpr int TX = 64, TY = 4;
 constexpr int NS = 19;  // LDS doubles (or floats) per node: f[9], f^neq[9], pad
 
-template <int H>
+template <int TXv, int TYv, int H>
 struct Region {
+  static constexpr int TX = TXv, TY = TYv;
   static constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RN = RX * RY;
   static constexpr int NRING = 2 * RX + 2 * RY;  // region nodes that can lie on the outer ring
+  // nodes updated by the first sub-step of a full block
+  static constexpr int MAXA = (TX + 2 * (H - 1)) * (TY + 2 * (H - 1));
 };
 
 // slot of region node (rx, ry) (global (gi, gj)) in the ring array, or -1
 // when the node is not a grid node on the outer ring
-template <int H>
+template <class G>
 __device__ __forceinline__ int ring_slot(int gi, int gj, int rx, int ry, int nux, int nuy) {
-  using G = Region<H>;
   if (gi < 0 || gj < 0 || gi >= nux || gj >= nuy) return -1;
   if (gj == 0) return rx;
   if (gj == nuy - 1) return G::RX + rx;
@@ -208,43 +211,35 @@ __device__ __forceinline__ int ring_slot(int gi, int gj, int rx, int ry, int nux
   return -1;
 }
 
-template <class R, int H>
+template <class R, class G>
 constexpr size_t substeps_lds_bytes() {
-  using G = Region<H>;
   return sizeof(R) * (size_t)(NS * G::RN + NS * G::NRING) + sizeof(int) * (size_t)G::RN;
 }
 
-// workgroup size: FP64 nodes need the register room of 512 threads, FP32
-// nodes fit 1024 (16 waves on one tile's LDS); a batch may choose others
-template <class R>
-constexpr int substep_threads() {
-  return sizeof(R) == 8 ? 512 : 1024;
-}
-
 // Advances tile t of a grid by `count` sub-steps m0 .. m0+count-1 of step k.
-template <class R, int H, int NT>
+template <class R, class G, int H, int NT>
 __device__ __forceinline__ void grid_substeps_block(
     const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
     const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int t,
     R dt, R dt_tau, const R *__restrict__ uw, int64_t k, int n_sub, int m0, int count,
     R *__restrict__ tape, R *__restrict__ wtape, const int *__restrict__ widx, int nwall) {
-  using G = Region<H>;
-  constexpr int RX = G::RX, RN = G::RN;
-  constexpr int PER = (RN + NT - 1) / NT;
+  constexpr int TX = G::TX, TY = G::TY, RX = G::RX, RN = G::RN;
+  constexpr int SPER = (RN + NT - 1) / NT;      // staging passes
+  constexpr int PER = (G::MAXA + NT - 1) / NT;  // update passes
   extern __shared__ __align__(16) unsigned char lds_raw[];
   R *sl = reinterpret_cast<R *>(lds_raw);   // [RN][NS] grid f, f^neq
   R *rl = sl + NS * RN;                     // [NRING][NS] f*, f^neq* on the outer ring
-  int *scls = reinterpret_cast<int *>(rl + NS * G::NRING);  // stencil class, -1 outside the grid
+  int *scode = reinterpret_cast<int *>(rl + NS * G::NRING);  // 4 * class + type, -1 outside the grid
   const int x0 = (t % tiles_x) * TX - H, y0 = (t / tiles_x) * TY - H;  // region origin
   const bool touches_ring = x0 <= 0 || y0 <= 0 || x0 + RX >= nux || y0 + G::RY >= nuy;
   const size_t N = (size_t)nux * nuy;
 
   // stage the region; a lane's loads are issued together
   {
-    R v[PER][9];
-    bool inside[PER];
+    R v[SPER][9];
+    bool inside[SPER];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
+    for (int u = 0; u < SPER; ++u) {
       const int idx = threadIdx.x + u * NT;
       const int gi = x0 + idx % RX, gj = y0 + idx / RX;
       const bool in = idx < RN && gi >= 0 && gi < nux && gj >= 0 && gj < nuy;
@@ -252,9 +247,12 @@ __device__ __forceinline__ void grid_substeps_block(
       const size_t p = in ? (size_t)gj * nux + gi : 0;
 #pragma unroll
       for (int q = 0; q < 9; ++q) v[u][q] = in ? f[q * N + p] : R(0);
-      if (idx < RN) scls[idx] = in ? cls[p] : -1;
+      if (idx < RN) {
+        const int c = in ? cls[p] : -1;
+        scode[idx] = c >= 0 ? 4 * c + tab[c].type : -1;
+      }
       if (touches_ring && in) {
-        const int rs = ring_slot<H>(gi, gj, idx % RX, idx / RX, nux, nuy);
+        const int rs = ring_slot<G>(gi, gj, idx % RX, idx / RX, nux, nuy);
         if (rs >= 0) {
 #pragma unroll
           for (int q = 0; q < 9; ++q) {
@@ -265,7 +263,7 @@ __device__ __forceinline__ void grid_substeps_block(
       }
     }
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
+    for (int u = 0; u < SPER; ++u) {
       const int idx = threadIdx.x + u * NT;
       if (idx >= RN) continue;
       R e[9], r, vx, vy;
@@ -285,36 +283,36 @@ __device__ __forceinline__ void grid_substeps_block(
   }
   __syncthreads();
 
-  // each lane keeps the same region nodes for all sub-steps, with their
-  // stencil coefficients in registers (27 per node: Gx, Gy, C)
-  R gx[PER][NSLOT], gy[PER][NSLOT], cc[PER][NSLOT];
-  int typ[PER];
+  // the node (region index) and code of every lane in every sub-step
+  int at_s[H][PER], code_s[H][PER];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int idx = threadIdx.x + u * NT;
-    const int c = idx < RN ? scls[idx] : -1;
-    typ[u] = c >= 0 ? tab[c].type : -1;
+  for (int sub = 0; sub < H; ++sub) {
+    const int ex = max(count - 1 - sub, 0);  // region growth still exact after sub-step `sub`
+    const int W = TX + 2 * ex, NA = sub < count ? W * (TY + 2 * ex) : 0, o = H - ex;
 #pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-      gx[u][s] = c >= 0 ? tab[c].Gx[s] : R(0);
-      gy[u][s] = c >= 0 ? tab[c].Gy[s] : R(0);
-      cc[u][s] = c >= 0 ? tab[c].C[s] : R(0);
+    for (int u = 0; u < PER; ++u) {
+      const int j = threadIdx.x + u * NT;
+      const int idx = j < NA ? (o + j / W) * RX + o + j % W : 0;
+      at_s[sub][u] = idx;
+      code_s[sub][u] = j < NA ? scode[idx] : -1;
     }
   }
 
-  for (int sub = 0; sub < count; ++sub) {
-    const int ex = count - 1 - sub;  // region growth still exact after this sub-step
+#pragma unroll
+  for (int sub = 0; sub < H; ++sub) {
+    if (sub >= count) break;
     const R uw_now = uw[k * n_sub + m0 + sub];
     R out[PER][9];
     bool upd[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int idx = threadIdx.x + u * NT;
+      const int idx = at_s[sub][u], code = code_s[sub][u];
       const int rx = idx % RX, ry = idx / RX;
-      upd[u] = idx < RN && typ[u] >= 0 && rx >= H - ex && rx < H + TX + ex && ry >= H - ex && ry < H + TY + ex;
+      upd[u] = code >= 0;
 #pragma unroll
       for (int q = 0; q < 9; ++q) out[u][q] = R(0);
       if (__ballot(upd[u]) == 0) continue;  // nothing to update in this wave
+      const int typ = code & 3;
       const int gi = x0 + rx, gj = y0 + ry;
       // LDS row (offset from the LDS base) of each stencil slot; on the outer
       // ring an interpolation node reads structured-derived values instead
@@ -325,25 +323,26 @@ __device__ __forceinline__ void grid_substeps_block(
         const int di = s % 3 - 1, dj = s / 3 - 1;
         const int cidx = upd[u] ? idx + dj * RX + di : idx;
         row[s] = cidx * NS;
-        if (typ[u] == NODE_INTERFACE && upd[u]) {
-          const int rs = ring_slot<H>(gi + di, gj + dj, rx + di, ry + dj, nux, nuy);
+        if (typ == NODE_INTERFACE && upd[u]) {
+          const int rs = ring_slot<G>(gi + di, gj + dj, rx + di, ry + dj, nux, nuy);
           if (rs >= 0) row[s] = NS * RN + rs * NS;
         }
       }
       // streaming c_q . sum_s G_s f_q,s and collision sum_s C_s f^neq_q,s
+      const GridClass<R> &cl = tab[upd[u] ? code >> 2 : 0];
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         R ax = R(0), ay = R(0), sc = R(0);
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
           const R fq = sl[row[s] + q];
-          if (CXd[q] != 0) ax = fmad(gx[u][s], fq, ax);
-          if (CYd[q] != 0) ay = fmad(gy[u][s], fq, ay);
-          sc = fmad(cc[u][s], sl[row[s] + 9 + q], sc);
+          if (CXd[q] != 0) ax = fmad(cl.Gx[s], fq, ax);
+          if (CYd[q] != 0) ay = fmad(cl.Gy[s], fq, ay);
+          sc = fmad(cl.C[s], sl[row[s] + 9 + q], sc);
         }
         out[u][q] = fmad(-dt_tau, sc, fmad(dt, R(CXd[q]) * ax + R(CYd[q]) * ay, sl[row[SELF_SLOT] + q]));
       }
-      if (typ[u] == NODE_WALL && upd[u]) {
+      if (typ == NODE_WALL && upd[u]) {
         // wall nodes: impose the lamina velocity, keep rho and f^neq
         R e[9], ew[9], r, vx, vy;
         moments<R>(out[u], r, vx, vy);
@@ -365,7 +364,7 @@ __device__ __forceinline__ void grid_substeps_block(
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       if (!upd[u]) continue;
-      const int idx = threadIdx.x + u * NT;
+      const int idx = at_s[sub][u];
       R e[9], r, vx, vy;
       moments<R>(out[u], r, vx, vy);
       equilibrium<R>(r, vx, vy, e);
@@ -403,32 +402,63 @@ __device__ __forceinline__ void grid_substeps_block(
   }
 }
 
-template <class R, int H, int NT>
-__global__ __launch_bounds__(NT) void k_grid_substeps(
+// Variants of the sub-step kernel: tile shape and workgroup size (one lane
+// per region node while staging, so one lane per updated node in every
+// sub-step). Variant 3's LDS fits two workgroups on a CU in FP64.
+template <int V>
+struct SubstepVariant;
+template <>
+struct SubstepVariant<0> {
+  using G = Region<16, 16, kSubstepBlock>;
+  static constexpr int NT = 576;
+};
+template <>
+struct SubstepVariant<1> {
+  using G = Region<32, 8, kSubstepBlock>;
+  static constexpr int NT = 640;
+};
+template <>
+struct SubstepVariant<2> {
+  using G = Region<64, 4, kSubstepBlock>;
+  static constexpr int NT = 896;
+};
+template <>
+struct SubstepVariant<3> {
+  using G = Region<16, 8, kSubstepBlock>;
+  static constexpr int NT = 384;
+};
+
+template <class R, int V>
+__global__ __launch_bounds__(SubstepVariant<V>::NT) void k_grid_substeps(
     const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
     const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int ntiles,
     R dt, R dt_tau, const R *__restrict__ uw, const int64_t *__restrict__ dk, int n_sub, int m0, int count,
     R *__restrict__ tape, R *__restrict__ wtape, const int *__restrict__ widx, int nwall) {
+  using SV = SubstepVariant<V>;
   const int b = blockIdx.x;  // tiles are dealt to the eight XCDs in contiguous bands
   const int t = (ntiles % 8 == 0) ? (b % 8) * (ntiles / 8) + (b / 8) : b;
-  grid_substeps_block<R, H, NT>(f, fout, star_f, star_n, cls, tab, nux, nuy, tiles_x, t, dt, dt_tau, uw, *dk, n_sub,
-                                m0, count, tape, wtape, widx, nwall);
+  grid_substeps_block<R, typename SV::G, kSubstepBlock, SV::NT>(f, fout, star_f, star_n, cls, tab, nux, nuy, tiles_x,
+                                                                t, dt, dt_tau, uw, *dk, n_sub, m0, count, tape, wtape,
+                                                                widx, nwall);
 }
 
 // launch m0 / kSubstepBlock of a batched step: item = (case, tile)
-template <class T, class R, int H, int NT>
-__global__ __launch_bounds__(NT) void kb_grid_substeps(const CaseView<T, R> *__restrict__ views,
-                                                       const int4 *__restrict__ items, int m0) {
+template <class T, class R, int V>
+__global__ __launch_bounds__(SubstepVariant<V>::NT) void kb_grid_substeps(const CaseView<T, R> *__restrict__ views,
+                                                                          const int4 *__restrict__ items, int m0) {
+  using SV = SubstepVariant<V>;
   const int4 it = items[blockIdx.x];
   const CaseView<T, R> &v = views[it.x];
   int64_t k;
   if (!batched_case(v, k)) return;
   const int cur = grid_cur(v, k), i = m0 / kSubstepBlock;
-  const int tiles_x = (v.nux + TX - 1) / TX;
-  grid_substeps_block<R, H, NT>(v.grid[cur ^ (i & 1)], v.grid[cur ^ ((i + 1) & 1)], v.star_f, v.star_n, v.cls,
-                                v.tab, v.nux, v.nuy, tiles_x, it.y, v.dt_u, v.dt_over_tau_u, v.uw, k, v.n_sub, m0,
-                                min(kSubstepBlock, v.n_sub - m0), nullptr, nullptr, nullptr, 0);
+  const int tiles_x = (v.nux + SV::G::TX - 1) / SV::G::TX;
+  grid_substeps_block<R, typename SV::G, kSubstepBlock, SV::NT>(
+      v.grid[cur ^ (i & 1)], v.grid[cur ^ ((i + 1) & 1)], v.star_f, v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x,
+      it.y, v.dt_u, v.dt_over_tau_u, v.uw, k, v.n_sub, m0, min(kSubstepBlock, v.n_sub - m0), nullptr, nullptr,
+      nullptr, 0);
 }
+
 
 // ---- K5: move the grid from y_k to y_{k+1} and refill it ---------------------
 // Each non-wall node is located, at its new position, in the grid of t_k:
@@ -602,18 +632,31 @@ inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
+void substep_tile(int variant, int *tx, int *ty) {
+  switch (variant) {
+    case 1: *tx = SubstepVariant<1>::G::TX, *ty = SubstepVariant<1>::G::TY; break;
+    case 2: *tx = SubstepVariant<2>::G::TX, *ty = SubstepVariant<2>::G::TY; break;
+    case 3: *tx = SubstepVariant<3>::G::TX, *ty = SubstepVariant<3>::G::TY; break;
+    default: *tx = SubstepVariant<0>::G::TX, *ty = SubstepVariant<0>::G::TY; break;
+  }
+}
+
 template <class T, class R>
 hipError_t Kernels<T, R>::prepare() {
-  constexpr int NTd = substep_threads<R>();
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_grid_substeps<R, kSubstepBlock, NTd>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)substeps_lds_bytes<R, kSubstepBlock>());
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_grid_substeps<T, R, kSubstepBlock, NTd>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)substeps_lds_bytes<R, kSubstepBlock>());
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_grid_substeps<T, R, kSubstepBlock, 512>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)substeps_lds_bytes<R, kSubstepBlock>());
+#define HLBM_LDS(V)                                                                                                  \
+  {reinterpret_cast<const void *>(&k_grid_substeps<R, V>), reinterpret_cast<const void *>(&kb_grid_substeps<T, R, V>), \
+   (int)substeps_lds_bytes<R, typename SubstepVariant<V>::G>()}
+  struct {
+    const void *f, *fb;
+    int lds;
+  } fns[] = {HLBM_LDS(0), HLBM_LDS(1), HLBM_LDS(2), HLBM_LDS(3)};
+#undef HLBM_LDS
+  for (const auto &e : fns) {
+    hipError_t rc = hipFuncSetAttribute(e.f, hipFuncAttributeMaxDynamicSharedMemorySize, e.lds);
+    if (rc == hipSuccess) rc = hipFuncSetAttribute(e.fb, hipFuncAttributeMaxDynamicSharedMemorySize, e.lds);
+    if (rc != hipSuccess) return rc;
+  }
+  return hipSuccess;
 }
 
 template <class T, class R>
@@ -643,14 +686,26 @@ void Kernels<T, R>::interface_donors(const CaseView<T, R> &v, hipStream_t s) {
 }
 
 template <class T, class R>
-void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
-                                  R *tape, R *wtape, const int *widx, int nwall) {
-  const int tiles_x = (v.nux + TX - 1) / TX, tiles_y = (v.nuy + TY - 1) / TY;
-  hipLaunchKernelGGL((k_grid_substeps<R, kSubstepBlock, substep_threads<R>()>), dim3(tiles_x * tiles_y),
-                     dim3(substep_threads<R>()),
-                     (substeps_lds_bytes<R, kSubstepBlock>()), s, f, fout, (const R *)v.star_f, (const R *)v.star_n,
+template <int V>
+void Kernels<T, R>::grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
+                                    R *tape, R *wtape, const int *widx, int nwall) {
+  using SV = SubstepVariant<V>;
+  const int tiles_x = (v.nux + SV::G::TX - 1) / SV::G::TX, tiles_y = (v.nuy + SV::G::TY - 1) / SV::G::TY;
+  hipLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT),
+                     (substeps_lds_bytes<R, typename SV::G>()), s, f, fout, (const R *)v.star_f, (const R *)v.star_n,
                      v.cls, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw,
                      (const int64_t *)v.dk, v.n_sub, m0, count, tape, wtape, widx, nwall);
+}
+
+template <class T, class R>
+void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
+                                  R *tape, R *wtape, const int *widx, int nwall, int variant) {
+  switch (variant < 0 ? default_substep_variant<R>() : variant) {
+    case 1: grid_substeps_v<1>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
+    case 2: grid_substeps_v<2>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
+    case 3: grid_substeps_v<3>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
+    default: grid_substeps_v<0>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
+  }
 }
 
 template <class T, class R>
@@ -689,13 +744,17 @@ void Kernels<T, R>::batched(BatchKernel which, const CaseView<T, R> *views, cons
     case BatchKernel::InterfaceDonors:
       hipLaunchKernelGGL((kb_interface_donors<T, R>), g, dim3(256), 0, s, views, items);
       break;
-    case BatchKernel::GridSubsteps:
-      if (threads == 512 && substep_threads<R>() != 512)
-        hipLaunchKernelGGL((kb_grid_substeps<T, R, kSubstepBlock, 512>), g, dim3(512),
-                           (substeps_lds_bytes<R, kSubstepBlock>()), s, views, items, m0);
-      else
-        hipLaunchKernelGGL((kb_grid_substeps<T, R, kSubstepBlock, substep_threads<R>()>), g,
-                           dim3(substep_threads<R>()), (substeps_lds_bytes<R, kSubstepBlock>()), s, views, items, m0);
+    case BatchKernel::GridSubsteps:  // threads: the sub-step variant (-1: default)
+      switch (threads < 0 ? default_substep_variant<R>() : threads) {
+#define HLBM_KB(V)                                                                                                \
+  hipLaunchKernelGGL((kb_grid_substeps<T, R, V>), g, dim3(SubstepVariant<V>::NT),                              \
+                     (substeps_lds_bytes<R, typename SubstepVariant<V>::G>()), s, views, items, m0)
+        case 1: HLBM_KB(1); break;
+        case 2: HLBM_KB(2); break;
+        case 3: HLBM_KB(3); break;
+        default: HLBM_KB(0); break;
+#undef HLBM_KB
+      }
       break;
     case BatchKernel::Refill:
       hipLaunchKernelGGL((kb_refill<T, R>), g, dim3(256), 0, s, views, items);

@@ -56,7 +56,7 @@ class Info(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("steps_per_graph", C.c_int32), ("lattice_threads", C.c_int32),
-                ("substep_threads", C.c_int32), ("order", C.c_int32), ("ms_per_step", C.c_double)]
+                ("substep_variant", C.c_int32), ("order", C.c_int32), ("ms_per_step", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -176,6 +176,17 @@ class Case:
         Cm = np.zeros((self.nnode, kmax))
         self._check(load().hlbm_get_stencil(self.h, kmax, _ptr(nbr, C.c_int32), _ptr(S), _ptr(Cm)))
         return nbr, S, Cm
+
+    def tune(self, trial_steps=4, variant=None):
+        """Pick the grid sub-step kernel variant: time each one over
+        trial_steps structured steps' worth of sub-steps (state untouched), or
+        apply ``variant`` (-1 = default) as given. Returns the schedule."""
+        t = Tuning()
+        if variant is not None:
+            t.substep_variant = variant
+            trial_steps = 0
+        self._check(load().hlbm_tune(self.h, trial_steps, C.byref(t)))
+        return t.as_dict()
 
     def timing(self, level=1):
         """1: every kernel of the step; 2: the stream-collide alone; 0: off."""
@@ -297,6 +308,7 @@ class Batch:
     def tune(self, trial_steps=16, schedule=None):
         """Autotune (trial_steps > 0) or apply ``schedule`` (dict) as given."""
         t = Tuning()
+        t.substep_variant = -1
         if schedule:
             for k, v in schedule.items():
                 setattr(t, k, v)

@@ -60,9 +60,10 @@ def test_batch_matches_single_cases_bitwise(storage):
 
 
 @pytest.mark.parametrize("schedule", [
-    dict(steps_per_graph=4, lattice_threads=128, substep_threads=0, order=1),
-    dict(steps_per_graph=16, lattice_threads=256, substep_threads=512, order=0),
-    dict(steps_per_graph=1, lattice_threads=64, substep_threads=0, order=1),
+    dict(steps_per_graph=4, lattice_threads=128, substep_variant=0, order=1),
+    dict(steps_per_graph=16, lattice_threads=256, substep_variant=1, order=0),
+    dict(steps_per_graph=1, lattice_threads=64, substep_variant=2, order=1),
+    dict(steps_per_graph=8, lattice_threads=192, substep_variant=3, order=0),
 ])
 def test_schedules_do_not_change_results(schedule):
     _say("schedule", schedule)
@@ -75,6 +76,46 @@ def test_schedules_do_not_change_results(schedule):
         batch.step(n)
     for i, c in enumerate(cfgs):
         _same(batch[i], _solo(c, hlbm.FP32))
+
+
+@pytest.mark.parametrize("storage", [hlbm.FP64, hlbm.FP32])
+def test_substep_variants_compute_identical_bits(storage):
+    """The four grid sub-step kernels (tile shape, workgroup size) differ
+    only in which workgroup and lane compute a node."""
+    c = preset("lamina_128x64")
+    c.pop("ckpt_every")
+    n = c.pop("steps") // 4
+    c["max_steps"] = n
+    want = hlbm.Case(storage=storage, **c)
+    want.step(n)
+    for v in range(4):
+        _say("sub-step variant", v, "storage", storage)
+        g = hlbm.Case(storage=storage, **c)
+        assert g.tune(variant=v)["substep_variant"] == v
+        g.step(n)
+        _same(g, want)
+
+
+def test_single_case_tune_leaves_state_alone():
+    _say("single-case tune")
+    c = preset("tiny_ragged")
+    n = c.pop("steps")
+    c["max_steps"] = n
+    a = hlbm.Case(storage=hlbm.FP64, **c)
+    b = hlbm.Case(storage=hlbm.FP64, **c)
+    a.step(n // 2)
+    b.step(n // 2)
+    lat, grid = a.lattice().copy(), a.grid().copy()
+    t = a.tune(trial_steps=2)
+    _say("chosen", t)
+    assert 0 <= t["substep_variant"] < 4 and t["ms_per_step"] > 0
+    assert np.array_equal(a.lattice(), lat) and np.array_equal(a.grid(), grid)
+    a.step(n - n // 2)
+    b.step(n - n // 2)
+    _same(a, b)
+    with pytest.raises(hlbm.HlbmError) as e:
+        a.tune(variant=4)
+    assert e.value.code == hlbm.E_ARG
 
 
 def test_autotune_then_run():
