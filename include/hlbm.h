@@ -112,17 +112,22 @@ typedef struct hlbm_info {
 #define HLBM_STATUS_UNSTABLE 2 /* a non-finite force appeared; the case stopped */
 
 /* Schedule of a handle, chosen by hlbm_tune. None of the choices changes
- * any result: every case computes the same bits. A single case uses only
- * substep_variant. */
+ * any result: every case computes the same bits. A single case uses the
+ * stream-collide shape and the sub-step variant. */
 typedef struct hlbm_tuning {
-  int32_t steps_per_graph; /* structured steps captured in one HIP graph     */
-  int32_t lattice_threads; /* workgroup size of the batched stream-collide   */
+  int32_t steps_per_graph; /* structured steps captured in one HIP graph
+                              (batch)                                      */
+  int32_t lattice_threads; /* stream-collide workgroup width: 64..256, a
+                              multiple of 64                               */
+  int32_t lattice_rows;    /* lattice rows per lane of the stream-collide:
+                              1, 2 or 4                                    */
   int32_t substep_variant; /* grid sub-step kernel (grid nodes per tile,
                               workgroup size): -1 default (FP64 1, else
                               3); 0: 16x16, 576; 1: 32x8, 640; 2: 64x4,
                               896; 3: 16x8, 384                            */
-  int32_t order;           /* 0: work lists case by case; 1: dealt to the 8
-                              XCDs in contiguous chunks                     */
+  int32_t order;           /* batch work lists: 0 case by case; 1 dealt to
+                              the 8 XCDs in contiguous chunks              */
+  int32_t reserved;
   double ms_per_step;      /* measured for the chosen schedule (output)      */
 } hlbm_tuning;
 
@@ -223,16 +228,19 @@ int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
 int hlbm_timing(hlbm_t *h, int32_t on);
 int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count);
 
-/* Autotuner. Batched handle: before its first step, time every candidate
- * schedule (steps per graph 4/8/16, lattice workgroup 128/256, sub-step
- * variant, work-list order) for trial_steps steps of the whole batch, keep
- * the fastest and restore the initial state. Single case (any time, state
- * untouched): time the n sub-steps of one structured step trial_steps times
- * with each sub-step variant, reading the current grid and writing only the
- * free grid buffer, and keep the fastest. trial_steps = 0 applies *t as
- * given instead. *t receives the schedule in use. Errors: HLBM_E_STATE
- * (batch: steps already taken), HLBM_E_ARG (invalid schedule),
- * HLBM_E_UNSUPPORTED (a single case without a grid). */
+/* Autotuner. Batched handle: before its first step, time candidate
+ * schedules for trial_steps steps of the whole batch, one choice at a time
+ * (steps per graph 4/8/16; stream-collide shape 128/256 x 1/2/4 rows;
+ * sub-step variant; work-list order) with the others held at the best so
+ * far, keep the fastest and restore the initial state. Single case (any
+ * time, state untouched): time trial_steps launches of the stream-collide
+ * in each shape and of one step's sub-steps in each variant, reading the
+ * current lattice and grid and writing only their free buffers, and keep
+ * the fastest (ms_per_step: the two chosen kernels' time per step).
+ * trial_steps = 0 applies *t as given instead (single case: lattice_threads
+ * = lattice_rows = 0 keeps the stream-collide shape). *t receives the
+ * schedule in use. Errors: HLBM_E_STATE (batch: steps already taken),
+ * HLBM_E_ARG (invalid schedule). */
 int hlbm_tune(hlbm_t *h, int32_t trial_steps, hlbm_tuning *t);
 
 /* Release the device memory and streams of the handle (NULL is a no-op). */

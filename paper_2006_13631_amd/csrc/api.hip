@@ -91,6 +91,11 @@ class CaseBase {
     }                                                                                 \
   } while (0)
 
+inline bool valid_lattice_shape(const hlbm_tuning &t) {
+  return t.lattice_threads >= 64 && t.lattice_threads <= 256 && t.lattice_threads % 64 == 0 &&
+         (t.lattice_rows == 1 || t.lattice_rows == 2 || t.lattice_rows == 4);
+}
+
 template <class T, class R>
 class Case final : public CaseBase {
  public:
@@ -102,7 +107,8 @@ class Case final : public CaseBase {
     h_ = c.h_u > 0.0 ? c.h_u : 1.0;
     has_grid_ = c.nux > 0 || c.nuy > 0;
     body_ = has_grid_ && c.b > 0.0 && !(c.flags & HLBM_FLAG_NO_BODY);
-    plane_ = (size_t)c.nx * c.ny;
+    nodes_ = (size_t)c.nx * c.ny;
+    plane_ = lattice_plane(c.nx, c.ny);
     if (has_grid_) {
       std::string e;
       if (!build_grid(c.nux, c.nuy, h_, c.b, body_, &grid_, &e)) {
@@ -197,9 +203,9 @@ class Case final : public CaseBase {
   // (the events are taken at the kernel's own start and end on its stream).
   void stream_collide_timed(const CaseView<T, R> &v) {
     if (timing_) {
-      Kernels<T, R>::stream_collide(v, s_main_, tev_[tslot_][8], tev_[tslot_][2]);
+      Kernels<T, R>::stream_collide(v, s_main_, tev_[tslot_][8], tev_[tslot_][2], lattice_threads_, lattice_rows_);
     } else {
-      Kernels<T, R>::stream_collide(v, s_main_);
+      Kernels<T, R>::stream_collide(v, s_main_, nullptr, nullptr, lattice_threads_, lattice_rows_);
     }
   }
 
@@ -332,10 +338,10 @@ class Case final : public CaseBase {
   int get_state(int which, void *buf, size_t bytes) override {
     HIPCHK(hipStreamSynchronize(s_main_));
     if (which == HLBM_STATE_LATTICE) {
-      if (bytes != 9 * plane_ * sizeof(double)) return fail(HLBM_E_ARG, "lattice state size mismatch");
+      if (bytes != 9 * nodes_ * sizeof(double)) return fail(HLBM_E_ARG, "lattice state size mismatch");
       double *tmp = nullptr;
       HIPCHK(hipMalloc(&tmp, bytes));
-      Kernels<T, R>::lattice_to_f64((const T *)lat_[0], tmp, plane_, s_main_);
+      Kernels<T, R>::lattice_to_f64((const T *)lat_[0], tmp, plane_, nodes_, s_main_);
       hipError_t e = hipMemcpyAsync(buf, tmp, bytes, hipMemcpyDeviceToHost, s_main_);
       if (e == hipSuccess) e = hipStreamSynchronize(s_main_);
       (void)hipFree(tmp);
@@ -355,13 +361,15 @@ class Case final : public CaseBase {
     if (which == HLBM_STATE_ADJ_LATTICE || which == HLBM_STATE_ADJ_GRID) {
       if (!adj_done_) return fail(HLBM_E_STATE, "no adjoint has been run");
       const bool lat = which == HLBM_STATE_ADJ_LATTICE;
-      const size_t n = lat ? 9 * plane_ : 9 * (size_t)grid_.nnode;
-      if (bytes != n * sizeof(double)) return fail(HLBM_E_ARG, "adjoint state size mismatch");
-      std::vector<R> tmp(n);
-      HIPCHK(hipMemcpy(tmp.data(), lat ? (void *)alat_[adj_lc_] : (void *)agrid_[adj_gc_], n * sizeof(R),
+      // lattice: [9][plane] on the device, [9][ny][nx] for the caller
+      const size_t per = lat ? nodes_ : (size_t)grid_.nnode, stride = lat ? plane_ : per;
+      if (bytes != 9 * per * sizeof(double)) return fail(HLBM_E_ARG, "adjoint state size mismatch");
+      std::vector<R> tmp(9 * stride);
+      HIPCHK(hipMemcpy(tmp.data(), lat ? (void *)alat_[adj_lc_] : (void *)agrid_[adj_gc_], 9 * stride * sizeof(R),
                        hipMemcpyDeviceToHost));
       double *out = (double *)buf;
-      for (size_t i = 0; i < n; ++i) out[i] = (double)tmp[i];
+      for (int q = 0; q < 9; ++q)
+        for (size_t i = 0; i < per; ++i) out[q * per + i] = (double)tmp[q * stride + i];
       return HLBM_OK;
     }
     return fail(HLBM_E_ARG, "unknown state selector");
@@ -372,12 +380,12 @@ class Case final : public CaseBase {
     if (which != HLBM_STATE_LATTICE && which != HLBM_STATE_GRID) return fail(HLBM_E_ARG, "state cannot be set");
     if (k_ > 0) ck_valid_ = false;
     if (which == HLBM_STATE_LATTICE) {
-      if (bytes != 9 * plane_ * sizeof(double)) return fail(HLBM_E_ARG, "lattice state size mismatch");
+      if (bytes != 9 * nodes_ * sizeof(double)) return fail(HLBM_E_ARG, "lattice state size mismatch");
       double *tmp = nullptr;
       HIPCHK(hipMalloc(&tmp, bytes));
       hipError_t e = hipMemcpyAsync(tmp, buf, bytes, hipMemcpyHostToDevice, s_main_);
       if (e == hipSuccess) {
-        Kernels<T, R>::lattice_from_f64(tmp, (T *)lat_[0], plane_, s_main_);
+        Kernels<T, R>::lattice_from_f64(tmp, (T *)lat_[0], plane_, nodes_, s_main_);
         e = hipStreamSynchronize(s_main_);
       }
       (void)hipFree(tmp);
@@ -516,49 +524,89 @@ class Case final : public CaseBase {
     return HLBM_OK;
   }
 
-  // Time the sub-step variants on the current grid: every launch reads
-  // gbuf_[gcur_] (never written here) and writes the free buffer, which the
-  // next step overwrites before reading, so the state is untouched.
+  // captured steps hold the launch shapes they were captured with
+  void drop_graphs() {
+    for (auto &g : gexec_) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  }
+
+  // Time the launch shapes of the stream-collide and the sub-step variants
+  // on the current state: every launch reads the current lattice or grid
+  // (never written here) and writes the free buffer, which the next step
+  // overwrites before reading, so the state is untouched.
   int tune(int trial_steps, hlbm_tuning *t) override {
     if (!t || trial_steps < 0) return fail(HLBM_E_ARG, "invalid tuning request");
-    if (!has_grid_) return fail(HLBM_E_UNSUPPORTED, "a case without a grid has nothing to tune");
     if (trial_steps == 0) {
-      if (t->substep_variant < -1 || t->substep_variant >= kSubstepVariants)
-        return fail(HLBM_E_ARG, "invalid sub-step variant");
+      const bool keep_shape = t->lattice_threads == 0 && t->lattice_rows == 0;
+      if ((!keep_shape && !valid_lattice_shape(*t)) || t->substep_variant < -1 ||
+          t->substep_variant >= kSubstepVariants)
+        return fail(HLBM_E_ARG, "invalid schedule");
+      if (!keep_shape) {
+        lattice_threads_ = t->lattice_threads;
+        lattice_rows_ = t->lattice_rows;
+      }
       substep_variant_ = t->substep_variant;
-      *t = hlbm_tuning{0, 0, substep_variant_, 0, 0.0};
+      HIPCHK(hipStreamSynchronize(s_main_));
+      drop_graphs();
+      *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, 0, 0, 0.0};
       return HLBM_OK;
     }
     HIPCHK(hipDeviceSynchronize());
-    const CaseView<T, R> v = view();
+    CaseView<T, R> v = view();
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    int best = default_substep_variant<R>();
-    float best_ms = 3e38f;
     hipError_t e = hipSuccess;
-    for (int sv = 0; sv < kSubstepVariants && e == hipSuccess; ++sv) {
-      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first pass warms up
-        e = hipEventRecord(e0, s_grid_);
-        for (int i = 0; i < trial_steps; ++i)
-          for (int m = 0; m < d_.n; m += kSubstepBlock)
-            Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[gcur_], (R *)gbuf_[1 - gcur_], m,
-                                         std::min(kSubstepBlock, d_.n - m), s_grid_, nullptr, nullptr, nullptr, 0, sv);
-        if (e == hipSuccess) e = hipEventRecord(e1, s_grid_);
+    // best of two timed passes of `launch` on `st`, in ms
+    auto timed = [&](hipStream_t st, auto launch) {
+      float best = 3e38f;
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // the first pass warms up
+        e = hipEventRecord(e0, st);
+        for (int i = 0; i < trial_steps; ++i) launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && rep == 1 && ms < best_ms) {
+        if (rep > 0 && ms < best) best = ms;
+      }
+      return best;
+    };
+    double total = 0.0;
+    float best_ms = 3e38f;
+    for (int lt : {128, 256})
+      for (int rows : {1, 2, 4}) {
+        const float ms = timed(s_main_, [&] { Kernels<T, R>::stream_collide(v, s_main_, nullptr, nullptr, lt, rows); });
+        if (e == hipSuccess && ms < best_ms) {
+          best_ms = ms;
+          lattice_threads_ = lt;
+          lattice_rows_ = rows;
+        }
+      }
+    total += best_ms;
+    if (has_grid_) {
+      best_ms = 3e38f;
+      int best = default_substep_variant<R>();
+      for (int sv = 0; sv < kSubstepVariants; ++sv) {
+        const float ms = timed(s_grid_, [&] {
+          for (int m = 0; m < d_.n; m += kSubstepBlock)
+            Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[gcur_], (R *)gbuf_[1 - gcur_], m,
+                                         std::min(kSubstepBlock, d_.n - m), s_grid_, nullptr, nullptr, nullptr, 0, sv);
+        });
+        if (e == hipSuccess && ms < best_ms) {
           best_ms = ms;
           best = sv;
         }
       }
+      substep_variant_ = best;
+      total += best_ms;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIPCHK(e);
-    substep_variant_ = best;
-    *t = hlbm_tuning{0, 0, best, 0, (double)best_ms / trial_steps};
+    drop_graphs();
+    *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, 0, 0, total / trial_steps};
     return HLBM_OK;
   }
 
@@ -729,6 +777,7 @@ class Case final : public CaseBase {
     v.A = (const T *)lat_[0];
     v.B = (T *)lat_[1];
     v.nx = cfg_.nx;
+    v.plane = plane_;
     v.ny = cfg_.ny;
     v.periodic_y = cfg_.bc == HLBM_BC_PERIODIC;
     v.inv_tau = (R)(1.0 / cfg_.tau);
@@ -801,7 +850,7 @@ class Case final : public CaseBase {
     *grid_bytes = has_grid_ ? 9 * (size_t)grid_.nnode * sizeof(R) : 0;
   }
   unsigned long long *refill_counters() const { return counts_; }
-  int64_t lattice_nodes() const { return (int64_t)plane_; }
+  int64_t lattice_nodes() const { return (int64_t)nodes_; }
   int64_t grid_nodes() const { return has_grid_ ? grid_.nnode : 0; }
 
  private:
@@ -984,6 +1033,7 @@ class Case final : public CaseBase {
     AdjCtx<T, R> &c = actx_;
     std::memset(&c, 0, sizeof(c));
     c.nx = cfg_.nx;
+    c.plane = plane_;
     c.ny = cfg_.ny;
     c.periodic_y = cfg_.bc == HLBM_BC_PERIODIC;
     c.has_grid = 1;
@@ -1063,7 +1113,7 @@ class Case final : public CaseBase {
       v.B = tape_lat(t, j + 1);
       v.counts = counts_scratch_;
       Kernels<T, R>::lattice_from_grid(v, tape_grid(t, j, 0), st);
-      Kernels<T, R>::stream_collide(v, st);
+      Kernels<T, R>::stream_collide(v, st, nullptr, nullptr, lattice_threads_, lattice_rows_);
       Kernels<T, R>::interface_donors(v, st);
       for (int m = 0; m < d_.n; m += kSubstepBlock) {
         const int cnt = std::min(kSubstepBlock, d_.n - m);
@@ -1133,7 +1183,8 @@ class Case final : public CaseBase {
   Derived d_{};
   double h_ = 1.0;
   bool has_grid_ = false, body_ = false;
-  size_t plane_ = 0;
+  size_t nodes_ = 0;  // lattice nodes nx * ny
+  size_t plane_ = 0;  // population-plane stride of every lattice-shaped device array
   HostGrid grid_;
   hipStream_t s_main_ = nullptr, s_grid_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
@@ -1142,6 +1193,7 @@ class Case final : public CaseBase {
   int tslot_ = 0;
   int timing_ = 0;  // 1: every kernel, 2: the stream-collide only
   int substep_variant_ = -1;  // grid sub-step kernel variant (-1: the default for R)
+  int lattice_threads_ = kLatticeThreads, lattice_rows_ = kLatticeRows;  // stream-collide launch shape
   double tms_[8] = {};
   int64_t tcount_[8] = {};
   std::vector<void *> owned_;
@@ -1262,7 +1314,7 @@ class Batch final : public CaseBase {
     for (int i = 0; i < n; ++i) v[i] = cases_[i]->batched_view();
     HIPCHK(hipMalloc(&views_, n * sizeof(CaseView<T, R>)));
     HIPCHK(hipMemcpy(views_, v.data(), n * sizeof(CaseView<T, R>), hipMemcpyHostToDevice));
-    tuning_ = {8, 256, -1, 0, 0.0};
+    tuning_ = {8, kLatticeThreads, kLatticeRows, -1, 1, 0, 0.0};
     return HLBM_OK;
   }
 
@@ -1296,9 +1348,8 @@ class Batch final : public CaseBase {
     for (auto &c : cases_)
       if (c->steps_taken() != 0) return fail(HLBM_E_STATE, "tuning must precede the first step");
     if (trial_steps == 0) {
-      if (t->steps_per_graph < 1 || t->steps_per_graph > 64 || t->lattice_threads < 64 || t->lattice_threads > 256 ||
-          t->lattice_threads % 64 || t->substep_variant < -1 || t->substep_variant >= kSubstepVariants || t->order < 0 ||
-          t->order > 1)
+      if (t->steps_per_graph < 1 || t->steps_per_graph > 64 || !valid_lattice_shape(*t) ||
+          t->substep_variant < -1 || t->substep_variant >= kSubstepVariants || t->order < 0 || t->order > 1)
         return fail(HLBM_E_ARG, "invalid schedule");
       tuning_ = *t;
       tuning_.ms_per_step = 0.0;
@@ -1321,23 +1372,37 @@ class Batch final : public CaseBase {
     std::vector<int> all;
     for (int i = 0; i < (int)cases_.size(); ++i)
       if (cases_[i]->max_steps() >= trial_steps) all.push_back(i);
+    // one choice at a time, the others held at the best found so far
     hlbm_tuning best = tuning_;
     double best_ms = 1e300;
     int rc = HLBM_OK;
-    for (int g : {4, 8, 16})
-      for (int lt : {128, 256})
-        for (int sv = 0; sv < kSubstepVariants && rc == HLBM_OK; ++sv)
-          for (int ord = 0; ord < 2 && rc == HLBM_OK; ++ord) {
-            tuning_ = {g, lt, sv, ord, 0.0};
-            invalidate();
-            float ms = 0.f;
-            rc = timed_trial(all, trial_steps, &ms);
-            if (rc == HLBM_OK) rc = restore(snap);
-            if (rc == HLBM_OK && ms / trial_steps < best_ms) {
-              best_ms = ms / trial_steps;
-              best = tuning_;
-            }
-          }
+    auto trial = [&](hlbm_tuning cand) {
+      if (rc != HLBM_OK) return;
+      tuning_ = cand;
+      invalidate();
+      float ms = 0.f;
+      rc = timed_trial(all, trial_steps, &ms);
+      if (rc == HLBM_OK) rc = restore(snap);
+      if (rc == HLBM_OK && ms / trial_steps < best_ms) {
+        best_ms = ms / trial_steps;
+        best = cand;
+      }
+    };
+    for (int g : {4, 8, 16}) trial(hlbm_tuning{g, best.lattice_threads, best.lattice_rows, best.substep_variant,
+                                               best.order, 0, 0.0});
+    const hlbm_tuning after_g = best;
+    for (int lt : {128, 256})
+      for (int rows : {1, 2, 4})
+        if (lt != after_g.lattice_threads || rows != after_g.lattice_rows)
+          trial(hlbm_tuning{after_g.steps_per_graph, lt, rows, after_g.substep_variant, after_g.order, 0, 0.0});
+    const hlbm_tuning after_l = best;
+    for (int sv = 0; sv < kSubstepVariants; ++sv)
+      if (sv != (after_l.substep_variant < 0 ? default_substep_variant<R>() : after_l.substep_variant))
+        trial(hlbm_tuning{after_l.steps_per_graph, after_l.lattice_threads, after_l.lattice_rows, sv, after_l.order, 0,
+                          0.0});
+    const hlbm_tuning after_s = best;
+    trial(hlbm_tuning{after_s.steps_per_graph, after_s.lattice_threads, after_s.lattice_rows, after_s.substep_variant,
+                      1 - after_s.order, 0, 0.0});
     for (void *p : snap) (void)hipFree(p);
     if (rc != HLBM_OK) return rc;
     tuning_ = best;
@@ -1426,11 +1491,11 @@ class Batch final : public CaseBase {
     lists_.assign(5, List{});
     int lmax = 0;
     std::vector<int4> k1, k2, dn, rf, fo;
-    const int lt = tuning_.lattice_threads;
+    const int lt = tuning_.lattice_threads, rows = tuning_.lattice_rows;
     for (int c : act) {
       const CaseView<T, R> v = cases_[c]->batched_view();
-      for (int y = 0; y < v.ny; ++y)
-        for (int bx = 0; bx < (v.nx + lt - 1) / lt; ++bx) k1.push_back(make_int4(c, bx, y, 0));
+      for (int by = 0; by < (v.ny + rows - 1) / rows; ++by)
+        for (int bx = 0; bx < (v.nx + lt - 1) / lt; ++bx) k1.push_back(make_int4(c, bx, by, 0));
       for (int by = 0; by < v.k2_h; ++by)
         for (int bx = 0; bx < (v.k2_w + 255) / 256; ++bx) k2.push_back(make_int4(c, bx, by, 0));
       for (int bx = 0; bx < (4 * v.n_iface + 255) / 256; ++bx) dn.push_back(make_int4(c, bx, 0, 0));
@@ -1463,7 +1528,8 @@ class Batch final : public CaseBase {
   void enqueue_step() {
     using K = Kernels<T, R>;
     K::batched(BatchKernel::LatticeFromGrid, views_, lists_[1].d, lists_[1].n, 0, 256, s_);
-    K::batched(BatchKernel::StreamCollide, views_, lists_[0].d, lists_[0].n, 0, tuning_.lattice_threads, s_);
+    K::batched(BatchKernel::StreamCollide, views_, lists_[0].d, lists_[0].n, 0, tuning_.lattice_threads, s_,
+               tuning_.lattice_rows);
     K::batched(BatchKernel::InterfaceDonors, views_, lists_[2].d, lists_[2].n, 0, 256, s_);
     for (size_t i = 5; i < lists_.size(); ++i)
       K::batched(BatchKernel::GridSubsteps, views_, lists_[i].d, lists_[i].n, (int)(i - 5) * kSubstepBlock,

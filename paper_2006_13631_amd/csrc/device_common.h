@@ -122,14 +122,14 @@ __device__ __forceinline__ void node_chain(R rho, R ux, R uy, R zr, R zx, R zy, 
 }
 
 // ---- streaming ----------------------------------------------------------------
-// Flat indices into a [9][ny][nx] array of the nine values the pull of node
-// (x, y) reads: population q arriving at (x, y) left x - c_q one step
+// Flat indices into a [9][plane] array (plane >= ny * nx, row-major nodes)
+// of the nine values the pull of node (x, y) reads: population q arriving at (x, y) left x - c_q one step
 // earlier; across a resting y wall, halfway bounce-back returns the opposite
 // population of the node itself. Every (population, node) pair of the array
 // is the source of exactly one (q, node) pair, so the adjoint of the pull is
 // a push to these same addresses.
-__device__ __forceinline__ void pull_index(int nx, int ny, int periodic_y, int x, int y, size_t idx[9]) {
-  const size_t plane = (size_t)nx * ny;
+__device__ __forceinline__ void pull_index(int nx, int ny, size_t plane, int periodic_y, int x, int y,
+                                           size_t idx[9]) {
   const int xm = x == 0 ? nx - 1 : x - 1;
   const int xp = x == nx - 1 ? 0 : x + 1;
   int ym = y - 1, yp = y + 1;
@@ -157,10 +157,10 @@ __device__ __forceinline__ void pull_index(int nx, int ny, int periodic_y, int x
 // Populations arriving at lattice node (x, y) at t_{k+1}: pulled from the
 // post-collision buffer of t_k (left side of Eq.(LBE)).
 template <class T, class R>
-__device__ __forceinline__ void pull(const T *__restrict__ A, int nx, int ny, int periodic_y, int x, int y,
-                                     R f[9]) {
+__device__ __forceinline__ void pull(const T *__restrict__ A, int nx, int ny, size_t plane, int periodic_y, int x,
+                                     int y, R f[9]) {
   size_t idx[9];
-  pull_index(nx, ny, periodic_y, x, y, idx);
+  pull_index(nx, ny, plane, periodic_y, x, y, idx);
   // a bounced-back value comes from the opposite population, whose rest
   // weight w_i is the same
 #pragma unroll
@@ -276,8 +276,8 @@ __device__ __forceinline__ RefillCell refill_cell(const GridGeom &g, double ybas
 // density, velocity and f^neq = f - f^eq of the pre-collision populations at
 // t_{k+1} pulled from A (refill type 1 and the grid's interface donors).
 template <class T, class R>
-__device__ __forceinline__ void lattice_bilinear(const T *__restrict__ A, int nx, int ny, int periodic_y, double X,
-                                                 double Y, R &rho, R &ux, R &uy, R fneq[9]) {
+__device__ __forceinline__ void lattice_bilinear(const T *__restrict__ A, int nx, int ny, size_t plane, int periodic_y,
+                                                 double X, double Y, R &rho, R &ux, R &uy, R fneq[9]) {
   const double fx = floor(X), fy = floor(Y);
   const double a = X - fx, b = Y - fy;
   int x0 = (int)fx, y0 = (int)fy;
@@ -291,7 +291,7 @@ __device__ __forceinline__ void lattice_bilinear(const T *__restrict__ A, int nx
     xd = xd >= nx ? xd - nx : (xd < 0 ? xd + nx : xd);
     if (periodic_y) yd = yd >= ny ? yd - ny : (yd < 0 ? yd + ny : yd);
     R f[9], e[9], r, vx, vy;
-    pull<T, R>(A, nx, ny, periodic_y, xd, yd, f);
+    pull<T, R>(A, nx, ny, plane, periodic_y, xd, yd, f);
     moments<R>(f, r, vx, vy);
     equilibrium<R>(r, vx, vy, e);
     const R w = R(w4[d]);
@@ -306,8 +306,8 @@ __device__ __forceinline__ void lattice_bilinear(const T *__restrict__ A, int nx
 // One lane's share of an interface node's donors: corner d of the lattice
 // cell around (X, Y), weighted (rho, u_x, u_y, f^neq[9]) in acc[12].
 template <class T, class R>
-__device__ __forceinline__ void donor_corner(const T *__restrict__ A, int nx, int ny, int periodic_y, double X,
-                                             double Y, int d, R acc[12]) {
+__device__ __forceinline__ void donor_corner(const T *__restrict__ A, int nx, int ny, size_t plane, int periodic_y,
+                                             double X, double Y, int d, R acc[12]) {
   const double fx = floor(X), fy = floor(Y);
   const double a = X - fx, b = Y - fy;
   const double w = (d & 1 ? a : 1.0 - a) * (d >> 1 ? b : 1.0 - b);
@@ -315,7 +315,7 @@ __device__ __forceinline__ void donor_corner(const T *__restrict__ A, int nx, in
   xd = xd >= nx ? xd - nx : (xd < 0 ? xd + nx : xd);
   if (periodic_y) yd = yd >= ny ? yd - ny : (yd < 0 ? yd + ny : yd);
   R f[9], e[9], r, vx, vy;
-  pull<T, R>(A, nx, ny, periodic_y, xd, yd, f);
+  pull<T, R>(A, nx, ny, plane, periodic_y, xd, yd, f);
   moments<R>(f, r, vx, vy);
   equilibrium<R>(r, vx, vy, e);
   const R wr = R(w);

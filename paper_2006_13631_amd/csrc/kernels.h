@@ -13,6 +13,7 @@ struct CaseView {
   const T *A;      // post-collision populations at t_k, [9][ny][nx]
   T *B;            // post-collision populations at t_{k+1}
   int nx, ny;
+  size_t plane;    // elements from one population plane to the next (>= nx * ny)
   int periodic_y;  // 1: periodic in y, 0: halfway bounce-back walls
   R inv_tau;       // 1 / tau_s
   R g_post;        // 2 (tau_s - 1) / (2 tau_s - 1), Eq.(postcollision2_s)
@@ -44,10 +45,21 @@ struct CaseView {
   int64_t max_steps;  // a batched case stops here
 };
 
+// Population-plane stride of lattice buffers: nx * ny rounded up to 256
+// nodes plus 2112. Planes a power of two apart put the nine streams of the
+// stream-collide on the same HBM channels at once; the offset spreads them.
+inline size_t lattice_plane(int nx, int ny) {
+  return (((size_t)nx * ny + 255) / 256) * 256 + 2112;
+}
+
 enum class BatchKernel { StreamCollide, LatticeFromGrid, InterfaceDonors, GridSubsteps, Refill, Force };
 
 // grid sub-steps advanced per launch (temporal blocking depth)
 constexpr int kSubstepBlock = 4;
+
+// default launch shape of the lattice stream-collide: workgroup width and
+// rows per lane
+constexpr int kLatticeThreads = 128, kLatticeRows = 2;
 
 // Variants of the grid sub-step kernel (tile of grid nodes per workgroup,
 // workgroup size):
@@ -64,10 +76,12 @@ void substep_tile(int variant, int *tx, int *ty);
 template <class T, class R>
 struct Kernels {
   static hipError_t prepare();  // one-time launch attributes (dynamic LDS of the sub-step)
-  static void fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStream_t s);
+  static void fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStream_t s);  // whole planes
   // start/stop (optional): events recorded at the kernel's own start and end
+  // threads x rows: workgroup width and lattice rows per lane (1, 2 or 4);
+  // <= 0 takes kLatticeThreads / kLatticeRows
   static void stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start = nullptr,
-                             hipEvent_t stop = nullptr);
+                             hipEvent_t stop = nullptr, int threads = 0, int rows = 0);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
   static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
   // sub-steps m0 .. m0+count-1 (count <= kSubstepBlock) in one launch; with
@@ -83,14 +97,15 @@ struct Kernels {
                               R *tape, R *wtape, const int *widx, int nwall);
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
   static void force(const CaseView<T, R> &v, const R *f, hipStream_t s);
-  static void lattice_to_f64(const T *src, double *dst, size_t plane, hipStream_t s);
+  // between a lattice buffer (plane stride) and a packed [9][nodes] FP64 array
+  static void lattice_to_f64(const T *src, double *dst, size_t plane, size_t nodes, hipStream_t s);
   // one launch of a case-batched step over a work list of int4 items
   // (case, block x, block y, 0); GridSubsteps: (case, tile) for sub-steps
   // m0 .. m0+3 of every listed case; threads: stream-collide workgroup size
   // (<= 256), or for GridSubsteps the sub-step variant (-1: default)
   static void batched(BatchKernel which, const CaseView<T, R> *views, const int4 *items, int nitems, int m0,
-                      int threads, hipStream_t s);
-  static void lattice_from_f64(const double *src, T *dst, size_t plane, hipStream_t s);
+                      int threads, hipStream_t s, int rows = 1);
+  static void lattice_from_f64(const double *src, T *dst, size_t plane, size_t nodes, hipStream_t s);
 };
 
 extern template struct Kernels<double, double>;

@@ -33,44 +33,57 @@ __device__ __forceinline__ int grid_cur(const CaseView<T, R> &v, int64_t k) {
 }
 
 // ---- K1: fused pull stream + BGK collide, Eq.(LBE) -------------------------
-template <class T, class R>
+// A lane updates RPT rows of one lattice column: the pulls of all its rows
+// are issued first, before the step's rectangle (a load that depends on the
+// device step counter) is known; nodes inside the rectangle (unused and
+// interpolation nodes) then carry their own values instead.
+template <class T, class R, int RPT>
 __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, const T *__restrict__ A,
-                                                     T *__restrict__ B, int64_t k, int bx, int by) {
+                                                     T *__restrict__ B, const int64_t *k_at, int bx, int by) {
   const int x = bx * blockDim.x + threadIdx.x;
-  const int y = by;
   if (x >= v.nx) return;
-  const size_t plane = (size_t)v.nx * v.ny, c = (size_t)y * v.nx + x;
-  bool inside = false;
+  const size_t plane = v.plane;
+  R f[RPT][9];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+    if (by * RPT + r < v.ny) pull<T, R>(A, v.nx, v.ny, plane, v.periodic_y, x, by * RPT + r, f[r]);
+  int ix0 = 1, ix1 = 0, iy0 = 1, iy1 = 0;  // empty rectangle without a grid
   if (v.has_grid) {
-    const StepParams &P = v.params[k];
-    inside = x >= P.ix0 && x <= P.ix1 && y >= P.iy0 && y <= P.iy1;
+    const StepParams &P = v.params[*k_at];
+    ix0 = P.ix0, ix1 = P.ix1, iy0 = P.iy0, iy1 = P.iy1;
   }
-  if (inside) {  // unused and interpolation nodes carry their values
 #pragma unroll
-    for (int q = 0; q < 9; ++q) B[q * plane + c] = A[q * plane + c];
-    return;
+  for (int r = 0; r < RPT; ++r) {
+    const int y = by * RPT + r;
+    if (y >= v.ny) continue;
+    const size_t c = (size_t)y * v.nx + x;
+    if (x >= ix0 && x <= ix1 && y >= iy0 && y <= iy1) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) B[q * plane + c] = A[q * plane + c];
+      continue;
+    }
+    R e[9], rho, ux, uy;
+    moments<R>(f[r], rho, ux, uy);
+    equilibrium<R>(rho, ux, uy, e);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Stor<T>::st_stream(B, q * plane + c, q, fmad(-v.inv_tau, f[r][q] - e[q], f[r][q]));
   }
-  R f[9], e[9], rho, ux, uy;
-  pull<T, R>(A, v.nx, v.ny, v.periodic_y, x, y, f);
-  moments<R>(f, rho, ux, uy);
-  equilibrium<R>(rho, ux, uy, e);
-#pragma unroll
-  for (int q = 0; q < 9; ++q) Stor<T>::st_stream(B, q * plane + c, q, fmad(-v.inv_tau, f[q] - e[q], f[q]));
 }
 
-template <class T, class R>
+template <class T, class R, int RPT>
 __global__ __launch_bounds__(256) void k_stream_collide(CaseView<T, R> v) {
-  stream_collide_block<T, R>(v, v.A, v.B, v.has_grid ? *v.dk : 0, blockIdx.x, blockIdx.y);
+  stream_collide_block<T, R, RPT>(v, v.A, v.B, v.dk, blockIdx.x, blockIdx.y);
 }
 
-template <class T, class R>
+// item = (case, column block, row group of RPT rows)
+template <class T, class R, int RPT>
 __global__ __launch_bounds__(256) void kb_stream_collide(const CaseView<T, R> *__restrict__ views,
                                                          const int4 *__restrict__ items) {
   const int4 it = items[blockIdx.x];
   const CaseView<T, R> &v = views[it.x];
   int64_t k;
   if (!batched_case(v, k)) return;
-  stream_collide_block<T, R>(v, v.lat[k & 1], v.lat[(k + 1) & 1], k, it.y, it.z);
+  stream_collide_block<T, R, RPT>(v, v.lat[k & 1], v.lat[(k + 1) & 1], v.dk, it.y, it.z);
 }
 
 // ---- K2: lattice interpolation nodes from the grid, Eq.(postcollision2_s) ----
@@ -95,7 +108,7 @@ __device__ __forceinline__ void lattice_from_grid_block(const CaseView<T, R> &v,
   grid_barycentric<R>(g, v.nnode, node, lam, rho, ux, uy, fneq);
   R e[9];
   equilibrium<R>(rho, ux, uy, e);
-  const size_t plane = (size_t)v.nx * v.ny, c = (size_t)y * v.nx + x;
+  const size_t plane = v.plane, c = (size_t)y * v.nx + x;
 #pragma unroll
   for (int q = 0; q < 9; ++q) Stor<T>::st(A, q * plane + c, q, e[q] + v.g_post * fneq[q]);
 }
@@ -136,7 +149,7 @@ __device__ __forceinline__ void interface_donors_block(const CaseView<T, R> &v, 
     const int i = p % v.nux, j = p / v.nux;
     const double X = v.xc + (double)(i - v.nux / 2) * v.h;
     const double Y = P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
-    donor_corner<T, R>(A, v.nx, v.ny, v.periodic_y, X, Y, d, acc);
+    donor_corner<T, R>(A, v.nx, v.ny, v.plane, v.periodic_y, X, Y, d, acc);
   }
 #pragma unroll
   for (int r = 0; r < 12; ++r) {
@@ -497,7 +510,7 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
     const double X = v.xc + (double)(i - v.nux / 2) * v.h;
     const double Ynew = P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
     R rho, ux, uy, fneq[9], e[9];
-    lattice_bilinear<T, R>(A, v.nx, v.ny, v.periodic_y, X, Ynew, rho, ux, uy, fneq);
+    lattice_bilinear<T, R>(A, v.nx, v.ny, v.plane, v.periodic_y, X, Ynew, rho, ux, uy, fneq);
     equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = e[q] + v.k_neq * fneq[q];
@@ -611,18 +624,18 @@ __global__ void k_fill_rest(T *lat, size_t plane, R *grid, int nnode) {
 }
 
 template <class T>
-__global__ void k_to_f64(const T *src, double *dst, size_t plane) {
+__global__ void k_to_f64(const T *src, double *dst, size_t plane, size_t nodes) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= plane) return;
-  for (int q = 0; q < 9; ++q) dst[q * plane + i] = (double)Stor<T>::ld(src, q * plane + i, q);
+  if (i >= nodes) return;
+  for (int q = 0; q < 9; ++q) dst[q * nodes + i] = (double)Stor<T>::ld(src, q * plane + i, q);
 }
 
 template <class T>
-__global__ void k_from_f64(const double *src, T *dst, size_t plane) {
+__global__ void k_from_f64(const double *src, T *dst, size_t plane, size_t nodes) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= plane) return;
+  if (i >= nodes) return;
   for (int q = 0; q < 9; ++q) {
-    const double x = src[q * plane + i];
+    const double x = src[q * nodes + i];
     if constexpr (sizeof(T) == 8) Stor<T>::st(dst, q * plane + i, q, x);
     else Stor<T>::st(dst, q * plane + i, q, (float)x);
   }
@@ -666,13 +679,21 @@ void Kernels<T, R>::fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStrea
 }
 
 template <class T, class R>
-void Kernels<T, R>::stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
-  if (start) {  // events taken by the command processor at the kernel's own start and end
-    hipExtLaunchKernelGGL((k_stream_collide<T, R>), dim3(blocks(v.nx, 256), v.ny), dim3(256), 0, s, start, stop, 0,
-                          v);
-  } else {
-    hipLaunchKernelGGL((k_stream_collide<T, R>), dim3(blocks(v.nx, 256), v.ny), dim3(256), 0, s, v);
+void Kernels<T, R>::stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start, hipEvent_t stop,
+                                   int threads, int rows) {
+  const int nt = threads > 0 ? threads : kLatticeThreads, rpt = rows > 0 ? rows : kLatticeRows;
+  const dim3 g(blocks(v.nx, nt), (v.ny + rpt - 1) / rpt);
+#define HLBM_K1(RPT)                                                                                     \
+  if (start) /* events taken by the command processor at the kernel's own start and end */             \
+    hipExtLaunchKernelGGL((k_stream_collide<T, R, RPT>), g, dim3(nt), 0, s, start, stop, 0, v);           \
+  else                                                                                                  \
+    hipLaunchKernelGGL((k_stream_collide<T, R, RPT>), g, dim3(nt), 0, s, v)
+  switch (rpt) {
+    case 4: HLBM_K1(4); break;
+    case 2: HLBM_K1(2); break;
+    default: HLBM_K1(1); break;
   }
+#undef HLBM_K1
 }
 
 template <class T, class R>
@@ -720,23 +741,27 @@ void Kernels<T, R>::force(const CaseView<T, R> &v, const R *f, hipStream_t s) {
 }
 
 template <class T, class R>
-void Kernels<T, R>::lattice_to_f64(const T *src, double *dst, size_t plane, hipStream_t s) {
-  hipLaunchKernelGGL((k_to_f64<T>), dim3(blocks(plane, 256)), dim3(256), 0, s, src, dst, plane);
+void Kernels<T, R>::lattice_to_f64(const T *src, double *dst, size_t plane, size_t nodes, hipStream_t s) {
+  hipLaunchKernelGGL((k_to_f64<T>), dim3(blocks(nodes, 256)), dim3(256), 0, s, src, dst, plane, nodes);
 }
 
 template <class T, class R>
-void Kernels<T, R>::lattice_from_f64(const double *src, T *dst, size_t plane, hipStream_t s) {
-  hipLaunchKernelGGL((k_from_f64<T>), dim3(blocks(plane, 256)), dim3(256), 0, s, src, dst, plane);
+void Kernels<T, R>::lattice_from_f64(const double *src, T *dst, size_t plane, size_t nodes, hipStream_t s) {
+  hipLaunchKernelGGL((k_from_f64<T>), dim3(blocks(nodes, 256)), dim3(256), 0, s, src, dst, plane, nodes);
 }
 
 template <class T, class R>
 void Kernels<T, R>::batched(BatchKernel which, const CaseView<T, R> *views, const int4 *items, int nitems, int m0,
-                            int threads, hipStream_t s) {
+                            int threads, hipStream_t s, int rows) {
   if (nitems <= 0) return;
   const dim3 g(nitems);
   switch (which) {
     case BatchKernel::StreamCollide:
-      hipLaunchKernelGGL((kb_stream_collide<T, R>), g, dim3(threads), 0, s, views, items);
+      switch (rows) {
+        case 4: hipLaunchKernelGGL((kb_stream_collide<T, R, 4>), g, dim3(threads), 0, s, views, items); break;
+        case 2: hipLaunchKernelGGL((kb_stream_collide<T, R, 2>), g, dim3(threads), 0, s, views, items); break;
+        default: hipLaunchKernelGGL((kb_stream_collide<T, R, 1>), g, dim3(threads), 0, s, views, items); break;
+      }
       break;
     case BatchKernel::LatticeFromGrid:
       hipLaunchKernelGGL((kb_lattice_from_grid<T, R>), g, dim3(256), 0, s, views, items);

@@ -56,7 +56,8 @@ class Info(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("steps_per_graph", C.c_int32), ("lattice_threads", C.c_int32),
-                ("substep_variant", C.c_int32), ("order", C.c_int32), ("ms_per_step", C.c_double)]
+                ("lattice_rows", C.c_int32), ("substep_variant", C.c_int32), ("order", C.c_int32),
+                ("reserved", C.c_int32), ("ms_per_step", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -177,13 +178,16 @@ class Case:
         self._check(load().hlbm_get_stencil(self.h, kmax, _ptr(nbr, C.c_int32), _ptr(S), _ptr(Cm)))
         return nbr, S, Cm
 
-    def tune(self, trial_steps=4, variant=None):
-        """Pick the grid sub-step kernel variant: time each one over
-        trial_steps structured steps' worth of sub-steps (state untouched), or
-        apply ``variant`` (-1 = default) as given. Returns the schedule."""
+    def tune(self, trial_steps=4, variant=None, lattice=None):
+        """Pick the stream-collide launch shape and the grid sub-step kernel
+        variant by timing each (state untouched), or apply ``variant`` (-1 =
+        default) and ``lattice`` = (threads, rows) as given. Returns the
+        schedule."""
         t = Tuning()
-        if variant is not None:
-            t.substep_variant = variant
+        if variant is not None or lattice is not None:
+            t.substep_variant = -1 if variant is None else variant
+            if lattice is not None:
+                t.lattice_threads, t.lattice_rows = lattice
             trial_steps = 0
         self._check(load().hlbm_tune(self.h, trial_steps, C.byref(t)))
         return t.as_dict()
@@ -307,8 +311,7 @@ class Batch:
 
     def tune(self, trial_steps=16, schedule=None):
         """Autotune (trial_steps > 0) or apply ``schedule`` (dict) as given."""
-        t = Tuning()
-        t.substep_variant = -1
+        t = Tuning(steps_per_graph=8, lattice_threads=128, lattice_rows=2, substep_variant=-1, order=1)
         if schedule:
             for k, v in schedule.items():
                 setattr(t, k, v)

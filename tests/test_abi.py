@@ -36,19 +36,19 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hlbm.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hlbm_config),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hlbm_config),'
                    ' offsetof(hlbm_config, max_steps), sizeof(hlbm_info), offsetof(hlbm_info, lattice_bytes),'
                    ' offsetof(hlbm_info, status), sizeof(hlbm_tuning), offsetof(hlbm_tuning, ms_per_step),'
-                   ' offsetof(hlbm_tuning, substep_variant));'
+                   ' offsetof(hlbm_tuning, substep_variant), offsetof(hlbm_tuning, lattice_rows));'
                    'return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
-    a, b, c, d, e, f, g, h = map(int, subprocess.check_output([str(exe)]).split())
+    a, b, c, d, e, f, g, h, i = map(int, subprocess.check_output([str(exe)]).split())
     assert a == C.sizeof(hlbm.Config) and b == hlbm.Config.max_steps.offset
     assert c == C.sizeof(hlbm.Info) and d == hlbm.Info.lattice_bytes.offset
     assert e == hlbm.Info.status.offset
     assert f == C.sizeof(hlbm.Tuning) and g == hlbm.Tuning.ms_per_step.offset
-    assert h == hlbm.Tuning.substep_variant.offset
+    assert h == hlbm.Tuning.substep_variant.offset and i == hlbm.Tuning.lattice_rows.offset
 
 
 @pytest.mark.parametrize("bad", [

@@ -60,10 +60,10 @@ def test_batch_matches_single_cases_bitwise(storage):
 
 
 @pytest.mark.parametrize("schedule", [
-    dict(steps_per_graph=4, lattice_threads=128, substep_variant=0, order=1),
-    dict(steps_per_graph=16, lattice_threads=256, substep_variant=1, order=0),
-    dict(steps_per_graph=1, lattice_threads=64, substep_variant=2, order=1),
-    dict(steps_per_graph=8, lattice_threads=192, substep_variant=3, order=0),
+    dict(steps_per_graph=4, lattice_threads=128, lattice_rows=1, substep_variant=0, order=1),
+    dict(steps_per_graph=16, lattice_threads=256, lattice_rows=2, substep_variant=1, order=0),
+    dict(steps_per_graph=1, lattice_threads=64, lattice_rows=4, substep_variant=2, order=1),
+    dict(steps_per_graph=8, lattice_threads=192, lattice_rows=2, substep_variant=3, order=0),
 ])
 def test_schedules_do_not_change_results(schedule):
     _say("schedule", schedule)
@@ -80,18 +80,21 @@ def test_schedules_do_not_change_results(schedule):
 
 @pytest.mark.parametrize("storage", [hlbm.FP64, hlbm.FP32])
 def test_substep_variants_compute_identical_bits(storage):
-    """The four grid sub-step kernels (tile shape, workgroup size) differ
-    only in which workgroup and lane compute a node."""
+    """The four grid sub-step kernels (tile shape, workgroup size) and the
+    stream-collide launch shapes differ only in which workgroup and lane
+    compute a node."""
     c = preset("lamina_128x64")
     c.pop("ckpt_every")
     n = c.pop("steps") // 4
     c["max_steps"] = n
     want = hlbm.Case(storage=storage, **c)
     want.step(n)
+    shapes = [(128, 1), (256, 2), (64, 4), (192, 1)]
     for v in range(4):
-        _say("sub-step variant", v, "storage", storage)
+        _say("sub-step variant", v, "stream-collide shape", shapes[v], "storage", storage)
         g = hlbm.Case(storage=storage, **c)
-        assert g.tune(variant=v)["substep_variant"] == v
+        t = g.tune(variant=v, lattice=shapes[v])
+        assert t["substep_variant"] == v and (t["lattice_threads"], t["lattice_rows"]) == shapes[v]
         g.step(n)
         _same(g, want)
 
@@ -109,13 +112,15 @@ def test_single_case_tune_leaves_state_alone():
     t = a.tune(trial_steps=2)
     _say("chosen", t)
     assert 0 <= t["substep_variant"] < 4 and t["ms_per_step"] > 0
+    assert t["lattice_threads"] in (128, 256) and t["lattice_rows"] in (1, 2, 4)
     assert np.array_equal(a.lattice(), lat) and np.array_equal(a.grid(), grid)
     a.step(n - n // 2)
     b.step(n - n // 2)
     _same(a, b)
-    with pytest.raises(hlbm.HlbmError) as e:
-        a.tune(variant=4)
-    assert e.value.code == hlbm.E_ARG
+    for bad in (dict(variant=4), dict(lattice=(96, 1)), dict(lattice=(128, 3))):
+        with pytest.raises(hlbm.HlbmError) as e:
+            a.tune(**bad)
+        assert e.value.code == hlbm.E_ARG
 
 
 def test_autotune_then_run():
@@ -124,7 +129,7 @@ def test_autotune_then_run():
     batch = hlbm.Batch(cfgs, storage=hlbm.FP32)
     t = batch.tune(trial_steps=8)
     _say("chosen", t)
-    assert t["steps_per_graph"] in (4, 8, 16) and t["ms_per_step"] > 0
+    assert t["steps_per_graph"] in (4, 8, 16) and t["ms_per_step"] > 0 and t["lattice_rows"] in (1, 2, 4)
     for m in batch.cases:
         assert m.info().step == 0
     batch.step(200)
