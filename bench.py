@@ -235,6 +235,74 @@ def sweep_leg(seed=0, periods=10.0, loop=True, tune_steps=8, chunk=4000, only=No
     return out
 
 
+def precision_leg(workload="lamina_4096", steps=None, chunk=1000):
+    """One case at FP64, FP32 and FP16-deviation storage: lattice MLUPS of
+    each, and its force history and Theta against the FP64 run (the
+    hydrodynamic-function error each reduced precision costs)."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.workloads import preset
+    cfg = preset(workload)
+    cfg.pop("steps")
+    cfg.pop("ckpt_every", None)
+    nu = (cfg["tau"] - 0.5) / 3.0
+    period = cfg["b"] ** 2 / (nu * cfg["beta"])
+    steps = steps or int(math.ceil(4.0 * period)) + 1  # the fit window [T, 4T)
+    runs = {}
+    for st in ("f64", "f32", "f16dev"):
+        case = H.Case(max_steps=steps, storage=H.STORAGE[st], **cfg)
+        sched = case.tune(trial_steps=4)
+        print(f"# precision {workload} {st} steps {steps} schedule {sched}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, diverged = 0, None
+        while done < steps:
+            n = min(chunk, steps - done)
+            try:
+                case.step(n)
+            except H.HlbmError as e:
+                if e.code != H.E_UNSTABLE:
+                    raise
+                diverged = case.info().step
+                break
+            done += n
+            print(f"# {st} {done}/{steps}", file=sys.stderr, flush=True)
+        dt = time.perf_counter() - t0
+        hist = case.history()
+        fin = np.all(np.isfinite(hist), axis=1)
+        n_fin = int(np.argmin(fin)) if not fin.all() else len(hist)
+        t1 = min(4.0, n_fin / period)
+        th = None
+        if t1 > 1.0 + 2.0 / period:
+            try:
+                th = case.theta(1.0, t1)
+            except H.HlbmError:
+                th = None
+        runs[st] = {"mlups": cfg["nx"] * cfg["ny"] * (diverged or steps) / dt / 1e6, "steps_run": diverged or steps,
+                    "diverged_at": diverged, "finite_steps": n_fin, "theta": th, "hist": hist[:n_fin],
+                    "fit_window_periods": [1.0, t1], "schedule": sched}
+        case.close()
+    ref = runs["f64"]
+    out = {"workload": workload, "steps": steps, "period_steps": round(period, 1)}
+    n_common = min(len(r["hist"]) for r in runs.values())
+    for st, r in runs.items():
+        # a run that blows up does so in every precision within a few steps;
+        # the force is compared over the first 90 % of the steps all kept finite
+        n = int(0.9 * n_common) if n_common < steps else n_common
+        scale = np.max(np.abs(ref["hist"][:n])) if n else float("nan")
+        err = float(np.max(np.abs(r["hist"][:n] - ref["hist"][:n])) / scale) if n else None
+        th, th64 = r["theta"], ref["theta"]
+        out[st] = {"mlups": round(r["mlups"], 1), "steps_run": r["steps_run"], "diverged_at": r["diverged_at"],
+                   "theta": None if th is None else [th.real, th.imag],
+                   "fit_window_periods": [round(x, 3) for x in r["fit_window_periods"]],
+                   "force_rel_err_vs_f64": err, "force_compared_steps": n,
+                   "theta_rel_err_vs_f64": None if (th is None or th64 is None) else abs(th - th64) / abs(th64),
+                   "schedule": {k: r["schedule"][k] for k in ("lattice_threads", "lattice_rows", "substep_variant")}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +323,10 @@ def main():
                     help="run only the parametric sweep (FP32 batch vs FP64 per-case loop) and print its line")
     ap.add_argument("--sweep-periods", type=float, default=10.0)
     ap.add_argument("--sweep-no-loop", action="store_true")
+    ap.add_argument("--precision", action="store_true",
+                    help="run only the storage-precision comparison (FP64 / FP32 / FP16-deviation) and print its line")
+    ap.add_argument("--precision-workload", default="lamina_4096,lamina_4096_stable")
+    ap.add_argument("--precision-steps", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
@@ -267,6 +339,11 @@ def main():
     if args.sweep:
         torch.cuda.set_device(0)
         print(json.dumps(sweep_leg(periods=args.sweep_periods, loop=not args.sweep_no_loop)), flush=True)
+        return
+    if args.precision:
+        torch.cuda.set_device(0)
+        for wl in args.precision_workload.split(","):
+            print(json.dumps(precision_leg(wl, args.precision_steps)), flush=True)
         return
 
     cfg = preset(args.workload)

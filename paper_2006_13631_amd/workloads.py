@@ -32,6 +32,11 @@ PRESETS = {
     # precision at scale: 4096^2 lattice, 1024x256 grid, 100000 steps
     "lamina_4096": dict(nx=4096, ny=4096, nux=1024, nuy=256, h_u=1.0, b=256.0, thickness=1.0,
                         tau=0.52, kc=3.0, beta=2000.0, steps=100000),
+    # the same lattice, grid and KC at a viscosity and frequency plain BGK
+    # sustains (U = 0.059, Ma = 0.10, Re = 450): period 13107 steps, fit
+    # window [T, 4T) inside 52429 steps
+    "lamina_4096_stable": dict(nx=4096, ny=4096, nux=1024, nuy=256, h_u=1.0, b=256.0, thickness=1.0,
+                               tau=0.6, kc=3.0, beta=150.0, steps=52429),
     # small cases for tests: several tiles, ragged sizes, odd grid width
     "tiny_ragged": dict(nx=77, ny=45, nux=33, nuy=16, h_u=1.0, b=12.0, thickness=1.0,
                         tau=0.7, kc=0.6, beta=40.0, steps=60),
