@@ -73,17 +73,26 @@ struct AdjCtx {
   double *part;             // parameter partial sums [slots][3] (A, omega, tau)
 };
 
+// per-sub-step scalars of one launch of the blocked sub-step adjoint
+template <class R>
+struct AdjSubScal {
+  R uw[4];                  // lamina velocity u_w at the end of the sub-step
+  double duwA[4], duwW[4];  // its derivatives in A and omega
+};
+
 template <class T, class R>
 struct AdjKernels {
   // recompute f*, f^neq* and the interpolated moments of the interface nodes
   static void star(const AdjCtx<T, R> &c, hipStream_t s);
   // refill and force adjoints: Ubn from Ub_next; Z1 and zf
   static void refill(const AdjCtx<T, R> &c, int slot0, hipStream_t s);
-  // one sub-step backwards: wall-velocity adjoint (lamina velocity uw of
-  // this sub-step and its A, omega derivatives), then the transposed
-  // stencil ub -> ub_out; first/last: m = n-1 / m = 0
-  static void substep(const AdjCtx<T, R> &c, const R *Um, const R *ub, R *ub_out, int m, R uw, double duwA,
-                      double duwW, int first, int last, int slot0, hipStream_t s);
+  // sub-steps m_hi, m_hi-1, ..., m_hi-count+1 backwards (count <= 4): per
+  // sub-step the wall-velocity adjoint (lamina velocity of that sub-step and
+  // its A, omega derivatives in sc, index m_hi - m), then the transposed
+  // stencil; ub -> ub_out; tape0: the step's taped grid states, sub-step m
+  // at tape0 + 9 m nnode; first/last: the launch holds m = n-1 / m = 0
+  static void substeps(const AdjCtx<T, R> &c, const R *tape0, const R *ub, R *ub_out, int m_hi, int count,
+                       const AdjSubScal<R> &sc, int first, int last, int slot0, hipStream_t s);
   // lattice side: donor gather E, stream-collide adjoint, grid-to-lattice adjoint
   static void donor_gather(const AdjCtx<T, R> &c, int slot0, hipStream_t s);
   static void stream_collide(const AdjCtx<T, R> &c, int slot0, hipStream_t s, hipEvent_t start = nullptr,

@@ -243,128 +243,219 @@ __device__ __forceinline__ void wall_vjp(R rho, R ux, R uy, R uw, R u[9], R &d_u
   d_uw = ayw;
 }
 
-// Transposed Eq.(ulbe)/Eq.(postcollision2_u) stencil. A workgroup (one
-// wave) owns a 16 x 4 tile and stages the adjoint of the 18 x 6 region (tile
-// plus one-node halo, zeros outside the grid) in LDS, wall nodes already
-// pulled back through the velocity imposition. Node q applies its transposed
-// stencil class to the nine region values around it.
-constexpr int ATX = 16, ATY = 4, ARX = ATX + 2, ARY = ATY + 2, ARN = ARX * ARY;
+// Transposed Eq.(ulbe)/Eq.(postcollision2_u) stencil, up to kAdjBlock
+// sub-steps backwards per launch (temporal blocking, as in the forward). A
+// workgroup owns an ATX x ATY tile and stages the adjoint of the tile plus a
+// kAdjBlock-node halo (zeros outside the grid) in LDS, wall nodes already
+// pulled back through the velocity imposition of the first sub-step it
+// reverses. Reversing sub-step m updates the region grown by the number of
+// sub-steps still to go in the launch: node q applies its transposed
+// stencil class to the nine region values around it and the chain of its
+// own non-equilibrium part at the taped state U_m; the new value of a wall
+// node is at once pulled back through the imposition of sub-step m - 1.
+// Lanes are dealt over each sub-step's rectangle. Parameter partials and
+// the running sums of the structured-derived adjoints (interface nodes)
+// are taken for the tile's own nodes only.
+constexpr int ATX = 16, ATY = 4, kAdjBlock = 4, ANT = 256;
 
 template <class T, class R>
-__global__ __launch_bounds__(NG) void k_adj_substep(AdjCtx<T, R> c, const R *__restrict__ Um,
-                                                    const R *__restrict__ ub, R *__restrict__ ub_out, int m, R uw,
-                                                    double duwA, double duwW, int first, int last, int slot0) {
-  __shared__ R sob[ARN * 9];
+__global__ __launch_bounds__(ANT) void k_adj_substeps(AdjCtx<T, R> c, const R *__restrict__ tape0,
+                                                      const R *__restrict__ ub, R *__restrict__ ub_out, int m_hi,
+                                                      int count, AdjSubScal<R> sc, int first, int last, int slot0) {
+  constexpr int H = kAdjBlock, RX = ATX + 2 * H, RY = ATY + 2 * H, RN = RX * RY;
+  constexpr int SPER = (RN + ANT - 1) / ANT;
+  constexpr int PER = ((ATX + 2 * (H - 1)) * (ATY + 2 * (H - 1)) + ANT - 1) / ANT;
+  __shared__ R sob[RN * 9];              // adjoint of the region's grid state
+  __shared__ int scls[RN];               // transposed stencil class, -1 outside the grid
+  __shared__ R acc[ATX * ATY * 18];      // running sums (sf, sn) of the tile's interface nodes
   const GridGeom &g = c.gg;
   const size_t N = (size_t)c.nnode;
   const int tiles_x = (g.nux + ATX - 1) / ATX;
-  const int x0 = (blockIdx.x % tiles_x) * ATX - 1, y0 = (blockIdx.x / tiles_x) * ATY - 1;
+  const int x0 = (blockIdx.x % tiles_x) * ATX - H, y0 = (blockIdx.x / tiles_x) * ATY - H;
   double pA = 0.0, pW = 0.0, pT = 0.0;
-  for (int idx = threadIdx.x; idx < ARN; idx += NG) {
-    const int rx = idx % ARX, ry = idx / ARX;
+  auto own = [&](int rx, int ry) { return rx >= H && rx < H + ATX && ry >= H && ry < H + ATY; };
+  // stage: the region's adjoint, walls pulled back through sub-step m_hi's imposition
+#pragma unroll
+  for (int u = 0; u < SPER; ++u) {
+    const int idx = threadIdx.x + u * ANT;
+    if (idx >= RN) continue;
+    const int rx = idx % RX, ry = idx / RX;
     const int gi = x0 + rx, gj = y0 + ry;
     const bool in = gi >= 0 && gj >= 0 && gi < g.nux && gj < g.nuy;
     const int p = in ? gj * g.nux + gi : 0;
-    R u[9];
+    R v[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) u[q] = in ? ub[q * N + p] : R(0);
+    for (int q = 0; q < 9; ++q) v[q] = in ? ub[q * N + p] : R(0);
+    scls[idx] = in ? c.acls[p] : -1;
     if (in && c.ntype[p] == NODE_WALL) {
-      const R *wt = c.wt + (size_t)m * 3 * c.n_wall;
+      const R *wt = c.wt + (size_t)m_hi * 3 * c.n_wall;
       const int w = c.widx[p];
       R d_uw;
-      wall_vjp<R>(wt[w], wt[c.n_wall + w], wt[2 * c.n_wall + w], uw, u, d_uw);
-      if (rx >= 1 && rx <= ATX && ry >= 1 && ry <= ATY) {  // count each wall node once
-        pA += (double)d_uw * duwA;
-        pW += (double)d_uw * duwW;
+      wall_vjp<R>(wt[w], wt[c.n_wall + w], wt[2 * c.n_wall + w], sc.uw[0], v, d_uw);
+      if (own(rx, ry)) {
+        pA += (double)d_uw * sc.duwA[0];
+        pW += (double)d_uw * sc.duwW[0];
       }
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) sob[idx * 9 + q] = u[q];
+    for (int q = 0; q < 9; ++q) sob[idx * 9 + q] = v[q];
+  }
+  for (int jn = threadIdx.x; jn < ATX * ATY; jn += ANT) {
+    const int gi = x0 + H + jn % ATX, gj = y0 + H + jn / ATX;
+    const bool iface = gi < g.nux && gj < g.nuy && c.ntype[gj * g.nux + gi] == NODE_INTERFACE;
+    const size_t p = iface ? (size_t)gj * g.nux + gi : 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      acc[jn * 18 + k] = (iface && !first) ? c.sbf[k * N + p] : R(0);
+      acc[jn * 18 + 9 + k] = (iface && !first) ? c.sbn[k * N + p] : R(0);
+    }
   }
   __syncthreads();
-  const int tx = threadIdx.x % ATX, ty = threadIdx.x / ATX;
-  const int gi = x0 + 1 + tx, gj = y0 + 1 + ty;
-  if (gi < g.nux && gj < g.nuy) {
-    const int ci = (ty + 1) * ARX + (tx + 1);
-    const size_t q = (size_t)gj * g.nux + gi;
-    const AdjClass<R> &cl = c.atab[c.acls[q]];
-    const int tq = cl.type, star = cl.star;
-    R accF[9], accN[9], sf[9], sn[9];
+
+  for (int sub = 0; sub < count; ++sub) {
+    const int m = m_hi - sub;
+    const int ex = count - 1 - sub;
+    const int W = ATX + 2 * ex, NA = W * (ATY + 2 * ex), o = H - ex;
+    const R *Um = tape0 + (size_t)m * 9 * N;
+    R out[PER][9];
+    int at[PER];
+    bool upd[PER];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) accF[k] = accN[k] = sf[k] = sn[k] = R(0);
+    for (int u = 0; u < PER; ++u) {
+      const int j = threadIdx.x + u * ANT;
+      const int rx = o + j % W, ry = o + j / W;
+      const int ci = j < NA ? ry * RX + rx : 0;
+      const int cls = j < NA ? scls[ci] : -1;
+      at[u] = ci;
+      upd[u] = cls >= 0;
 #pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-      const int ri = ci + (s / 3 - 1) * ARX + (s % 3 - 1);
-      const R gx = cl.Gx[s], gy = cl.Gy[s], cc = cl.C[s];
-      const bool st_s = (star >> s) & 1;
+      for (int k = 0; k < 9; ++k) out[u][k] = R(0);
+      if (!upd[u]) continue;
+      const size_t q = (size_t)(y0 + ry) * g.nux + (x0 + rx);
+      R f[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const R o = sob[ri * 9 + k];
-        const R st = c.dt * (R(CXd[k]) * gx + R(CYd[k]) * gy) * o;
-        const R ct = -c.dt_tau * cc * o;
-        if (st_s) {
-          sf[k] += st;
-          sn[k] += ct;
-        } else {
-          accF[k] += st;
-          accN[k] += ct;
-        }
-      }
-    }
-    // the node's own value: its f, or f* at an interface node
+      for (int k = 0; k < 9; ++k) f[k] = Um[k * N + q];
+      const AdjClass<R> &cl = c.atab[cls];
+      const int tq = cl.type, star = cl.star;
+      R accF[9], accN[9], sf[9], sn[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      if (tq == NODE_INTERFACE) sf[k] += sob[ci * 9 + k];
-      else accF[k] += sob[ci * 9 + k];
-    }
-    R f[9], e[9], rho, ux, uy, fb[9];
+      for (int k = 0; k < 9; ++k) accF[k] = accN[k] = sf[k] = sn[k] = R(0);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) f[k] = Um[k * N + q];
-    moments<R>(f, rho, ux, uy);
-    equilibrium<R>(rho, ux, uy, e);
-    node_chain<R>(rho, ux, uy, R(0), R(0), R(0), accN, fb);
-    double dn = 0.0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      ub_out[k * N + q] = accF[k] + fb[k];
-      dn += (double)accN[k] * (double)(f[k] - e[k]);
-    }
-    if (tq == NODE_INTERFACE) {
-      double ds = 0.0;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const R stn = c.star_n[k * N + q];
-        ds += (double)sn[k] * (double)stn;
-        if (!first) {
-          sf[k] += c.sbf[k * N + q];
-          sn[k] += c.sbn[k * N + q];
-        }
-        c.sbf[k * N + q] = sf[k];
-        c.sbn[k * N + q] = sn[k];
-      }
-      dn += ds;
-      if (last) {
-        // donor adjoint: f* = f^eq(rho, u) + k f^neq, f^neq* = k f^neq
-        R z[12], tot[9];
-        double dk = 0.0;
+      for (int s = 0; s < NSLOT; ++s) {
+        const int ri = ci + (s / 3 - 1) * RX + (s % 3 - 1);
+        const R gx = cl.Gx[s], gy = cl.Gy[s], cc = cl.C[s];
+        const bool st_s = (star >> s) & 1;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-          tot[k] = sf[k] + sn[k];
-          dk += (double)tot[k] * (double)c.star_n[k * N + q];
+          const R ov = sob[ri * 9 + k];
+          const R st = c.dt * (R(CXd[k]) * gx + R(CYd[k]) * gy) * ov;
+          const R ct = -c.dt_tau * cc * ov;
+          if (st_s) {
+            sf[k] += st;
+            sn[k] += ct;
+          } else {
+            accF[k] += st;
+            accN[k] += ct;
+          }
         }
-        equilibrium_vjp<R>(c.M2[q], c.M2[N + q], c.M2[2 * N + q], sf, z[0], z[1], z[2]);
+      }
+      // the node's own value: its f, or f* at an interface node
 #pragma unroll
-        for (int k = 0; k < 9; ++k) z[3 + k] = c.k_neq * tot[k];
+      for (int k = 0; k < 9; ++k) {
+        if (tq == NODE_INTERFACE) sf[k] += sob[ci * 9 + k];
+        else accF[k] += sob[ci * 9 + k];
+      }
+      R e[9], rho, ux, uy, fb[9];
+      moments<R>(f, rho, ux, uy);
+      equilibrium<R>(rho, ux, uy, e);
+      node_chain<R>(rho, ux, uy, R(0), R(0), R(0), accN, fb);
+      double dn = 0.0;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) c.Z2[k * N + q] = z[k];
-        // d f^neq*/d tau = (d k/d tau) f^neq = (d k/d tau)/k f^neq*
-        pT += dk * (1.0 / (2.0 * c.tau * c.tau)) / (double)c.k_neq;
+      for (int k = 0; k < 9; ++k) {
+        out[u][k] = accF[k] + fb[k];
+        dn += (double)accN[k] * (double)(f[k] - e[k]);
+      }
+      if (tq == NODE_INTERFACE) {
+        double ds = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ds += (double)sn[k] * (double)c.star_n[k * N + q];
+        dn += ds;
+      }
+      if (own(rx, ry)) {
+        // d(dt_u/tau_u)/d tau = -dt_u/tau_u^2: the collision adjoints carry -dt_u/tau_u
+        pT += dn * (-1.0 / c.tau_u);
+        if (tq == NODE_INTERFACE) {
+          const int jn = (ry - H) * ATX + (rx - H);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            acc[jn * 18 + k] += sf[k];
+            acc[jn * 18 + 9 + k] += sn[k];
+          }
+        }
       }
     }
-    // d(dt_u/tau_u)/d tau = -dt_u/tau_u^2: the collision adjoints carry -dt_u/tau_u
-    pT += dn * (-1.0 / c.tau_u);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      if (!upd[u]) continue;
+      const int ci = at[u];
+      if (sub + 1 < count) {  // pull a wall node back through sub-step m - 1's imposition
+        const int rx = ci % RX, ry = ci / RX;
+        const size_t p = (size_t)(y0 + ry) * g.nux + (x0 + rx);
+        if (c.ntype[p] == NODE_WALL) {
+          const R *wt = c.wt + (size_t)(m - 1) * 3 * c.n_wall;
+          const int w = c.widx[p];
+          R d_uw;
+          wall_vjp<R>(wt[w], wt[c.n_wall + w], wt[2 * c.n_wall + w], sc.uw[sub + 1], out[u], d_uw);
+          if (own(rx, ry)) {
+            pA += (double)d_uw * sc.duwA[sub + 1];
+            pW += (double)d_uw * sc.duwW[sub + 1];
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sob[ci * 9 + k] = out[u][k];
+    }
+    __syncthreads();
   }
-  block_accum3<NG>(pA, pW, pT, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+
+  // the tile is exact: write it back, with the running star sums
+  for (int jn = threadIdx.x; jn < ATX * ATY; jn += ANT) {
+    const int rx = H + jn % ATX, ry = H + jn / ATX;
+    const int gi = x0 + rx, gj = y0 + ry;
+    if (gi >= g.nux || gj >= g.nuy) continue;
+    const int ci = ry * RX + rx;
+    const size_t q = (size_t)gj * g.nux + gi;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) ub_out[k * N + q] = sob[ci * 9 + k];
+    if (c.ntype[q] != NODE_INTERFACE) continue;
+    R sf[9], sn[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      sf[k] = acc[jn * 18 + k];
+      sn[k] = acc[jn * 18 + 9 + k];
+      c.sbf[k * N + q] = sf[k];
+      c.sbn[k * N + q] = sn[k];
+    }
+    if (last) {
+      // donor adjoint: f* = f^eq(rho, u) + k f^neq, f^neq* = k f^neq
+      R z[12], tot[9];
+      double dk = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        tot[k] = sf[k] + sn[k];
+        dk += (double)tot[k] * (double)c.star_n[k * N + q];
+      }
+      equilibrium_vjp<R>(c.M2[q], c.M2[N + q], c.M2[2 * N + q], sf, z[0], z[1], z[2]);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) z[3 + k] = c.k_neq * tot[k];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) c.Z2[k * N + q] = z[k];
+      // d f^neq*/d tau = (d k/d tau) f^neq = (d k/d tau)/k f^neq*
+      pT += dk * (1.0 / (2.0 * c.tau * c.tau)) / (double)c.k_neq;
+    }
+  }
+  block_accum3<ANT>(pA, pW, pT, c.part + 3 * (size_t)(slot0 + blockIdx.x));
 }
 
 // ---- donor gather: dJ/d f_pre at lattice nodes read by bilinear donors ------------
@@ -639,10 +730,10 @@ int AdjKernels<T, R>::substep_slots(const AdjCtx<T, R> &c) {
   return ((c.gg.nux + ATX - 1) / ATX) * ((c.gg.nuy + ATY - 1) / ATY);
 }
 template <class T, class R>
-void AdjKernels<T, R>::substep(const AdjCtx<T, R> &c, const R *Um, const R *ub, R *ub_out, int m, R uw, double duwA,
-                               double duwW, int first, int last, int slot0, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_substep<T, R>), dim3(substep_slots(c)), dim3(NG), 0, s, c, Um, ub, ub_out, m, uw, duwA,
-                     duwW, first, last, slot0);
+void AdjKernels<T, R>::substeps(const AdjCtx<T, R> &c, const R *tape0, const R *ub, R *ub_out, int m_hi, int count,
+                                const AdjSubScal<R> &sc, int first, int last, int slot0, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_substeps<T, R>), dim3(substep_slots(c)), dim3(ANT), 0, s, c, tape0, ub, ub_out, m_hi,
+                     count, sc, first, last, slot0);
 }
 
 template <class T, class R>

@@ -1150,14 +1150,18 @@ class Case final : public CaseBase {
     c.Ubn = agrid_[1 - gc];
     AK::star(c, s_main_);
     AK::refill(c, slot_refill_, s_main_);
-    int gin = 1 - gc;  // holds the adjoint of the grid after sub-step m+1
-    for (int m = d_.n - 1; m >= 0; --m) {
-      const double tm = (double)k + (double)(m + 1) / (double)d_.n;
-      const R uw = (R)(A * om * std::cos(om * tm));
-      const double duwA = om * std::cos(om * tm);
-      const double duwW = A * std::cos(om * tm) - A * om * tm * std::sin(om * tm);
-      AK::substep(c, tape_grid(tape, j, m), agrid_[gin], agrid_[1 - gin], m, uw, duwA, duwW, m == d_.n - 1, m == 0,
-                  slot_sub_, s_main_);
+    int gin = 1 - gc;  // holds the adjoint of the grid after sub-step m_hi + 1
+    for (int m_hi = d_.n - 1; m_hi >= 0; m_hi -= 4) {
+      const int count = std::min(4, m_hi + 1);
+      AdjSubScal<R> sc{};
+      for (int i = 0; i < count; ++i) {
+        const double tm = (double)k + (double)(m_hi - i + 1) / (double)d_.n;
+        sc.uw[i] = (R)(A * om * std::cos(om * tm));
+        sc.duwA[i] = om * std::cos(om * tm);
+        sc.duwW[i] = A * std::cos(om * tm) - A * om * tm * std::sin(om * tm);
+      }
+      AK::substeps(c, tape_grid(tape, j, 0), agrid_[gin], agrid_[1 - gin], m_hi, count, sc, m_hi == d_.n - 1,
+                   m_hi - count + 1 == 0, slot_sub_, s_main_);
       gin = 1 - gin;
     }
     AK::donor_gather(c, slot_eg_, s_main_);
