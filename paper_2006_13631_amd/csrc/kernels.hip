@@ -246,6 +246,11 @@ __device__ __forceinline__ void grid_substeps_block(
   const int x0 = (t % tiles_x) * TX - H, y0 = (t / tiles_x) * TY - H;  // region origin
   const bool touches_ring = x0 <= 0 || y0 <= 0 || x0 + RX >= nux || y0 + G::RY >= nuy;
   const size_t N = (size_t)nux * nuy;
+  // the lamina velocity of every sub-step of the launch, read up front: a
+  // scalar load still in flight would hold up every later LDS wait
+  R uwv[H];
+#pragma unroll
+  for (int sub = 0; sub < H; ++sub) uwv[sub] = sub < count ? uw[k * n_sub + m0 + sub] : R(0);
 
   // stage the region; a lane's loads are issued together
   {
@@ -314,7 +319,7 @@ __device__ __forceinline__ void grid_substeps_block(
 #pragma unroll
   for (int sub = 0; sub < H; ++sub) {
     if (sub >= count) break;
-    const R uw_now = uw[k * n_sub + m0 + sub];
+    const R uw_now = uwv[sub];
     R out[PER][9];
     bool upd[PER];
 #pragma unroll
