@@ -239,6 +239,7 @@ __device__ __forceinline__ void grid_substeps_block(
   constexpr int TX = G::TX, TY = G::TY, RX = G::RX, RN = G::RN;
   constexpr int SPER = (RN + NT - 1) / NT;      // staging passes
   constexpr int PER = (G::MAXA + NT - 1) / NT;  // update passes
+  int at_s[H][PER], code_s[H][PER];
   extern __shared__ __align__(16) unsigned char lds_raw[];
   R *sl = reinterpret_cast<R *>(lds_raw);   // [RN][NS] grid f, f^neq
   R *rl = sl + NS * RN;                     // [NRING][NS] f*, f^neq* on the outer ring
@@ -302,7 +303,6 @@ __device__ __forceinline__ void grid_substeps_block(
   __syncthreads();
 
   // the node (region index) and code of every lane in every sub-step
-  int at_s[H][PER], code_s[H][PER];
 #pragma unroll
   for (int sub = 0; sub < H; ++sub) {
     const int ex = max(count - 1 - sub, 0);  // region growth still exact after sub-step `sub`
@@ -316,58 +316,60 @@ __device__ __forceinline__ void grid_substeps_block(
     }
   }
 
+  // Eq.(ulbe) at one node: streaming c_q . sum_s G_s f_q,s and collision
+  // sum_s C_s f^neq_q,s; on the outer ring an interpolation node reads
+  // structured-derived values instead (Eq.(postcollision2_u)). Absent
+  // neighbours have zero weights.
+  auto update_node = [&](int idx, int code, R o9[9]) {
+    const int rx = idx % RX, ry = idx / RX;
+    const int typ = code & 3;
+    const int gi = x0 + rx, gj = y0 + ry;
+    int row[NSLOT];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const int di = s % 3 - 1, dj = s / 3 - 1;
+      row[s] = (idx + dj * RX + di) * NS;
+      if (typ == NODE_INTERFACE) {
+        const int rs = ring_slot<G>(gi + di, gj + dj, rx + di, ry + dj, nux, nuy);
+        if (rs >= 0) row[s] = NS * RN + rs * NS;
+      }
+    }
+    const GridClass<R> &cl = tab[code >> 2];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      R ax = R(0), ay = R(0), sc = R(0);
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s) {
+        const R fq = sl[row[s] + q];
+        if (CXd[q] != 0) ax = fmad(cl.Gx[s], fq, ax);
+        if (CYd[q] != 0) ay = fmad(cl.Gy[s], fq, ay);
+        sc = fmad(cl.C[s], sl[row[s] + 9 + q], sc);
+      }
+      o9[q] = fmad(-dt_tau, sc, fmad(dt, R(CXd[q]) * ax + R(CYd[q]) * ay, sl[row[SELF_SLOT] + q]));
+    }
+  };
 #pragma unroll
   for (int sub = 0; sub < H; ++sub) {
     if (sub >= count) break;
     const R uw_now = uwv[sub];
     R out[PER][9];
-    bool upd[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int idx = at_s[sub][u], code = code_s[sub][u];
-      const int rx = idx % RX, ry = idx / RX;
-      upd[u] = code >= 0;
 #pragma unroll
       for (int q = 0; q < 9; ++q) out[u][q] = R(0);
-      if (__ballot(upd[u]) == 0) continue;  // nothing to update in this wave
-      const int typ = code & 3;
-      const int gi = x0 + rx, gj = y0 + ry;
-      // LDS row (offset from the LDS base) of each stencil slot; on the outer
-      // ring an interpolation node reads structured-derived values instead
-      // (Eq.(postcollision2_u)). Absent neighbours have zero weights.
-      int row[NSLOT];
-#pragma unroll
-      for (int s = 0; s < NSLOT; ++s) {
-        const int di = s % 3 - 1, dj = s / 3 - 1;
-        const int cidx = upd[u] ? idx + dj * RX + di : idx;
-        row[s] = cidx * NS;
-        if (typ == NODE_INTERFACE && upd[u]) {
-          const int rs = ring_slot<G>(gi + di, gj + dj, rx + di, ry + dj, nux, nuy);
-          if (rs >= 0) row[s] = NS * RN + rs * NS;
-        }
-      }
-      // streaming c_q . sum_s G_s f_q,s and collision sum_s C_s f^neq_q,s
-      const GridClass<R> &cl = tab[upd[u] ? code >> 2 : 0];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        R ax = R(0), ay = R(0), sc = R(0);
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s) {
-          const R fq = sl[row[s] + q];
-          if (CXd[q] != 0) ax = fmad(cl.Gx[s], fq, ax);
-          if (CYd[q] != 0) ay = fmad(cl.Gy[s], fq, ay);
-          sc = fmad(cl.C[s], sl[row[s] + 9 + q], sc);
-        }
-        out[u][q] = fmad(-dt_tau, sc, fmad(dt, R(CXd[q]) * ax + R(CYd[q]) * ay, sl[row[SELF_SLOT] + q]));
-      }
-      if (typ == NODE_WALL && upd[u]) {
+      if (__ballot(code >= 0) == 0) continue;  // nothing to update in this wave
+      if (code < 0) continue;
+      update_node(idx, code, out[u]);
+      if ((code & 3) == NODE_WALL) {
         // wall nodes: impose the lamina velocity, keep rho and f^neq
+        const int rx = idx % RX, ry = idx / RX;
         R e[9], ew[9], r, vx, vy;
         moments<R>(out[u], r, vx, vy);
         if (wtape && rx >= H && rx < H + TX && ry >= H && ry < H + TY) {
           // taped for the adjoint: the moments before the velocity is imposed
           R *wt = wtape + (size_t)(m0 + sub) * 3 * nwall;
-          const int w = widx[(size_t)gj * nux + gi];
+          const int w = widx[(size_t)(y0 + ry) * nux + (x0 + rx)];
           wt[w] = r;
           wt[nwall + w] = vx;
           wt[2 * nwall + w] = vy;
@@ -381,7 +383,7 @@ __device__ __forceinline__ void grid_substeps_block(
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      if (!upd[u]) continue;
+      if (code_s[sub][u] < 0) continue;
       const int idx = at_s[sub][u];
       R e[9], r, vx, vy;
       moments<R>(out[u], r, vx, vy);
@@ -421,30 +423,19 @@ __device__ __forceinline__ void grid_substeps_block(
 }
 
 // Variants of the sub-step kernel: tile shape and workgroup size (one lane
-// per region node while staging, so one lane per updated node in every
-// sub-step). Variant 3's LDS fits two workgroups on a CU in FP64.
+// per region node while staging). Variant 3's LDS fits two workgroups on a
+// CU in FP64 and more in FP32 (many small grids).
+template <int TXv, int TYv, int NTv>
+struct SubstepShape {
+  using G = Region<TXv, TYv, kSubstepBlock>;
+  static constexpr int NT = NTv;
+};
 template <int V>
 struct SubstepVariant;
-template <>
-struct SubstepVariant<0> {
-  using G = Region<16, 16, kSubstepBlock>;
-  static constexpr int NT = 576;
-};
-template <>
-struct SubstepVariant<1> {
-  using G = Region<32, 8, kSubstepBlock>;
-  static constexpr int NT = 640;
-};
-template <>
-struct SubstepVariant<2> {
-  using G = Region<64, 4, kSubstepBlock>;
-  static constexpr int NT = 896;
-};
-template <>
-struct SubstepVariant<3> {
-  using G = Region<16, 8, kSubstepBlock>;
-  static constexpr int NT = 384;
-};
+template <> struct SubstepVariant<0> : SubstepShape<16, 16, 576> {};
+template <> struct SubstepVariant<1> : SubstepShape<32, 8, 640> {};
+template <> struct SubstepVariant<2> : SubstepShape<64, 4, 896> {};
+template <> struct SubstepVariant<3> : SubstepShape<16, 8, 384> {};
 
 template <class R, int V>
 __global__ __launch_bounds__(SubstepVariant<V>::NT) void k_grid_substeps(
@@ -652,10 +643,17 @@ inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b
 
 void substep_tile(int variant, int *tx, int *ty) {
   switch (variant) {
-    case 1: *tx = SubstepVariant<1>::G::TX, *ty = SubstepVariant<1>::G::TY; break;
-    case 2: *tx = SubstepVariant<2>::G::TX, *ty = SubstepVariant<2>::G::TY; break;
-    case 3: *tx = SubstepVariant<3>::G::TX, *ty = SubstepVariant<3>::G::TY; break;
-    default: *tx = SubstepVariant<0>::G::TX, *ty = SubstepVariant<0>::G::TY; break;
+#define HLBM_TILE(V)                     \
+  case V:                                \
+    *tx = SubstepVariant<V>::G::TX;      \
+    *ty = SubstepVariant<V>::G::TY;      \
+    break;
+    HLBM_TILE(1) HLBM_TILE(2) HLBM_TILE(3)
+#undef HLBM_TILE
+    default:
+      *tx = SubstepVariant<0>::G::TX;
+      *ty = SubstepVariant<0>::G::TY;
+      break;
   }
 }
 
@@ -727,9 +725,10 @@ template <class T, class R>
 void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
                                   R *tape, R *wtape, const int *widx, int nwall, int variant) {
   switch (variant < 0 ? default_substep_variant<R>() : variant) {
-    case 1: grid_substeps_v<1>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
-    case 2: grid_substeps_v<2>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
-    case 3: grid_substeps_v<3>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
+#define HLBM_V(V) \
+  case V: grid_substeps_v<V>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
+    HLBM_V(1) HLBM_V(2) HLBM_V(3)
+#undef HLBM_V
     default: grid_substeps_v<0>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
   }
 }
