@@ -299,7 +299,7 @@ def precision_leg(workload="lamina_4096", steps=None, chunk=1000):
                    "fit_window_periods": [round(x, 3) for x in r["fit_window_periods"]],
                    "force_rel_err_vs_f64": err, "force_compared_steps": n,
                    "theta_rel_err_vs_f64": None if (th is None or th64 is None) else abs(th - th64) / abs(th64),
-                   "schedule": {k: r["schedule"][k] for k in ("lattice_threads", "lattice_rows", "substep_variant")}}
+                   "schedule": {k: r["schedule"][k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}}
     return out
 
 
@@ -414,7 +414,7 @@ def main():
         "config": {"workload": args.workload, "nx": nx, "ny": ny, "nux": cfg["nux"], "nuy": cfg["nuy"],
                    "b": cfg["b"], "tau": cfg["tau"], "kc": cfg["kc"], "beta": cfg["beta"],
                    "n_sub": info.n_sub, "storage": args.storage,
-                   "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant")}},
+                   "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.workload, args.storage),

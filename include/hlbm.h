@@ -113,7 +113,7 @@ typedef struct hlbm_info {
 
 /* Schedule of a handle, chosen by hlbm_tune. None of the choices changes
  * any result: every case computes the same bits. A single case uses the
- * stream-collide shape and the sub-step variant. */
+ * stream-collide shape and order and the sub-step variant. */
 typedef struct hlbm_tuning {
   int32_t steps_per_graph; /* structured steps captured in one HIP graph
                               (batch)                                      */
@@ -125,8 +125,10 @@ typedef struct hlbm_tuning {
                               workgroup size): -1 default (FP64 1, else
                               3); 0: 16x16, 576; 1: 32x8, 640; 2: 64x4,
                               896; 3: 16x8, 384                            */
-  int32_t order;           /* batch work lists: 0 case by case; 1 dealt to
-                              the 8 XCDs in contiguous chunks              */
+  int32_t order;           /* batch work lists: 0 case by case, 1 dealt to
+                              the 8 XCDs in contiguous chunks; single
+                              case: 1 gives each XCD a contiguous band of
+                              stream-collide rows                          */
   int32_t reserved;
   double ms_per_step;      /* measured for the chosen schedule (output)      */
 } hlbm_tuning;
@@ -234,7 +236,7 @@ int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count)
  * sub-step variant; work-list order) with the others held at the best so
  * far, keep the fastest and restore the initial state. Single case (any
  * time, state untouched): time trial_steps launches of the stream-collide
- * in each shape and of one step's sub-steps in each variant, reading the
+ * in each shape and order and of one step's sub-steps in each variant, reading the
  * current lattice and grid and writing only their free buffers, and keep
  * the fastest (ms_per_step: the two chosen kernels' time per step).
  * trial_steps = 0 applies *t as given instead (single case: lattice_threads

@@ -203,9 +203,10 @@ class Case final : public CaseBase {
   // (the events are taken at the kernel's own start and end on its stream).
   void stream_collide_timed(const CaseView<T, R> &v) {
     if (timing_) {
-      Kernels<T, R>::stream_collide(v, s_main_, tev_[tslot_][8], tev_[tslot_][2], lattice_threads_, lattice_rows_);
+      Kernels<T, R>::stream_collide(v, s_main_, tev_[tslot_][8], tev_[tslot_][2], lattice_threads_, lattice_rows_,
+                                    lattice_order_);
     } else {
-      Kernels<T, R>::stream_collide(v, s_main_, nullptr, nullptr, lattice_threads_, lattice_rows_);
+      Kernels<T, R>::stream_collide(v, s_main_, nullptr, nullptr, lattice_threads_, lattice_rows_, lattice_order_);
     }
   }
 
@@ -541,16 +542,17 @@ class Case final : public CaseBase {
     if (trial_steps == 0) {
       const bool keep_shape = t->lattice_threads == 0 && t->lattice_rows == 0;
       if ((!keep_shape && !valid_lattice_shape(*t)) || t->substep_variant < -1 ||
-          t->substep_variant >= kSubstepVariants)
+          t->substep_variant >= kSubstepVariants || t->order < 0 || t->order > 1)
         return fail(HLBM_E_ARG, "invalid schedule");
       if (!keep_shape) {
         lattice_threads_ = t->lattice_threads;
         lattice_rows_ = t->lattice_rows;
       }
       substep_variant_ = t->substep_variant;
+      lattice_order_ = t->order;
       HIPCHK(hipStreamSynchronize(s_main_));
       drop_graphs();
-      *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, 0, 0, 0.0};
+      *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, 0, 0.0};
       return HLBM_OK;
     }
     HIPCHK(hipDeviceSynchronize());
@@ -576,14 +578,17 @@ class Case final : public CaseBase {
     double total = 0.0;
     float best_ms = 3e38f;
     for (int lt : {128, 256})
-      for (int rows : {1, 2, 4}) {
-        const float ms = timed(s_main_, [&] { Kernels<T, R>::stream_collide(v, s_main_, nullptr, nullptr, lt, rows); });
-        if (e == hipSuccess && ms < best_ms) {
-          best_ms = ms;
-          lattice_threads_ = lt;
-          lattice_rows_ = rows;
+      for (int rows : {1, 2, 4})
+        for (int ord : {0, 1}) {
+          const float ms =
+              timed(s_main_, [&] { Kernels<T, R>::stream_collide(v, s_main_, nullptr, nullptr, lt, rows, ord); });
+          if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            lattice_threads_ = lt;
+            lattice_rows_ = rows;
+            lattice_order_ = ord;
+          }
         }
-      }
     total += best_ms;
     if (has_grid_) {
       best_ms = 3e38f;
@@ -606,7 +611,7 @@ class Case final : public CaseBase {
     (void)hipEventDestroy(e1);
     HIPCHK(e);
     drop_graphs();
-    *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, 0, 0, total / trial_steps};
+    *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, 0, total / trial_steps};
     return HLBM_OK;
   }
 
@@ -1113,7 +1118,7 @@ class Case final : public CaseBase {
       v.B = tape_lat(t, j + 1);
       v.counts = counts_scratch_;
       Kernels<T, R>::lattice_from_grid(v, tape_grid(t, j, 0), st);
-      Kernels<T, R>::stream_collide(v, st, nullptr, nullptr, lattice_threads_, lattice_rows_);
+      Kernels<T, R>::stream_collide(v, st, nullptr, nullptr, lattice_threads_, lattice_rows_, lattice_order_);
       Kernels<T, R>::interface_donors(v, st);
       for (int m = 0; m < d_.n; m += kSubstepBlock) {
         const int cnt = std::min(kSubstepBlock, d_.n - m);
@@ -1198,6 +1203,7 @@ class Case final : public CaseBase {
   int timing_ = 0;  // 1: every kernel, 2: the stream-collide only
   int substep_variant_ = -1;  // grid sub-step kernel variant (-1: the default for R)
   int lattice_threads_ = kLatticeThreads, lattice_rows_ = kLatticeRows;  // stream-collide launch shape
+  int lattice_order_ = 0;  // 1: stream-collide rows banded by XCD
   double tms_[8] = {};
   int64_t tcount_[8] = {};
   std::vector<void *> owned_;

@@ -79,9 +79,10 @@ struct Kernels {
   static void fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStream_t s);  // whole planes
   // start/stop (optional): events recorded at the kernel's own start and end
   // threads x rows: workgroup width and lattice rows per lane (1, 2 or 4);
-  // <= 0 takes kLatticeThreads / kLatticeRows
+  // <= 0 takes kLatticeThreads / kLatticeRows; order 1: each XCD takes a
+  // contiguous band of rows
   static void stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start = nullptr,
-                             hipEvent_t stop = nullptr, int threads = 0, int rows = 0);
+                             hipEvent_t stop = nullptr, int threads = 0, int rows = 0, int order = 0);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
   static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
   // sub-steps m0 .. m0+count-1 (count <= kSubstepBlock) in one launch; with

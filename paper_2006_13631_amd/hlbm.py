@@ -178,16 +178,17 @@ class Case:
         self._check(load().hlbm_get_stencil(self.h, kmax, _ptr(nbr, C.c_int32), _ptr(S), _ptr(Cm)))
         return nbr, S, Cm
 
-    def tune(self, trial_steps=4, variant=None, lattice=None):
-        """Pick the stream-collide launch shape and the grid sub-step kernel
-        variant by timing each (state untouched), or apply ``variant`` (-1 =
-        default) and ``lattice`` = (threads, rows) as given. Returns the
-        schedule."""
+    def tune(self, trial_steps=4, variant=None, lattice=None, order=None):
+        """Pick the stream-collide launch shape and order and the grid
+        sub-step kernel variant by timing each (state untouched), or apply
+        ``variant`` (-1 = default), ``lattice`` = (threads, rows) and
+        ``order`` (1: rows banded by XCD) as given. Returns the schedule."""
         t = Tuning()
-        if variant is not None or lattice is not None:
+        if variant is not None or lattice is not None or order is not None:
             t.substep_variant = -1 if variant is None else variant
             if lattice is not None:
                 t.lattice_threads, t.lattice_rows = lattice
+            t.order = 0 if order is None else order
             trial_steps = 0
         self._check(load().hlbm_tune(self.h, trial_steps, C.byref(t)))
         return t.as_dict()

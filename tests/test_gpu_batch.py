@@ -93,8 +93,9 @@ def test_substep_variants_compute_identical_bits(storage):
     for v in range(4):
         _say("sub-step variant", v, "stream-collide shape", shapes[v], "storage", storage)
         g = hlbm.Case(storage=storage, **c)
-        t = g.tune(variant=v, lattice=shapes[v])
+        t = g.tune(variant=v, lattice=shapes[v], order=v % 2)
         assert t["substep_variant"] == v and (t["lattice_threads"], t["lattice_rows"]) == shapes[v]
+        assert t["order"] == v % 2
         g.step(n)
         _same(g, want)
 
@@ -117,7 +118,7 @@ def test_single_case_tune_leaves_state_alone():
     a.step(n - n // 2)
     b.step(n - n // 2)
     _same(a, b)
-    for bad in (dict(variant=4), dict(lattice=(96, 1)), dict(lattice=(128, 3))):
+    for bad in (dict(variant=4), dict(lattice=(96, 1)), dict(lattice=(128, 3)), dict(order=2)):
         with pytest.raises(hlbm.HlbmError) as e:
             a.tune(**bad)
         assert e.value.code == hlbm.E_ARG
