@@ -98,10 +98,26 @@ static int wrap(int a, int n) { return ((a % n) + n) % n; }
 /* Streaming (left side of Eq.(LBE)) written in pull form: the population
  * arriving at (x,y) along c_i left x - c_i one step earlier. Across a y wall
  * (bc 0) it is the opposite population of the same node, reflected halfway;
- * a wall moving with x-velocity uw adds 2 w_i rho0 c_i.u_w / c_s^2. */
+ * a wall moving with x-velocity uw adds 2 w_i rho0 c_i.u_w / c_s^2.
+ * The paper's boundaries (bc 2): across an x wall (at rest) the same
+ * halfway reflection; at a y end, where no population arrives from outside,
+ * the incoming one equals that of the next row in (zero normal gradient),
+ * which that node pulled from this node's own row. A population crossing
+ * both a wall and an end (corner nodes) is reflected by the wall. */
 static void pull_node(const real *A, int nx, int ny, int bc, int x, int y,
                       real u_bot, real u_top, real f[9]) {
   for (int i = 0; i < 9; ++i) {
+    if (bc == OR_BC_PAPER) {
+      const int xp = x - CX[i];
+      if (xp < 0 || xp >= nx) {
+        f[i] = A[lidx(nx, ny, OPP[i], x, y)];
+        continue;
+      }
+      int yp = y - CY[i];
+      if (yp < 0 || yp >= ny) yp = y;
+      f[i] = A[lidx(nx, ny, i, xp, yp)];
+      continue;
+    }
     const int xs = wrap(x - CX[i], nx);
     int ys = y - CY[i];
     if (bc == OR_BC_PERIODIC) {
@@ -816,7 +832,7 @@ int or_create(const or_config *c, or_sim **out) {
   if (!c || !out) return OR_E_ARG;
   *out = NULL;
   if (c->nx < 3 || c->ny < 3 || !(c->tau > 0.5) || c->max_steps < 0) return OR_E_ARG;
-  if (c->bc != OR_BC_PERIODIC_X_WALLS_Y && c->bc != OR_BC_PERIODIC) return OR_E_ARG;
+  if (c->bc != OR_BC_PERIODIC_X_WALLS_Y && c->bc != OR_BC_PERIODIC && c->bc != OR_BC_PAPER) return OR_E_ARG;
   const int has_mesh = (c->nux > 0 || c->nuy > 0);
   const int body = has_mesh && c->b > 0.0 && !(c->flags & OR_FLAG_NO_BODY);
   or_sim *s = xcalloc(1, sizeof(or_sim));
@@ -886,7 +902,7 @@ int or_create(const or_config *c, or_sim **out) {
     const double hx = (double)(c->nux / 2) * s->h, hxr = (double)(c->nux - 1 - c->nux / 2) * s->h;
     const double hy = 0.5 * (double)(c->nuy - 1) * s->h;
     if (s->xc - hx < 1.0 || s->xc + hxr > (double)c->nx - 2.0) { free_sim(s); return OR_E_ARG; }
-    if (c->bc == OR_BC_PERIODIC_X_WALLS_Y &&
+    if (c->bc != OR_BC_PERIODIC &&
         (s->yc - hy - fabs(RE(s->A)) < 1.0 || s->yc + hy + fabs(RE(s->A)) > (double)c->ny - 2.0)) {
       free_sim(s);
       return OR_E_ARG;

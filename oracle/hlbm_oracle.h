@@ -25,6 +25,9 @@ extern "C" {
 /* boundary conditions of the background lattice */
 #define OR_BC_PERIODIC_X_WALLS_Y 0 /* periodic in x, halfway bounce-back walls at y=-1/2, ny-1/2 */
 #define OR_BC_PERIODIC 1           /* periodic in x and y */
+#define OR_BC_PAPER 2              /* the paper's outer boundaries (Sec. Problem statement):
+                                      no-slip walls at x=-1/2, nx-1/2 (halfway bounce-back),
+                                      zero-gradient outflow at the y ends */
 
 /* mesh node roles (Sec. Refill procedure) */
 #define OR_NODE_INTERIOR 0  /* discretization node of the body-fitted grid      */

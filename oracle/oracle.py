@@ -25,6 +25,7 @@ _LIB_CS = os.path.join(_HERE, "liboracle_cs.so")
 
 BC_PERIODIC_X_WALLS_Y = 0
 BC_PERIODIC = 1
+BC_PAPER = 2
 FLAG_NO_BODY = 1
 NODE_INTERIOR, NODE_INTERFACE, NODE_WALL = 0, 1, 2
 

@@ -144,3 +144,82 @@ def test_stokes_second_problem_lattice(oracle):
     e2, d2 = _stokes_lattice(oracle, 1600, 96)
     assert 10 * d1 < 48 and 10 * d2 < 96
     assert e1 < 0.02 and e2 < e1, (e1, e2)
+
+
+# ---- the paper's outer boundaries: no-slip x walls, outflow y ends ----------
+
+def test_paper_boundaries_stream_as_defined(oracle):
+    """Pure streaming (tau -> infinity) on a random state: interior
+    populations shift along c_i; at an x wall the incoming population is the
+    node's own opposite one (halfway bounce-back at rest); at a y end the
+    incoming population equals that of the next row in (zero normal
+    gradient); at the four corners the wall decides."""
+    from paper_2006_13631_amd.workloads import random_populations
+    cx, cy, w = oracle.d2q9()
+    opp = [int(np.flatnonzero((cx == -cx[i]) & (cy == -cy[i]))[0]) for i in range(9)]
+    ny, nx = 7, 9
+    A = random_populations((9, ny, nx), seed=11, base=w, spread=0.3)
+    B = oracle.lattice_step(A, 1e300, bc=oracle.BC_PAPER)
+    for i in range(9):
+        for y in range(ny):
+            for x in range(nx):
+                xs, ys = x - cx[i], y - cy[i]
+                if not 0 <= xs < nx:
+                    want = A[opp[i], y, x]
+                elif not 0 <= ys < ny:
+                    want = B[i, y + cy[i], x]   # the next row in
+                else:
+                    want = A[i, ys, xs]
+                assert B[i, y, x] == want, (i, y, x)
+
+
+def test_paper_boundaries_rest_and_uniform_rows(oracle):
+    """The rest state is a fixed point, and a state that does not vary
+    along y stays so exactly (the outflow ends then act like periodic ones)."""
+    from paper_2006_13631_amd.workloads import random_populations
+    _, _, w = oracle.d2q9()
+    A = np.broadcast_to(w[:, None, None], (9, 12, 10)).copy()
+    B = A
+    for _ in range(10):
+        B = oracle.lattice_step(B, 0.7, bc=oracle.BC_PAPER)
+    assert np.max(np.abs(A - B)) < 1e-15
+    row = random_populations((9, 1, 10), seed=5, base=w, spread=0.05)
+    A = np.repeat(row, 8, axis=1)
+    for _ in range(25):
+        A = oracle.lattice_step(A, 0.9, bc=oracle.BC_PAPER)
+    assert np.max(np.abs(A - A[:, :1, :])) == 0.0
+
+
+def _channel_shear_decay(oracle, nx, tau=0.8, steps=None, U=1e-4):
+    """u_y(x) = U sin(pi (x + 1/2) / nx) between the no-slip x walls (at
+    x = -1/2 and nx - 1/2), uniform along y: decays as exp(-nu k^2 t),
+    k = pi / nx. Returns the relative error of the measured rate."""
+    cx, cy, w = oracle.d2q9()
+    nu = (tau - 0.5) / 3.0
+    k = math.pi / nx
+    x = np.arange(nx) + 0.5
+    uy = U * np.sin(k * x)
+    f = np.zeros((9, 4, nx))
+    for i in range(9):
+        f[i] = w[i] * (1.0 + 3.0 * cy[i] * uy + 4.5 * (cy[i] * uy) ** 2 - 1.5 * uy ** 2)[None, :]
+    steps = steps or int(round(0.5 / (nu * k * k)))
+    amp0 = None
+    for t in range(steps + 1):
+        if t == steps // 4:
+            r = f.sum(0)
+            amp0 = ((cy[:, None, None] * f).sum(0) / r)[0] @ np.sin(k * x)
+        if t < steps:
+            f = oracle.lattice_step(f, tau, bc=oracle.BC_PAPER)
+    r = f.sum(0)
+    amp1 = ((cy[:, None, None] * f).sum(0) / r)[0] @ np.sin(k * x)
+    rate = -math.log(amp1 / amp0) / (steps - steps // 4)
+    return abs(rate - nu * k * k) / (nu * k * k)
+
+
+def test_paper_boundaries_channel_shear_decay(oracle):
+    """No-slip walls in x: the slowest shear mode of the channel decays at the
+    viscous rate nu (pi/nx)^2, to second order in the resolution."""
+    e16 = _channel_shear_decay(oracle, 16)
+    e32 = _channel_shear_decay(oracle, 32)
+    assert e32 < 1e-2
+    assert e16 / e32 > 3.0
