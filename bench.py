@@ -303,6 +303,56 @@ def precision_leg(workload="lamina_4096", steps=None, chunk=1000):
     return out
 
 
+def study_leg(b=64, storage="f64", tune_steps=8, chunk=2000):
+    """The paper's (epsilon, beta) study (35 pairs under Eq.(betalimit), 5L x 5L
+    domain, the paper's outer boundaries) as one batch; Theta of each case
+    beside the semianalytical values the paper compares with (context: a
+    different discretisation and resolution, not a parity bar)."""
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.theory import theta_semianalytical
+    from paper_2006_13631_amd.workloads import paper_study_cases
+    cases = paper_study_cases(b=b)
+    cfgs = [{k: v for k, v in c.items() if k not in ("eps", "beta_p")} for c in cases]
+    t0 = time.perf_counter()
+    batch = H.Batch(cfgs, storage=H.STORAGE[storage])
+    sched = batch.tune(trial_steps=tune_steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    longest = max(c["max_steps"] for c in cfgs)
+    done = 0
+    while done < longest:
+        n = min(chunk, longest - done)
+        batch.step(n)
+        done += n
+        print(f"# study {done}/{longest} steps", file=sys.stderr, flush=True)
+    batch[0].info()
+    t2 = time.perf_counter()
+    rows = []
+    devs_re, devs_im = [], []
+    for i, c in enumerate(cases):
+        inf = batch[i].info()
+        th = batch[i].theta() if inf.status == H.STATUS_DONE else None
+        ref = theta_semianalytical(c["beta_p"], c["eps"])
+        row = {"eps": c["eps"], "beta": c["beta_p"], "steps": c["max_steps"], "status": int(inf.status),
+               "theta": None if th is None else [round(th.real, 5), round(th.imag, 5)],
+               "semianalytical": [round(ref.real, 5), round(ref.imag, 5)]}
+        if th is not None:
+            row["dev_re"] = round((th.real - ref.real) / ref.real, 4)
+            row["dev_im"] = round((th.imag - ref.imag) / ref.imag, 4)
+            devs_re.append(abs(row["dev_re"]))
+            devs_im.append(abs(row["dev_im"]))
+        rows.append(row)
+    import statistics
+    return {"metric": "the paper's (epsilon, beta) study: Theta per case, cases/hour", "unit": "cases/hour",
+            "storage": storage, "cases": len(cases), "lattice": f"{5 * b}^2 (5L x 5L), L = {b}",
+            "grid": f"{4 * b} x {b}", "bc": "paper (no-slip x walls, outflow y ends)",
+            "tau": cases[0]["tau"], "schedule": sched, "setup_s": round(t1 - t0, 2), "run_s": round(t2 - t1, 2),
+            "value": round(len(cases) / ((t2 - t0) / 3600.0), 1),
+            "median_abs_dev_re": statistics.median(devs_re) if devs_re else None,
+            "median_abs_dev_im": statistics.median(devs_im) if devs_im else None, "per_case": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +377,10 @@ def main():
                     help="run only the storage-precision comparison (FP64 / FP32 / FP16-deviation) and print its line")
     ap.add_argument("--precision-workload", default="lamina_4096,lamina_4096_stable")
     ap.add_argument("--precision-steps", type=int, default=None)
+    ap.add_argument("--study", action="store_true",
+                    help="run only the paper's (epsilon, beta) study as one batch and print its line")
+    ap.add_argument("--study-b", type=int, default=64)
+    ap.add_argument("--study-storage", default="f64", choices=list(BYTES))
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
@@ -339,6 +393,10 @@ def main():
     if args.sweep:
         torch.cuda.set_device(0)
         print(json.dumps(sweep_leg(periods=args.sweep_periods, loop=not args.sweep_no_loop)), flush=True)
+        return
+    if args.study:
+        torch.cuda.set_device(0)
+        print(json.dumps(study_leg(args.study_b, args.study_storage)), flush=True)
         return
     if args.precision:
         torch.cuda.set_device(0)

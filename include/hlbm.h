@@ -48,6 +48,12 @@ extern "C" {
 #define HLBM_BC_PERIODIC_X_WALLS_Y 0 /* periodic in x; halfway bounce-back walls
                                         at rest at y = -1/2 and y = ny - 1/2 */
 #define HLBM_BC_PERIODIC 1           /* periodic in x and y                  */
+#define HLBM_BC_PAPER 2              /* the paper's outer boundaries (Sec.
+                                        Problem statement): no-slip walls at
+                                        x = -1/2, nx - 1/2 (halfway bounce-
+                                        back) and zero-gradient outflow at the
+                                        y ends; no adjoint (ckpt_every must
+                                        be 0: HLBM_E_UNSUPPORTED)             */
 
 /* ---- storage of the lattice populations ------------------------------- */
 #define HLBM_FP64 0     /* FP64 storage and arithmetic                          */

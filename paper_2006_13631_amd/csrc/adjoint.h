@@ -30,7 +30,7 @@ struct AdjClass {
 template <class T, class R>
 struct AdjCtx {
   // lattice
-  int nx, ny, periodic_y, has_grid;
+  int nx, ny, bc, has_grid;
   size_t plane;      // population-plane stride of Lt, Lb_next and Lb
   const T *Lt;       // taped lattice of step k after the grid-to-lattice writes (L'_k)
   const R *Lb_next;  // adjoint of L_{k+1}, [9][ny][nx]

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(NG) void k_adj_star(AdjCtx<T, R> c) {
   if (valid) {
     p = c.iface[t];
     const int i = p % c.gg.nux, j = p / c.gg.nux;
-    donor_corner<T, R>(c.Lt, c.nx, c.ny, c.plane, c.periodic_y, grid_x(c.gg, i), grid_y(c.gg, c.P.ybase, j), d, acc);
+    donor_corner<T, R>(c.Lt, c.nx, c.ny, c.plane, c.bc, grid_x(c.gg, i), grid_y(c.gg, c.P.ybase, j), d, acc);
   }
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NG) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
     for (int s = 0; s < 9; ++s) ub[s] = c.Ub_next[s * N + q];
     if (kind == 1) {
       R rho, ux, uy, fneq[9];
-      lattice_bilinear<T, R>(c.Lt, c.nx, c.ny, c.plane, c.periodic_y, grid_x(g, i), grid_y(g, c.P.ybase1, j), rho, ux,
+      lattice_bilinear<T, R>(c.Lt, c.nx, c.ny, c.plane, c.bc, grid_x(g, i), grid_y(g, c.P.ybase1, j), rho, ux,
                              uy, fneq);
       equilibrium_vjp<R>(rho, ux, uy, ub, z[0], z[1], z[2]);
       double sn = 0.0;
@@ -512,7 +512,7 @@ __global__ __launch_bounds__(NG) void k_adj_donor_gather(AdjCtx<T, R> c, int slo
       }
       if (any) {
         R f[9], e[9], rho, ux, uy, fneq[9];
-        pull<T, R>(c.Lt, c.nx, c.ny, c.plane, c.periodic_y, x, y, f);
+        pull<T, R>(c.Lt, c.nx, c.ny, c.plane, c.bc, x, y, f);
         moments<R>(f, rho, ux, uy);
         equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(NT) void k_adj_stream_collide(AdjCtx<T, R> c, int s
   if (x < c.nx) {
     const size_t plane = c.plane, cc = (size_t)y * c.nx + x;
     size_t idx[9];
-    pull_index(c.nx, c.ny, c.plane, c.periodic_y, x, y, idx);
+    pull_index(c.nx, c.ny, c.plane, c.bc, x, y, idx);
     const bool inside = c.has_grid && x >= c.P.ix0 && x <= c.P.ix1 && y >= c.P.iy0 && y <= c.P.iy1;
     R v[9];
     if (inside) {

@@ -784,7 +784,7 @@ class Case final : public CaseBase {
     v.nx = cfg_.nx;
     v.plane = plane_;
     v.ny = cfg_.ny;
-    v.periodic_y = cfg_.bc == HLBM_BC_PERIODIC;
+    v.bc = cfg_.bc;
     v.inv_tau = (R)(1.0 / cfg_.tau);
     v.g_post = (R)(2.0 * (cfg_.tau - 1.0) / (2.0 * cfg_.tau - 1.0));
     v.k_neq = (R)(1.0 - 1.0 / (2.0 * cfg_.tau));
@@ -1040,7 +1040,7 @@ class Case final : public CaseBase {
     c.nx = cfg_.nx;
     c.plane = plane_;
     c.ny = cfg_.ny;
-    c.periodic_y = cfg_.bc == HLBM_BC_PERIODIC;
+    c.bc = cfg_.bc;
     c.has_grid = 1;
     c.tau = cfg_.tau;
     c.tau_u = d_.tau_u;
@@ -1265,7 +1265,16 @@ class Case final : public CaseBase {
 int validate(const hlbm_config &c, std::string *err) {
   if (c.nx < 3 || c.ny < 3) { *err = "lattice needs nx, ny >= 3"; return HLBM_E_ARG; }
   if (!(c.tau > 0.5)) { *err = "tau must exceed 1/2"; return HLBM_E_ARG; }
-  if (c.bc != HLBM_BC_PERIODIC_X_WALLS_Y && c.bc != HLBM_BC_PERIODIC) { *err = "unknown bc"; return HLBM_E_ARG; }
+  if (c.bc != HLBM_BC_PERIODIC_X_WALLS_Y && c.bc != HLBM_BC_PERIODIC && c.bc != HLBM_BC_PAPER) {
+    *err = "unknown bc";
+    return HLBM_E_ARG;
+  }
+  if (c.bc == HLBM_BC_PAPER && c.ckpt_every > 0) {
+    // the outflow ends read some populations twice, so the pull is not a
+    // permutation and the adjoint's push form does not hold
+    *err = "no adjoint with the paper's outflow boundaries";
+    return HLBM_E_UNSUPPORTED;
+  }
   if (c.storage < HLBM_FP64 || c.storage > HLBM_FP16_DEV) { *err = "unknown storage"; return HLBM_E_ARG; }
   if (c.max_steps < 0 || c.n_sub < 0 || c.reserved != 0 || c.ckpt_every < 0) { *err = "invalid counts"; return HLBM_E_ARG; }
   if (c.flags & ~HLBM_FLAG_NO_BODY) { *err = "unknown flags"; return HLBM_E_ARG; }
@@ -1280,7 +1289,7 @@ int validate(const hlbm_config &c, std::string *err) {
   const double hx = (double)(c.nux / 2) * h, hxr = (double)(c.nux - 1 - c.nux / 2) * h;
   const double hy = 0.5 * (double)(c.nuy - 1) * h;
   if (d.xc - hx < 1.0 || d.xc + hxr > (double)c.nx - 2.0) { *err = "grid leaves the lattice in x"; return HLBM_E_ARG; }
-  if (c.bc == HLBM_BC_PERIODIC_X_WALLS_Y &&
+  if (c.bc != HLBM_BC_PERIODIC &&
       (d.yc - hy - std::fabs(d.A) < 1.0 || d.yc + hy + std::fabs(d.A) > (double)c.ny - 2.0)) {
     *err = "grid motion leaves the lattice in y";
     return HLBM_E_ARG;

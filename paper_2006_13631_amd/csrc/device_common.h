@@ -123,20 +123,29 @@ __device__ __forceinline__ void node_chain(R rho, R ux, R uy, R zr, R zx, R zy, 
 
 // ---- streaming ----------------------------------------------------------------
 // Flat indices into a [9][plane] array (plane >= ny * nx, row-major nodes)
-// of the nine values the pull of node (x, y) reads: population q arriving at (x, y) left x - c_q one step
-// earlier; across a resting y wall, halfway bounce-back returns the opposite
-// population of the node itself. Every (population, node) pair of the array
-// is the source of exactly one (q, node) pair, so the adjoint of the pull is
-// a push to these same addresses.
-__device__ __forceinline__ void pull_index(int nx, int ny, size_t plane, int periodic_y, int x, int y,
-                                           size_t idx[9]) {
+// of the nine values the pull of node (x, y) reads: population q arriving
+// at (x, y) left x - c_q one step earlier. bc 0: periodic in x, and across a
+// resting y wall halfway bounce-back returns the opposite population of the
+// node itself; bc 1: periodic in x and y; bc 2 (the paper's boundaries):
+// the same bounce-back across the x walls, and at a y end the incoming
+// population equals that of the next row in (zero normal gradient), i.e. it
+// is pulled from the node's own row; a population crossing both a wall and
+// an end is reflected by the wall. For bc 0 and 1 every (population, node)
+// pair of the array is the source of exactly one (q, node) pair, so the
+// adjoint of the pull is a push to these same addresses (not so for bc 2).
+__device__ __forceinline__ void pull_index(int nx, int ny, size_t plane, int bc, int x, int y, size_t idx[9]) {
   const int xm = x == 0 ? nx - 1 : x - 1;
   const int xp = x == nx - 1 ? 0 : x + 1;
   int ym = y - 1, yp = y + 1;
-  bool lo = false, hi = false;
-  if (periodic_y) {
+  bool lo = false, hi = false, wl = false, wr = false;
+  if (bc == 1) {
     ym = y == 0 ? ny - 1 : ym;
     yp = y == ny - 1 ? 0 : yp;
+  } else if (bc == 2) {
+    ym = y == 0 ? y : ym;
+    yp = y == ny - 1 ? y : yp;
+    wl = (x == 0);
+    wr = (x == nx - 1);
   } else {
     lo = (y == 0);
     hi = (y == ny - 1);
@@ -144,23 +153,23 @@ __device__ __forceinline__ void pull_index(int nx, int ny, size_t plane, int per
   const size_t r = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
   const size_t c = r + x;
   idx[0] = c;
-  idx[1] = 1 * plane + r + xm;
-  idx[3] = 3 * plane + r + xp;
+  idx[1] = wl ? 3 * plane + c : 1 * plane + r + xm;
+  idx[3] = wr ? 1 * plane + c : 3 * plane + r + xp;
   idx[2] = lo ? 4 * plane + c : 2 * plane + rm + x;
-  idx[5] = lo ? 7 * plane + c : 5 * plane + rm + xm;
-  idx[6] = lo ? 8 * plane + c : 6 * plane + rm + xp;
+  idx[5] = wl ? 7 * plane + c : (lo ? 7 * plane + c : 5 * plane + rm + xm);
+  idx[6] = wr ? 8 * plane + c : (lo ? 8 * plane + c : 6 * plane + rm + xp);
   idx[4] = hi ? 2 * plane + c : 4 * plane + rp + x;
-  idx[7] = hi ? 5 * plane + c : 7 * plane + rp + xp;
-  idx[8] = hi ? 6 * plane + c : 8 * plane + rp + xm;
+  idx[7] = wr ? 5 * plane + c : (hi ? 5 * plane + c : 7 * plane + rp + xp);
+  idx[8] = wl ? 6 * plane + c : (hi ? 6 * plane + c : 8 * plane + rp + xm);
 }
 
 // Populations arriving at lattice node (x, y) at t_{k+1}: pulled from the
 // post-collision buffer of t_k (left side of Eq.(LBE)).
 template <class T, class R>
-__device__ __forceinline__ void pull(const T *__restrict__ A, int nx, int ny, size_t plane, int periodic_y, int x,
+__device__ __forceinline__ void pull(const T *__restrict__ A, int nx, int ny, size_t plane, int bc, int x,
                                      int y, R f[9]) {
   size_t idx[9];
-  pull_index(nx, ny, plane, periodic_y, x, y, idx);
+  pull_index(nx, ny, plane, bc, x, y, idx);
   // a bounced-back value comes from the opposite population, whose rest
   // weight w_i is the same
 #pragma unroll
@@ -276,7 +285,7 @@ __device__ __forceinline__ RefillCell refill_cell(const GridGeom &g, double ybas
 // density, velocity and f^neq = f - f^eq of the pre-collision populations at
 // t_{k+1} pulled from A (refill type 1 and the grid's interface donors).
 template <class T, class R>
-__device__ __forceinline__ void lattice_bilinear(const T *__restrict__ A, int nx, int ny, size_t plane, int periodic_y,
+__device__ __forceinline__ void lattice_bilinear(const T *__restrict__ A, int nx, int ny, size_t plane, int bc,
                                                  double X, double Y, R &rho, R &ux, R &uy, R fneq[9]) {
   const double fx = floor(X), fy = floor(Y);
   const double a = X - fx, b = Y - fy;
@@ -289,9 +298,9 @@ __device__ __forceinline__ void lattice_bilinear(const T *__restrict__ A, int nx
   for (int d = 0; d < 4; ++d) {
     int xd = x0 + (d & 1), yd = y0 + (d >> 1);
     xd = xd >= nx ? xd - nx : (xd < 0 ? xd + nx : xd);
-    if (periodic_y) yd = yd >= ny ? yd - ny : (yd < 0 ? yd + ny : yd);
+    if (bc) yd = yd >= ny ? yd - ny : (yd < 0 ? yd + ny : yd);
     R f[9], e[9], r, vx, vy;
-    pull<T, R>(A, nx, ny, plane, periodic_y, xd, yd, f);
+    pull<T, R>(A, nx, ny, plane, bc, xd, yd, f);
     moments<R>(f, r, vx, vy);
     equilibrium<R>(r, vx, vy, e);
     const R w = R(w4[d]);
@@ -306,16 +315,16 @@ __device__ __forceinline__ void lattice_bilinear(const T *__restrict__ A, int nx
 // One lane's share of an interface node's donors: corner d of the lattice
 // cell around (X, Y), weighted (rho, u_x, u_y, f^neq[9]) in acc[12].
 template <class T, class R>
-__device__ __forceinline__ void donor_corner(const T *__restrict__ A, int nx, int ny, size_t plane, int periodic_y,
+__device__ __forceinline__ void donor_corner(const T *__restrict__ A, int nx, int ny, size_t plane, int bc,
                                              double X, double Y, int d, R acc[12]) {
   const double fx = floor(X), fy = floor(Y);
   const double a = X - fx, b = Y - fy;
   const double w = (d & 1 ? a : 1.0 - a) * (d >> 1 ? b : 1.0 - b);
   int xd = (int)fx + (d & 1), yd = (int)fy + (d >> 1);
   xd = xd >= nx ? xd - nx : (xd < 0 ? xd + nx : xd);
-  if (periodic_y) yd = yd >= ny ? yd - ny : (yd < 0 ? yd + ny : yd);
+  if (bc) yd = yd >= ny ? yd - ny : (yd < 0 ? yd + ny : yd);
   R f[9], e[9], r, vx, vy;
-  pull<T, R>(A, nx, ny, plane, periodic_y, xd, yd, f);
+  pull<T, R>(A, nx, ny, plane, bc, xd, yd, f);
   moments<R>(f, r, vx, vy);
   equilibrium<R>(r, vx, vy, e);
   const R wr = R(w);

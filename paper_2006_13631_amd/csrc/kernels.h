@@ -14,7 +14,7 @@ struct CaseView {
   T *B;            // post-collision populations at t_{k+1}
   int nx, ny;
   size_t plane;    // elements from one population plane to the next (>= nx * ny)
-  int periodic_y;  // 1: periodic in y, 0: halfway bounce-back walls
+  int bc;          // HLBM_BC_*: 0 periodic x + y walls, 1 periodic, 2 x walls + y outflow
   R inv_tau;       // 1 / tau_s
   R g_post;        // 2 (tau_s - 1) / (2 tau_s - 1), Eq.(postcollision2_s)
   R k_neq;         // 1 - 1/(2 tau_s), Eq.(continuity_stresses)

@@ -46,7 +46,7 @@ __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, co
   R f[RPT][9];
 #pragma unroll
   for (int r = 0; r < RPT; ++r)
-    if (by * RPT + r < v.ny) pull<T, R>(A, v.nx, v.ny, plane, v.periodic_y, x, by * RPT + r, f[r]);
+    if (by * RPT + r < v.ny) pull<T, R>(A, v.nx, v.ny, plane, v.bc, x, by * RPT + r, f[r]);
   int ix0 = 1, ix1 = 0, iy0 = 1, iy1 = 0;  // empty rectangle without a grid
   if (v.has_grid) {
     const StepParams &P = v.params[*k_at];
@@ -154,7 +154,7 @@ __device__ __forceinline__ void interface_donors_block(const CaseView<T, R> &v, 
     const int i = p % v.nux, j = p / v.nux;
     const double X = v.xc + (double)(i - v.nux / 2) * v.h;
     const double Y = P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
-    donor_corner<T, R>(A, v.nx, v.ny, v.plane, v.periodic_y, X, Y, d, acc);
+    donor_corner<T, R>(A, v.nx, v.ny, v.plane, v.bc, X, Y, d, acc);
   }
 #pragma unroll
   for (int r = 0; r < 12; ++r) {
@@ -511,7 +511,7 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
     const double X = v.xc + (double)(i - v.nux / 2) * v.h;
     const double Ynew = P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
     R rho, ux, uy, fneq[9], e[9];
-    lattice_bilinear<T, R>(A, v.nx, v.ny, v.plane, v.periodic_y, X, Ynew, rho, ux, uy, fneq);
+    lattice_bilinear<T, R>(A, v.nx, v.ny, v.plane, v.bc, X, Ynew, rho, ux, uy, fneq);
     equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = e[q] + v.k_neq * fneq[q];

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhlbm.so")
 
 OK, E_ARG, E_NOMEM, E_HIP, E_UNSTABLE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-BC_PERIODIC_X_WALLS_Y, BC_PERIODIC = 0, 1
+BC_PERIODIC_X_WALLS_Y, BC_PERIODIC, BC_PAPER = 0, 1, 2
 FP64, FP32, FP16_DEV = 0, 1, 2
 FLAG_NO_BODY = 1
 STATE_LATTICE, STATE_GRID, STATE_ADJ_LATTICE, STATE_ADJ_GRID = 0, 1, 2, 3

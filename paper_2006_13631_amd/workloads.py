@@ -99,6 +99,32 @@ def sweep_cases(seed: int = 0, periods: float = 10.0, mach: float = 0.05):
     return out, flagged
 
 
+# the paper's parameter grid (Sec. Problem statement)
+STUDY_EPS = (0.02, 0.03, 0.04, 0.05, 0.075, 0.1)
+STUDY_BETA = (20, 50, 100, 150, 200, 250, 300)
+
+
+def paper_study_cases(b: int = 64, tau: float = 0.7, periods: float = 4.0):
+    """The (epsilon, beta) study of the paper as runnable configurations:
+    every pair of the grid with beta < 2.6 epsilon^-1.6 (Eq.(betalimit); 35
+    pairs), on a 5L x 5L lattice with the paper's outer boundaries (bc 2),
+    lamina L = b, body-fitted grid 4L x L, one relaxation time (the paper
+    keeps tau between 0.7 and 0.9), KC = 2 pi epsilon, and enough steps for
+    the fit window [T, 4T). Each configuration also carries its eps and
+    beta_p (the paper's beta) for reporting."""
+    out = []
+    nu = (tau - 0.5) / 3.0
+    for eps in STUDY_EPS:
+        for beta in STUDY_BETA:
+            if not beta < 2.6 * eps ** -1.6:
+                continue
+            period = b * b / (nu * beta)
+            out.append(dict(nx=5 * b, ny=5 * b, nux=4 * b, nuy=b, h_u=1.0, b=float(b), thickness=1.0, tau=tau,
+                            kc=2.0 * math.pi * eps, beta=float(beta), bc=2,
+                            max_steps=int(math.ceil(periods * period)) + 1, eps=eps, beta_p=beta))
+    return out
+
+
 def random_populations(shape, seed: int, base: np.ndarray, spread: float = 0.02) -> np.ndarray:
     """base * (1 + u), u uniform in [-spread, spread]; base broadcasts over the
     trailing axes of ``shape`` (first axis = population index)."""

@@ -32,7 +32,10 @@ def _cases():
     d = preset("tiny_adjoint", bc=hlbm.BC_PERIODIC)
     d.pop("steps")
     d["max_steps"] = 75
-    return [a, b, c, d]
+    from paper_2006_13631_amd.workloads import paper_study_cases
+    e = {k: v for k, v in paper_study_cases(b=16)[-1].items() if k not in ("eps", "beta_p")}
+    e["max_steps"] = 80                                  # the paper's boundaries, 80^2
+    return [a, b, c, d, e]
 
 
 def _solo(cfg, storage):
@@ -151,7 +154,7 @@ def test_unstable_case_stops_alone():
     batch.step(100)
     inf = batch[1].info()
     assert inf.status == hlbm.STATUS_UNSTABLE and inf.step < cfgs[1]["max_steps"]
-    for i in (0, 2, 3):
+    for i in (0, 2, 3, 4):
         assert batch[i].info().status == hlbm.STATUS_DONE
         _same(batch[i], _solo(cfgs[i], hlbm.FP64))
 

@@ -74,7 +74,7 @@ def test_stencil_matches_oracle(oracle, name):
     assert g.info().n_classes < 200
 
 
-@pytest.mark.parametrize("bc", [hlbm.BC_PERIODIC_X_WALLS_Y, hlbm.BC_PERIODIC])
+@pytest.mark.parametrize("bc", [hlbm.BC_PERIODIC_X_WALLS_Y, hlbm.BC_PERIODIC, hlbm.BC_PAPER])
 def test_lattice_only_random_state(oracle, bc):
     """Eq.(LBE) alone on a ragged 77 x 45 lattice from a random state."""
     _say("lattice only bc", bc)
@@ -138,6 +138,36 @@ def test_periodic_lattice_with_body(oracle):
     o, g, n = _pair(oracle, preset("tiny_ragged"), bc=hlbm.BC_PERIODIC)
     o.step(n)
     g.step(n)
+    _check_state(o, g)
+
+
+def test_paper_boundaries_with_body(oracle):
+    """No-slip x walls and outflow y ends around the lamina, random start on
+    both grids (ragged lattice, odd grid width)."""
+    _say("paper boundaries with lamina")
+    cfg = preset("tiny_ragged")
+    o, g, n = _pair(oracle, cfg, bc=hlbm.BC_PAPER)
+    _, _, w = oracle.d2q9()
+    fl = random_populations((9, cfg["ny"], cfg["nx"]), seed=31, base=w, spread=0.01)
+    fg = random_populations((9, o.nnode), seed=32, base=w, spread=0.01)
+    for s in (o, g):
+        s.set_lattice(fl)
+        s.set_grid(fg)
+    o.step(n)
+    g.step(n)
+    _check_state(o, g)
+
+
+def test_paper_study_case(oracle):
+    """A case of the paper's (epsilon, beta) study at a small size: 5L x 5L
+    domain with the paper's boundaries, grid 4L x L."""
+    from paper_2006_13631_amd.workloads import paper_study_cases
+    c = [c for c in paper_study_cases(b=16) if c["eps"] == 0.1 and c["beta_p"] == 100][0]
+    cfg = {k: v for k, v in c.items() if k not in ("eps", "beta_p", "max_steps")}
+    _say("paper study case", cfg)
+    o, g, _ = _pair(oracle, dict(cfg, steps=300))
+    o.step(300)
+    g.step(300)
     _check_state(o, g)
 
 
