@@ -347,7 +347,7 @@ def study_leg(b=64, storage="f64", tune_steps=8, chunk=2000):
     return {"metric": "the paper's (epsilon, beta) study: Theta per case, cases/hour", "unit": "cases/hour",
             "storage": storage, "cases": len(cases), "lattice": f"{5 * b}^2 (5L x 5L), L = {b}",
             "grid": f"{4 * b} x {b}", "bc": "paper (no-slip x walls, outflow y ends)",
-            "tau": cases[0]["tau"], "schedule": sched, "setup_s": round(t1 - t0, 2), "run_s": round(t2 - t1, 2),
+            "tau": [round(min(c["tau"] for c in cases), 4), round(max(c["tau"] for c in cases), 4)], "schedule": sched, "setup_s": round(t1 - t0, 2), "run_s": round(t2 - t1, 2),
             "value": round(len(cases) / ((t2 - t0) / 3600.0), 1),
             "median_abs_dev_re": statistics.median(devs_re) if devs_re else None,
             "median_abs_dev_im": statistics.median(devs_im) if devs_im else None, "per_case": rows}

@@ -104,20 +104,25 @@ STUDY_EPS = (0.02, 0.03, 0.04, 0.05, 0.075, 0.1)
 STUDY_BETA = (20, 50, 100, 150, 200, 250, 300)
 
 
-def paper_study_cases(b: int = 64, tau: float = 0.7, periods: float = 4.0):
+def paper_study_cases(b: int = 64, waves: float = 4.0, periods: float = 4.0, tau_max: float = 0.9):
     """The (epsilon, beta) study of the paper as runnable configurations:
     every pair of the grid with beta < 2.6 epsilon^-1.6 (Eq.(betalimit); 35
     pairs), on a 5L x 5L lattice with the paper's outer boundaries (bc 2),
-    lamina L = b, body-fitted grid 4L x L, one relaxation time (the paper
-    keeps tau between 0.7 and 0.9), KC = 2 pi epsilon, and enough steps for
-    the fit window [T, 4T). Each configuration also carries its eps and
-    beta_p (the paper's beta) for reporting."""
+    lamina L = b, body-fitted grid 4L x L, KC = 2 pi epsilon, and enough
+    steps for the fit window [T, 4T). The paper keeps tau between 0.7 and 0.9
+    with L = 800 lattice units; at a small L that would make the acoustic
+    wavelength c_s T shorter than the domain, so here the viscosity is chosen
+    per case for c_s T = waves x 5L, i.e. nu = c_s L / (5 waves beta), with
+    tau at most tau_max. Each configuration also carries its eps and beta_p
+    (the paper's beta) for reporting."""
     out = []
-    nu = (tau - 0.5) / 3.0
+    cs = 1.0 / math.sqrt(3.0)
     for eps in STUDY_EPS:
         for beta in STUDY_BETA:
             if not beta < 2.6 * eps ** -1.6:
                 continue
+            tau = min(tau_max, 0.5 + 3.0 * cs * b / (5.0 * waves * beta))
+            nu = (tau - 0.5) / 3.0
             period = b * b / (nu * beta)
             out.append(dict(nx=5 * b, ny=5 * b, nux=4 * b, nuy=b, h_u=1.0, b=float(b), thickness=1.0, tau=tau,
                             kc=2.0 * math.pi * eps, beta=float(beta), bc=2,

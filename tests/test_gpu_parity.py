@@ -162,7 +162,7 @@ def test_paper_study_case(oracle):
     """A case of the paper's (epsilon, beta) study at a small size: 5L x 5L
     domain with the paper's boundaries, grid 4L x L."""
     from paper_2006_13631_amd.workloads import paper_study_cases
-    c = [c for c in paper_study_cases(b=16) if c["eps"] == 0.1 and c["beta_p"] == 100][0]
+    c = [c for c in paper_study_cases(b=16) if c["eps"] == 0.1 and c["beta_p"] == 20][0]
     cfg = {k: v for k, v in c.items() if k not in ("eps", "beta_p", "max_steps")}
     _say("paper study case", cfg)
     o, g, _ = _pair(oracle, dict(cfg, steps=300))
