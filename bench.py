@@ -353,6 +353,41 @@ def study_leg(b=64, storage="f64", tune_steps=8, chunk=2000):
             "median_abs_dev_im": statistics.median(devs_im) if devs_im else None, "per_case": rows}
 
 
+def storage_leg(workload, storage, steps, warmup, timing_steps):
+    """The same workload at another storage precision: lattice MLUPS over
+    graph-replayed steps, the stream-collide's mean duration (its own events)
+    against its algorithmic bytes, and Theta over the steps run."""
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.workloads import preset
+    cfg = preset(workload)
+    case = H.case_from_preset(cfg, storage=storage, max_steps=warmup + steps + timing_steps)
+    case.step(warmup)
+    sched = case.tune(trial_steps=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    case.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    case.timing(2)
+    case.step(timing_steps)
+    ms, n = case.timing_get(H.K_STREAM_COLLIDE)
+    case.timing(0)
+    nodes = cfg["nx"] * cfg["ny"]
+    avg = ms / 1000.0 / max(n, 1)
+    gbs = 18 * BYTES[storage] * nodes / avg / 1e9
+    th = None
+    try:
+        th = case.theta()
+    except H.HlbmError:
+        pass
+    return {"storage": storage, "value": round(nodes * steps / dt / 1e6, 2), "unit": "MLUPS",
+            "ms_per_step": round(1000.0 * dt / steps, 4), "stream_collide_us": round(avg * 1e6, 3),
+            "stream_collide_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "theta": None if th is None else [th.real, th.imag],
+            "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +404,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=None)
     ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--no-f32", action="store_true", help="skip the FP32 line of the main workload")
     ap.add_argument("--sweep", action="store_true",
                     help="run only the parametric sweep (FP32 batch vs FP64 per-case loop) and print its line")
     ap.add_argument("--sweep-periods", type=float, default=10.0)
@@ -482,6 +518,10 @@ def main():
         "mlups_total": round((nx * ny + info.n_sub * info.nnode) * steps / dt / 1e6, 2),
         "theta": None if th is None else [th.real, th.imag],
     }
+    case.close()
+    if args.storage == "f64" and not args.no_f32:
+        # the sweep-scale configuration is quoted at FP64 and FP32
+        out["f32"] = storage_leg(args.workload, "f32", steps, W, args.timing_steps)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_workload, H.STORAGE[args.adjoint_storage], args.adjoint_window,
                                      0.0 if args.no_fd else 1e-4, args.adjoint_steps)
