@@ -52,8 +52,7 @@ extern "C" {
                                         Problem statement): no-slip walls at
                                         x = -1/2, nx - 1/2 (halfway bounce-
                                         back) and zero-gradient outflow at the
-                                        y ends; no adjoint (ckpt_every must
-                                        be 0: HLBM_E_UNSUPPORTED)             */
+                                        y ends                                */
 
 /* ---- storage of the lattice populations ------------------------------- */
 #define HLBM_FP64 0     /* FP64 storage and arithmetic                          */

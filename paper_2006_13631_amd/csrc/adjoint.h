@@ -70,6 +70,8 @@ struct AdjCtx {
   int k2_x0, k2_w, k2_h;
   R *E;                     // [9][eh][ew] adjoint of the pre-collision f at donor lattice nodes
   int ex0, ey0, ew, eh;
+  R *Vend;                  // outflow ends (bc 2): [4][9][nx] post-collision adjoints of rows 0, 1,
+                            // ny-2, ny-1, gathered into the end rows of Lb afterwards
   double *part;             // parameter partial sums [slots][3] (A, omega, tau)
 };
 

@@ -575,10 +575,64 @@ __global__ __launch_bounds__(NT) void k_adj_stream_collide(AdjCtx<T, R> c, int s
         for (int q = 0; q < 9; ++q) v[q] += c.E[q * eplane + at];
       }
     }
+    if (c.bc == 2) {
+      // outflow ends: a source in an end row may have two readers (the next
+      // row in, and the end node through the zero-gradient copy) or none;
+      // those rows are gathered by k_adj_outflow_ends from the adjoints kept
+      // here for the two rows at each end
+      const int er = y <= 1 ? y : (y >= c.ny - 2 ? 4 - (c.ny - y) : -1);
+      if (er >= 0) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) c.Lb[idx[q]] = v[q];
+        for (int q = 0; q < 9; ++q) c.Vend[((size_t)er * 9 + q) * c.nx + x] = v[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const size_t row = (idx[q] % plane) / (size_t)c.nx;
+        if (row != 0 && row != (size_t)(c.ny - 1)) c.Lb[idx[q]] = v[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) c.Lb[idx[q]] = v[q];
+    }
   }
   block_accum3<NT>(0.0, 0.0, pT, c.part + 3 * (size_t)(slot0 + blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// Outflow ends (bc 2): every population of the two end rows of Lb is the sum
+// of the adjoints of all (node, population) pairs whose pull read it, found
+// among the nine nodes around it, in a fixed order.
+template <class T, class R>
+__global__ __launch_bounds__(NT) void k_adj_outflow_ends(AdjCtx<T, R> c) {
+  const int x = blockIdx.x * NT + threadIdx.x;
+  const int end = blockIdx.y;  // 0: row 0, 1: row ny - 1
+  if (x >= c.nx) return;
+  const int y = end ? c.ny - 1 : 0;
+  const size_t plane = c.plane, s = (size_t)y * c.nx + x;
+  R acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = R(0);
+  for (int dy = -1; dy <= 1; ++dy) {
+    const int ty = y + dy;
+    if (ty < 0 || ty >= c.ny) continue;
+    const int er = ty <= 1 ? ty : 4 - (c.ny - ty);  // ty is within two rows of this end
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int tx = x + dx;
+      if (tx < 0 || tx >= c.nx) continue;
+      size_t idx[9];
+      pull_index(c.nx, c.ny, plane, c.bc, tx, ty, idx);
+#pragma unroll
+      for (int qp = 0; qp < 9; ++qp) {
+        if (idx[qp] % plane != s) continue;
+        const int q = (int)(idx[qp] / plane);
+        const R v = c.Vend[((size_t)er * 9 + qp) * c.nx + tx];
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+          if (k == q) acc[k] += v;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) c.Lb[q * plane + s] = acc[q];
 }
 
 // ---- grid-to-lattice adjoint, lattice side ---------------------------------------
@@ -758,6 +812,7 @@ void AdjKernels<T, R>::stream_collide(const AdjCtx<T, R> &c, int slot0, hipStrea
   } else {
     hipLaunchKernelGGL((k_adj_stream_collide<T, R>), dim3(blocks(c.nx, NT), c.ny), dim3(NT), 0, s, c, slot0);
   }
+  if (c.bc == 2) hipLaunchKernelGGL((k_adj_outflow_ends<T, R>), dim3(blocks(c.nx, NT), 2), dim3(NT), 0, s, c);
 }
 
 template <class T, class R>

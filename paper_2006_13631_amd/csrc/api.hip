@@ -968,6 +968,7 @@ class Case final : public CaseBase {
     HIPCHK(alloc(&zf_, (size_t)N));
     HIPCHK(alloc(&Z3_, 12 * (size_t)k2_w_ * k2_h_ * sizeof(R)));
     HIPCHK(alloc(&E_, 9 * (size_t)ew_ * eh_ * sizeof(R)));
+    if (cfg_.bc == HLBM_BC_PAPER) HIPCHK(alloc(&Vend_, 4 * 9 * (size_t)cfg_.nx * sizeof(R)));
     HIPCHK(alloc(&grad_dev_, 3 * sizeof(double)));
     HIPCHK(alloc(&counts_scratch_, 2 * sizeof(unsigned long long)));
     HIPCHK(hipMemset(Z2_, 0, 12 * (size_t)N * sizeof(R)));
@@ -1076,6 +1077,7 @@ class Case final : public CaseBase {
     c.k2_w = k2_w_;
     c.k2_h = k2_h_;
     c.E = E_;
+    c.Vend = Vend_;
     c.ex0 = ex0_;
     c.ey0 = ey0_;
     c.ew = ew_;
@@ -1244,6 +1246,7 @@ class Case final : public CaseBase {
   R *alat_[2] = {nullptr, nullptr}, *agrid_[2] = {nullptr, nullptr};
   int adj_lc_ = 0, adj_gc_ = 0;
   R *M2_ = nullptr, *sbf_ = nullptr, *sbn_ = nullptr, *Z1_ = nullptr, *Z2_ = nullptr, *Z3_ = nullptr, *E_ = nullptr;
+  R *Vend_ = nullptr;  // outflow ends: adjoints of the two rows at each end
   unsigned char *zf_ = nullptr;
   int *wall_nodes_ = nullptr, *widx_ = nullptr, *acls_ = nullptr;
   unsigned char *ntype_ = nullptr;
@@ -1268,12 +1271,6 @@ int validate(const hlbm_config &c, std::string *err) {
   if (c.bc != HLBM_BC_PERIODIC_X_WALLS_Y && c.bc != HLBM_BC_PERIODIC && c.bc != HLBM_BC_PAPER) {
     *err = "unknown bc";
     return HLBM_E_ARG;
-  }
-  if (c.bc == HLBM_BC_PAPER && c.ckpt_every > 0) {
-    // the outflow ends read some populations twice, so the pull is not a
-    // permutation and the adjoint's push form does not hold
-    *err = "no adjoint with the paper's outflow boundaries";
-    return HLBM_E_UNSUPPORTED;
   }
   if (c.storage < HLBM_FP64 || c.storage > HLBM_FP16_DEV) { *err = "unknown storage"; return HLBM_E_ARG; }
   if (c.max_steps < 0 || c.n_sub < 0 || c.reserved != 0 || c.ckpt_every < 0) { *err = "invalid counts"; return HLBM_E_ARG; }

@@ -147,6 +147,27 @@ def test_adjoint_periodic_bc(oracle):
     _compare(gpu, ref)
 
 
+def test_adjoint_paper_boundaries(oracle):
+    """The paper's outer boundaries (no-slip x walls, outflow y ends), random
+    start: parameters, the grid direction, a lattice direction over the
+    whole lattice and one confined to the two rows at each outflow end and
+    the wall columns (the rows whose sources have two readers or none)."""
+    _say("adjoint, paper boundaries")
+    c = _cfg("tiny_adjoint", bc=hlbm.BC_PAPER)
+    n = 30
+    f0, g0, dirs = _random_state(oracle, c, 61)
+    _, _, wq = oracle.d2q9()
+    rng = np.random.default_rng(64)
+    edge = np.zeros(f0.shape)
+    edge[:, [0, 1, -2, -1], :] = rng.standard_normal((9, 4, c["nx"])) * wq[:, None, None]
+    edge[:, :, [0, -1]] = rng.standard_normal((9, c["ny"], 2)) * wq[:, None, None]
+    dirs = dirs + [(edge, np.zeros(g0.shape))]
+    w = _weights(n, 17)
+    ref = _oracle_derivatives(oracle, c, n, w, f0, g0, dirs)
+    gpu, _ = _gpu_derivatives(c, n, w, f0, g0, dirs, ckpt=8)
+    _compare(gpu, ref, names=("A", "omega", "tau", "lattice", "grid", "edges"))
+
+
 @pytest.mark.timeout(600)
 def test_adjoint_lamina_128x64_copy(oracle):
     """The 128 x 64 copy of the differentiation case over two 200-step
