@@ -65,7 +65,10 @@ constexpr int kLatticeThreads = 128, kLatticeRows = 2;
 // workgroup size):
 //   0: 16 x 16, 576 threads   1: 32 x 8, 640 threads
 //   2: 64 x 4, 896 threads    3: 16 x 8, 384 threads
-constexpr int kSubstepVariants = 4;
+//   4: 8 x 8, 64 threads      5: 16 x 8, 128 threads
+//   6: 16 x 16, 256 threads   7: 8 x 4, 64 threads
+// (4-7: several nodes per lane, more workgroups per CU)
+constexpr int kSubstepVariants = 8;
 template <class R>
 constexpr int default_substep_variant() {
   return sizeof(R) == 8 ? 1 : 3;  // fastest at the 512 x 128 grid (hlbm_tune measures)

@@ -441,6 +441,10 @@ template <> struct SubstepVariant<0> : SubstepShape<16, 16, 576> {};
 template <> struct SubstepVariant<1> : SubstepShape<32, 8, 640> {};
 template <> struct SubstepVariant<2> : SubstepShape<64, 4, 896> {};
 template <> struct SubstepVariant<3> : SubstepShape<16, 8, 384> {};
+template <> struct SubstepVariant<4> : SubstepShape<8, 8, 64> {};
+template <> struct SubstepVariant<5> : SubstepShape<16, 8, 128> {};
+template <> struct SubstepVariant<6> : SubstepShape<16, 16, 256> {};
+template <> struct SubstepVariant<7> : SubstepShape<8, 4, 64> {};
 
 template <class R, int V>
 __global__ __launch_bounds__(SubstepVariant<V>::NT) void k_grid_substeps(
@@ -653,7 +657,7 @@ void substep_tile(int variant, int *tx, int *ty) {
     *tx = SubstepVariant<V>::G::TX;      \
     *ty = SubstepVariant<V>::G::TY;      \
     break;
-    HLBM_TILE(1) HLBM_TILE(2) HLBM_TILE(3)
+    HLBM_TILE(1) HLBM_TILE(2) HLBM_TILE(3) HLBM_TILE(4) HLBM_TILE(5) HLBM_TILE(6) HLBM_TILE(7)
 #undef HLBM_TILE
     default:
       *tx = SubstepVariant<0>::G::TX;
@@ -670,7 +674,8 @@ hipError_t Kernels<T, R>::prepare() {
   struct {
     const void *f, *fb;
     int lds;
-  } fns[] = {HLBM_LDS(0), HLBM_LDS(1), HLBM_LDS(2), HLBM_LDS(3)};
+  } fns[] = {HLBM_LDS(0), HLBM_LDS(1), HLBM_LDS(2), HLBM_LDS(3),
+             HLBM_LDS(4), HLBM_LDS(5), HLBM_LDS(6), HLBM_LDS(7)};
 #undef HLBM_LDS
   for (const auto &e : fns) {
     hipError_t rc = hipFuncSetAttribute(e.f, hipFuncAttributeMaxDynamicSharedMemorySize, e.lds);
@@ -735,7 +740,7 @@ void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, 
   switch (variant < 0 ? default_substep_variant<R>() : variant) {
 #define HLBM_V(V) \
   case V: grid_substeps_v<V>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
-    HLBM_V(1) HLBM_V(2) HLBM_V(3)
+    HLBM_V(1) HLBM_V(2) HLBM_V(3) HLBM_V(4) HLBM_V(5) HLBM_V(6) HLBM_V(7)
 #undef HLBM_V
     default: grid_substeps_v<0>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
   }
@@ -789,6 +794,10 @@ void Kernels<T, R>::batched(BatchKernel which, const CaseView<T, R> *views, cons
         case 1: HLBM_KB(1); break;
         case 2: HLBM_KB(2); break;
         case 3: HLBM_KB(3); break;
+        case 4: HLBM_KB(4); break;
+        case 5: HLBM_KB(5); break;
+        case 6: HLBM_KB(6); break;
+        case 7: HLBM_KB(7); break;
         default: HLBM_KB(0); break;
 #undef HLBM_KB
       }

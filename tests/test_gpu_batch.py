@@ -92,8 +92,8 @@ def test_substep_variants_compute_identical_bits(storage):
     c["max_steps"] = n
     want = hlbm.Case(storage=storage, **c)
     want.step(n)
-    shapes = [(128, 1), (256, 2), (64, 4), (192, 1)]
-    for v in range(4):
+    shapes = [(128, 1), (256, 2), (64, 4), (192, 1)] * 2
+    for v in range(8):
         _say("sub-step variant", v, "stream-collide shape", shapes[v], "storage", storage)
         g = hlbm.Case(storage=storage, **c)
         t = g.tune(variant=v, lattice=shapes[v], order=v % 2)
@@ -115,13 +115,13 @@ def test_single_case_tune_leaves_state_alone():
     lat, grid = a.lattice().copy(), a.grid().copy()
     t = a.tune(trial_steps=2)
     _say("chosen", t)
-    assert 0 <= t["substep_variant"] < 4 and t["ms_per_step"] > 0
+    assert 0 <= t["substep_variant"] < 8 and t["ms_per_step"] > 0
     assert t["lattice_threads"] in (128, 256) and t["lattice_rows"] in (1, 2, 4)
     assert np.array_equal(a.lattice(), lat) and np.array_equal(a.grid(), grid)
     a.step(n - n // 2)
     b.step(n - n // 2)
     _same(a, b)
-    for bad in (dict(variant=4), dict(lattice=(96, 1)), dict(lattice=(128, 3)), dict(order=2)):
+    for bad in (dict(variant=8), dict(lattice=(96, 1)), dict(lattice=(128, 3)), dict(order=2)):
         with pytest.raises(hlbm.HlbmError) as e:
             a.tune(**bad)
         assert e.value.code == hlbm.E_ARG
