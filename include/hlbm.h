@@ -136,7 +136,9 @@ typedef struct hlbm_tuning {
                               the 8 XCDs in contiguous chunks; single
                               case: 1 gives each XCD a contiguous band of
                               stream-collide rows                          */
-  int32_t reserved;
+  int32_t tail_variant;    /* batch: sub-step variant once at most
+                              max(1, ncases/8) cases still run (-1: the
+                              same as substep_variant); single case: -1    */
   double ms_per_step;      /* measured for the chosen schedule (output)      */
 } hlbm_tuning;
 
@@ -241,7 +243,9 @@ int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count)
  * schedules for trial_steps steps of the whole batch, one choice at a time
  * (steps per graph 4/8/16; stream-collide shape 128/256 x 1/2/4 rows;
  * sub-step variant; work-list order) with the others held at the best so
- * far, keep the fastest and restore the initial state. Single case (any
+ * far, then the sub-step variant on the longest-running max(1, ncases/8)
+ * cases alone (tail_variant), keep the fastest and restore the initial
+ * state. Single case (any
  * time, state untouched): time trial_steps launches of the stream-collide
  * in each shape and order and of one step's sub-steps in each variant, reading the
  * current lattice and grid and writing only their free buffers, and keep

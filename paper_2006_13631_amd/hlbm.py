@@ -57,7 +57,7 @@ class Info(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("steps_per_graph", C.c_int32), ("lattice_threads", C.c_int32),
                 ("lattice_rows", C.c_int32), ("substep_variant", C.c_int32), ("order", C.c_int32),
-                ("reserved", C.c_int32), ("ms_per_step", C.c_double)]
+                ("tail_variant", C.c_int32), ("ms_per_step", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -312,7 +312,8 @@ class Batch:
 
     def tune(self, trial_steps=16, schedule=None):
         """Autotune (trial_steps > 0) or apply ``schedule`` (dict) as given."""
-        t = Tuning(steps_per_graph=8, lattice_threads=128, lattice_rows=2, substep_variant=-1, order=1)
+        t = Tuning(steps_per_graph=8, lattice_threads=128, lattice_rows=2, substep_variant=-1, order=1,
+                   tail_variant=-1)
         if schedule:
             for k, v in schedule.items():
                 setattr(t, k, v)

@@ -67,6 +67,7 @@ def test_batch_matches_single_cases_bitwise(storage):
     dict(steps_per_graph=16, lattice_threads=256, lattice_rows=2, substep_variant=1, order=0),
     dict(steps_per_graph=1, lattice_threads=64, lattice_rows=4, substep_variant=2, order=1),
     dict(steps_per_graph=8, lattice_threads=192, lattice_rows=2, substep_variant=3, order=0),
+    dict(steps_per_graph=4, lattice_threads=128, lattice_rows=2, substep_variant=6, order=1, tail_variant=3),
 ])
 def test_schedules_do_not_change_results(schedule):
     _say("schedule", schedule)
