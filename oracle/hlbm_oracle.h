@@ -28,6 +28,10 @@ extern "C" {
 #define OR_BC_PAPER 2              /* the paper's outer boundaries (Sec. Problem statement):
                                       no-slip walls at x=-1/2, nx-1/2 (halfway bounce-back),
                                       zero-gradient outflow at the y ends */
+#define OR_BC_RING 3               /* the outermost ring of nodes is given from outside
+                                      (a refinement level fed by the next coarser one):
+                                      ring nodes are not updated, every other node pulls
+                                      from inside the lattice */
 
 /* mesh node roles (Sec. Refill procedure) */
 #define OR_NODE_INTERIOR 0  /* discretization node of the body-fitted grid      */
@@ -132,6 +136,33 @@ int or_set_mesh(or_sim *s, const double *in);
 int64_t or_history(const or_sim *s, double *out, int64_t cap);
 /* status of lattice node (x,y) at step k: 0 disc, 1 interpolation, 2 unused */
 int32_t or_lattice_status(const or_sim *s, int64_t k, int32_t x, int32_t y);
+
+/* ---- structured refinement levels ------------------------------------ */
+/* Level 0 is an nx0 x ny0 lattice with boundaries bc0 (walls may move with
+ * x-velocities u_bot, u_top under bc 0). Level l+1 covers the node box
+ * box[4l .. 4l+3] = (x0, y0, x1, y1) of level l (inclusive, at least two
+ * nodes inside level l's edges, at least four cells wide) with twice the
+ * resolution: 2 (x1 - x0) + 1 by 2 (y1 - y0) + 1 nodes. The finest level is
+ * the hybrid case `fine` (bc OR_BC_RING, nx and ny as implied by the last
+ * box, tau and the body in its own lattice units); tau of each coarser level
+ * follows from equal viscosity. One or_ml_step advances level 0 by one step
+ * and level l by 2^l steps. */
+#define OR_ML_MAX_LEVELS 8
+/* planted mistakes, for tests that show the pins detect them */
+#define OR_ML_FLAG_PLANT_NO_RESCALE 256 /* f^neq not rescaled between levels */
+#define OR_ML_FLAG_PLANT_SAME_TAU 512   /* every level relaxes with the finest tau */
+typedef struct or_ml or_ml;
+int or_ml_create(const or_config *fine, int32_t nlevels, int32_t nx0, int32_t ny0, int32_t bc0,
+                 double u_bot, double u_top, const int32_t *box, int32_t flags, or_ml **out);
+void or_ml_destroy(or_ml *s);
+int or_ml_step(or_ml *s, int64_t nsteps);
+int or_ml_level_shape(const or_ml *s, int32_t level, int32_t *nx, int32_t *ny, double *tau);
+/* level state [9][ny][nx], post-collision at the current time */
+int or_ml_get_level(const or_ml *s, int32_t level, double *out);
+int or_ml_set_level(or_ml *s, int32_t level, const double *in);
+/* the finest level's hybrid case (history, grid, info) */
+or_sim *or_ml_finest(or_ml *s);
+int64_t or_ml_steps(const or_ml *s);
 
 /* ---- hydrodynamic function fit (Sec. Hydrodynamic function extraction) -- */
 /* hist: (Fx,Fy) pairs, entry k at t=k+1. Window [t0, t1) in periods.

@@ -26,6 +26,9 @@ _LIB_CS = os.path.join(_HERE, "liboracle_cs.so")
 BC_PERIODIC_X_WALLS_Y = 0
 BC_PERIODIC = 1
 BC_PAPER = 2
+BC_RING = 3
+ML_PLANT_NO_RESCALE = 256
+ML_PLANT_SAME_TAU = 512
 FLAG_NO_BODY = 1
 NODE_INTERIOR, NODE_INTERFACE, NODE_WALL = 0, 1, 2
 
@@ -107,6 +110,18 @@ def lib():
         L.or_lattice_status.restype = C.c_int32
         L.or_fit_theta.argtypes = [_D, C.c_int64, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_double, _D]
+        L.or_ml_create.argtypes = [C.POINTER(Config), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                   C.c_double, C.c_double, _I, C.c_int32, C.POINTER(vp)]
+        L.or_ml_destroy.argtypes = [vp]
+        L.or_ml_step.argtypes = [vp, C.c_int64]
+        L.or_ml_level_shape.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_double)]
+        L.or_ml_get_level.argtypes = [vp, C.c_int32, _D]
+        L.or_ml_set_level.argtypes = [vp, C.c_int32, _D]
+        L.or_ml_finest.argtypes = [vp]
+        L.or_ml_finest.restype = vp
+        L.or_ml_steps.argtypes = [vp]
+        L.or_ml_steps.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -155,7 +170,7 @@ def lattice_step(A: np.ndarray, tau: float, bc: int = BC_PERIODIC, u_bot: float 
     """One Eq.(LBE) step on a [9][ny][nx] array; returns the new array."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     _, ny, nx = A.shape
-    B = np.empty_like(A)
+    B = A.copy()  # a ring-fed lattice (bc 3) leaves its ring as it was
     dptr = None
     if disc is not None:
         disc = np.ascontiguousarray(disc, dtype=np.uint8)
@@ -300,6 +315,92 @@ class Sim:
     def status(self, k):
         return np.array([[lib().or_lattice_status(self.ptr, k, x, y) for x in range(self.nx)]
                          for y in range(self.ny)], dtype=np.int32)
+
+
+class _FinestView(Sim):
+    """The finest level of a :class:`MultiLevel`, owned by it."""
+
+    def __init__(self, ptr, nx, ny, owner):
+        self.ptr = C.c_void_p(ptr)
+        self._owner = owner
+        self.nx, self.ny = nx, ny
+        self.nnode = self.info().nnode
+
+    def __del__(self):
+        pass  # freed with its owner
+
+    def step(self, n=1):
+        raise RuntimeError("the finest level advances with its MultiLevel")
+
+
+def level_shape(box):
+    """Node counts of the level covering node box (x0, y0, x1, y1)."""
+    x0, y0, x1, y1 = box
+    return 2 * (x1 - x0) + 1, 2 * (y1 - y0) + 1
+
+
+class MultiLevel:
+    """Nested structured refinement levels with a hybrid case on the finest.
+
+    ``boxes[l] = (x0, y0, x1, y1)``: node box of level l covered by level
+    l+1. ``fine`` holds the finest level's configuration (tau, body, grid)
+    in its own lattice units; its lattice size follows from the last box."""
+
+    def __init__(self, nx0, ny0, boxes, bc0=BC_PERIODIC_X_WALLS_Y, u_bot=0.0, u_top=0.0, flags=0,
+                 **fine):
+        nx, ny = level_shape(boxes[-1])
+        fine = dict(fine)
+        fine.setdefault("tau", 0.8)
+        self.cfg = Config(nx, ny, fine.get("nux", 0), fine.get("nuy", 0), fine.get("h_u", 1.0),
+                          fine.get("b", 0.0), fine.get("thickness", 1.0), fine["tau"],
+                          fine.get("kc", 0.0), fine.get("beta", 0.0), fine.get("n_sub", 0), BC_RING,
+                          fine.get("flags", 0), fine.get("max_steps", 0))
+        box = np.ascontiguousarray(np.array(boxes, dtype=np.int32).reshape(-1))
+        h = C.c_void_p()
+        rc = lib().or_ml_create(C.byref(self.cfg), len(boxes) + 1, nx0, ny0, bc0, u_bot, u_top, box,
+                                flags, C.byref(h))
+        if rc != 0:
+            raise ValueError(f"or_ml_create rejected the configuration (code {rc})")
+        self.ptr = h
+        self.nlevels = len(boxes) + 1
+        self.boxes = [tuple(b) for b in boxes]
+        self.shapes = []
+        self.taus = []
+        for l in range(self.nlevels):
+            a, b_, t = C.c_int32(), C.c_int32(), C.c_double()
+            lib().or_ml_level_shape(self.ptr, l, C.byref(a), C.byref(b_), C.byref(t))
+            self.shapes.append((a.value, b_.value))
+            self.taus.append(t.value)
+        self.finest = _FinestView(lib().or_ml_finest(self.ptr), nx, ny, self)
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.or_ml_destroy(self.ptr)
+            self.ptr = None
+
+    def step(self, n=1):
+        rc = lib().or_ml_step(self.ptr, n)
+        if rc != 0:
+            raise RuntimeError(f"or_ml_step failed (code {rc})")
+
+    def steps(self):
+        return lib().or_ml_steps(self.ptr)
+
+    def level(self, l):
+        nx, ny = self.shapes[l]
+        out = np.zeros((9, ny, nx))
+        lib().or_ml_get_level(self.ptr, l, out)
+        return out
+
+    def set_level(self, l, f):
+        nx, ny = self.shapes[l]
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        if f.shape != (9, ny, nx):
+            raise ValueError(f"level {l} holds (9, {ny}, {nx}) populations")
+        lib().or_ml_set_level(self.ptr, l, f)
+
+    def history(self):
+        return self.finest.history()
 
 
 class SimCS:
