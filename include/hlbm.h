@@ -53,6 +53,9 @@ extern "C" {
                                         x = -1/2, nx - 1/2 (halfway bounce-
                                         back) and zero-gradient outflow at the
                                         y ends                                */
+#define HLBM_BC_RING 3               /* finest level of a multi-level handle
+                                        only: the outermost ring of nodes is
+                                        written from the next coarser level   */
 
 /* ---- storage of the lattice populations ------------------------------- */
 #define HLBM_FP64 0     /* FP64 storage and arithmetic                          */
@@ -71,6 +74,10 @@ extern "C" {
                                     at t_0) from the last hlbm_adjoint       */
 #define HLBM_STATE_ADJ_GRID 3    /* get only, double [9][nux*nuy]: dJ/d(grid at
                                     t_0) from the last hlbm_adjoint          */
+#define HLBM_STATE_LEVEL 16      /* + l: double [9][ny_l][nx_l], post-collision f
+                                    of refinement level l of a multi-level
+                                    handle (l = nlevels-1 is the finest, also
+                                    HLBM_STATE_LATTICE)                       */
 
 /* Problem and discretisation (Sec. Problem statement, Sec. HLBM).
  * Grid node (i, j) sits at x = nx/2 + (i - nux/2) h_u (integer division) and
@@ -159,6 +166,54 @@ typedef struct hlbm hlbm_t;
  * |A omega| >= 1; in a batch, mixed storage or ckpt_every != 0),
  * HLBM_E_NOMEM, HLBM_E_HIP. On error *out is set to NULL. */
 int hlbm_create(const hlbm_config *cfg, int32_t ncases, hlbm_t **out);
+
+/* ---- structured refinement levels ------------------------------------ */
+/* The paper divides the structured domain into refinement levels (Sec.
+ * Problem statement: four levels, the relaxation time given on the finest)
+ * and prints no interface scheme; the one built here: level l+1 covers the
+ * node box box[l] = (x0, y0, x1, y1) of level l (inclusive) with twice the
+ * resolution, 2 (x1-x0) + 1 by 2 (y1-y0) + 1 nodes, coinciding with level l
+ * at every other node. Each level steps with Delta t = Delta x (acoustic
+ * scaling), two steps per step of the next coarser level, and relaxes with
+ * tau_l - 1/2 = (tau_fine - 1/2) / 2^(L-1-l) (equal viscosity). At the
+ * interfaces the pre-collision density, velocity and f^neq = f - f^eq are
+ * exchanged, f^neq scaled by the ratio of tau Delta x of the two levels
+ * (first-order Chapman-Enskog), and written as post-collision populations
+ * f^eq + (1 - 1/tau) f^neq: the ring of level l+1 before each of its steps,
+ * linear along the box perimeter between level-l nodes and linear in time
+ * between level l's states at t and t+1; level l's nodes one inside the box
+ * after every second step of level l+1. */
+#define HLBM_MAX_LEVELS 8
+typedef struct hlbm_levels {
+  int32_t nlevels;  /* 2 .. HLBM_MAX_LEVELS                                */
+  int32_t nx0, ny0; /* level-0 lattice nodes                               */
+  int32_t bc0;      /* boundaries of level 0: HLBM_BC_PERIODIC_X_WALLS_Y,
+                       HLBM_BC_PERIODIC or HLBM_BC_PAPER                   */
+  int32_t box[HLBM_MAX_LEVELS - 1][4]; /* box[l]: x0, y0, x1, y1 in level-l
+                       nodes; 2 <= x0, x0 + 4 <= x1 <= nx_l - 3, same in y */
+} hlbm_levels;
+
+/* Create a multi-level handle. `fine` configures the finest level in its own
+ * lattice units (tau, the lamina and its grid, storage, max_steps counted in
+ * finest steps): nx and ny must be the shape the last box implies, bc must
+ * be HLBM_BC_RING and ckpt_every 0; the grid and its motion must stay
+ * inside the finest level (the geometric checks of hlbm_create). Every
+ * level starts at rest. On the handle, hlbm_step(h, n) advances level 0 by
+ * n steps (level l by n 2^l); hlbm_force, hlbm_info_get and
+ * hlbm_get_stencil report the finest level's case; hlbm_get/set_state take
+ * HLBM_STATE_LEVEL + l (set: the level's state is taken as steady, both of
+ * its time levels get it), HLBM_STATE_LATTICE and HLBM_STATE_GRID for the
+ * finest level; hlbm_tune tunes the finest level's kernels and applies its
+ * stream-collide shape to every level. hlbm_adjoint and hlbm_timing return
+ * HLBM_E_UNSUPPORTED. Errors: HLBM_E_ARG (invalid levels or boxes, or a
+ * finest configuration hlbm_create would reject), HLBM_E_NOMEM, HLBM_E_HIP. */
+int hlbm_create_multilevel(const hlbm_config *fine, const hlbm_levels *levels,
+                           hlbm_t **out);
+
+/* Shape and relaxation time of level `level` of a multi-level handle.
+ * HLBM_E_STATE on another handle, HLBM_E_ARG for a level out of range. */
+int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny,
+                     double *tau);
 
 /* Advance nsteps structured steps t_k -> t_{k+1} (Sec. HLBM and Sec. Refill
  * procedure): lattice interpolation nodes from the grid (Eq.

@@ -845,6 +845,24 @@ class Case final : public CaseBase {
     }
     k_ += m;
   }
+  // ---- hooks for a multi-level handle that runs this case as its finest level
+  hipStream_t stream() const { return s_main_; }
+  void *lattice_buffer(int i) const { return lat_[i]; }  // 0: state at t_k, 1: at t_{k-1}
+  size_t plane() const { return plane_; }
+  bool has_grid() const { return has_grid_; }
+  hipError_t enqueue_one() { return enqueue_step(); }
+  struct Layout {
+    void *l0, *l1;
+    int gcur;
+    int64_t k;
+  };
+  Layout layout() const { return {lat_[0], lat_[1], gcur_, k_}; }
+  void set_layout(const Layout &l) {
+    lat_[0] = l.l0;
+    lat_[1] = l.l1;
+    gcur_ = l.gcur;
+    k_ = l.k;
+  }
   // every lattice and grid buffer, for snapshots
   void buffers(void **lat, void **grid, size_t *lat_bytes, size_t *grid_bytes) const {
     lat[0] = lat_[0];
@@ -1265,10 +1283,15 @@ class Case final : public CaseBase {
 
 // Configuration checks shared by all storage types (mirrors the geometric
 // requirements stated in hlbm.h).
-int validate(const hlbm_config &c, std::string *err) {
+int validate(const hlbm_config &c, std::string *err, bool ring_ok = false) {
   if (c.nx < 3 || c.ny < 3) { *err = "lattice needs nx, ny >= 3"; return HLBM_E_ARG; }
   if (!(c.tau > 0.5)) { *err = "tau must exceed 1/2"; return HLBM_E_ARG; }
-  if (c.bc != HLBM_BC_PERIODIC_X_WALLS_Y && c.bc != HLBM_BC_PERIODIC && c.bc != HLBM_BC_PAPER) {
+  if (c.bc == HLBM_BC_RING && !ring_ok) {
+    *err = "bc HLBM_BC_RING is for the finest level of a multi-level handle";
+    return HLBM_E_ARG;
+  }
+  if (c.bc != HLBM_BC_PERIODIC_X_WALLS_Y && c.bc != HLBM_BC_PERIODIC && c.bc != HLBM_BC_PAPER &&
+      c.bc != HLBM_BC_RING) {
     *err = "unknown bc";
     return HLBM_E_ARG;
   }
@@ -1661,6 +1684,360 @@ class Batch final : public CaseBase {
   int sv_ = 0;      // sub-step variant of the current work lists
 };
 
+// Nested structured refinement levels. Levels 0 .. L-2 are plain lattices
+// owned here; the finest is a Case (lattice with or without the body-fitted
+// grid) whose outermost ring of nodes is written from level L-2. One step
+// advances level 0 by one step and level l by 2^l steps, recursively: level
+// l streams and collides (skipping the nodes the finer level covers),
+// records the pre-collision moments on the perimeter of the finer level's
+// box, runs two steps of the finer level with its ring interpolated at
+// t and t + 1/2, and takes its nodes one inside the box from the finer
+// level at t + 1. Everything runs on the finest case's stream; one step of
+// level 0 is captured as one HIP graph per buffer arrangement of level 0
+// (every finer level takes an even number of steps, so its buffers are back
+// in place).
+template <class T, class R>
+class MultiLevel final : public CaseBase {
+ public:
+  ~MultiLevel() override { release(); }
+
+  int init(const hlbm_config &fine, const hlbm_levels &lv) {
+    L_ = lv.nlevels;
+    fine_cfg_ = fine;
+    fine_ = std::make_unique<Case<T, R>>();
+    int rc = fine_->init(fine);
+    if (rc != HLBM_OK) {
+      err = fine_->err;
+      return rc;
+    }
+    s_ = fine_->stream();
+    // equal viscosity: tau - 1/2 halves from each level to the next coarser
+    std::vector<double> taus(L_);
+    taus[L_ - 1] = fine.tau;
+    for (int l = L_ - 2; l >= 0; --l) taus[l] = 0.5 + 0.5 * (taus[l + 1] - 0.5);
+    int nx = lv.nx0, ny = lv.ny0;
+    for (int l = 0; l < L_ - 1; ++l) {
+      Level &c = lev_[l];
+      c.nx = nx;
+      c.ny = ny;
+      c.bc = l == 0 ? lv.bc0 : 3;
+      c.tau = taus[l];
+      c.box = {lv.box[l][0], lv.box[l][1], lv.box[l][2], lv.box[l][3]};
+      c.plane = lattice_plane(nx, ny);
+      for (int i = 0; i < 2; ++i) {
+        HIPCHK(alloc(&c.lat[i], 9 * c.plane * sizeof(T)));
+        HIPCHK(alloc(&c.m[i], 12 * (size_t)c.box.perimeter() * sizeof(R)));
+        Kernels<T, R>::fill_rest((T *)c.lat[i], c.plane, nullptr, 0, s_);
+      }
+      c.base = c.lat[0];
+      LevelKernels<T, R>::box_moments((const T *)c.lat[0], c.nx, c.ny, c.plane, c.bc, c.box, (R *)c.m[0], s_);
+      nx = 2 * c.box.W() + 1;
+      ny = 2 * c.box.H() + 1;
+    }
+    use_graphs_ = std::getenv("HLBM_NO_GRAPHS") == nullptr;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s_));
+    return HLBM_OK;
+  }
+
+  int step(int64_t nsteps) override {
+    if (nsteps < 0) return fail(HLBM_E_ARG, "nsteps < 0");
+    const int64_t per = (int64_t)1 << (L_ - 1);
+    if (fine_->has_grid() && fine_->steps_taken() + nsteps * per > fine_->max_steps())
+      return fail(HLBM_E_ARG, "force history of the finest level would exceed max_steps");
+    for (int64_t i = 0; i < nsteps; ++i) {
+      if (use_graphs_) {
+        hipGraphExec_t g = nullptr;
+        HIPCHK(graph(&g));
+        HIPCHK(hipGraphLaunch(g, s_));
+        // level 0 took one step, every finer level an even number
+        std::swap(lev_[0].lat[0], lev_[0].lat[1]);
+        std::swap(lev_[0].m[0], lev_[0].m[1]);
+        fine_->advance_host(per);
+      } else {
+        HIPCHK(advance(0));
+      }
+    }
+    HIPCHK(hipStreamSynchronize(s_));
+    if (fine_->has_grid()) {
+      int flag = 0;
+      HIPCHK(hipMemcpy(&flag, fine_->flag(), sizeof(int), hipMemcpyDeviceToHost));
+      if (flag) return fail(HLBM_E_UNSTABLE, "non-finite force on the lamina");
+    }
+    return HLBM_OK;
+  }
+
+  int get_state(int which, void *buf, size_t bytes) override {
+    const int l = which == HLBM_STATE_LATTICE ? L_ - 1 : which - HLBM_STATE_LEVEL;
+    if (which != HLBM_STATE_LATTICE && (l < 0 || l >= L_)) {
+      if (which == HLBM_STATE_GRID) return relay(fine_->get_state(which, buf, bytes));
+      return fail(HLBM_E_ARG, "unknown state selector");
+    }
+    if (l == L_ - 1) return relay(fine_->get_state(HLBM_STATE_LATTICE, buf, bytes));
+    const Level &c = lev_[l];
+    const size_t nodes = (size_t)c.nx * c.ny;
+    if (bytes != 9 * nodes * sizeof(double)) return fail(HLBM_E_ARG, "level state size mismatch");
+    HIPCHK(hipStreamSynchronize(s_));
+    double *tmp = nullptr;
+    HIPCHK(hipMalloc(&tmp, bytes));
+    Kernels<T, R>::lattice_to_f64((const T *)c.lat[0], tmp, c.plane, nodes, s_);
+    hipError_t e = hipMemcpyAsync(buf, tmp, bytes, hipMemcpyDeviceToHost, s_);
+    if (e == hipSuccess) e = hipStreamSynchronize(s_);
+    (void)hipFree(tmp);
+    HIPCHK(e);
+    return HLBM_OK;
+  }
+
+  // A level is set as a steady state: both of its buffers, and the moments
+  // on the perimeter of the finer level's box as those of the current time.
+  int set_state(int which, const void *buf, size_t bytes) override {
+    const int l = which == HLBM_STATE_LATTICE ? L_ - 1 : which - HLBM_STATE_LEVEL;
+    if (which != HLBM_STATE_LATTICE && (l < 0 || l >= L_)) {
+      if (which == HLBM_STATE_GRID) return relay(fine_->set_state(which, buf, bytes));
+      return fail(HLBM_E_ARG, "state cannot be set");
+    }
+    if (l == L_ - 1) {
+      const int rc = fine_->set_state(HLBM_STATE_LATTICE, buf, bytes);
+      if (rc != HLBM_OK) return relay(rc);
+      HIPCHK(hipMemcpy(fine_->lattice_buffer(1), fine_->lattice_buffer(0), 9 * fine_->plane() * sizeof(T),
+                       hipMemcpyDeviceToDevice));
+      return HLBM_OK;
+    }
+    Level &c = lev_[l];
+    const size_t nodes = (size_t)c.nx * c.ny;
+    if (bytes != 9 * nodes * sizeof(double)) return fail(HLBM_E_ARG, "level state size mismatch");
+    HIPCHK(hipStreamSynchronize(s_));
+    double *tmp = nullptr;
+    HIPCHK(hipMalloc(&tmp, bytes));
+    hipError_t e = hipMemcpyAsync(tmp, buf, bytes, hipMemcpyHostToDevice, s_);
+    if (e == hipSuccess) {
+      for (int i = 0; i < 2; ++i) Kernels<T, R>::lattice_from_f64(tmp, (T *)c.lat[i], c.plane, nodes, s_);
+      LevelKernels<T, R>::box_moments((const T *)c.lat[0], c.nx, c.ny, c.plane, c.bc, c.box, (R *)c.m[0], s_);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(s_);
+    }
+    (void)hipFree(tmp);
+    HIPCHK(e);
+    return HLBM_OK;
+  }
+
+  int force(double *hist, int64_t cap, int64_t *n_out, double t0, double t1, double th[2]) override {
+    return relay(fine_->force(hist, cap, n_out, t0, t1, th));
+  }
+  int info(hlbm_info *o) override { return relay(fine_->info(o)); }
+  int stencil(int kmax, int32_t *nbr, double *S, double *C) override {
+    return relay(fine_->stencil(kmax, nbr, S, C));
+  }
+  int timing(int) override { return fail(HLBM_E_UNSUPPORTED, "per-kernel timing of a multi-level handle"); }
+  int timing_get(int, double *, int64_t *) override {
+    return fail(HLBM_E_UNSUPPORTED, "per-kernel timing of a multi-level handle");
+  }
+  int adjoint(const double *, int64_t, double *) override {
+    return fail(HLBM_E_UNSUPPORTED, "adjoint of a multi-level handle");
+  }
+
+  // the finest case's autotuner; its stream-collide shape serves every level
+  int tune(int trial_steps, hlbm_tuning *t) override {
+    HIPCHK(hipStreamSynchronize(s_));
+    const int rc = fine_->tune(trial_steps, t);
+    if (rc != HLBM_OK) return relay(rc);
+    threads_ = t->lattice_threads;
+    rows_ = t->lattice_rows;
+    order_ = t->order;
+    drop_graphs();
+    return HLBM_OK;
+  }
+
+  int shape(int l, int *nx, int *ny, double *tau) const {
+    if (l < 0 || l >= L_) return HLBM_E_ARG;
+    if (l == L_ - 1) {
+      *nx = fine_cfg_.nx;
+      *ny = fine_cfg_.ny;
+      *tau = fine_cfg_.tau;
+    } else {
+      *nx = lev_[l].nx;
+      *ny = lev_[l].ny;
+      *tau = lev_[l].tau;
+    }
+    return HLBM_OK;
+  }
+
+ private:
+  struct Level {
+    int nx = 0, ny = 0, bc = 0;
+    double tau = 0.0;
+    size_t plane = 0;
+    LevelBox box{};
+    void *lat[2] = {nullptr, nullptr};  // post-collision state at t (0) and t - 1 (1)
+    void *m[2] = {nullptr, nullptr};    // perimeter moments at t (0) and t + 1 (1)
+    void *base = nullptr;
+  };
+
+  CaseView<T, R> level_view(int l) const {
+    const Level &c = lev_[l];
+    CaseView<T, R> v{};
+    v.A = (const T *)c.lat[0];
+    v.B = (T *)c.lat[1];
+    v.nx = c.nx;
+    v.ny = c.ny;
+    v.plane = c.plane;
+    v.bc = c.bc;
+    v.inv_tau = (R)(1.0 / c.tau);
+    v.sx0 = c.box.x0;
+    v.sx1 = c.box.x1;
+    v.sy0 = c.box.y0;
+    v.sy1 = c.box.y1;
+    return v;
+  }
+
+  void child(int l, void **cur, void **prev, int *nx, int *ny, size_t *plane, double *tau) const {
+    if (l == L_ - 1) {
+      *cur = fine_->lattice_buffer(0);
+      *prev = fine_->lattice_buffer(1);
+      *nx = fine_cfg_.nx;
+      *ny = fine_cfg_.ny;
+      *plane = fine_->plane();
+      *tau = fine_cfg_.tau;
+    } else {
+      const Level &c = lev_[l];
+      *cur = c.lat[0];
+      *prev = c.lat[1];
+      *nx = c.nx;
+      *ny = c.ny;
+      *plane = c.plane;
+      *tau = c.tau;
+    }
+  }
+
+  // enqueue one step of level l (and 2^(l'-l) of every finer level l')
+  hipError_t advance(int l) {
+    if (l == L_ - 1) return fine_->enqueue_one();
+    Level &c = lev_[l];
+    Kernels<T, R>::stream_collide(level_view(l), s_, nullptr, nullptr, threads_, rows_, order_);
+    std::swap(c.lat[0], c.lat[1]);
+    LevelKernels<T, R>::box_moments((const T *)c.lat[1], c.nx, c.ny, c.plane, c.bc, c.box, (R *)c.m[1], s_);
+    void *fc, *fp;
+    int nxf, nyf;
+    size_t planef;
+    double tauf;
+    child(l + 1, &fc, &fp, &nxf, &nyf, &planef, &tauf);
+    // f^neq scales with tau Delta x between the levels
+    const double kf = (1.0 - 1.0 / tauf) * (tauf / (2.0 * c.tau));
+    const double kc = (1.0 - 1.0 / c.tau) * (2.0 * c.tau / tauf);
+    for (int h = 0; h < 2; ++h) {
+      child(l + 1, &fc, &fp, &nxf, &nyf, &planef, &tauf);
+      LevelKernels<T, R>::prolong((const R *)c.m[0], (const R *)c.m[1], c.box, 0.5 * (double)h, kf, (T *)fc, nxf, nyf,
+                                  planef, s_);
+      const hipError_t e = advance(l + 1);
+      if (e != hipSuccess) return e;
+    }
+    child(l + 1, &fc, &fp, &nxf, &nyf, &planef, &tauf);
+    LevelKernels<T, R>::restrict_level((const T *)fp, nxf, nyf, planef, c.box, kc, (T *)c.lat[0], c.nx, c.plane,
+                                       s_);
+    std::swap(c.m[0], c.m[1]);
+    return hipGetLastError();
+  }
+
+  hipError_t graph(hipGraphExec_t *out) {
+    const int key = lev_[0].lat[0] == lev_[0].base ? 0 : 1;
+    if (gexec_[key]) {
+      *out = gexec_[key];
+      return hipSuccess;
+    }
+    Level saved[kMaxLevels];
+    for (int l = 0; l < L_ - 1; ++l) saved[l] = lev_[l];
+    const auto fl = fine_->layout();
+    hipError_t e = hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t e2 = advance(0);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s_, &g);
+    for (int l = 0; l < L_ - 1; ++l) lev_[l] = saved[l];
+    fine_->set_layout(fl);
+    if (e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return e2;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&gexec_[key], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    *out = gexec_[key];
+    return hipSuccess;
+  }
+
+  void drop_graphs() {
+    for (auto &g : gexec_) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  }
+
+  template <class P>
+  hipError_t alloc(P **p, size_t bytes) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 256));
+    if (e == hipSuccess) owned_.push_back(q);
+    *p = (P *)q;
+    return e;
+  }
+
+  void release() {
+    if (s_) (void)hipStreamSynchronize(s_);
+    drop_graphs();
+    for (void *p : owned_) (void)hipFree(p);
+    owned_.clear();
+  }
+
+  int fail(int code, const char *msg) {
+    err = msg;
+    return code;
+  }
+  int relay(int rc) {
+    if (rc != HLBM_OK) err = fine_->err;
+    return rc;
+  }
+
+  static constexpr int kMaxLevels = HLBM_MAX_LEVELS;
+  int L_ = 0;
+  hlbm_config fine_cfg_{};
+  std::unique_ptr<Case<T, R>> fine_;
+  Level lev_[kMaxLevels];
+  hipStream_t s_ = nullptr;
+  hipGraphExec_t gexec_[2] = {nullptr, nullptr};
+  bool use_graphs_ = true;
+  int threads_ = 0, rows_ = 0, order_ = 0;
+  std::vector<void *> owned_;
+};
+
+// Checks of a multi-level configuration (mirrors hlbm.h).
+int validate_levels(const hlbm_config &f, const hlbm_levels &lv, std::string *err) {
+  if (lv.nlevels < 2 || lv.nlevels > HLBM_MAX_LEVELS) { *err = "nlevels must be 2 .. HLBM_MAX_LEVELS"; return HLBM_E_ARG; }
+  if (lv.bc0 != HLBM_BC_PERIODIC_X_WALLS_Y && lv.bc0 != HLBM_BC_PERIODIC && lv.bc0 != HLBM_BC_PAPER) {
+    *err = "unknown bc0";
+    return HLBM_E_ARG;
+  }
+  int nx = lv.nx0, ny = lv.ny0;
+  for (int l = 0; l < lv.nlevels - 1; ++l) {
+    const int32_t *b = lv.box[l];
+    if (nx < 3 || ny < 3 || b[0] < 2 || b[1] < 2 || b[2] > nx - 3 || b[3] > ny - 3 || b[2] - b[0] < 4 ||
+        b[3] - b[1] < 4) {
+      *err = "box of level " + std::to_string(l + 1) +
+             " must lie two nodes inside level " + std::to_string(l) + " and span at least four cells";
+      return HLBM_E_ARG;
+    }
+    nx = 2 * (b[2] - b[0]) + 1;
+    ny = 2 * (b[3] - b[1]) + 1;
+  }
+  if (f.nx != nx || f.ny != ny) {
+    *err = "finest level must be " + std::to_string(nx) + " x " + std::to_string(ny) + " nodes";
+    return HLBM_E_ARG;
+  }
+  if (f.bc != HLBM_BC_RING) { *err = "the finest level takes bc HLBM_BC_RING"; return HLBM_E_ARG; }
+  if (f.ckpt_every != 0) { *err = "a multi-level handle takes no checkpoints"; return HLBM_E_ARG; }
+  return validate(f, err, true);
+}
+
 }  // namespace
 }  // namespace mghlbm
 
@@ -1726,6 +2103,60 @@ int hlbm_create(const hlbm_config *cfg, int32_t ncases, hlbm_t **out) {
   if (!h) { g_create_error = "host allocation failed"; return HLBM_E_NOMEM; }
   h->c = std::move(c);
   *out = h;
+  return HLBM_OK;
+}
+
+int hlbm_create_multilevel(const hlbm_config *fine, const hlbm_levels *lv, hlbm_t **out) {
+  using namespace mghlbm;
+  if (out) *out = nullptr;
+  if (!fine || !lv || !out) { g_create_error = "null argument"; return HLBM_E_ARG; }
+  std::string e;
+  int rc = validate_levels(*fine, *lv, &e);
+  if (rc != HLBM_OK) { g_create_error = e; return rc; }
+  std::unique_ptr<CaseBase> c;
+  try {
+    if (fine->storage == HLBM_FP64) {
+      auto p = std::make_unique<MultiLevel<double, double>>();
+      rc = p->init(*fine, *lv);
+      c = std::move(p);
+    } else if (fine->storage == HLBM_FP32) {
+      auto p = std::make_unique<MultiLevel<float, float>>();
+      rc = p->init(*fine, *lv);
+      c = std::move(p);
+    } else {
+      auto p = std::make_unique<MultiLevel<__half, float>>();
+      rc = p->init(*fine, *lv);
+      c = std::move(p);
+    }
+  } catch (const std::bad_alloc &) {
+    g_create_error = "host allocation failed";
+    return HLBM_E_NOMEM;
+  }
+  if (rc != HLBM_OK) {
+    g_create_error = c->err;
+    return rc == HLBM_E_HIP && g_create_error.find("out of memory") != std::string::npos ? HLBM_E_NOMEM : rc;
+  }
+  hlbm_t *h = new (std::nothrow) hlbm_t;
+  if (!h) { g_create_error = "host allocation failed"; return HLBM_E_NOMEM; }
+  h->c = std::move(c);
+  *out = h;
+  return HLBM_OK;
+}
+
+int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny, double *tau) {
+  if (!h || !nx || !ny || !tau) return HLBM_E_ARG;
+  int a = 0, b = 0;
+  double t = 0.0;
+  int rc = HLBM_E_STATE;
+  if (auto *m = dynamic_cast<mghlbm::MultiLevel<double, double> *>(h->c.get())) rc = m->shape(level, &a, &b, &t);
+  else if (auto *m = dynamic_cast<mghlbm::MultiLevel<float, float> *>(h->c.get())) rc = m->shape(level, &a, &b, &t);
+  else if (auto *m = dynamic_cast<mghlbm::MultiLevel<__half, float> *>(h->c.get())) rc = m->shape(level, &a, &b, &t);
+  if (rc == HLBM_E_STATE) h->c->err = "not a multi-level handle";
+  else if (rc != HLBM_OK) h->c->err = "level out of range";
+  if (rc != HLBM_OK) return rc;
+  *nx = a;
+  *ny = b;
+  *tau = t;
   return HLBM_OK;
 }
 

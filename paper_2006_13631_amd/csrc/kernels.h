@@ -14,7 +14,11 @@ struct CaseView {
   T *B;            // post-collision populations at t_{k+1}
   int nx, ny;
   size_t plane;    // elements from one population plane to the next (>= nx * ny)
-  int bc;          // HLBM_BC_*: 0 periodic x + y walls, 1 periodic, 2 x walls + y outflow
+  int bc;          // HLBM_BC_*: 0 periodic x + y walls, 1 periodic, 2 x walls + y outflow,
+                   // 3 outermost ring written from a coarser level (not updated here)
+  // nodes strictly inside (sx0, sx1) x (sy0, sy1) are neither read nor
+  // written by the stream-collide (a finer level covers them); empty: 0
+  int sx0, sx1, sy0, sy1;
   R inv_tau;       // 1 / tau_s
   R g_post;        // 2 (tau_s - 1) / (2 tau_s - 1), Eq.(postcollision2_s)
   R k_neq;         // 1 - 1/(2 tau_s), Eq.(continuity_stresses)
@@ -112,8 +116,38 @@ struct Kernels {
   static void lattice_from_f64(const double *src, T *dst, size_t plane, size_t nodes, hipStream_t s);
 };
 
+// Exchange between structured refinement levels. A box (x0, y0, x1, y1) of
+// a coarse level is covered by the next finer level; its perimeter nodes are
+// numbered p = 0 .. 2 (W + H) - 1 (W = x1 - x0, H = y1 - y0): bottom row
+// x0..x1, top row x0..x1, left column y0+1..y1-1, right column y0+1..y1-1.
+struct LevelBox {
+  int x0, y0, x1, y1;
+  int W() const { return x1 - x0; }
+  int H() const { return y1 - y0; }
+  int perimeter() const { return 2 * (W() + H()); }
+};
+
+template <class T, class R>
+struct LevelKernels {
+  // m [12][nper]: pre-collision (rho, u_x, u_y, f^neq) on the box perimeter,
+  // pulled from post-collision buffer P of the coarse level
+  static void box_moments(const T *P, int nx, int ny, size_t plane, int bc, LevelBox box, R *m, hipStream_t s);
+  // ring of the finer level (nxf x nyf, buffer F): moments m0 at t and m1 at
+  // t + 1 weighted (1 - tw1, tw1), f = f^eq + kf f^neq
+  static void prolong(const R *m0, const R *m1, LevelBox box, double tw1, double kf, T *F, int nxf, int nyf,
+                      size_t planef, hipStream_t s);
+  // coarse nodes one inside the box (buffer Cb) from the finer level's
+  // pre-collision state pulled from its post-collision buffer Fprev:
+  // f = f^eq + kc f^neq
+  static void restrict_level(const T *Fprev, int nxf, int nyf, size_t planef, LevelBox box, double kc, T *Cb,
+                             int nx, size_t plane, hipStream_t s);
+};
+
 extern template struct Kernels<double, double>;
 extern template struct Kernels<float, float>;
 extern template struct Kernels<__half, float>;
+extern template struct LevelKernels<double, double>;
+extern template struct LevelKernels<float, float>;
+extern template struct LevelKernels<__half, float>;
 
 }  // namespace mghlbm

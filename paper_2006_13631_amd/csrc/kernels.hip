@@ -36,7 +36,15 @@ __device__ __forceinline__ int grid_cur(const CaseView<T, R> &v, int64_t k) {
 // A lane updates RPT rows of one lattice column: the pulls of all its rows
 // are issued first, before the step's rectangle (a load that depends on the
 // device step counter) is known; nodes inside the rectangle (unused and
-// interpolation nodes) then carry their own values instead.
+// interpolation nodes) then carry their own values instead. Nodes a finer
+// level covers, and the ring of a level fed by a coarser one, are skipped
+// before any load.
+template <class T, class R>
+__device__ __forceinline__ bool static_skip(const CaseView<T, R> &v, int x, int y) {
+  return (x > v.sx0 && x < v.sx1 && y > v.sy0 && y < v.sy1) ||
+         (v.bc == 3 && (x == 0 || y == 0 || x == v.nx - 1 || y == v.ny - 1));
+}
+
 template <class T, class R, int RPT>
 __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, const T *__restrict__ A,
                                                      T *__restrict__ B, const int64_t *k_at, int bx, int by) {
@@ -46,7 +54,8 @@ __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, co
   R f[RPT][9];
 #pragma unroll
   for (int r = 0; r < RPT; ++r)
-    if (by * RPT + r < v.ny) pull<T, R>(A, v.nx, v.ny, plane, v.bc, x, by * RPT + r, f[r]);
+    if (by * RPT + r < v.ny && !static_skip(v, x, by * RPT + r))
+      pull<T, R>(A, v.nx, v.ny, plane, v.bc, x, by * RPT + r, f[r]);
   int ix0 = 1, ix1 = 0, iy0 = 1, iy1 = 0;  // empty rectangle without a grid
   if (v.has_grid) {
     const StepParams &P = v.params[*k_at];
@@ -55,7 +64,7 @@ __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, co
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int y = by * RPT + r;
-    if (y >= v.ny) continue;
+    if (y >= v.ny || static_skip(v, x, y)) continue;
     const size_t c = (size_t)y * v.nx + x;
     if (x >= ix0 && x <= ix1 && y >= iy0 && y <= iy1) {
 #pragma unroll
@@ -646,9 +655,125 @@ __global__ void k_from_f64(const double *src, T *dst, size_t plane, size_t nodes
   }
 }
 
+// ---- structured refinement levels ---------------------------------------------
+// Interface exchange between a level and the next finer one (refinement ratio
+// 2, acoustic scaling, equal viscosity): pre-collision density, velocity and
+// f^neq, the latter rescaled by the ratio of tau Delta x of the two levels
+// (first-order Chapman-Enskog), written back as post-collision populations.
+
+// coarse node of perimeter index p
+__device__ __forceinline__ void perimeter_node(const LevelBox &b, int p, int &x, int &y) {
+  const int W = b.x1 - b.x0, H = b.y1 - b.y0;
+  if (p <= W) {
+    x = b.x0 + p;
+    y = b.y0;
+  } else if (p <= 2 * W + 1) {
+    x = b.x0 + p - (W + 1);
+    y = b.y1;
+  } else if (p <= 2 * W + H) {
+    x = b.x0;
+    y = b.y0 + 1 + p - (2 * W + 2);
+  } else {
+    x = b.x1;
+    y = b.y0 + 1 + p - (2 * W + H + 1);
+  }
+}
+
+// perimeter index of perimeter node (x, y)
+__device__ __forceinline__ int perimeter_index(const LevelBox &b, int x, int y) {
+  const int W = b.x1 - b.x0, H = b.y1 - b.y0;
+  if (y == b.y0) return x - b.x0;
+  if (y == b.y1) return W + 1 + x - b.x0;
+  if (x == b.x0) return 2 * W + 2 + y - b.y0 - 1;
+  return 2 * W + H + 1 + y - b.y0 - 1;
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_box_moments(const T *__restrict__ P, int nx, int ny, size_t plane, int bc,
+                                                     LevelBox box, R *__restrict__ m) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x, n = 2 * (box.x1 - box.x0 + box.y1 - box.y0);
+  if (p >= n) return;
+  int x, y;
+  perimeter_node(box, p, x, y);
+  R f[9], e[9], rho, ux, uy;
+  pull<T, R>(P, nx, ny, plane, bc, x, y, f);
+  moments<R>(f, rho, ux, uy);
+  equilibrium<R>(rho, ux, uy, e);
+  m[p] = rho;
+  m[n + p] = ux;
+  m[2 * n + p] = uy;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) m[(3 + q) * n + p] = f[q] - e[q];
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_prolong(const R *__restrict__ m0, const R *__restrict__ m1, LevelBox box,
+                                                 R tw1, R kf, T *__restrict__ F, int nxf, int nyf, size_t planef) {
+  const LevelBox fb{0, 0, nxf - 1, nyf - 1};
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 2 * (nxf - 1 + nyf - 1)) return;
+  int i, j;
+  perimeter_node(fb, q, i, j);
+  // coarse position (x0 + i/2, y0 + j/2): a perimeter node, or the midpoint
+  // of two along the perimeter
+  const int X2 = 2 * box.x0 + i, Y2 = 2 * box.y0 + j;
+  const int xa = X2 >> 1, ya = Y2 >> 1;
+  const int pa = perimeter_index(box, xa, ya), pb = perimeter_index(box, xa + (X2 & 1), ya + (Y2 & 1));
+  const int n = 2 * (box.x1 - box.x0 + box.y1 - box.y0);
+  const R tw0 = R(1) - tw1, half = R(0.5);
+  R g[12];
+#pragma unroll
+  for (int r = 0; r < 12; ++r)
+    g[r] = tw0 * (half * (m0[r * n + pa] + m0[r * n + pb])) + tw1 * (half * (m1[r * n + pa] + m1[r * n + pb]));
+  R e[9];
+  equilibrium<R>(g[0], g[1], g[2], e);
+  const size_t c = (size_t)j * nxf + i;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Stor<T>::st(F, k * planef + c, k, e[k] + kf * g[3 + k]);
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ Fprev, int nxf, int nyf, size_t planef,
+                                                  LevelBox box, R kc, T *__restrict__ Cb, int nx, size_t plane) {
+  const LevelBox ib{box.x0 + 1, box.y0 + 1, box.x1 - 1, box.y1 - 1};
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= 2 * (ib.x1 - ib.x0 + ib.y1 - ib.y0)) return;
+  int x, y;
+  perimeter_node(ib, p, x, y);
+  R g[9], e[9], rho, ux, uy;
+  pull<T, R>(Fprev, nxf, nyf, planef, 3, 2 * (x - box.x0), 2 * (y - box.y0), g);
+  moments<R>(g, rho, ux, uy);
+  equilibrium<R>(rho, ux, uy, e);
+  const size_t c = (size_t)y * nx + x;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Stor<T>::st(Cb, q * plane + c, q, e[q] + kc * (g[q] - e[q]));
+}
+
 inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
+
+template <class T, class R>
+void LevelKernels<T, R>::box_moments(const T *P, int nx, int ny, size_t plane, int bc, LevelBox box, R *m,
+                                     hipStream_t s) {
+  hipLaunchKernelGGL((k_box_moments<T, R>), dim3(blocks(box.perimeter(), 256)), dim3(256), 0, s, P, nx, ny, plane,
+                     bc, box, m);
+}
+
+template <class T, class R>
+void LevelKernels<T, R>::prolong(const R *m0, const R *m1, LevelBox box, double tw1, double kf, T *F, int nxf,
+                                 int nyf, size_t planef, hipStream_t s) {
+  hipLaunchKernelGGL((k_prolong<T, R>), dim3(blocks(2 * (nxf - 1 + nyf - 1), 256)), dim3(256), 0, s, m0, m1, box,
+                     (R)tw1, (R)kf, F, nxf, nyf, planef);
+}
+
+template <class T, class R>
+void LevelKernels<T, R>::restrict_level(const T *Fprev, int nxf, int nyf, size_t planef, LevelBox box, double kc,
+                                        T *Cb, int nx, size_t plane, hipStream_t s) {
+  const int n = 2 * (box.W() - 2 + box.H() - 2);
+  hipLaunchKernelGGL((k_restrict<T, R>), dim3(blocks(n, 256)), dim3(256), 0, s, Fprev, nxf, nyf, planef, box,
+                     (R)kc, Cb, nx, plane);
+}
 
 void substep_tile(int variant, int *tx, int *ty) {
   switch (variant) {
@@ -814,5 +939,8 @@ void Kernels<T, R>::batched(BatchKernel which, const CaseView<T, R> *views, cons
 template struct Kernels<double, double>;
 template struct Kernels<float, float>;
 template struct Kernels<__half, float>;
+template struct LevelKernels<double, double>;
+template struct LevelKernels<float, float>;
+template struct LevelKernels<__half, float>;
 
 }  // namespace mghlbm

@@ -14,17 +14,20 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhlbm.so")
 
 OK, E_ARG, E_NOMEM, E_HIP, E_UNSTABLE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-BC_PERIODIC_X_WALLS_Y, BC_PERIODIC, BC_PAPER = 0, 1, 2
+BC_PERIODIC_X_WALLS_Y, BC_PERIODIC, BC_PAPER, BC_RING = 0, 1, 2, 3
 FP64, FP32, FP16_DEV = 0, 1, 2
 FLAG_NO_BODY = 1
 STATE_LATTICE, STATE_GRID, STATE_ADJ_LATTICE, STATE_ADJ_GRID = 0, 1, 2, 3
+STATE_LEVEL = 16
+MAX_LEVELS = 8
 (K_STREAM_COLLIDE, K_LATTICE_FROM_GRID, K_GRID_SUBSTEPS, K_REFILL, K_FORCE, K_STEP,
  K_ADJ_STREAM_COLLIDE, K_ADJOINT) = range(8)
 STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV}
 
 EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_state",
            "hlbm_set_state", "hlbm_info_get", "hlbm_get_stencil", "hlbm_timing",
-           "hlbm_timing_get", "hlbm_tune", "hlbm_destroy", "hlbm_last_error")
+           "hlbm_timing_get", "hlbm_tune", "hlbm_destroy", "hlbm_last_error",
+           "hlbm_create_multilevel", "hlbm_level_shape")
 STATUS_RUNNING, STATUS_DONE, STATUS_UNSTABLE = 0, 1, 2
 
 
@@ -63,6 +66,11 @@ class Tuning(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Levels(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("nx0", C.c_int32), ("ny0", C.c_int32), ("bc0", C.c_int32),
+                ("box", (C.c_int32 * 4) * (MAX_LEVELS - 1))]
+
+
 _lib = None
 
 
@@ -87,6 +95,8 @@ def load(path: str = LIB_PATH):
     L.hlbm_timing.argtypes = [vp, i32]
     L.hlbm_timing_get.argtypes = [vp, i32, dp, C.POINTER(i64)]
     L.hlbm_tune.argtypes = [vp, i32, C.POINTER(Tuning)]
+    L.hlbm_create_multilevel.argtypes = [C.POINTER(Config), C.POINTER(Levels), C.POINTER(vp)]
+    L.hlbm_level_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), dp]
     L.hlbm_destroy.argtypes = [vp]
     L.hlbm_destroy.restype = None
     L.hlbm_last_error.argtypes = [vp]
@@ -222,6 +232,63 @@ class Case:
         out = np.zeros((9, self.nnode))
         self._check(load().hlbm_get_state(self.h, 0, STATE_ADJ_GRID, out.ctypes.data, out.nbytes))
         return out
+
+
+def level_shape(box):
+    """Node counts of the level covering node box (x0, y0, x1, y1)."""
+    x0, y0, x1, y1 = box
+    return 2 * (x1 - x0) + 1, 2 * (y1 - y0) + 1
+
+
+class MultiLevel(Case):
+    """Nested structured refinement levels on the GPU, the finest carrying
+    the lamina case. ``boxes[l] = (x0, y0, x1, y1)``: node box of level l
+    covered by level l+1. Keyword arguments configure the finest level in
+    its own lattice units (as for :class:`Case`, without nx, ny, bc). The
+    history, theta, info and grid are the finest level's; ``step(n)``
+    advances level 0 by n steps."""
+
+    def __init__(self, nx0, ny0, boxes, bc0=BC_PERIODIC_X_WALLS_Y, storage=FP64, **fine):
+        L = load()
+        if isinstance(storage, str):
+            storage = STORAGE[storage]
+        if not 1 <= len(boxes) <= MAX_LEVELS - 1:
+            raise HlbmError(E_ARG, f"2 .. {MAX_LEVELS} levels")
+        nx, ny = level_shape(boxes[-1])
+        self.cfg = Config(nx, ny, fine.get("nux", 0), fine.get("nuy", 0), fine.get("h_u", 1.0),
+                          fine.get("b", 0.0), fine.get("thickness", 1.0), fine.get("tau", 0.8),
+                          fine.get("kc", 0.0), fine.get("beta", 0.0), fine.get("n_sub", 0), BC_RING,
+                          storage, fine.get("flags", 0), 0, 0, fine.get("max_steps", 0))
+        lv = Levels()
+        lv.nlevels, lv.nx0, lv.ny0, lv.bc0 = len(boxes) + 1, nx0, ny0, bc0
+        for l, b in enumerate(boxes):
+            for i in range(4):
+                lv.box[l][i] = int(b[i])
+        h = C.c_void_p()
+        rc = L.hlbm_create_multilevel(C.byref(self.cfg), C.byref(lv), C.byref(h))
+        if rc != 0:
+            raise HlbmError(rc, L.hlbm_last_error(None).decode())
+        self.h = h
+        self.nx, self.ny = nx, ny
+        self.nlevels = len(boxes) + 1
+        self.boxes = [tuple(b) for b in boxes]
+        self.shapes, self.taus = [], []
+        for l in range(self.nlevels):
+            a, b_, t = C.c_int32(), C.c_int32(), C.c_double()
+            self._check(L.hlbm_level_shape(self.h, l, C.byref(a), C.byref(b_), C.byref(t)))
+            self.shapes.append((a.value, b_.value))
+            self.taus.append(t.value)
+        self.nnode = self.info().nnode
+
+    def level(self, l):
+        nx, ny = self.shapes[l]
+        out = np.zeros((9, ny, nx))
+        self._check(load().hlbm_get_state(self.h, 0, STATE_LEVEL + l, out.ctypes.data, out.nbytes))
+        return out
+
+    def set_level(self, l, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self._check(load().hlbm_set_state(self.h, 0, STATE_LEVEL + l, f.ctypes.data, f.nbytes))
 
 
 class _Member:

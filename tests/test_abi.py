@@ -87,3 +87,51 @@ def test_invalid_batch_rejected_on_host(second):
     assert rc == hlbm.E_ARG and not h.value
     assert b"case 1" in hlbm.load().hlbm_last_error(None) or second.get("storage") is not None \
         or second.get("ckpt_every") or second.get("nux") == 0
+
+
+def test_levels_struct_layout(tmp_path):
+    src = tmp_path / "levels.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hlbm.h"\n'
+                   'int main(void){printf("%zu %zu %d\\n", sizeof(hlbm_levels), offsetof(hlbm_levels, box),'
+                   ' HLBM_STATE_LEVEL); return 0;}\n')
+    exe = tmp_path / "levels"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    a, b, c = map(int, subprocess.check_output([str(exe)]).split())
+    assert a == C.sizeof(hlbm.Levels) and b == hlbm.Levels.box.offset and c == hlbm.STATE_LEVEL
+
+
+def test_ring_boundaries_only_in_a_multilevel_handle():
+    with pytest.raises(hlbm.HlbmError) as ei:
+        hlbm.Case(nx=33, ny=33, tau=0.8, bc=hlbm.BC_RING)
+    assert ei.value.code == hlbm.E_ARG
+
+
+@pytest.mark.parametrize("boxes,extra", [
+    ([(1, 4, 12, 12)], {}),               # box too close to level 0's edge
+    ([(4, 4, 7, 12)], {}),                # box fewer than four cells wide
+    ([(4, 4, 14, 12)], {}),               # box beyond nx - 3
+    ([(4, 4, 12, 12)] * 8, {}),           # nine levels
+    ([(4, 4, 12, 12)], {"tau": 0.5}),     # invalid finest configuration
+])
+def test_invalid_levels_rejected_on_host(boxes, extra):
+    with pytest.raises(hlbm.HlbmError) as ei:
+        hlbm.MultiLevel(16, 16, boxes, **dict(dict(tau=0.8), **extra))
+    assert ei.value.code == hlbm.E_ARG
+
+
+def test_multilevel_finest_shape_and_bc_checked_on_host():
+    L = hlbm.load()
+    lv = hlbm.Levels()
+    lv.nlevels, lv.nx0, lv.ny0, lv.bc0 = 2, 16, 16, 0
+    for i, v in enumerate((4, 4, 12, 12)):
+        lv.box[0][i] = v
+    h = C.c_void_p()
+    for kw in (dict(nx=16, ny=17, bc=hlbm.BC_RING), dict(nx=17, ny=17, bc=0),
+               dict(nx=17, ny=17, bc=hlbm.BC_RING, ckpt_every=4)):
+        cfg = _cfg_struct(nux=0, nuy=0, b=0.0, **kw)
+        assert L.hlbm_create_multilevel(C.byref(cfg), C.byref(lv), C.byref(h)) == hlbm.E_ARG
+        assert not h.value
+    cfg = _cfg_struct(nx=17, ny=17, nux=0, nuy=0, b=0.0, bc=hlbm.BC_RING)
+    for n in (1, 9):
+        lv.nlevels = n
+        assert L.hlbm_create_multilevel(C.byref(cfg), C.byref(lv), C.byref(h)) == hlbm.E_ARG
