@@ -353,6 +353,57 @@ def study_leg(b=64, storage="f64", tune_steps=8, chunk=2000):
             "median_abs_dev_im": statistics.median(devs_im) if devs_im else None, "per_case": rows}
 
 
+def levels_leg(b=800, nlevels=4, storage="f64", steps=40, warmup=4, uniform=True):
+    """The paper's structured refinement: 4 levels over a 5L x 5L domain, the
+    lamina (L = 800 at the finest resolution, the paper's value) on the
+    finest. Times level-0 steps (2^(levels-1) finest steps each) replayed as
+    HIP graphs, and the same lamina, grid and finest resolution on one
+    uniform lattice over the whole domain, per finest step."""
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.workloads import paper_levels
+    d = paper_levels(b=b, nlevels=nlevels)
+    per = 2 ** (nlevels - 1)
+    fine = dict(d["fine"])
+    m = H.MultiLevel(d["nx0"], d["ny0"], d["boxes"], bc0=d["bc0"], storage=H.STORAGE[storage],
+                     max_steps=(steps + warmup) * per, **fine)
+    sched = m.tune(trial_steps=4)
+    inf = m.info()
+    print(f"# levels {m.shapes} taus {m.taus} n_sub {inf.n_sub} schedule {sched}", file=sys.stderr, flush=True)
+    m.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nodes = [nx * ny * 2 ** l for l, (nx, ny) in enumerate(m.shapes)]
+    grid_sub = inf.nnode * inf.n_sub * per
+    out = {"workload": f"paper_levels_{b}", "storage": storage, "levels": [
+        {"nx": nx, "ny": ny, "tau": round(t, 6), "steps_per_level0_step": 2 ** l, "box": list(bx) if l < len(d["boxes"]) else None}
+        for l, ((nx, ny), t, bx) in enumerate(zip(m.shapes, m.taus, d["boxes"] + [None]))],
+        "grid": [fine["nux"], fine["nuy"]], "n_sub": inf.n_sub, "level0_steps": steps,
+        "ms_per_level0_step": round(dt / steps * 1e3, 4), "ms_per_finest_step": round(dt / steps / per * 1e3, 4),
+        "mlups_levels": round(sum(nodes) * steps / dt / 1e6, 1),
+        "mlups_total": round((sum(nodes) + grid_sub) * steps / dt / 1e6, 1),
+        "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}}
+    m.close()
+    if uniform:
+        n = 5 * b + 1
+        c = H.Case(nx=n, ny=n, bc=H.BC_PAPER, storage=H.STORAGE[storage], max_steps=(steps + warmup) * per, **fine)
+        c.tune(trial_steps=4)
+        c.step(warmup * per)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(steps * per)
+        torch.cuda.synchronize()
+        du = time.perf_counter() - t0
+        c.close()
+        out["uniform"] = {"nx": n, "ny": n, "ms_per_step": round(du / (steps * per) * 1e3, 4),
+                          "mlups": round(n * n * steps * per / du / 1e6, 1)}
+        out["speedup_vs_uniform"] = round(du / dt, 3)
+    return out
+
+
 def storage_leg(workload, storage, steps, warmup, timing_steps):
     """The same workload at another storage precision: lattice MLUPS over
     graph-replayed steps, the stream-collide's mean duration (its own events)
@@ -417,6 +468,12 @@ def main():
                     help="run only the paper's (epsilon, beta) study as one batch and print its line")
     ap.add_argument("--study-b", type=int, default=64)
     ap.add_argument("--study-storage", default="f64", choices=list(BYTES))
+    ap.add_argument("--levels", action="store_true",
+                    help="run only the paper's 4-level refinement (L = 800 on the finest level) against a "
+                         "uniform finest lattice and print its line")
+    ap.add_argument("--levels-storage", default="f64", choices=list(BYTES))
+    ap.add_argument("--levels-steps", type=int, default=40)
+    ap.add_argument("--levels-no-uniform", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
@@ -429,6 +486,11 @@ def main():
     if args.sweep:
         torch.cuda.set_device(0)
         print(json.dumps(sweep_leg(periods=args.sweep_periods, loop=not args.sweep_no_loop)), flush=True)
+        return
+    if args.levels:
+        torch.cuda.set_device(0)
+        print(json.dumps(levels_leg(storage=args.levels_storage, steps=args.levels_steps,
+                                    uniform=not args.levels_no_uniform)), flush=True)
         return
     if args.study:
         torch.cuda.set_device(0)

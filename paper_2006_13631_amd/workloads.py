@@ -130,6 +130,37 @@ def paper_study_cases(b: int = 64, waves: float = 4.0, periods: float = 4.0, tau
     return out
 
 
+def paper_levels(b: int = 800, nlevels: int = 4, eps: float = 0.1, beta: float = 50.0, tau: float = 0.8,
+                 margin: int = 16, pad: int = 8) -> dict:
+    """The paper's structured refinement (Sec. Problem statement): a 5L x 5L
+    domain, ``nlevels`` levels with the lamina (width L = b at the finest
+    resolution, relaxation time tau there) on the finest. Level 0 spans the
+    domain with spacing 2^(nlevels-1); each box is centred in its level,
+    ``margin`` nodes clear of the finer level on every side; the finest
+    level holds the 4b x b body-fitted grid, its motion amplitude A and
+    ``pad`` nodes on each side. Returns nx0, ny0, bc0 (2: the paper's outer
+    boundaries), boxes and the finest level's configuration."""
+    kc = 2.0 * math.pi * eps
+    A = kc * b / (2.0 * math.pi)
+    W = -(-(4 * b + 2 * pad) // 2)
+    H = int(math.ceil((b + 2.0 * A + 2 * pad) / 2.0))
+    sizes = [(W, H)]  # box widths in cells, finest box first
+    for _ in range(nlevels - 2):
+        W, H = -(-(W + 2 * margin) // 2), -(-(H + 2 * margin) // 2)
+        sizes.append((W, H))
+    sizes.reverse()
+    n0 = (5 * b) // 2 ** (nlevels - 1) + 1
+    boxes, nx, ny = [], n0, n0
+    for W, H in sizes:
+        if W + 2 * margin + 1 > nx or H + 2 * margin + 1 > ny:
+            raise ValueError("the levels do not fit the 5L x 5L domain")
+        x0, y0 = (nx - 1 - W) // 2, (ny - 1 - H) // 2
+        boxes.append((x0, y0, x0 + W, y0 + H))
+        nx, ny = 2 * W + 1, 2 * H + 1
+    fine = dict(nux=4 * b, nuy=b, h_u=1.0, b=float(b), thickness=1.0, tau=tau, kc=kc, beta=beta)
+    return dict(nx0=n0, ny0=n0, bc0=2, boxes=boxes, fine=fine, finest=(nx, ny))
+
+
 def random_populations(shape, seed: int, base: np.ndarray, spread: float = 0.02) -> np.ndarray:
     """base * (1 + u), u uniform in [-spread, spread]; base broadcasts over the
     trailing axes of ``shape`` (first axis = population index)."""
