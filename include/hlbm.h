@@ -138,7 +138,11 @@ typedef struct hlbm_tuning {
                               3); 0: 16x16, 576; 1: 32x8, 640; 2: 64x4,
                               896; 3: 16x8, 384; 4: 8x8, 64; 5: 16x8,
                               128; 6: 16x16, 256; 7: 8x4, 64 (4-7: several
-                              nodes per lane, more workgroups per CU)      */
+                              nodes per lane, more workgroups per CU),
+                              each up to 4 sub-steps per launch; single
+                              case only: 8: 32x8, 256 and 9: 16x16, 256,
+                              one sub-step per launch; 10: 32x8, 384, two
+                              (large grids)                                */
   int32_t order;           /* batch work lists: 0 case by case, 1 dealt to
                               the 8 XCDs in contiguous chunks; single
                               case: 1 gives each XCD a contiguous band of

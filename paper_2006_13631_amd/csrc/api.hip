@@ -233,8 +233,9 @@ class Case final : public CaseBase {
       if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][3], s_grid_));
       Kernels<T, R>::interface_donors(v, s_grid_);
       int cur = gcur_;
-      for (int m = 0; m < d_.n; m += kSubstepBlock) {
-        const int cnt = std::min(kSubstepBlock, d_.n - m);
+      const int blk = substep_block(substep_variant_);
+      for (int m = 0; m < d_.n; m += blk) {
+        const int cnt = std::min(blk, d_.n - m);
         Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_, nullptr, nullptr,
                                      nullptr, 0, substep_variant_);
         cur = 1 - cur;
@@ -542,7 +543,7 @@ class Case final : public CaseBase {
     if (trial_steps == 0) {
       const bool keep_shape = t->lattice_threads == 0 && t->lattice_rows == 0;
       if ((!keep_shape && !valid_lattice_shape(*t)) || t->substep_variant < -1 ||
-          t->substep_variant >= kSubstepVariants || t->order < 0 || t->order > 1)
+          t->substep_variant >= kSubstepVariantsSingle || t->order < 0 || t->order > 1)
         return fail(HLBM_E_ARG, "invalid schedule");
       if (!keep_shape) {
         lattice_threads_ = t->lattice_threads;
@@ -593,11 +594,12 @@ class Case final : public CaseBase {
     if (has_grid_) {
       best_ms = 3e38f;
       int best = default_substep_variant<R>();
-      for (int sv = 0; sv < kSubstepVariants; ++sv) {
+      for (int sv = 0; sv < kSubstepVariantsSingle; ++sv) {
+        const int blk = substep_block(sv);
         const float ms = timed(s_grid_, [&] {
-          for (int m = 0; m < d_.n; m += kSubstepBlock)
+          for (int m = 0; m < d_.n; m += blk)
             Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[gcur_], (R *)gbuf_[1 - gcur_], m,
-                                         std::min(kSubstepBlock, d_.n - m), s_grid_, nullptr, nullptr, nullptr, 0, sv);
+                                         std::min(blk, d_.n - m), s_grid_, nullptr, nullptr, nullptr, 0, sv);
         });
         if (e == hipSuccess && ms < best_ms) {
           best_ms = ms;
@@ -838,7 +840,8 @@ class Case final : public CaseBase {
   int *flag() const { return flag_; }
   // host bookkeeping after m steps done on the device by batched kernels
   void advance_host(int64_t m) {
-    const int launches = (d_.n + kSubstepBlock - 1) / kSubstepBlock;
+    const int blk = substep_block(substep_variant_);
+    const int launches = (d_.n + blk - 1) / blk;
     if (m & 1) {
       std::swap(lat_[0], lat_[1]);
       if ((launches + 1) & 1) gcur_ = 1 - gcur_;
@@ -1142,8 +1145,10 @@ class Case final : public CaseBase {
       Kernels<T, R>::interface_donors(v, st);
       for (int m = 0; m < d_.n; m += kSubstepBlock) {
         const int cnt = std::min(kSubstepBlock, d_.n - m);
+        // the tape is written in blocks of kSubstepBlock sub-steps
+        const int sv = substep_block(substep_variant_) == kSubstepBlock ? substep_variant_ : -1;
         Kernels<T, R>::grid_substeps(v, tape_grid(t, j, m), tape_grid(t, j, m + cnt), m, cnt, st, tape_grid(t, j, 0),
-                                     tape_wall(t, j), widx_, std::max(n_wall_, 1), substep_variant_);
+                                     tape_wall(t, j), widx_, std::max(n_wall_, 1), sv);
       }
       Kernels<T, R>::refill(v, tape_grid(t, j, d_.n), tape_grid(t, j + 1, 0), st);
     }

@@ -71,8 +71,17 @@ constexpr int kLatticeThreads = 128, kLatticeRows = 2;
 //   2: 64 x 4, 896 threads    3: 16 x 8, 384 threads
 //   4: 8 x 8, 64 threads      5: 16 x 8, 128 threads
 //   6: 16 x 16, 256 threads   7: 8 x 4, 64 threads
-// (4-7: several nodes per lane, more workgroups per CU)
-constexpr int kSubstepVariants = 8;
+// (4-7: several nodes per lane, more workgroups per CU), all advancing up to
+// kSubstepBlock sub-steps per launch; single cases also take
+//   8: 32 x 8, 256 threads, one sub-step per launch
+//   9: 16 x 16, 256 threads, one sub-step per launch
+//  10: 32 x 8, 384 threads, two sub-steps per launch
+// (large grids, where the halo updates of deeper blocking cost more than
+// the loads they save)
+constexpr int kSubstepVariants = 8;         // case-batched kernels
+constexpr int kSubstepVariantsSingle = 11;  // single-case kernels
+// sub-steps a launch of `variant` advances at most (callers step by it)
+int substep_block(int variant);
 template <class R>
 constexpr int default_substep_variant() {
   return sizeof(R) == 8 ? 1 : 3;  // fastest at the 512 x 128 grid (hlbm_tune measures)

@@ -439,10 +439,11 @@ __device__ __forceinline__ void grid_substeps_block(
 // Variants of the sub-step kernel: tile shape and workgroup size (one lane
 // per region node while staging). Variant 3's LDS fits two workgroups on a
 // CU in FP64 and more in FP32 (many small grids).
-template <int TXv, int TYv, int NTv>
+template <int TXv, int TYv, int NTv, int Hv = kSubstepBlock>
 struct SubstepShape {
-  using G = Region<TXv, TYv, kSubstepBlock>;
+  using G = Region<TXv, TYv, Hv>;
   static constexpr int NT = NTv;
+  static constexpr int H = Hv;  // sub-steps per launch, and the halo width
 };
 template <int V>
 struct SubstepVariant;
@@ -454,6 +455,9 @@ template <> struct SubstepVariant<4> : SubstepShape<8, 8, 64> {};
 template <> struct SubstepVariant<5> : SubstepShape<16, 8, 128> {};
 template <> struct SubstepVariant<6> : SubstepShape<16, 16, 256> {};
 template <> struct SubstepVariant<7> : SubstepShape<8, 4, 64> {};
+template <> struct SubstepVariant<8> : SubstepShape<32, 8, 256, 1> {};
+template <> struct SubstepVariant<9> : SubstepShape<16, 16, 256, 1> {};
+template <> struct SubstepVariant<10> : SubstepShape<32, 8, 384, 2> {};
 
 template <class R, int V>
 __global__ __launch_bounds__(SubstepVariant<V>::NT) void k_grid_substeps(
@@ -464,9 +468,8 @@ __global__ __launch_bounds__(SubstepVariant<V>::NT) void k_grid_substeps(
   using SV = SubstepVariant<V>;
   const int b = blockIdx.x;  // tiles are dealt to the eight XCDs in contiguous bands
   const int t = (ntiles % 8 == 0) ? (b % 8) * (ntiles / 8) + (b / 8) : b;
-  grid_substeps_block<R, typename SV::G, kSubstepBlock, SV::NT>(f, fout, star_f, star_n, cls, tab, nux, nuy, tiles_x,
-                                                                t, dt, dt_tau, uw, *dk, n_sub, m0, count, tape, wtape,
-                                                                widx, nwall);
+  grid_substeps_block<R, typename SV::G, SV::H, SV::NT>(f, fout, star_f, star_n, cls, tab, nux, nuy, tiles_x, t, dt,
+                                                        dt_tau, uw, *dk, n_sub, m0, count, tape, wtape, widx, nwall);
 }
 
 // launch m0 / kSubstepBlock of a batched step: item = (case, tile)
@@ -775,6 +778,15 @@ void LevelKernels<T, R>::restrict_level(const T *Fprev, int nxf, int nyf, size_t
                      (R)kc, Cb, nx, plane);
 }
 
+int substep_block(int variant) {
+  switch (variant) {
+    case 8: return SubstepVariant<8>::H;
+    case 9: return SubstepVariant<9>::H;
+    case 10: return SubstepVariant<10>::H;
+    default: return kSubstepBlock;
+  }
+}
+
 void substep_tile(int variant, int *tx, int *ty) {
   switch (variant) {
 #define HLBM_TILE(V)                     \
@@ -796,15 +808,25 @@ hipError_t Kernels<T, R>::prepare() {
 #define HLBM_LDS(V)                                                                                                  \
   {reinterpret_cast<const void *>(&k_grid_substeps<R, V>), reinterpret_cast<const void *>(&kb_grid_substeps<T, R, V>), \
    (int)substeps_lds_bytes<R, typename SubstepVariant<V>::G>()}
-  struct {
+  struct FnLds {
     const void *f, *fb;
     int lds;
-  } fns[] = {HLBM_LDS(0), HLBM_LDS(1), HLBM_LDS(2), HLBM_LDS(3),
+  };
+  const FnLds fns[] = {HLBM_LDS(0), HLBM_LDS(1), HLBM_LDS(2), HLBM_LDS(3),
              HLBM_LDS(4), HLBM_LDS(5), HLBM_LDS(6), HLBM_LDS(7)};
 #undef HLBM_LDS
   for (const auto &e : fns) {
     hipError_t rc = hipFuncSetAttribute(e.f, hipFuncAttributeMaxDynamicSharedMemorySize, e.lds);
     if (rc == hipSuccess) rc = hipFuncSetAttribute(e.fb, hipFuncAttributeMaxDynamicSharedMemorySize, e.lds);
+    if (rc != hipSuccess) return rc;
+  }
+#define HLBM_LDS1(V)                                                                                      \
+  {reinterpret_cast<const void *>(&k_grid_substeps<R, V>), nullptr,                                       \
+   (int)substeps_lds_bytes<R, typename SubstepVariant<V>::G>()}
+  const FnLds single[] = {HLBM_LDS1(8), HLBM_LDS1(9), HLBM_LDS1(10)};
+#undef HLBM_LDS1
+  for (const auto &e : single) {
+    const hipError_t rc = hipFuncSetAttribute(e.f, hipFuncAttributeMaxDynamicSharedMemorySize, e.lds);
     if (rc != hipSuccess) return rc;
   }
   return hipSuccess;
@@ -865,7 +887,7 @@ void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, 
   switch (variant < 0 ? default_substep_variant<R>() : variant) {
 #define HLBM_V(V) \
   case V: grid_substeps_v<V>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
-    HLBM_V(1) HLBM_V(2) HLBM_V(3) HLBM_V(4) HLBM_V(5) HLBM_V(6) HLBM_V(7)
+    HLBM_V(1) HLBM_V(2) HLBM_V(3) HLBM_V(4) HLBM_V(5) HLBM_V(6) HLBM_V(7) HLBM_V(8) HLBM_V(9) HLBM_V(10)
 #undef HLBM_V
     default: grid_substeps_v<0>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
   }

@@ -84,17 +84,17 @@ def test_schedules_do_not_change_results(schedule):
 
 @pytest.mark.parametrize("storage", [hlbm.FP64, hlbm.FP32])
 def test_substep_variants_compute_identical_bits(storage):
-    """The four grid sub-step kernels (tile shape, workgroup size) and the
-    stream-collide launch shapes differ only in which workgroup and lane
-    compute a node."""
+    """The grid sub-step kernels (tile shape, workgroup size, sub-steps per
+    launch) and the stream-collide launch shapes differ only in which
+    workgroup and lane compute a node."""
     c = preset("lamina_128x64")
     c.pop("ckpt_every")
     n = c.pop("steps") // 4
     c["max_steps"] = n
     want = hlbm.Case(storage=storage, **c)
     want.step(n)
-    shapes = [(128, 1), (256, 2), (64, 4), (192, 1)] * 2
-    for v in range(8):
+    shapes = [(128, 1), (256, 2), (64, 4), (192, 1)] * 3
+    for v in range(11):
         _say("sub-step variant", v, "stream-collide shape", shapes[v], "storage", storage)
         g = hlbm.Case(storage=storage, **c)
         t = g.tune(variant=v, lattice=shapes[v], order=v % 2)
@@ -116,13 +116,13 @@ def test_single_case_tune_leaves_state_alone():
     lat, grid = a.lattice().copy(), a.grid().copy()
     t = a.tune(trial_steps=2)
     _say("chosen", t)
-    assert 0 <= t["substep_variant"] < 8 and t["ms_per_step"] > 0
+    assert 0 <= t["substep_variant"] < 11 and t["ms_per_step"] > 0
     assert t["lattice_threads"] in (128, 256) and t["lattice_rows"] in (1, 2, 4)
     assert np.array_equal(a.lattice(), lat) and np.array_equal(a.grid(), grid)
     a.step(n - n // 2)
     b.step(n - n // 2)
     _same(a, b)
-    for bad in (dict(variant=8), dict(lattice=(96, 1)), dict(lattice=(128, 3)), dict(order=2)):
+    for bad in (dict(variant=11), dict(lattice=(96, 1)), dict(lattice=(128, 3)), dict(order=2)):
         with pytest.raises(hlbm.HlbmError) as e:
             a.tune(**bad)
         assert e.value.code == hlbm.E_ARG
