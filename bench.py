@@ -404,6 +404,61 @@ def levels_leg(b=800, nlevels=4, storage="f64", steps=40, warmup=4, uniform=True
     return out
 
 
+def levels_theta_leg(b=256, nlevels=4, eps=0.1, beta=20.0, tau=0.8, storage="f64", periods=4.2, chunk=2048):
+    """Theta of the lamina on the finest of the paper's refinement levels
+    against one uniform lattice at the finest resolution over the same
+    5L x 5L domain (same grid, tau, boundaries), and the time each takes;
+    the semianalytical value of the paper's Eqs. (hydro_gamma),(hydro_delta)
+    beside them as context."""
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.theory import theta_semianalytical
+    from paper_2006_13631_amd.workloads import paper_levels
+    d = paper_levels(b=b, nlevels=nlevels, eps=eps, beta=beta, tau=tau, margin=8)
+    per = 2 ** (nlevels - 1)
+    nu = (tau - 0.5) / 3.0
+    period = b * b / (nu * beta)  # finest steps
+    n0 = int(math.ceil(periods * period / per))
+    runs = {}
+    for kind in ("levels", "uniform"):
+        if kind == "levels":
+            c = H.MultiLevel(d["nx0"], d["ny0"], d["boxes"], bc0=d["bc0"], storage=H.STORAGE[storage],
+                             max_steps=n0 * per, **d["fine"])
+            total, unit = n0, per
+        else:
+            n = 5 * b + 1
+            c = H.Case(nx=n, ny=n, bc=H.BC_PAPER, storage=H.STORAGE[storage], max_steps=n0 * per, **d["fine"])
+            total, unit = n0 * per, 1
+        c.tune(trial_steps=4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < total:
+            k = min(chunk, total - done)
+            c.step(k)
+            done += k
+            print(f"# levels theta {kind} {done}/{total}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        th = c.theta(1.0, 4.0)
+        runs[kind] = {"theta": [th.real, th.imag], "s": round(dt, 3),
+                      "ms_per_finest_step": round(dt / (total * unit) * 1e3, 4)}
+        if kind == "levels":
+            runs[kind]["levels"] = [list(sh) for sh in c.shapes]
+        else:
+            runs[kind]["lattice"] = [5 * b + 1, 5 * b + 1]
+        c.close()
+    tl = complex(*runs["levels"]["theta"])
+    tu = complex(*runs["uniform"]["theta"])
+    ts = theta_semianalytical(beta, eps)
+    return {"workload": f"paper_levels_{b}_theta", "storage": storage, "nlevels": nlevels, "eps": eps,
+            "beta": beta, "tau_finest": tau, "grid": [4 * b, b], "finest_steps": n0 * per,
+            "period_steps": round(period, 1), **runs,
+            "theta_rel_diff_levels_vs_uniform": abs(tl - tu) / abs(tu),
+            "speedup_vs_uniform": round(runs["uniform"]["s"] / runs["levels"]["s"], 3),
+            "theta_semianalytical": [ts.real, ts.imag]}
+
+
 def storage_leg(workload, storage, steps, warmup, timing_steps):
     """The same workload at another storage precision: lattice MLUPS over
     graph-replayed steps, the stream-collide's mean duration (its own events)
@@ -474,6 +529,9 @@ def main():
     ap.add_argument("--levels-storage", default="f64", choices=list(BYTES))
     ap.add_argument("--levels-steps", type=int, default=40)
     ap.add_argument("--levels-no-uniform", action="store_true")
+    ap.add_argument("--levels-theta", action="store_true",
+                    help="run only Theta on 4 refinement levels (L = 256 at the finest) against a uniform "
+                         "finest lattice over the same domain and print its line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
@@ -486,6 +544,10 @@ def main():
     if args.sweep:
         torch.cuda.set_device(0)
         print(json.dumps(sweep_leg(periods=args.sweep_periods, loop=not args.sweep_no_loop)), flush=True)
+        return
+    if args.levels_theta:
+        torch.cuda.set_device(0)
+        print(json.dumps(levels_theta_leg(storage=args.levels_storage)), flush=True)
         return
     if args.levels:
         torch.cuda.set_device(0)
