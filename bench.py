@@ -41,11 +41,11 @@ BYTES = {"f64": 8, "f32": 4, "f16dev": 2}
 CALIB_COPY_BYTES = 256 << 20  # plain device copy that scales the HBM byte counters
 
 
-def measured_traffic(workload, storage):
-    """HBM bytes per stream-collide launch from the committed counter summary,
+def measured_traffic(workload, storage, kernel="k_stream_collide"):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
     or None when there is none or the kernel source changed since."""
     from paper_2006_13631_amd.profiling import source_sha256
-    path = os.path.join(ROOT, "profiles", f"pmc_k_stream_collide.{workload}.{storage}.json")
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}.{workload}.{storage}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -487,8 +487,11 @@ def storage_leg(workload, storage, steps, warmup, timing_steps):
         th = case.theta()
     except H.HlbmError:
         pass
+    two = bool(case.info().two_step)
     return {"storage": storage, "value": round(nodes * steps / dt / 1e6, 2), "unit": "MLUPS",
-            "ms_per_step": round(1000.0 * dt / steps, 4), "stream_collide_us": round(avg * 1e6, 3),
+            "ms_per_step": round(1000.0 * dt / steps, 4),
+            "stream_collide_kernel": "k_stream_collide2" if two else "k_stream_collide",
+            "stream_collide_steps_per_launch": 2 if two else 1, "stream_collide_us": round(avg * 1e6, 3),
             "stream_collide_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
             "theta": None if th is None else [th.real, th.imag],
             "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}}
@@ -601,7 +604,10 @@ def main():
     mlups = nx * ny * steps / dt / 1e6
 
     # the stream-collide's own start and end events on its stream, nothing
-    # else recorded in these steps
+    # else recorded in these steps (on the two-step path: the launch that
+    # advances the lattice outside the band by two steps, reading it once and
+    # writing it once)
+    two = bool(case.info().two_step)
     case.timing(2)
     case.step(args.timing_steps)
     ms_k1, n_k1 = case.timing_get(H.K_STREAM_COLLIDE)
@@ -635,8 +641,10 @@ def main():
                    "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, args.storage),
-                     "kernel": "k_stream_collide", "avg_us": round(avg_s * 1e6, 3),
+                     "traffic": measured_traffic(args.workload, args.storage,
+                                                 "k_stream_collide2" if two else "k_stream_collide"),
+                     "kernel": "k_stream_collide2" if two else "k_stream_collide",
+                     "steps_per_launch": 2 if two else 1, "avg_us": round(avg_s * 1e6, 3),
                      "bytes_per_launch": alg_bytes},
         "kernel_avg_us": kern,
         "mlups_total": round((nx * ny + info.n_sub * info.nnode) * steps / dt / 1e6, 2),

@@ -116,7 +116,9 @@ typedef struct hlbm_info {
   int64_t n_type1, n_type2, n_type3; /* refill counts, summed over steps */
   int64_t lattice_bytes; /* device bytes of one lattice buffer          */
   int32_t status;        /* HLBM_STATUS_*                               */
-  int32_t reserved;
+  int32_t two_step;      /* 1: pairs of steps advance the lattice away
+                            from the grid in one launch (the band near it
+                            one step at a time); same results either way */
 } hlbm_info;
 
 #define HLBM_STATUS_RUNNING 0  /* steps left                                  */

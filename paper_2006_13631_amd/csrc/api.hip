@@ -101,7 +101,9 @@ class Case final : public CaseBase {
  public:
   ~Case() override { release(); }
 
-  int init(const hlbm_config &c) {
+  // two_step: allow the two-step stream-collide (single cases; a batch
+  // advances its members with the case-batched kernels)
+  int init(const hlbm_config &c, bool two_step = true) {
     cfg_ = c;
     d_ = derive(c);
     h_ = c.h_u > 0.0 ? c.h_u : 1.0;
@@ -191,12 +193,24 @@ class Case final : public CaseBase {
         HIPCHK(alloc(&ck_grid_, (size_t)nck_ * ck_grid_bytes_));
       }
     }
+    two_step_ = two_step && std::getenv("HLBM_ONE_STEP") == nullptr && s_grid_ == s_main_ && choose_band();
+    if (two_step_) {
+      HIPCHK(alloc(&lat_[2], 9 * plane_ * sizeof(T)));
+      Kernels<T, R>::fill_rest((T *)lat_[2], plane_, nullptr, 0, s_main_);
+    }
+    for (int i = 0; i < 3; ++i) phys_[i] = lat_[i];
     Kernels<T, R>::fill_rest((T *)lat_[0], plane_, has_grid_ ? (R *)gbuf_[0] : nullptr, N, s_main_);
     Kernels<T, R>::fill_rest((T *)lat_[1], plane_, has_grid_ ? (R *)gbuf_[1] : nullptr, N, s_main_);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s_main_));
     return HLBM_OK;
   }
+
+#define ENQ(expr)                  \
+  do {                             \
+    e = (expr);                    \
+    if (e != hipSuccess) return e; \
+  } while (0)
 
   // Enqueue one structured step t_k -> t_{k+1} (host bookkeeping included).
   // Stream-collide with its own start and end events when timing is on
@@ -212,11 +226,6 @@ class Case final : public CaseBase {
 
   hipError_t enqueue_step() {
     hipError_t e = hipSuccess;
-#define ENQ(expr)                  \
-  do {                             \
-    e = (expr);                    \
-    if (e != hipSuccess) return e; \
-  } while (0)
     CaseView<T, R> v = view();
     if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][0], s_main_));
     if (has_grid_) {
@@ -230,22 +239,7 @@ class Case final : public CaseBase {
       // 2. lattice stream-collide, Eq.(LBE)
       stream_collide_timed(v);
       // 3.-6. grid path: donors, n sub-steps, refill, force
-      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][3], s_grid_));
-      Kernels<T, R>::interface_donors(v, s_grid_);
-      int cur = gcur_;
-      const int blk = substep_block(substep_variant_);
-      for (int m = 0; m < d_.n; m += blk) {
-        const int cnt = std::min(blk, d_.n - m);
-        Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_, nullptr, nullptr,
-                                     nullptr, 0, substep_variant_);
-        cur = 1 - cur;
-      }
-      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][4], s_grid_));
-      Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
-      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][5], s_grid_));
-      Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_);
-      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][6], s_grid_));
-      gcur_ = 1 - cur;
+      ENQ(enqueue_grid_path(v));
       if (s_grid_ != s_main_) {
         ENQ(hipEventRecord(ev_join_, s_grid_));
         ENQ(hipStreamWaitEvent(s_main_, ev_join_, 0));
@@ -259,31 +253,120 @@ class Case final : public CaseBase {
     ENQ(hipGetLastError());
     std::swap(lat_[0], lat_[1]);
     ++k_;
-#undef ENQ
     return hipSuccess;
   }
 
-  // kGraphSteps steps (even) captured as one HIP graph per buffer
-  // arrangement: after an even number of steps the lattice and grid buffers
-  // are back in place, so the graph can be replayed; kernels read the step
-  // index from device memory.
+  // Grid path of the step whose lattice (post-collision at t_k) v.A holds:
+  // donors, n sub-steps, refill, force (steps 3-6 of the step).
+  hipError_t enqueue_grid_path(const CaseView<T, R> &v) {
+    hipError_t e = hipSuccess;
+    if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][3], s_grid_));
+    Kernels<T, R>::interface_donors(v, s_grid_);
+    int cur = gcur_;
+    const int blk = substep_block(substep_variant_);
+    for (int m = 0; m < d_.n; m += blk) {
+      const int cnt = std::min(blk, d_.n - m);
+      Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_, nullptr, nullptr,
+                                   nullptr, 0, substep_variant_);
+      cur = 1 - cur;
+    }
+    if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][4], s_grid_));
+    Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
+    if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][5], s_grid_));
+    Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_);
+    if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][6], s_grid_));
+    gcur_ = 1 - cur;
+    return e;
+  }
+
+  // Two structured steps t_k -> t_{k+2}. Outside the band the lattice takes
+  // both steps in one launch (A -> C); the band takes the first step there
+  // too (into B), and after step k's grid path and step k+1's interpolation
+  // nodes, its second step with the single-step kernel (B -> C, on the band
+  // only). Every node computes what two single steps compute, in the same
+  // arithmetic. Afterwards C holds t_{k+2}.
+  hipError_t enqueue_pair() {
+    hipError_t e = hipSuccess;
+    CaseView<T, R> v = view();
+    if (has_grid_) Kernels<T, R>::lattice_from_grid(v, (const R *)gbuf_[gcur_], s_main_);
+    if (timing_ == 2) Kernels<T, R>::stream_collide2(v, s_main_, tev_[tslot_][8], tev_[tslot_][2]);
+    else Kernels<T, R>::stream_collide2(v, s_main_);
+    if (has_grid_) {
+      ENQ(enqueue_grid_path(v));
+      CaseView<T, R> w = view();
+      w.A = (const T *)lat_[1];
+      w.B = (T *)lat_[2];
+      w.wx0 = band_[0];
+      w.ww = band_[1] - band_[0] + 1;
+      w.wy0 = band_[2];
+      w.wh = band_[3] - band_[2] + 1;
+      Kernels<T, R>::lattice_from_grid(w, (const R *)gbuf_[gcur_], s_main_);
+      Kernels<T, R>::stream_collide(w, s_main_, nullptr, nullptr, lattice_threads_, lattice_rows_, 0);
+      ENQ(enqueue_grid_path(w));
+    }
+    if (timing_) ++tslot_;
+    ENQ(hipGetLastError());
+    void *a = lat_[0], *b = lat_[1];
+    lat_[0] = lat_[2];
+    lat_[1] = a;
+    lat_[2] = b;
+    k_ += 2;
+    return hipSuccess;
+  }
+
+  // n steps: pairs on the two-step path where it is on, single steps
+  // otherwise (and for an odd last step)
+  hipError_t enqueue_steps(int n, int *done) {
+    *done = 0;
+    while (*done < n) {
+      hipError_t e;
+      if (two_step_ && timing_ != 1 && n - *done >= 2) {
+        e = enqueue_pair();
+        if (e == hipSuccess) *done += 2;
+      } else {
+        e = enqueue_step();
+        if (e == hipSuccess) *done += 1;
+      }
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
+  // which physical lattice buffer each role holds, and the grid buffer
+  int layout_key() const {
+    int i0 = 0, i1 = 0;
+    for (int i = 0; i < 3; ++i) {
+      if (lat_[0] == phys_[i]) i0 = i;
+      if (lat_[1] == phys_[i]) i1 = i;
+    }
+    return (3 * i0 + i1) * 2 + gcur_;
+  }
+
+  // kGraphSteps steps captured as one HIP graph per buffer arrangement:
+  // kernels read the step index from device memory, so a graph replays for
+  // every later kGraphSteps steps that start from the same arrangement.
   hipError_t graph_for_current_layout(hipGraphExec_t *out) {
-    const int key = (lat_[0] == lat_base_ ? 0 : 1) + 2 * gcur_;
+    const int key = layout_key();
     if (gexec_[key]) {
       *out = gexec_[key];
       return hipSuccess;
     }
-    void *l0 = lat_[0], *l1 = lat_[1];
+    void *l0 = lat_[0], *l1 = lat_[1], *l2 = lat_[2];
     const int g0 = gcur_;
     const int64_t k0 = k_;
     hipError_t e = hipStreamBeginCapture(s_main_, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t e2 = hipSuccess;
-    for (int i = 0; i < kGraphSteps && e2 == hipSuccess; ++i) e2 = enqueue_step();
+    int n = 0;
+    hipError_t e2 = enqueue_steps(kGraphSteps, &n);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s_main_, &g);
+    after_graph_[key][0] = lat_[0];
+    after_graph_[key][1] = lat_[1];
+    after_graph_[key][2] = lat_[2];
+    after_gcur_[key] = gcur_;
     lat_[0] = l0;
     lat_[1] = l1;
+    lat_[2] = l2;
     gcur_ = g0;
     k_ = k0;
     if (e2 != hipSuccess) {
@@ -318,13 +401,19 @@ class Case final : public CaseBase {
         hipGraphExec_t ge = nullptr;
         HIPCHK(graph_for_current_layout(&ge));
         HIPCHK(hipGraphLaunch(ge, s_main_));
-        // same buffer layout, kGraphSteps steps further
+        // the buffer arrangement the captured steps end in
+        const int key = layout_key();
+        lat_[0] = after_graph_[key][0];
+        lat_[1] = after_graph_[key][1];
+        lat_[2] = after_graph_[key][2];
+        gcur_ = after_gcur_[key];
         k_ += kGraphSteps;
         done += kGraphSteps;
       } else {
-        HIPCHK(enqueue_step());
+        int n = 0;
+        HIPCHK(enqueue_steps(room >= 2 && timing_ != 1 ? 2 : 1, &n));
         if (timing_ && tslot_ == kTimingRing) HIPCHK(harvest());
-        ++done;
+        done += n;
       }
     }
     if (timing_ && tslot_ > 0) HIPCHK(harvest());
@@ -458,6 +547,7 @@ class Case final : public CaseBase {
     o->step = k_;
     o->y = d_.A * std::sin(d_.omega * (double)k_);
     o->lattice_bytes = (int64_t)(9 * plane_ * sizeof(T));
+    o->two_step = two_step_ ? 1 : 0;
     {
       int flag = 0;
       if (has_grid_) HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
@@ -767,6 +857,36 @@ class Case final : public CaseBase {
     iy1 = (int)std::floor(ry1);
   }
 
+  // Band of the two-step path: every lattice node within kBand of a
+  // fictitious rectangle of any step (k = 0 .. max_steps, and k - 1 = 0),
+  // so a node outside it meets no interpolation node, carried node, grid
+  // donor or refill donor in either step of a pair. False when the path
+  // does not apply (lattice too small for its tile, ring boundaries, or a
+  // band that would wrap across a periodic edge).
+  bool choose_band() {
+    if (cfg_.bc != HLBM_BC_PERIODIC_X_WALLS_Y && cfg_.bc != HLBM_BC_PERIODIC && cfg_.bc != HLBM_BC_PAPER) return false;
+    if (cfg_.nx < kTwoStepTX + 2 || cfg_.ny < kTwoStepTY + 2) return false;
+    if (!has_grid_) return true;  // no band: every node takes both steps at once
+    constexpr int kBand = 6;
+    int x0 = cfg_.nx, x1 = -1, y0 = cfg_.ny, y1 = -1;
+    for (const StepParams &P : P_host_) {
+      x0 = std::min({x0, P.ix0, P.pix0});
+      x1 = std::max({x1, P.ix1, P.pix1});
+      y0 = std::min({y0, P.iy0, P.piy0});
+      y1 = std::max({y1, P.iy1, P.piy1});
+    }
+    x0 -= kBand;
+    x1 += kBand;
+    y0 -= kBand;
+    y1 += kBand;
+    if (x0 < 0 || y0 < 0 || x1 >= cfg_.nx || y1 >= cfg_.ny) return false;
+    band_[0] = x0;
+    band_[1] = x1;
+    band_[2] = y0;
+    band_[3] = y1;
+    return true;
+  }
+
   StepParams params_at(int64_t k) const {
     StepParams P;
     P.y = motion(k);
@@ -783,9 +903,18 @@ class Case final : public CaseBase {
     CaseView<T, R> v{};
     v.A = (const T *)lat_[0];
     v.B = (T *)lat_[1];
+    v.C = (T *)lat_[2];
     v.nx = cfg_.nx;
     v.plane = plane_;
     v.ny = cfg_.ny;
+    v.wx0 = 0;
+    v.wy0 = 0;
+    v.ww = cfg_.nx;
+    v.wh = cfg_.ny;
+    v.bx0 = band_[0];
+    v.bx1 = band_[1];
+    v.by0 = band_[2];
+    v.by1 = band_[3];
     v.bc = cfg_.bc;
     v.inv_tau = (R)(1.0 / cfg_.tau);
     v.g_post = (R)(2.0 * (cfg_.tau - 1.0) / (2.0 * cfg_.tau - 1.0));
@@ -855,14 +984,15 @@ class Case final : public CaseBase {
   bool has_grid() const { return has_grid_; }
   hipError_t enqueue_one() { return enqueue_step(); }
   struct Layout {
-    void *l0, *l1;
+    void *l0, *l1, *l2;
     int gcur;
     int64_t k;
   };
-  Layout layout() const { return {lat_[0], lat_[1], gcur_, k_}; }
+  Layout layout() const { return {lat_[0], lat_[1], lat_[2], gcur_, k_}; }
   void set_layout(const Layout &l) {
     lat_[0] = l.l0;
     lat_[1] = l.l1;
+    lat_[2] = l.l2;
     gcur_ = l.gcur;
     k_ = l.k;
   }
@@ -1232,7 +1362,12 @@ class Case final : public CaseBase {
   double tms_[8] = {};
   int64_t tcount_[8] = {};
   std::vector<void *> owned_;
-  void *lat_[2] = {nullptr, nullptr};
+  void *lat_[3] = {nullptr, nullptr, nullptr};  // state at t_k, free, free (two-step path)
+  void *phys_[3] = {nullptr, nullptr, nullptr};  // the physical buffers
+  bool two_step_ = false;
+  int band_[4] = {-10, -20, -10, -20};  // x0, x1, y0, y1 of the band (inclusive; empty, far outside)
+  void *after_graph_[18][3] = {};
+  int after_gcur_[18] = {};
   void *gbuf_[2] = {nullptr, nullptr};
   int gcur_ = 0;
   R *star_f_ = nullptr, *star_n_ = nullptr;
@@ -1249,7 +1384,7 @@ class Case final : public CaseBase {
   int64_t k_ = 0;
   bool use_graphs_ = true;
   void *lat_base_ = nullptr;
-  hipGraphExec_t gexec_[4] = {};
+  hipGraphExec_t gexec_[18] = {};
   std::vector<StepParams> P_host_;
   // checkpoints
   int ckW_ = 0;
@@ -1285,6 +1420,8 @@ class Case final : public CaseBase {
   hipEvent_t tev_adj_ring_[kTimingRing][2] = {};
   int aslot_ = 0;
 };
+
+#undef ENQ
 
 // Configuration checks shared by all storage types (mirrors the geometric
 // requirements stated in hlbm.h).
@@ -1344,7 +1481,7 @@ class Batch final : public CaseBase {
   int init(const hlbm_config *cfgs, int n) {
     for (int i = 0; i < n; ++i) {
       auto c = std::make_unique<Case<T, R>>();
-      const int rc = c->init(cfgs[i]);
+      const int rc = c->init(cfgs[i], false);
       if (rc != HLBM_OK) {
         err = "case " + std::to_string(i) + ": " + c->err;
         return rc;
@@ -1888,6 +2025,10 @@ class MultiLevel final : public CaseBase {
     v.plane = c.plane;
     v.bc = c.bc;
     v.inv_tau = (R)(1.0 / c.tau);
+    v.wx0 = 0;
+    v.wy0 = 0;
+    v.ww = c.nx;
+    v.wh = c.ny;
     v.sx0 = c.box.x0;
     v.sx1 = c.box.x1;
     v.sy0 = c.box.y0;

@@ -35,6 +35,8 @@ struct Stor<double> {
   static __device__ __forceinline__ void st_stream(double *p, size_t i, int, double v) {
     __builtin_nontemporal_store(v, p + i);
   }
+  // the value a store followed by a load returns
+  static __device__ __forceinline__ double round_trip(double v, int) { return v; }
 };
 template <>
 struct Stor<float> {
@@ -43,6 +45,7 @@ struct Stor<float> {
   static __device__ __forceinline__ void st_stream(float *p, size_t i, int, float v) {
     __builtin_nontemporal_store(v, p + i);
   }
+  static __device__ __forceinline__ float round_trip(float v, int) { return v; }
 };
 template <>
 struct Stor<__half> {  // deviation from the rest equilibrium w_i
@@ -56,6 +59,9 @@ struct Stor<__half> {  // deviation from the rest equilibrium w_i
     const __half h = __float2half_rn(v - wgt<float>(q));
     __builtin_nontemporal_store(*reinterpret_cast<const unsigned short *>(&h),
                                 reinterpret_cast<unsigned short *>(p + i));
+  }
+  static __device__ __forceinline__ float round_trip(float v, int q) {
+    return __half2float(__float2half_rn(v - wgt<float>(q))) + wgt<float>(q);
   }
 };
 
@@ -161,6 +167,40 @@ __device__ __forceinline__ void pull_index(int nx, int ny, size_t plane, int bc,
   idx[4] = hi ? 2 * plane + c : 4 * plane + rp + x;
   idx[7] = wr ? 5 * plane + c : (hi ? 5 * plane + c : 7 * plane + rp + xp);
   idx[8] = wl ? 6 * plane + c : (hi ? 6 * plane + c : 8 * plane + rp + xm);
+}
+
+// The same streaming rules as pull_index, as the source of one population:
+// population q arriving at (x, y) is population qs of node (xs, ys) one step
+// earlier (bc 0, 1, 2).
+__device__ __forceinline__ void pull_source(int nx, int ny, int bc, int x, int y, int q, int &qs, int &xs,
+                                            int &ys) {
+  constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  int sx = x - CXd[q], sy = y - CYd[q];
+  qs = q;
+  if (bc == 2) {
+    if (sx < 0 || sx >= nx) {  // x wall: halfway bounce-back, also at the corners
+      qs = opp[q];
+      xs = x;
+      ys = y;
+      return;
+    }
+    if (sy < 0 || sy >= ny) sy = y;  // y end: from the node's own row
+    xs = sx;
+    ys = sy;
+    return;
+  }
+  xs = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+  if (bc == 1) {
+    ys = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+    return;
+  }
+  if (sy < 0 || sy >= ny) {  // y wall: halfway bounce-back
+    qs = opp[q];
+    xs = x;
+    ys = y;
+    return;
+  }
+  ys = sy;
 }
 
 // Populations arriving at lattice node (x, y) at t_{k+1}: pulled from the

@@ -19,6 +19,16 @@ struct CaseView {
   // nodes strictly inside (sx0, sx1) x (sy0, sy1) are neither read nor
   // written by the stream-collide (a finer level covers them); empty: 0
   int sx0, sx1, sy0, sy1;
+  // window of nodes a single-step stream-collide updates: [wx0, wx0 + ww)
+  // x [wy0, wy0 + wh) (the whole lattice unless a two-step launch covers
+  // the rest)
+  int wx0, wy0, ww, wh;
+  // two steps per launch: C receives the state at t_{k+2} outside the band
+  // [bx0, bx1] x [by0, by1] (inclusive; empty when bx0 > bx1), where the
+  // grid coupling needs every step; B receives t_{k+1} on the band and one
+  // node around it
+  T *C;
+  int bx0, bx1, by0, by1;
   R inv_tau;       // 1 / tau_s
   R g_post;        // 2 (tau_s - 1) / (2 tau_s - 1), Eq.(postcollision2_s)
   R k_neq;         // 1 - 1/(2 tau_s), Eq.(continuity_stresses)
@@ -64,6 +74,8 @@ constexpr int kSubstepBlock = 4;
 // default launch shape of the lattice stream-collide: workgroup width and
 // rows per lane
 constexpr int kLatticeThreads = 128, kLatticeRows = 2;
+// tile of the two-step stream-collide
+constexpr int kTwoStepTX = 64, kTwoStepTY = 8;
 
 // Variants of the grid sub-step kernel (tile of grid nodes per workgroup,
 // workgroup size):
@@ -99,6 +111,11 @@ struct Kernels {
   // contiguous band of rows
   static void stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start = nullptr,
                              hipEvent_t stop = nullptr, int threads = 0, int rows = 0, int order = 0);
+  // two steps t_k -> t_{k+2} in one launch (tile of kTwoStepTX x kTwoStepTY
+  // nodes, the first step on the tile and a one-node ring kept in LDS);
+  // needs nx >= kTwoStepTX + 2 and ny >= kTwoStepTY + 2
+  static void stream_collide2(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start = nullptr,
+                              hipEvent_t stop = nullptr);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
   static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
   // sub-steps m0 .. m0+count-1 (count <= kSubstepBlock) in one launch; with

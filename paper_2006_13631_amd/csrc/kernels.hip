@@ -48,14 +48,14 @@ __device__ __forceinline__ bool static_skip(const CaseView<T, R> &v, int x, int 
 template <class T, class R, int RPT>
 __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, const T *__restrict__ A,
                                                      T *__restrict__ B, const int64_t *k_at, int bx, int by) {
-  const int x = bx * blockDim.x + threadIdx.x;
-  if (x >= v.nx) return;
+  const int x = v.wx0 + bx * blockDim.x + threadIdx.x;
+  if (x >= v.wx0 + v.ww) return;
   const size_t plane = v.plane;
+  const int y0 = v.wy0 + by * RPT, yend = v.wy0 + v.wh;
   R f[RPT][9];
 #pragma unroll
   for (int r = 0; r < RPT; ++r)
-    if (by * RPT + r < v.ny && !static_skip(v, x, by * RPT + r))
-      pull<T, R>(A, v.nx, v.ny, plane, v.bc, x, by * RPT + r, f[r]);
+    if (y0 + r < yend && !static_skip(v, x, y0 + r)) pull<T, R>(A, v.nx, v.ny, plane, v.bc, x, y0 + r, f[r]);
   int ix0 = 1, ix1 = 0, iy0 = 1, iy1 = 0;  // empty rectangle without a grid
   if (v.has_grid) {
     const StepParams &P = v.params[*k_at];
@@ -63,8 +63,8 @@ __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, co
   }
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int y = by * RPT + r;
-    if (y >= v.ny || static_skip(v, x, y)) continue;
+    const int y = y0 + r;
+    if (y >= yend || static_skip(v, x, y)) continue;
     const size_t c = (size_t)y * v.nx + x;
     if (x >= ix0 && x <= ix1 && y >= iy0 && y <= iy1) {
 #pragma unroll
@@ -98,6 +98,93 @@ __global__ __launch_bounds__(256) void kb_stream_collide(const CaseView<T, R> *_
   int64_t k;
   if (!batched_case(v, k)) return;
   stream_collide_block<T, R, RPT>(v, v.lat[k & 1], v.lat[(k + 1) & 1], v.dk, it.y, it.z);
+}
+
+// ---- K1 over two steps --------------------------------------------------------
+// Nodes farther than the band from the fictitious rectangle never meet the
+// grid coupling over two steps, so they advance t_k -> t_{k+2} in one
+// launch: the first step (the same arithmetic as K1, rectangle nodes
+// carrying their values) on the tile and a one-node ring around it, kept in
+// LDS; the second step pulls from there, following the boundary rules of
+// pull_source; it sees each first-step value as the stored lattice would
+// hold it (rounded to the storage type). The band and one node around it
+// also get t_{k+1} in B, from
+// which the single-step kernel advances the band after the grid has written
+// its interpolation nodes.
+template <class T, class R>
+__global__ __launch_bounds__(512) void k_stream_collide2(CaseView<T, R> v, int tiles_x) {
+  constexpr int TX = kTwoStepTX, TY = kTwoStepTY, NT = 512, LX = TX + 2, LY = TY + 2, LN = LX * LY;
+  constexpr int P1 = (LN + NT - 1) / NT;
+  static_assert(TX * TY == NT, "one output node per lane");
+  __shared__ R s[9 * LN];
+  const int nx = v.nx, ny = v.ny;
+  const size_t plane = v.plane;
+  const int tx0 = (blockIdx.x % tiles_x) * TX, ty0 = (blockIdx.x / tiles_x) * TY;
+  R f[P1][9];
+  int node[P1];
+#pragma unroll
+  for (int u = 0; u < P1; ++u) {
+    const int i = threadIdx.x + u * NT;
+    if (i < LN) {
+      const int gx = ((tx0 - 1 + i % LX) % nx + nx) % nx, gy = ((ty0 - 1 + i / LX) % ny + ny) % ny;
+      node[u] = gy * nx + gx;
+      pull<T, R>(v.A, nx, ny, plane, v.bc, gx, gy, f[u]);
+    }
+  }
+  int ix0 = 1, ix1 = 0, iy0 = 1, iy1 = 0;
+  if (v.has_grid) {
+    const StepParams &P = v.params[*v.dk];
+    ix0 = P.ix0, ix1 = P.ix1, iy0 = P.iy0, iy1 = P.iy1;
+  }
+#pragma unroll
+  for (int u = 0; u < P1; ++u) {
+    const int i = threadIdx.x + u * NT;
+    if (i >= LN) continue;
+    const int gx = node[u] % nx, gy = node[u] / nx;
+    if (gx >= ix0 && gx <= ix1 && gy >= iy0 && gy <= iy1) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) f[u][q] = Stor<T>::ld(v.A, q * plane + node[u], q);
+    } else {
+      R e[9], rho, ux, uy;
+      moments<R>(f[u], rho, ux, uy);
+      equilibrium<R>(rho, ux, uy, e);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) f[u][q] = fmad(-v.inv_tau, f[u][q] - e[q], f[u][q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s[q * LN + i] = f[u][q];
+  }
+  __syncthreads();
+  const int ox = threadIdx.x % TX, oy = threadIdx.x / TX;
+  const int x = tx0 + ox, y = ty0 + oy;
+  if (x >= nx || y >= ny) return;
+  const size_t c = (size_t)y * nx + x;
+  const int l = (oy + 1) * LX + ox + 1;
+  if (x >= v.bx0 - 1 && x <= v.bx1 + 1 && y >= v.by0 - 1 && y <= v.by1 + 1) {
+    if (x >= ix0 && x <= ix1 && y >= iy0 && y <= iy1) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) v.B[q * plane + c] = v.A[q * plane + c];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Stor<T>::st_stream(v.B, q * plane + c, q, s[q * LN + l]);
+    }
+    if (x >= v.bx0 && x <= v.bx1 && y >= v.by0 && y <= v.by1) return;
+  }
+  R g[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    int qs, xs, ys;
+    pull_source(nx, ny, v.bc, x, y, q, qs, xs, ys);
+    int lx = xs - (tx0 - 1), ly = ys - (ty0 - 1);  // tile coordinates, across a periodic seam too
+    lx += lx < 0 ? nx : (lx >= LX ? -nx : 0);
+    ly += ly < 0 ? ny : (ly >= LY ? -ny : 0);
+    g[q] = Stor<T>::round_trip(s[qs * LN + ly * LX + lx], qs);  // as if stored at t_{k+1} and loaded
+  }
+  R e[9], rho, ux, uy;
+  moments<R>(g, rho, ux, uy);
+  equilibrium<R>(rho, ux, uy, e);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Stor<T>::st_stream(v.C, q * plane + c, q, fmad(-v.inv_tau, g[q] - e[q], g[q]));
 }
 
 // ---- K2: lattice interpolation nodes from the grid, Eq.(postcollision2_s) ----
@@ -842,7 +929,8 @@ template <class T, class R>
 void Kernels<T, R>::stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start, hipEvent_t stop,
                                    int threads, int rows, int order) {
   const int nt = threads > 0 ? threads : kLatticeThreads, rpt = rows > 0 ? rows : kLatticeRows;
-  const int nbx = (int)blocks(v.nx, nt), nblocks = nbx * ((v.ny + rpt - 1) / rpt);
+  if (v.ww <= 0 || v.wh <= 0) return;
+  const int nbx = (int)blocks(v.ww, nt), nblocks = nbx * ((v.wh + rpt - 1) / rpt);
   const dim3 g(nblocks);
   const int band = order & 1;
 #define HLBM_K1(RPT)                                                                                            \
@@ -857,6 +945,16 @@ void Kernels<T, R>::stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEv
     default: HLBM_K1(1); break;
   }
 #undef HLBM_K1
+}
+
+template <class T, class R>
+void Kernels<T, R>::stream_collide2(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  const int tiles_x = (int)blocks(v.nx, kTwoStepTX), tiles = tiles_x * (int)blocks(v.ny, kTwoStepTY);
+  if (start || stop)
+    hipExtLaunchKernelGGL((k_stream_collide2<T, R>), dim3(tiles), dim3(kTwoStepTX * kTwoStepTY), 0, s, start, stop, 0,
+                          v, tiles_x);
+  else
+    hipLaunchKernelGGL((k_stream_collide2<T, R>), dim3(tiles), dim3(kTwoStepTX * kTwoStepTY), 0, s, v, tiles_x);
 }
 
 template <class T, class R>

@@ -54,7 +54,7 @@ class Info(C.Structure):
                  "n_classes")] + \
                [("step", C.c_int64), ("y", C.c_double), ("n_type1", C.c_int64),
                 ("n_type2", C.c_int64), ("n_type3", C.c_int64), ("lattice_bytes", C.c_int64),
-                ("status", C.c_int32), ("reserved", C.c_int32)]
+                ("status", C.c_int32), ("two_step", C.c_int32)]
 
 
 class Tuning(C.Structure):

@@ -82,7 +82,7 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dic
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         per = _per_dispatch(path, counter)
-        kv = [v for n, vs in per.items() if kernel in n for v in vs]
+        kv = [v for n, vs in per.items() if kernel + "<" in n for v in vs]  # the kernel, not a longer name
         cv = [v for n, vs in per.items() if COPY_KERNEL in n for v in vs]
         if not kv or not cv:
             raise SystemExit(f"{counter}: no dispatch of {kernel!r} or of the copy kernel in {path}")
