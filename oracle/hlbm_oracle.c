@@ -787,6 +787,11 @@ struct or_sim {
   real *hist;
   int64_t hist_cap, hist_n;
   int64_t nt1, nt2, nt3;
+  /* two-way coupled motion (or_set_motion): M y'' + C y' + K y = F_y */
+  int fsi;
+  double M, Ks, Cd, y_max;
+  double y_cur, y_prev, v_cur;
+  double *mhist; /* [hist_cap + 1][2]: (y, v) at t_k */
 };
 
 /* prescribed motion y(t) = A sin(omega t) (Sec. Problem statement), t = k */
@@ -830,7 +835,7 @@ static void free_sim(or_sim *s) {
   if (!s) return;
   free(s->fA); free(s->fB); free(s->disc); or_mesh_free(s->m);
   free(s->fu); free(s->fu2); free(s->star_eq); free(s->star_neq);
-  free(s->uwx); free(s->uwy); free(s->hist);
+  free(s->uwx); free(s->uwy); free(s->hist); free(s->mhist);
   free(s);
 }
 
@@ -1063,9 +1068,10 @@ int or_step(or_sim *s, int64_t nsteps) {
     } else {
       const or_mesh *m = s->m;
       const int N = m->nnode;
-      const real yk = motion_y(s, k);
-      const real yprev = (k > 0) ? motion_y(s, k - 1) : yk;
-      const real yk1 = motion_y(s, k + 1);
+      /* lamina offset at t_k and t_{k-1}: prescribed, or the coupled state */
+      const real yk = s->fsi ? s->y_cur : motion_y(s, k);
+      const real yprev = s->fsi ? s->y_prev : ((k > 0) ? motion_y(s, k - 1) : yk);
+      real yk1 = s->fsi ? 0.0 : motion_y(s, k + 1);
       const rect_t R = rect_at(s, RE(yk)), Rp = rect_at(s, RE(yprev));
       /* 1. lattice interpolation nodes, plus nodes the moving fictitious line
        *    has just uncovered (Sec. Refill procedure, last paragraphs), get
@@ -1097,7 +1103,8 @@ int or_step(or_sim *s, int64_t nsteps) {
        *    each sub-step */
       for (int sub = 0; sub < s->n; ++sub) {
         const double t = (double)k + (double)(sub + 1) / (double)s->n;
-        const real uw = s->A * s->omega * RCOS(s->omega * t);
+        /* coupled motion: the lamina keeps the velocity of t_k over the step */
+        const real uw = s->fsi ? s->v_cur : s->A * s->omega * RCOS(s->omega * t);
         for (int p = 0; p < N; ++p) {
           s->uwx[p] = 0.0;
           s->uwy[p] = uw;
@@ -1114,6 +1121,23 @@ int or_step(or_sim *s, int64_t nsteps) {
       s->hist[2 * s->hist_n + 1] = F[1];
       s->hist_n++;
       if (!isfinite(RE(F[0])) || !isfinite(RE(F[1]))) return OR_E_UNSTABLE;
+#ifndef OR_COMPLEX_STEP
+      if (s->fsi) {
+        /* the body's equation of motion, semi-implicit Euler with Delta t = 1:
+         * the force at t_{k+1} and the state at t_k give v_{k+1}, then
+         * y_{k+1} = y_k + v_{k+1} */
+        const double acc = (F[1] - s->Ks * s->y_cur - s->Cd * s->v_cur) / s->M;
+        const double v1 = s->v_cur + acc;
+        const double y1 = s->y_cur + v1;
+        if (!(fabs(y1) <= s->y_max) || !(fabs(v1) < 1.0)) return OR_E_UNSTABLE;
+        yk1 = y1;
+        s->y_prev = s->y_cur;
+        s->y_cur = y1;
+        s->v_cur = v1;
+        s->mhist[2 * s->hist_n] = y1;
+        s->mhist[2 * s->hist_n + 1] = v1;
+      }
+#endif
       /* 6. move the grid to y_{k+1} and refill it */
       refill(s, yk, yk1);
     }
@@ -1149,7 +1173,7 @@ int or_info_get(const or_sim *s, or_info *o) {
   o->beta_limit_ok = (o->eps > 0.0) ? (s->beta < 2.6 * pow(o->eps, -1.6)) : 1;
   o->n_sub = s->n;
   o->step = s->k;
-  o->y = RE(motion_y(s, s->k));
+  o->y = s->fsi ? s->y_cur : RE(motion_y(s, s->k));
   o->n_type1 = s->nt1;
   o->n_type2 = s->nt2;
   o->n_type3 = s->nt3;
@@ -1186,6 +1210,40 @@ int or_set_mesh(or_sim *s, const double *in) {
   memcpy(s->fu, in, (size_t)9 * s->m->nnode * sizeof(double));
   return OR_OK;
 }
+/* Two-way coupled motion instead of the prescribed one (before the first
+ * step; a grid with the lamina): the lamina, of mass M per unit depth on a
+ * spring K and damper C, moves under the y-force of the fluid. The state
+ * starts at (y0, v0); |y| may not exceed y_max, which the geometric checks
+ * of or_create take in place of the amplitude A. */
+int or_set_motion(or_sim *s, double M, double K, double C, double y0, double v0, double y_max) {
+  if (!s || !s->m || !(s->body_b > 0.0) || s->k != 0) return OR_E_STATE;
+  if (!(M > 0.0) || !(K >= 0.0) || !(C >= 0.0) || !(y_max > 0.0) || !(fabs(y0) <= y_max) || !(fabs(v0) < 1.0))
+    return OR_E_ARG;
+  const double hy = 0.5 * (double)(s->nuy - 1) * s->h;
+  if (s->bc != OR_BC_PERIODIC && (s->yc - hy - y_max < 1.0 || s->yc + hy + y_max > (double)s->ny - 2.0))
+    return OR_E_ARG;
+  double *mh = calloc((size_t)2 * (s->hist_cap + 1), sizeof(double));
+  if (!mh) return OR_E_NOMEM;
+  free(s->mhist);
+  s->mhist = mh;
+  s->fsi = 1;
+  s->M = M;
+  s->Ks = K;
+  s->Cd = C;
+  s->y_max = y_max;
+  s->y_cur = s->y_prev = y0;
+  s->v_cur = v0;
+  return OR_OK;
+}
+
+/* (y, v) after each step: entry k at t = k+1; returns the count */
+int64_t or_motion_history(const or_sim *s, double *out, int64_t cap) {
+  if (!s->fsi) return 0;
+  const int64_t n = s->hist_n < cap ? s->hist_n : cap;
+  if (out) memcpy(out, s->mhist, (size_t)2 * n * sizeof(double));
+  return s->hist_n;
+}
+
 int64_t or_history(const or_sim *s, double *out, int64_t cap) {
   const int64_t n = s->hist_n < cap ? s->hist_n : cap;
   if (out) memcpy(out, s->hist, (size_t)2 * n * sizeof(double));

@@ -134,6 +134,11 @@ int or_get_mesh(const or_sim *s, double *out);
 int or_set_mesh(or_sim *s, const double *in);
 /* force history: entry k holds (Fx, Fy) at t = k+1; returns count */
 int64_t or_history(const or_sim *s, double *out, int64_t cap);
+/* two-way coupled motion (before the first step): M y'' + C y' + K y = F_y
+ * per unit depth, from (y0, v0), |y| <= y_max (see hlbm_oracle.c) */
+int or_set_motion(or_sim *s, double M, double K, double C, double y0, double v0, double y_max);
+/* (y, v) after each step of a coupled run: entry k at t = k+1 */
+int64_t or_motion_history(const or_sim *s, double *out, int64_t cap);
 /* status of lattice node (x,y) at step k: 0 disc, 1 interpolation, 2 unused */
 int32_t or_lattice_status(const or_sim *s, int64_t k, int32_t x, int32_t y);
 

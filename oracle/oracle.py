@@ -110,6 +110,9 @@ def lib():
         L.or_lattice_status.restype = C.c_int32
         L.or_fit_theta.argtypes = [_D, C.c_int64, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_double, _D]
+        L.or_set_motion.argtypes = [vp] + [C.c_double] * 6
+        L.or_motion_history.argtypes = [vp, _D, C.c_int64]
+        L.or_motion_history.restype = C.c_int64
         L.or_ml_create.argtypes = [C.POINTER(Config), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                    C.c_double, C.c_double, _I, C.c_int32, C.POINTER(vp)]
         L.or_ml_destroy.argtypes = [vp]
@@ -310,6 +313,18 @@ class Sim:
         n = lib().or_history(self.ptr, np.zeros(2), 0)
         out = np.zeros((max(n, 1), 2))
         lib().or_history(self.ptr, out, n)
+        return out[:n]
+
+    def set_motion(self, mass, stiffness, damping=0.0, y0=0.0, v0=0.0, y_max=1.0):
+        """Two-way coupled motion M y'' + C y' + K y = F_y (before the first step)."""
+        rc = lib().or_set_motion(self.ptr, mass, stiffness, damping, y0, v0, y_max)
+        if rc != 0:
+            raise ValueError(f"or_set_motion rejected the arguments (code {rc})")
+
+    def motion_history(self):
+        n = lib().or_motion_history(self.ptr, np.zeros(2), 0)
+        out = np.zeros((max(n, 1), 2))
+        lib().or_motion_history(self.ptr, out, n)
         return out[:n]
 
     def status(self, k):
