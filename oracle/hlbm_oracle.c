@@ -1134,8 +1134,8 @@ int or_step(or_sim *s, int64_t nsteps) {
         s->y_prev = s->y_cur;
         s->y_cur = y1;
         s->v_cur = v1;
-        s->mhist[2 * s->hist_n] = y1;
-        s->mhist[2 * s->hist_n + 1] = v1;
+        s->mhist[2 * (s->hist_n - 1)] = y1; /* the entry of this step's force */
+        s->mhist[2 * (s->hist_n - 1) + 1] = v1;
       }
 #endif
       /* 6. move the grid to y_{k+1} and refill it */
