@@ -74,6 +74,9 @@ extern "C" {
                                     at t_0) from the last hlbm_adjoint       */
 #define HLBM_STATE_ADJ_GRID 3    /* get only, double [9][nux*nuy]: dJ/d(grid at
                                     t_0) from the last hlbm_adjoint          */
+#define HLBM_STATE_MOTION 4      /* get only, double [steps][2]: (y, v) of a
+                                    coupled lamina after each step, entry k
+                                    at t = k+1 (hlbm_set_motion)              */
 #define HLBM_STATE_LEVEL 16      /* + l: double [9][ny_l][nx_l], post-collision f
                                     of refinement level l of a multi-level
                                     handle (l = nlevels-1 is the finest, also
@@ -220,6 +223,36 @@ int hlbm_create_multilevel(const hlbm_config *fine, const hlbm_levels *levels,
  * HLBM_E_STATE on another handle, HLBM_E_ARG for a level out of range. */
 int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny,
                      double *tau);
+
+/* ---- two-way coupled motion ------------------------------------------- */
+/* The paper prescribes the lamina's motion (Sec. Problem statement: known a
+ * priori). Instead, the lamina may be mounted on a spring and damper and
+ * moved by the fluid: M y'' + C y' + K y = F_y per unit depth, F_y the
+ * wall force of each step. Advanced once per step by semi-implicit Euler
+ * with Delta t = 1 (v_{k+1} = v_k + (F_y(t_{k+1}) - K y_k - C v_k)/M, then
+ * y_{k+1} = y_k + v_{k+1}); during the sub-steps of step k the wall moves
+ * with v_k. On the device: the force kernel updates the state and writes
+ * the next step's offset, fictitious rectangle and wall velocities. */
+typedef struct hlbm_motion {
+  double mass;      /* M > 0, per unit depth (lattice units, rho0 = 1)    */
+  double stiffness; /* K >= 0                                            */
+  double damping;   /* C >= 0                                            */
+  double y0, v0;    /* state at t_0: |y0| <= y_max, |v0| < 1             */
+  double y_max;     /* bound on |y|: the grid and its lattice donors must
+                       stay inside the lattice for every |y| <= y_max (the
+                       checks of hlbm_create with y_max for |A|); a state
+                       beyond it, or |v| >= 1, stops the case:
+                       HLBM_E_UNSTABLE                                    */
+} hlbm_motion;
+
+/* Switch a single case with a lamina to coupled motion, before its first
+ * step (kc and beta then play no part). hlbm_force keeps fitting Theta
+ * only where the caller's omega applies; the motion is read with
+ * hlbm_get_state(HLBM_STATE_MOTION). Errors: HLBM_E_STATE (steps already
+ * taken, no lamina), HLBM_E_ARG (invalid parameters or bound),
+ * HLBM_E_UNSUPPORTED (a batch or multi-level handle). hlbm_adjoint of a
+ * coupled case returns HLBM_E_UNSUPPORTED. */
+int hlbm_set_motion(hlbm_t *h, int32_t case_id, const hlbm_motion *m);
 
 /* Advance nsteps structured steps t_k -> t_{k+1} (Sec. HLBM and Sec. Refill
  * procedure): lattice interpolation nodes from the grid (Eq.

@@ -73,6 +73,12 @@ class CaseBase {
   virtual int adjoint(const double *dJ, int64_t n, double grad[3]) = 0;
   // case `id` of a handle (the handle itself for a single case)
   virtual CaseBase *sub(int id) { return id == 0 ? this : nullptr; }
+  virtual int set_motion(int case_id, const hlbm_motion *m) {
+    (void)case_id;
+    (void)m;
+    err = "coupled motion applies to single cases";
+    return HLBM_E_UNSUPPORTED;
+  }
   virtual int tune(int trial_steps, hlbm_tuning *t) {
     (void)trial_steps;
     (void)t;
@@ -271,9 +277,16 @@ class Case final : public CaseBase {
       cur = 1 - cur;
     }
     if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][4], s_grid_));
-    Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
-    if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][5], s_grid_));
-    Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_);
+    if (fsi_) {
+      // coupled motion: the force gives y_{k+1}, which the refill needs
+      Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_, 0);
+      Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
+      Kernels<T, R>::advance_step(v, s_grid_);
+    } else {
+      Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
+      if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][5], s_grid_));
+      Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_);
+    }
     if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][6], s_grid_));
     gcur_ = 1 - cur;
     return e;
@@ -449,6 +462,12 @@ class Case final : public CaseBase {
       for (size_t i = 0; i < n; ++i) out[i] = (double)tmp[i];
       return HLBM_OK;
     }
+    if (which == HLBM_STATE_MOTION) {
+      if (!fsi_) return fail(HLBM_E_STATE, "case has prescribed motion");
+      if (bytes != 2 * (size_t)k_ * sizeof(double)) return fail(HLBM_E_ARG, "motion state size mismatch");
+      if (k_ > 0) HIPCHK(hipMemcpy(buf, mstate_ + 2, bytes, hipMemcpyDeviceToHost));
+      return HLBM_OK;
+    }
     if (which == HLBM_STATE_ADJ_LATTICE || which == HLBM_STATE_ADJ_GRID) {
       if (!adj_done_) return fail(HLBM_E_STATE, "no adjoint has been run");
       const bool lat = which == HLBM_STATE_ADJ_LATTICE;
@@ -546,6 +565,10 @@ class Case final : public CaseBase {
     o->n_sub = d_.n;
     o->step = k_;
     o->y = d_.A * std::sin(d_.omega * (double)k_);
+    if (fsi_) {
+      HIPCHK(hipStreamSynchronize(s_main_));
+      HIPCHK(hipMemcpy(&o->y, mstate_ + 2 * k_, sizeof(double), hipMemcpyDeviceToHost));
+    }
     o->lattice_bytes = (int64_t)(9 * plane_ * sizeof(T));
     o->two_step = two_step_ ? 1 : 0;
     {
@@ -613,6 +636,42 @@ class Case final : public CaseBase {
     }
     if (on < 0 || on > 2) return fail(HLBM_E_ARG, "timing level must be 0, 1 or 2");
     timing_ = on;
+    return HLBM_OK;
+  }
+
+  int set_motion(int case_id, const hlbm_motion *m) override {
+    if (case_id != 0) return fail(HLBM_E_ARG, "case_id must be 0");
+    if (!m) return fail(HLBM_E_ARG, "null argument");
+    if (k_ != 0) return fail(HLBM_E_STATE, "coupled motion must be set before the first step");
+    if (!has_grid_ || !body_) return fail(HLBM_E_STATE, "coupled motion needs a grid with the lamina");
+    if (!(m->mass > 0.0) || !(m->stiffness >= 0.0) || !(m->damping >= 0.0) || !(m->y_max > 0.0) ||
+        !(std::fabs(m->y0) <= m->y_max) || !(std::fabs(m->v0) < 1.0))
+      return fail(HLBM_E_ARG, "invalid coupled-motion parameters");
+    const double hy = 0.5 * (double)(cfg_.nuy - 1) * h_;
+    if (cfg_.bc != HLBM_BC_PERIODIC &&
+        (d_.yc - hy - m->y_max < 1.0 || d_.yc + hy + m->y_max > (double)cfg_.ny - 2.0))
+      return fail(HLBM_E_ARG, "grid motion up to y_max leaves the lattice in y");
+    HIPCHK(hipStreamSynchronize(s_main_));
+    const int64_t cap = std::max<int64_t>(cfg_.max_steps, 1);
+    if (!mstate_) HIPCHK(alloc(&mstate_, 2 * (size_t)(cap + 1) * sizeof(double)));
+    std::vector<double> st(2 * (size_t)(cap + 1), 0.0);
+    st[0] = m->y0;
+    st[1] = m->v0;
+    HIPCHK(hipMemcpy(mstate_, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice));
+    mot_ = *m;
+    fsi_ = true;
+    // step 0 at y0 (the previous offset is the current one at k = 0); later
+    // steps are written by the device
+    StepParams P0 = params_at(0);
+    P_host_[0] = P0;
+    HIPCHK(hipMemcpy(params_, &P0, sizeof(StepParams), hipMemcpyHostToDevice));
+    std::vector<R> uw0(d_.n, (R)m->v0);
+    HIPCHK(hipMemcpy(uw_, uw0.data(), uw0.size() * sizeof(R), hipMemcpyHostToDevice));
+    // interpolation rows: the rectangle and its position one step earlier
+    k2_h_ = P0.iy1 - P0.iy0 + 1 + 3;
+    // the two-step band must cover every rectangle |y| <= y_max reaches
+    if (two_step_ && !choose_band()) two_step_ = false;
+    drop_graphs();
     return HLBM_OK;
   }
 
@@ -722,6 +781,7 @@ class Case final : public CaseBase {
     if (!has_grid_) return fail(HLBM_E_STATE, "case has no grid, so no force to differentiate");
     if (ckW_ <= 0) return fail(HLBM_E_STATE, "case was created with ckpt_every = 0");
     if (!ck_valid_) return fail(HLBM_E_STATE, "state was replaced after step 0; the checkpoints no longer hold");
+    if (fsi_) return fail(HLBM_E_UNSUPPORTED, "adjoint of a case with coupled motion");
     if (n != k_ || n <= 0) return fail(HLBM_E_ARG, "the cotangent must cover every step taken (n = steps)");
     HIPCHK(hipStreamSynchronize(s_main_));
     int rc = adjoint_setup();
@@ -841,7 +901,10 @@ class Case final : public CaseBase {
     return code;
   }
 
-  double motion(int64_t k) const { return d_.A * std::sin(d_.omega * (double)k); }
+  double motion(int64_t k) const {
+    if (fsi_) return k == 0 ? mot_.y0 : 0.0;  // coupled: only t_0 is known on the host
+    return d_.A * std::sin(d_.omega * (double)k);
+  }
 
   // Fictitious rectangle: the grid's node bounding box at offset y, inset by
   // two lattice units; lattice node (i, j) is inside when the closed
@@ -874,6 +937,14 @@ class Case final : public CaseBase {
       x1 = std::max({x1, P.ix1, P.pix1});
       y0 = std::min({y0, P.iy0, P.piy0});
       y1 = std::max({y1, P.iy1, P.piy1});
+    }
+    if (fsi_) {  // every offset |y| <= y_max
+      for (double y : {-mot_.y_max, mot_.y_max}) {
+        int a, b, c, d;
+        rect(y, a, b, c, d);
+        y0 = std::min(y0, c);
+        y1 = std::max(y1, d);
+      }
     }
     x0 -= kBand;
     x1 += kBand;
@@ -915,6 +986,19 @@ class Case final : public CaseBase {
     v.bx1 = band_[1];
     v.by0 = band_[2];
     v.by1 = band_[3];
+    if (fsi_) {
+      v.mot.on = 1;
+      v.mot.M = mot_.mass;
+      v.mot.K = mot_.stiffness;
+      v.mot.C = mot_.damping;
+      v.mot.y_max = mot_.y_max;
+      v.mot.yc = d_.yc;
+      v.mot.c0 = (0.0 - 0.5 * (double)(cfg_.nuy - 1)) * h_;
+      v.mot.c1 = ((double)(cfg_.nuy - 1) - 0.5 * (double)(cfg_.nuy - 1)) * h_;
+      v.mot.margin = kMargin;
+      v.mot.state = mstate_;
+      v.mot.cap = cfg_.max_steps;
+    }
     v.bc = cfg_.bc;
     v.inv_tau = (R)(1.0 / cfg_.tau);
     v.g_post = (R)(2.0 * (cfg_.tau - 1.0) / (2.0 * cfg_.tau - 1.0));
@@ -1365,6 +1449,9 @@ class Case final : public CaseBase {
   void *lat_[3] = {nullptr, nullptr, nullptr};  // state at t_k, free, free (two-step path)
   void *phys_[3] = {nullptr, nullptr, nullptr};  // the physical buffers
   bool two_step_ = false;
+  bool fsi_ = false;  // two-way coupled motion (hlbm_set_motion)
+  hlbm_motion mot_{};
+  double *mstate_ = nullptr;  // [max_steps + 1][2] (y, v) on the device
   int band_[4] = {-10, -20, -10, -20};  // x0, x1, y0, y1 of the band (inclusive; empty, far outside)
   void *after_graph_[18][3] = {};
   int after_gcur_[18] = {};
@@ -2304,6 +2391,11 @@ int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny, double 
   *ny = b;
   *tau = t;
   return HLBM_OK;
+}
+
+int hlbm_set_motion(hlbm_t *h, int32_t case_id, const hlbm_motion *m) {
+  if (!h) return HLBM_E_ARG;
+  return h->c->set_motion(case_id, m);
 }
 
 int hlbm_step(hlbm_t *h, int64_t nsteps) {

@@ -5,6 +5,18 @@
 
 namespace mghlbm {
 
+// Two-way coupled motion of the lamina: M y'' + C y' + K y = F_y per unit
+// depth, advanced by the force kernel, which also fills the next step's
+// scalars (the rectangle rows as the host computes them: ceil((yc + y) + c0
+// + margin), floor((yc + y) + c1 - margin)) and wall velocities.
+struct MotionCtx {
+  int on;
+  double M, K, C, y_max;
+  double yc, c0, c1, margin;
+  double *state;  // [max_steps + 1][2]: (y, v) at t_k
+  int64_t cap;    // max_steps
+};
+
 // Everything a kernel of one case needs, by value. Pointers are device
 // pointers; the lattice pointers are swapped by the host between steps.
 template <class T, class R>
@@ -29,6 +41,7 @@ struct CaseView {
   // node around it
   T *C;
   int bx0, bx1, by0, by1;
+  MotionCtx mot;
   R inv_tau;       // 1 / tau_s
   R g_post;        // 2 (tau_s - 1) / (2 tau_s - 1), Eq.(postcollision2_s)
   R k_neq;         // 1 - 1/(2 tau_s), Eq.(continuity_stresses)
@@ -130,7 +143,10 @@ struct Kernels {
   static void grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
                               R *tape, R *wtape, const int *widx, int nwall);
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
-  static void force(const CaseView<T, R> &v, const R *f, hipStream_t s);
+  // advance = 0: leave the step counter (a coupled-motion step then runs the
+  // refill and advance_step after it)
+  static void force(const CaseView<T, R> &v, const R *f, hipStream_t s, int advance = 1);
+  static void advance_step(const CaseView<T, R> &v, hipStream_t s);
   // between a lattice buffer (plane stride) and a packed [9][nodes] FP64 array
   static void lattice_to_f64(const T *src, double *dst, size_t plane, size_t nodes, hipStream_t s);
   // one launch of a case-batched step over a work list of int4 items

@@ -646,7 +646,9 @@ __global__ __launch_bounds__(256) void kb_refill(const CaseView<T, R> *__restric
 // shuffle reduction and one LDS pass across the four waves.
 template <class R>
 __device__ __forceinline__ void force_block(const R *__restrict__ f, const WallEdge *__restrict__ wall,
-                                            int n_wall_edges, int nnode, int64_t *dk, double *hist, int *flag) {
+                                            int n_wall_edges, int nnode, int64_t *dk, double *hist, int *flag,
+                                            const MotionCtx &mot = MotionCtx{}, StepParams *P = nullptr,
+                                            R *uw = nullptr, int n_sub = 0, int advance = 1) {
   __shared__ double red[2][4];
   double Fx = 0.0, Fy = 0.0;
   for (int e = threadIdx.x; e < n_wall_edges; e += blockDim.x) {
@@ -696,14 +698,53 @@ __device__ __forceinline__ void force_block(const R *__restrict__ f, const WallE
     hist[2 * k] = sx;
     hist[2 * k + 1] = sy;
     if (!isfinite(sx) || !isfinite(sy)) *flag = 1;
-    *dk = k + 1;
+    if (mot.on) {
+      // semi-implicit Euler, Delta t = 1: v_{k+1} from the force at t_{k+1},
+      // then y_{k+1} = y_k + v_{k+1}; a state leaving |y| <= y_max or
+      // |v| < 1 stops the case (flag) and the motion is frozen, so every
+      // table stays inside the bounds the lattice was checked for
+      const double y = mot.state[2 * k], vel = mot.state[2 * k + 1];
+      const double acc = (sy - mot.K * y - mot.C * vel) / mot.M;
+      double v1 = vel + acc, y1 = y + v1;
+      if (!(fabs(y1) <= mot.y_max) || !(fabs(v1) < 1.0)) {
+        *flag = 1;
+        y1 = y;
+        v1 = 0.0;
+      }
+      mot.state[2 * (k + 1)] = y1;
+      mot.state[2 * (k + 1) + 1] = v1;
+      StepParams &Pk = P[k];
+      Pk.y1 = y1;
+      Pk.ybase1 = mot.yc + y1;
+      if (k + 1 <= mot.cap) {
+        StepParams &Pn = P[k + 1];
+        Pn.y = y1;
+        Pn.ybase = mot.yc + y1;
+        Pn.ix0 = Pk.ix0;
+        Pn.ix1 = Pk.ix1;
+        Pn.iy0 = (int)ceil(((mot.yc + y1) + mot.c0) + mot.margin);
+        Pn.iy1 = (int)floor(((mot.yc + y1) + mot.c1) - mot.margin);
+        Pn.pix0 = Pk.ix0;
+        Pn.pix1 = Pk.ix1;
+        Pn.piy0 = Pk.iy0;
+        Pn.piy1 = Pk.iy1;
+      }
+      if (k + 1 < mot.cap)
+        for (int m = 0; m < n_sub; ++m) uw[(k + 1) * n_sub + m] = (R)v1;
+    }
+    if (advance) *dk = k + 1;
   }
+}
+
+__global__ void k_advance_step(int64_t *dk) {
+  if (threadIdx.x == 0) *dk = *dk + 1;
 }
 
 template <class R>
 __global__ __launch_bounds__(256) void k_force(const R *__restrict__ f, const WallEdge *__restrict__ wall,
-                                               int n_wall_edges, int nnode, int64_t *dk, double *hist, int *flag) {
-  force_block<R>(f, wall, n_wall_edges, nnode, dk, hist, flag);
+                                               int n_wall_edges, int nnode, int64_t *dk, double *hist, int *flag,
+                                               MotionCtx mot, StepParams *P, R *uw, int n_sub, int advance) {
+  force_block<R>(f, wall, n_wall_edges, nnode, dk, hist, flag, mot, P, uw, n_sub, advance);
 }
 
 // one workgroup per case: item = (case)
@@ -997,9 +1038,14 @@ void Kernels<T, R>::refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipS
 }
 
 template <class T, class R>
-void Kernels<T, R>::force(const CaseView<T, R> &v, const R *f, hipStream_t s) {
+void Kernels<T, R>::force(const CaseView<T, R> &v, const R *f, hipStream_t s, int advance) {
   hipLaunchKernelGGL((k_force<R>), dim3(1), dim3(256), 0, s, f, v.wall, v.n_wall_edges, v.nnode, v.dk, v.hist,
-                     v.flag);
+                     v.flag, v.mot, const_cast<StepParams *>(v.params), const_cast<R *>(v.uw), v.n_sub, advance);
+}
+
+template <class T, class R>
+void Kernels<T, R>::advance_step(const CaseView<T, R> &v, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(64), 0, s, v.dk);
 }
 
 template <class T, class R>

@@ -18,6 +18,7 @@ BC_PERIODIC_X_WALLS_Y, BC_PERIODIC, BC_PAPER, BC_RING = 0, 1, 2, 3
 FP64, FP32, FP16_DEV = 0, 1, 2
 FLAG_NO_BODY = 1
 STATE_LATTICE, STATE_GRID, STATE_ADJ_LATTICE, STATE_ADJ_GRID = 0, 1, 2, 3
+STATE_MOTION = 4
 STATE_LEVEL = 16
 MAX_LEVELS = 8
 (K_STREAM_COLLIDE, K_LATTICE_FROM_GRID, K_GRID_SUBSTEPS, K_REFILL, K_FORCE, K_STEP,
@@ -27,7 +28,7 @@ STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV}
 EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_state",
            "hlbm_set_state", "hlbm_info_get", "hlbm_get_stencil", "hlbm_timing",
            "hlbm_timing_get", "hlbm_tune", "hlbm_destroy", "hlbm_last_error",
-           "hlbm_create_multilevel", "hlbm_level_shape")
+           "hlbm_create_multilevel", "hlbm_level_shape", "hlbm_set_motion")
 STATUS_RUNNING, STATUS_DONE, STATUS_UNSTABLE = 0, 1, 2
 
 
@@ -66,6 +67,10 @@ class Tuning(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Motion(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("mass", "stiffness", "damping", "y0", "v0", "y_max")]
+
+
 class Levels(C.Structure):
     _fields_ = [("nlevels", C.c_int32), ("nx0", C.c_int32), ("ny0", C.c_int32), ("bc0", C.c_int32),
                 ("box", (C.c_int32 * 4) * (MAX_LEVELS - 1))]
@@ -97,6 +102,7 @@ def load(path: str = LIB_PATH):
     L.hlbm_tune.argtypes = [vp, i32, C.POINTER(Tuning)]
     L.hlbm_create_multilevel.argtypes = [C.POINTER(Config), C.POINTER(Levels), C.POINTER(vp)]
     L.hlbm_level_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), dp]
+    L.hlbm_set_motion.argtypes = [vp, i32, C.POINTER(Motion)]
     L.hlbm_destroy.argtypes = [vp]
     L.hlbm_destroy.restype = None
     L.hlbm_last_error.argtypes = [vp]
@@ -220,6 +226,18 @@ class Case:
         dJ = np.ascontiguousarray(dJ_dF, dtype=np.float64).reshape(-1, 2)
         self._check(load().hlbm_adjoint(self.h, 0, _ptr(dJ), dJ.shape[0], _ptr(g)))
         return g
+
+    def set_motion(self, mass, stiffness, damping=0.0, y0=0.0, v0=0.0, y_max=1.0):
+        """Two-way coupled motion M y'' + C y' + K y = F_y (before the first step)."""
+        m = Motion(mass, stiffness, damping, y0, v0, y_max)
+        self._check(load().hlbm_set_motion(self.h, 0, C.byref(m)))
+
+    def motion_history(self):
+        """(y, v) after each step of a coupled case, entry k at t = k+1."""
+        n = self.info().step
+        out = np.zeros((n, 2))
+        self._check(load().hlbm_get_state(self.h, 0, STATE_MOTION, out.ctypes.data, out.nbytes))
+        return out
 
     def adjoint_lattice(self):
         """dJ/d(lattice at t_0) from the last adjoint."""

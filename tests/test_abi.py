@@ -135,3 +135,14 @@ def test_multilevel_finest_shape_and_bc_checked_on_host():
     for n in (1, 9):
         lv.nlevels = n
         assert L.hlbm_create_multilevel(C.byref(cfg), C.byref(lv), C.byref(h)) == hlbm.E_ARG
+
+
+def test_motion_struct_layout(tmp_path):
+    src = tmp_path / "motion.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hlbm.h"\n'
+                   'int main(void){printf("%zu %zu %d\\n", sizeof(hlbm_motion), offsetof(hlbm_motion, y_max),'
+                   ' HLBM_STATE_MOTION); return 0;}\n')
+    exe = tmp_path / "motion"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    a, b, c = map(int, subprocess.check_output([str(exe)]).split())
+    assert a == C.sizeof(hlbm.Motion) and b == hlbm.Motion.y_max.offset and c == hlbm.STATE_MOTION
