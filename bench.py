@@ -459,6 +459,54 @@ def levels_theta_leg(b=256, nlevels=4, eps=0.1, beta=20.0, tau=0.8, storage="f64
             "theta_semianalytical": [ts.real, ts.imag]}
 
 
+def coupled_leg(workload="lamina_2048", storage="f64", periods=2.5, mass_ratio=1.0, chunk=1000):
+    """The workload's lattice and grid with the lamina elastically mounted
+    instead of driven: released from y0 = b/16, spring set so that the
+    undamped period in vacuum is the workload's forcing period, mass
+    mass_ratio times (pi/4) rho b^2. Lattice MLUPS of the coupled steps
+    (the same kernels plus the motion update) beside the prescribed-motion
+    run of the main line, and the free decay: mean half period and
+    amplitude ratio per half period over the first swings."""
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.workloads import preset
+    cfg = preset(workload)
+    cfg.pop("steps")
+    cfg.pop("ckpt_every", None)
+    b = cfg["b"]
+    nu = (cfg["tau"] - 0.5) / 3.0
+    omega = 2 * math.pi * nu * cfg["beta"] / (b * b)
+    period = 2 * math.pi / omega
+    steps = int(periods * period)
+    M = mass_ratio * math.pi / 4 * b * b
+    K = M * omega * omega
+    A = cfg["kc"] * b / (2 * math.pi)
+    case = H.Case(storage=H.STORAGE[storage], max_steps=steps, **cfg)
+    case.set_motion(M, K, 0.0, y0=b / 16, v0=0.0, y_max=max(abs(A), b / 8))
+    sched = case.tune(trial_steps=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        case.step(n)
+        done += n
+        print(f"# coupled {done}/{steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    y = case.motion_history()[:, 0]
+    case.close()
+    zc = np.where(np.diff(np.sign(y)) != 0)[0]
+    halves = np.diff(zc[:6]) if len(zc) > 2 else np.array([])
+    peaks = [float(np.abs(y[zc[i]:zc[i + 1]]).max()) for i in range(min(len(zc) - 1, 5))]
+    ratios = [peaks[i + 1] / peaks[i] for i in range(len(peaks) - 1)]
+    return {"workload": workload + "_coupled", "storage": storage, "steps": steps,
+            "mass": M, "stiffness": K, "y0": b / 16, "vacuum_period_steps": round(period, 1),
+            "mlups": round(cfg["nx"] * cfg["ny"] * steps / dt / 1e6, 1), "ms_per_step": round(1e3 * dt / steps, 4),
+            "half_periods": [int(h) for h in halves], "peak_ratios": [round(r, 4) for r in ratios],
+            "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}}
+
+
 def storage_leg(workload, storage, steps, warmup, timing_steps):
     """The same workload at another storage precision: lattice MLUPS over
     graph-replayed steps, the stream-collide's mean duration (its own events)
@@ -532,6 +580,9 @@ def main():
     ap.add_argument("--levels-storage", default="f64", choices=list(BYTES))
     ap.add_argument("--levels-steps", type=int, default=40)
     ap.add_argument("--levels-no-uniform", action="store_true")
+    ap.add_argument("--coupled", action="store_true",
+                    help="run only the main workload with the lamina elastically mounted (two-way coupled) and "
+                         "print its line")
     ap.add_argument("--levels-theta", action="store_true",
                     help="run only Theta on 4 refinement levels (L = 256 at the finest) against a uniform "
                          "finest lattice over the same domain and print its line")
@@ -547,6 +598,10 @@ def main():
     if args.sweep:
         torch.cuda.set_device(0)
         print(json.dumps(sweep_leg(periods=args.sweep_periods, loop=not args.sweep_no_loop)), flush=True)
+        return
+    if args.coupled:
+        torch.cuda.set_device(0)
+        print(json.dumps(coupled_leg(args.workload, args.storage)), flush=True)
         return
     if args.levels_theta:
         torch.cuda.set_device(0)
