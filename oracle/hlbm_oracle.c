@@ -605,6 +605,56 @@ or_mesh *or_mesh_lamina(int32_t nux, int32_t nuy, double h, double b) {
   return mesh_finish(m);
 }
 
+/* The same grid with graded spacing: column i at local x = X[i], row j at
+ * local y = Y[j] (both strictly increasing); each cell is cut along the
+ * diagonal of its side of the centre (the rising one for cells with
+ * 2 ci + 1 < nux, as in the uniform grid), the lamina slot is the cells of
+ * row nuy/2-1 inside |x| <= b/2, and the lamina thickness is
+ * Y[nuy/2] - Y[nuy/2-1]. */
+or_mesh *or_mesh_lamina_coords(int32_t nux, int32_t nuy, const double *X, const double *Y, double b) {
+  if (nux < 4 || nuy < 4 || (nuy % 2) != 0 || !X || !Y || b < 0.0) return NULL;
+  for (int i = 0; i + 1 < nux; ++i)
+    if (!(X[i + 1] > X[i])) return NULL;
+  for (int j = 0; j + 1 < nuy; ++j)
+    if (!(Y[j + 1] > Y[j])) return NULL;
+  or_mesh *m = mesh_alloc(nux * nuy, 2 * (nux - 1) * (nuy - 1));
+  if (!m) return NULL;
+  const double T = Y[nuy / 2] - Y[nuy / 2 - 1];
+  m->b = b;
+  m->T = (b > 0.0) ? T : 0.0;
+  const double half = 0.5 * b + 1e-9 * T;
+  for (int j = 0; j < nuy; ++j)
+    for (int i = 0; i < nux; ++i) {
+      const int p = j * nux + i;
+      m->x[p] = X[i];
+      m->y[p] = Y[j];
+      if (b > 0.0 && (j == nuy / 2 - 1 || j == nuy / 2) && fabs(X[i]) <= half)
+        m->type[p] = OR_NODE_WALL;
+      else if (i == 0 || j == 0 || i == nux - 1 || j == nuy - 1)
+        m->type[p] = OR_NODE_INTERFACE;
+      else
+        m->type[p] = OR_NODE_INTERIOR;
+    }
+  int nt = 0;
+  for (int cj = 0; cj < nuy - 1; ++cj)
+    for (int ci = 0; ci < nux - 1; ++ci) {
+      if (b > 0.0 && cj == nuy / 2 - 1 && X[ci] >= -half && X[ci + 1] <= half) continue; /* inside the lamina */
+      const int n00 = cj * nux + ci, n10 = n00 + 1, n01 = n00 + nux, n11 = n01 + 1;
+      const double cx[4] = {X[ci], X[ci + 1], X[ci], X[ci + 1]}, cy[4] = {Y[cj], Y[cj], Y[cj + 1], Y[cj + 1]};
+      const int id[4] = {n00, n10, n01, n11};
+      static const int up[2][3] = {{0, 1, 3}, {0, 3, 2}}, down[2][3] = {{0, 1, 2}, {1, 3, 2}};
+      const int(*tr)[3] = (2 * ci + 1 < nux) ? up : down;
+      for (int t = 0; t < 2; ++t, ++nt)
+        for (int a = 0; a < 3; ++a) {
+          m->tri[3 * nt + a] = id[tr[t][a]];
+          m->txy[6 * nt + 2 * a] = cx[tr[t][a]];
+          m->txy[6 * nt + 2 * a + 1] = cy[tr[t][a]];
+        }
+    }
+  m->ntri = nt;
+  return mesh_finish(m);
+}
+
 or_mesh *or_mesh_periodic(int32_t nx, int32_t ny, double h) {
   if (nx < 3 || ny < 3 || !(h > 0.0)) return NULL;
   or_mesh *m = mesh_alloc(nx * ny, 2 * nx * ny);
@@ -787,6 +837,7 @@ struct or_sim {
   real *hist;
   int64_t hist_cap, hist_n;
   int64_t nt1, nt2, nt3;
+  double ex0, ex1, ey0, ey1; /* local extents of the grid's nodes */
   /* two-way coupled motion (or_set_motion): M y'' + C y' + K y = F_y */
   int fsi;
   double M, Ks, Cd, y_max;
@@ -804,10 +855,10 @@ typedef struct { double x0, x1, y0, y1; } rect_t;
 
 static rect_t rect_at(const or_sim *s, double y) {
   rect_t r;
-  r.x0 = s->xc + (double)(0 - s->nux / 2) * s->h + s->margin;
-  r.x1 = s->xc + (double)(s->nux - 1 - s->nux / 2) * s->h - s->margin;
-  r.y0 = s->yc + y + (0.0 - 0.5 * (double)(s->nuy - 1)) * s->h + s->margin;
-  r.y1 = s->yc + y + ((double)(s->nuy - 1) - 0.5 * (double)(s->nuy - 1)) * s->h - s->margin;
+  r.x0 = s->xc + s->ex0 + s->margin;
+  r.x1 = s->xc + s->ex1 - s->margin;
+  r.y0 = s->yc + y + s->ey0 + s->margin;
+  r.y1 = s->yc + y + s->ey1 - s->margin;
   return r;
 }
 
@@ -841,7 +892,8 @@ static void free_sim(or_sim *s) {
 
 void or_destroy(or_sim *s) { free_sim(s); }
 
-int or_create(const or_config *c, or_sim **out) {
+/* X, Y: columns and rows of a graded grid (or_create_graded), or NULL */
+static int create_sim(const or_config *c, const double *X, const double *Y, or_sim **out) {
   if (!c || !out) return OR_E_ARG;
   *out = NULL;
   if (c->nx < 3 || c->ny < 3 || !(c->tau > 0.5) || c->max_steps < 0) return OR_E_ARG;
@@ -904,18 +956,35 @@ int or_create(const or_config *c, or_sim **out) {
       s->fB[(size_t)i * c->nx * c->ny + p] = WT[i];
     }
   if (has_mesh) {
-    if (body && fabs(c->thickness - s->h) > 1e-12 * s->h) { free_sim(s); return OR_E_ARG; }
+    if (X && (c->nux < 4 || c->nuy < 4 || (c->nuy % 2) != 0)) { free_sim(s); return OR_E_ARG; }
+    if (X)
+      for (int j = 0; j < c->nuy; ++j)
+        if (Y[j] != -Y[c->nuy - 1 - j]) { free_sim(s); return OR_E_ARG; } /* rows symmetric about the lamina */
+    const double Tg = X ? Y[c->nuy / 2] - Y[c->nuy / 2 - 1] : s->h; /* thickness of the lamina slot */
+    if (body && fabs(c->thickness - Tg) > 1e-12 * Tg) { free_sim(s); return OR_E_ARG; }
     if (c->n_sub < 0) { free_sim(s); return OR_E_ARG; }
     /* explicit stability of the grid scheme, Delta t_u < 2 tau_u */
     if (!(s->dt_u < 2.0 * RE(s->tau_u))) { free_sim(s); return OR_E_ARG; }
-    s->m = or_mesh_lamina(c->nux, c->nuy, s->h, s->body_b);
+    if (X) {
+      s->m = or_mesh_lamina_coords(c->nux, c->nuy, X, Y, s->body_b);
+      s->ex0 = X[0];
+      s->ex1 = X[c->nux - 1];
+      s->ey0 = Y[0];
+      s->ey1 = Y[c->nuy - 1];
+    } else {
+      s->m = or_mesh_lamina(c->nux, c->nuy, s->h, s->body_b);
+      s->ex0 = (double)(0 - c->nux / 2) * s->h;
+      s->ex1 = (double)(c->nux - 1 - c->nux / 2) * s->h;
+      s->ey0 = (0.0 - 0.5 * (double)(c->nuy - 1)) * s->h;
+      s->ey1 = ((double)(c->nuy - 1) - 0.5 * (double)(c->nuy - 1)) * s->h;
+    }
     if (!s->m) { free_sim(s); return OR_E_ARG; }
     s->T = s->m->T;
     /* geometric requirements: the grid and the lattice donors of its outer
      * nodes stay inside the lattice; the fictitious rectangle holds the body
      * with a one-unit gap; a node moves less than one lattice unit per step */
-    const double hx = (double)(c->nux / 2) * s->h, hxr = (double)(c->nux - 1 - c->nux / 2) * s->h;
-    const double hy = 0.5 * (double)(c->nuy - 1) * s->h;
+    const double hx = -s->ex0, hxr = s->ex1;
+    const double hy = s->ey1;
     if (s->xc - hx < 1.0 || s->xc + hxr > (double)c->nx - 2.0) { free_sim(s); return OR_E_ARG; }
     if (c->bc != OR_BC_PERIODIC &&
         (s->yc - hy - fabs(RE(s->A)) < 1.0 || s->yc + hy + fabs(RE(s->A)) > (double)c->ny - 2.0)) {
@@ -923,7 +992,7 @@ int or_create(const or_config *c, or_sim **out) {
       return OR_E_ARG;
     }
     if (body && (0.5 * c->b + 1.0 > hx - s->margin - 1.0 || 0.5 * c->b + 1.0 > hxr - s->margin - 1.0 ||
-                       0.5 * s->h + 1.0 > hy - s->margin - 1.0)) {
+                       0.5 * Tg + 1.0 > hy - s->margin - 1.0)) {
       free_sim(s);
       return OR_E_ARG;
     }
@@ -944,6 +1013,16 @@ int or_create(const or_config *c, or_sim **out) {
   }
   *out = s;
   return OR_OK;
+}
+
+int or_create(const or_config *c, or_sim **out) { return create_sim(c, NULL, NULL, out); }
+
+/* A case whose grid has graded spacing: columns at local x = X[nux], rows at
+ * y = Y[nuy] (or_mesh_lamina_coords; rows symmetric about the lamina, whose
+ * thickness Y[nuy/2] - Y[nuy/2-1] must equal cfg->thickness; h_u unused). */
+int or_create_graded(const or_config *c, const double *X, const double *Y, or_sim **out) {
+  if (!X || !Y) return OR_E_ARG;
+  return create_sim(c, X, Y, out);
 }
 
 /* lattice populations arriving at node (x,y) at t_{k+1}: pulled from the
@@ -1219,8 +1298,7 @@ int or_set_motion(or_sim *s, double M, double K, double C, double y0, double v0,
   if (!s || !s->m || !(s->body_b > 0.0) || s->k != 0) return OR_E_STATE;
   if (!(M > 0.0) || !(K >= 0.0) || !(C >= 0.0) || !(y_max > 0.0) || !(fabs(y0) <= y_max) || !(fabs(v0) < 1.0))
     return OR_E_ARG;
-  const double hy = 0.5 * (double)(s->nuy - 1) * s->h;
-  if (s->bc != OR_BC_PERIODIC && (s->yc - hy - y_max < 1.0 || s->yc + hy + y_max > (double)s->ny - 2.0))
+  if (s->bc != OR_BC_PERIODIC && (s->yc + s->ey0 - y_max < 1.0 || s->yc + s->ey1 + y_max > (double)s->ny - 2.0))
     return OR_E_ARG;
   double *mh = calloc((size_t)2 * (s->hist_cap + 1), sizeof(double));
   if (!mh) return OR_E_NOMEM;

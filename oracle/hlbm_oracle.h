@@ -92,6 +92,9 @@ void or_lattice_step(const double *A, double *B, int32_t nx, int32_t ny,
 /* ---- finite-volume mesh, Eq.(ulbe) ----------------------------------- */
 /* lamina grid: nux*nuy nodes, spacing h, lamina slot of width b (0: none) */
 or_mesh *or_mesh_lamina(int32_t nux, int32_t nuy, double h, double b);
+/* the lamina grid with graded spacing: columns at local x = X[i], rows at
+ * y = Y[j] (strictly increasing), thickness Y[nuy/2] - Y[nuy/2-1] */
+or_mesh *or_mesh_lamina_coords(int32_t nux, int32_t nuy, const double *X, const double *Y, double b);
 /* doubly periodic nx*ny grid of spacing h, every node interior */
 or_mesh *or_mesh_periodic(int32_t nx, int32_t ny, double h);
 /* channel periodic in x, rows 0 and ny-1 are walls */
@@ -123,6 +126,9 @@ void or_mesh_force(const or_mesh *m, const double *f, double F[2]);
 
 /* ---- the hybrid method ----------------------------------------------- */
 int or_create(const or_config *cfg, or_sim **out);
+/* a case with a graded grid: columns at local x = X[nux], rows at y =
+ * Y[nuy] (rows symmetric about the lamina, thickness Y[nuy/2] - Y[nuy/2-1]) */
+int or_create_graded(const or_config *cfg, const double *X, const double *Y, or_sim **out);
 void or_destroy(or_sim *s);
 int or_step(or_sim *s, int64_t nsteps);
 int or_info_get(const or_sim *s, or_info *out);

@@ -111,6 +111,9 @@ def lib():
         L.or_fit_theta.argtypes = [_D, C.c_int64, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_double, _D]
         L.or_set_motion.argtypes = [vp] + [C.c_double] * 6
+        L.or_create_graded.argtypes = [C.POINTER(Config), _D, _D, C.POINTER(vp)]
+        L.or_mesh_lamina_coords.argtypes = [C.c_int32, C.c_int32, _D, _D, C.c_double]
+        L.or_mesh_lamina_coords.restype = vp
         L.or_motion_history.argtypes = [vp, _D, C.c_int64]
         L.or_motion_history.restype = C.c_int64
         L.or_ml_create.argtypes = [C.POINTER(Config), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -200,6 +203,12 @@ class Mesh:
         return cls(lib().or_mesh_lamina(nux, nuy, h, b))
 
     @classmethod
+    def lamina_coords(cls, X, Y, b=0.0):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        return cls(lib().or_mesh_lamina_coords(len(X), len(Y), X, Y, b))
+
+    @classmethod
     def periodic(cls, nx, ny, h=1.0):
         return cls(lib().or_mesh_periodic(nx, ny, h))
 
@@ -263,11 +272,19 @@ class Sim:
     """The hybrid method, advanced step by step on the CPU."""
 
     def __init__(self, nx, ny, nux=0, nuy=0, h_u=1.0, b=0.0, thickness=1.0, tau=0.8, kc=0.0,
-                 beta=0.0, n_sub=0, bc=BC_PERIODIC_X_WALLS_Y, flags=0, max_steps=0):
+                 beta=0.0, n_sub=0, bc=BC_PERIODIC_X_WALLS_Y, flags=0, max_steps=0, x_nodes=None,
+                 y_nodes=None):
         self.cfg = Config(nx, ny, nux, nuy, h_u, b, thickness, tau, kc, beta, n_sub, bc, flags,
                           max_steps)
         h = C.c_void_p()
-        rc = lib().or_create(C.byref(self.cfg), C.byref(h))
+        if x_nodes is not None or y_nodes is not None:  # graded grid
+            gx = np.ascontiguousarray(x_nodes, dtype=np.float64)
+            gy = np.ascontiguousarray(y_nodes, dtype=np.float64)
+            if gx.shape != (nux,) or gy.shape != (nuy,):
+                raise ValueError("x_nodes and y_nodes need nux and nuy entries")
+            rc = lib().or_create_graded(C.byref(self.cfg), gx, gy, C.byref(h))
+        else:
+            rc = lib().or_create(C.byref(self.cfg), C.byref(h))
         if rc != 0:
             raise ValueError(f"or_create rejected the configuration (code {rc})")
         self.ptr = h

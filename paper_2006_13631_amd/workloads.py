@@ -161,6 +161,28 @@ def paper_levels(b: int = 800, nlevels: int = 4, eps: float = 0.1, beta: float =
     return dict(nx0=n0, ny0=n0, bc0=2, boxes=boxes, fine=fine, finest=(nx, ny))
 
 
+def graded_nodes(n: int, h_min: float, ratio: float, h_max: float, fine: float = 0.0) -> np.ndarray:
+    """Node coordinates of a graded grid line centred at 0: spacing h_min
+    out to |x| = fine, then growing by `ratio` per cell up to h_max. Odd n:
+    a node sits at 0 (grid columns); even n: the two middle nodes sit at
+    +-h_min/2 (grid rows around the lamina, whose thickness is h_min).
+    Symmetric about 0."""
+    odd = n % 2 == 1
+    half = []
+    x = 0.0 if odd else 0.5 * h_min
+    h = h_min
+    m = n // 2 + (1 if odd else 0)
+    for _ in range(m):
+        half.append(x)
+        if x + 0.5 * h_min > fine:
+            h = min(h * ratio, h_max)
+        x += h
+    half = np.array(half)
+    if odd:
+        return np.concatenate([-half[:0:-1], half])
+    return np.concatenate([-half[::-1], half])
+
+
 def random_populations(shape, seed: int, base: np.ndarray, spread: float = 0.02) -> np.ndarray:
     """base * (1 + u), u uniform in [-spread, spread]; base broadcasts over the
     trailing axes of ``shape`` (first axis = population index)."""

@@ -17,7 +17,15 @@ assembly against closed forms computed here independently:
 import numpy as np
 import pytest
 
+from paper_2006_13631_amd.workloads import graded_nodes
+
+# graded lamina grids (spacing growing away from the lamina)
+GX = graded_nodes(15, 0.5, 1.4, 2.0, fine=2.0)
+GY = graded_nodes(10, 0.5, 1.5, 2.0)
+
 MESHES = [
+    ("graded", dict(X=GX, Y=GY, b=3.0)),
+    ("graded", dict(X=graded_nodes(11, 1.0, 1.3, 3.0), Y=graded_nodes(8, 1.0, 1.3, 3.0), b=0.0)),
     ("lamina", dict(nux=12, nuy=8, h=1.0, b=4.0)),
     ("lamina", dict(nux=13, nuy=10, h=0.5, b=3.0)),
     ("lamina", dict(nux=9, nuy=6, h=1.0, b=0.0)),
@@ -27,6 +35,8 @@ MESHES = [
 
 
 def _mesh(oracle, kind, kw):
+    if kind == "graded":
+        return oracle.Mesh.lamina_coords(kw["X"], kw["Y"], kw["b"])
     if kind == "lamina":
         return oracle.Mesh.lamina(kw["nux"], kw["nuy"], kw["h"], kw["b"])
     if kind == "periodic":
@@ -101,7 +111,8 @@ def test_stencil_consistency(oracle, kind, kw):
     assert np.max(np.abs(Cm.sum(1) - 1.0)) < 1e-14
     assert np.max(np.abs(S.sum(2))) < 1e-13
     # linear fields along a periodic direction are not single-valued
-    dirs = {"lamina": ((1.0, 0.0), (0.0, 1.0), (0.3, -0.7)), "channel": ((0.0, 1.0),), "periodic": ()}
+    dirs = {"lamina": ((1.0, 0.0), (0.0, 1.0), (0.3, -0.7)), "graded": ((1.0, 0.0), (0.0, 1.0), (0.3, -0.7)),
+            "channel": ((0.0, 1.0),), "periodic": ()}
     for a in dirs[kind]:
         lin = a[0] * x + a[1] * y
         got = np.einsum("pik,pk->pi", S, np.where(nbr >= 0, lin[nbr], 0.0))
@@ -131,8 +142,9 @@ def test_grid_geometry(oracle):
     assert fwd == mir
 
 
-def test_point_location_vs_exhaustive(oracle):
-    m = oracle.Mesh.lamina(10, 8, 1.0, 4.0)
+@pytest.mark.parametrize("graded", [False, True])
+def test_point_location_vs_exhaustive(oracle, graded):
+    m = oracle.Mesh.lamina_coords(GX, GY, 3.0) if graded else oracle.Mesh.lamina(10, 8, 1.0, 4.0)
     tri, txy = m.triangles()
     rng = np.random.default_rng(7)
     pts = rng.uniform([-6, -4.5], [5, 4.5], size=(400, 2))
