@@ -224,6 +224,23 @@ int hlbm_create_multilevel(const hlbm_config *fine, const hlbm_levels *levels,
 int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny,
                      double *tau);
 
+/* ---- graded body-fitted grid ------------------------------------------ */
+/* A single case whose grid has graded spacing (the paper refines its
+ * unstructured grid toward the body): column i of the grid at local
+ * x = x_nodes[i], row j at local y = y_nodes[j] (lamina centre at the
+ * origin; both strictly increasing, the rows symmetric about the lamina,
+ * y_nodes[j] = -y_nodes[nuy-1-j]); each cell is cut along the diagonal of
+ * its side of the centre as in the uniform grid, the lamina fills the cells
+ * of row nuy/2-1 inside |x| <= b/2, and cfg->thickness must equal
+ * y_nodes[nuy/2] - y_nodes[nuy/2-1]. h_u is not used for the grid. The
+ * finite-volume matrices follow the cells' own sizes; the fictitious
+ * rectangle is the grid's bounding box inset by 2. Otherwise as
+ * hlbm_create with ncases = 1 (the geometric checks use the grid's
+ * extents). ckpt_every must be 0: hlbm_adjoint of a graded case returns
+ * HLBM_E_UNSUPPORTED. */
+int hlbm_create_graded(const hlbm_config *cfg, const double *x_nodes,
+                       const double *y_nodes, hlbm_t **out);
+
 /* ---- two-way coupled motion ------------------------------------------- */
 /* The paper prescribes the lamina's motion (Sec. Problem statement: known a
  * priori). Instead, the lamina may be mounted on a spring and damper and

@@ -109,7 +109,9 @@ class Case final : public CaseBase {
 
   // two_step: allow the two-step stream-collide (single cases; a batch
   // advances its members with the case-batched kernels)
-  int init(const hlbm_config &c, bool two_step = true) {
+  // gx, gy (optional): local x of each grid column and y of each row of a
+  // graded grid (hlbm_create_graded)
+  int init(const hlbm_config &c, bool two_step = true, const double *gx = nullptr, const double *gy = nullptr) {
     cfg_ = c;
     d_ = derive(c);
     h_ = c.h_u > 0.0 ? c.h_u : 1.0;
@@ -117,9 +119,22 @@ class Case final : public CaseBase {
     body_ = has_grid_ && c.b > 0.0 && !(c.flags & HLBM_FLAG_NO_BODY);
     nodes_ = (size_t)c.nx * c.ny;
     plane_ = lattice_plane(c.nx, c.ny);
+    // the grid's local extents (the same expressions as the node positions)
+    gex0_ = (double)(0 - c.nux / 2) * h_;
+    gex1_ = (double)(c.nux - 1 - c.nux / 2) * h_;
+    gey0_ = (0.0 - 0.5 * (double)(c.nuy - 1)) * h_;
+    gey1_ = ((double)(c.nuy - 1) - 0.5 * (double)(c.nuy - 1)) * h_;
+    if (gx) {
+      gx_.assign(gx, gx + c.nux);
+      gy_.assign(gy, gy + c.nuy);
+      gex0_ = gx[0];
+      gex1_ = gx[c.nux - 1];
+      gey0_ = gy[0];
+      gey1_ = gy[c.nuy - 1];
+    }
     if (has_grid_) {
       std::string e;
-      if (!build_grid(c.nux, c.nuy, h_, c.b, body_, &grid_, &e)) {
+      if (!build_grid(c.nux, c.nuy, h_, c.b, body_, &grid_, &e, gx, gy)) {
         err = e;
         return HLBM_E_ARG;
       }
@@ -170,6 +185,10 @@ class Case final : public CaseBase {
       HIPCHK(upload(&cls_, grid_.cls.data(), grid_.cls.size() * sizeof(int)));
       HIPCHK(upload(&iface_, grid_.iface.data(), grid_.iface.size() * sizeof(int)));
       HIPCHK(upload(&wall_, grid_.wall.data(), grid_.wall.size() * sizeof(WallEdge)));
+      if (!gx_.empty()) {
+        HIPCHK(upload(&dgx_, gx_.data(), gx_.size() * sizeof(double)));
+        HIPCHK(upload(&dgy_, gy_.data(), gy_.size() * sizeof(double)));
+      }
       // per-step scalars for k = 0 .. max_steps, wall velocity per sub-step
       std::vector<StepParams> &P = P_host_;
       P.resize(cap + 1);
@@ -647,9 +666,8 @@ class Case final : public CaseBase {
     if (!(m->mass > 0.0) || !(m->stiffness >= 0.0) || !(m->damping >= 0.0) || !(m->y_max > 0.0) ||
         !(std::fabs(m->y0) <= m->y_max) || !(std::fabs(m->v0) < 1.0))
       return fail(HLBM_E_ARG, "invalid coupled-motion parameters");
-    const double hy = 0.5 * (double)(cfg_.nuy - 1) * h_;
     if (cfg_.bc != HLBM_BC_PERIODIC &&
-        (d_.yc - hy - m->y_max < 1.0 || d_.yc + hy + m->y_max > (double)cfg_.ny - 2.0))
+        (d_.yc + gey0_ - m->y_max < 1.0 || d_.yc + gey1_ + m->y_max > (double)cfg_.ny - 2.0))
       return fail(HLBM_E_ARG, "grid motion up to y_max leaves the lattice in y");
     HIPCHK(hipStreamSynchronize(s_main_));
     const int64_t cap = std::max<int64_t>(cfg_.max_steps, 1);
@@ -782,6 +800,7 @@ class Case final : public CaseBase {
     if (ckW_ <= 0) return fail(HLBM_E_STATE, "case was created with ckpt_every = 0");
     if (!ck_valid_) return fail(HLBM_E_STATE, "state was replaced after step 0; the checkpoints no longer hold");
     if (fsi_) return fail(HLBM_E_UNSUPPORTED, "adjoint of a case with coupled motion");
+    if (!gx_.empty()) return fail(HLBM_E_UNSUPPORTED, "adjoint of a graded grid");
     if (n != k_ || n <= 0) return fail(HLBM_E_ARG, "the cotangent must cover every step taken (n = steps)");
     HIPCHK(hipStreamSynchronize(s_main_));
     int rc = adjoint_setup();
@@ -910,10 +929,10 @@ class Case final : public CaseBase {
   // two lattice units; lattice node (i, j) is inside when the closed
   // rectangle holds it, i.e. ceil(x0) <= i <= floor(x1), same in y.
   void rect(double y, int &ix0, int &ix1, int &iy0, int &iy1) const {
-    const double rx0 = d_.xc + (double)(0 - cfg_.nux / 2) * h_ + kMargin;
-    const double rx1 = d_.xc + (double)(cfg_.nux - 1 - cfg_.nux / 2) * h_ - kMargin;
-    const double ry0 = d_.yc + y + (0.0 - 0.5 * (double)(cfg_.nuy - 1)) * h_ + kMargin;
-    const double ry1 = d_.yc + y + ((double)(cfg_.nuy - 1) - 0.5 * (double)(cfg_.nuy - 1)) * h_ - kMargin;
+    const double rx0 = d_.xc + gex0_ + kMargin;
+    const double rx1 = d_.xc + gex1_ - kMargin;
+    const double ry0 = d_.yc + y + gey0_ + kMargin;
+    const double ry1 = d_.yc + y + gey1_ - kMargin;
     ix0 = (int)std::ceil(rx0);
     ix1 = (int)std::floor(rx1);
     iy0 = (int)std::ceil(ry0);
@@ -993,8 +1012,8 @@ class Case final : public CaseBase {
       v.mot.C = mot_.damping;
       v.mot.y_max = mot_.y_max;
       v.mot.yc = d_.yc;
-      v.mot.c0 = (0.0 - 0.5 * (double)(cfg_.nuy - 1)) * h_;
-      v.mot.c1 = ((double)(cfg_.nuy - 1) - 0.5 * (double)(cfg_.nuy - 1)) * h_;
+      v.mot.c0 = gey0_;
+      v.mot.c1 = gey1_;
       v.mot.margin = kMargin;
       v.mot.state = mstate_;
       v.mot.cap = cfg_.max_steps;
@@ -1017,6 +1036,8 @@ class Case final : public CaseBase {
       v.half_b = 0.5 * grid_.b;
       v.half_T = 0.5 * grid_.T;
       v.body = body_;
+      v.gx = dgx_;
+      v.gy = dgy_;
       v.cls = cls_;
       v.tab = tab_;
       v.iface = iface_;
@@ -1450,6 +1471,9 @@ class Case final : public CaseBase {
   void *phys_[3] = {nullptr, nullptr, nullptr};  // the physical buffers
   bool two_step_ = false;
   bool fsi_ = false;  // two-way coupled motion (hlbm_set_motion)
+  double gex0_ = 0.0, gex1_ = 0.0, gey0_ = 0.0, gey1_ = 0.0;  // local extents of the grid
+  std::vector<double> gx_, gy_;  // graded grid: columns and rows (empty: uniform)
+  double *dgx_ = nullptr, *dgy_ = nullptr;
   hlbm_motion mot_{};
   double *mstate_ = nullptr;  // [max_steps + 1][2] (y, v) on the device
   int band_[4] = {-10, -20, -10, -20};  // x0, x1, y0, y1 of the band (inclusive; empty, far outside)
@@ -1512,7 +1536,8 @@ class Case final : public CaseBase {
 
 // Configuration checks shared by all storage types (mirrors the geometric
 // requirements stated in hlbm.h).
-int validate(const hlbm_config &c, std::string *err, bool ring_ok = false) {
+int validate(const hlbm_config &c, std::string *err, bool ring_ok = false, const double *gx = nullptr,
+             const double *gy = nullptr) {
   if (c.nx < 3 || c.ny < 3) { *err = "lattice needs nx, ny >= 3"; return HLBM_E_ARG; }
   if (!(c.tau > 0.5)) { *err = "tau must exceed 1/2"; return HLBM_E_ARG; }
   if (c.bc == HLBM_BC_RING && !ring_ok) {
@@ -1532,11 +1557,29 @@ int validate(const hlbm_config &c, std::string *err, bool ring_ok = false) {
   const Derived d = derive(c);
   const double h = c.h_u > 0.0 ? c.h_u : 1.0;
   const bool body = c.b > 0.0 && !(c.flags & HLBM_FLAG_NO_BODY);
-  if (body && std::fabs(c.thickness - h) > 1e-12 * h) { *err = "lamina thickness must equal h_u"; return HLBM_E_ARG; }
+  // extents of the grid (uniform spacing h, or the graded columns and rows)
+  double hx = (double)(c.nux / 2) * h, hxr = (double)(c.nux - 1 - c.nux / 2) * h;
+  double hy = 0.5 * (double)(c.nuy - 1) * h, Tg = h;
+  if (gx) {
+    if (c.nux < 4 || c.nuy < 4 || (c.nuy % 2)) { *err = "grid needs nux >= 4 and even nuy >= 4"; return HLBM_E_ARG; }
+    for (int i = 0; i + 1 < c.nux; ++i)
+      if (!(gx[i + 1] > gx[i])) { *err = "graded grid columns must increase"; return HLBM_E_ARG; }
+    for (int j = 0; j < c.nuy; ++j)
+      if (!(j + 1 == c.nuy || gy[j + 1] > gy[j]) || gy[j] != -gy[c.nuy - 1 - j]) {
+        *err = "graded grid rows must increase and be symmetric about the lamina";
+        return HLBM_E_ARG;
+      }
+    hx = -gx[0];
+    hxr = gx[c.nux - 1];
+    hy = gy[c.nuy - 1];
+    Tg = gy[c.nuy / 2] - gy[c.nuy / 2 - 1];
+  }
+  if (body && std::fabs(c.thickness - Tg) > 1e-12 * Tg) {
+    *err = gx ? "lamina thickness must equal the slot rows' spacing" : "lamina thickness must equal h_u";
+    return HLBM_E_ARG;
+  }
   if (!(1.0 / (double)d.n < 2.0 * d.tau_u)) { *err = "grid sub-step violates Delta t_u < 2 tau_u"; return HLBM_E_ARG; }
   if (c.nux < 4 || c.nuy < 4 || (c.nuy % 2)) { *err = "grid needs nux >= 4 and even nuy >= 4"; return HLBM_E_ARG; }
-  const double hx = (double)(c.nux / 2) * h, hxr = (double)(c.nux - 1 - c.nux / 2) * h;
-  const double hy = 0.5 * (double)(c.nuy - 1) * h;
   if (d.xc - hx < 1.0 || d.xc + hxr > (double)c.nx - 2.0) { *err = "grid leaves the lattice in x"; return HLBM_E_ARG; }
   if (c.bc != HLBM_BC_PERIODIC &&
       (d.yc - hy - std::fabs(d.A) < 1.0 || d.yc + hy + std::fabs(d.A) > (double)c.ny - 2.0)) {
@@ -1544,7 +1587,7 @@ int validate(const hlbm_config &c, std::string *err, bool ring_ok = false) {
     return HLBM_E_ARG;
   }
   if (body && (0.5 * c.b + 1.0 > hx - kMargin - 1.0 || 0.5 * c.b + 1.0 > hxr - kMargin - 1.0 ||
-               0.5 * h + 1.0 > hy - kMargin - 1.0)) {
+               0.5 * Tg + 1.0 > hy - kMargin - 1.0)) {
     *err = "lamina does not fit inside the fictitious rectangle";
     return HLBM_E_ARG;
   }
@@ -2390,6 +2433,45 @@ int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny, double 
   *nx = a;
   *ny = b;
   *tau = t;
+  return HLBM_OK;
+}
+
+int hlbm_create_graded(const hlbm_config *cfg, const double *x_nodes, const double *y_nodes, hlbm_t **out) {
+  using namespace mghlbm;
+  if (out) *out = nullptr;
+  if (!cfg || !x_nodes || !y_nodes || !out) { g_create_error = "null argument"; return HLBM_E_ARG; }
+  if (cfg->nux <= 0 || cfg->nuy <= 0) { g_create_error = "a graded case needs a grid"; return HLBM_E_ARG; }
+  if (cfg->ckpt_every != 0) { g_create_error = "a graded case takes no checkpoints (no adjoint)"; return HLBM_E_ARG; }
+  std::string e;
+  int rc = validate(*cfg, &e, false, x_nodes, y_nodes);
+  if (rc != HLBM_OK) { g_create_error = e; return rc; }
+  std::unique_ptr<CaseBase> c;
+  try {
+    if (cfg->storage == HLBM_FP64) {
+      auto p = std::make_unique<Case<double, double>>();
+      rc = p->init(*cfg, true, x_nodes, y_nodes);
+      c = std::move(p);
+    } else if (cfg->storage == HLBM_FP32) {
+      auto p = std::make_unique<Case<float, float>>();
+      rc = p->init(*cfg, true, x_nodes, y_nodes);
+      c = std::move(p);
+    } else {
+      auto p = std::make_unique<Case<__half, float>>();
+      rc = p->init(*cfg, true, x_nodes, y_nodes);
+      c = std::move(p);
+    }
+  } catch (const std::bad_alloc &) {
+    g_create_error = "host allocation failed";
+    return HLBM_E_NOMEM;
+  }
+  if (rc != HLBM_OK) {
+    g_create_error = c->err;
+    return rc;
+  }
+  hlbm_t *h = new (std::nothrow) hlbm_t;
+  if (!h) { g_create_error = "host allocation failed"; return HLBM_E_NOMEM; }
+  h->c = std::move(c);
+  *out = h;
   return HLBM_OK;
 }
 

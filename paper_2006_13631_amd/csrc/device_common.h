@@ -265,12 +265,34 @@ struct GridGeom {
   int nux, nuy;
   double h, xc, half_b, half_T;
   int body;
+  // graded grid: local x of every column, y of every row (null: uniform
+  // spacing h, column i at (i - nux/2) h, row j at (j - (nuy-1)/2) h)
+  const double *gx = nullptr, *gy = nullptr;
 };
+
+// largest c in [0, n-2] with v[c] <= x (0 when x < v[0]); v increasing
+__device__ __forceinline__ int graded_cell(const double *v, int n, double x) {
+  int lo = 0, hi = n - 2;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (v[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // Lattice node (x, y) inside the grid at t_k (lower grid row at Y0): its
 // cell and local coordinates, as used by the lattice interpolation nodes.
 __device__ __forceinline__ void lattice_node_cell(const GridGeom &g, double ybase, int x, int y, int &ci, int &cj,
                                                   double &a, double &b) {
+  if (g.gx) {  // graded: the cell holding the point, local coordinates in [0, 1]
+    const double lx = (double)x - g.xc, ly = (double)y - ybase;
+    ci = graded_cell(g.gx, g.nux, lx);
+    cj = graded_cell(g.gy, g.nuy, ly);
+    a = (lx - g.gx[ci]) / (g.gx[ci + 1] - g.gx[ci]);
+    b = (ly - g.gy[cj]) / (g.gy[cj + 1] - g.gy[cj]);
+    return;
+  }
   const double X0 = g.xc + (double)(0 - g.nux / 2) * g.h;
   const double Y0 = ybase + (0.0 - 0.5 * (double)(g.nuy - 1)) * g.h;
   const double s = ((double)x - X0) / g.h, t = ((double)y - Y0) / g.h;
@@ -288,7 +310,42 @@ struct RefillCell {
   double a, b;
 };
 
+__device__ __forceinline__ RefillCell refill_cell_graded(const GridGeom &g, double ybase, double ybase1, int i,
+                                                         int j) {
+  // the grid moves in y only: the node keeps its column, and its new height
+  // is located among the old rows
+  const double tol = 1e-12;
+  const double xrel = g.gx[i];
+  const double Ynew = ybase1 + g.gy[j];
+  const double py = Ynew - ybase;
+  const int slot_row = g.nuy / 2 - 1;
+  const double half = g.half_b + 1e-9 * (2.0 * g.half_T);
+  auto body_cell = [&](int ci, int cj) {
+    return g.body && cj == slot_row && g.gx[ci] >= -half && g.gx[ci + 1] <= half;
+  };
+  auto frac = [&](int cj) { return (py - g.gy[cj]) / (g.gy[cj + 1] - g.gy[cj]); };
+  RefillCell r{0, 0, 0, 0.0, 0.0};
+  const double span0 = g.gy[1] - g.gy[0], span1 = g.gy[g.nuy - 1] - g.gy[g.nuy - 2];
+  if (py >= g.gy[0] - tol * span0 && py <= g.gy[g.nuy - 1] + tol * span1) {
+    r.cj = graded_cell(g.gy, g.nuy, py);
+    r.ci = min(i, g.nux - 2);
+    r.a = (double)(i - r.ci);
+    r.b = frac(r.cj);
+    r.kind = 3;
+    if (body_cell(r.ci, r.cj)) {
+      if (r.b <= tol && r.cj > 0 && !body_cell(r.ci, r.cj - 1)) { r.cj -= 1; r.b = frac(r.cj); }
+      else if (r.b >= 1.0 - tol && r.cj < g.nuy - 2 && !body_cell(r.ci, r.cj + 1)) { r.cj += 1; r.b = frac(r.cj); }
+      else if (r.a <= tol && r.ci > 0 && !body_cell(r.ci - 1, r.cj)) { r.ci -= 1; r.a += 1.0; }
+      else if (r.a >= 1.0 - tol && r.ci < g.nux - 2 && !body_cell(r.ci + 1, r.cj)) { r.ci += 1; r.a -= 1.0; }
+      else r.kind = 0;
+    }
+  }
+  if (r.kind != 3) r.kind = (g.body && fabs(xrel) < g.half_b && fabs(py) < g.half_T) ? 2 : 1;
+  return r;
+}
+
 __device__ __forceinline__ RefillCell refill_cell(const GridGeom &g, double ybase, double ybase1, int i, int j) {
+  if (g.gx) return refill_cell_graded(g, ybase, ybase1, i, j);
   const double tol = 1e-12;
   const double xrel = (double)(i - g.nux / 2) * g.h;
   const double Ynew = ybase1 + ((double)j - 0.5 * (double)(g.nuy - 1)) * g.h;

@@ -2,7 +2,8 @@
 //
 // Grid (Sec. HLBM: unstructured triangular mesh around the body): nux*nuy
 // nodes with spacing h, node (i, j) at local x = (i - nux/2) h,
-// y = (j - (nuy-1)/2) h. Each quad cell is cut into two triangles along a
+// y = (j - (nuy-1)/2) h, or graded: column i at x = gx[i], row j at
+// y = gy[j] (the lamina thickness is then gy[nuy/2] - gy[nuy/2-1]). Each quad cell is cut into two triangles along a
 // diagonal that is mirrored about the centre line x = 0 (rising diagonal for
 // cells left of it), so the grid is left-right symmetric. The lamina of width
 // b and thickness h fills the cells between rows nuy/2-1 and nuy/2 with
@@ -44,21 +45,39 @@ void cell_triangles(bool rising, Tri out[2]) {
 
 }  // namespace
 
-bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, std::string *err) {
+bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, std::string *err, const double *gx,
+                const double *gy) {
   if (nux < 4 || nuy < 4 || (nuy % 2) != 0 || !(h > 0.0) || (body && !(b > 0.0))) {
     *err = "grid needs nux >= 4, even nuy >= 4, h > 0 and b > 0 with a body";
     return false;
   }
+  const bool graded = gx != nullptr;
+  if (graded) {
+    for (int i = 0; i + 1 < nux; ++i)
+      if (!(gx[i + 1] > gx[i])) {
+        *err = "graded grid columns must increase";
+        return false;
+      }
+    for (int j = 0; j + 1 < nuy; ++j)
+      if (!(gy[j + 1] > gy[j])) {
+        *err = "graded grid rows must increase";
+        return false;
+      }
+  }
+  // cell widths and node positions: uniform spacing h, or the given columns and rows
+  const double T = graded ? gy[nuy / 2] - gy[nuy / 2 - 1] : h;
   g->nux = nux;
   g->nuy = nuy;
   g->h = h;
   g->b = body ? b : 0.0;
-  g->T = body ? h : 0.0;
+  g->T = body ? T : 0.0;
   g->body = body;
   const int N = nux * nuy;
   g->nnode = N;
-  auto xl = [&](int i) { return (double)(i - nux / 2) * h; };
-  const double half = 0.5 * b + 1e-9 * h;
+  auto xl = [&](int i) { return graded ? gx[i] : (double)(i - nux / 2) * h; };
+  auto wxc = [&](int ci) { return graded ? gx[ci + 1] - gx[ci] : h; };
+  auto wyc = [&](int cj) { return graded ? gy[cj + 1] - gy[cj] : h; };
+  const double half = 0.5 * b + 1e-9 * T;
   const int slot_row = nuy / 2 - 1;
   auto body_cell = [&](int ci, int cj) {
     return body && cj == slot_row && xl(ci) >= -half && xl(ci + 1) <= half;
@@ -81,7 +100,6 @@ bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, st
 
   // per node: the (up to four) cells around it, visited in a fixed local
   // order so nodes with the same neighbourhood get bit-identical sums
-  const double Xc[4] = {0.0, h, 0.0, h}, Yc[4] = {0.0, 0.0, h, h};
   std::map<std::vector<uint64_t>, int> class_of;
   g->cls.assign(N, 0);
   g->classes.clear();
@@ -95,6 +113,8 @@ bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, st
           const int ci = i + di, cj = j + dj;
           if (ci < 0 || cj < 0 || ci >= nux - 1 || cj >= nuy - 1 || body_cell(ci, cj)) continue;
           const int me = (-di) + 2 * (-dj);  // corner id of p in this cell
+          const double wx = wxc(ci), wy = wyc(cj);
+          const double Xc[4] = {0.0, wx, 0.0, wx}, Yc[4] = {0.0, 0.0, wy, wy};
           Tri tris[2];
           cell_triangles(rising(ci), tris);
           for (const Tri &t : tris) {
@@ -157,11 +177,11 @@ bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, st
       }
     const int top = slot_row + 1, bot = slot_row;
     for (int i = i0; i < i1; ++i) {
-      g->wall.push_back({top * nux + i, top * nux + i + 1, 0.0, 1.0, h});
-      g->wall.push_back({bot * nux + i, bot * nux + i + 1, 0.0, -1.0, h});
+      g->wall.push_back({top * nux + i, top * nux + i + 1, 0.0, 1.0, wxc(i)});
+      g->wall.push_back({bot * nux + i, bot * nux + i + 1, 0.0, -1.0, wxc(i)});
     }
-    g->wall.push_back({bot * nux + i0, top * nux + i0, -1.0, 0.0, h});
-    g->wall.push_back({bot * nux + i1, top * nux + i1, 1.0, 0.0, h});
+    g->wall.push_back({bot * nux + i0, top * nux + i0, -1.0, 0.0, T});
+    g->wall.push_back({bot * nux + i1, top * nux + i1, 1.0, 0.0, T});
   }
   return true;
 }

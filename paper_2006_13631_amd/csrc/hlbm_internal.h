@@ -68,6 +68,8 @@ struct HostGrid {
 
 // Builds the grid, its median-dual finite-volume matrices and stencil
 // classes. Returns false with a message on invalid geometry.
-bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, std::string *err);
+// gx, gy (optional): local x of each column and y of each row of a graded grid.
+bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, std::string *err,
+                const double *gx = nullptr, const double *gy = nullptr);
 
 }  // namespace mghlbm

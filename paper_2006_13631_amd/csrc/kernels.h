@@ -50,6 +50,7 @@ struct CaseView {
   int nux, nuy, nnode, n_iface, n_wall_edges, n_sub;
   double h, xc, yc, half_b, half_T;
   int body;
+  const double *gx, *gy;  // graded grid: local x of each column, y of each row (null: uniform)
   const int *cls;
   const GridClass<R> *tab;
   const int *iface;

@@ -200,7 +200,7 @@ __device__ __forceinline__ void lattice_from_grid_block(const CaseView<T, R> &v,
   const int y = min(P.iy0, P.piy0) + by;
   if (x >= v.k2_x0 + v.k2_w || y > max(P.iy1, P.piy1)) return;
   if (!from_grid_target(P, x, y)) return;
-  const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body};
+  const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body, v.gx, v.gy};
   int ci, cj, node[3];
   double a, b, lam[3], dlam[3];
   lattice_node_cell(gg, P.ybase, x, y, ci, cj, a, b);
@@ -248,8 +248,8 @@ __device__ __forceinline__ void interface_donors_block(const CaseView<T, R> &v, 
     const StepParams &P = v.params[k];
     p = v.iface[t];
     const int i = p % v.nux, j = p / v.nux;
-    const double X = v.xc + (double)(i - v.nux / 2) * v.h;
-    const double Y = P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
+    const double X = v.gx ? v.xc + v.gx[i] : v.xc + (double)(i - v.nux / 2) * v.h;
+    const double Y = v.gy ? P.ybase + v.gy[j] : P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
     donor_corner<T, R>(A, v.nx, v.ny, v.plane, v.bc, X, Y, d, acc);
   }
 #pragma unroll
@@ -597,7 +597,7 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
     return;
   }
   const StepParams &P = v.params[k];
-  const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body};
+  const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body, v.gx, v.gy};
   const RefillCell rc = refill_cell(gg, P.ybase, P.ybase1, i, j);
   if (rc.kind == 3) {
     int node[3];
@@ -611,8 +611,8 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
     for (int q = 0; q < 9; ++q) out[q] = fo[q * N + p];
     atomicAdd(&v.counts[1], 1ull);
   } else {
-    const double X = v.xc + (double)(i - v.nux / 2) * v.h;
-    const double Ynew = P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
+    const double X = v.gx ? v.xc + v.gx[i] : v.xc + (double)(i - v.nux / 2) * v.h;
+    const double Ynew = v.gy ? P.ybase1 + v.gy[j] : P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
     R rho, ux, uy, fneq[9], e[9];
     lattice_bilinear<T, R>(A, v.nx, v.ny, v.plane, v.bc, X, Ynew, rho, ux, uy, fneq);
     equilibrium<R>(rho, ux, uy, e);

@@ -28,7 +28,7 @@ STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV}
 EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_state",
            "hlbm_set_state", "hlbm_info_get", "hlbm_get_stencil", "hlbm_timing",
            "hlbm_timing_get", "hlbm_tune", "hlbm_destroy", "hlbm_last_error",
-           "hlbm_create_multilevel", "hlbm_level_shape", "hlbm_set_motion")
+           "hlbm_create_multilevel", "hlbm_level_shape", "hlbm_set_motion", "hlbm_create_graded")
 STATUS_RUNNING, STATUS_DONE, STATUS_UNSTABLE = 0, 1, 2
 
 
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     L.hlbm_create_multilevel.argtypes = [C.POINTER(Config), C.POINTER(Levels), C.POINTER(vp)]
     L.hlbm_level_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), dp]
     L.hlbm_set_motion.argtypes = [vp, i32, C.POINTER(Motion)]
+    L.hlbm_create_graded.argtypes = [C.POINTER(Config), dp, dp, C.POINTER(vp)]
     L.hlbm_destroy.argtypes = [vp]
     L.hlbm_destroy.restype = None
     L.hlbm_last_error.argtypes = [vp]
@@ -120,14 +121,21 @@ class Case:
 
     def __init__(self, nx, ny, nux=0, nuy=0, h_u=1.0, b=0.0, thickness=1.0, tau=0.8, kc=0.0,
                  beta=0.0, n_sub=0, bc=BC_PERIODIC_X_WALLS_Y, storage=FP64, flags=0,
-                 ckpt_every=0, max_steps=0):
+                 ckpt_every=0, max_steps=0, x_nodes=None, y_nodes=None):
         L = load()
         if isinstance(storage, str):
             storage = STORAGE[storage]
         self.cfg = Config(nx, ny, nux, nuy, h_u, b, thickness, tau, kc, beta, n_sub, bc, storage,
                           flags, ckpt_every, 0, max_steps)
         h = C.c_void_p()
-        rc = L.hlbm_create(C.byref(self.cfg), 1, C.byref(h))
+        if x_nodes is not None or y_nodes is not None:  # graded grid
+            gx = np.ascontiguousarray(x_nodes, dtype=np.float64)
+            gy = np.ascontiguousarray(y_nodes, dtype=np.float64)
+            if gx.shape != (nux,) or gy.shape != (nuy,):
+                raise HlbmError(E_ARG, "x_nodes and y_nodes need nux and nuy entries")
+            rc = L.hlbm_create_graded(C.byref(self.cfg), _ptr(gx), _ptr(gy), C.byref(h))
+        else:
+            rc = L.hlbm_create(C.byref(self.cfg), 1, C.byref(h))
         if rc != 0:
             raise HlbmError(rc, L.hlbm_last_error(None).decode())
         self.h = h

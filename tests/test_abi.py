@@ -146,3 +146,15 @@ def test_motion_struct_layout(tmp_path):
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     a, b, c = map(int, subprocess.check_output([str(exe)]).split())
     assert a == C.sizeof(hlbm.Motion) and b == hlbm.Motion.y_max.offset and c == hlbm.STATE_MOTION
+
+
+def test_graded_configuration_checked_on_host():
+    from paper_2006_13631_amd.workloads import graded_nodes
+    gx, gy = graded_nodes(31, 0.5, 1.25, 1.5, fine=5.0), graded_nodes(16, 0.5, 1.3, 1.5)
+    cfg = dict(nx=64, ny=48, nux=31, nuy=16, b=8.0, thickness=0.5, tau=0.8, kc=1.0, beta=20.0, max_steps=4)
+    for bad in (dict(y_nodes=gy + 0.1), dict(x_nodes=gx[::-1].copy()), dict(x_nodes=gx * 4)):
+        kw = dict(x_nodes=gx, y_nodes=gy)
+        kw.update(bad)
+        with pytest.raises(hlbm.HlbmError) as ei:
+            hlbm.Case(**cfg, **kw)
+        assert ei.value.code == hlbm.E_ARG
