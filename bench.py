@@ -507,6 +507,52 @@ def coupled_leg(workload="lamina_2048", storage="f64", periods=2.5, mass_ratio=1
             "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}}
 
 
+def graded_leg(workload="lamina_1024", storage="f64"):
+    """The workload's lamina on its uniform grid (spacing 1) and on a graded
+    grid over the same extent (spacing 1 over the lamina, growing to 2 away
+    from it: about half the nodes): time per step and Theta over [T, 4T)."""
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.workloads import graded_nodes, preset
+    cfg = preset(workload)
+    steps = cfg.pop("steps")
+    cfg.pop("ckpt_every", None)
+    half_x = cfg["nux"] // 2 * cfg["h_u"]
+    half_y = 0.5 * (cfg["nuy"] - 1) * cfg["h_u"]
+    nx_, ny_ = 5, 4
+    while graded_nodes(nx_, 1.0, 1.04, 2.0, fine=0.6 * cfg["b"])[-1] < half_x:
+        nx_ += 2
+    while graded_nodes(ny_, 1.0, 1.06, 2.0, fine=4.0)[-1] < half_y:
+        ny_ += 2
+    gx = graded_nodes(nx_, 1.0, 1.04, 2.0, fine=0.6 * cfg["b"])
+    gy = graded_nodes(ny_, 1.0, 1.06, 2.0, fine=4.0)
+    out = {"workload": workload, "storage": storage, "steps": steps}
+    thetas = {}
+    for kind in ("uniform", "graded"):
+        kw = dict(cfg, storage=H.STORAGE[storage], max_steps=steps)
+        if kind == "graded":
+            kw.update(nux=nx_, nuy=ny_, x_nodes=gx, y_nodes=gy)
+        c = H.Case(**kw)
+        c.tune(trial_steps=4)
+        c.step(8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(steps - 8)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        th = c.theta(1.0, 4.0)
+        thetas[kind] = th
+        out[kind] = {"grid": [kw["nux"], kw["nuy"]], "grid_nodes": c.info().nnode,
+                     "ms_per_step": round(1e3 * dt / (steps - 8), 4),
+                     "mlups": round(cfg["nx"] * cfg["ny"] * (steps - 8) / dt / 1e6, 1),
+                     "theta": [th.real, th.imag]}
+        print(f"# graded leg {kind}: {out[kind]}", file=sys.stderr, flush=True)
+        c.close()
+    out["theta_rel_diff"] = abs(thetas["graded"] - thetas["uniform"]) / abs(thetas["uniform"])
+    out["speedup"] = round(out["uniform"]["ms_per_step"] / out["graded"]["ms_per_step"], 3)
+    return out
+
+
 def storage_leg(workload, storage, steps, warmup, timing_steps):
     """The same workload at another storage precision: lattice MLUPS over
     graph-replayed steps, the stream-collide's mean duration (its own events)
@@ -580,6 +626,9 @@ def main():
     ap.add_argument("--levels-storage", default="f64", choices=list(BYTES))
     ap.add_argument("--levels-steps", type=int, default=40)
     ap.add_argument("--levels-no-uniform", action="store_true")
+    ap.add_argument("--graded", action="store_true",
+                    help="run only the differentiation case on its uniform grid and on a graded grid of the same "
+                         "extent and print their line")
     ap.add_argument("--coupled", action="store_true",
                     help="run only the main workload with the lamina elastically mounted (two-way coupled) and "
                          "print its line")
@@ -598,6 +647,10 @@ def main():
     if args.sweep:
         torch.cuda.set_device(0)
         print(json.dumps(sweep_leg(periods=args.sweep_periods, loop=not args.sweep_no_loop)), flush=True)
+        return
+    if args.graded:
+        torch.cuda.set_device(0)
+        print(json.dumps(graded_leg()), flush=True)
         return
     if args.coupled:
         torch.cuda.set_device(0)
