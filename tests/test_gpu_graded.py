@@ -88,3 +88,17 @@ def test_fp32_graded_tracks_fp64(oracle):
     e = _rel(g.history(), o.history())
     _say("fp32 graded force error", e)
     assert e < 1e-3
+
+
+def test_coupled_motion_on_a_graded_grid(oracle):
+    steps = 150
+    mot = dict(mass=40.0, stiffness=0.05, damping=0.0, y0=1.5, v0=0.0, y_max=5.0)
+    cfg = dict(CASE, kc=0.0)
+    o = oracle.Sim(max_steps=steps, x_nodes=GX, y_nodes=GY, **cfg)
+    g = hlbm.Case(max_steps=steps, x_nodes=GX, y_nodes=GY, **cfg)
+    o.set_motion(**mot)
+    g.set_motion(**mot)
+    o.step(steps)
+    g.step(steps)
+    _check(o, g)
+    assert _rel(g.motion_history(), o.motion_history()) <= TOL

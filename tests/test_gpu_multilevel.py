@@ -122,3 +122,18 @@ def test_fp32_levels_track_the_oracle(oracle):
         e = np.max(np.abs(dev_g - dev_o)) / np.max(np.abs(dev_o))
         _say("fp32 level", l, e)
         assert e < 1e-3
+
+
+def test_fp16_deviation_levels_track_the_oracle(oracle):
+    boxes = [(10, 12, 38, 28)]
+    o, g = _pair(oracle, 48, 40, boxes, hlbm.BC_PERIODIC_X_WALLS_Y, storage=hlbm.FP16_DEV, max_steps=40,
+                 **LAMINA)
+    o.step(20)
+    g.step(20)
+    _, _, w = oracle.d2q9()
+    for l in range(2):
+        dev_o = o.level(l) - w[:, None, None]
+        dev_g = g.level(l) - w[:, None, None]
+        e = np.max(np.abs(dev_g - dev_o)) / np.max(np.abs(dev_o))
+        _say("fp16 level", l, e)
+        assert e < 2e-2
