@@ -54,19 +54,50 @@ def measured_traffic(workload, storage, kernel="k_stream_collide"):
     return rec["bytes_per_launch"]
 
 
+def host_cores():
+    """Host threads this process may use (its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return min(n, int(env)) if env.isdigit() and int(env) > 0 else n
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, steps):
-    """The oracle as it stands, single-threaded, on `steps` steps."""
+    """The oracle as it stands on `steps` steps: single-threaded (the figure
+    quoted), then with its per-node loops on every host core. Both runs must
+    end in the same bits."""
     from oracle import oracle as O
     c = dict(cfg)
     c.pop("steps", None)
     c.pop("ckpt_every", None)
-    s = O.Sim(max_steps=steps, **c)
-    t0 = time.perf_counter()
-    s.step(steps)
-    dt = time.perf_counter() - t0
-    return {"value": c["nx"] * c["ny"] * steps / dt / 1e6, "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first {steps} steps of the same workload, FP64, one thread ({dt:.1f} s)"}
+    runs = {}
+    for threads in (1, host_cores()):
+        O.set_threads(threads)
+        s = O.Sim(max_steps=steps, **c)
+        t0 = time.perf_counter()
+        s.step(steps)
+        dt = time.perf_counter() - t0
+        runs[threads] = (dt, s.history(), s.lattice())
+        del s
+    O.set_threads(1)
+    (t1, h1, f1), (tn, hn, fn) = runs[1], runs[max(runs)]
+    mlups = lambda dt: c["nx"] * c["ny"] * steps / dt / 1e6
+    return {"value": mlups(t1), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} steps of the same workload, FP64, one thread ({t1:.1f} s)",
+            "all_cores": {"value": mlups(tn), "cores": max(runs), "seconds": tn,
+                          "same_bits": bool(np.array_equal(h1, hn) and np.array_equal(f1, fn)),
+                          "nproc": os.cpu_count(), "cpu": cpu_model()}}
 
 
 def adjoint_leg(workload, storage, W_ckpt, fd_step, steps=None):

@@ -51,6 +51,9 @@ static const double WT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
 static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 static const double CS2 = 1.0 / 3.0; /* lattice speed of sound squared */
 
+/* host threads of the per-node loops; 1 (serial) unless or_set_threads asks */
+static int or_threads = 1;
+
 void or_d2q9(int32_t cx[9], int32_t cy[9], double w[9]) {
   for (int i = 0; i < 9; ++i) {
     cx[i] = CX[i];
@@ -140,6 +143,8 @@ static void pull_node(const real *A, int nx, int ny, int bc, int x, int y,
 static void lattice_step_r(const real *A, real *B, int32_t nx, int32_t ny,
                            int32_t bc, real tau, real u_bot, real u_top,
                            const uint8_t *disc) {
+  /* nodes are independent: rows may run on several threads (same results) */
+#pragma omp parallel for schedule(static) num_threads(or_threads) if (or_threads > 1)
   for (int y = 0; y < ny; ++y) {
     for (int x = 0; x < nx; ++x) {
       /* the ring of a ring-fed level is written from the coarser level */
@@ -729,6 +734,8 @@ static void fv_substep_r(const or_mesh *m, const real *f, const real *star_eq,
                          double dt_u, const real *uwx, const real *uwy) {
   const int N = m->nnode;
   real *feq = malloc((size_t)9 * N * sizeof(real));
+  /* per-node loops (same results on any number of threads) */
+#pragma omp parallel for schedule(static) num_threads(or_threads) if (or_threads > 1)
   for (int p = 0; p < N; ++p) {
     real fp[9], e[9], rho, ux, uy;
     for (int i = 0; i < 9; ++i) fp[i] = f[(size_t)i * N + p];
@@ -736,6 +743,7 @@ static void fv_substep_r(const or_mesh *m, const real *f, const real *star_eq,
     feq_r(rho, ux, uy, e);
     for (int i = 0; i < 9; ++i) feq[(size_t)i * N + p] = e[i];
   }
+#pragma omp parallel for schedule(static) num_threads(or_threads) if (or_threads > 1)
   for (int p = 0; p < N; ++p) {
     const int iface = (m->type[p] == OR_NODE_INTERFACE);
     real out[9];
@@ -1016,6 +1024,18 @@ static int create_sim(const or_config *c, const double *X, const double *Y, or_s
 }
 
 int or_create(const or_config *c, or_sim **out) { return create_sim(c, NULL, NULL, out); }
+
+/* threads of the per-node loops: 1 unless asked (1 without OpenMP); n <= 0
+ * leaves the setting alone; returns the number in effect */
+int or_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) or_threads = n;
+  return or_threads;
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 /* A case whose grid has graded spacing: columns at local x = X[nux], rows at
  * y = Y[nuy] (or_mesh_lamina_coords; rows symmetric about the lamina, whose

@@ -126,6 +126,10 @@ void or_mesh_force(const or_mesh *m, const double *f, double F[2]);
 
 /* ---- the hybrid method ----------------------------------------------- */
 int or_create(const or_config *cfg, or_sim **out);
+/* host threads of the per-node loops (lattice stream-collide, grid
+ * sub-steps), 1 by default; n <= 0 only queries. Results do not depend on
+ * it. Returns the number in effect (always 1 in a build without OpenMP). */
+int or_set_threads(int32_t n);
 /* a case with a graded grid: columns at local x = X[nux], rows at y =
  * Y[nuy] (rows symmetric about the lamina, thickness Y[nuy/2] - Y[nuy/2-1]) */
 int or_create_graded(const or_config *cfg, const double *X, const double *Y, or_sim **out);

@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
     plain doubles and once as the complex-step variant."""
     for out, extra in ((_LIB, []), (_LIB_CS, ["-DOR_COMPLEX_STEP"])):
         if force or not os.path.exists(out):
-            cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-fPIC", *extra,
+            cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-fPIC", "-fopenmp", *extra,
                    "-shared", "-o", out + ".tmp", _SRC, "-lm"]
             subprocess.check_call(cmd)
             os.replace(out + ".tmp", out)
@@ -110,6 +110,8 @@ def lib():
         L.or_lattice_status.restype = C.c_int32
         L.or_fit_theta.argtypes = [_D, C.c_int64, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_double, _D]
+        L.or_set_threads.argtypes = [C.c_int32]
+        L.or_set_threads.restype = C.c_int32
         L.or_set_motion.argtypes = [vp] + [C.c_double] * 6
         L.or_create_graded.argtypes = [C.POINTER(Config), _D, _D, C.POINTER(vp)]
         L.or_mesh_lamina_coords.argtypes = [C.c_int32, C.c_int32, _D, _D, C.c_double]
@@ -146,6 +148,8 @@ def lib_cs():
         L.or_destroy.argtypes = [vp]
         L.or_step.argtypes = [vp, C.c_int64]
         L.or_info_get.argtypes = [vp, C.POINTER(Info)]
+        L.or_set_threads.argtypes = [C.c_int32]
+        L.or_set_threads.restype = C.c_int32
         L.or_cs_perturb.argtypes = [vp, C.c_double, C.c_double, C.c_double]
         for f in ("or_cs_get_lattice", "or_cs_get_mesh"):
             getattr(L, f).argtypes = [vp, _D, _D]
@@ -155,6 +159,12 @@ def lib_cs():
         L.or_cs_history.restype = C.c_int64
         _lib_cs = L
     return _lib_cs
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the oracle's per-node loops (1 unless set; n <= 0
+    queries). Results do not depend on it."""
+    return lib().or_set_threads(n)
 
 
 def d2q9():
