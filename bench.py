@@ -100,6 +100,86 @@ def cpu_baseline(cfg, steps):
                           "nproc": os.cpu_count(), "cpu": cpu_model()}}
 
 
+def oracle_timing_leg(big_steps=100, log=None):
+    """The oracle timed on the host, single-threaded and with its per-node
+    loops on every host core (the bits must agree): the 256x128 case and the
+    128x64 copy of the differentiation case in full (the latter also with
+    its complex-step derivatives along A, omega and tau, one run each), the
+    2048^2 and 4096^2 workloads on their first `big_steps` steps, whose full
+    runs are extrapolated from the per-step time."""
+    from oracle import oracle as O
+    from paper_2006_13631_amd.workloads import preset
+    log = log or (lambda *a: print(*a, file=sys.stderr, flush=True))
+    cores = host_cores()
+
+    def timed(name, steps, threads, cs=None, chunk=None):
+        c = preset(name)
+        c.pop("steps")
+        c.pop("ckpt_every", None)
+        O.set_threads(threads)
+        O.lib_cs().or_set_threads(threads)
+        s = O.Sim(max_steps=steps, **c) if cs is None else O.SimCS(*cs, max_steps=steps, **c)
+        inf = s.info()
+        chunk = chunk or steps
+        t, done = 0.0, 0
+        while done < steps:
+            n = min(chunk, steps - done)
+            t0 = time.perf_counter()
+            s.step(n)
+            t += time.perf_counter() - t0
+            done += n
+            log(f"# oracle {name} threads={threads}{' complex-step' if cs else ''}: "
+                f"{done}/{steps} steps, {t:.1f} s")
+        node_steps = c["nx"] * c["ny"] * steps
+        grid_steps = inf.n_sub * inf.nnode * steps
+        row = {"seconds": t, "ms_per_step": 1e3 * t / steps, "mlups": node_steps / t / 1e6,
+               "mlups_total": (node_steps + grid_steps) / t / 1e6}
+        out = (s.history(), s.lattice())
+        del s
+        return row, out
+
+    def same(a, b):
+        return all(np.array_equal(np.asarray(x), np.asarray(y)) for x, y in zip(a, b))
+
+    rows = {}
+    plan = [("lamina_256x128", None, None), ("lamina_128x64", None, None),
+            ("lamina_2048", big_steps, 10), ("lamina_4096", big_steps, 5)]
+    for name, steps, chunk in plan:
+        full = preset(name)["steps"]
+        steps = steps or full
+        r1, o1 = timed(name, steps, 1, chunk=chunk)
+        rn, on = timed(name, steps, cores, chunk=chunk)
+        row = {"steps": steps, "full_steps": full, "one_thread": r1, "all_cores": rn,
+               "same_bits": same(o1, on)}
+        del o1, on
+        if steps < full:
+            row["full_run_hours_extrapolated"] = {"one_thread": r1["seconds"] * full / steps / 3600,
+                                                  "all_cores": rn["seconds"] * full / steps / 3600}
+        rows[name] = row
+    # derivatives of the differentiation copy: one complex-step run per
+    # direction (A, omega, tau)
+    name = "lamina_128x64"
+    full = preset(name)["steps"]
+    cs = {}
+    for threads in (1, cores):
+        tot, outs = 0.0, []
+        for d in range(3):
+            h = [0.0, 0.0, 0.0]
+            h[d] = 1e-20
+            r, o = timed(name, full, threads, cs=tuple(h))
+            tot += r["seconds"]
+            outs.append(o)
+        cs[threads] = (tot, outs)
+    rows[name]["complex_step_derivatives"] = {
+        "runs": 3, "one_thread_s": cs[1][0], "all_cores_s": cs[cores][0],
+        "ratio_to_forward_one_thread": cs[1][0] / rows[name]["one_thread"]["seconds"],
+        "same_bits": all(same(a, b) for a, b in zip(cs[1][1], cs[cores][1]))}
+    O.set_threads(1)
+    O.lib_cs().or_set_threads(1)
+    return {"oracle_timing": rows, "cores": cores, "nproc": os.cpu_count(), "cpu": cpu_model(),
+            "build": "gcc -O2 -ffp-contract=off -fopenmp, FP64"}
+
+
 def adjoint_leg(workload, storage, W_ckpt, fd_step, steps=None):
     import torch
     from paper_2006_13631_amd import hlbm as H
@@ -663,6 +743,10 @@ def main():
     ap.add_argument("--coupled", action="store_true",
                     help="run only the main workload with the lamina elastically mounted (two-way coupled) and "
                          "print its line")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="run only the oracle's host timing (one thread and all host cores) on the four "
+                         "workloads and print its line")
+    ap.add_argument("--oracle-steps", type=int, default=100)
     ap.add_argument("--levels-theta", action="store_true",
                     help="run only Theta on 4 refinement levels (L = 256 at the finest) against a uniform "
                          "finest lattice over the same domain and print its line")
@@ -670,6 +754,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing_leg(args.oracle_steps)), flush=True)
+        return
 
     import torch
     from paper_2006_13631_amd import hlbm as H
