@@ -871,7 +871,12 @@ def main():
                                                  "k_stream_collide2" if two else "k_stream_collide"),
                      "kernel": "k_stream_collide2" if two else "k_stream_collide",
                      "steps_per_launch": 2 if two else 1, "avg_us": round(avg_s * 1e6, 3),
-                     "bytes_per_launch": alg_bytes},
+                     "bytes_per_launch": alg_bytes,
+                     # per lattice step: the kernel's time, and the least time
+                     # any one-step-per-launch kernel needs at peak (read and
+                     # write the lattice once per step)
+                     "us_per_step": round(avg_s * 1e6 / (2 if two else 1), 3),
+                     "single_step_floor_us": round(alg_bytes / (HBM_PEAK_GBS * 1e9) * 1e6, 3)},
         "kernel_avg_us": kern,
         "mlups_total": round((nx * ny + info.n_sub * info.nnode) * steps / dt / 1e6, 2),
         "theta": None if th is None else [th.real, th.imag],
