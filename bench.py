@@ -710,7 +710,7 @@ def main():
     ap.add_argument("--workload", default="lamina_2048")
     ap.add_argument("--storage", default="f64", choices=list(BYTES))
     ap.add_argument("--timing-steps", type=int, default=160)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--adjoint-workload", default="lamina_1024")
     ap.add_argument("--adjoint-storage", default="f32", choices=list(BYTES))
