@@ -2424,9 +2424,10 @@ int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny, double 
   int a = 0, b = 0;
   double t = 0.0;
   int rc = HLBM_E_STATE;
-  if (auto *m = dynamic_cast<mghlbm::MultiLevel<double, double> *>(h->c.get())) rc = m->shape(level, &a, &b, &t);
-  else if (auto *m = dynamic_cast<mghlbm::MultiLevel<float, float> *>(h->c.get())) rc = m->shape(level, &a, &b, &t);
-  else if (auto *m = dynamic_cast<mghlbm::MultiLevel<__half, float> *>(h->c.get())) rc = m->shape(level, &a, &b, &t);
+  if (auto *m64 = dynamic_cast<mghlbm::MultiLevel<double, double> *>(h->c.get())) rc = m64->shape(level, &a, &b, &t);
+  else if (auto *m32 = dynamic_cast<mghlbm::MultiLevel<float, float> *>(h->c.get())) rc = m32->shape(level, &a, &b, &t);
+  else if (auto *m16 = dynamic_cast<mghlbm::MultiLevel<__half, float> *>(h->c.get()))
+    rc = m16->shape(level, &a, &b, &t);
   if (rc == HLBM_E_STATE) h->c->err = "not a multi-level handle";
   else if (rc != HLBM_OK) h->c->err = "level out of range";
   if (rc != HLBM_OK) return rc;

@@ -129,13 +129,13 @@ bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, st
             V += area / 3.0;
             for (int q = 0; q < 3; ++q) {
               const int qb = (q + 1) % 3, qc = (q + 2) % 3;
-              const double gx = -(py[qc] - py[qb]) / (2.0 * area);
-              const double gy = (px[qc] - px[qb]) / (2.0 * area);
+              const double dphx = -(py[qc] - py[qb]) / (2.0 * area);
+              const double dphy = (px[qc] - px[qb]) / (2.0 * area);
               const int cq = t.v[q];
               const int sdi = (cq & 1) - (me & 1), sdj = (cq >> 1) - (me >> 1);
               const int s = (sdj + 1) * 3 + (sdi + 1);
-              Gx[s] -= (area / 3.0) * gx;
-              Gy[s] -= (area / 3.0) * gy;
+              Gx[s] -= (area / 3.0) * dphx;
+              Gy[s] -= (area / 3.0) * dphy;
               C[s] += area * (q == a ? 11.0 / 54.0 : 7.0 / 108.0);
             }
           }
