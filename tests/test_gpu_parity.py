@@ -195,6 +195,41 @@ def test_lamina_2048_first_steps(oracle):
     _check_state(o, g)
 
 
+def _host_threads():
+    import os
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return min(n, int(env)) if env.isdigit() and int(env) > 0 else n
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name,steps,schedule", [
+    # the schedule the autotuner picks for the 2048^2 FP64 benchmark line
+    ("lamina_2048", 26, dict(variant=1, lattice=(128, 1), order=1)),
+    # and for the 4096^2 FP64 precision line
+    ("lamina_4096", 10, dict(variant=9, lattice=(256, 1), order=0)),
+])
+def test_full_size_in_benchmark_configuration(oracle, name, steps, schedule):
+    """The benchmark workloads at full size in the launch configuration the
+    benchmark times: its tuned schedule, pairs of steps on the two-step
+    lattice path, and 8 steps per HIP graph replayed from several buffer
+    arrangements (26 steps: three graphs and a pair; 10: one graph and a
+    pair). Whole-array comparison. The oracle runs its per-node loops on
+    every host core, which leaves its bits unchanged."""
+    _say(name, steps, "steps, schedule", schedule)
+    oracle.set_threads(_host_threads())
+    try:
+        o, g, _ = _pair(oracle, preset(name), steps=steps)
+        t = g.tune(**schedule)
+        assert t["substep_variant"] == schedule["variant"]
+        assert g.info().two_step == 1
+        o.step(steps)
+        g.step(steps)
+        _check_state(o, g)
+    finally:
+        oracle.set_threads(1)
+
+
 @pytest.mark.parametrize("storage,tol", [(hlbm.FP32, 2e-3), (hlbm.FP16_DEV, 3e-2)])
 def test_reduced_precision_theta(storage, tol):
     """FP32 and FP16-deviation storage against the FP64 run of the
