@@ -95,6 +95,38 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dic
     return res
 
 
+def counters(path: str, kernels: list) -> str:
+    """Mean per dispatch of every counter in a rocprofv3 --pmc CSV for each
+    kernel (a name matches when it contains the given text), and ratios of
+    counters whose units cancel."""
+    rows = list(csv.DictReader(open(path)))
+    names = sorted({r["Counter_Name"] for r in rows})
+    out = []
+    for k in kernels:
+        mean = {}
+        for c in names:
+            vs = [v for n, lst in _per_dispatch(path, c).items() if k in n for v in lst]
+            if vs:
+                mean[c] = (sum(vs) / len(vs), len(vs))
+        if not mean:
+            out.append(f"{k}: no dispatch")
+            continue
+        out.append(f"{k}  ({max(n for _, n in mean.values())} dispatches)")
+        for c, (v, _) in mean.items():
+            out.append(f"  {c:<24s} {v:16.1f}")
+        g = {c: v for c, (v, _) in mean.items()}
+        ratios = [("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "wave cycles waiting on any instruction"),
+                  ("SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES", "wave cycles waiting on LDS"),
+                  ("SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "wave cycles issuing VALU"),
+                  ("SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS", "bank-conflict cycles per LDS instruction"),
+                  ("SQ_INSTS_VALU", "SQ_WAVES", "VALU instructions per wave"),
+                  ("SQ_INSTS_LDS", "SQ_WAVES", "LDS instructions per wave")]
+        for a, b, label in ratios:
+            if a in g and b in g and g[b] > 0:
+                out.append(f"  {a} / {b} = {g[a] / g[b]:.3f}  ({label})")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -106,6 +138,12 @@ def main(argv=None):
     s.add_argument("--kernel", default="k_stream_collide")
     s.add_argument("--windows")
     s.add_argument("--note", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--kernels", required=True, help="texts a kernel name must contain, separated by ';'")
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--note", default="")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -116,6 +154,14 @@ def main(argv=None):
     t.add_argument("--out", required=True)
     t.add_argument("--command", required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        text = (f"# rocprofv3 counters, mean per dispatch\n# command: {a.command}\n"
+                + counters(a.csv, a.kernels.split(";")) + "\n")
+        if a.note:
+            text += "".join(f"# {line}\n" for line in a.note.split("\n"))
+        open(a.out, "w").write(text)
+        print(text)
+        return
     if a.cmd == "stats":
         text = f"# rocprofv3 kernel statistics\n# command: {a.command}\n" + stats_table(a.csv) + "\n"
         if a.trace and a.windows:
