@@ -5,17 +5,17 @@ cent of it (Fig. results); a confined 8b x 8b domain adds a few per cent more
 (Table sensitivity). This is context, not parity: it guards against gross
 errors (a wrong sign, a lost wall term) that the unit pins could miss.
 
-It takes about two minutes on one core, so it runs only with HLBM_SLOW=1.
+It takes about two minutes on one core; the oracle's per-node loops run on
+every core the process may use (which leaves its bits unchanged).
 """
 import math
 import os
 
-import pytest
-
 from physics_refs import theta_semianalytical
 
-pytestmark = pytest.mark.skipif(os.environ.get("HLBM_SLOW") != "1",
-                                reason="two-minute oracle run; set HLBM_SLOW=1")
+
+def _cores():
+    return max(1, len(os.sched_getaffinity(0)))
 
 
 def test_theta_near_semianalytical(oracle):
@@ -25,7 +25,11 @@ def test_theta_near_semianalytical(oracle):
     period = 2 * math.pi / (2 * math.pi * nu * beta / b ** 2)
     steps = int(4 * period) + 2
     s = oracle.Sim(N, N, 64, 32, 1.0, b, 1.0, tau, kc, beta, max_steps=steps)
-    s.step(steps)
+    oracle.set_threads(_cores())
+    try:
+        s.step(steps)
+    finally:
+        oracle.set_threads(1)
     inf = s.info()
     th = oracle.fit_theta(s.history(), inf.omega, inf.A, b)
     ref = theta_semianalytical(beta, eps)
