@@ -205,17 +205,18 @@ def _host_threads():
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("name,steps,schedule", [
     # the schedule the autotuner picks for the 2048^2 FP64 benchmark line
-    ("lamina_2048", 26, dict(variant=1, lattice=(128, 1), order=1)),
+    ("lamina_2048", 202, dict(variant=1, lattice=(128, 1), order=1)),
     # and for the 4096^2 FP64 precision line
-    ("lamina_4096", 10, dict(variant=9, lattice=(256, 1), order=0)),
+    ("lamina_4096", 26, dict(variant=9, lattice=(256, 1), order=0)),
 ])
 def test_full_size_in_benchmark_configuration(oracle, name, steps, schedule):
     """The benchmark workloads at full size in the launch configuration the
     benchmark times: its tuned schedule, pairs of steps on the two-step
     lattice path, and 8 steps per HIP graph replayed from several buffer
-    arrangements (26 steps: three graphs and a pair; 10: one graph and a
-    pair). Whole-array comparison. The oracle runs its per-node loops on
-    every host core, which leaves its bits unchanged."""
+    arrangements, ending on a pair. Over 202 steps the 2048^2 grid moves
+    about 20 lattice units, through every kind of refill. Whole-array
+    comparison. The oracle runs its per-node loops on every host core,
+    which leaves its bits unchanged."""
     _say(name, steps, "steps, schedule", schedule)
     oracle.set_threads(_host_threads())
     try:
