@@ -878,6 +878,13 @@ def main():
                      "us_per_step": round(avg_s * 1e6 / (2 if two else 1), 3),
                      "single_step_floor_us": round(alg_bytes / (HBM_PEAK_GBS * 1e9) * 1e6, 3)},
         "kernel_avg_us": kern,
+        # the grid path is L2 / LDS resident and latency-bound: its time per
+        # sub-step, and the algorithmic bytes of a sub-step (read and write
+        # 9 populations per grid node) over that time
+        "grid": None if not kern.get("grid_substeps") or not info.n_sub else {
+            "us_per_substep": round(kern["grid_substeps"] / info.n_sub, 3),
+            "algorithmic_gbs": round(18 * BYTES[args.storage] * info.nnode
+                                     / (kern["grid_substeps"] / info.n_sub * 1e-6) / 1e9, 1)},
         "mlups_total": round((nx * ny + info.n_sub * info.nnode) * steps / dt / 1e6, 2),
         "theta": None if th is None else [th.real, th.imag],
     }
