@@ -681,7 +681,9 @@ or_mesh *or_mesh_periodic(int32_t nx, int32_t ny, double h) {
   return mesh_finish(m);
 }
 
-or_mesh *or_mesh_channel(int32_t nx, int32_t ny, double h) {
+/* grid periodic in x, node (i, j) at (i h, j h); row 0 is a wall, the top
+ * row a wall (a channel) or the outer boundary (a band on a wall) */
+static or_mesh *mesh_strip(int32_t nx, int32_t ny, double h, int top_type) {
   if (nx < 3 || ny < 3 || !(h > 0.0)) return NULL;
   or_mesh *m = mesh_alloc(nx * ny, 2 * nx * (ny - 1));
   if (!m) return NULL;
@@ -689,7 +691,7 @@ or_mesh *or_mesh_channel(int32_t nx, int32_t ny, double h) {
     for (int i = 0; i < nx; ++i) {
       m->x[j * nx + i] = i * h;
       m->y[j * nx + i] = j * h;
-      m->type[j * nx + i] = (j == 0 || j == ny - 1) ? OR_NODE_WALL : OR_NODE_INTERIOR;
+      m->type[j * nx + i] = (j == 0) ? OR_NODE_WALL : (j == ny - 1) ? top_type : OR_NODE_INTERIOR;
     }
   int nt = 0;
   for (int cj = 0; cj < ny - 1; ++cj)
@@ -701,6 +703,8 @@ or_mesh *or_mesh_channel(int32_t nx, int32_t ny, double h) {
   m->ntri = nt;
   return mesh_finish(m);
 }
+
+or_mesh *or_mesh_channel(int32_t nx, int32_t ny, double h) { return mesh_strip(nx, ny, h, OR_NODE_WALL); }
 
 void or_mesh_stencil(const or_mesh *m, int32_t kmax, int32_t *nbr, double *S,
                      double *C, double *V) {
@@ -851,6 +855,12 @@ struct or_sim {
   double M, Ks, Cd, y_max;
   double y_cur, y_prev, v_cur;
   double *mhist; /* [hist_cap + 1][2]: (y, v) at t_k */
+  int plant;             /* OR_FLAG_PLANT_* (tests only) */
+  double u_bot, u_top;   /* tangential velocities of the lattice's y walls */
+  /* wall band (or_create_wallband): a static grid on a tangentially
+   * oscillating wall, periodic in x, in place of the lamina grid */
+  int band;
+  double band_U, band_omega;
 };
 
 /* prescribed motion y(t) = A sin(omega t) (Sec. Problem statement), t = k */
@@ -884,6 +894,13 @@ static int lattice_status(const rect_t *r, int x, int y) {
   return 2;
 }
 
+int or_set_walls(or_sim *s, double u_bot, double u_top) {
+  if (!s || s->bc != OR_BC_PERIODIC_X_WALLS_Y) return OR_E_ARG;
+  s->u_bot = u_bot;
+  s->u_top = u_top;
+  return OR_OK;
+}
+
 int32_t or_lattice_status(const or_sim *s, int64_t k, int32_t x, int32_t y) {
   if (!s->m) return 0;
   rect_t r = rect_at(s, RE(motion_y(s, k)));
@@ -912,6 +929,8 @@ static int create_sim(const or_config *c, const double *X, const double *Y, or_s
   const int body = has_mesh && c->b > 0.0 && !(c->flags & OR_FLAG_NO_BODY);
   or_sim *s = xcalloc(1, sizeof(or_sim));
   if (!s) return OR_E_NOMEM;
+  s->plant = c->flags & (OR_FLAG_PLANT_S_FACTOR | OR_FLAG_PLANT_NO_KNEQ | OR_FLAG_PLANT_SWAP_BILIN_Y |
+                         OR_FLAG_PLANT_SWAP_BILIN_X | OR_FLAG_PLANT_BARY);
   s->nx = c->nx;
   s->ny = c->ny;
   s->nux = c->nux;
@@ -1025,6 +1044,55 @@ static int create_sim(const or_config *c, const double *X, const double *Y, or_s
 
 int or_create(const or_config *c, or_sim **out) { return create_sim(c, NULL, NULL, out); }
 
+/* A static grid band on a tangentially oscillating wall (see the header):
+ * the lattice of create_sim without a lamina, then the band grid, its
+ * arrays and the fictitious line y = y_wall + nband - 1 - margin. */
+int or_create_wallband(const or_config *c, int32_t nband, double x_off, double y_wall, double U,
+                       double omega, or_sim **out) {
+  if (!c || !out) return OR_E_ARG;
+  *out = NULL;
+  if (c->bc != OR_BC_PERIODIC_X_WALLS_Y || nband < 4 || !(x_off >= 0.0 && x_off < 1.0) ||
+      !(y_wall >= 0.0) || !(y_wall + nband + 2.0 < c->ny - 2.0) || c->n_sub < 0)
+    return OR_E_ARG;
+  or_config lc = *c;
+  lc.nux = 0;
+  lc.nuy = 0;
+  lc.b = 0.0;
+  or_sim *s = NULL;
+  int rc = create_sim(&lc, NULL, NULL, &s);
+  if (rc != OR_OK) return rc;
+  if (!(s->dt_u < 2.0 * RE(s->tau_u))) { free_sim(s); return OR_E_ARG; }
+  s->m = mesh_strip(c->nx, nband, 1.0, OR_NODE_INTERFACE);
+  if (!s->m) { free_sim(s); return OR_E_ARG; }
+  s->band = 1;
+  s->band_U = U;
+  s->band_omega = omega;
+  s->nux = c->nx;
+  s->nuy = nband;
+  s->xc = x_off;
+  s->yc = y_wall;
+  s->ex0 = -1e300;
+  s->ex1 = 1e300;
+  s->ey0 = -1e300;
+  s->ey1 = (double)(nband - 1);
+  const int N = s->m->nnode;
+  s->fu = malloc((size_t)9 * N * sizeof(real));
+  s->fu2 = malloc((size_t)9 * N * sizeof(real));
+  s->star_eq = xcalloc((size_t)9 * N, sizeof(real));
+  s->star_neq = xcalloc((size_t)9 * N, sizeof(real));
+  s->uwx = xcalloc(N, sizeof(real));
+  s->uwy = xcalloc(N, sizeof(real));
+  if (!s->fu || !s->fu2 || !s->star_eq || !s->star_neq || !s->uwx || !s->uwy) {
+    free_sim(s);
+    return OR_E_NOMEM;
+  }
+  for (int i = 0; i < 9; ++i)
+    for (int p = 0; p < N; ++p) s->fu[(size_t)i * N + p] = WT[i];
+  *out = s;
+  return OR_OK;
+}
+
+
 /* threads of the per-node loops: 1 unless asked (1 without OpenMP); n <= 0
  * leaves the setting alone; returns the number in effect */
 int or_set_threads(int32_t n) {
@@ -1049,7 +1117,7 @@ int or_create_graded(const or_config *c, const double *X, const double *Y, or_si
  * post-collision buffer of t_k (the pre-collision f of Eq.(LBE)'s left side) */
 static void lattice_pre(const or_sim *s, int x, int y, real f[9]) {
   pull_node(s->fA, s->nx, s->ny, s->bc, wrap(x, s->nx), s->bc == OR_BC_PERIODIC ? wrap(y, s->ny) : y,
-            0.0, 0.0, f);
+            s->u_bot, s->u_top, f);
 }
 
 /* Bilinear Lagrange interpolation over the four lattice nodes of the cell
@@ -1060,7 +1128,9 @@ static void lattice_bilinear(const or_sim *s, double X, real Y, real *rho,
                              real *ux, real *uy, real fneq[9]) {
   const double fx = floor(X), fy = floor(RE(Y));
   const int x0 = (int)fx, y0 = (int)fy;
-  const real a = X - fx, bb = Y - fy;
+  real a = X - fx, bb = Y - fy;
+  if (s->plant & OR_FLAG_PLANT_SWAP_BILIN_X) a = 1.0 - a;
+  if (s->plant & OR_FLAG_PLANT_SWAP_BILIN_Y) bb = 1.0 - bb;
   const real wgt[4] = {(1.0 - a) * (1.0 - bb), a * (1.0 - bb), (1.0 - a) * bb, a * bb};
   const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
   *rho = 0.0;
@@ -1079,42 +1149,97 @@ static void lattice_bilinear(const or_sim *s, double X, real Y, real *rho,
   }
 }
 
-/* Eq.(postcollision2_s) at lattice node (x,y) from the grid at offset y_k:
- * barycentric interpolation of rho, u and f^neq,u over the enclosing triangle,
- * f^eq rebuilt from the interpolated moments. */
-static int lattice_from_grid(or_sim *s, int x, int y, real yk) {
+/* planted mistake (tests only): the barycentric weights in a rotated vertex
+ * order */
+static void plant_rotate(const or_sim *s, real lam[3]) {
+  if (!(s->plant & OR_FLAG_PLANT_BARY)) return;
+  const real l0 = lam[0];
+  lam[0] = lam[1];
+  lam[1] = lam[2];
+  lam[2] = l0;
+}
+
+/* Barycentric interpolation of the grid at lattice position (X, Y) with the
+ * grid at offset yk: density, velocity and f^neq,u = f^u - f^eq(rho^u, u^u)
+ * over the enclosing triangle (Sec. Refill procedure: barycentric on the
+ * grid; reading: the moments and f^neq are interpolated, f^eq is rebuilt
+ * from the interpolated moments). A band grid is periodic in x. */
+static int grid_interp(const or_sim *s, double X, real Y, real yk, real *rho, real *ux, real *uy,
+                       real fneq[9]) {
   const or_mesh *m = s->m;
   const int N = m->nnode;
   double lam0[3];
-  const real px = (double)x - s->xc, py = (double)y - (s->yc + yk);
-  const int t = or_mesh_locate(m, RE(px), RE(py), lam0);
+  double px = X - s->xc;
+  if (s->band) px -= (double)s->nx * floor(px / (double)s->nx);
+  const real py = Y - (s->yc + yk);
+  const int t = or_mesh_locate(m, px, RE(py), lam0);
   if (t < 0) return OR_E_STATE;
   real lam[3];
   bary_r(&m->txy[6 * t], px, py, lam);
-  real rho = 0.0, ux = 0.0, uy = 0.0, fneq[9] = {0};
+  plant_rotate(s, lam);
+  *rho = 0.0;
+  *ux = 0.0;
+  *uy = 0.0;
+  for (int i = 0; i < 9; ++i) fneq[i] = 0.0;
   for (int a = 0; a < 3; ++a) {
     const int p = m->tri[3 * t + a];
     real f[9], e[9], r, vx, vy;
     for (int i = 0; i < 9; ++i) f[i] = s->fu[(size_t)i * N + p];
     moments(f, &r, &vx, &vy);
     feq_r(r, vx, vy, e);
-    rho += lam[a] * r;
-    ux += lam[a] * vx;
-    uy += lam[a] * vy;
+    *rho += lam[a] * r;
+    *ux += lam[a] * vx;
+    *uy += lam[a] * vy;
     for (int i = 0; i < 9; ++i) fneq[i] += lam[a] * (f[i] - e[i]);
   }
+  return OR_OK;
+}
+
+/* Eq.(postcollision2_s) at lattice node (x,y) from the grid at offset y_k:
+ * the interpolated moments and f^neq,u of grid_interp, written as the
+ * post-collision populations f^eq + 2 (tau_s - 1)/(2 tau_s - 1) f^neq,u. */
+static int lattice_from_grid(or_sim *s, int x, int y, real yk) {
+  real rho, ux, uy, fneq[9];
+  if (grid_interp(s, (double)x, (double)y, yk, &rho, &ux, &uy, fneq) != OR_OK) return OR_E_STATE;
   real e[9];
   feq_r(rho, ux, uy, e);
-  const real g = 2.0 * (s->tau_s - 1.0) / (2.0 * s->tau_s - 1.0);
+  const real g = (s->plant & OR_FLAG_PLANT_S_FACTOR) ? 1.0 - 1.0 / s->tau_s
+                                                     : 2.0 * (s->tau_s - 1.0) / (2.0 * s->tau_s - 1.0);
   for (int i = 0; i < 9; ++i) s->fA[lidx(s->nx, s->ny, i, x, y)] = e[i] + g * fneq[i];
   return OR_OK;
 }
+
+#ifndef OR_COMPLEX_STEP
+int or_probe_bilinear(const or_sim *s, double X, double Y, double out[12]) {
+  if (!s || !out) return OR_E_ARG;
+  real rho, ux, uy, fneq[9];
+  lattice_bilinear(s, X, Y, &rho, &ux, &uy, fneq);
+  out[0] = rho;
+  out[1] = ux;
+  out[2] = uy;
+  for (int i = 0; i < 9; ++i) out[3 + i] = fneq[i];
+  return OR_OK;
+}
+
+int or_probe_grid(const or_sim *s, double X, double Y, double out[12]) {
+  if (!s || !out || !s->m) return OR_E_ARG;
+  real rho, ux, uy, fneq[9];
+  const real yk = s->fsi ? s->y_cur : motion_y(s, s->k);
+  if (grid_interp(s, X, Y, yk, &rho, &ux, &uy, fneq) != OR_OK) return OR_E_STATE;
+  out[0] = rho;
+  out[1] = ux;
+  out[2] = uy;
+  for (int i = 0; i < 9; ++i) out[3 + i] = fneq[i];
+  return OR_OK;
+}
+#endif
 
 /* Refill after the move from y_k to y_k1 (Sec. Refill procedure). */
 static void refill(or_sim *s, real yk, real yk1) {
   const or_mesh *m = s->m;
   const int N = m->nnode;
-  const real kneq = 1.0 - 1.0 / (2.0 * s->tau_s); /* Eq.(continuity_stresses) */
+  /* Eq.(continuity_stresses) */
+  const real kneq = (s->plant & OR_FLAG_PLANT_NO_KNEQ) ? 1.0 : 1.0 - 1.0 / (2.0 * s->tau_s);
   for (int p = 0; p < N; ++p) {
     real out[9];
     if (m->type[p] == OR_NODE_WALL) {
@@ -1128,7 +1253,10 @@ static void refill(or_sim *s, real yk, real yk1) {
       double lam0[3];
       real lam[3];
       const int t = or_mesh_locate(m, X - s->xc, RE(py), lam0);
-      if (t >= 0) bary_r(&m->txy[6 * t], X - s->xc, py, lam);
+      if (t >= 0) {
+        bary_r(&m->txy[6 * t], X - s->xc, py, lam);
+        plant_rotate(s, lam);
+      }
       if (t >= 0) {
         /* type 3: barycentric interpolation in the old triangle */
         for (int i = 0; i < 9; ++i) {
@@ -1163,7 +1291,7 @@ int or_step(or_sim *s, int64_t nsteps) {
   for (int64_t it = 0; it < nsteps; ++it) {
     const int64_t k = s->k;
     if (!s->m) {
-      lattice_step_r(s->fA, s->fB, nx, ny, s->bc, s->tau_s, 0.0, 0.0, NULL);
+      lattice_step_r(s->fA, s->fB, nx, ny, s->bc, s->tau_s, s->u_bot, s->u_top, NULL);
     } else {
       const or_mesh *m = s->m;
       const int N = m->nnode;
@@ -1183,10 +1311,10 @@ int or_step(or_sim *s, int64_t nsteps) {
             if (lattice_from_grid(s, x, y, yk) != OR_OK) return OR_E_STATE;
         }
       /* 2. Eq.(LBE) on the discretization nodes */
-      lattice_step_r(s->fA, s->fB, nx, ny, s->bc, s->tau_s, 0.0, 0.0, s->disc);
+      lattice_step_r(s->fA, s->fB, nx, ny, s->bc, s->tau_s, s->u_bot, s->u_top, s->disc);
       /* 3. structured-derived values at the grid's outer nodes, from the
        *    lattice at t_{k+1} (pre-collision), held over the n sub-steps */
-      const real kneq = 1.0 - 1.0 / (2.0 * s->tau_s);
+      const real kneq = (s->plant & OR_FLAG_PLANT_NO_KNEQ) ? 1.0 : 1.0 - 1.0 / (2.0 * s->tau_s);
       for (int p = 0; p < N; ++p) {
         if (m->type[p] != OR_NODE_INTERFACE) continue;
         real rho, ux, uy, fneq[9], e[9];
@@ -1208,6 +1336,11 @@ int or_step(or_sim *s, int64_t nsteps) {
           s->uwx[p] = 0.0;
           s->uwy[p] = uw;
         }
+        if (s->band) /* the band's wall moves tangentially */
+          for (int p = 0; p < N; ++p) {
+            s->uwx[p] = s->band_U * cos(s->band_omega * t);
+            s->uwy[p] = 0.0;
+          }
         fv_substep_r(m, s->fu, s->star_eq, s->star_neq, s->fu2, s->tau_u, s->dt_u, s->uwx, s->uwy);
         real *tmp = s->fu;
         s->fu = s->fu2;
@@ -1237,8 +1370,8 @@ int or_step(or_sim *s, int64_t nsteps) {
         s->mhist[2 * (s->hist_n - 1) + 1] = v1;
       }
 #endif
-      /* 6. move the grid to y_{k+1} and refill it */
-      refill(s, yk, yk1);
+      /* 6. move the grid to y_{k+1} and refill it (a wall band stays put) */
+      if (!s->band) refill(s, yk, yk1);
     }
     real *tmp = s->fA;
     s->fA = s->fB;

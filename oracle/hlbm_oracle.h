@@ -63,6 +63,17 @@ typedef struct or_config {
 /* grid without the lamina slot (b still sets A and omega); for invariance
  * checks of the moving-grid coupling */
 #define OR_FLAG_NO_BODY 1
+/* planted mistakes in the lattice-grid exchange, for tests that show the pins
+ * of the interface detect them */
+#define OR_FLAG_PLANT_S_FACTOR 2   /* Eq.(postcollision2_s) with 1 - 1/tau_s in place
+                                      of 2 (tau_s - 1)/(2 tau_s - 1)              */
+#define OR_FLAG_PLANT_NO_KNEQ 4    /* f^neq,s not rescaled by 1 - 1/(2 tau_s) in the
+                                      interface donors and the type-1 refill      */
+#define OR_FLAG_PLANT_SWAP_BILIN_Y 8  /* bilinear weights mirrored in y           */
+#define OR_FLAG_PLANT_SWAP_BILIN_X 16 /* bilinear weights mirrored in x           */
+#define OR_FLAG_PLANT_BARY 32      /* barycentric weights of the grid interpolation
+                                      and the type-3 refill taken in a rotated
+                                      vertex order                                */
 
 typedef struct or_info {
   double nu, tau_u, dt_u, A, omega, period, u_max, mach, reynolds, eps;
@@ -151,6 +162,28 @@ int or_set_motion(or_sim *s, double M, double K, double C, double y0, double v0,
 int64_t or_motion_history(const or_sim *s, double *out, int64_t cap);
 /* status of lattice node (x,y) at step k: 0 disc, 1 interpolation, 2 unused */
 int32_t or_lattice_status(const or_sim *s, int64_t k, int32_t x, int32_t y);
+/* tangential x-velocities of the lattice's y walls (bc 0; both 0 unless set) */
+int or_set_walls(or_sim *s, double u_bot, double u_top);
+/* A case whose grid is a band on a wall instead of a lamina: the band is
+ * periodic in x with cfg->nx columns and nband rows of unit spacing, node
+ * (i, j) at lattice position (x_off + i, y_wall + j); row 0 lies on a wall
+ * that moves tangentially with velocity U cos(omega t), the top row takes
+ * Eq.(postcollision2_u) from the lattice, and lattice nodes below the band's
+ * top row minus the margin of 2 are carried by the grid (the fictitious line
+ * of Sec. Refill procedure becomes y = y_wall + nband - 3). The grid does not
+ * move. Used by the Stokes-layer pin of the lattice-grid interface.
+ * cfg: nx, ny, tau, n_sub, bc (must be OR_BC_PERIODIC_X_WALLS_Y), flags
+ * (planted mistakes only), max_steps; the other fields are ignored. */
+int or_create_wallband(const or_config *cfg, int32_t nband, double x_off, double y_wall, double U,
+                       double omega, or_sim **out);
+/* Probes of the two interpolations of the exchange, for tests. Both return
+ * (rho, ux, uy, f^neq[9]) at a point given in lattice coordinates:
+ * or_probe_bilinear over the four lattice nodes of the enclosing cell, from
+ * the pre-collision populations at t_{k+1} (type-1 refill and interface
+ * donors); or_probe_grid over the enclosing grid triangle at the current
+ * offset (Eq.(postcollision2_s)). OR_E_STATE if no triangle holds the point. */
+int or_probe_bilinear(const or_sim *s, double X, double Y, double out[12]);
+int or_probe_grid(const or_sim *s, double X, double Y, double out[12]);
 
 /* ---- structured refinement levels ------------------------------------ */
 /* Level 0 is an nx0 x ny0 lattice with boundaries bc0 (walls may move with

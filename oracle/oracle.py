@@ -30,6 +30,12 @@ BC_RING = 3
 ML_PLANT_NO_RESCALE = 256
 ML_PLANT_SAME_TAU = 512
 FLAG_NO_BODY = 1
+# planted mistakes in the lattice-grid exchange (tests show the pins catch them)
+PLANT_S_FACTOR = 2       # 1 - 1/tau_s in place of Eq.(postcollision2_s)'s 2(tau_s-1)/(2tau_s-1)
+PLANT_NO_KNEQ = 4        # the (1 - 1/(2 tau_s)) rescale of f^neq,s dropped
+PLANT_SWAP_BILIN_Y = 8   # bilinear weights mirrored in y
+PLANT_SWAP_BILIN_X = 16  # bilinear weights mirrored in x
+PLANT_BARY = 32          # barycentric weights in a rotated vertex order
 NODE_INTERIOR, NODE_INTERFACE, NODE_WALL = 0, 1, 2
 
 
@@ -108,6 +114,11 @@ def lib():
         L.or_history.restype = C.c_int64
         L.or_lattice_status.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32]
         L.or_lattice_status.restype = C.c_int32
+        L.or_set_walls.argtypes = [vp, C.c_double, C.c_double]
+        L.or_create_wallband.argtypes = [C.POINTER(Config), C.c_int32, C.c_double, C.c_double,
+                                         C.c_double, C.c_double, C.POINTER(vp)]
+        for f in ("or_probe_bilinear", "or_probe_grid"):
+            getattr(L, f).argtypes = [vp, C.c_double, C.c_double, _D]
         L.or_fit_theta.argtypes = [_D, C.c_int64, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_double, _D]
         L.or_set_threads.argtypes = [C.c_int32]
@@ -353,6 +364,43 @@ class Sim:
         out = np.zeros((max(n, 1), 2))
         lib().or_motion_history(self.ptr, out, n)
         return out[:n]
+
+    @classmethod
+    def wallband(cls, nx, ny, nband, tau, U, omega, x_off=0.0, y_wall=0.0, n_sub=0, flags=0,
+                 max_steps=0):
+        """A static grid band of nband rows on a wall oscillating tangentially
+        with U cos(omega t), the lattice above it (or_create_wallband)."""
+        self = cls.__new__(cls)
+        self.cfg = Config(nx, ny, 0, 0, 1.0, 0.0, 1.0, tau, 0.0, 0.0, n_sub,
+                          BC_PERIODIC_X_WALLS_Y, flags, max_steps)
+        h = C.c_void_p()
+        rc = lib().or_create_wallband(C.byref(self.cfg), nband, x_off, y_wall, U, omega, C.byref(h))
+        if rc != 0:
+            raise ValueError(f"or_create_wallband rejected the configuration (code {rc})")
+        self.ptr = h
+        self.nx, self.ny = nx, ny
+        self.nnode = self.info().nnode
+        return self
+
+    def set_walls(self, u_bot, u_top):
+        """Tangential x-velocities of the lattice's y walls (bc 0)."""
+        if lib().or_set_walls(self.ptr, u_bot, u_top) != 0:
+            raise ValueError("moving walls need bc BC_PERIODIC_X_WALLS_Y")
+
+    def probe_bilinear(self, X, Y):
+        """(rho, ux, uy, f^neq[9]) bilinear from the lattice's pre-collision
+        populations at t_{k+1}, at lattice position (X, Y)."""
+        out = np.zeros(12)
+        lib().or_probe_bilinear(self.ptr, X, Y, out)
+        return out
+
+    def probe_grid(self, X, Y):
+        """(rho, ux, uy, f^neq[9]) barycentric from the grid at its current
+        offset, at lattice position (X, Y)."""
+        out = np.zeros(12)
+        if lib().or_probe_grid(self.ptr, X, Y, out) != 0:
+            raise ValueError("no grid triangle holds the point")
+        return out
 
     def status(self, k):
         return np.array([[lib().or_lattice_status(self.ptr, k, x, y) for x in range(self.nx)]
