@@ -31,7 +31,8 @@ def build(verbose: bool = False) -> str:
     objs = []
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wshadow",
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    for src in SOURCES:
+    procs = []
+    for src in SOURCES:  # the sources compile independently, in parallel
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         # forward kernels: no contraction of a*b+c, so an expression rounds the
         # same wherever it is inlined (single-case and case-batched kernels
@@ -42,8 +43,11 @@ def build(verbose: bool = False) -> str:
                *common, contract, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
