@@ -321,6 +321,28 @@ int hlbm_get_state(hlbm_t *h, int32_t case_id, int32_t which, void *host_buf,
 int hlbm_set_state(hlbm_t *h, int32_t case_id, int32_t which,
                    const void *host_buf, size_t bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as hlbm_get_state for which = HLBM_STATE_LATTICE or HLBM_STATE_GRID (the
+ * same bits), but it calls no hipMalloc, hipFree or other allocating
+ * routine. hlbm_get_state converts the state to FP64 in a device buffer it
+ * allocates for the call; this variant converts one population plane at a
+ * time, in pieces of at most HLBM_NOALLOC_SCRATCH_BYTES, in a static device
+ * buffer of that size which each GPU the library runs on holds until the
+ * process ends, and copies each piece to host_buf before converting the
+ * next, so a state of any size is read and no size exceeds the buffer.
+ * Every call on a GPU shares that GPU's buffer: calls that overlap on one
+ * GPU (from several host threads) race and must be serialized by the
+ * caller. Blocks until the copy is done. Errors: HLBM_E_ARG (another
+ * selector, a case_id out of range, NULL host_buf, or bytes not 8 times the
+ * array's size in doubles), HLBM_E_STATE (HLBM_STATE_GRID of a case without
+ * a grid), HLBM_E_HIP (the device address of the buffer could not be
+ * obtained, or a copy failed). A multi-level handle reads its finest level
+ * and grid; its coarser levels are not read this way. */
+#define HLBM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20) /* 64 MiB per GPU */
+int hlbm_get_state_noalloc(hlbm_t *h, int32_t case_id, int32_t which,
+                           void *host_buf, size_t bytes);
+
 /* Derived parameters and counters. */
 int hlbm_info_get(hlbm_t *h, int32_t case_id, hlbm_info *out);
 

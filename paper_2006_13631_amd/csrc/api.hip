@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -22,8 +23,61 @@
 #include "hlbm.h"
 #include "kernels.h"
 
+// Staging buffer of hlbm_get_state_noalloc: one per GPU, held from module
+// load until the process ends. Host code must not use its name as an address
+// (it is a host-side stand-in); scratch_on() looks up the device address.
+static __device__ __align__(256) double scratch[(size_t)HLBM_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
 namespace mghlbm {
 namespace {
+
+constexpr size_t kScratchElems = (size_t)HLBM_NOALLOC_SCRATCH_BYTES / sizeof(double);
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, taken once per device with that
+// device current (each GPU holds its own copy at its own address).
+hipError_t scratch_on(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Nine population planes of `per` values each (plane q at element q * stride
+// of the device array) to the packed FP64 host array out[9][per]: launch(q,
+// a, n, buf) converts values a .. a+n-1 of plane q into buf (at most `cap`
+// doubles), which is then copied out; the pieces follow each other on
+// stream s, so a conversion never overwrites a piece still being copied.
+template <class Launch>
+hipError_t stage_planes(double *out, size_t per, double *buf, size_t cap, hipStream_t s, Launch launch) {
+  for (int q = 0; q < 9; ++q)
+    for (size_t a = 0; a < per; a += cap) {
+      const size_t n = std::min(cap, per - a);
+      launch(q, a, n, buf);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(out + (size_t)q * per + a, buf, n * sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return e;
+    }
+  return hipStreamSynchronize(s);
+}
 
 std::string g_create_error;
 
@@ -65,6 +119,15 @@ class CaseBase {
   virtual int step(int64_t n) = 0;
   virtual int get_state(int which, void *buf, size_t bytes) = 0;
   virtual int set_state(int which, const void *buf, size_t bytes) = 0;
+  // get_state of the lattice and grid states through the static staging
+  // buffer, without allocating
+  virtual int get_state_noalloc(int which, void *buf, size_t bytes) {
+    (void)which;
+    (void)buf;
+    (void)bytes;
+    err = "this handle has no allocation-free state read";
+    return HLBM_E_UNSUPPORTED;
+  }
   virtual int force(double *hist, int64_t cap, int64_t *n_out, double t0, double t1, double th[2]) = 0;
   virtual int info(hlbm_info *o) = 0;
   virtual int stencil(int kmax, int32_t *nbr, double *S, double *C) = 0;
@@ -140,6 +203,7 @@ class Case final : public CaseBase {
       }
     }
     HIPCHK((Kernels<T, R>::prepare()));
+    HIPCHK(hipGetDevice(&dev_));
     HIPCHK(hipStreamCreateWithFlags(&s_main_, hipStreamNonBlocking));
     // The grid path may run on a second stream, concurrently with the
     // lattice update; measured on MI355X it is faster on the same stream
@@ -502,6 +566,27 @@ class Case final : public CaseBase {
       return HLBM_OK;
     }
     return fail(HLBM_E_ARG, "unknown state selector");
+  }
+
+  // The lattice or grid state as get_state returns it, converted to FP64 a
+  // piece at a time in the static staging buffer instead of an allocated one.
+  int get_state_noalloc(int which, void *buf, size_t bytes) override {
+    if (which != HLBM_STATE_LATTICE && which != HLBM_STATE_GRID)
+      return fail(HLBM_E_ARG, "only the lattice and grid states are read without allocating");
+    if (which == HLBM_STATE_GRID && !has_grid_) return fail(HLBM_E_STATE, "case has no grid");
+    const bool lat = which == HLBM_STATE_LATTICE;
+    const size_t per = lat ? nodes_ : (size_t)grid_.nnode, stride = lat ? plane_ : per;
+    if (bytes != 9 * per * sizeof(double)) return fail(HLBM_E_ARG, lat ? "lattice state size mismatch" : "grid state size mismatch");
+    double *sc = nullptr;
+    HIPCHK(scratch_on(dev_, &sc));
+    HIPCHK(hipStreamSynchronize(s_main_));
+    const T *L = (const T *)lat_[0];
+    const R *G = has_grid_ ? (const R *)gbuf_[gcur_] : nullptr;
+    HIPCHK(stage_planes((double *)buf, per, sc, kScratchElems, s_main_, [&](int q, size_t a, size_t n, double *dst) {
+      if (lat) Kernels<T, R>::lattice_stage_f64(L + (size_t)q * stride + a, dst, n, q, s_main_);
+      else Kernels<T, R>::grid_stage_f64(G + (size_t)q * stride + a, dst, n, s_main_);
+    }));
+    return HLBM_OK;
   }
 
   int set_state(int which, const void *buf, size_t bytes) override {
@@ -1455,6 +1540,7 @@ class Case final : public CaseBase {
   size_t nodes_ = 0;  // lattice nodes nx * ny
   size_t plane_ = 0;  // population-plane stride of every lattice-shaped device array
   HostGrid grid_;
+  int dev_ = 0;  // the device the case was created on
   hipStream_t s_main_ = nullptr, s_grid_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
   static constexpr int kTimingRing = 64;  // steps recorded between harvests
@@ -2060,6 +2146,12 @@ class MultiLevel final : public CaseBase {
     return HLBM_OK;
   }
 
+  int get_state_noalloc(int which, void *buf, size_t bytes) override {
+    if (which != HLBM_STATE_LATTICE && which != HLBM_STATE_GRID)
+      return fail(HLBM_E_ARG, "only the finest lattice and the grid are read without allocating");
+    return relay(fine_->get_state_noalloc(which, buf, bytes));
+  }
+
   // A level is set as a steady state: both of its buffers, and the moments
   // on the perimeter of the finer level's box as those of the current time.
   int set_state(int which, const void *buf, size_t bytes) override {
@@ -2514,6 +2606,15 @@ int hlbm_get_state(hlbm_t *h, int32_t case_id, int32_t which, void *buf, size_t 
   mghlbm::CaseBase *c = pick(h, case_id);
   if (!c) return HLBM_E_ARG;
   const int rc = c->get_state(which, buf, bytes);
+  if (rc != HLBM_OK && c != h->c.get()) h->c->err = c->err;
+  return rc;
+}
+
+int hlbm_get_state_noalloc(hlbm_t *h, int32_t case_id, int32_t which, void *host_buf, size_t bytes) {
+  if (!h || !host_buf) return HLBM_E_ARG;
+  mghlbm::CaseBase *c = pick(h, case_id);
+  if (!c) return HLBM_E_ARG;
+  const int rc = c->get_state_noalloc(which, host_buf, bytes);
   if (rc != HLBM_OK && c != h->c.get()) h->c->err = c->err;
   return rc;
 }

@@ -150,6 +150,10 @@ struct Kernels {
   static void advance_step(const CaseView<T, R> &v, hipStream_t s);
   // between a lattice buffer (plane stride) and a packed [9][nodes] FP64 array
   static void lattice_to_f64(const T *src, double *dst, size_t plane, size_t nodes, hipStream_t s);
+  // n consecutive values of population plane q of a lattice buffer (src
+  // points at the first), or of a grid array, as FP64 into dst
+  static void lattice_stage_f64(const T *src, double *dst, size_t n, int q, hipStream_t s);
+  static void grid_stage_f64(const R *src, double *dst, size_t n, hipStream_t s);
   // one launch of a case-batched step over a work list of int4 items
   // (case, block x, block y, 0); GridSubsteps: (case, tile) for sub-steps
   // m0 .. m0+3 of every listed case; threads: stream-collide workgroup size

@@ -775,6 +775,13 @@ __global__ void k_to_f64(const T *src, double *dst, size_t plane, size_t nodes) 
   for (int q = 0; q < 9; ++q) dst[q * nodes + i] = (double)Stor<T>::ld(src, q * plane + i, q);
 }
 
+// n consecutive elements of one population plane q (storage type E) as FP64
+template <class E>
+__global__ void k_stage_f64(const E *src, double *dst, size_t n, int q) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)Stor<E>::ld(src, i, q);
+}
+
 template <class T>
 __global__ void k_from_f64(const double *src, T *dst, size_t plane, size_t nodes) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1051,6 +1058,16 @@ void Kernels<T, R>::advance_step(const CaseView<T, R> &v, hipStream_t s) {
 template <class T, class R>
 void Kernels<T, R>::lattice_to_f64(const T *src, double *dst, size_t plane, size_t nodes, hipStream_t s) {
   hipLaunchKernelGGL((k_to_f64<T>), dim3(blocks(nodes, 256)), dim3(256), 0, s, src, dst, plane, nodes);
+}
+
+template <class T, class R>
+void Kernels<T, R>::lattice_stage_f64(const T *src, double *dst, size_t n, int q, hipStream_t s) {
+  hipLaunchKernelGGL((k_stage_f64<T>), dim3(blocks(n, 256)), dim3(256), 0, s, src, dst, n, q);
+}
+
+template <class T, class R>
+void Kernels<T, R>::grid_stage_f64(const R *src, double *dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_stage_f64<R>), dim3(blocks(n, 256)), dim3(256), 0, s, src, dst, n, 0);
 }
 
 template <class T, class R>

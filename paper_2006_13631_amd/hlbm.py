@@ -28,7 +28,8 @@ STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV}
 EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_state",
            "hlbm_set_state", "hlbm_info_get", "hlbm_get_stencil", "hlbm_timing",
            "hlbm_timing_get", "hlbm_tune", "hlbm_destroy", "hlbm_last_error",
-           "hlbm_create_multilevel", "hlbm_level_shape", "hlbm_set_motion", "hlbm_create_graded")
+           "hlbm_create_multilevel", "hlbm_level_shape", "hlbm_set_motion", "hlbm_create_graded",
+           "hlbm_get_state_noalloc")
 STATUS_RUNNING, STATUS_DONE, STATUS_UNSTABLE = 0, 1, 2
 
 
@@ -95,6 +96,7 @@ def load(path: str = LIB_PATH):
     L.hlbm_adjoint.argtypes = [vp, i32, dp, i64, dp]
     L.hlbm_get_state.argtypes = [vp, i32, i32, vp, C.c_size_t]
     L.hlbm_set_state.argtypes = [vp, i32, i32, vp, C.c_size_t]
+    L.hlbm_get_state_noalloc.argtypes = [vp, i32, i32, vp, C.c_size_t]
     L.hlbm_info_get.argtypes = [vp, i32, C.POINTER(Info)]
     L.hlbm_get_stencil.argtypes = [vp, i32, C.POINTER(C.c_int32), dp, dp]
     L.hlbm_timing.argtypes = [vp, i32]
