@@ -292,8 +292,14 @@ __global__ __launch_bounds__(256) void kb_interface_donors(const CaseView<T, R> 
 //
 // One launch advances `count` <= H sub-steps (temporal blocking). A
 // workgroup owns a TX x TY tile and stages the tile plus an H-node halo in
-// LDS, node-major (f then f^neq, stride 19 so wave64 reads are free of bank
-// conflicts): every node's moments are computed once per sub-step. It also
+// LDS, node-major: f and the three products rho u_a u_b of the node's
+// moments (stride 13, odd, so wave64 reads of 64-bit values are free of bank
+// conflicts). The collision sum needs f^neq = f - f^eq(rho, u) of every
+// neighbour; since f^eq is linear in (rho, rho u, rho u u), the C-weighted
+// sum of the neighbours' f^eq follows from the C-weighted sums of their f
+// (which give sum C rho and sum C rho u) and of their rho u u, so a
+// neighbour's f is read once for both the streaming and the collision sum
+// and its f^neq is never stored. It also
 // keeps the structured-derived values of nodes on the grid's outer ring and
 // the stencil class and type of each node. Sub-step s updates the region
 // grown by count-1-s around the tile, so after `count` sub-steps the tile is
@@ -302,7 +308,19 @@ __global__ __launch_bounds__(256) void kb_interface_donors(const CaseView<T, R> 
 // it; stencil coefficients are read from the class table (interior nodes
 // share one class, so the reads are cache broadcasts). Tiles are dealt to
 // the eight XCDs in contiguous bands.
-constexpr int NS = 19;  // LDS doubles (or floats) per node: f[9], f^neq[9], pad
+constexpr int NS = 13;  // LDS doubles (or floats) per node: f[9], rho u_x u_x, rho u_x u_y, rho u_y u_y, pad
+
+// the products rho u_x u_x, rho u_x u_y, rho u_y u_y of f's moments (the
+// quadratic part of f^eq)
+template <class R>
+__device__ __forceinline__ void quad_moments(const R f[9], R P[3]) {
+  R r, vx, vy;
+  moments<R>(f, r, vx, vy);
+  const R jx = r * vx, jy = r * vy;
+  P[0] = jx * vx;
+  P[1] = jx * vy;
+  P[2] = jy * vy;
+}
 
 template <int TXv, int TYv, int H>
 struct Region {
@@ -340,10 +358,9 @@ __device__ __forceinline__ void grid_substeps_block(
   constexpr int TX = G::TX, TY = G::TY, RX = G::RX, RN = G::RN;
   constexpr int SPER = (RN + NT - 1) / NT;      // staging passes
   constexpr int PER = (G::MAXA + NT - 1) / NT;  // update passes
-  int at_s[H][PER], code_s[H][PER];
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  R *sl = reinterpret_cast<R *>(lds_raw);   // [RN][NS] grid f, f^neq
-  R *rl = sl + NS * RN;                     // [NRING][NS] f*, f^neq* on the outer ring
+  R *sl = reinterpret_cast<R *>(lds_raw);   // [RN][NS] grid f, rho u u
+  R *rl = sl + NS * RN;                     // [NRING][NS] f*, rho* u* u* on the outer ring
   int *scode = reinterpret_cast<int *>(rl + NS * G::NRING);  // 4 * class + type, -1 outside the grid
   const int x0 = (t % tiles_x) * TX - H, y0 = (t / tiles_x) * TY - H;  // region origin
   const bool touches_ring = x0 <= 0 || y0 <= 0 || x0 + RX >= nux || y0 + G::RY >= nuy;
@@ -374,11 +391,14 @@ __device__ __forceinline__ void grid_substeps_block(
       if (touches_ring && in) {
         const int rs = ring_slot<G>(gi, gj, idx % RX, idx / RX, nux, nuy);
         if (rs >= 0) {
+          R fs[9], P[3];
 #pragma unroll
-          for (int q = 0; q < 9; ++q) {
-            rl[rs * NS + q] = star_f[q * N + p];
-            rl[rs * NS + 9 + q] = star_n[q * N + p];
-          }
+          for (int q = 0; q < 9; ++q) fs[q] = star_f[q * N + p];
+          quad_moments<R>(fs, P);
+#pragma unroll
+          for (int q = 0; q < 9; ++q) rl[rs * NS + q] = fs[q];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) rl[rs * NS + 9 + a] = P[a];
         }
       }
     }
@@ -386,42 +406,33 @@ __device__ __forceinline__ void grid_substeps_block(
     for (int u = 0; u < SPER; ++u) {
       const int idx = threadIdx.x + u * NT;
       if (idx >= RN) continue;
-      R e[9], r, vx, vy;
-      if (inside[u]) {
-        moments<R>(v[u], r, vx, vy);
-        equilibrium<R>(r, vx, vy, e);
-      } else {
+      R P[3] = {R(0), R(0), R(0)};
+      if (inside[u]) quad_moments<R>(v[u], P);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) e[q] = v[u][q];
-      }
+      for (int q = 0; q < 9; ++q) sl[idx * NS + q] = v[u][q];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        sl[idx * NS + q] = v[u][q];
-        sl[idx * NS + 9 + q] = v[u][q] - e[q];
-      }
+      for (int a = 0; a < 3; ++a) sl[idx * NS + 9 + a] = P[a];
     }
   }
   __syncthreads();
 
-  // the node (region index) and code of every lane in every sub-step
-#pragma unroll
-  for (int sub = 0; sub < H; ++sub) {
+  // the node (region index) and code of pass u of a lane in sub-step sub
+  auto lane_node = [&](int sub, int u, int &idx, int &code) {
     const int ex = max(count - 1 - sub, 0);  // region growth still exact after sub-step `sub`
     const int W = TX + 2 * ex, NA = sub < count ? W * (TY + 2 * ex) : 0, o = H - ex;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int j = threadIdx.x + u * NT;
-      const int idx = j < NA ? (o + j / W) * RX + o + j % W : 0;
-      at_s[sub][u] = idx;
-      code_s[sub][u] = j < NA ? scode[idx] : -1;
-    }
-  }
+    const int j = threadIdx.x + u * NT;
+    idx = j < NA ? (o + j / W) * RX + o + j % W : 0;
+    code = j < NA ? scode[idx] : -1;
+  };
 
   // Eq.(ulbe) at one node: streaming c_q . sum_s G_s f_q,s and collision
-  // sum_s C_s f^neq_q,s; on the outer ring an interpolation node reads
+  // sum_s C_s f^neq_q,s = A_q - sum_s C_s f^eq_q(m_s), A_q = sum_s C_s f_q,s,
+  // where sum_s C_s f^eq_q(m_s) = w_q (S_rho + 3 c_q.S_j + 4.5 c_q c_q : S_P
+  // - 1.5 tr S_P) with S_rho = sum_q A_q, S_j = sum_q c_q A_q and S_P =
+  // sum_s C_s (rho u u)_s. On the outer ring an interpolation node reads
   // structured-derived values instead (Eq.(postcollision2_u)). Absent
   // neighbours have zero weights.
-  auto update_node = [&](int idx, int code, R o9[9]) {
+  auto update_node = [&](int idx, int code, const GridClass<R> &cl, R o9[9]) {
     const int rx = idx % RX, ry = idx / RX;
     const int typ = code & 3;
     const int gi = x0 + rx, gj = y0 + ry;
@@ -435,18 +446,40 @@ __device__ __forceinline__ void grid_substeps_block(
         if (rs >= 0) row[s] = NS * RN + rs * NS;
       }
     }
-    const GridClass<R> &cl = tab[code >> 2];
+    // out_q = f_q + dt c_q.(G f_q) - dt/tau (A_q - sum_s C_s f^eq_q(m_s)): the
+    // part without the f^eq sum first, population by population, while the
+    // sums S_rho and S_j accumulate; then the f^eq sum of every population
+    R srho = R(0), sjx = R(0), sjy = R(0);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      R ax = R(0), ay = R(0), sc = R(0);
+      R a = R(0), ax = R(0), ay = R(0);
 #pragma unroll
       for (int s = 0; s < NSLOT; ++s) {
         const R fq = sl[row[s] + q];
+        a = fmad(cl.C[s], fq, a);
         if (CXd[q] != 0) ax = fmad(cl.Gx[s], fq, ax);
         if (CYd[q] != 0) ay = fmad(cl.Gy[s], fq, ay);
-        sc = fmad(cl.C[s], sl[row[s] + 9 + q], sc);
       }
-      o9[q] = fmad(-dt_tau, sc, fmad(dt, R(CXd[q]) * ax + R(CYd[q]) * ay, sl[row[SELF_SLOT] + q]));
+      srho += a;
+      if (CXd[q] != 0) sjx += R(CXd[q]) * a;
+      if (CYd[q] != 0) sjy += R(CYd[q]) * a;
+      o9[q] = fmad(-dt_tau, a, fmad(dt, R(CXd[q]) * ax + R(CYd[q]) * ay, sl[row[SELF_SLOT] + q]));
+    }
+    R pxx = R(0), pxy = R(0), pyy = R(0);
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const R c = cl.C[s];
+      pxx = fmad(c, sl[row[s] + 9], pxx);
+      pxy = fmad(c, sl[row[s] + 10], pxy);
+      pyy = fmad(c, sl[row[s] + 11], pyy);
+    }
+    const R base = fmad(R(-1.5), pxx + pyy, srho);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const R cx = R(CXd[q]), cy = R(CYd[q]);
+      const R cu = cx * sjx + cy * sjy;
+      const R cc = (cx * cx) * pxx + (R(2) * cx * cy) * pxy + (cy * cy) * pyy;
+      o9[q] = fmad(dt_tau * wgt<R>(q), fmad(R(4.5), cc, fmad(R(3), cu, base)), o9[q]);
     }
   };
 #pragma unroll
@@ -456,12 +489,16 @@ __device__ __forceinline__ void grid_substeps_block(
     R out[PER][9];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int idx = at_s[sub][u], code = code_s[sub][u];
+      int idx, code;
+      lane_node(sub, u, idx, code);
 #pragma unroll
       for (int q = 0; q < 9; ++q) out[u][q] = R(0);
-      if (__ballot(code >= 0) == 0) continue;  // nothing to update in this wave
+      // one pass per stencil class present in the wave (one pass for most
+      // waves): the class index is wave-uniform, so its coefficients sit in
+      // scalar registers
+      if (__ballot(code >= 0) == 0) continue;
       if (code < 0) continue;
-      update_node(idx, code, out[u]);
+      update_node(idx, code, tab[code >> 2], out[u]);
       if ((code & 3) == NODE_WALL) {
         // wall nodes: impose the lamina velocity, keep rho and f^neq
         const int rx = idx % RX, ry = idx / RX;
@@ -484,16 +521,15 @@ __device__ __forceinline__ void grid_substeps_block(
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      if (code_s[sub][u] < 0) continue;
-      const int idx = at_s[sub][u];
-      R e[9], r, vx, vy;
-      moments<R>(out[u], r, vx, vy);
-      equilibrium<R>(r, vx, vy, e);
+      int idx, code;
+      lane_node(sub, u, idx, code);
+      if (code < 0) continue;
+      R P[3];
+      quad_moments<R>(out[u], P);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        sl[idx * NS + q] = out[u][q];
-        sl[idx * NS + 9 + q] = out[u][q] - e[q];
-      }
+      for (int q = 0; q < 9; ++q) sl[idx * NS + q] = out[u][q];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sl[idx * NS + 9 + a] = P[a];
     }
     __syncthreads();
     // the tile is exact after every sub-step: a tape keeps the intermediate ones
