@@ -4,16 +4,23 @@ A step is one structured time step of the whole hot path: lattice
 interpolation nodes from the grid, lattice stream-collide, the grid's
 interface donors and n finite-volume sub-steps, move + refill, wall force.
 Default workload: the 2048^2 lamina case (512 x 128 grid, tau 0.55, KC 1,
-beta 1000), FP64: 100 warm-up steps, 1000 timed steps, then 160 steps with
-HIP events at the stream-collide's own start and end and 24 steps with
-events around every kernel. With plain BGK this configuration goes
-supersonic at the lamina tips and diverges near step 1330 (on the CPU oracle
-as on the GPU), so all 1284 steps stay before it.
+beta 1000), FP64: 100 warm-up steps, the library's autotuner (which also
+captures the HIP graphs the steps replay), 1000 timed steps in one call,
+then 80 steps with HIP events at the stream-collide's own start and end,
+80 with events at the first grid sub-step launch's own start and end, and
+24 steps with events around every kernel. With plain BGK this configuration
+goes supersonic at the lamina tips and diverges near step 1330 (on the CPU
+oracle as on the GPU), so every step stays before it.
 
 Prints one JSON line: lattice MLUPS (whole job), a roofline entry for the
-dominant kernel (lattice stream-collide, HBM bound, 18 s bytes per node
-update, timed with HIP events on its stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+dominant kernel (the grid sub-step kernel: the largest share of the step's
+GPU time; 18 s bytes per grid node and sub-step, four sub-steps per launch,
+timed with HIP events on its stream; its grid is cache-resident, so the
+fraction is of algorithmic bytes over the HBM peak), the same for the
+lattice stream-collide (two steps per launch: the fraction of the
+algorithmic bytes of both steps, and of the bytes it must move, one read and
+one write of the lattice), and the CPU oracle timed on a bounded sample of
+the same workload.
 
 The "adjoint" entry times the differentiation case (1024^2 lattice, 256 x 64
 grid, FP32, 4000 steps, checkpoints every 200 steps): the forward run with
@@ -672,7 +679,7 @@ def storage_leg(workload, storage, steps, warmup, timing_steps):
     from paper_2006_13631_amd import hlbm as H
     from paper_2006_13631_amd.workloads import preset
     cfg = preset(workload)
-    case = H.case_from_preset(cfg, storage=storage, max_steps=warmup + steps + timing_steps)
+    case = H.case_from_preset(cfg, storage=storage, max_steps=warmup + steps + 2 * timing_steps)
     case.step(warmup)
     sched = case.tune(trial_steps=4)
     torch.cuda.synchronize()
@@ -683,10 +690,17 @@ def storage_leg(workload, storage, steps, warmup, timing_steps):
     case.timing(2)
     case.step(timing_steps)
     ms, n = case.timing_get(H.K_STREAM_COLLIDE)
+    case.timing(3)
+    case.step(timing_steps)
+    ms_g, n_g = case.timing_get(H.K_SUBSTEP_LAUNCH)
     case.timing(0)
+    info = case.info()
     nodes = cfg["nx"] * cfg["ny"]
     avg = ms / 1000.0 / max(n, 1)
     gbs = 18 * BYTES[storage] * nodes / avg / 1e9
+    per_launch = min(4, info.n_sub)
+    avg_g = ms_g / 1000.0 / max(n_g, 1)
+    grid_gbs = 18 * {"f64": 8}.get(storage, 4) * info.nnode * per_launch / avg_g / 1e9
     th = None
     try:
         th = case.theta()
@@ -698,6 +712,8 @@ def storage_leg(workload, storage, steps, warmup, timing_steps):
             "stream_collide_kernel": "k_stream_collide2" if two else "k_stream_collide",
             "stream_collide_steps_per_launch": 2 if two else 1, "stream_collide_us": round(avg * 1e6, 3),
             "stream_collide_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "substep_launch_us": round(avg_g * 1e6, 3), "substep_gbs": round(grid_gbs, 1),
+            "substep_frac": round(grid_gbs / HBM_PEAK_GBS, 4),
             "theta": None if th is None else [th.real, th.imag],
             "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}}
 
@@ -709,7 +725,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="lamina_2048")
     ap.add_argument("--storage", default="f64", choices=list(BYTES))
-    ap.add_argument("--timing-steps", type=int, default=160)
+    ap.add_argument("--timing-steps", type=int, default=80,
+                    help="event-timed steps of the stream-collide, then as many of the grid sub-steps")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--adjoint-workload", default="lamina_1024")
@@ -797,7 +814,7 @@ def main():
     steps = args.steps if args.steps is not None else min(cfg["steps"], 1000)
     W = args.warmup
     detail_steps = 24
-    total = W + steps + args.timing_steps + detail_steps
+    total = W + steps + 2 * args.timing_steps + detail_steps
     torch.cuda.set_device(0)
     # a plain copy of known size, so counter runs of this command can scale
     # the HBM byte counters (not part of any timed region)
@@ -812,20 +829,16 @@ def main():
           f"grid nodes {info.nnode} warmup {W} steps {steps}", file=sys.stderr, flush=True)
 
     case.step(W)
-    # launch shapes picked by the library's autotuner (state untouched)
+    # launch shapes picked by the library's autotuner (state untouched); it
+    # also captures the HIP graphs of the steps that follow
     sched = case.tune(trial_steps=4)
     print(f"# schedule {sched}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = 0
-    chunk = max(1, steps // 10)
-    while done < steps:
-        n = min(chunk, steps - done)
-        case.step(n)
-        done += n
-        print(f"# {done}/{steps} steps", file=sys.stderr, flush=True)
+    case.step(steps)  # one call: whole graphs replayed, one wait at the end
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    print(f"# {steps} timed steps in {dt:.4f} s", file=sys.stderr, flush=True)
     nx, ny = cfg["nx"], cfg["ny"]
     mlups = nx * ny * steps / dt / 1e6
 
@@ -837,6 +850,11 @@ def main():
     case.timing(2)
     case.step(args.timing_steps)
     ms_k1, n_k1 = case.timing_get(H.K_STREAM_COLLIDE)
+    # the first grid sub-step launch of each step (of each pair on the
+    # two-step path), its own start and end events, nothing else recorded
+    case.timing(3)
+    case.step(args.timing_steps)
+    ms_g, n_g = case.timing_get(H.K_SUBSTEP_LAUNCH)
     # then every kernel (events between all kernels; informational)
     case.timing(1)
     case.step(detail_steps)
@@ -847,9 +865,18 @@ def main():
         ms, cnt = case.timing_get(kid)
         kern[name] = round(1000.0 * ms / max(cnt, 1), 3)
     case.timing(0)
+    s_b = BYTES[args.storage]
     avg_s = ms_k1 / 1000.0 / max(n_k1, 1)
-    alg_bytes = 18 * BYTES[args.storage] * nx * ny
-    achieved = alg_bytes / avg_s / 1e9
+    lat_bytes = 18 * s_b * nx * ny  # one read and one write of the lattice
+    spl = 2 if two else 1
+    lat_kernel = "k_stream_collide2" if two else "k_stream_collide"
+    # the grid sub-step kernel: 18 s bytes per node and sub-step, the
+    # launch's sub-steps (4, or n when fewer)
+    per_launch = min(4, info.n_sub)
+    grid_kernel = f"k_grid_substeps<{ {'f64': 'double'}.get(args.storage, 'float') }, {sched['substep_variant']}>"
+    avg_g = ms_g / 1000.0 / max(n_g, 1)
+    grid_bytes = 18 * s_b * info.nnode * per_launch
+    grid_achieved = grid_bytes / avg_g / 1e9
     th = None
     try:
         th = case.theta()
@@ -857,7 +884,7 @@ def main():
         pass
 
     out = {
-        "metric": "lattice MLUPS (whole MG-HLBM step) + HBM roofline fraction of the stream-collide kernel",
+        "metric": "lattice MLUPS (whole MG-HLBM step) + HBM roofline fraction of the dominant kernel",
         "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": W,
         "ms_per_step": round(1000.0 * dt / steps, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
@@ -865,26 +892,27 @@ def main():
                    "b": cfg["b"], "tau": cfg["tau"], "kc": cfg["kc"], "beta": cfg["beta"],
                    "n_sub": info.n_sub, "storage": args.storage,
                    "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, args.storage,
-                                                 "k_stream_collide2" if two else "k_stream_collide"),
-                     "kernel": "k_stream_collide2" if two else "k_stream_collide",
-                     "steps_per_launch": 2 if two else 1, "avg_us": round(avg_s * 1e6, 3),
-                     "bytes_per_launch": alg_bytes,
-                     # per lattice step: the kernel's time, and the least time
-                     # any one-step-per-launch kernel needs at peak (read and
-                     # write the lattice once per step)
-                     "us_per_step": round(avg_s * 1e6 / (2 if two else 1), 3),
-                     "single_step_floor_us": round(alg_bytes / (HBM_PEAK_GBS * 1e9) * 1e6, 3)},
+        # the dominant kernel: the grid sub-steps (n launches' worth per step
+        # against the lattice's one); its grid stays in L2 and the memory-side
+        # cache, so this is algorithmic bytes over the HBM peak
+        "roofline": {"bound": "hbm", "achieved": round(grid_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(grid_achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.workload, args.storage, "k_grid_substeps"),
+                     "kernel": grid_kernel, "substeps_per_launch": per_launch,
+                     "launches_per_step": -(-info.n_sub // per_launch), "avg_us": round(avg_g * 1e6, 3),
+                     "bytes_per_launch": grid_bytes, "resident": "L2 + memory-side cache"},
+        # the lattice stream-collide: `frac` prices a launch at the
+        # algorithmic bytes of the steps it advances (18 s per node update);
+        # `frac_moved` at the bytes it must move, one read and one write
+        "lattice": {"kernel": lat_kernel, "steps_per_launch": spl, "avg_us": round(avg_s * 1e6, 3),
+                    "us_per_step": round(avg_s * 1e6 / spl, 3),
+                    "bytes_per_launch": spl * lat_bytes,
+                    "achieved": round(spl * lat_bytes / avg_s / 1e9, 1),
+                    "frac": round(spl * lat_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                    "moved_bytes_per_launch": lat_bytes,
+                    "frac_moved": round(lat_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(args.workload, args.storage, lat_kernel)},
         "kernel_avg_us": kern,
-        # the grid path is L2 / LDS resident and latency-bound: its time per
-        # sub-step, and the algorithmic bytes of a sub-step (read and write
-        # 9 populations per grid node) over that time
-        "grid": None if not kern.get("grid_substeps") or not info.n_sub else {
-            "us_per_substep": round(kern["grid_substeps"] / info.n_sub, 3),
-            "algorithmic_gbs": round(18 * BYTES[args.storage] * info.nnode
-                                     / (kern["grid_substeps"] / info.n_sub * 1e-6) / 1e9, 1)},
         "mlups_total": round((nx * ny + info.n_sub * info.nnode) * steps / dt / 1e6, 2),
         "theta": None if th is None else [th.real, th.imag],
     }

@@ -358,9 +358,11 @@ int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
  * hlbm_step and hlbm_adjoint calls, records: level 1, every kernel of the
  * step (events between all kernels); level 2, the stream-collide alone, by
  * events taken at that kernel's own start and end and nothing else in the
- * step; 0 turns recording off. Timed steps are launched one by one instead
- * of as graphs. hlbm_timing_get returns for kernel id (HLBM_K_*) the summed
- * milliseconds and launch count. */
+ * step; level 3 (a case with a grid), the first grid sub-step launch of
+ * every step (of every pair of steps on the two-step path) the same way;
+ * 0 turns recording off. Timed steps are launched one by one instead of as
+ * graphs. hlbm_timing_get returns for kernel id (HLBM_K_*) the summed
+ * milliseconds and launch count. HLBM_E_STATE for level 3 without a grid. */
 #define HLBM_K_STREAM_COLLIDE 0 /* lattice stream-collide, Eq.(LBE)            */
 #define HLBM_K_LATTICE_FROM_GRID 1 /* Eq.(postcollision2_s)                    */
 #define HLBM_K_GRID_SUBSTEPS 2  /* donors + n sub-steps, Eqs.(ulbe),(postcollision2_u) */
@@ -369,6 +371,8 @@ int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
 #define HLBM_K_STEP 5           /* whole structured step                       */
 #define HLBM_K_ADJ_STREAM_COLLIDE 6 /* adjoint of the lattice stream-collide   */
 #define HLBM_K_ADJOINT 7        /* whole hlbm_adjoint call (count = steps)     */
+#define HLBM_K_SUBSTEP_LAUNCH 8 /* level 3: the first grid sub-step launch of a
+                                   step (up to 4 sub-steps, Eq.(ulbe))        */
 int hlbm_timing(hlbm_t *h, int32_t on);
 int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count);
 
@@ -384,7 +388,9 @@ int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count)
  * current lattice and grid and writing only their free buffers, and keep
  * the fastest (ms_per_step: the two chosen kernels' time per step).
  * trial_steps = 0 applies *t as given instead (single case: lattice_threads
- * = lattice_rows = 0 keeps the stream-collide shape). *t receives the
+ * = lattice_rows = 0 keeps the stream-collide shape). A single case then
+ * captures the HIP graphs its next steps replay, so later hlbm_step calls
+ * only launch them. *t receives the
  * schedule in use. Errors: HLBM_E_STATE (batch: steps already taken),
  * HLBM_E_ARG (invalid schedule). */
 int hlbm_tune(hlbm_t *h, int32_t trial_steps, hlbm_tuning *t);

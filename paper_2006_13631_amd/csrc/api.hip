@@ -305,7 +305,7 @@ class Case final : public CaseBase {
   // Stream-collide with its own start and end events when timing is on
   // (the events are taken at the kernel's own start and end on its stream).
   void stream_collide_timed(const CaseView<T, R> &v) {
-    if (timing_) {
+    if (timing_ == 1 || timing_ == 2) {
       Kernels<T, R>::stream_collide(v, s_main_, tev_[tslot_][8], tev_[tslot_][2], lattice_threads_, lattice_rows_,
                                     lattice_order_);
     } else {
@@ -353,10 +353,15 @@ class Case final : public CaseBase {
     Kernels<T, R>::interface_donors(v, s_grid_);
     int cur = gcur_;
     const int blk = substep_block(substep_variant_);
+    // level 3: the step's first sub-step launch, once per timing slot
+    const bool time_sub = timing_ == 3 && sub_mark_ != tslot_;
+    if (time_sub) sub_mark_ = tslot_;
     for (int m = 0; m < d_.n; m += blk) {
       const int cnt = std::min(blk, d_.n - m);
+      const bool ev = time_sub && m == 0;
       Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_, nullptr, nullptr,
-                                   nullptr, 0, substep_variant_);
+                                   nullptr, 0, substep_variant_, ev ? tev_[tslot_][8] : nullptr,
+                                   ev ? tev_[tslot_][2] : nullptr);
       cur = 1 - cur;
     }
     if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][4], s_grid_));
@@ -734,11 +739,13 @@ class Case final : public CaseBase {
       for (auto &ring : tev_)
         for (auto &e : ring) HIPCHK(hipEventCreate(&e));
     tslot_ = 0;
-    for (int i = 0; i < 8; ++i) {
+    sub_mark_ = -1;
+    for (int i = 0; i < kTimedKernels; ++i) {
       tms_[i] = 0.0;
       tcount_[i] = 0;
     }
-    if (on < 0 || on > 2) return fail(HLBM_E_ARG, "timing level must be 0, 1 or 2");
+    if (on < 0 || on > 3) return fail(HLBM_E_ARG, "timing level must be 0, 1, 2 or 3");
+    if (on == 3 && !has_grid_) return fail(HLBM_E_STATE, "timing level 3 times the grid sub-steps of a case with a grid");
     timing_ = on;
     return HLBM_OK;
   }
@@ -778,6 +785,32 @@ class Case final : public CaseBase {
     return HLBM_OK;
   }
 
+  // Capture the graphs of every buffer arrangement the steps will pass
+  // through from the current one (the arrangements form a cycle), so that
+  // later steps only replay; nothing runs and the state is untouched.
+  hipError_t prime_graphs() {
+    if (!use_graphs_ || timing_) return hipSuccess;
+    void *l0 = lat_[0], *l1 = lat_[1], *l2 = lat_[2];
+    const int g0 = gcur_, start = layout_key();
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 18 && e == hipSuccess; ++i) {
+      hipGraphExec_t ge = nullptr;
+      e = graph_for_current_layout(&ge);
+      if (e != hipSuccess) break;
+      const int key = layout_key();
+      lat_[0] = after_graph_[key][0];
+      lat_[1] = after_graph_[key][1];
+      lat_[2] = after_graph_[key][2];
+      gcur_ = after_gcur_[key];
+      if (layout_key() == start) break;
+    }
+    lat_[0] = l0;
+    lat_[1] = l1;
+    lat_[2] = l2;
+    gcur_ = g0;
+    return e;
+  }
+
   // captured steps hold the launch shapes they were captured with
   void drop_graphs() {
     for (auto &g : gexec_) {
@@ -805,6 +838,7 @@ class Case final : public CaseBase {
       lattice_order_ = t->order;
       HIPCHK(hipStreamSynchronize(s_main_));
       drop_graphs();
+      HIPCHK(prime_graphs());
       *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, -1, 0.0};
       return HLBM_OK;
     }
@@ -865,12 +899,13 @@ class Case final : public CaseBase {
     (void)hipEventDestroy(e1);
     HIPCHK(e);
     drop_graphs();
+    HIPCHK(prime_graphs());
     *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, -1, total / trial_steps};
     return HLBM_OK;
   }
 
   int timing_get(int kernel, double *ms, int64_t *count) override {
-    if (kernel < 0 || kernel > 7) return fail(HLBM_E_ARG, "unknown kernel id");
+    if (kernel < 0 || kernel >= kTimedKernels) return fail(HLBM_E_ARG, "unknown kernel id");
     if (ms) *ms = tms_[kernel];
     if (count) *count = tcount_[kernel];
     return HLBM_OK;
@@ -1231,7 +1266,7 @@ class Case final : public CaseBase {
           tcount_[id] += 1;
         }
       };
-      add(HLBM_K_STREAM_COLLIDE, t[8], t[2]);
+      add(timing_ == 3 ? HLBM_K_SUBSTEP_LAUNCH : HLBM_K_STREAM_COLLIDE, t[8], t[2]);
       if (timing_ != 1) continue;
       if (has_grid_) {
         add(HLBM_K_LATTICE_FROM_GRID, t[0], t[1]);
@@ -1550,8 +1585,10 @@ class Case final : public CaseBase {
   int substep_variant_ = -1;  // grid sub-step kernel variant (-1: the default for R)
   int lattice_threads_ = kLatticeThreads, lattice_rows_ = kLatticeRows;  // stream-collide launch shape
   int lattice_order_ = 0;  // 1: stream-collide rows banded by XCD
-  double tms_[8] = {};
-  int64_t tcount_[8] = {};
+  static constexpr int kTimedKernels = 9;  // HLBM_K_* ids
+  double tms_[kTimedKernels] = {};
+  int64_t tcount_[kTimedKernels] = {};
+  int sub_mark_ = -1;  // timing slot whose first sub-step launch is timed (level 3)
   std::vector<void *> owned_;
   void *lat_[3] = {nullptr, nullptr, nullptr};  // state at t_k, free, free (two-step path)
   void *phys_[3] = {nullptr, nullptr, nullptr};  // the physical buffers

@@ -137,12 +137,13 @@ struct Kernels {
   // tape + m * 9 * nnode, and the moments (rho, u_x, u_y) of every wall node
   // before its velocity is imposed in sub-step m at wtape + (3 m + c) nwall
   // + widx[node]
+  // start, stop (optional): events taken at the launch's own start and end
   static void grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
                             R *tape = nullptr, R *wtape = nullptr, const int *widx = nullptr, int nwall = 0,
-                            int variant = -1);
+                            int variant = -1, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
   template <int V>
   static void grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
-                              R *tape, R *wtape, const int *widx, int nwall);
+                              R *tape, R *wtape, const int *widx, int nwall, hipEvent_t start, hipEvent_t stop);
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
   // advance = 0: leave the step counter (a coupled-motion step then runs the
   // refill and advance_step after it)

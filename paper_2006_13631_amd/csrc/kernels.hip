@@ -1054,24 +1054,33 @@ void Kernels<T, R>::interface_donors(const CaseView<T, R> &v, hipStream_t s) {
 template <class T, class R>
 template <int V>
 void Kernels<T, R>::grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
-                                    R *tape, R *wtape, const int *widx, int nwall) {
+                                    R *tape, R *wtape, const int *widx, int nwall, hipEvent_t start,
+                                    hipEvent_t stop) {
   using SV = SubstepVariant<V>;
   const int tiles_x = (v.nux + SV::G::TX - 1) / SV::G::TX, tiles_y = (v.nuy + SV::G::TY - 1) / SV::G::TY;
-  hipLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT),
-                     (substeps_lds_bytes<R, typename SV::G>()), s, f, fout, (const R *)v.star_f, (const R *)v.star_n,
-                     v.cls, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw,
-                     (const int64_t *)v.dk, v.n_sub, m0, count, tape, wtape, widx, nwall);
+  if (start || stop)
+    hipExtLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT),
+                          (substeps_lds_bytes<R, typename SV::G>()), s, start, stop, 0, f, fout,
+                          (const R *)v.star_f, (const R *)v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x,
+                          tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m0,
+                          count, tape, wtape, widx, nwall);
+  else
+    hipLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT),
+                       (substeps_lds_bytes<R, typename SV::G>()), s, f, fout, (const R *)v.star_f,
+                       (const R *)v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u,
+                       v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m0, count, tape, wtape, widx, nwall);
 }
 
 template <class T, class R>
 void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
-                                  R *tape, R *wtape, const int *widx, int nwall, int variant) {
+                                  R *tape, R *wtape, const int *widx, int nwall, int variant, hipEvent_t start,
+                                  hipEvent_t stop) {
   switch (variant < 0 ? default_substep_variant<R>() : variant) {
 #define HLBM_V(V) \
-  case V: grid_substeps_v<V>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
+  case V: grid_substeps_v<V>(v, f, fout, m0, count, s, tape, wtape, widx, nwall, start, stop); break;
     HLBM_V(1) HLBM_V(2) HLBM_V(3) HLBM_V(4) HLBM_V(5) HLBM_V(6) HLBM_V(7) HLBM_V(8) HLBM_V(9) HLBM_V(10)
 #undef HLBM_V
-    default: grid_substeps_v<0>(v, f, fout, m0, count, s, tape, wtape, widx, nwall); break;
+    default: grid_substeps_v<0>(v, f, fout, m0, count, s, tape, wtape, widx, nwall, start, stop); break;
   }
 }
 

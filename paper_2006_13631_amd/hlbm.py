@@ -22,7 +22,7 @@ STATE_MOTION = 4
 STATE_LEVEL = 16
 MAX_LEVELS = 8
 (K_STREAM_COLLIDE, K_LATTICE_FROM_GRID, K_GRID_SUBSTEPS, K_REFILL, K_FORCE, K_STEP,
- K_ADJ_STREAM_COLLIDE, K_ADJOINT) = range(8)
+ K_ADJ_STREAM_COLLIDE, K_ADJOINT, K_SUBSTEP_LAUNCH) = range(9)
 STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV}
 
 EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_state",
@@ -220,7 +220,8 @@ class Case:
         return t.as_dict()
 
     def timing(self, level=1):
-        """1: every kernel of the step; 2: the stream-collide alone; 0: off."""
+        """1: every kernel of the step; 2: the stream-collide alone; 3: the
+        first grid sub-step launch of each step alone; 0: off."""
         self._check(load().hlbm_timing(self.h, int(level)))
 
     def timing_get(self, kernel):
