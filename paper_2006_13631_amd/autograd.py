@@ -62,7 +62,7 @@ def theta(hist: torch.Tensor, A, omega, b: float, t0: float = 1.0, t1: float = 4
     """Theta = (a_s + i a_c) / ((pi/4) omega^2 b^2 A) from F_y(t) ~ a_s sin(omega
     t) + a_c cos(omega t) over t0 T <= t < t1 T, t = k + 1, T = 2 pi / omega.
     Returns a complex128 tensor."""
-    om = float(omega)
+    om = float(omega.detach()) if torch.is_tensor(omega) else float(omega)
     T = 2.0 * math.pi / om
     t = np.arange(1, hist.shape[0] + 1, dtype=np.float64)
     sel = np.nonzero((t >= t0 * T) & (t < t1 * T))[0]

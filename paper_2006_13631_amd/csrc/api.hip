@@ -160,6 +160,17 @@ class CaseBase {
     }                                                                                 \
   } while (0)
 
+// a checked copy: a refused one names the cause
+#define COPYCHK(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      err = copy_fault_ ? std::string("refused a device copy that leaves its allocation: ") + #expr \
+                        : std::string(#expr) + ": " + hipGetErrorString(e_);          \
+      return HLBM_E_HIP;                                                              \
+    }                                                                                 \
+  } while (0)
+
 inline bool valid_lattice_shape(const hlbm_tuning &t) {
   return t.lattice_threads >= 64 && t.lattice_threads <= 256 && t.lattice_threads % 64 == 0 &&
          (t.lattice_rows == 1 || t.lattice_rows == 2 || t.lattice_rows == 4);
@@ -491,10 +502,10 @@ class Case final : public CaseBase {
       if (ckW_ > 0) {
         if (k_ % ckW_ == 0 && k_ / ckW_ < nck_) {
           const size_t w = (size_t)(k_ / ckW_);
-          HIPCHK(hipMemcpyAsync((char *)ck_lat_ + w * ck_lat_bytes_, lat_[0], ck_lat_bytes_,
-                                hipMemcpyDeviceToDevice, s_main_));
-          HIPCHK(hipMemcpyAsync((char *)ck_grid_ + w * ck_grid_bytes_, gbuf_[gcur_], ck_grid_bytes_,
-                                hipMemcpyDeviceToDevice, s_main_));
+          COPYCHK(copy_checked((char *)ck_lat_ + w * ck_lat_bytes_, lat_[0], ck_lat_bytes_,
+                               hipMemcpyDeviceToDevice, s_main_));
+          COPYCHK(copy_checked((char *)ck_grid_ + w * ck_grid_bytes_, gbuf_[gcur_], ck_grid_bytes_,
+                               hipMemcpyDeviceToDevice, s_main_));
         }
         room = std::min<int64_t>(room, ckW_ - k_ % ckW_);
       }
@@ -519,11 +530,10 @@ class Case final : public CaseBase {
     }
     if (timing_ && tslot_ > 0) HIPCHK(harvest());
     HIPCHK(hipStreamSynchronize(s_main_));
-    if (has_grid_) {
-      int flag = 0;
-      HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
-      if (flag) return fail(HLBM_E_UNSTABLE, "non-finite force on the lamina");
-    }
+    int flag = 0;
+    HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag & 2) return fail(HLBM_E_UNSTABLE, "a density became non-positive or not a number");
+    if (flag) return fail(HLBM_E_UNSTABLE, has_grid_ ? "non-finite force on the lamina" : "unstable");
     return HLBM_OK;
   }
 
@@ -682,7 +692,7 @@ class Case final : public CaseBase {
     o->two_step = two_step_ ? 1 : 0;
     {
       int flag = 0;
-      if (has_grid_) HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
       o->status = flag ? HLBM_STATUS_UNSTABLE : (has_grid_ && k_ >= cfg_.max_steps ? HLBM_STATUS_DONE : HLBM_STATUS_RUNNING);
     }
     if (has_grid_) {
@@ -946,7 +956,7 @@ class Case final : public CaseBase {
     {
       int64_t k0, k1;
       window(nwin - 1, k0, k1);
-      HIPCHK(recompute(tape_of(nwin - 1), nwin - 1, k0, k1, s_aux_));
+      COPYCHK(recompute(tape_of(nwin - 1), nwin - 1, k0, k1, s_aux_));
       HIPCHK(hipEventRecord(ev_rec_[tape_of(nwin - 1)], s_aux_));
     }
     for (int64_t w = nwin - 1; w >= 0; --w) {
@@ -956,7 +966,7 @@ class Case final : public CaseBase {
         const int tp = tape_of(w - 1);
         window(w - 1, k0, k1);
         HIPCHK(hipStreamWaitEvent(s_aux_, ev_rev_[tp], 0));
-        HIPCHK(recompute(tp, w - 1, k0, k1, s_aux_));
+        COPYCHK(recompute(tp, w - 1, k0, k1, s_aux_));
         HIPCHK(hipEventRecord(ev_rec_[tp], s_aux_));
       }
       window(w, k0, k1);
@@ -966,7 +976,7 @@ class Case final : public CaseBase {
       if (w > 0 && ntapes_ == 1) {
         window(w - 1, k0, k1);
         HIPCHK(hipStreamWaitEvent(s_aux_, ev_rev_[t], 0));
-        HIPCHK(recompute(t, w - 1, k0, k1, s_aux_));
+        COPYCHK(recompute(t, w - 1, k0, k1, s_aux_));
         HIPCHK(hipEventRecord(ev_rec_[t], s_aux_));
       }
     }
@@ -999,9 +1009,32 @@ class Case final : public CaseBase {
   hipError_t alloc(P **p, size_t bytes) {
     void *q = nullptr;
     hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 256));
-    if (e == hipSuccess) owned_.push_back(q);
+    if (e == hipSuccess) {
+      owned_.push_back(q);
+      owned_bytes_.push_back(bytes);
+    }
     *p = (P *)q;
     return e;
+  }
+  // true when [p, p + n) lies inside one device allocation of this case
+  bool owns(const void *p, size_t n) const {
+    const char *c = (const char *)p;
+    for (size_t i = 0; i < owned_.size(); ++i) {
+      const char *a = (const char *)owned_[i];
+      if (c >= a && n <= owned_bytes_[i] && (size_t)(c - a) <= owned_bytes_[i] - n) return true;
+    }
+    return false;
+  }
+  // an asynchronous copy whose device side (both sides between two device
+  // buffers) is checked against this case's allocations before it is enqueued
+  hipError_t copy_checked(void *dst, const void *src, size_t n, hipMemcpyKind kind, hipStream_t st) {
+    const bool dev_dst = kind == hipMemcpyDeviceToDevice || kind == hipMemcpyHostToDevice;
+    const bool dev_src = kind == hipMemcpyDeviceToDevice || kind == hipMemcpyDeviceToHost;
+    if ((dev_dst && !owns(dst, n)) || (dev_src && !owns(src, n))) {
+      copy_fault_ = true;
+      return hipErrorInvalidValue;
+    }
+    return hipMemcpyAsync(dst, src, n, kind, st);
   }
   template <class P>
   hipError_t upload(P **p, const void *src, size_t bytes) {
@@ -1111,6 +1144,7 @@ class Case final : public CaseBase {
 
   CaseView<T, R> view() const {
     CaseView<T, R> v{};
+    v.flag = flag_;
     v.A = (const T *)lat_[0];
     v.B = (T *)lat_[1];
     v.C = (T *)lat_[2];
@@ -1170,7 +1204,6 @@ class Case final : public CaseBase {
       v.params = params_;
       v.dk = dk_;
       v.hist = hist_;
-      v.flag = flag_;
       v.counts = counts_;
       v.k2_x0 = k2_x0_;
       v.k2_w = k2_w_;
@@ -1482,11 +1515,11 @@ class Case final : public CaseBase {
   // of every sub-step and the wall moments the adjoint needs.
   hipError_t recompute(int t, int64_t w, int64_t k0, int64_t k1, hipStream_t st) {
     if (t < 0 || t >= ntapes_ || w < 0 || w >= nck_ || k1 - k0 > ckW_) return hipErrorInvalidValue;
-    hipError_t e = hipMemcpyAsync(tape_lat(t, 0), (char *)ck_lat_ + (size_t)w * ck_lat_bytes_, ck_lat_bytes_,
-                                  hipMemcpyDeviceToDevice, st);
+    hipError_t e = copy_checked(tape_lat(t, 0), (char *)ck_lat_ + (size_t)w * ck_lat_bytes_, ck_lat_bytes_,
+                                hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(tape_grid(t, 0, 0), (char *)ck_grid_ + (size_t)w * ck_grid_bytes_, ck_grid_bytes_,
-                       hipMemcpyDeviceToDevice, st);
+    e = copy_checked(tape_grid(t, 0, 0), (char *)ck_grid_ + (size_t)w * ck_grid_bytes_, ck_grid_bytes_,
+                     hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
     for (int64_t k = k0; k < k1; ++k) {
       const int64_t j = k - k0;
@@ -1590,6 +1623,8 @@ class Case final : public CaseBase {
   int64_t tcount_[kTimedKernels] = {};
   int sub_mark_ = -1;  // timing slot whose first sub-step launch is timed (level 3)
   std::vector<void *> owned_;
+  std::vector<size_t> owned_bytes_;  // requested bytes of each owned_ entry
+  bool copy_fault_ = false;          // a copy was refused for leaving its allocation
   void *lat_[3] = {nullptr, nullptr, nullptr};  // state at t_k, free, free (two-step path)
   void *phys_[3] = {nullptr, nullptr, nullptr};  // the physical buffers
   bool two_step_ = false;
@@ -2154,11 +2189,10 @@ class MultiLevel final : public CaseBase {
       }
     }
     HIPCHK(hipStreamSynchronize(s_));
-    if (fine_->has_grid()) {
-      int flag = 0;
-      HIPCHK(hipMemcpy(&flag, fine_->flag(), sizeof(int), hipMemcpyDeviceToHost));
-      if (flag) return fail(HLBM_E_UNSTABLE, "non-finite force on the lamina");
-    }
+    int flag = 0;
+    HIPCHK(hipMemcpy(&flag, fine_->flag(), sizeof(int), hipMemcpyDeviceToHost));
+    if (flag & 2) return fail(HLBM_E_UNSTABLE, "a density of the finest level became non-positive or not a number");
+    if (flag) return fail(HLBM_E_UNSTABLE, "non-finite force on the lamina");
     return HLBM_OK;
   }
 

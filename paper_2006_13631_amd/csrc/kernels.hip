@@ -45,6 +45,14 @@ __device__ __forceinline__ bool static_skip(const CaseView<T, R> &v, int x, int 
          (v.bc == 3 && (x == 0 || y == 0 || x == v.nx - 1 || y == v.ny - 1));
 }
 
+// a density that is not positive (or not a number) stops the case: bit 2 of
+// its flag (bit 1: a non-finite force)
+constexpr int kFlagForce = 1, kFlagDensity = 2;
+template <class R>
+__device__ __forceinline__ void check_density(int *flag, R rho) {
+  if (!(rho > R(0)) && flag) atomicOr(flag, kFlagDensity);
+}
+
 template <class T, class R, int RPT>
 __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, const T *__restrict__ A,
                                                      T *__restrict__ B, const int64_t *k_at, int bx, int by) {
@@ -73,6 +81,7 @@ __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, co
     }
     R e[9], rho, ux, uy;
     moments<R>(f[r], rho, ux, uy);
+    check_density(v.flag, rho);
     equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
     for (int q = 0; q < 9; ++q) Stor<T>::st_stream(B, q * plane + c, q, fmad(-v.inv_tau, f[r][q] - e[q], f[r][q]));
@@ -182,6 +191,7 @@ __global__ __launch_bounds__(512) void k_stream_collide2(CaseView<T, R> v, int t
   }
   R e[9], rho, ux, uy;
   moments<R>(g, rho, ux, uy);
+  check_density(v.flag, rho);
   equilibrium<R>(rho, ux, uy, e);
 #pragma unroll
   for (int q = 0; q < 9; ++q) Stor<T>::st_stream(v.C, q * plane + c, q, fmad(-v.inv_tau, g[q] - e[q], g[q]));
@@ -656,8 +666,13 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
     for (int q = 0; q < 9; ++q) out[q] = e[q] + v.k_neq * fneq[q];
     atomicAdd(&v.counts[0], 1ull);
   }
+  R rho = R(0);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) fn[q * N + p] = out[q];
+  for (int q = 0; q < 9; ++q) {
+    fn[q * N + p] = out[q];
+    rho += out[q];
+  }
+  check_density(v.flag, rho);
 }
 
 template <class T, class R>
@@ -733,7 +748,7 @@ __device__ __forceinline__ void force_block(const R *__restrict__ f, const WallE
     const int64_t k = *dk;
     hist[2 * k] = sx;
     hist[2 * k + 1] = sy;
-    if (!isfinite(sx) || !isfinite(sy)) *flag = 1;
+    if (!isfinite(sx) || !isfinite(sy)) atomicOr(flag, kFlagForce);
     if (mot.on) {
       // semi-implicit Euler, Delta t = 1: v_{k+1} from the force at t_{k+1},
       // then y_{k+1} = y_k + v_{k+1}; a state leaving |y| <= y_max or
@@ -743,7 +758,7 @@ __device__ __forceinline__ void force_block(const R *__restrict__ f, const WallE
       const double acc = (sy - mot.K * y - mot.C * vel) / mot.M;
       double v1 = vel + acc, y1 = y + v1;
       if (!(fabs(y1) <= mot.y_max) || !(fabs(v1) < 1.0)) {
-        *flag = 1;
+        atomicOr(flag, kFlagForce);
         y1 = y;
         v1 = 0.0;
       }
