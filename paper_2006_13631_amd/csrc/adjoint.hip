@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NG) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
         if (r.kind != 3) continue;
         int node[3];
         double lam[3], dl[3];
-        cell_triangle(r.ci, r.cj, g.nux, r.a, r.b, node, lam, dl);
+        cell_triangle(r.ci, r.cj, g.nux, r.a, r.b, node, lam, dl, r.tri);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           if (node[a] != q) continue;
@@ -650,10 +650,10 @@ __global__ __launch_bounds__(NT) void k_adj_from_grid(AdjCtx<T, R> c, int slot0)
 #pragma unroll
     for (int k = 0; k < 12; ++k) z[k] = R(0);
     if (y <= max(c.P.iy1, c.P.piy1) && from_grid_target(c.P, x, y)) {
-      int ci, cj, node[3];
+      int ci, cj, tri, node[3];
       double a, b, lam[3], dl[3];
-      lattice_node_cell(c.gg, c.P.ybase, x, y, ci, cj, a, b);
-      cell_triangle(ci, cj, c.gg.nux, a, b, node, lam, dl);
+      lattice_node_cell(c.gg, c.P.ybase, x, y, ci, cj, a, b, tri);
+      cell_triangle(ci, cj, c.gg.nux, a, b, node, lam, dl, tri);
       R rho, ux, uy, fneq[9];
       grid_barycentric<R>(c.U0, c.nnode, node, lam, rho, ux, uy, fneq);
       const size_t plane = c.plane, cc = (size_t)y * c.nx + x;
@@ -706,10 +706,10 @@ __global__ __launch_bounds__(NG) void k_adj_from_grid_gather(AdjCtx<T, R> c, R *
     for (int yl = (deep || away) ? yhi + 1 : ylo; yl <= yhi; ++yl) {
       for (int xl = xlo; xl <= xhi; ++xl) {
         if (!from_grid_target(c.P, xl, yl)) continue;
-        int ci, cj, node[3];
+        int ci, cj, tri, node[3];
         double a, b, lam[3], dl[3];
-        lattice_node_cell(g, c.P.ybase, xl, yl, ci, cj, a, b);
-        cell_triangle(ci, cj, g.nux, a, b, node, lam, dl);
+        lattice_node_cell(g, c.P.ybase, xl, yl, ci, cj, a, b, tri);
+        cell_triangle(ci, cj, g.nux, a, b, node, lam, dl, tri);
         const size_t at = (size_t)(yl - ybot) * c.k2_w + (xl - c.k2_x0);
 #pragma unroll
         for (int n = 0; n < 3; ++n) {

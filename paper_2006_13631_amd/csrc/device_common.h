@@ -233,12 +233,13 @@ __device__ __forceinline__ void bilinear_corner(double X, double Y, int d, int &
 // Triangle of the grid cell (ci, cj) containing local cell coordinates
 // (a, b) in [0,1]^2, its barycentric weights and their derivative in b.
 // Cells left of the centre line are cut by the rising diagonal, cells right
-// of it by the falling one.
+// of it by the falling one. tri: 0 the cell's first triangle, 1 its second,
+// -1 the one the coordinates fall in (the first on the diagonal).
 __device__ __forceinline__ void cell_triangle(int ci, int cj, int nux, double a, double b, int node[3],
-                                              double lam[3], double dlam_db[3]) {
+                                              double lam[3], double dlam_db[3], int tri = -1) {
   const int n00 = cj * nux + ci, n10 = n00 + 1, n01 = n00 + nux, n11 = n01 + 1;
   if (2 * ci + 1 < nux) {
-    if (b <= a) {  // (n00, n10, n11)
+    if (tri == 0 || (tri < 0 && b <= a)) {  // (n00, n10, n11)
       node[0] = n00; node[1] = n10; node[2] = n11;
       lam[0] = 1.0 - a; lam[1] = a - b; lam[2] = b;
       dlam_db[0] = 0.0; dlam_db[1] = -1.0; dlam_db[2] = 1.0;
@@ -248,7 +249,7 @@ __device__ __forceinline__ void cell_triangle(int ci, int cj, int nux, double a,
       dlam_db[0] = -1.0; dlam_db[1] = 0.0; dlam_db[2] = 1.0;
     }
   } else {
-    if (a + b <= 1.0) {  // (n00, n10, n01)
+    if (tri == 0 || (tri < 0 && a + b <= 1.0)) {  // (n00, n10, n01)
       node[0] = n00; node[1] = n10; node[2] = n01;
       lam[0] = 1.0 - a - b; lam[1] = a; lam[2] = b;
       dlam_db[0] = -1.0; dlam_db[1] = 0.0; dlam_db[2] = 1.0;
@@ -281,16 +282,82 @@ __device__ __forceinline__ int graded_cell(const double *v, int n, double x) {
   return lo;
 }
 
+// true for a cell of the lamina slot (no triangles)
+__device__ __forceinline__ bool body_cell(const GridGeom &g, int ci, int cj) {
+  if (!g.body || cj != g.nuy / 2 - 1) return false;
+  if (g.gx) {
+    const double half = g.half_b + 1e-9 * (2.0 * g.half_T);
+    return g.gx[ci] >= -half && g.gx[ci + 1] <= half;
+  }
+  const double half = g.half_b + 1e-9 * g.h;
+  return (double)(ci - g.nux / 2) * g.h >= -half && (double)(ci + 1 - g.nux / 2) * g.h <= half;
+}
+
+// whether triangle tri (0: the cell's first) of cell ci holds local
+// coordinates (a, b), every barycentric weight >= -tol
+__device__ __forceinline__ bool cell_holds(int ci, int nux, double a, double b, int tri, double tol) {
+  if (2 * ci + 1 < nux) {
+    if (tri == 0) return 1.0 - a >= -tol && a - b >= -tol && b >= -tol;
+    return 1.0 - b >= -tol && a >= -tol && b - a >= -tol;
+  }
+  if (tri == 0) return 1.0 - a - b >= -tol && a >= -tol && b >= -tol;
+  return 1.0 - b >= -tol && a + b - 1.0 >= -tol && 1.0 - a >= -tol;
+}
+
+// Point location with the tie rule of the reading: a point goes to the
+// lowest-numbered triangle that holds it within 1e-12 in its barycentric
+// weights, triangles numbered cell by cell row-major from the bottom row,
+// a cell's first triangle first. The point lies in or next to cell
+// (ci0, cj0); coord(i, j, a, b) gives its local coordinates in cell (i, j).
+// Only where several triangles hold the point does the choice matter, and
+// then only for derivatives across a row line (values are continuous).
+template <class Coord>
+__device__ __forceinline__ bool lowest_triangle(const GridGeom &g, int ci0, int cj0, Coord coord, int &ci, int &cj,
+                                                double &a, double &b, int &tri) {
+  const double tol = 1e-12;
+  // the neighbours below, left of, right of or above cell (ci0, cj0) can
+  // hold the point only when it lies within tol of that side
+  double a0, b0;
+  coord(ci0, cj0, a0, b0);
+  const int jlo = b0 <= tol ? -1 : 0, jhi = b0 >= 1.0 - tol ? 1 : 0;
+  const int ilo = a0 <= tol ? -1 : 0, ihi = a0 >= 1.0 - tol ? 1 : 0;
+  for (int dj = jlo; dj <= jhi; ++dj)
+    for (int di = ilo; di <= ihi; ++di) {
+      const int i = ci0 + di, j = cj0 + dj;
+      if (i < 0 || j < 0 || i > g.nux - 2 || j > g.nuy - 2) continue;
+      double aa, bb;
+      coord(i, j, aa, bb);
+      // outside the cell's closed square widened by tol: no triangle of it
+      if (aa < -tol || aa > 1.0 + tol || bb < -tol || bb > 1.0 + tol || body_cell(g, i, j)) continue;
+      for (int t = 0; t < 2; ++t)
+        if (cell_holds(i, g.nux, aa, bb, t, tol)) {
+          ci = i;
+          cj = j;
+          a = aa;
+          b = bb;
+          tri = t;
+          return true;
+        }
+    }
+  return false;
+}
+
 // Lattice node (x, y) inside the grid at t_k (lower grid row at Y0): its
-// cell and local coordinates, as used by the lattice interpolation nodes.
+// cell, local coordinates and triangle, as used by the lattice
+// interpolation nodes.
 __device__ __forceinline__ void lattice_node_cell(const GridGeom &g, double ybase, int x, int y, int &ci, int &cj,
-                                                  double &a, double &b) {
+                                                  double &a, double &b, int &tri) {
+  tri = -1;
   if (g.gx) {  // graded: the cell holding the point, local coordinates in [0, 1]
     const double lx = (double)x - g.xc, ly = (double)y - ybase;
     ci = graded_cell(g.gx, g.nux, lx);
     cj = graded_cell(g.gy, g.nuy, ly);
     a = (lx - g.gx[ci]) / (g.gx[ci + 1] - g.gx[ci]);
     b = (ly - g.gy[cj]) / (g.gy[cj + 1] - g.gy[cj]);
+    (void)lowest_triangle(g, ci, cj, [&](int i, int j, double &aa, double &bb) {
+      aa = (lx - g.gx[i]) / (g.gx[i + 1] - g.gx[i]);
+      bb = (ly - g.gy[j]) / (g.gy[j + 1] - g.gy[j]);
+    }, ci, cj, a, b, tri);
     return;
   }
   const double X0 = g.xc + (double)(0 - g.nux / 2) * g.h;
@@ -300,6 +367,10 @@ __device__ __forceinline__ void lattice_node_cell(const GridGeom &g, double ybas
   cj = min(max((int)floor(t), 0), g.nuy - 2);
   a = s - ci;
   b = t - cj;
+  (void)lowest_triangle(g, ci, cj, [&](int i, int j, double &aa, double &bb) {
+    aa = s - i;
+    bb = t - j;
+  }, ci, cj, a, b, tri);
 }
 
 // Refill classification of grid node (i, j) moved from ybase to ybase1
@@ -308,71 +379,43 @@ __device__ __forceinline__ void lattice_node_cell(const GridGeom &g, double ybas
 struct RefillCell {
   int kind, ci, cj;
   double a, b;
+  int tri;  // triangle of the cell (kind 3)
 };
 
 __device__ __forceinline__ RefillCell refill_cell_graded(const GridGeom &g, double ybase, double ybase1, int i,
                                                          int j) {
   // the grid moves in y only: the node keeps its column, and its new height
   // is located among the old rows
-  const double tol = 1e-12;
   const double xrel = g.gx[i];
   const double Ynew = ybase1 + g.gy[j];
   const double py = Ynew - ybase;
-  const int slot_row = g.nuy / 2 - 1;
-  const double half = g.half_b + 1e-9 * (2.0 * g.half_T);
-  auto body_cell = [&](int ci, int cj) {
-    return g.body && cj == slot_row && g.gx[ci] >= -half && g.gx[ci + 1] <= half;
-  };
-  auto frac = [&](int cj) { return (py - g.gy[cj]) / (g.gy[cj + 1] - g.gy[cj]); };
-  RefillCell r{0, 0, 0, 0.0, 0.0};
-  const double span0 = g.gy[1] - g.gy[0], span1 = g.gy[g.nuy - 1] - g.gy[g.nuy - 2];
-  if (py >= g.gy[0] - tol * span0 && py <= g.gy[g.nuy - 1] + tol * span1) {
-    r.cj = graded_cell(g.gy, g.nuy, py);
-    r.ci = min(i, g.nux - 2);
-    r.a = (double)(i - r.ci);
-    r.b = frac(r.cj);
+  RefillCell r{0, 0, 0, 0.0, 0.0, -1};
+  const int ci0 = min(i, g.nux - 2), cj0 = graded_cell(g.gy, g.nuy, py);
+  if (lowest_triangle(g, ci0, cj0, [&](int ci, int cj, double &aa, double &bb) {
+        aa = (xrel - g.gx[ci]) / (g.gx[ci + 1] - g.gx[ci]);
+        bb = (py - g.gy[cj]) / (g.gy[cj + 1] - g.gy[cj]);
+      }, r.ci, r.cj, r.a, r.b, r.tri))
     r.kind = 3;
-    if (body_cell(r.ci, r.cj)) {
-      if (r.b <= tol && r.cj > 0 && !body_cell(r.ci, r.cj - 1)) { r.cj -= 1; r.b = frac(r.cj); }
-      else if (r.b >= 1.0 - tol && r.cj < g.nuy - 2 && !body_cell(r.ci, r.cj + 1)) { r.cj += 1; r.b = frac(r.cj); }
-      else if (r.a <= tol && r.ci > 0 && !body_cell(r.ci - 1, r.cj)) { r.ci -= 1; r.a += 1.0; }
-      else if (r.a >= 1.0 - tol && r.ci < g.nux - 2 && !body_cell(r.ci + 1, r.cj)) { r.ci += 1; r.a -= 1.0; }
-      else r.kind = 0;
-    }
-  }
-  if (r.kind != 3) r.kind = (g.body && fabs(xrel) < g.half_b && fabs(py) < g.half_T) ? 2 : 1;
+  else
+    r.kind = (g.body && fabs(xrel) < g.half_b && fabs(py) < g.half_T) ? 2 : 1;
   return r;
 }
 
 __device__ __forceinline__ RefillCell refill_cell(const GridGeom &g, double ybase, double ybase1, int i, int j) {
   if (g.gx) return refill_cell_graded(g, ybase, ybase1, i, j);
-  const double tol = 1e-12;
   const double xrel = (double)(i - g.nux / 2) * g.h;
   const double Ynew = ybase1 + ((double)j - 0.5 * (double)(g.nuy - 1)) * g.h;
   const double Y0 = ybase + (0.0 - 0.5 * (double)(g.nuy - 1)) * g.h;
   const double s = (double)i, t = (Ynew - Y0) / g.h;
-  const int slot_row = g.nuy / 2 - 1;
-  const double half = g.half_b + 1e-9 * g.h;
-  auto body_cell = [&](int ci, int cj) {
-    return g.body && cj == slot_row && (double)(ci - g.nux / 2) * g.h >= -half &&
-           (double)(ci + 1 - g.nux / 2) * g.h <= half;
-  };
-  RefillCell r{0, 0, 0, 0.0, 0.0};
-  if (t >= -tol && t <= (double)(g.nuy - 1) + tol) {
-    r.cj = min(max((int)floor(t), 0), g.nuy - 2);
-    r.ci = min(max((int)floor(s), 0), g.nux - 2);
-    r.b = t - r.cj;
-    r.a = s - r.ci;
+  RefillCell r{0, 0, 0, 0.0, 0.0, -1};
+  const int ci0 = min(max((int)floor(s), 0), g.nux - 2), cj0 = min(max((int)floor(t), 0), g.nuy - 2);
+  if (lowest_triangle(g, ci0, cj0, [&](int ci, int cj, double &aa, double &bb) {
+        aa = s - ci;
+        bb = t - cj;
+      }, r.ci, r.cj, r.a, r.b, r.tri))
     r.kind = 3;
-    if (body_cell(r.ci, r.cj)) {
-      if (r.b <= tol && r.cj > 0 && !body_cell(r.ci, r.cj - 1)) { r.cj -= 1; r.b += 1.0; }
-      else if (r.b >= 1.0 - tol && r.cj < g.nuy - 2 && !body_cell(r.ci, r.cj + 1)) { r.cj += 1; r.b -= 1.0; }
-      else if (r.a <= tol && r.ci > 0 && !body_cell(r.ci - 1, r.cj)) { r.ci -= 1; r.a += 1.0; }
-      else if (r.a >= 1.0 - tol && r.ci < g.nux - 2 && !body_cell(r.ci + 1, r.cj)) { r.ci += 1; r.a -= 1.0; }
-      else r.kind = 0;
-    }
-  }
-  if (r.kind != 3) r.kind = (g.body && fabs(xrel) < g.half_b && fabs(Ynew - ybase) < g.half_T) ? 2 : 1;
+  else
+    r.kind = (g.body && fabs(xrel) < g.half_b && fabs(Ynew - ybase) < g.half_T) ? 2 : 1;
   return r;
 }
 

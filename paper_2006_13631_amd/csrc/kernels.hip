@@ -211,10 +211,10 @@ __device__ __forceinline__ void lattice_from_grid_block(const CaseView<T, R> &v,
   if (x >= v.k2_x0 + v.k2_w || y > max(P.iy1, P.piy1)) return;
   if (!from_grid_target(P, x, y)) return;
   const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body, v.gx, v.gy};
-  int ci, cj, node[3];
+  int ci, cj, tri, node[3];
   double a, b, lam[3], dlam[3];
-  lattice_node_cell(gg, P.ybase, x, y, ci, cj, a, b);
-  cell_triangle(ci, cj, v.nux, a, b, node, lam, dlam);
+  lattice_node_cell(gg, P.ybase, x, y, ci, cj, a, b, tri);
+  cell_triangle(ci, cj, v.nux, a, b, node, lam, dlam, tri);
   R rho, ux, uy, fneq[9];
   grid_barycentric<R>(g, v.nnode, node, lam, rho, ux, uy, fneq);
   R e[9];
@@ -648,7 +648,7 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
   if (rc.kind == 3) {
     int node[3];
     double lam[3], dlam[3];
-    cell_triangle(rc.ci, rc.cj, v.nux, rc.a, rc.b, node, lam, dlam);
+    cell_triangle(rc.ci, rc.cj, v.nux, rc.a, rc.b, node, lam, dlam, rc.tri);
 #pragma unroll
     for (int q = 0; q < 9; ++q)
       out[q] = R(lam[0]) * fo[q * N + node[0]] + R(lam[1]) * fo[q * N + node[1]] + R(lam[2]) * fo[q * N + node[2]];

@@ -5,6 +5,7 @@ single-case path is parity-tested against the oracle), whatever schedule the
 autotuner picks; cases stop at their own max_steps; a case whose force turns
 non-finite stops and is reported while the others carry on.
 """
+import os
 import sys
 
 import numpy as np
@@ -60,6 +61,32 @@ def test_batch_matches_single_cases_bitwise(storage):
         inf = batch[i].info()
         assert inf.step == c["max_steps"] and inf.status == hlbm.STATUS_DONE
         _same(batch[i], _solo(c, storage))
+
+
+def test_batch_fp64_members_match_the_oracle(oracle):
+    """Every member of an FP64 batch (uneven lattices, grids, sub-step
+    counts and boundaries, autotuned schedule) against the oracle run of its
+    configuration, element by element: lattice, grid and force history
+    within 1e-12 of the oracle's largest value."""
+    _say("batch members vs oracle")
+    cfgs = _cases()
+    batch = hlbm.Batch(cfgs, storage=hlbm.FP64)
+    batch.tune(trial_steps=4)
+    batch.step(max(c["max_steps"] for c in cfgs))
+    oracle.set_threads(min(16, len(os.sched_getaffinity(0))))
+    try:
+        for i, c in enumerate(cfgs):
+            o = oracle.Sim(**c)
+            o.step(c["max_steps"])
+            m = batch[i]
+            for name, got, want in (("lattice", m.lattice(), o.lattice()), ("grid", m.grid(), o.grid()),
+                                    ("force", m.history(), o.history())):
+                assert got.shape == want.shape, (i, name)
+                err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+                _say("case", i, name, err)
+                assert err <= 1e-12, (i, name, err)
+    finally:
+        oracle.set_threads(1)
 
 
 @pytest.mark.parametrize("schedule", [
