@@ -353,13 +353,20 @@ __device__ __forceinline__ int ring_slot(int gi, int gj, int rx, int ry, int nux
   return -1;
 }
 
-template <class R, class G>
+// DB: two copies of the region, so that a sub-step reads one and writes the
+// other and a single barrier separates sub-steps
+template <class R, class G, bool DB = false>
 constexpr size_t substeps_lds_bytes() {
-  return sizeof(R) * (size_t)(NS * G::RN + NS * G::NRING) + sizeof(int) * (size_t)G::RN;
+  return sizeof(R) * (size_t)(NS * G::RN * (DB ? 2 : 1) + NS * G::NRING) + sizeof(int) * (size_t)G::RN;
+}
+// the region is double-buffered when both copies fit a CU's LDS
+template <class R, class G>
+constexpr bool substeps_double_buffer() {
+  return substeps_lds_bytes<R, G, true>() <= 160u * 1024u;
 }
 
 // Advances tile t of a grid by `count` sub-steps m0 .. m0+count-1 of step k.
-template <class R, class G, int H, int NT>
+template <class R, class G, int H, int NT, bool DB = false>
 __device__ __forceinline__ void grid_substeps_block(
     const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
     const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int t,
@@ -369,8 +376,9 @@ __device__ __forceinline__ void grid_substeps_block(
   constexpr int SPER = (RN + NT - 1) / NT;      // staging passes
   constexpr int PER = (G::MAXA + NT - 1) / NT;  // update passes
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  R *sl = reinterpret_cast<R *>(lds_raw);   // [RN][NS] grid f, rho u u
-  R *rl = sl + NS * RN;                     // [NRING][NS] f*, rho* u* u* on the outer ring
+  R *sl = reinterpret_cast<R *>(lds_raw);   // [RN][NS] grid f, rho u u (DB: two copies)
+  constexpr int RING = NS * RN * (DB ? 2 : 1);  // offset of the ring values
+  R *rl = sl + RING;                        // [NRING][NS] f*, rho* u* u* on the outer ring
   int *scode = reinterpret_cast<int *>(rl + NS * G::NRING);  // 4 * class + type, -1 outside the grid
   const int x0 = (t % tiles_x) * TX - H, y0 = (t / tiles_x) * TY - H;  // region origin
   const bool touches_ring = x0 <= 0 || y0 <= 0 || x0 + RX >= nux || y0 + G::RY >= nuy;
@@ -422,6 +430,9 @@ __device__ __forceinline__ void grid_substeps_block(
       for (int q = 0; q < 9; ++q) sl[idx * NS + q] = v[u][q];
 #pragma unroll
       for (int a = 0; a < 3; ++a) sl[idx * NS + 9 + a] = P[a];
+      if (DB && !inside[u])  // never written by a sub-step: zero in both copies
+#pragma unroll
+        for (int a = 0; a < NS; ++a) sl[NS * RN + idx * NS + a] = R(0);
     }
   }
   __syncthreads();
@@ -442,7 +453,7 @@ __device__ __forceinline__ void grid_substeps_block(
   // sum_s C_s (rho u u)_s. On the outer ring an interpolation node reads
   // structured-derived values instead (Eq.(postcollision2_u)). Absent
   // neighbours have zero weights.
-  auto update_node = [&](int idx, int code, const GridClass<R> &cl, R o9[9]) {
+  auto update_node = [&](int idx, int code, const GridClass<R> &cl, int cur, R o9[9]) {
     const int rx = idx % RX, ry = idx / RX;
     const int typ = code & 3;
     const int gi = x0 + rx, gj = y0 + ry;
@@ -450,10 +461,10 @@ __device__ __forceinline__ void grid_substeps_block(
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
       const int di = s % 3 - 1, dj = s / 3 - 1;
-      row[s] = (idx + dj * RX + di) * NS;
+      row[s] = cur + (idx + dj * RX + di) * NS;
       if (typ == NODE_INTERFACE) {
         const int rs = ring_slot<G>(gi + di, gj + dj, rx + di, ry + dj, nux, nuy);
-        if (rs >= 0) row[s] = NS * RN + rs * NS;
+        if (rs >= 0) row[s] = RING + rs * NS;
       }
     }
     // out_q = f_q + dt c_q.(G f_q) - dt/tau (A_q - sum_s C_s f^eq_q(m_s)): the
@@ -492,10 +503,14 @@ __device__ __forceinline__ void grid_substeps_block(
       o9[q] = fmad(dt_tau * wgt<R>(q), fmad(R(4.5), cc, fmad(R(3), cu, base)), o9[q]);
     }
   };
+  // copy a sub-step reads (offset into the LDS values); DB: the other copy
+  // receives its results
+  auto copy_of = [&](int sub) { return DB ? (sub & 1) * NS * RN : 0; };
 #pragma unroll
   for (int sub = 0; sub < H; ++sub) {
     if (sub >= count) break;
     const R uw_now = uwv[sub];
+    const int cur = copy_of(sub), nxt = copy_of(sub + 1);
     R out[PER][9];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -503,12 +518,9 @@ __device__ __forceinline__ void grid_substeps_block(
       lane_node(sub, u, idx, code);
 #pragma unroll
       for (int q = 0; q < 9; ++q) out[u][q] = R(0);
-      // one pass per stencil class present in the wave (one pass for most
-      // waves): the class index is wave-uniform, so its coefficients sit in
-      // scalar registers
-      if (__ballot(code >= 0) == 0) continue;
+      if (__ballot(code >= 0) == 0) continue;  // nothing to update in this wave
       if (code < 0) continue;
-      update_node(idx, code, tab[code >> 2], out[u]);
+      update_node(idx, code, tab[code >> 2], cur, out[u]);
       if ((code & 3) == NODE_WALL) {
         // wall nodes: impose the lamina velocity, keep rho and f^neq
         const int rx = idx % RX, ry = idx / RX;
@@ -527,19 +539,29 @@ __device__ __forceinline__ void grid_substeps_block(
 #pragma unroll
         for (int q = 0; q < 9; ++q) out[u][q] = ew[q] + (out[u][q] - e[q]);
       }
+      if (DB) {  // the other copy: written at once, read after the barrier
+        R P[3];
+        quad_moments<R>(out[u], P);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sl[nxt + idx * NS + q] = out[u][q];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sl[nxt + idx * NS + 9 + a] = P[a];
+      }
     }
-    __syncthreads();
+    if (!DB) {  // one copy: every read of the sub-step ends before the writes
+      __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      int idx, code;
-      lane_node(sub, u, idx, code);
-      if (code < 0) continue;
-      R P[3];
-      quad_moments<R>(out[u], P);
+      for (int u = 0; u < PER; ++u) {
+        int idx, code;
+        lane_node(sub, u, idx, code);
+        if (code < 0) continue;
+        R P[3];
+        quad_moments<R>(out[u], P);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) sl[idx * NS + q] = out[u][q];
+        for (int q = 0; q < 9; ++q) sl[idx * NS + q] = out[u][q];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) sl[idx * NS + 9 + a] = P[a];
+        for (int a = 0; a < 3; ++a) sl[idx * NS + 9 + a] = P[a];
+      }
     }
     __syncthreads();
     // the tile is exact after every sub-step: a tape keeps the intermediate ones
@@ -552,12 +574,13 @@ __device__ __forceinline__ void grid_substeps_block(
         const int ci = ry * RX + rx;
         const size_t p = (size_t)gj * nux + gi;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) dst[q * N + p] = sl[ci * NS + q];
+        for (int q = 0; q < 9; ++q) dst[q * N + p] = sl[nxt + ci * NS + q];
       }
     }
   }
 
   // the tile is exact: write it back
+  const int last = copy_of(count);
   for (int j = threadIdx.x; j < TX * TY; j += NT) {
     const int rx = H + j % TX, ry = H + j / TX;
     const int gi = x0 + rx, gj = y0 + ry;
@@ -565,7 +588,7 @@ __device__ __forceinline__ void grid_substeps_block(
     const int ci = ry * RX + rx;
     const size_t p = (size_t)gj * nux + gi;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) fout[q * N + p] = sl[ci * NS + q];
+    for (int q = 0; q < 9; ++q) fout[q * N + p] = sl[last + ci * NS + q];
   }
 }
 
@@ -601,8 +624,9 @@ __global__ __launch_bounds__(SubstepVariant<V>::NT) void k_grid_substeps(
   using SV = SubstepVariant<V>;
   const int b = blockIdx.x;  // tiles are dealt to the eight XCDs in contiguous bands
   const int t = (ntiles % 8 == 0) ? (b % 8) * (ntiles / 8) + (b / 8) : b;
-  grid_substeps_block<R, typename SV::G, SV::H, SV::NT>(f, fout, star_f, star_n, cls, tab, nux, nuy, tiles_x, t, dt,
-                                                        dt_tau, uw, *dk, n_sub, m0, count, tape, wtape, widx, nwall);
+  grid_substeps_block<R, typename SV::G, SV::H, SV::NT, substeps_double_buffer<R, typename SV::G>()>(
+      f, fout, star_f, star_n, cls, tab, nux, nuy, tiles_x, t, dt, dt_tau, uw, *dk, n_sub, m0, count, tape, wtape,
+      widx, nwall);
 }
 
 // launch m0 / kSubstepBlock of a batched step: item = (case, tile)
@@ -993,22 +1017,25 @@ template <class T, class R>
 hipError_t Kernels<T, R>::prepare() {
 #define HLBM_LDS(V)                                                                                                  \
   {reinterpret_cast<const void *>(&k_grid_substeps<R, V>), reinterpret_cast<const void *>(&kb_grid_substeps<T, R, V>), \
+   (int)substeps_lds_bytes<R, typename SubstepVariant<V>::G,                                                          \
+                           substeps_double_buffer<R, typename SubstepVariant<V>::G>()>(),                            \
    (int)substeps_lds_bytes<R, typename SubstepVariant<V>::G>()}
   struct FnLds {
     const void *f, *fb;
-    int lds;
+    int lds, lds_b;
   };
   const FnLds fns[] = {HLBM_LDS(0), HLBM_LDS(1), HLBM_LDS(2), HLBM_LDS(3),
              HLBM_LDS(4), HLBM_LDS(5), HLBM_LDS(6), HLBM_LDS(7)};
 #undef HLBM_LDS
   for (const auto &e : fns) {
     hipError_t rc = hipFuncSetAttribute(e.f, hipFuncAttributeMaxDynamicSharedMemorySize, e.lds);
-    if (rc == hipSuccess) rc = hipFuncSetAttribute(e.fb, hipFuncAttributeMaxDynamicSharedMemorySize, e.lds);
+    if (rc == hipSuccess) rc = hipFuncSetAttribute(e.fb, hipFuncAttributeMaxDynamicSharedMemorySize, e.lds_b);
     if (rc != hipSuccess) return rc;
   }
 #define HLBM_LDS1(V)                                                                                      \
   {reinterpret_cast<const void *>(&k_grid_substeps<R, V>), nullptr,                                       \
-   (int)substeps_lds_bytes<R, typename SubstepVariant<V>::G>()}
+   (int)substeps_lds_bytes<R, typename SubstepVariant<V>::G,                                              \
+                           substeps_double_buffer<R, typename SubstepVariant<V>::G>()>(), 0}
   const FnLds single[] = {HLBM_LDS1(8), HLBM_LDS1(9), HLBM_LDS1(10)};
 #undef HLBM_LDS1
   for (const auto &e : single) {
@@ -1073,15 +1100,16 @@ void Kernels<T, R>::grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout
                                     hipEvent_t stop) {
   using SV = SubstepVariant<V>;
   const int tiles_x = (v.nux + SV::G::TX - 1) / SV::G::TX, tiles_y = (v.nuy + SV::G::TY - 1) / SV::G::TY;
+  constexpr size_t lds = substeps_lds_bytes<R, typename SV::G, substeps_double_buffer<R, typename SV::G>()>();
   if (start || stop)
-    hipExtLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT),
-                          (substeps_lds_bytes<R, typename SV::G>()), s, start, stop, 0, f, fout,
+    hipExtLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT), lds, s, start, stop, 0,
+                          f, fout,
                           (const R *)v.star_f, (const R *)v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x,
                           tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m0,
                           count, tape, wtape, widx, nwall);
   else
-    hipLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT),
-                       (substeps_lds_bytes<R, typename SV::G>()), s, f, fout, (const R *)v.star_f,
+    hipLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT), lds, s, f, fout,
+                       (const R *)v.star_f,
                        (const R *)v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u,
                        v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m0, count, tape, wtape, widx, nwall);
 }
