@@ -337,10 +337,14 @@ def sweep_leg(seed=0, periods=10.0, loop=True, tune_steps=8, chunk=4000, only=No
     print(f"# sweep: {n} cases, FP32 batch, schedule {tuning}", file=sys.stderr, flush=True)
     longest = max(c["max_steps"] for c in cases)
     t0 = time.perf_counter()
-    done = 0
+    done, running, t_tail = 0, n, 0.0
+    tail_n = max(1, n // 8)        # the batch's tail: at most this many cases still run
     while done < longest:
         m = min(chunk, longest - done)
+        tc = time.perf_counter()
         batch.step(m)
+        if running <= tail_n:
+            t_tail += time.perf_counter() - tc
         done += m
         running = sum(1 for k in range(n) if batch[k].info().status == H.STATUS_RUNNING)
         print(f"# batch step {done}/{longest}, running {running}, {time.perf_counter() - t0:.1f} s",
@@ -367,6 +371,7 @@ def sweep_leg(seed=0, periods=10.0, loop=True, tune_steps=8, chunk=4000, only=No
                      "tune_s": round(t_tune, 2), "run_s": round(t_batch, 2),
                      "cases_per_hour": round(n / ((t_create + t_tune + t_batch) / 3600.0), 1),
                      "cases_per_hour_run_only": round(n / (t_batch / 3600.0), 1),
+                     "tail_s": round(t_tail, 2), "tail_cases": tail_n,
                      "diverged": int(sum(1 for x in st32 if x == H.STATUS_UNSTABLE))}}
     out["value"] = out["batch"]["cases_per_hour"]
     if loop:

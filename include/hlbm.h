@@ -155,6 +155,18 @@ typedef struct hlbm_tuning {
   int32_t tail_variant;    /* batch: sub-step variant once at most
                               max(1, ncases/8) cases still run (-1: the
                               same as substep_variant); single case: -1    */
+  int32_t persistent;      /* batch: 0 HIP graphs of steps_per_graph steps;
+                              1 one cooperative launch per run of up to
+                              256 steps, every workgroup walking the
+                              kernels of a step with a grid-wide barrier
+                              between them; 2 graphs, then the cooperative
+                              launch once at most max(1, ncases/8) cases
+                              run. The cooperative launch takes sub-step
+                              variants 4-7 (others: 5) and one lattice row
+                              per lane; single case: 0                     */
+  int32_t persistent_groups; /* batch: workgroups of the cooperative launch
+                              (0: as many as the widest kernel of a step
+                              has work items, at most what fits at once)   */
   double ms_per_step;      /* measured for the chosen schedule (output)      */
 } hlbm_tuning;
 
@@ -379,10 +391,11 @@ int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count)
 /* Autotuner. Batched handle: before its first step, time candidate
  * schedules for trial_steps steps of the whole batch, one choice at a time
  * (steps per graph 4/8/16; stream-collide shape 128/256 x 1/2/4 rows;
- * sub-step variant; work-list order) with the others held at the best so
- * far, then the sub-step variant on the longest-running max(1, ncases/8)
- * cases alone (tail_variant), keep the fastest and restore the initial
- * state. Single case (any
+ * sub-step variant; work-list order; the cooperative launch in variants
+ * 4-7, then its workgroup count) with the others held at the best so
+ * far, then the sub-step variant and the launch kind on the
+ * longest-running max(1, ncases/8) cases alone (tail_variant, persistent
+ * 2), keep the fastest and restore the initial state. Single case (any
  * time, state untouched): time trial_steps launches of the stream-collide
  * in each shape and order and of one step's sub-steps in each variant, reading the
  * current lattice and grid and writing only their free buffers, and keep

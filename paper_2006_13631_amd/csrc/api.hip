@@ -849,7 +849,7 @@ class Case final : public CaseBase {
       HIPCHK(hipStreamSynchronize(s_main_));
       drop_graphs();
       HIPCHK(prime_graphs());
-      *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, -1, 0.0};
+      *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, -1, 0, 0, 0.0};
       return HLBM_OK;
     }
     HIPCHK(hipDeviceSynchronize());
@@ -910,7 +910,8 @@ class Case final : public CaseBase {
     HIPCHK(e);
     drop_graphs();
     HIPCHK(prime_graphs());
-    *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, -1, total / trial_steps};
+    *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, -1, 0, 0,
+                      total / trial_steps};
     return HLBM_OK;
   }
 
@@ -1783,7 +1784,7 @@ class Batch final : public CaseBase {
     for (int i = 0; i < n; ++i) v[i] = cases_[i]->batched_view();
     HIPCHK(hipMalloc(&views_, n * sizeof(CaseView<T, R>)));
     HIPCHK(hipMemcpy(views_, v.data(), n * sizeof(CaseView<T, R>), hipMemcpyHostToDevice));
-    tuning_ = {8, kLatticeThreads, kLatticeRows, -1, 1, -1, 0.0};
+    tuning_ = {8, kLatticeThreads, kLatticeRows, -1, 1, -1, 0, 0, 0.0};
     tail_n_ = std::max(1, n / 8);
     return HLBM_OK;
   }
@@ -1820,7 +1821,8 @@ class Batch final : public CaseBase {
     if (trial_steps == 0) {
       if (t->steps_per_graph < 1 || t->steps_per_graph > 64 || !valid_lattice_shape(*t) ||
           t->substep_variant < -1 || t->substep_variant >= kSubstepVariants || t->order < 0 || t->order > 1 ||
-          t->tail_variant < -1 || t->tail_variant >= kSubstepVariants)
+          t->tail_variant < -1 || t->tail_variant >= kSubstepVariants || t->persistent < 0 || t->persistent > 2 ||
+          t->persistent_groups < 0)
         return fail(HLBM_E_ARG, "invalid schedule");
       tuning_ = *t;
       tuning_.ms_per_step = 0.0;
@@ -1859,48 +1861,89 @@ class Batch final : public CaseBase {
         best = cand;
       }
     };
-    for (int g : {4, 8, 16}) trial(hlbm_tuning{g, best.lattice_threads, best.lattice_rows, best.substep_variant,
-                                               best.order, -1, 0.0});
+    auto cand = [](hlbm_tuning b) {
+      b.tail_variant = -1;
+      b.ms_per_step = 0.0;
+      return b;
+    };
+    for (int g : {4, 8, 16}) {
+      hlbm_tuning c = cand(best);
+      c.steps_per_graph = g;
+      trial(c);
+    }
     const hlbm_tuning after_g = best;
     for (int lt : {128, 256})
       for (int rows : {1, 2, 4})
-        if (lt != after_g.lattice_threads || rows != after_g.lattice_rows)
-          trial(hlbm_tuning{after_g.steps_per_graph, lt, rows, after_g.substep_variant, after_g.order, -1, 0.0});
+        if (lt != after_g.lattice_threads || rows != after_g.lattice_rows) {
+          hlbm_tuning c = cand(after_g);
+          c.lattice_threads = lt;
+          c.lattice_rows = rows;
+          trial(c);
+        }
     const hlbm_tuning after_l = best;
     for (int sv = 0; sv < kSubstepVariants; ++sv)
-      if (sv != (after_l.substep_variant < 0 ? default_substep_variant<R>() : after_l.substep_variant))
-        trial(hlbm_tuning{after_l.steps_per_graph, after_l.lattice_threads, after_l.lattice_rows, sv, after_l.order, -1,
-                          0.0});
+      if (sv != (after_l.substep_variant < 0 ? default_substep_variant<R>() : after_l.substep_variant)) {
+        hlbm_tuning c = cand(after_l);
+        c.substep_variant = sv;
+        trial(c);
+      }
     const hlbm_tuning after_s = best;
-    trial(hlbm_tuning{after_s.steps_per_graph, after_s.lattice_threads, after_s.lattice_rows, after_s.substep_variant,
-                      1 - after_s.order, -1, 0.0});
+    {
+      hlbm_tuning c = cand(after_s);
+      c.order = 1 - after_s.order;
+      trial(c);
+    }
+    // one persistent cooperative launch per run instead of the graphs, in
+    // each of its sub-step variants, then its workgroup count
+    const hlbm_tuning after_o = best;
+    for (int sv = kPersistentFirst; sv <= kPersistentLast; ++sv) {
+      hlbm_tuning c = cand(after_o);
+      c.persistent = 1;
+      c.persistent_groups = 0;
+      c.substep_variant = sv;
+      trial(c);
+    }
+    if (best.persistent == 1) {
+      const hlbm_tuning after_p = best;
+      for (int g : {256, 512, 1024}) {
+        hlbm_tuning c = cand(after_p);
+        c.persistent_groups = g;
+        trial(c);
+      }
+    }
     const double all_ms = best_ms;
     // the last few cases (the longest runs) often want another sub-step
-    // kernel than the full set: time the variants on them alone
+    // kernel than the full set, or the persistent launch: time them alone
     std::vector<int> tail(all);
     std::sort(tail.begin(), tail.end(),
               [&](int a, int b) { return cases_[a]->max_steps() > cases_[b]->max_steps(); });
     if ((int)tail.size() > tail_n_) tail.resize(tail_n_);
-    int tail_sv = -1;
+    int tail_sv = -1, tail_persistent = 0;
     if (rc == HLBM_OK && !tail.empty() && tail.size() < all.size()) {
       float tail_best = 3e38f;
-      for (int sv = 0; sv < kSubstepVariants && rc == HLBM_OK; ++sv) {
-        tuning_ = best;
-        tuning_.substep_variant = sv;
-        invalidate();
-        float ms = 0.f;
-        rc = timed_trial(tail, trial_steps, &ms);
-        if (rc == HLBM_OK) rc = restore(snap);
-        if (rc == HLBM_OK && ms < tail_best) {
-          tail_best = ms;
-          tail_sv = sv;
+      for (int mode = best.persistent == 1 ? 1 : 0; mode <= 1 && rc == HLBM_OK; ++mode)
+        for (int sv = mode ? kPersistentFirst : 0; sv <= (mode ? kPersistentLast : kSubstepVariants - 1) &&
+                                                    rc == HLBM_OK;
+             ++sv) {
+          tuning_ = best;
+          tuning_.persistent = mode;
+          tuning_.substep_variant = sv;
+          invalidate();
+          float ms = 0.f;
+          rc = timed_trial(tail, trial_steps, &ms);
+          if (rc == HLBM_OK) rc = restore(snap);
+          if (rc == HLBM_OK && ms < tail_best) {
+            tail_best = ms;
+            tail_sv = sv;
+            tail_persistent = mode;
+          }
         }
-      }
     }
     for (void *p : snap) (void)hipFree(p);
     if (rc != HLBM_OK) return rc;
     tuning_ = best;
     tuning_.tail_variant = tail_sv;
+    if (best.persistent == 0 && tail_persistent) tuning_.persistent = 2;
     tuning_.ms_per_step = all_ms;
     invalidate();
     *t = tuning_;
@@ -1939,6 +1982,11 @@ class Batch final : public CaseBase {
     if (gexec_) (void)hipGraphExecDestroy(gexec_);
     gexec_ = nullptr;
     listed_.clear();
+    if (pitems_) (void)hipFree(pitems_);
+    if (pprog_) (void)hipFree(pprog_);
+    pitems_ = nullptr;
+    pprog_ = nullptr;
+    plisted_.clear();
   }
 
   void release() {
@@ -1978,13 +2026,97 @@ class Batch final : public CaseBase {
     return e;
   }
 
+  bool is_tail(const std::vector<int> &act) const { return (int)act.size() <= tail_n_; }
+
+  // the sub-step kernel for this set of running cases
+  int variant_for(const std::vector<int> &act) const {
+    const int sv = (tuning_.tail_variant >= 0 && is_tail(act)) ? tuning_.tail_variant : tuning_.substep_variant;
+    return sv < 0 ? default_substep_variant<R>() : sv;
+  }
+
+  bool persistent_for(const std::vector<int> &act) const {
+    return tuning_.persistent == 1 || (tuning_.persistent == 2 && is_tail(act));
+  }
+
+  // work items and phases of one persistent step over the running cases:
+  // the items of every phase built for workgroups of the persistent
+  // kernel's width (one lattice row per stream-collide item), in the order
+  // of the graph path's launches
+  hipError_t build_persistent(const std::vector<int> &act) {
+    const int sv = variant_for(act);
+    pv_ = (sv >= kPersistentFirst && sv <= kPersistentLast) ? sv : kPersistentDefault;
+    const int nt = Kernels<T, R>::persistent_threads(pv_);
+    std::vector<int4> items;
+    std::vector<BatchPhase> prog;
+    int widest = 1;
+    auto phase = [&](BatchKernel which, int m0, auto &&fill) {
+      const int first = (int)items.size();
+      for (int c : act) fill(c, cases_[c]->batched_view());
+      const int n = (int)items.size() - first;
+      if (n > 0) prog.push_back(BatchPhase{(int)which, first, n, m0});
+      widest = std::max(widest, n);
+    };
+    phase(BatchKernel::LatticeFromGrid, 0, [&](int c, const CaseView<T, R> &v) {
+      for (int by = 0; by < v.k2_h; ++by)
+        for (int bx = 0; bx < (v.k2_w + nt - 1) / nt; ++bx) items.push_back(make_int4(c, bx, by, 0));
+    });
+    phase(BatchKernel::StreamCollide, 0, [&](int c, const CaseView<T, R> &v) {
+      for (int by = 0; by < v.ny; ++by)
+        for (int bx = 0; bx < (v.nx + nt - 1) / nt; ++bx) items.push_back(make_int4(c, bx, by, 0));
+    });
+    phase(BatchKernel::InterfaceDonors, 0, [&](int c, const CaseView<T, R> &v) {
+      for (int bx = 0; bx < (4 * v.n_iface + nt - 1) / nt; ++bx) items.push_back(make_int4(c, bx, 0, 0));
+    });
+    int lmax = 0;
+    for (int c : act) {
+      const CaseView<T, R> v = cases_[c]->batched_view();
+      lmax = std::max(lmax, (v.n_sub + kSubstepBlock - 1) / kSubstepBlock);
+    }
+    int tx, ty;
+    substep_tile(pv_, &tx, &ty);
+    for (int i = 0; i < lmax; ++i)
+      phase(BatchKernel::GridSubsteps, i * kSubstepBlock, [&](int c, const CaseView<T, R> &v) {
+        if ((v.n_sub + kSubstepBlock - 1) / kSubstepBlock <= i) return;
+        const int tiles = ((v.nux + tx - 1) / tx) * ((v.nuy + ty - 1) / ty);
+        for (int t = 0; t < tiles; ++t) items.push_back(make_int4(c, t, 0, 0));
+      });
+    phase(BatchKernel::Refill, 0, [&](int c, const CaseView<T, R> &v) {
+      for (int bx = 0; bx < (v.nnode + nt - 1) / nt; ++bx) items.push_back(make_int4(c, bx, 0, 0));
+    });
+    phase(BatchKernel::Force, 0, [&](int c, const CaseView<T, R> &) { items.push_back(make_int4(c, 0, 0, 0)); });
+    hipError_t e = hipMalloc(&pitems_, items.size() * sizeof(int4));
+    if (e == hipSuccess) e = hipMemcpy(pitems_, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&pprog_, prog.size() * sizeof(BatchPhase));
+    if (e == hipSuccess)
+      e = hipMemcpy(pprog_, prog.data(), prog.size() * sizeof(BatchPhase), hipMemcpyHostToDevice);
+    pnphase_ = (int)prog.size();
+    // more workgroups than the widest phase has items would only wait
+    pgroups_ = tuning_.persistent_groups > 0 ? std::min(tuning_.persistent_groups, widest) : widest;
+    plisted_ = act;
+    return e;
+  }
+
+  hipError_t ensure_persistent(const std::vector<int> &act) {
+    if (pitems_ && act == plisted_) return hipSuccess;
+    invalidate();
+    return build_persistent(act);
+  }
+
+  // m steps of the running cases in cooperative launches of at most
+  // kPersistentChunk steps each
+  hipError_t launch_persistent(int64_t m) {
+    for (int64_t s = 0; s < m; s += kPersistentChunk) {
+      const int n = (int)std::min<int64_t>(kPersistentChunk, m - s);
+      hipError_t e = Kernels<T, R>::batched_persistent(views_, pitems_, pprog_, pnphase_, n, pv_, pgroups_, s_);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
   // work lists of the running cases: stream-collide, lattice-from-grid,
   // donors, refill, force, then one per sub-step launch
   hipError_t build_lists(const std::vector<int> &act) {
-    // the sub-step kernel for this set of running cases
-    const int sv = (tuning_.tail_variant >= 0 && (int)act.size() <= tail_n_) ? tuning_.tail_variant
-                                                                             : tuning_.substep_variant;
-    sv_ = sv < 0 ? default_substep_variant<R>() : sv;
+    sv_ = variant_for(act);
     for (auto &l : lists_)
       if (l.d) (void)hipFree(l.d);
     lists_.assign(5, List{});
@@ -2055,10 +2187,15 @@ class Batch final : public CaseBase {
 
   // m steps of the running cases act (none of them ends before m steps)
   int run(const std::vector<int> &act, int64_t m) {
-    HIPCHK(ensure_graph(act));
-    int64_t s = 0;
-    for (; s + tuning_.steps_per_graph <= m; s += tuning_.steps_per_graph) HIPCHK(hipGraphLaunch(gexec_, s_));
-    for (; s < m; ++s) enqueue_step();
+    if (persistent_for(act)) {
+      HIPCHK(ensure_persistent(act));
+      HIPCHK(launch_persistent(m));
+    } else {
+      HIPCHK(ensure_graph(act));
+      int64_t s = 0;
+      for (; s + tuning_.steps_per_graph <= m; s += tuning_.steps_per_graph) HIPCHK(hipGraphLaunch(gexec_, s_));
+      for (; s < m; ++s) enqueue_step();
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s_));
     for (int c : act) {
@@ -2072,13 +2209,20 @@ class Batch final : public CaseBase {
   }
 
   int timed_trial(const std::vector<int> &act, int steps, float *ms) {
-    HIPCHK(ensure_graph(act));
-    // one untimed graph launch, then the timed steps
-    HIPCHK(hipGraphLaunch(gexec_, s_));
-    HIPCHK(hipEventRecord(ev0_, s_));
-    int s = 0;
-    for (; s + tuning_.steps_per_graph <= steps; s += tuning_.steps_per_graph) HIPCHK(hipGraphLaunch(gexec_, s_));
-    for (; s < steps; ++s) enqueue_step();
+    if (persistent_for(act)) {
+      HIPCHK(ensure_persistent(act));
+      HIPCHK(launch_persistent(tuning_.steps_per_graph));  // untimed
+      HIPCHK(hipEventRecord(ev0_, s_));
+      HIPCHK(launch_persistent(steps));
+    } else {
+      HIPCHK(ensure_graph(act));
+      // one untimed graph launch, then the timed steps
+      HIPCHK(hipGraphLaunch(gexec_, s_));
+      HIPCHK(hipEventRecord(ev0_, s_));
+      int s = 0;
+      for (; s + tuning_.steps_per_graph <= steps; s += tuning_.steps_per_graph) HIPCHK(hipGraphLaunch(gexec_, s_));
+      for (; s < steps; ++s) enqueue_step();
+    }
     HIPCHK(hipEventRecord(ev1_, s_));
     HIPCHK(hipEventSynchronize(ev1_));
     HIPCHK(hipEventElapsedTime(ms, ev0_, ev1_));
@@ -2112,6 +2256,13 @@ class Batch final : public CaseBase {
   hlbm_tuning tuning_{};
   int tail_n_ = 1;  // at most this many running cases: the tail's sub-step variant
   int sv_ = 0;      // sub-step variant of the current work lists
+  // persistent launch: items and phases of the running cases plisted_
+  int4 *pitems_ = nullptr;
+  BatchPhase *pprog_ = nullptr;
+  std::vector<int> plisted_;
+  int pnphase_ = 0, pgroups_ = 1, pv_ = kPersistentDefault;
+  static constexpr int kPersistentFirst = 4, kPersistentLast = 7, kPersistentDefault = 5;
+  static constexpr int64_t kPersistentChunk = 256;
 };
 
 // Nested structured refinement levels. Levels 0 .. L-2 are plain lattices

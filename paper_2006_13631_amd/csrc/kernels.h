@@ -82,6 +82,12 @@ inline size_t lattice_plane(int nx, int ny) {
 
 enum class BatchKernel { StreamCollide, LatticeFromGrid, InterfaceDonors, GridSubsteps, Refill, Force };
 
+// one phase of a persistent batched step: block function `which`
+// (BatchKernel), work items first .. first+n-1, first sub-step m0
+struct BatchPhase {
+  int which, first, n, m0;
+};
+
 // grid sub-steps advanced per launch (temporal blocking depth)
 constexpr int kSubstepBlock = 4;
 
@@ -162,6 +168,15 @@ struct Kernels {
   static void batched(BatchKernel which, const CaseView<T, R> *views, const int4 *items, int nitems, int m0,
                       int threads, hipStream_t s, int rows = 1);
   static void lattice_from_f64(const double *src, T *dst, size_t plane, size_t nodes, hipStream_t s);
+  // `steps` steps of the running cases in one cooperative launch of at most
+  // max_groups workgroups of the sub-step variant's width (variants 4-7),
+  // walking the phases prog[0 .. nphase-1] of a step with a grid barrier
+  // after each; the work items are built for that width and one lattice row
+  // per lane
+  static hipError_t batched_persistent(const CaseView<T, R> *views, const int4 *items, const BatchPhase *prog,
+                                       int nphase, int steps, int variant, int max_groups, hipStream_t s);
+  // workgroup width of the persistent kernel of a sub-step variant (0: none)
+  static int persistent_threads(int variant);
 };
 
 // Exchange between structured refinement levels. A box (x0, y0, x1, y1) of

@@ -4,8 +4,10 @@
 // for the lattice and [9][nnode] for the body-fitted grid. T is the storage
 // type of the lattice and R the arithmetic type (FP64/FP64, FP32/FP32,
 // FP16 holding f_i - w_i / FP32). The grid is kept in R.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device_common.h"
@@ -717,55 +719,60 @@ __global__ __launch_bounds__(256) void kb_refill(const CaseView<T, R> *__restric
 
 // ---- K6: force on the lamina, then advance the step counter ------------------
 // Traction -p' n + sigma' n on each wall edge (trapezoid rule), p' = c_s^2
-// (rho - 1), sigma'_ab = -sum_i c_ia c_ib f_i^neq; FP64 accumulation, wave64
-// shuffle reduction and one LDS pass across the four waves.
+// (rho - 1), sigma'_ab = -sum_i c_ia c_ib f_i^neq; FP64 accumulation over 256
+// virtual lanes (lane l takes edges l, l + 256, ...), a wave64 shuffle
+// reduction per group of 64 and one LDS pass across the four groups, so the
+// sum is rounded the same way whatever the workgroup width (a multiple of
+// 64, at most 256).
+constexpr int kForceLanes = 256;
 template <class R>
 __device__ __forceinline__ void force_block(const R *__restrict__ f, const WallEdge *__restrict__ wall,
                                             int n_wall_edges, int nnode, int64_t *dk, double *hist, int *flag,
                                             const MotionCtx &mot = MotionCtx{}, StepParams *P = nullptr,
                                             R *uw = nullptr, int n_sub = 0, int advance = 1) {
-  __shared__ double red[2][4];
-  double Fx = 0.0, Fy = 0.0;
-  for (int e = threadIdx.x; e < n_wall_edges; e += blockDim.x) {
-    const WallEdge w = wall[e];
-    double tx = 0.0, ty = 0.0;
-    for (int s = 0; s < 2; ++s) {
-      const int p = s ? w.b : w.a;
-      R fp[9], eq[9], r, vx, vy;
+  __shared__ double red[2][kForceLanes / 64];
+  const int lane = threadIdx.x & 63;
+  for (int vw = threadIdx.x >> 6; vw < kForceLanes / 64; vw += blockDim.x >> 6) {
+    double Fx = 0.0, Fy = 0.0;
+    for (int e = vw * 64 + lane; e < n_wall_edges; e += kForceLanes) {
+      const WallEdge w = wall[e];
+      double tx = 0.0, ty = 0.0;
+      for (int s = 0; s < 2; ++s) {
+        const int p = s ? w.b : w.a;
+        R fp[9], eq[9], r, vx, vy;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) fp[q] = f[(size_t)q * nnode + p];
-      moments<R>(fp, r, vx, vy);
-      equilibrium<R>(r, vx, vy, eq);
-      double sxx = 0.0, sxy = 0.0, syy = 0.0;
+        for (int q = 0; q < 9; ++q) fp[q] = f[(size_t)q * nnode + p];
+        moments<R>(fp, r, vx, vy);
+        equilibrium<R>(r, vx, vy, eq);
+        double sxx = 0.0, sxy = 0.0, syy = 0.0;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const double fn = (double)fp[q] - (double)eq[q];
-        sxx -= double(CXd[q] * CXd[q]) * fn;
-        sxy -= double(CXd[q] * CYd[q]) * fn;
-        syy -= double(CYd[q] * CYd[q]) * fn;
+        for (int q = 0; q < 9; ++q) {
+          const double fn = (double)fp[q] - (double)eq[q];
+          sxx -= double(CXd[q] * CXd[q]) * fn;
+          sxy -= double(CXd[q] * CYd[q]) * fn;
+          syy -= double(CYd[q] * CYd[q]) * fn;
+        }
+        const double pp = ((double)r - 1.0) / 3.0;
+        tx += -pp * w.nx + sxx * w.nx + sxy * w.ny;
+        ty += -pp * w.ny + sxy * w.nx + syy * w.ny;
       }
-      const double pp = ((double)r - 1.0) / 3.0;
-      tx += -pp * w.nx + sxx * w.nx + sxy * w.ny;
-      ty += -pp * w.ny + sxy * w.nx + syy * w.ny;
+      Fx += 0.5 * w.len * tx;
+      Fy += 0.5 * w.len * ty;
     }
-    Fx += 0.5 * w.len * tx;
-    Fy += 0.5 * w.len * ty;
-  }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    Fx += __shfl_xor(Fx, o, 64);
-    Fy += __shfl_xor(Fy, o, 64);
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) {
-    red[0][wave] = Fx;
-    red[1][wave] = Fy;
+    for (int o = 32; o > 0; o >>= 1) {
+      Fx += __shfl_xor(Fx, o, 64);
+      Fy += __shfl_xor(Fy, o, 64);
+    }
+    if (lane == 0) {
+      red[0][vw] = Fx;
+      red[1][vw] = Fy;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
     double sx = 0.0, sy = 0.0;
-    for (int i = 0; i < nw; ++i) {
+    for (int i = 0; i < kForceLanes / 64; ++i) {
       sx += red[0][i];
       sy += red[1][i];
     }
@@ -832,6 +839,68 @@ __global__ __launch_bounds__(256) void kb_force(const CaseView<T, R> *__restrict
   if (!batched_case(v, k)) return;
   const int cur = grid_cur(v, k), L = (v.n_sub + kSubstepBlock - 1) / kSubstepBlock;
   force_block<R>(v.grid[cur ^ (L & 1)], v.wall, v.n_wall_edges, v.nnode, v.dk, v.hist, v.flag);
+}
+
+// ---- persistent case-batched steps -------------------------------------------
+// One cooperative launch advances the running cases of a batch by `steps`
+// steps: every workgroup walks the phases of a step in their order (lattice
+// interpolation nodes, stream-collide, donors, the sub-step blocks, refill,
+// force), taking every gridDim-th work item of a phase, and the whole grid
+// meets at a barrier after each phase, where the other path ends a launch.
+// The work items and their block functions are those of the kb_* kernels,
+// built for workgroups of the sub-step variant's width.
+template <class T, class R, int V>
+__device__ __forceinline__ void batch_item(const CaseView<T, R> *__restrict__ views, int4 it, int which, int m0) {
+  using SV = SubstepVariant<V>;
+  const CaseView<T, R> &v = views[it.x];
+  int64_t k;
+  if (!batched_case(v, k)) return;
+  const int cur = grid_cur(v, k), L = (v.n_sub + kSubstepBlock - 1) / kSubstepBlock;
+  switch (which) {
+    case (int)BatchKernel::LatticeFromGrid:
+      lattice_from_grid_block<T, R>(v, v.lat[k & 1], v.grid[cur], k, it.y, it.z);
+      break;
+    case (int)BatchKernel::StreamCollide:
+      stream_collide_block<T, R, 1>(v, v.lat[k & 1], v.lat[(k + 1) & 1], v.dk, it.y, it.z);
+      break;
+    case (int)BatchKernel::InterfaceDonors:
+      interface_donors_block<T, R>(v, v.lat[k & 1], k, it.y);
+      break;
+    case (int)BatchKernel::GridSubsteps: {
+      const int i = m0 / kSubstepBlock;
+      const int tiles_x = (v.nux + SV::G::TX - 1) / SV::G::TX;
+      grid_substeps_block<R, typename SV::G, kSubstepBlock, SV::NT>(
+          v.grid[cur ^ (i & 1)], v.grid[cur ^ ((i + 1) & 1)], v.star_f, v.star_n, v.cls, v.tab, v.nux, v.nuy,
+          tiles_x, it.y, v.dt_u, v.dt_over_tau_u, v.uw, k, v.n_sub, m0, min(kSubstepBlock, v.n_sub - m0), nullptr,
+          nullptr, nullptr, 0);
+      break;
+    }
+    case (int)BatchKernel::Refill:
+      refill_block<T, R>(v, v.lat[k & 1], v.grid[cur ^ (L & 1)], v.grid[cur ^ ((L + 1) & 1)], k, it.y);
+      break;
+    default:  // Force
+      force_block<R>(v.grid[cur ^ (L & 1)], v.wall, v.n_wall_edges, v.nnode, v.dk, v.hist, v.flag);
+      break;
+  }
+}
+
+template <class T, class R, int V>
+__global__ __launch_bounds__(SubstepVariant<V>::NT) void kb_persistent(const CaseView<T, R> *__restrict__ views,
+                                                                       const int4 *__restrict__ items,
+                                                                       const BatchPhase *__restrict__ prog,
+                                                                       int nphase, int steps) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int s = 0; s < steps; ++s)
+    for (int p = 0; p < nphase; ++p) {
+      const BatchPhase ph = prog[p];
+      for (int i = blockIdx.x; i < ph.n; i += gridDim.x) {
+        batch_item<T, R, V>(views, items[ph.first + i], ph.which, ph.m0);
+        __syncthreads();  // the next item reuses the LDS
+      }
+      __threadfence();  // this phase's writes, then every workgroup's, before the next phase reads them
+      grid.sync();
+      __threadfence();
+    }
 }
 
 template <class T, class R>
@@ -1204,6 +1273,45 @@ void Kernels<T, R>::batched(BatchKernel which, const CaseView<T, R> *views, cons
     case BatchKernel::Force:
       hipLaunchKernelGGL((kb_force<T, R>), g, dim3(256), 0, s, views, items);
       break;
+  }
+}
+
+template <class T, class R>
+hipError_t Kernels<T, R>::batched_persistent(const CaseView<T, R> *views, const int4 *items, const BatchPhase *prog,
+                                             int nphase, int steps, int variant, int max_groups, hipStream_t s) {
+  const void *fn = nullptr;
+  int nt = 0, lds = 0;
+  switch (variant) {
+#define HLBM_P(V)                                                                        \
+  case V:                                                                                \
+    fn = reinterpret_cast<const void *>(&kb_persistent<T, R, V>);                        \
+    nt = SubstepVariant<V>::NT;                                                          \
+    lds = (int)substeps_lds_bytes<R, typename SubstepVariant<V>::G>();                   \
+    break;
+    HLBM_P(4) HLBM_P(5) HLBM_P(6) HLBM_P(7)
+#undef HLBM_P
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  int dev = 0, per_cu = 0, cus = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, lds);
+  if (e != hipSuccess) return e;
+  // every workgroup must be resident at once for the grid barrier
+  const int groups = std::max(1, std::min(max_groups, per_cu * cus));
+  void *args[] = {(void *)&views, (void *)&items, (void *)&prog, (void *)&nphase, (void *)&steps};
+  return hipLaunchCooperativeKernel(fn, dim3(groups), dim3(nt), args, lds, s);
+}
+
+template <class T, class R>
+int Kernels<T, R>::persistent_threads(int variant) {
+  switch (variant) {
+    case 4: return SubstepVariant<4>::NT;
+    case 5: return SubstepVariant<5>::NT;
+    case 6: return SubstepVariant<6>::NT;
+    case 7: return SubstepVariant<7>::NT;
+    default: return 0;
   }
 }
 

@@ -62,7 +62,8 @@ class Info(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("steps_per_graph", C.c_int32), ("lattice_threads", C.c_int32),
                 ("lattice_rows", C.c_int32), ("substep_variant", C.c_int32), ("order", C.c_int32),
-                ("tail_variant", C.c_int32), ("ms_per_step", C.c_double)]
+                ("tail_variant", C.c_int32), ("persistent", C.c_int32), ("persistent_groups", C.c_int32),
+                ("ms_per_step", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -95,6 +95,15 @@ def test_batch_fp64_members_match_the_oracle(oracle):
     dict(steps_per_graph=1, lattice_threads=64, lattice_rows=4, substep_variant=2, order=1),
     dict(steps_per_graph=8, lattice_threads=192, lattice_rows=2, substep_variant=3, order=0),
     dict(steps_per_graph=4, lattice_threads=128, lattice_rows=2, substep_variant=6, order=1, tail_variant=3),
+    # one cooperative launch per run, every phase of a step behind a grid barrier
+    dict(steps_per_graph=4, lattice_threads=128, lattice_rows=2, substep_variant=5, order=0, persistent=1),
+    dict(steps_per_graph=8, lattice_threads=128, lattice_rows=1, substep_variant=4, order=1, persistent=1,
+         persistent_groups=37),
+    dict(steps_per_graph=8, lattice_threads=128, lattice_rows=1, substep_variant=7, order=0, persistent=1,
+         persistent_groups=1),
+    dict(steps_per_graph=4, lattice_threads=256, lattice_rows=4, substep_variant=1, order=1, tail_variant=6,
+         persistent=2),
+    dict(steps_per_graph=4, lattice_threads=256, lattice_rows=4, substep_variant=2, order=1, persistent=1),
 ])
 def test_schedules_do_not_change_results(schedule):
     _say("schedule", schedule)
@@ -185,6 +194,44 @@ def test_unstable_case_stops_alone():
     for i in (0, 2, 3, 4):
         assert batch[i].info().status == hlbm.STATUS_DONE
         _same(batch[i], _solo(cfgs[i], hlbm.FP64))
+
+
+@pytest.mark.parametrize("storage", [hlbm.FP64, hlbm.FP16_DEV])
+def test_persistent_launch_matches_single_cases_bitwise(storage):
+    _say("persistent batch vs single, storage", storage)
+    cfgs = _cases()
+    batch = hlbm.Batch(cfgs, storage=storage)
+    got = batch.tune(schedule=dict(steps_per_graph=8, lattice_threads=128, lattice_rows=2, substep_variant=6,
+                                   order=0, persistent=1))
+    assert got["persistent"] == 1
+    batch.step(max(c["max_steps"] for c in cfgs))
+    for i, c in enumerate(cfgs):
+        assert batch[i].info().status == hlbm.STATUS_DONE
+        _same(batch[i], _solo(c, storage))
+
+
+def test_persistent_unstable_case_stops_alone():
+    _say("unstable member, persistent launch")
+    cfgs = _cases()
+    batch = hlbm.Batch(cfgs, storage=hlbm.FP64)
+    batch.tune(schedule=dict(steps_per_graph=8, lattice_threads=128, lattice_rows=2, substep_variant=5, order=0,
+                             persistent=1))
+    g = batch[1].grid()
+    g[:] = np.nan
+    batch[1].set_grid(g)
+    batch.step(100)
+    assert batch[1].info().status == hlbm.STATUS_UNSTABLE
+    for i in (0, 2, 3, 4):
+        assert batch[i].info().status == hlbm.STATUS_DONE
+        _same(batch[i], _solo(cfgs[i], hlbm.FP64))
+
+
+def test_invalid_persistent_schedule_is_rejected():
+    batch = hlbm.Batch(_cases()[:2])
+    for bad in (dict(persistent=3), dict(persistent=-1), dict(persistent=1, persistent_groups=-2)):
+        with pytest.raises(hlbm.HlbmError) as e:
+            batch.tune(schedule=bad)
+        assert e.value.code == hlbm.E_ARG
 
 
 def test_batch_has_no_adjoint():
