@@ -255,6 +255,8 @@ class Case final : public CaseBase {
           t.Gx[s] = (R)g.Gx[s];
           t.Gy[s] = (R)g.Gy[s];
         }
+        auto zero = [&](int s) { return t.C[s] == R(0) && t.Gx[s] == R(0) && t.Gy[s] == R(0); };
+        t.zero_diag = (zero(2) && zero(6) ? kZeroDiag26 : 0) | (zero(0) && zero(8) ? kZeroDiag08 : 0);
       }
       HIPCHK(upload(&tab_, tab.data(), tab.size() * sizeof(GridClass<R>)));
       HIPCHK(upload(&cls_, grid_.cls.data(), grid_.cls.size() * sizeof(int)));

@@ -43,8 +43,13 @@ struct GridClass {
   R Gy[NSLOT];      // y weights of the streaming matrix
   R C[NSLOT];       // collision matrix C_ik
   int type;         // NodeType
-  int pad;
+  int zero_diag;    // bit 0: slots 2 and 6 (the (+1,-1) and (-1,+1)
+                    // neighbours) carry zero weights; bit 1: slots 0 and 8
 };
+
+// slots a split-quad node lacks: the two diagonal neighbours across the
+// diagonals its cells are not split along
+constexpr int kZeroDiag26 = 1, kZeroDiag08 = 2;
 
 struct WallEdge {
   int a, b;         // node indices

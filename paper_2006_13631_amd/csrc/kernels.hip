@@ -8,6 +8,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "device_common.h"
@@ -406,7 +407,7 @@ __device__ __forceinline__ void grid_substeps_block(
       for (int q = 0; q < 9; ++q) v[u][q] = in ? f[q * N + p] : R(0);
       if (idx < RN) {
         const int c = in ? cls[p] : -1;
-        scode[idx] = c >= 0 ? 4 * c + tab[c].type : -1;
+        scode[idx] = c >= 0 ? 16 * c + 4 * tab[c].zero_diag + tab[c].type : -1;
       }
       if (touches_ring && in) {
         const int rs = ring_slot<G>(gi, gj, idx % RX, idx / RX, nux, nuy);
@@ -455,13 +456,17 @@ __device__ __forceinline__ void grid_substeps_block(
   // sum_s C_s (rho u u)_s. On the outer ring an interpolation node reads
   // structured-derived values instead (Eq.(postcollision2_u)). Absent
   // neighbours have zero weights.
-  auto update_node = [&](int idx, int code, const GridClass<R> &cl, int cur, R o9[9]) {
+  // Slots outside the mask M are known to carry zero weights and are skipped
+  // (the same sums: a zero-weight term adds an exact zero).
+  auto update_node = [&](auto mask, int idx, int code, const GridClass<R> &cl, int cur, R o9[9]) {
+    constexpr int M = decltype(mask)::value;
     const int rx = idx % RX, ry = idx / RX;
     const int typ = code & 3;
     const int gi = x0 + rx, gj = y0 + ry;
     int row[NSLOT];
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
+      if (!((M >> s) & 1)) continue;
       const int di = s % 3 - 1, dj = s / 3 - 1;
       row[s] = cur + (idx + dj * RX + di) * NS;
       if (typ == NODE_INTERFACE) {
@@ -478,6 +483,7 @@ __device__ __forceinline__ void grid_substeps_block(
       R a = R(0), ax = R(0), ay = R(0);
 #pragma unroll
       for (int s = 0; s < NSLOT; ++s) {
+        if (!((M >> s) & 1)) continue;
         const R fq = sl[row[s] + q];
         a = fmad(cl.C[s], fq, a);
         if (CXd[q] != 0) ax = fmad(cl.Gx[s], fq, ax);
@@ -491,6 +497,7 @@ __device__ __forceinline__ void grid_substeps_block(
     R pxx = R(0), pxy = R(0), pyy = R(0);
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
+      if (!((M >> s) & 1)) continue;
       const R c = cl.C[s];
       pxx = fmad(c, sl[row[s] + 9], pxx);
       pxy = fmad(c, sl[row[s] + 10], pxy);
@@ -521,8 +528,22 @@ __device__ __forceinline__ void grid_substeps_block(
 #pragma unroll
       for (int q = 0; q < 9; ++q) out[u][q] = R(0);
       if (__ballot(code >= 0) == 0) continue;  // nothing to update in this wave
+      // a wave whose nodes all lack the same two diagonal neighbours (the
+      // interior of either half of a split-quad grid) skips those slots;
+      // with one node per lane only, to bound the code size
+      int zd = 0;
+      if constexpr (PER == 1) {
+        const int z = code >= 0 ? (code >> 2) & 3 : kZeroDiag26 | kZeroDiag08;
+        zd = __ballot(!(z & kZeroDiag26)) == 0 ? kZeroDiag26 : __ballot(!(z & kZeroDiag08)) == 0 ? kZeroDiag08 : 0;
+      }
       if (code < 0) continue;
-      update_node(idx, code, tab[code >> 2], cur, out[u]);
+      const GridClass<R> &cl = tab[code >> 4];
+      if (zd == kZeroDiag26)
+        update_node(std::integral_constant<int, 0x1FF & ~(1 << 2 | 1 << 6)>{}, idx, code, cl, cur, out[u]);
+      else if (zd == kZeroDiag08)
+        update_node(std::integral_constant<int, 0x1FF & ~(1 << 0 | 1 << 8)>{}, idx, code, cl, cur, out[u]);
+      else
+        update_node(std::integral_constant<int, 0x1FF>{}, idx, code, cl, cur, out[u]);
       if ((code & 3) == NODE_WALL) {
         // wall nodes: impose the lamina velocity, keep rho and f^neq
         const int rx = idx % RX, ry = idx / RX;
