@@ -917,18 +917,29 @@ static void free_sim(or_sim *s) {
 
 void or_destroy(or_sim *s) { free_sim(s); }
 
-/* X, Y: columns and rows of a graded grid (or_create_graded), or NULL */
-static int create_sim(const or_config *c, const double *X, const double *Y, or_sim **out) {
-  if (!c || !out) return OR_E_ARG;
-  *out = NULL;
-  if (c->nx < 3 || c->ny < 3 || !(c->tau > 0.5) || c->max_steps < 0) return OR_E_ARG;
-  if (c->bc != OR_BC_PERIODIC_X_WALLS_Y && c->bc != OR_BC_PERIODIC && c->bc != OR_BC_PAPER &&
-      c->bc != OR_BC_RING)
+/* X, Y: columns and rows of a graded grid (or_create_graded), or NULL;
+ * M: a finished mesh of any triangulation (or_create_mesh), or NULL; the
+ * case owns it from here on */
+static int create_sim(const or_config *c, const double *X, const double *Y, or_mesh *M, or_sim **out) {
+  if (!c || !out) {
+    or_mesh_free(M);
     return OR_E_ARG;
-  const int has_mesh = (c->nux > 0 || c->nuy > 0);
+  }
+  *out = NULL;
+  if (c->nx < 3 || c->ny < 3 || !(c->tau > 0.5) || c->max_steps < 0 ||
+      (c->bc != OR_BC_PERIODIC_X_WALLS_Y && c->bc != OR_BC_PERIODIC && c->bc != OR_BC_PAPER &&
+       c->bc != OR_BC_RING)) {
+    or_mesh_free(M);
+    return OR_E_ARG;
+  }
+  const int has_mesh = (c->nux > 0 || c->nuy > 0) || M;
   const int body = has_mesh && c->b > 0.0 && !(c->flags & OR_FLAG_NO_BODY);
   or_sim *s = xcalloc(1, sizeof(or_sim));
-  if (!s) return OR_E_NOMEM;
+  if (!s) {
+    or_mesh_free(M);
+    return OR_E_NOMEM;
+  }
+  s->m = M;
   s->plant = c->flags & (OR_FLAG_PLANT_S_FACTOR | OR_FLAG_PLANT_NO_KNEQ | OR_FLAG_PLANT_SWAP_BILIN_Y |
                          OR_FLAG_PLANT_SWAP_BILIN_X | OR_FLAG_PLANT_BARY);
   s->nx = c->nx;
@@ -987,12 +998,27 @@ static int create_sim(const or_config *c, const double *X, const double *Y, or_s
     if (X)
       for (int j = 0; j < c->nuy; ++j)
         if (Y[j] != -Y[c->nuy - 1 - j]) { free_sim(s); return OR_E_ARG; } /* rows symmetric about the lamina */
-    const double Tg = X ? Y[c->nuy / 2] - Y[c->nuy / 2 - 1] : s->h; /* thickness of the lamina slot */
+    /* thickness of the lamina slot (a given triangulation: as configured) */
+    const double Tg = M ? c->thickness : X ? Y[c->nuy / 2] - Y[c->nuy / 2 - 1] : s->h;
     if (body && fabs(c->thickness - Tg) > 1e-12 * Tg) { free_sim(s); return OR_E_ARG; }
     if (c->n_sub < 0) { free_sim(s); return OR_E_ARG; }
     /* explicit stability of the grid scheme, Delta t_u < 2 tau_u */
     if (!(s->dt_u < 2.0 * RE(s->tau_u))) { free_sim(s); return OR_E_ARG; }
-    if (X) {
+    if (M) {
+      /* the grid's outer boundary is the bounding box of its nodes */
+      s->ex0 = s->ey0 = 1e300;
+      s->ex1 = s->ey1 = -1e300;
+      for (int p = 0; p < M->nnode; ++p) {
+        s->ex0 = fmin(s->ex0, M->x[p]);
+        s->ex1 = fmax(s->ex1, M->x[p]);
+        s->ey0 = fmin(s->ey0, M->y[p]);
+        s->ey1 = fmax(s->ey1, M->y[p]);
+      }
+      if (!(s->ey1 > 0.0 && s->ey0 < 0.0 && fabs(s->ey0 + s->ey1) <= 1e-12 * s->ey1)) {
+        free_sim(s); /* rows symmetric about the lamina, as the other grids */
+        return OR_E_ARG;
+      }
+    } else if (X) {
       s->m = or_mesh_lamina_coords(c->nux, c->nuy, X, Y, s->body_b);
       s->ex0 = X[0];
       s->ex1 = X[c->nux - 1];
@@ -1042,7 +1068,52 @@ static int create_sim(const or_config *c, const double *X, const double *Y, or_s
   return OR_OK;
 }
 
-int or_create(const or_config *c, or_sim **out) { return create_sim(c, NULL, NULL, out); }
+int or_create(const or_config *c, or_sim **out) { return create_sim(c, NULL, NULL, NULL, out); }
+
+/* A case on a given triangulation (see the header): the mesh is copied,
+ * its matrices and buckets built by the same routines as the lamina grid's,
+ * the lamina geometry (b, thickness) taken from the configuration. */
+int or_create_mesh(const or_config *c, int32_t nnode, const double *xy, const int32_t *type, int32_t ntri,
+                   const int32_t *tri, or_sim **out) {
+  if (!c || !out || !xy || !type || !tri || nnode < 3 || ntri < 1) return OR_E_ARG;
+  *out = NULL;
+  or_mesh *m = mesh_alloc(nnode, ntri);
+  if (!m) return OR_E_NOMEM;
+  int nwall = 0, nface = 0;
+  for (int p = 0; p < nnode; ++p) {
+    if (type[p] != OR_NODE_INTERIOR && type[p] != OR_NODE_INTERFACE && type[p] != OR_NODE_WALL) {
+      or_mesh_free(m);
+      return OR_E_ARG;
+    }
+    m->x[p] = xy[2 * p];
+    m->y[p] = xy[2 * p + 1];
+    m->type[p] = type[p];
+    nwall += type[p] == OR_NODE_WALL;
+    nface += type[p] == OR_NODE_INTERFACE;
+  }
+  for (int t = 0; t < ntri; ++t)
+    for (int a = 0; a < 3; ++a) {
+      const int id = tri[3 * t + a];
+      if (id < 0 || id >= nnode) {
+        or_mesh_free(m);
+        return OR_E_ARG;
+      }
+      m->tri[3 * t + a] = id;
+      m->txy[6 * t + 2 * a] = m->x[id];
+      m->txy[6 * t + 2 * a + 1] = m->y[id];
+    }
+  m->ntri = ntri;
+  const int body = c->b > 0.0 && !(c->flags & OR_FLAG_NO_BODY);
+  if (nface == 0 || (body && nwall == 0) || (!body && nwall > 0)) {
+    or_mesh_free(m);
+    return OR_E_ARG;
+  }
+  m->b = body ? c->b : 0.0;
+  m->T = body ? c->thickness : 0.0;
+  m = mesh_finish(m); /* frees the mesh on failure (a triangle not counter-clockwise, ...) */
+  if (!m) return OR_E_ARG;
+  return create_sim(c, NULL, NULL, m, out);
+}
 
 /* A static grid band on a tangentially oscillating wall (see the header):
  * the lattice of create_sim without a lamina, then the band grid, its
@@ -1059,7 +1130,7 @@ int or_create_wallband(const or_config *c, int32_t nband, double x_off, double y
   lc.nuy = 0;
   lc.b = 0.0;
   or_sim *s = NULL;
-  int rc = create_sim(&lc, NULL, NULL, &s);
+  int rc = create_sim(&lc, NULL, NULL, NULL, &s);
   if (rc != OR_OK) return rc;
   if (!(s->dt_u < 2.0 * RE(s->tau_u))) { free_sim(s); return OR_E_ARG; }
   s->m = mesh_strip(c->nx, nband, 1.0, OR_NODE_INTERFACE);
@@ -1110,7 +1181,7 @@ int or_set_threads(int32_t n) {
  * thickness Y[nuy/2] - Y[nuy/2-1] must equal cfg->thickness; h_u unused). */
 int or_create_graded(const or_config *c, const double *X, const double *Y, or_sim **out) {
   if (!X || !Y) return OR_E_ARG;
-  return create_sim(c, X, Y, out);
+  return create_sim(c, X, Y, NULL, out);
 }
 
 /* lattice populations arriving at node (x,y) at t_{k+1}: pulled from the

@@ -144,6 +144,15 @@ int or_set_threads(int32_t n);
 /* a case with a graded grid: columns at local x = X[nux], rows at y =
  * Y[nuy] (rows symmetric about the lamina, thickness Y[nuy/2] - Y[nuy/2-1]) */
 int or_create_graded(const or_config *cfg, const double *X, const double *Y, or_sim **out);
+/* a case on any triangulation of the grid region (Sec. Hybrid lattice
+ * Boltzmann method: an unstructured mesh around the body): nodes at local
+ * coordinates xy [nnode][2] (lamina centre at the origin), types [nnode]
+ * (OR_NODE_*: the outer boundary's nodes are interface nodes, the lamina's
+ * wall nodes), counter-clockwise triangles tri [ntri][3]. The grid's outer
+ * boundary is the bounding box of the nodes (symmetric in y); the lamina is
+ * |x| < b/2, |y| < thickness/2 (cfg->nux, nuy, h_u unused). */
+int or_create_mesh(const or_config *cfg, int32_t nnode, const double *xy, const int32_t *type, int32_t ntri,
+                   const int32_t *tri, or_sim **out);
 void or_destroy(or_sim *s);
 int or_step(or_sim *s, int64_t nsteps);
 int or_info_get(const or_sim *s, or_info *out);

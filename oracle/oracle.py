@@ -125,6 +125,7 @@ def lib():
         L.or_set_threads.restype = C.c_int32
         L.or_set_motion.argtypes = [vp] + [C.c_double] * 6
         L.or_create_graded.argtypes = [C.POINTER(Config), _D, _D, C.POINTER(vp)]
+        L.or_create_mesh.argtypes = [C.POINTER(Config), C.c_int32, _D, _I, C.c_int32, _I, C.POINTER(vp)]
         L.or_mesh_lamina_coords.argtypes = [C.c_int32, C.c_int32, _D, _D, C.c_double]
         L.or_mesh_lamina_coords.restype = vp
         L.or_motion_history.argtypes = [vp, _D, C.c_int64]
@@ -294,11 +295,18 @@ class Sim:
 
     def __init__(self, nx, ny, nux=0, nuy=0, h_u=1.0, b=0.0, thickness=1.0, tau=0.8, kc=0.0,
                  beta=0.0, n_sub=0, bc=BC_PERIODIC_X_WALLS_Y, flags=0, max_steps=0, x_nodes=None,
-                 y_nodes=None):
+                 y_nodes=None, mesh=None):
         self.cfg = Config(nx, ny, nux, nuy, h_u, b, thickness, tau, kc, beta, n_sub, bc, flags,
                           max_steps)
         h = C.c_void_p()
-        if x_nodes is not None or y_nodes is not None:  # graded grid
+        if mesh is not None:  # any triangulation: (xy [n, 2], node types [n], triangles [m, 3])
+            xy = np.ascontiguousarray(mesh[0], dtype=np.float64)
+            ty = np.ascontiguousarray(mesh[1], dtype=np.int32)
+            tri = np.ascontiguousarray(mesh[2], dtype=np.int32)
+            if xy.ndim != 2 or xy.shape[1] != 2 or ty.shape != (len(xy),) or tri.ndim != 2 or tri.shape[1] != 3:
+                raise ValueError("mesh needs xy [n, 2], types [n] and triangles [m, 3]")
+            rc = lib().or_create_mesh(C.byref(self.cfg), len(xy), xy, ty, len(tri), tri, C.byref(h))
+        elif x_nodes is not None or y_nodes is not None:  # graded grid
             gx = np.ascontiguousarray(x_nodes, dtype=np.float64)
             gy = np.ascontiguousarray(y_nodes, dtype=np.float64)
             if gx.shape != (nux,) or gy.shape != (nuy,):
@@ -329,7 +337,9 @@ class Sim:
         return i
 
     def mesh(self) -> Mesh:
-        return Mesh(lib().or_sim_mesh(self.ptr), owned=False)
+        m = Mesh(lib().or_sim_mesh(self.ptr), owned=False)
+        m._owner = self  # the case owns the mesh: keep it alive with the view
+        return m
 
     def lattice(self):
         out = np.zeros((9, self.ny, self.nx))

@@ -120,15 +120,16 @@ def test_barycentric_reproduces_linear_fields(oracle):
     assert _grid_error(oracle, oracle.PLANT_BARY) > 1e-6
 
 
-def _couette(oracle, gamma, tau, flags=0, steps=70):
+def _couette(oracle, gamma, tau, flags=0, steps=70, mesh=None):
     """Plane Couette flow u = gamma (y - y_c) between walls moving with
     -+gamma ny/2, a grid without body oscillating through it; both grids
     start in the first-order state. Returns the final and the expected state
-    of the lattice (discretization nodes) and the grid."""
+    of the lattice (discretization nodes) and the grid. mesh: a triangulation
+    of the same 23 x 15 region in place of the 24 x 16 split-quad grid."""
     nx, ny = 64, 48
     cx, cy, w = oracle.d2q9()
-    s = oracle.Sim(nx, ny, 24, 16, 1.0, 8.0, 1.0, tau, 1.0, 20.0, 0,
-                   oracle.BC_PERIODIC_X_WALLS_Y, oracle.FLAG_NO_BODY | flags, steps)
+    s = oracle.Sim(nx, ny, 0 if mesh else 24, 0 if mesh else 16, 1.0, 8.0, 1.0, tau, 1.0, 20.0, 0,
+                   oracle.BC_PERIODIC_X_WALLS_Y, oracle.FLAG_NO_BODY | flags, steps, mesh=mesh)
     yc = 0.5 * (ny - 1)
     s.set_walls(-gamma * ny / 2, gamma * ny / 2)
     Y, _ = np.mgrid[0:ny, 0:nx].astype(float)
@@ -150,10 +151,10 @@ def _couette(oracle, gamma, tau, flags=0, steps=70):
     return s.lattice()[:, disc], lat[:, disc], s.grid(), grid_state(inf.y)
 
 
-def _couette_odd_error(oracle, gamma, tau, flags=0):
+def _couette_odd_error(oracle, gamma, tau, flags=0, mesh=None):
     """Error of the part odd in gamma, per unit gamma (lattice, grid)."""
-    p = _couette(oracle, gamma, tau, flags)
-    m = _couette(oracle, -gamma, tau, flags)
+    p = _couette(oracle, gamma, tau, flags, mesh=mesh)
+    m = _couette(oracle, -gamma, tau, flags, mesh=mesh)
     eL = np.max(np.abs((p[0] - m[0]) / 2 - (p[1] - m[1]) / 2)) / gamma
     eG = np.max(np.abs((p[2] - m[2]) / 2 - (p[3] - m[3]) / 2)) / gamma
     return max(eL, eG)
@@ -173,6 +174,23 @@ def test_couette_through_moving_interface(oracle, tau):
     for plant in (oracle.PLANT_S_FACTOR, oracle.PLANT_NO_KNEQ, oracle.PLANT_SWAP_BILIN_Y,
                   oracle.PLANT_BARY):
         assert _couette_odd_error(oracle, 1e-5, tau, plant) > 1e-2, plant
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_couette_through_moving_unstructured_interface(oracle, seed):
+    """The same first-order Couette state through an oscillating Delaunay
+    triangulation of the grid region (irregular node positions and
+    neighbour counts): every step locates lattice nodes and refilled grid
+    nodes in arbitrary triangles, and the stencils come from arbitrary
+    control volumes, yet the state is kept to third order in gamma."""
+    from paper_2006_13631_amd.meshes import lamina_triangulation
+    mesh = lamina_triangulation(23.0, 15.0, b=0.0, h_wall=1.0, h_far=1.0, seed=seed)
+    e5 = _couette_odd_error(oracle, 1e-5, 0.8, mesh=mesh)
+    e4 = _couette_odd_error(oracle, 1e-4, 0.8, mesh=mesh)
+    assert e5 < 1e-8, e5
+    assert 50 < e4 / e5 < 200, (e4, e5)
+    for plant in (oracle.PLANT_S_FACTOR, oracle.PLANT_NO_KNEQ, oracle.PLANT_BARY):
+        assert _couette_odd_error(oracle, 1e-5, 0.8, plant, mesh=mesh) > 1e-2, plant
 
 
 def _stokes_band(oracle, period, ny, nband, tau=0.6, flags=0, periods=5):
