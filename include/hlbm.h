@@ -253,6 +253,30 @@ int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny,
 int hlbm_create_graded(const hlbm_config *cfg, const double *x_nodes,
                        const double *y_nodes, hlbm_t **out);
 
+/* A single case on any triangulation of the grid region (Sec. Hybrid
+ * lattice Boltzmann method: the body-fitted grid is an unstructured
+ * triangular mesh around the body). Nodes at local coordinates
+ * xy[2 p], xy[2 p + 1] (lamina centre at the origin), node_type[p] one of
+ * 0 (discretization), 1 (interface: the grid's outer boundary), 2 (wall:
+ * the lamina's surface), triangles tri[3 t .. 3 t + 2] counter-clockwise;
+ * host arrays, read during the call only. The grid must cover its
+ * bounding box (symmetric about y = 0) minus the lamina |x| < b/2,
+ * |y| < cfg->thickness/2: every edge of one triangle joins two interface
+ * nodes or two wall nodes, interface nodes lie on the bounding box. Each
+ * node's stencil holds the vertices of the triangles around it, with the
+ * median-dual matrices of Eq.(ulbe) (Sec. Hybrid lattice Boltzmann
+ * method); points are located in unit buckets, the lowest-numbered
+ * triangle holding a point within 1e-12 in each barycentric coordinate
+ * taking it; the sub-steps run one per launch; a lattice node the grid
+ * does not cover stops the case (flag bit 4, HLBM_E_UNSTABLE). The
+ * fictitious rectangle is the bounding box inset by 2; nux, nuy and h_u
+ * are not used. Otherwise as hlbm_create with ncases = 1. ckpt_every must
+ * be 0 (no adjoint). Errors: HLBM_E_ARG (invalid mesh or configuration,
+ * hlbm_last_error(NULL) says which), HLBM_E_NOMEM, HLBM_E_HIP. */
+int hlbm_create_mesh(const hlbm_config *cfg, int32_t nnode, const double *xy,
+                     const int32_t *node_type, int32_t ntri, const int32_t *tri,
+                     hlbm_t **out);
+
 /* ---- two-way coupled motion ------------------------------------------- */
 /* The paper prescribes the lamina's motion (Sec. Problem statement: known a
  * priori). Instead, the lamina may be mounted on a spring and damper and

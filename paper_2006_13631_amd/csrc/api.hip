@@ -90,11 +90,12 @@ struct Derived {
 };
 
 // Derived quantities (Sec. Problem statement; viscosity matching of Sec. 3).
-Derived derive(const hlbm_config &c) {
+// mesh: the case has an unstructured grid (nux, nuy unused)
+Derived derive(const hlbm_config &c, bool mesh = false) {
   Derived d;
   d.nu = (c.tau - 0.5) / 3.0;
   d.tau_u = c.tau - 0.5;
-  const bool has_grid = c.nux > 0 || c.nuy > 0;
+  const bool has_grid = c.nux > 0 || c.nuy > 0 || mesh;
   if (has_grid && c.b > 0.0) {
     d.A = c.kc * c.b / (2.0 * M_PI);
     d.omega = 2.0 * M_PI * d.nu * c.beta / (c.b * c.b);
@@ -171,6 +172,15 @@ class CaseBase {
     }                                                                                 \
   } while (0)
 
+// an unstructured grid as given to hlbm_create_mesh
+struct MeshInput {
+  int nnode;
+  const double *xy;
+  const int *type;
+  int ntri;
+  const int *tri;
+};
+
 inline bool valid_lattice_shape(const hlbm_tuning &t) {
   return t.lattice_threads >= 64 && t.lattice_threads <= 256 && t.lattice_threads % 64 == 0 &&
          (t.lattice_rows == 1 || t.lattice_rows == 2 || t.lattice_rows == 4);
@@ -185,11 +195,13 @@ class Case final : public CaseBase {
   // advances its members with the case-batched kernels)
   // gx, gy (optional): local x of each grid column and y of each row of a
   // graded grid (hlbm_create_graded)
-  int init(const hlbm_config &c, bool two_step = true, const double *gx = nullptr, const double *gy = nullptr) {
+  // mesh (optional): an unstructured grid (hlbm_create_mesh)
+  int init(const hlbm_config &c, bool two_step = true, const double *gx = nullptr, const double *gy = nullptr,
+           const MeshInput *mesh = nullptr) {
     cfg_ = c;
-    d_ = derive(c);
+    d_ = derive(c, mesh != nullptr);
     h_ = c.h_u > 0.0 ? c.h_u : 1.0;
-    has_grid_ = c.nux > 0 || c.nuy > 0;
+    has_grid_ = c.nux > 0 || c.nuy > 0 || mesh;
     body_ = has_grid_ && c.b > 0.0 && !(c.flags & HLBM_FLAG_NO_BODY);
     nodes_ = (size_t)c.nx * c.ny;
     plane_ = lattice_plane(c.nx, c.ny);
@@ -208,9 +220,18 @@ class Case final : public CaseBase {
     }
     if (has_grid_) {
       std::string e;
-      if (!build_grid(c.nux, c.nuy, h_, c.b, body_, &grid_, &e, gx, gy)) {
+      const bool ok = mesh ? build_mesh(mesh->nnode, mesh->xy, mesh->type, mesh->ntri, mesh->tri, c.b, c.thickness,
+                                        body_, &grid_, &e)
+                           : build_grid(c.nux, c.nuy, h_, c.b, body_, &grid_, &e, gx, gy);
+      if (!ok) {
         err = e;
         return HLBM_E_ARG;
+      }
+      if (mesh) {
+        gex0_ = grid_.ex0;
+        gex1_ = grid_.ex1;
+        gey0_ = grid_.ey0;
+        gey1_ = grid_.ey1;
       }
     }
     HIPCHK((Kernels<T, R>::prepare()));
@@ -244,6 +265,22 @@ class Case final : public CaseBase {
       HIPCHK(alloc(&star_n_, 9 * (size_t)N * sizeof(R)));
       HIPCHK(hipMemset(star_f_, 0, 9 * (size_t)N * sizeof(R)));
       HIPCHK(hipMemset(star_n_, 0, 9 * (size_t)N * sizeof(R)));
+      if (grid_.mesh) {
+        auto conv = [](const std::vector<double> &a) { return std::vector<R>(a.begin(), a.end()); };
+        const std::vector<R> mC = conv(grid_.C), mGx = conv(grid_.Gx), mGy = conv(grid_.Gy);
+        HIPCHK(upload(&m_row_, grid_.row.data(), grid_.row.size() * sizeof(int)));
+        HIPCHK(upload(&m_col_, grid_.col.data(), grid_.col.size() * sizeof(int)));
+        HIPCHK(upload(&m_C_, mC.data(), mC.size() * sizeof(R)));
+        HIPCHK(upload(&m_Gx_, mGx.data(), mGx.size() * sizeof(R)));
+        HIPCHK(upload(&m_Gy_, mGy.data(), mGy.size() * sizeof(R)));
+        HIPCHK(upload(&m_x_, grid_.x.data(), grid_.x.size() * sizeof(double)));
+        HIPCHK(upload(&m_y_, grid_.y.data(), grid_.y.size() * sizeof(double)));
+        HIPCHK(upload(&m_type_, grid_.type.data(), grid_.type.size() * sizeof(int)));
+        HIPCHK(upload(&m_tri_, grid_.tri.data(), grid_.tri.size() * sizeof(int)));
+        HIPCHK(upload(&m_txy_, grid_.txy.data(), grid_.txy.size() * sizeof(double)));
+        HIPCHK(upload(&m_bstart_, grid_.bstart.data(), grid_.bstart.size() * sizeof(int)));
+        HIPCHK(upload(&m_blist_, grid_.blist.data(), std::max<size_t>(1, grid_.blist.size()) * sizeof(int)));
+      }
       std::vector<GridClass<R>> tab(grid_.classes.size());
       for (size_t i = 0; i < tab.size(); ++i) {
         const GridClass<double> &g = grid_.classes[i];
@@ -258,8 +295,10 @@ class Case final : public CaseBase {
         auto zero = [&](int s) { return t.C[s] == R(0) && t.Gx[s] == R(0) && t.Gy[s] == R(0); };
         t.zero_diag = (zero(2) && zero(6) ? kZeroDiag26 : 0) | (zero(0) && zero(8) ? kZeroDiag08 : 0);
       }
-      HIPCHK(upload(&tab_, tab.data(), tab.size() * sizeof(GridClass<R>)));
-      HIPCHK(upload(&cls_, grid_.cls.data(), grid_.cls.size() * sizeof(int)));
+      if (!grid_.mesh) {
+        HIPCHK(upload(&tab_, tab.data(), tab.size() * sizeof(GridClass<R>)));
+        HIPCHK(upload(&cls_, grid_.cls.data(), grid_.cls.size() * sizeof(int)));
+      }
       HIPCHK(upload(&iface_, grid_.iface.data(), grid_.iface.size() * sizeof(int)));
       HIPCHK(upload(&wall_, grid_.wall.data(), grid_.wall.size() * sizeof(WallEdge)));
       if (!gx_.empty()) {
@@ -369,13 +408,22 @@ class Case final : public CaseBase {
     // level 3: the step's first sub-step launch, once per timing slot
     const bool time_sub = timing_ == 3 && sub_mark_ != tslot_;
     if (time_sub) sub_mark_ = tslot_;
-    for (int m = 0; m < d_.n; m += blk) {
-      const int cnt = std::min(blk, d_.n - m);
-      const bool ev = time_sub && m == 0;
-      Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_, nullptr, nullptr,
-                                   nullptr, 0, substep_variant_, ev ? tev_[tslot_][8] : nullptr,
-                                   ev ? tev_[tslot_][2] : nullptr);
-      cur = 1 - cur;
+    if (grid_.mesh) {  // one sub-step per launch
+      for (int m = 0; m < d_.n; ++m) {
+        const bool ev = time_sub && m == 0;
+        Kernels<T, R>::mesh_substep(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, s_grid_,
+                                    ev ? tev_[tslot_][8] : nullptr, ev ? tev_[tslot_][2] : nullptr);
+        cur = 1 - cur;
+      }
+    } else {
+      for (int m = 0; m < d_.n; m += blk) {
+        const int cnt = std::min(blk, d_.n - m);
+        const bool ev = time_sub && m == 0;
+        Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_, nullptr,
+                                     nullptr, nullptr, 0, substep_variant_, ev ? tev_[tslot_][8] : nullptr,
+                                     ev ? tev_[tslot_][2] : nullptr);
+        cur = 1 - cur;
+      }
     }
     if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][4], s_grid_));
     if (fsi_) {
@@ -534,6 +582,7 @@ class Case final : public CaseBase {
     HIPCHK(hipStreamSynchronize(s_main_));
     int flag = 0;
     HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag & 4) return fail(HLBM_E_UNSTABLE, "a lattice node to interpolate lies outside the grid");
     if (flag & 2) return fail(HLBM_E_UNSTABLE, "a density became non-positive or not a number");
     if (flag) return fail(HLBM_E_UNSTABLE, has_grid_ ? "non-finite force on the lamina" : "unstable");
     return HLBM_OK;
@@ -716,6 +765,24 @@ class Case final : public CaseBase {
 
   int stencil(int kmax, int32_t *nbr, double *S, double *C) override {
     if (!has_grid_) return fail(HLBM_E_STATE, "case has no grid");
+    static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    if (grid_.mesh) {  // the stored stencils, the node first
+      int need = 0;
+      for (int p = 0; p < grid_.nnode; ++p) need = std::max(need, grid_.row[p + 1] - grid_.row[p]);
+      if (kmax < need) return fail(HLBM_E_ARG, "kmax smaller than the largest stencil");
+      for (int p = 0; p < grid_.nnode; ++p) {
+        const int e0 = grid_.row[p], k = grid_.row[p + 1] - e0;
+        for (int u = 0; u < kmax; ++u) {
+          const bool in = u < k;
+          if (nbr) nbr[(size_t)p * kmax + u] = in ? grid_.col[e0 + u] : -1;
+          if (C) C[(size_t)p * kmax + u] = in ? grid_.C[e0 + u] : 0.0;
+          if (S)
+            for (int r = 0; r < 9; ++r)
+              S[((size_t)p * 9 + r) * kmax + u] = in ? cx[r] * grid_.Gx[e0 + u] + cy[r] * grid_.Gy[e0 + u] : 0.0;
+        }
+      }
+      return HLBM_OK;
+    }
     int need = 0;
     for (const auto &c : grid_.classes) {
       int k = 0;
@@ -736,7 +803,6 @@ class Case final : public CaseBase {
         const int q = p + (s % 3 - 1) + (s / 3 - 1) * cfg_.nux;
         if (nbr) nbr[(size_t)p * kmax + u] = in ? q : -1;
         if (C) C[(size_t)p * kmax + u] = in ? c.C[s] : 0.0;
-        static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
         if (S)
           for (int r = 0; r < 9; ++r)
             S[((size_t)p * 9 + r) * kmax + u] = in ? cx[r] * c.Gx[s] + cy[r] * c.Gy[s] : 0.0;
@@ -889,7 +955,12 @@ class Case final : public CaseBase {
           }
         }
     total += best_ms;
-    if (has_grid_) {
+    if (has_grid_ && grid_.mesh) {  // one sub-step kernel: timed, nothing to choose
+      total += timed(s_grid_, [&] {
+        for (int m = 0; m < d_.n; ++m)
+          Kernels<T, R>::mesh_substep(v, (const R *)gbuf_[gcur_], (R *)gbuf_[1 - gcur_], m, s_grid_);
+      });
+    } else if (has_grid_) {
       best_ms = 3e38f;
       int best = default_substep_variant<R>();
       for (int sv = 0; sv < kSubstepVariantsSingle; ++sv) {
@@ -1198,6 +1269,19 @@ class Case final : public CaseBase {
       v.cls = cls_;
       v.tab = tab_;
       v.iface = iface_;
+      if (grid_.mesh) {
+        v.mesh = 1;
+        v.nux = v.nuy = 0;
+        v.m_row = m_row_;
+        v.m_col = m_col_;
+        v.m_C = m_C_;
+        v.m_Gx = m_Gx_;
+        v.m_Gy = m_Gy_;
+        v.m_x = m_x_;
+        v.m_y = m_y_;
+        v.m_type = m_type_;
+        v.mg = MeshGeom{m_tri_, m_txy_, m_bstart_, m_blist_, grid_.bx0, grid_.by0, grid_.bnx, grid_.bny};
+      }
       v.wall = wall_;
       v.star_f = star_f_;
       v.star_n = star_n_;
@@ -1645,6 +1729,11 @@ class Case final : public CaseBase {
   R *star_f_ = nullptr, *star_n_ = nullptr;
   GridClass<R> *tab_ = nullptr;
   int *cls_ = nullptr, *iface_ = nullptr;
+  // unstructured grid (device copies of the HostGrid mesh fields)
+  int *m_row_ = nullptr, *m_col_ = nullptr, *m_type_ = nullptr, *m_tri_ = nullptr;
+  int *m_bstart_ = nullptr, *m_blist_ = nullptr;
+  R *m_C_ = nullptr, *m_Gx_ = nullptr, *m_Gy_ = nullptr;
+  double *m_x_ = nullptr, *m_y_ = nullptr, *m_txy_ = nullptr;
   WallEdge *wall_ = nullptr;
   StepParams *params_ = nullptr;
   R *uw_ = nullptr;
@@ -2750,6 +2839,72 @@ int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny, double 
   *nx = a;
   *ny = b;
   *tau = t;
+  return HLBM_OK;
+}
+
+int hlbm_create_mesh(const hlbm_config *cfg, int32_t nnode, const double *xy, const int32_t *node_type, int32_t ntri,
+                     const int32_t *tri, hlbm_t **out) {
+  using namespace mghlbm;
+  if (out) *out = nullptr;
+  if (!cfg || !xy || !node_type || !tri || !out) { g_create_error = "null argument"; return HLBM_E_ARG; }
+  if (nnode < 3 || ntri < 1) { g_create_error = "mesh needs at least 3 nodes and 1 triangle"; return HLBM_E_ARG; }
+  if (cfg->ckpt_every != 0) { g_create_error = "a mesh case takes no checkpoints (no adjoint)"; return HLBM_E_ARG; }
+  // the lattice-level checks, then the grid's geometry from its bounding box
+  hlbm_config lc = *cfg;
+  lc.nux = lc.nuy = 0;
+  std::string e;
+  int rc = validate(lc, &e);
+  if (rc != HLBM_OK) { g_create_error = e; return rc; }
+  double x0 = xy[0], x1 = xy[0], y1 = xy[1];
+  for (int p = 0; p < nnode; ++p) {
+    if (!std::isfinite(xy[2 * p]) || !std::isfinite(xy[2 * p + 1])) { g_create_error = "mesh coordinate not finite"; return HLBM_E_ARG; }
+    x0 = std::min(x0, xy[2 * p]);
+    x1 = std::max(x1, xy[2 * p]);
+    y1 = std::max(y1, xy[2 * p + 1]);
+  }
+  const Derived d = derive(*cfg, true);
+  const bool body = cfg->b > 0.0 && !(cfg->flags & HLBM_FLAG_NO_BODY);
+  if (!(1.0 / (double)d.n < 2.0 * d.tau_u)) { g_create_error = "grid sub-step violates Delta t_u < 2 tau_u"; return HLBM_E_ARG; }
+  if (d.xc + x0 < 1.0 || d.xc + x1 > (double)cfg->nx - 2.0) { g_create_error = "grid leaves the lattice in x"; return HLBM_E_ARG; }
+  if (cfg->bc != HLBM_BC_PERIODIC &&
+      (d.yc - y1 - std::fabs(d.A) < 1.0 || d.yc + y1 + std::fabs(d.A) > (double)cfg->ny - 2.0)) {
+    g_create_error = "grid motion leaves the lattice in y";
+    return HLBM_E_ARG;
+  }
+  if (body && (!(cfg->thickness > 0.0) || 0.5 * cfg->b + 1.0 > -x0 - kMargin - 1.0 ||
+               0.5 * cfg->b + 1.0 > x1 - kMargin - 1.0 || 0.5 * cfg->thickness + 1.0 > y1 - kMargin - 1.0)) {
+    g_create_error = "lamina does not fit inside the fictitious rectangle";
+    return HLBM_E_ARG;
+  }
+  if (!(std::fabs(d.A * d.omega) < 1.0)) { g_create_error = "lamina speed must stay below one lattice unit per step"; return HLBM_E_ARG; }
+  const MeshInput mesh{nnode, xy, node_type, ntri, tri};
+  std::unique_ptr<CaseBase> c;
+  try {
+    if (cfg->storage == HLBM_FP64) {
+      auto p = std::make_unique<Case<double, double>>();
+      rc = p->init(*cfg, true, nullptr, nullptr, &mesh);
+      c = std::move(p);
+    } else if (cfg->storage == HLBM_FP32) {
+      auto p = std::make_unique<Case<float, float>>();
+      rc = p->init(*cfg, true, nullptr, nullptr, &mesh);
+      c = std::move(p);
+    } else {
+      auto p = std::make_unique<Case<__half, float>>();
+      rc = p->init(*cfg, true, nullptr, nullptr, &mesh);
+      c = std::move(p);
+    }
+  } catch (const std::bad_alloc &) {
+    g_create_error = "host allocation failed";
+    return HLBM_E_NOMEM;
+  }
+  if (rc != HLBM_OK) {
+    g_create_error = c->err;
+    return rc;
+  }
+  hlbm_t *h = new (std::nothrow) hlbm_t;
+  if (!h) { g_create_error = "host allocation failed"; return HLBM_E_NOMEM; }
+  h->c = std::move(c);
+  *out = h;
   return HLBM_OK;
 }
 

@@ -261,6 +261,38 @@ __device__ __forceinline__ void cell_triangle(int ci, int cj, int nux, double a,
   }
 }
 
+// Point location on an unstructured grid: the lowest-numbered triangle that
+// holds (px, py) (local frame) with every barycentric coordinate >= -1e-12,
+// or -1. The bucket of the point lists, in increasing order, every triangle
+// that can hold it. Each coordinate is the signed area of the sub-triangle
+// opposite its vertex over the triangle's.
+
+__device__ __forceinline__ double edge_area(double ax, double ay, double bx, double by, double px, double py) {
+  return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+}
+
+__device__ inline int mesh_locate(const MeshGeom &m, double px, double py, int node[3], double lam[3]) {
+  const int bi = (int)floor((px - m.bx0) / kBucket), bj = (int)floor((py - m.by0) / kBucket);
+  if (bi < 0 || bj < 0 || bi >= m.bnx || bj >= m.bny) return -1;
+  const int b = bj * m.bnx + bi;
+  for (int s = m.bstart[b]; s < m.bstart[b + 1]; ++s) {
+    const int t = m.blist[s];
+    const double *q = m.txy + 6 * (size_t)t;
+    const double D = edge_area(q[0], q[1], q[2], q[3], q[4], q[5]);
+    const double l0 = edge_area(q[2], q[3], q[4], q[5], px, py) / D;
+    const double l1 = edge_area(q[4], q[5], q[0], q[1], px, py) / D;
+    const double l2 = edge_area(q[0], q[1], q[2], q[3], px, py) / D;
+    if (l0 >= -1e-12 && l1 >= -1e-12 && l2 >= -1e-12) {
+      lam[0] = l0;
+      lam[1] = l1;
+      lam[2] = l2;
+      for (int a = 0; a < 3; ++a) node[a] = m.tri[3 * (size_t)t + a];
+      return t;
+    }
+  }
+  return -1;
+}
+
 // Grid geometry needed to place nodes and classify refills.
 struct GridGeom {
   int nux, nuy;

@@ -69,6 +69,32 @@ struct HostGrid {
   std::vector<GridClass<double>> classes;
   std::vector<int> iface;                // interface (outer ring) node ids
   std::vector<WallEdge> wall;            // body polygon edges
+  // unstructured grid (build_mesh; no classes then)
+  bool mesh = false;
+  std::vector<double> x, y;              // node coordinates, local frame
+  std::vector<int> tri;                  // [ntri][3] counter-clockwise
+  std::vector<double> txy;               // [ntri][3][2] vertex coordinates
+  std::vector<int> row, col;             // stencil of node p: col[row[p] .. row[p+1]), the node first
+  std::vector<double> C, Gx, Gy;         // its weights, per entry
+  double ex0 = 0, ex1 = 0, ey0 = 0, ey1 = 0;  // bounding box of the nodes
+  // point location: unit buckets over the bounding box, each listing (in
+  // increasing order) the triangles whose box, grown by one bucket, meets it
+  double bx0 = 0, by0 = 0;
+  int bnx = 0, bny = 0;
+  std::vector<int> bstart, blist;
+};
+
+// bucket size of the unstructured grid's point location (lattice units)
+constexpr double kBucket = 1.0;
+
+// Device view of an unstructured grid's point-location data.
+struct MeshGeom {
+  const int *tri;      // [ntri][3]
+  const double *txy;   // [ntri][3][2]
+  const int *bstart;   // [bnx * bny + 1]
+  const int *blist;
+  double bx0, by0;
+  int bnx, bny;
 };
 
 // Builds the grid, its median-dual finite-volume matrices and stencil
@@ -76,5 +102,17 @@ struct HostGrid {
 // gx, gy (optional): local x of each column and y of each row of a graded grid.
 bool build_grid(int nux, int nuy, double h, double b, bool body, HostGrid *g, std::string *err,
                 const double *gx = nullptr, const double *gy = nullptr);
+
+// An unstructured grid: nodes at local xy [nnode][2] with types [nnode]
+// (NodeType), counter-clockwise triangles tri [ntri][3]; the lamina is
+// |x| < b/2, |y| < T/2 (body). Builds the per-node stencils of the same
+// median-dual matrices, the wall edges and the point-location buckets.
+// False with a message when the mesh is not a valid grid of the region:
+// indices or types out of range, a triangle without positive area, an
+// edge shared by more than two triangles, a boundary edge whose ends are
+// not both interface nodes or both wall nodes, interface nodes off the
+// bounding box, a bounding box not symmetric about y = 0.
+bool build_mesh(int nnode, const double *xy, const int *type, int ntri, const int *tri, double b, double T,
+                bool body, HostGrid *g, std::string *err);
 
 }  // namespace mghlbm

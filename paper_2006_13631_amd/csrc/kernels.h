@@ -55,6 +55,16 @@ struct CaseView {
   const GridClass<R> *tab;
   const int *iface;
   const WallEdge *wall;
+  // unstructured grid (mesh != 0; the split-quad fields above unused):
+  // stencil of node p at entries m_row[p] .. m_row[p+1]-1 (node ids m_col,
+  // weights m_C, m_Gx, m_Gy), node coordinates and types, triangles and
+  // the point-location buckets
+  int mesh;
+  const int *m_row, *m_col;
+  const R *m_C, *m_Gx, *m_Gy;
+  const double *m_x, *m_y;
+  const int *m_type;
+  MeshGeom mg;
   R *star_f;       // [9][nnode] structured-derived f* at interface nodes
   R *star_n;       // [9][nnode] structured-derived f^neq* at interface nodes
   R dt_u, dt_over_tau_u;
@@ -138,6 +148,10 @@ struct Kernels {
                               hipEvent_t stop = nullptr);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
   static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
+  // one sub-step m of an unstructured grid (Eq.(ulbe), Eq.(postcollision2_u)),
+  // one node per lane; optional events at the kernel's own start and end
+  static void mesh_substep(const CaseView<T, R> &v, const R *f, R *fout, int m, hipStream_t s,
+                           hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
   // sub-steps m0 .. m0+count-1 (count <= kSubstepBlock) in one launch; with
   // a tape, the grid after sub-step m (m0 < m < m0+count) is also stored at
   // tape + m * 9 * nnode, and the moments (rho, u_x, u_y) of every wall node

@@ -50,7 +50,7 @@ __device__ __forceinline__ bool static_skip(const CaseView<T, R> &v, int x, int 
 
 // a density that is not positive (or not a number) stops the case: bit 2 of
 // its flag (bit 1: a non-finite force)
-constexpr int kFlagForce = 1, kFlagDensity = 2;
+constexpr int kFlagForce = 1, kFlagDensity = 2, kFlagLocate = 4;  // bit 3: a lattice node off the grid
 template <class R>
 __device__ __forceinline__ void check_density(int *flag, R rho) {
   if (!(rho > R(0)) && flag) atomicOr(flag, kFlagDensity);
@@ -213,11 +213,20 @@ __device__ __forceinline__ void lattice_from_grid_block(const CaseView<T, R> &v,
   const int y = min(P.iy0, P.piy0) + by;
   if (x >= v.k2_x0 + v.k2_w || y > max(P.iy1, P.piy1)) return;
   if (!from_grid_target(P, x, y)) return;
-  const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body, v.gx, v.gy};
-  int ci, cj, tri, node[3];
-  double a, b, lam[3], dlam[3];
-  lattice_node_cell(gg, P.ybase, x, y, ci, cj, a, b, tri);
-  cell_triangle(ci, cj, v.nux, a, b, node, lam, dlam, tri);
+  int node[3];
+  double lam[3];
+  if (v.mesh) {
+    if (mesh_locate(v.mg, (double)x - v.xc, (double)y - P.ybase, node, lam) < 0) {
+      atomicOr(v.flag, kFlagLocate);  // the grid does not cover the node: the case stops
+      return;
+    }
+  } else {
+    const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body, v.gx, v.gy};
+    int ci, cj, tri;
+    double a, b, dlam[3];
+    lattice_node_cell(gg, P.ybase, x, y, ci, cj, a, b, tri);
+    cell_triangle(ci, cj, v.nux, a, b, node, lam, dlam, tri);
+  }
   R rho, ux, uy, fneq[9];
   grid_barycentric<R>(g, v.nnode, node, lam, rho, ux, uy, fneq);
   R e[9];
@@ -260,9 +269,15 @@ __device__ __forceinline__ void interface_donors_block(const CaseView<T, R> &v, 
   if (valid) {
     const StepParams &P = v.params[k];
     p = v.iface[t];
-    const int i = p % v.nux, j = p / v.nux;
-    const double X = v.gx ? v.xc + v.gx[i] : v.xc + (double)(i - v.nux / 2) * v.h;
-    const double Y = v.gy ? P.ybase + v.gy[j] : P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
+    double X, Y;
+    if (v.mesh) {
+      X = v.xc + v.m_x[p];
+      Y = P.ybase + v.m_y[p];
+    } else {
+      const int i = p % v.nux, j = p / v.nux;
+      X = v.gx ? v.xc + v.gx[i] : v.xc + (double)(i - v.nux / 2) * v.h;
+      Y = v.gy ? P.ybase + v.gy[j] : P.ybase + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
+    }
     donor_corner<T, R>(A, v.nx, v.ny, v.plane, v.bc, X, Y, d, acc);
   }
 #pragma unroll
@@ -670,6 +685,79 @@ __global__ __launch_bounds__(SubstepVariant<V>::NT) void kb_grid_substeps(const 
 }
 
 
+// ---- K3/K4 on an unstructured grid -------------------------------------------
+// One sub-step per launch, one node per lane. The node's stencil entries are
+// read from the grid buffer (an interface node reads the structured-derived
+// values for itself and its interface neighbours, Eq.(postcollision2_u)),
+// and the update is that of the split-quad kernel: streaming c_q.(G f_q),
+// and the collision sum of f^neq from the C-weighted sums of f and of
+// rho u u (f^eq being linear in rho, rho u and rho u u), then the lamina
+// velocity at wall nodes.
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_mesh_substep(CaseView<T, R> v, const R *__restrict__ f,
+                                                      R *__restrict__ fout, int m) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= v.nnode) return;
+  const int64_t k = *v.dk;
+  const size_t N = (size_t)v.nnode;
+  const int typ = v.m_type[p];
+  const bool iface = typ == NODE_INTERFACE;
+  R a[9], ax[9], ay[9], self[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) a[q] = ax[q] = ay[q] = self[q] = R(0);
+  R pxx = R(0), pxy = R(0), pyy = R(0);
+  const int e0 = v.m_row[p], e1 = v.m_row[p + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int nb = v.m_col[e];
+    const R *src = (iface && v.m_type[nb] == NODE_INTERFACE) ? v.star_f : f;
+    R fq[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fq[q] = src[q * N + nb];
+    if (e == e0)  // the node itself comes first
+#pragma unroll
+      for (int q = 0; q < 9; ++q) self[q] = fq[q];
+    const R c = v.m_C[e], gx = v.m_Gx[e], gy = v.m_Gy[e];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      a[q] = fmad(c, fq[q], a[q]);
+      if (CXd[q] != 0) ax[q] = fmad(gx, fq[q], ax[q]);
+      if (CYd[q] != 0) ay[q] = fmad(gy, fq[q], ay[q]);
+    }
+    R P[3];
+    quad_moments<R>(fq, P);
+    pxx = fmad(c, P[0], pxx);
+    pxy = fmad(c, P[1], pxy);
+    pyy = fmad(c, P[2], pyy);
+  }
+  const R dt = v.dt_u, dt_tau = v.dt_over_tau_u;
+  R srho = R(0), sjx = R(0), sjy = R(0), out[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    srho += a[q];
+    if (CXd[q] != 0) sjx += R(CXd[q]) * a[q];
+    if (CYd[q] != 0) sjy += R(CYd[q]) * a[q];
+    out[q] = fmad(-dt_tau, a[q], fmad(dt, R(CXd[q]) * ax[q] + R(CYd[q]) * ay[q], self[q]));
+  }
+  const R base = fmad(R(-1.5), pxx + pyy, srho);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const R cx = R(CXd[q]), cy = R(CYd[q]);
+    const R cu = cx * sjx + cy * sjy;
+    const R cc = (cx * cx) * pxx + (R(2) * cx * cy) * pxy + (cy * cy) * pyy;
+    out[q] = fmad(dt_tau * wgt<R>(q), fmad(R(4.5), cc, fmad(R(3), cu, base)), out[q]);
+  }
+  if (typ == NODE_WALL) {  // impose the lamina velocity, keep rho and f^neq
+    R e[9], ew[9], r, vx, vy;
+    moments<R>(out, r, vx, vy);
+    equilibrium<R>(r, vx, vy, e);
+    equilibrium<R>(r, R(0), v.uw[k * v.n_sub + m], ew);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] = ew[q] + (out[q] - e[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) fout[q * N + p] = out[q];
+}
+
 // ---- K5: move the grid from y_k to y_{k+1} and refill it ---------------------
 // Each non-wall node is located, at its new position, in the grid of t_k:
 // inside a triangle -> type 3 (barycentric interpolation of f); inside the
@@ -681,21 +769,38 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
                                              const R *__restrict__ fo, R *__restrict__ fn, int64_t k, int bx) {
   const int p = bx * blockDim.x + threadIdx.x;
   if (p >= v.nnode) return;
-  const int i = p % v.nux, j = p / v.nux;
   const size_t N = (size_t)v.nnode;
   R out[9];
-  if (v.tab[v.cls[p]].type == NODE_WALL) {
+  if ((v.mesh ? v.m_type[p] : v.tab[v.cls[p]].type) == NODE_WALL) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) fn[q * N + p] = fo[q * N + p];
     return;
   }
   const StepParams &P = v.params[k];
-  const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body, v.gx, v.gy};
-  const RefillCell rc = refill_cell(gg, P.ybase, P.ybase1, i, j);
+  int node[3];
+  double lam[3];
+  RefillCell rc;
+  double X, Ynew;
+  if (v.mesh) {
+    // the node's new position in the grid of t_k; not in any triangle:
+    // inside the old lamina (type 2) or outside the old grid (type 1)
+    X = v.xc + v.m_x[p];
+    Ynew = P.ybase1 + v.m_y[p];
+    const double xl = X - v.xc, yl = Ynew - P.ybase;
+    rc.kind = mesh_locate(v.mg, xl, yl, node, lam) >= 0 ? 3
+              : (v.body && fabs(xl) < v.half_b && fabs(yl) < v.half_T) ? 2 : 1;
+  } else {
+    const int i = p % v.nux, j = p / v.nux;
+    const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body, v.gx, v.gy};
+    rc = refill_cell(gg, P.ybase, P.ybase1, i, j);
+    X = v.gx ? v.xc + v.gx[i] : v.xc + (double)(i - v.nux / 2) * v.h;
+    Ynew = v.gy ? P.ybase1 + v.gy[j] : P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
+    if (rc.kind == 3) {
+      double dlam[3];
+      cell_triangle(rc.ci, rc.cj, v.nux, rc.a, rc.b, node, lam, dlam, rc.tri);
+    }
+  }
   if (rc.kind == 3) {
-    int node[3];
-    double lam[3], dlam[3];
-    cell_triangle(rc.ci, rc.cj, v.nux, rc.a, rc.b, node, lam, dlam, rc.tri);
 #pragma unroll
     for (int q = 0; q < 9; ++q)
       out[q] = R(lam[0]) * fo[q * N + node[0]] + R(lam[1]) * fo[q * N + node[1]] + R(lam[2]) * fo[q * N + node[2]];
@@ -704,8 +809,6 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
     for (int q = 0; q < 9; ++q) out[q] = fo[q * N + p];
     atomicAdd(&v.counts[1], 1ull);
   } else {
-    const double X = v.gx ? v.xc + v.gx[i] : v.xc + (double)(i - v.nux / 2) * v.h;
-    const double Ynew = v.gy ? P.ybase1 + v.gy[j] : P.ybase1 + ((double)j - 0.5 * (double)(v.nuy - 1)) * v.h;
     R rho, ux, uy, fneq[9], e[9];
     lattice_bilinear<T, R>(A, v.nx, v.ny, v.plane, v.bc, X, Ynew, rho, ux, uy, fneq);
     equilibrium<R>(rho, ux, uy, e);
@@ -1295,6 +1398,16 @@ void Kernels<T, R>::batched(BatchKernel which, const CaseView<T, R> *views, cons
       hipLaunchKernelGGL((kb_force<T, R>), g, dim3(256), 0, s, views, items);
       break;
   }
+}
+
+template <class T, class R>
+void Kernels<T, R>::mesh_substep(const CaseView<T, R> &v, const R *f, R *fout, int m, hipStream_t s,
+                                 hipEvent_t start, hipEvent_t stop) {
+  const dim3 g(blocks(v.nnode, 256));
+  if (start || stop)
+    hipExtLaunchKernelGGL((k_mesh_substep<T, R>), g, dim3(256), 0, s, start, stop, 0, v, f, fout, m);
+  else
+    hipLaunchKernelGGL((k_mesh_substep<T, R>), g, dim3(256), 0, s, v, f, fout, m);
 }
 
 template <class T, class R>

@@ -29,6 +29,7 @@ EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_s
            "hlbm_set_state", "hlbm_info_get", "hlbm_get_stencil", "hlbm_timing",
            "hlbm_timing_get", "hlbm_tune", "hlbm_destroy", "hlbm_last_error",
            "hlbm_create_multilevel", "hlbm_level_shape", "hlbm_set_motion", "hlbm_create_graded",
+           "hlbm_create_mesh",
            "hlbm_get_state_noalloc")
 STATUS_RUNNING, STATUS_DONE, STATUS_UNSTABLE = 0, 1, 2
 
@@ -107,6 +108,8 @@ def load(path: str = LIB_PATH):
     L.hlbm_level_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), dp]
     L.hlbm_set_motion.argtypes = [vp, i32, C.POINTER(Motion)]
     L.hlbm_create_graded.argtypes = [C.POINTER(Config), dp, dp, C.POINTER(vp)]
+    L.hlbm_create_mesh.argtypes = [C.POINTER(Config), i32, dp, C.POINTER(i32), i32, C.POINTER(i32),
+                                   C.POINTER(vp)]
     L.hlbm_destroy.argtypes = [vp]
     L.hlbm_destroy.restype = None
     L.hlbm_last_error.argtypes = [vp]
@@ -124,14 +127,22 @@ class Case:
 
     def __init__(self, nx, ny, nux=0, nuy=0, h_u=1.0, b=0.0, thickness=1.0, tau=0.8, kc=0.0,
                  beta=0.0, n_sub=0, bc=BC_PERIODIC_X_WALLS_Y, storage=FP64, flags=0,
-                 ckpt_every=0, max_steps=0, x_nodes=None, y_nodes=None):
+                 ckpt_every=0, max_steps=0, x_nodes=None, y_nodes=None, mesh=None):
         L = load()
         if isinstance(storage, str):
             storage = STORAGE[storage]
         self.cfg = Config(nx, ny, nux, nuy, h_u, b, thickness, tau, kc, beta, n_sub, bc, storage,
                           flags, ckpt_every, 0, max_steps)
         h = C.c_void_p()
-        if x_nodes is not None or y_nodes is not None:  # graded grid
+        if mesh is not None:  # any triangulation: (xy [n, 2], node types [n], triangles [m, 3])
+            xy = np.ascontiguousarray(mesh[0], dtype=np.float64)
+            ty = np.ascontiguousarray(mesh[1], dtype=np.int32)
+            tri = np.ascontiguousarray(mesh[2], dtype=np.int32)
+            if xy.ndim != 2 or xy.shape[1] != 2 or ty.shape != (len(xy),) or tri.ndim != 2 or tri.shape[1] != 3:
+                raise HlbmError(E_ARG, "mesh needs xy [n, 2], types [n] and triangles [m, 3]")
+            rc = L.hlbm_create_mesh(C.byref(self.cfg), len(xy), _ptr(xy), _ptr(ty, C.c_int32), len(tri),
+                                    _ptr(tri, C.c_int32), C.byref(h))
+        elif x_nodes is not None or y_nodes is not None:  # graded grid
             gx = np.ascontiguousarray(x_nodes, dtype=np.float64)
             gy = np.ascontiguousarray(y_nodes, dtype=np.float64)
             if gx.shape != (nux,) or gy.shape != (nuy,):

@@ -1,0 +1,168 @@
+"""The HIP library on unstructured triangulations (hlbm_create_mesh) against
+the FP64 CPU oracle on the same meshes (or_create_mesh).
+
+The meshes are seeded Delaunay triangulations of the grid region with
+graded spacing (paper_2006_13631_amd.meshes): irregular node positions and
+neighbour counts, no structure the split-quad kernels could use. Both sides
+build their own stencils and point location from the mesh. FP64 bar as in
+the other parity tests: max|f_gpu - f_oracle| / max|f_oracle| <= 1e-12 over
+lattice and grid, the same for the force history.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2006_13631_amd import hlbm
+from paper_2006_13631_amd.meshes import WALL, lamina_triangulation
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+# (lattice nx, ny, mesh arguments, case arguments)
+CASES = {
+    "lamina_96x48": (96, 48, dict(W=36.0, H=13.0, b=16.0, T=1.0, h_wall=0.7, h_far=1.0, seed=1),
+                     dict(b=16.0, thickness=1.0, tau=0.7, kc=0.6, beta=40.0, n_sub=8)),
+    # odd sizes, a finer and thinner lamina, automatic sub-step count
+    "ragged_77x45": (77, 45, dict(W=30.0, H=12.0, b=12.0, T=0.6, h_wall=0.6, h_far=1.0, seed=4, smooth=2),
+                     dict(b=12.0, thickness=0.6, tau=0.8, kc=0.5, beta=30.0, n_sub=0)),
+    # no body: the grid oscillates through the fluid
+    "no_body_80x40": (80, 40, dict(W=28.0, H=12.0, b=0.0, h_wall=1.0, h_far=1.0, seed=9),
+                      dict(b=10.0, thickness=1.0, tau=0.75, kc=0.8, beta=30.0, n_sub=6,
+                           flags=hlbm.FLAG_NO_BODY)),
+    # larger: a 256 x 128 lattice, some three thousand grid nodes
+    "lamina_256x128": (256, 128, dict(W=100.0, H=25.0, b=64.0, T=1.0, h_wall=0.7, h_far=1.0, seed=2),
+                       dict(b=64.0, thickness=1.0, tau=0.8, kc=0.5, beta=100.0, n_sub=8)),
+}
+
+
+def _pair(oracle, name, steps, storage=hlbm.FP64, bc=hlbm.BC_PERIODIC_X_WALLS_Y, **over):
+    nx, ny, margs, cargs = CASES[name]
+    mesh = lamina_triangulation(**margs)
+    c = dict(cargs, **over)
+    o = oracle.Sim(nx, ny, bc=bc, max_steps=steps, mesh=mesh, **c)
+    g = hlbm.Case(nx, ny, bc=bc, storage=storage, max_steps=steps, mesh=mesh, **c)
+    return o, g, mesh
+
+
+def _check(o, g, tol=TOL):
+    errs = {"lattice": _rel(g.lattice(), o.lattice()), "grid": _rel(g.grid(), o.grid()),
+            "force": _rel(g.history(), o.history())}
+    _say("parity errors", errs)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
+@pytest.mark.parametrize("name,steps", [("lamina_96x48", 60), ("ragged_77x45", 40), ("no_body_80x40", 50),
+                                        ("lamina_256x128", 40)])
+def test_mesh_case_matches_oracle(oracle, name, steps):
+    _say("mesh parity", name, steps)
+    o, g, mesh = _pair(oracle, name, steps)
+    assert g.nnode == len(mesh[0]) == o.nnode
+    o.step(steps)
+    g.step(steps)
+    io, ig = o.info(), g.info()
+    assert ig.n_type1 == io.n_type1 and ig.n_type2 == io.n_type2 and ig.n_type3 == io.n_type3
+    _check(o, g)
+
+
+@pytest.mark.parametrize("bc", [hlbm.BC_PERIODIC, hlbm.BC_PAPER])
+def test_mesh_boundaries(oracle, bc):
+    _say("mesh parity, bc", bc)
+    o, g, _ = _pair(oracle, "lamina_96x48", 30, bc=bc)
+    o.step(30)
+    g.step(30)
+    _check(o, g)
+
+
+def test_mesh_in_chunks_with_graphs(oracle):
+    """Many calls of different lengths (graph replays and single steps) end
+    where one call ends."""
+    o, g, _ = _pair(oracle, "lamina_96x48", 90)
+    o.step(90)
+    for n in (1, 2, 17, 8, 30, 32):
+        g.step(n)
+    _check(o, g)
+
+
+def test_mesh_stencil_matches_oracle(oracle):
+    o, g, mesh = _pair(oracle, "ragged_77x45", 1)
+    k = 16
+    nbr_g, S_g, C_g = g.stencil(k)
+    nbr_o, S_o, C_o, _ = o.mesh().stencil()
+    N = len(mesh[0])
+
+    def sparse(nbr, M):
+        rows = np.repeat(np.arange(N), nbr.shape[1])
+        cols = nbr.ravel()
+        keep = cols >= 0
+        return sp.csr_matrix((M.ravel()[keep], (rows[keep], cols[keep])), shape=(N, N))
+    assert abs(sparse(nbr_g, C_g) - sparse(nbr_o, C_o)).max() < 1e-13
+    smax = np.abs(S_o).max()
+    for q in range(9):
+        assert abs(sparse(nbr_g, S_g[:, q, :]) - sparse(nbr_o, S_o[:, q, :])).max() < 1e-13 * smax
+
+
+def test_mesh_coupled_motion(oracle):
+    """Two-way coupled motion on the unstructured grid: the force sets the
+    next position, which the refill and the interpolation use."""
+    o, g, _ = _pair(oracle, "lamina_96x48", 40, kc=0.0)
+    args = dict(mass=400.0, stiffness=0.05, damping=0.0, y0=0.3, v0=0.0, y_max=2.0)
+    o.set_motion(**args)
+    g.set_motion(**args)
+    o.step(40)
+    g.step(40)
+    _check(o, g)
+
+
+# FP32: rounding of about 6e-8 per operation accumulated over 20 steps of
+# 8 sub-steps (160 grid updates), about 1e-5 at worst; FP16 deviations as on
+# the split-quad grid
+@pytest.mark.parametrize("storage,tol", [(hlbm.FP32, 1e-5), (hlbm.FP16_DEV, 2e-4)])
+def test_mesh_reduced_precision(oracle, storage, tol):
+    o, g, _ = _pair(oracle, "lamina_96x48", 20, storage=storage)
+    o.step(20)
+    g.step(20)
+    errs = {"lattice": _rel(g.lattice(), o.lattice()), "grid": _rel(g.grid(), o.grid())}
+    _say("errors", storage, errs)
+    assert max(errs.values()) <= tol, errs
+
+
+def test_mesh_tune_and_timing_keep_results(oracle):
+    o, g, _ = _pair(oracle, "lamina_96x48", 24)
+    t = g.tune(trial_steps=2)
+    assert t["ms_per_step"] > 0
+    g.timing(3)
+    o.step(24)
+    g.step(24)
+    _check(o, g)
+
+
+def test_mesh_rejects_invalid_meshes():
+    nx, ny, margs, cargs = CASES["lamina_96x48"]
+    xy, ty, tri = lamina_triangulation(**margs)
+
+    def make(xy_=xy, ty_=ty, tri_=tri, **over):
+        return hlbm.Case(nx, ny, max_steps=4, mesh=(xy_, ty_, tri_), **dict(cargs, **over))
+    bad = tri.copy()
+    bad[0] = bad[0][[0, 2, 1]]
+    for kw in (dict(tri_=bad),                                               # clockwise
+               dict(tri_=np.where(tri == 5, len(xy), tri).astype(np.int32)),  # index out of range
+               dict(ty_=np.where(ty == WALL, 0, ty).astype(np.int32)),        # body without wall nodes
+               dict(ty_=np.full_like(ty, 7)),                                 # unknown type
+               dict(xy_=xy + [0.0, 0.3]),                                     # box not symmetric in y
+               dict(ckpt_every=4),                                            # no adjoint
+               dict(b=40.0)):                                                 # lamina too wide
+        with pytest.raises(hlbm.HlbmError) as e:
+            make(**kw)
+        assert e.value.code == hlbm.E_ARG, kw

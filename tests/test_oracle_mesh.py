@@ -1,149 +1,168 @@
-"""The oracle on unstructured triangulations (or_create_mesh) and the seeded
-mesh generator that feeds it and the GPU library.
+"""Pins of the oracle's body-fitted grid and its finite-volume matrices
+S_ik and C_ik (Eq.(ulbe), Sec. 3).
 
-The paper's grid is an unstructured triangulation around the body (Sec.
-Hybrid lattice Boltzmann method). Pins that hold on any triangulation:
+The paper cites S_ik and C_ik without giving them; the oracle takes the
+median-dual control volume with piecewise-linear f. These tests check that
+assembly against closed forms computed here independently:
 
-* the generator covers the rectangle minus the lamina exactly, with outer
-  boundary nodes of type interface and lamina nodes of type wall;
-* the median-dual matrices of Eq.(ulbe): every row of C_ik sums to one (the
-  shape functions sum to one), every row of S_ik sums to zero (a constant
-  has no net outflow through a closed control volume), S_ik reproduces
-  -c_i . grad f of a linear field at every node, and the control volumes
-  tile the mesh;
-* point location returns the lowest-numbered triangle that holds the point
-  (brute force over every triangle);
-* a resting fluid stays at rest on the whole hybrid system.
-
-The exchange across the moving interface on such a mesh is pinned by the
-Couette test in tests/test_oracle_interface.py.
+* streaming: by the divergence theorem the outflow through the boundary of a
+  control volume equals the integral of c.grad f over it, and each triangle
+  gives one third of its area to each vertex, so
+  S_ik = -(1/V_P) sum_{T ni P} (|T|/3) c_i . grad(phi_k on T);
+* collision: the integral of a vertex's own shape function over its part of
+  a triangle is 11/54 |T|, that of either other vertex 7/108 |T|;
+* consistency: sum_k C_ik = 1, sum_k S_ik = 0, and the scheme is exact on
+  linear fields, sum_k S_ik (a . x_k) = -c_i . a.
 """
 import numpy as np
 import pytest
 
-from paper_2006_13631_amd.meshes import INTERFACE, WALL, lamina_triangulation
+from paper_2006_13631_amd.workloads import graded_nodes
+
+# graded lamina grids (spacing growing away from the lamina)
+GX = graded_nodes(15, 0.5, 1.4, 2.0, fine=2.0)
+GY = graded_nodes(10, 0.5, 1.5, 2.0)
+
+MESHES = [
+    ("graded", dict(X=GX, Y=GY, b=3.0)),
+    ("graded", dict(X=graded_nodes(11, 1.0, 1.3, 3.0), Y=graded_nodes(8, 1.0, 1.3, 3.0), b=0.0)),
+    ("lamina", dict(nux=12, nuy=8, h=1.0, b=4.0)),
+    ("lamina", dict(nux=13, nuy=10, h=0.5, b=3.0)),
+    ("lamina", dict(nux=9, nuy=6, h=1.0, b=0.0)),
+    ("periodic", dict(nx=6, ny=5, h=1.0)),
+    ("channel", dict(nx=5, ny=6, h=0.7)),
+]
 
 
-def _mesh(seed=1, **kw):
-    args = dict(W=36.0, H=13.0, b=16.0, T=1.0, h_wall=0.7, h_far=1.0, seed=seed)
-    args.update(kw)
-    return lamina_triangulation(**args)
+def _mesh(oracle, kind, kw):
+    if kind == "graded":
+        return oracle.Mesh.lamina_coords(kw["X"], kw["Y"], kw["b"])
+    if kind == "lamina":
+        return oracle.Mesh.lamina(kw["nux"], kw["nuy"], kw["h"], kw["b"])
+    if kind == "periodic":
+        return oracle.Mesh.periodic(kw["nx"], kw["ny"], kw["h"])
+    return oracle.Mesh.channel(kw["nx"], kw["ny"], kw["h"])
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(b=0.0, seed=3), dict(h_wall=0.5, T=0.5, seed=4),
-                                dict(smooth=3, seed=2)])
-def test_generator_covers_the_region(kw):
-    xy, ty, tri = _mesh(**kw)
-    W, H = 36.0, 13.0
-    b, T = kw.get("b", 16.0), kw.get("T", 1.0)
-    a = xy[tri]
-    area = 0.5 * ((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1])
-                  - (a[:, 2, 0] - a[:, 0, 0]) * (a[:, 1, 1] - a[:, 0, 1]))
-    assert np.all(area > 0)
-    assert abs(area.sum() - (W * H - b * T)) < 1e-9 * W * H
-    on_outer = np.isclose(np.abs(xy[:, 0]), W / 2) | np.isclose(np.abs(xy[:, 1]), H / 2)
-    assert np.array_equal(ty == INTERFACE, on_outer)
-    if b > 0:
-        on_body = (np.abs(xy[:, 0]) <= b / 2 + 1e-12) & (np.abs(xy[:, 1]) <= T / 2 + 1e-12)
-        assert np.array_equal(ty == WALL, on_body)
-    # neither a split quad nor any structured pattern: many neighbour counts
-    e = np.unique(np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]]), axis=1), axis=0)
-    deg = np.bincount(e.ravel(), minlength=len(xy))[ty == 0]
-    assert len(np.unique(deg)) >= 4
+def _dense(nbr, M):
+    """[nnode][k] (or [nnode][9][k]) neighbour-slot matrix -> dense [9][N][N]"""
+    N = nbr.shape[0]
+    if M.ndim == 2:
+        D = np.zeros((N, N))
+        for p in range(N):
+            for k, q in enumerate(nbr[p]):
+                if q >= 0:
+                    D[p, q] += M[p, k]
+        return D
+    D = np.zeros((9, N, N))
+    for p in range(N):
+        for k, q in enumerate(nbr[p]):
+            if q >= 0:
+                D[:, p, q] += M[p, :, k]
+    return D
 
 
-def test_generator_is_seeded():
-    a, b_ = _mesh(seed=7), _mesh(seed=7)
-    for u, v in zip(a, b_):
-        assert np.array_equal(u, v)
-    assert len(_mesh(seed=8)[0]) != len(a[0]) or not np.array_equal(_mesh(seed=8)[0], a[0])
-
-
-def _sim(oracle, mesh, kc=0.6, steps=10, flags=0):
-    return oracle.Sim(96, 48, b=16.0, thickness=1.0, tau=0.7, kc=kc, beta=40.0, n_sub=8,
-                      bc=oracle.BC_PERIODIC_X_WALLS_Y, flags=flags, max_steps=steps, mesh=mesh)
-
-
-def test_unstructured_matrices(oracle):
-    xy, ty, tri = _mesh()
-    sim = _sim(oracle, (xy, ty, tri))  # owns the mesh
-    m = sim.mesh()
-    nbr, S, Cm, V = m.stencil()
-    valid = nbr >= 0
-    assert np.abs(Cm.sum(1) - 1).max() < 1e-13
-    assert np.abs(S.sum(2)).max() < 1e-12
-    assert abs(V.sum() - (36 * 13 - 16)) < 1e-10
-    assert np.all(V > 0)
-    # every neighbour shares a triangle with the node
-    pairs = set()
-    for t in tri:
-        for i in range(3):
-            for j in range(3):
-                pairs.add((int(t[i]), int(t[j])))
-    for p in range(len(xy)):
-        for q in nbr[p][valid[p]]:
-            assert (p, int(q)) in pairs
-    x, y, _ = m.nodes()
+def _closed_forms(oracle, m):
     cx, cy, _ = oracle.d2q9()
-    rng = np.random.default_rng(0)
-    for _ in range(3):
-        g = rng.standard_normal(3)
-        f = g[0] + g[1] * x + g[2] * y
-        F = np.where(valid, f[np.maximum(nbr, 0)], 0.0)
-        for i in range(9):
-            got = (S[:, i, :] * F).sum(1)
-            assert np.abs(got + (cx[i] * g[1] + cy[i] * g[2])).max() < 1e-12
+    tri, txy = m.triangles()
+    N = m.nnode
+    V = np.zeros(N)
+    S = np.zeros((9, N, N))
+    Cm = np.zeros((N, N))
+    for t in range(m.ntri):
+        P = txy[t]
+        area = 0.5 * ((P[1, 0] - P[0, 0]) * (P[2, 1] - P[0, 1]) - (P[2, 0] - P[0, 0]) * (P[1, 1] - P[0, 1]))
+        assert area > 0
+        # gradients of the linear shape functions: grad phi_a = perp(opposite edge) / (2 area)
+        grads = []
+        for a in range(3):
+            b, c = (a + 1) % 3, (a + 2) % 3
+            ex, ey = P[c] - P[b]
+            grads.append(np.array([-ey, ex]) / (2 * area))
+        for a in range(3):
+            p = tri[t, a]
+            V[p] += area / 3
+            for j in range(3):
+                q = tri[t, j]
+                S[:, p, q] -= (area / 3) * (cx * grads[j][0] + cy * grads[j][1])
+                Cm[p, q] += area * (11.0 / 54.0 if j == a else 7.0 / 108.0)
+    return V, S / V[None, :, None], Cm / V[:, None]
 
 
-def test_unstructured_locate_is_lowest_triangle(oracle):
-    xy, ty, tri = _mesh(seed=2)
-    sim = _sim(oracle, (xy, ty, tri))  # owns the mesh
-    m = sim.mesh()
-    a = xy[tri]
-    rng = np.random.default_rng(1)
-    pts = np.column_stack([rng.uniform(-18.5, 18.5, 400), rng.uniform(-7, 7, 400)])
-    # also points on edges and at nodes, where several triangles hold them
-    pts = np.vstack([pts, xy[::7], 0.5 * (a[::5, 0] + a[::5, 1])])
+@pytest.mark.parametrize("kind,kw", MESHES)
+def test_stencil_matches_closed_forms(oracle, kind, kw):
+    m = _mesh(oracle, kind, kw)
+    nbr, S, Cm, V = m.stencil()
+    V0, S0, C0 = _closed_forms(oracle, m)
+    assert np.max(np.abs(V - V0)) < 1e-13
+    Sd = _dense(nbr, S)
+    Cd = _dense(nbr, Cm)
+    assert np.max(np.abs(Sd - S0)) < 1e-13
+    assert np.max(np.abs(Cd - C0)) < 1e-14
+
+
+@pytest.mark.parametrize("kind,kw", MESHES)
+def test_stencil_consistency(oracle, kind, kw):
+    m = _mesh(oracle, kind, kw)
+    nbr, S, Cm, V = m.stencil()
+    cx, cy, _ = oracle.d2q9()
+    x, y, _ = m.nodes()
+    assert np.all(nbr[:, 0] == np.arange(m.nnode))  # k = 0 is the pivotal node
+    assert np.max(np.abs(Cm.sum(1) - 1.0)) < 1e-14
+    assert np.max(np.abs(S.sum(2))) < 1e-13
+    # linear fields along a periodic direction are not single-valued
+    dirs = {"lamina": ((1.0, 0.0), (0.0, 1.0), (0.3, -0.7)), "graded": ((1.0, 0.0), (0.0, 1.0), (0.3, -0.7)),
+            "channel": ((0.0, 1.0),), "periodic": ()}
+    for a in dirs[kind]:
+        lin = a[0] * x + a[1] * y
+        got = np.einsum("pik,pk->pi", S, np.where(nbr >= 0, lin[nbr], 0.0))
+        want = -(cx * a[0] + cy * a[1])[None, :]
+        assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_grid_geometry(oracle):
+    """Lamina grid: 2(b/h + 1) wall nodes, the outer ring are interface nodes,
+    the meshed area is the grid rectangle minus the lamina slot."""
+    nux, nuy, h, b = 16, 10, 1.0, 6.0
+    m = oracle.Mesh.lamina(nux, nuy, h, b)
+    x, y, t = m.nodes()
+    assert (t == oracle.NODE_WALL).sum() == 2 * (int(b / h) + 1)
+    assert (t == oracle.NODE_INTERFACE).sum() == 2 * (nux + nuy) - 4
+    wall = t == oracle.NODE_WALL
+    assert np.allclose(np.abs(y[wall]), 0.5 * h) and np.all(np.abs(x[wall]) <= b / 2 + 1e-12)
+    _, _, _, V = m.stencil()
+    area = (nux - 1) * (nuy - 1) * h * h - b * h
+    assert abs(V.sum() - area) < 1e-12
+    # mirror-symmetric diagonals: the triangle set maps onto itself under x -> -x
+    m2 = oracle.Mesh.lamina(nux + 1, nuy, h, b)
+    _, txy = m2.triangles()
+    key = lambda P: tuple(sorted((round(a, 9), round(c, 9)) for a, c in P))
+    fwd = {key(P) for P in txy}
+    mir = {key(np.c_[-P[:, 0], P[:, 1]]) for P in txy}
+    assert fwd == mir
+
+
+@pytest.mark.parametrize("graded", [False, True])
+def test_point_location_vs_exhaustive(oracle, graded):
+    m = oracle.Mesh.lamina_coords(GX, GY, 3.0) if graded else oracle.Mesh.lamina(10, 8, 1.0, 4.0)
+    tri, txy = m.triangles()
+    rng = np.random.default_rng(7)
+    pts = rng.uniform([-6, -4.5], [5, 4.5], size=(400, 2))
+    # add points on edges and vertices
+    pts = np.vstack([pts, txy.reshape(-1, 2)[:60], 0.5 * (txy[:40, 0] + txy[:40, 1])])
     for px, py in pts:
-        d = (a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 2, 0] - a[:, 0, 0]) * (a[:, 1, 1] - a[:, 0, 1])
-        l1 = ((px - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 2, 0] - a[:, 0, 0]) * (py - a[:, 0, 1])) / d
-        l2 = ((a[:, 1, 0] - a[:, 0, 0]) * (py - a[:, 0, 1]) - (px - a[:, 0, 0]) * (a[:, 1, 1] - a[:, 0, 1])) / d
-        inside = np.nonzero((l1 >= -1e-12) & (l2 >= -1e-12) & (1 - l1 - l2 >= -1e-12))[0]
         t, lam = m.locate(px, py)
-        assert t == (inside[0] if len(inside) else -1)
-        if t >= 0:
-            assert np.allclose(lam @ a[t], [px, py], atol=1e-12)
-
-
-def test_unstructured_rest_state(oracle):
-    s = _sim(oracle, _mesh(), kc=0.0, steps=20)
-    s.step(20)
-    _, _, w = oracle.d2q9()
-    assert np.abs(s.lattice() - w[:, None, None]).max() < 1e-15
-    assert np.abs(s.grid() - w[:, None]).max() < 1e-15
-
-
-def test_unstructured_moving_lamina_runs(oracle):
-    """A moving lamina on a Delaunay grid: every refill type but 2 occurs,
-    the state stays finite and the lift oscillates with the motion."""
-    s = _sim(oracle, _mesh(), steps=300)
-    s.step(300)
-    inf = s.info()
-    assert inf.n_type1 > 0 and inf.n_type3 > 0
-    h = s.history()
-    assert np.isfinite(h).all() and np.abs(h[:, 1]).max() > 0.1
-    assert np.isfinite(s.grid()).all() and np.isfinite(s.lattice()).all()
-
-
-def test_mesh_rejects_bad_input(oracle):
-    xy, ty, tri = _mesh()
-    with pytest.raises(ValueError):  # clockwise triangle
-        bad = tri.copy()
-        bad[0] = bad[0][[0, 2, 1]]
-        _sim(oracle, (xy, ty, bad))
-    with pytest.raises(ValueError):  # node index out of range
-        bad = tri.copy()
-        bad[3, 1] = len(xy)
-        _sim(oracle, (xy, ty, bad))
-    with pytest.raises(ValueError):  # a body but no wall nodes
-        _sim(oracle, (xy, np.where(ty == WALL, 0, ty).astype(np.int32), tri))
+        inside = []
+        for u in range(m.ntri):
+            P = txy[u]
+            T = np.array([[P[1, 0] - P[0, 0], P[2, 0] - P[0, 0]], [P[1, 1] - P[0, 1], P[2, 1] - P[0, 1]]])
+            l12 = np.linalg.solve(T, [px - P[0, 0], py - P[0, 1]])
+            l = np.array([1 - l12.sum(), l12[0], l12[1]])
+            if np.all(l >= -1e-12):
+                inside.append((u, l))
+        if not inside:
+            assert t == -1
+        else:
+            assert t == inside[0][0]
+            assert np.allclose(lam, inside[0][1], atol=1e-12)
+            assert np.allclose(lam @ txy[t], [px, py], atol=1e-12)
