@@ -307,10 +307,11 @@ def adjoint_leg(workload, storage, W_ckpt, fd_step, steps=None):
     }
 
 
-def sweep_leg(seed=0, periods=10.0, loop=True, tune_steps=8, chunk=4000, only=None):
+def sweep_leg(seed=0, periods=10.0, loop=True, tune_steps=8, chunk=4000, only=None, overrides=None):
     """The (KC, beta) sweep: all cases as one FP32 batch (autotuned schedule)
     against the plain FP64 loop over the same cases one by one; Theta of each
-    case compared at the 1e-3 relative bar."""
+    case compared at the 1e-3 relative bar. overrides: schedule entries that
+    replace the tuned ones (e.g. the persistent launch) before the run."""
     import torch
     from paper_2006_13631_amd import hlbm as H
     from paper_2006_13631_amd.workloads import sweep_cases
@@ -333,6 +334,10 @@ def sweep_leg(seed=0, periods=10.0, loop=True, tune_steps=8, chunk=4000, only=No
     t_create = time.perf_counter() - t0
     t0 = time.perf_counter()
     tuning = batch.tune(trial_steps=tune_steps)
+    if overrides:
+        sched = dict(tuning, **overrides)
+        sched.pop("ms_per_step", None)
+        tuning = batch.tune(schedule=sched)
     t_tune = time.perf_counter() - t0
     print(f"# sweep: {n} cases, FP32 batch, schedule {tuning}", file=sys.stderr, flush=True)
     longest = max(c["max_steps"] for c in cases)
@@ -811,6 +816,8 @@ def main():
                     help="run only the parametric sweep (FP32 batch vs FP64 per-case loop) and print its line")
     ap.add_argument("--sweep-periods", type=float, default=10.0)
     ap.add_argument("--sweep-no-loop", action="store_true")
+    ap.add_argument("--sweep-schedule", default=None,
+                    help="JSON object of schedule entries replacing the tuned ones (e.g. persistent)")
     ap.add_argument("--precision", action="store_true",
                     help="run only the storage-precision comparison (FP64 / FP32 / FP16-deviation) and print its line")
     ap.add_argument("--precision-workload", default="lamina_4096,lamina_4096_stable")
@@ -852,7 +859,9 @@ def main():
 
     if args.sweep:
         torch.cuda.set_device(0)
-        print(json.dumps(sweep_leg(periods=args.sweep_periods, loop=not args.sweep_no_loop)), flush=True)
+        over = json.loads(args.sweep_schedule) if args.sweep_schedule else None
+        print(json.dumps(sweep_leg(periods=args.sweep_periods, loop=not args.sweep_no_loop, overrides=over)),
+              flush=True)
         return
     if args.graded:
         torch.cuda.set_device(0)
