@@ -7,7 +7,7 @@ Default workload: the 2048^2 lamina case (512 x 128 grid, tau 0.55, KC 1,
 beta 1000), FP64: 100 warm-up steps, the library's autotuner (which also
 captures the HIP graphs the steps replay), 1000 timed steps in one call,
 then 80 steps with HIP events at the stream-collide's own start and end,
-80 with events at the first grid sub-step launch's own start and end, and
+80 with events at every grid sub-step launch's own start and end, and
 24 steps with events around every kernel. With plain BGK this configuration
 goes supersonic at the lamina tips and diverges near step 1330 (on the CPU
 oracle as on the GPU), so every step stays before it.
@@ -49,16 +49,24 @@ CALIB_COPY_BYTES = 256 << 20  # plain device copy that scales the HBM byte count
 
 
 def measured_traffic(workload, storage, kernel="k_stream_collide"):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when there is none or the kernel source changed since."""
-    from paper_2006_13631_amd.profiling import source_sha256
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}.{workload}.{storage}.json")
+    """HBM bytes per launch of `kernel` (a name, or a name with template
+    arguments for one instance) from the committed counter summary, or None
+    when there is none or the kernel source changed since."""
+    from paper_2006_13631_amd.profiling import kernel_file, source_sha256
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel_file(kernel)}.{workload}.{storage}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_sha256") != source_sha256():
+    if rec.get("source_sha256") != source_sha256() or rec.get("kernel") != kernel:
         return None
     return rec["bytes_per_launch"]
+
+
+def substeps_per_launch(variant, n_sub):
+    """Mean grid sub-steps per launch of a step: variants 8 and 9 advance
+    one per launch, 10 two, the others up to four."""
+    blk = {8: 1, 9: 1, 10: 2}.get(variant, 4)
+    return n_sub / -(-n_sub // blk)
 
 
 def host_cores():
@@ -774,7 +782,7 @@ def storage_leg(workload, storage, steps, warmup, timing_steps):
     nodes = cfg["nx"] * cfg["ny"]
     avg = ms / 1000.0 / max(n, 1)
     gbs = 18 * BYTES[storage] * nodes / avg / 1e9
-    per_launch = min(4, info.n_sub)
+    per_launch = substeps_per_launch(sched["substep_variant"], info.n_sub)
     avg_g = ms_g / 1000.0 / max(n_g, 1)
     grid_gbs = 18 * {"f64": 8}.get(storage, 4) * info.nnode * per_launch / avg_g / 1e9
     th = None
@@ -952,10 +960,10 @@ def main():
     lat_kernel = "k_stream_collide2" if two else "k_stream_collide"
     # the grid sub-step kernel: 18 s bytes per node and sub-step, the
     # launch's sub-steps (4, or n when fewer)
-    per_launch = min(4, info.n_sub)
+    per_launch = substeps_per_launch(sched["substep_variant"], info.n_sub)
     grid_kernel = f"k_grid_substeps<{ {'f64': 'double'}.get(args.storage, 'float') }, {sched['substep_variant']}>"
     avg_g = ms_g / 1000.0 / max(n_g, 1)
-    grid_bytes = 18 * s_b * info.nnode * per_launch
+    grid_bytes = int(round(18 * s_b * info.nnode * per_launch))
     grid_achieved = grid_bytes / avg_g / 1e9
     th = None
     try:
@@ -977,9 +985,9 @@ def main():
         # cache, so this is algorithmic bytes over the HBM peak
         "roofline": {"bound": "hbm", "achieved": round(grid_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(grid_achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, args.storage, "k_grid_substeps"),
+                     "traffic": measured_traffic(args.workload, args.storage, grid_kernel),
                      "kernel": grid_kernel, "substeps_per_launch": per_launch,
-                     "launches_per_step": -(-info.n_sub // per_launch), "avg_us": round(avg_g * 1e6, 3),
+                     "launches_per_step": round(info.n_sub / per_launch), "avg_us": round(avg_g * 1e6, 3),
                      "bytes_per_launch": grid_bytes, "resident": "L2 + memory-side cache"},
         # the lattice stream-collide: `frac` prices a launch at the
         # algorithmic bytes of the steps it advances (18 s per node update);

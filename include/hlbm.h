@@ -394,8 +394,9 @@ int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
  * hlbm_step and hlbm_adjoint calls, records: level 1, every kernel of the
  * step (events between all kernels); level 2, the stream-collide alone, by
  * events taken at that kernel's own start and end and nothing else in the
- * step; level 3 (a case with a grid), the first grid sub-step launch of
- * every step (of every pair of steps on the two-step path) the same way;
+ * step; level 3 (a case with a grid), each grid sub-step launch of
+ * every step (of one step of every pair on the two-step path; at most 16
+ * per step) the same way;
  * 0 turns recording off. Timed steps are launched one by one instead of as
  * graphs. hlbm_timing_get returns for kernel id (HLBM_K_*) the summed
  * milliseconds and launch count. HLBM_E_STATE for level 3 without a grid. */
@@ -407,8 +408,9 @@ int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
 #define HLBM_K_STEP 5           /* whole structured step                       */
 #define HLBM_K_ADJ_STREAM_COLLIDE 6 /* adjoint of the lattice stream-collide   */
 #define HLBM_K_ADJOINT 7        /* whole hlbm_adjoint call (count = steps)     */
-#define HLBM_K_SUBSTEP_LAUNCH 8 /* level 3: the first grid sub-step launch of a
-                                   step (up to 4 sub-steps, Eq.(ulbe))        */
+#define HLBM_K_SUBSTEP_LAUNCH 8 /* level 3: each grid sub-step launch of a step
+                                   (up to 16 per step; up to 4 sub-steps each,
+                                   Eq.(ulbe)), count = launches timed        */
 int hlbm_timing(hlbm_t *h, int32_t on);
 int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count);
 

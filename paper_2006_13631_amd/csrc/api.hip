@@ -405,23 +405,31 @@ class Case final : public CaseBase {
     Kernels<T, R>::interface_donors(v, s_grid_);
     int cur = gcur_;
     const int blk = substep_block(substep_variant_);
-    // level 3: the step's first sub-step launch, once per timing slot
+    // level 3: every sub-step launch of the step (up to kTimedLaunches),
+    // once per timing slot
     const bool time_sub = timing_ == 3 && sub_mark_ != tslot_;
-    if (time_sub) sub_mark_ = tslot_;
+    if (time_sub) {
+      sub_mark_ = tslot_;
+      sub_n_[tslot_] = 0;
+    }
+    auto sub_ev = [&](int which) -> hipEvent_t {  // 0: start, 1: end of the next timed launch
+      if (!time_sub || sub_n_[tslot_] >= kTimedLaunches) return nullptr;
+      hipEvent_t ev = tev3_[tslot_][2 * sub_n_[tslot_] + which];
+      if (which == 1) ++sub_n_[tslot_];
+      return ev;
+    };
     if (grid_.mesh) {  // one sub-step per launch
       for (int m = 0; m < d_.n; ++m) {
-        const bool ev = time_sub && m == 0;
-        Kernels<T, R>::mesh_substep(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, s_grid_,
-                                    ev ? tev_[tslot_][8] : nullptr, ev ? tev_[tslot_][2] : nullptr);
+        hipEvent_t e0 = sub_ev(0), e1 = sub_ev(1);
+        Kernels<T, R>::mesh_substep(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, s_grid_, e0, e1);
         cur = 1 - cur;
       }
     } else {
       for (int m = 0; m < d_.n; m += blk) {
         const int cnt = std::min(blk, d_.n - m);
-        const bool ev = time_sub && m == 0;
+        hipEvent_t e0 = sub_ev(0), e1 = sub_ev(1);
         Kernels<T, R>::grid_substeps(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], m, cnt, s_grid_, nullptr,
-                                     nullptr, nullptr, 0, substep_variant_, ev ? tev_[tslot_][8] : nullptr,
-                                     ev ? tev_[tslot_][2] : nullptr);
+                                     nullptr, nullptr, 0, substep_variant_, e0, e1);
         cur = 1 - cur;
       }
     }
@@ -816,8 +824,12 @@ class Case final : public CaseBase {
     if (on && !tev_[0][0])
       for (auto &ring : tev_)
         for (auto &e : ring) HIPCHK(hipEventCreate(&e));
+    if (on == 3 && !tev3_[0][0])
+      for (auto &ring : tev3_)
+        for (auto &e : ring) HIPCHK(hipEventCreate(&e));
     tslot_ = 0;
     sub_mark_ = -1;
+    for (int &n : sub_n_) n = 0;
     for (int i = 0; i < kTimedKernels; ++i) {
       tms_[i] = 0.0;
       tcount_[i] = 0;
@@ -1127,6 +1139,9 @@ class Case final : public CaseBase {
     for (auto &ring : tev_)
       for (auto &e : ring)
         if (e) (void)hipEventDestroy(e);
+    for (auto &ring : tev3_)
+      for (auto &e : ring)
+        if (e) (void)hipEventDestroy(e);
     for (auto &e : tev_adj_)
       if (e) (void)hipEventDestroy(e);
     for (auto &pr : tev_adj_ring_)
@@ -1374,8 +1389,9 @@ class Case final : public CaseBase {
   // Accumulates the timings of the steps recorded in the event ring (the
   // steps ran back to back; only here does the host wait for them).
   hipError_t harvest() {
-    hipError_t e = hipEventSynchronize(tev_[tslot_ - 1][2]);
+    hipError_t e = timing_ == 3 ? hipSuccess : hipEventSynchronize(tev_[tslot_ - 1][2]);
     if (e == hipSuccess) e = hipStreamSynchronize(s_main_);
+    if (e == hipSuccess && s_grid_ != s_main_) e = hipStreamSynchronize(s_grid_);
     if (e != hipSuccess) return e;
     for (int i = 0; i < tslot_; ++i) {
       hipEvent_t *t = tev_[i];
@@ -1386,7 +1402,12 @@ class Case final : public CaseBase {
           tcount_[id] += 1;
         }
       };
-      add(timing_ == 3 ? HLBM_K_SUBSTEP_LAUNCH : HLBM_K_STREAM_COLLIDE, t[8], t[2]);
+      if (timing_ == 3) {
+        for (int j = 0; j < sub_n_[i]; ++j) add(HLBM_K_SUBSTEP_LAUNCH, tev3_[i][2 * j], tev3_[i][2 * j + 1]);
+        sub_n_[i] = 0;
+        continue;
+      }
+      add(HLBM_K_STREAM_COLLIDE, t[8], t[2]);
       if (timing_ != 1) continue;
       if (has_grid_) {
         add(HLBM_K_LATTICE_FROM_GRID, t[0], t[1]);
@@ -1700,6 +1721,10 @@ class Case final : public CaseBase {
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
   static constexpr int kTimingRing = 64;  // steps recorded between harvests
   hipEvent_t tev_[kTimingRing][9] = {};
+  // level 3: start and end events of each sub-step launch of a step
+  static constexpr int kTimedLaunches = 16;
+  hipEvent_t tev3_[kTimingRing][2 * kTimedLaunches] = {};
+  int sub_n_[kTimingRing] = {};
   int tslot_ = 0;
   int timing_ = 0;  // 1: every kernel, 2: the stream-collide only
   int substep_variant_ = -1;  // grid sub-step kernel variant (-1: the default for R)

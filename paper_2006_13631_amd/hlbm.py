@@ -233,7 +233,7 @@ class Case:
 
     def timing(self, level=1):
         """1: every kernel of the step; 2: the stream-collide alone; 3: the
-        first grid sub-step launch of each step alone; 0: off."""
+        grid sub-step launches of each step alone, each by its own events; 0: off."""
         self._check(load().hlbm_timing(self.h, int(level)))
 
     def timing_get(self, kernel):

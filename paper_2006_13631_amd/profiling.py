@@ -18,6 +18,7 @@ import collections
 import csv
 import hashlib
 import json
+import re
 import os
 import sys
 
@@ -78,11 +79,18 @@ def _per_dispatch(path: str, counter: str):
     return out
 
 
+def kernel_file(kernel: str) -> str:
+    """File-name form of a kernel name (template arguments joined by '_')."""
+    return re.sub(r"[^A-Za-z0-9_]+", "_", kernel).strip("_")
+
+
 def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dict:
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         per = _per_dispatch(path, counter)
-        kv = [v for n, vs in per.items() if kernel + "<" in n for v in vs]  # the kernel, not a longer name
+        # the kernel, not a longer name; with template arguments, that instance only
+        match = (lambda n: kernel + "(" in n) if "<" in kernel else (lambda n: kernel + "<" in n)
+        kv = [v for n, vs in per.items() if match(n) for v in vs]
         cv = [v for n, vs in per.items() if COPY_KERNEL in n for v in vs]
         if not kv or not cv:
             raise SystemExit(f"{counter}: no dispatch of {kernel!r} or of the copy kernel in {path}")
