@@ -755,6 +755,73 @@ def graded_leg(workload="lamina_1024", storage="f64"):
     return out
 
 
+def mesh_leg(workload="lamina_2048", storage="f64", steps=200, warmup=20, timing_steps=40, h_wall=1.0, seed=1):
+    """The workload's lamina on an unstructured Delaunay grid of the same
+    extent (spacing h_wall on the lamina growing to 1, seeded) against its
+    split-quad grid: time per step, the CSR sub-step kernel's mean launch
+    time (its own events, one sub-step per launch) against its algorithmic
+    bytes (the stencil's neighbours read and the node written, 9 values
+    each), and the lattice MLUPS. The mesh grid is L2-resident, so the
+    achieved rate is not an HBM fraction."""
+    import torch
+    from paper_2006_13631_amd import hlbm as H
+    from paper_2006_13631_amd.meshes import lamina_triangulation
+    from paper_2006_13631_amd.workloads import preset
+    cfg = preset(workload)
+    cfg.pop("steps")
+    cfg.pop("ckpt_every", None)
+    W = (cfg["nux"] - 1) * cfg["h_u"]
+    Hh = (cfg["nuy"] - 1) * cfg["h_u"]
+    t0 = time.perf_counter()
+    mesh = lamina_triangulation(W, Hh, b=cfg["b"], T=cfg["thickness"], h_wall=h_wall, h_far=1.0, seed=seed)
+    t_mesh = time.perf_counter() - t0
+    tri = mesh[2]
+    edges = np.unique(np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]]), axis=1), axis=0)
+    entries = len(mesh[0]) + 2 * len(edges)  # stencil entries: the node and its neighbours
+    s_b = BYTES[storage]
+    out = {"workload": workload, "storage": storage, "steps": steps,
+           "mesh": {"W": W, "H": Hh, "h_wall": h_wall, "h_far": 1.0, "seed": seed, "nodes": len(mesh[0]),
+                    "triangles": int(len(tri)), "mean_stencil": round(entries / len(mesh[0]), 3),
+                    "generate_s": round(t_mesh, 2)}}
+    total = warmup + steps + timing_steps
+    for kind in ("split_quad", "unstructured"):
+        kw = dict(cfg, storage=H.STORAGE[storage], max_steps=total)
+        if kind == "unstructured":
+            kw["mesh"] = mesh
+        c = H.Case(**kw)
+        c.step(warmup)
+        sched = c.tune(trial_steps=4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        c.timing(3)
+        c.step(timing_steps)
+        ms_g, n_g = c.timing_get(H.K_SUBSTEP_LAUNCH)
+        c.timing(0)
+        inf = c.info()
+        avg_g = ms_g / 1000.0 / max(n_g, 1)
+        rec = {"grid_nodes": inf.nnode, "n_sub": inf.n_sub, "ms_per_step": round(1e3 * dt / steps, 4),
+               "mlups": round(cfg["nx"] * cfg["ny"] * steps / dt / 1e6, 1),
+               "substep_launch_us": round(avg_g * 1e6, 3), "launches_timed": n_g,
+               "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}}
+        if kind == "unstructured":
+            byts = (entries + inf.nnode) * 9 * s_b  # stencil reads + one write per node
+            rec.update({"substeps_per_launch": 1, "bytes_per_launch": byts,
+                        "achieved_gbs": round(byts / avg_g / 1e9, 1), "kernel": f"k_mesh_substep<{storage}>"})
+        else:
+            per = substeps_per_launch(sched["substep_variant"], inf.n_sub)
+            byts = int(round(18 * s_b * inf.nnode * per))
+            rec.update({"substeps_per_launch": per, "bytes_per_launch": byts,
+                        "achieved_gbs": round(byts / avg_g / 1e9, 1),
+                        "kernel": f"k_grid_substeps<{storage}, {sched['substep_variant']}>"})
+        out[kind] = rec
+        print(f"# mesh leg {kind}: {rec}", file=sys.stderr, flush=True)
+        c.close()
+    return out
+
+
 def storage_leg(workload, storage, steps, warmup, timing_steps):
     """The same workload at another storage precision: lattice MLUPS over
     graph-replayed steps, the stream-collide's mean duration (its own events)
@@ -843,6 +910,10 @@ def main():
     ap.add_argument("--graded", action="store_true",
                     help="run only the differentiation case on its uniform grid and on a graded grid of the same "
                          "extent and print their line")
+    ap.add_argument("--mesh", action="store_true",
+                    help="run only the main workload on an unstructured Delaunay grid against its split-quad grid "
+                         "and print their line")
+    ap.add_argument("--mesh-steps", type=int, default=200)
     ap.add_argument("--coupled", action="store_true",
                     help="run only the main workload with the lamina elastically mounted (two-way coupled) and "
                          "print its line")
@@ -874,6 +945,10 @@ def main():
     if args.graded:
         torch.cuda.set_device(0)
         print(json.dumps(graded_leg()), flush=True)
+        return
+    if args.mesh:
+        torch.cuda.set_device(0)
+        print(json.dumps(mesh_leg(args.workload, args.storage, steps=args.mesh_steps)), flush=True)
         return
     if args.coupled:
         torch.cuda.set_device(0)

@@ -693,9 +693,12 @@ __global__ __launch_bounds__(SubstepVariant<V>::NT) void kb_grid_substeps(const 
 // and the collision sum of f^neq from the C-weighted sums of f and of
 // rho u u (f^eq being linear in rho, rho u and rho u u), then the lamina
 // velocity at wall nodes.
+// small workgroups: a grid of some ten thousand nodes still spreads over
+// every CU
+constexpr int kMeshThreads = 64;
 template <class T, class R>
-__global__ __launch_bounds__(256) void k_mesh_substep(CaseView<T, R> v, const R *__restrict__ f,
-                                                      R *__restrict__ fout, int m) {
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_substep(CaseView<T, R> v, const R *__restrict__ f,
+                                                               R *__restrict__ fout, int m) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= v.nnode) return;
   const int64_t k = *v.dk;
@@ -1403,11 +1406,11 @@ void Kernels<T, R>::batched(BatchKernel which, const CaseView<T, R> *views, cons
 template <class T, class R>
 void Kernels<T, R>::mesh_substep(const CaseView<T, R> &v, const R *f, R *fout, int m, hipStream_t s,
                                  hipEvent_t start, hipEvent_t stop) {
-  const dim3 g(blocks(v.nnode, 256));
+  const dim3 g(blocks(v.nnode, kMeshThreads));
   if (start || stop)
-    hipExtLaunchKernelGGL((k_mesh_substep<T, R>), g, dim3(256), 0, s, start, stop, 0, v, f, fout, m);
+    hipExtLaunchKernelGGL((k_mesh_substep<T, R>), g, dim3(kMeshThreads), 0, s, start, stop, 0, v, f, fout, m);
   else
-    hipLaunchKernelGGL((k_mesh_substep<T, R>), g, dim3(256), 0, s, v, f, fout, m);
+    hipLaunchKernelGGL((k_mesh_substep<T, R>), g, dim3(kMeshThreads), 0, s, v, f, fout, m);
 }
 
 template <class T, class R>

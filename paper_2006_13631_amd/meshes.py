@@ -51,7 +51,7 @@ def lamina_triangulation(W, H, b=0.0, T=1.0, h_wall=0.5, h_far=1.0, grading=0.3,
     with the triangles inside the lamina removed. Raises ValueError when the
     result does not cover the region exactly (then change the spacing or the
     seed)."""
-    from scipy.spatial import Delaunay
+    from scipy.spatial import Delaunay, cKDTree
 
     if not (W > 0 and H > 0 and h_wall > 0 and h_far >= h_wall):
         raise ValueError("need W, H > 0 and h_far >= h_wall > 0")
@@ -80,39 +80,38 @@ def lamina_triangulation(W, H, b=0.0, T=1.0, h_wall=0.5, h_far=1.0, grading=0.3,
     if body:
         keep &= _dist_rect(cand, hb, ht) >= 0.5 * hc
     cand, hc = cand[keep], hc[keep]
-    cell = 0.8 * h_wall
-    grid: dict[tuple[int, int], list[int]] = {}
-    pts = [tuple(p) for p in np.vstack([outer, wall])]
-
-    def put(i):
-        x, y = pts[i]
-        grid.setdefault((math.floor(x / cell), math.floor(y / cell)), []).append(i)
-    for i in range(len(pts)):
-        put(i)
-    reach = math.ceil(0.8 * h_far / cell)
-    for (x, y), h in zip(cand, hc):
-        r = 0.8 * h
-        cx, cy = math.floor(x / cell), math.floor(y / cell)
-        ok = True
-        for gx in range(cx - reach, cx + reach + 1):
-            for gy in range(cy - reach, cy + reach + 1):
-                for j in grid.get((gx, gy), ()):
-                    px, py = pts[j]
-                    if (px - x) ** 2 + (py - y) ** 2 < r * r:
-                        ok = False
-                        break
-                if not ok:
-                    break
-            if not ok:
-                break
-        if ok:
-            pts.append((x, y))
-            put(len(pts) - 1)
-    xy = np.array(pts, dtype=float)
+    # in chunks: a candidate is checked against the nodes accepted before its
+    # chunk with a k-d tree, then against the earlier ones of its own chunk
+    pts = np.vstack([outer, wall])
+    chunk = 4096
+    for c0 in range(0, len(cand), chunk):
+        c, h = cand[c0:c0 + chunk], hc[c0:c0 + chunk]
+        d, _ = cKDTree(pts).query(c, k=1)
+        ok = np.nonzero(d >= 0.8 * h)[0]
+        if len(ok) == 0:
+            continue
+        sub, subh = c[ok], h[ok]
+        earlier = [[] for _ in range(len(sub))]
+        for i, j in cKDTree(sub).query_pairs(0.8 * subh.max()):
+            earlier[max(i, j)].append(min(i, j))
+        taken = np.zeros(len(sub), bool)
+        for j in range(len(sub)):
+            r2 = (0.8 * subh[j]) ** 2
+            taken[j] = not any(taken[i] and ((sub[i] - sub[j]) ** 2).sum() < r2 for i in earlier[j])
+        pts = np.vstack([pts, sub[taken]])
+    xy = np.asarray(pts, dtype=float)
     n_out, n_wall = len(outer), len(wall)
     node_type = np.full(len(xy), INTERIOR, np.int32)
     node_type[:n_out] = INTERFACE
     node_type[n_out:n_out + n_wall] = WALL
+    # number the nodes along a Z-order curve of unit cells, so that nodes
+    # with nearby numbers are near each other (and share neighbours)
+    cell = np.floor((xy - xy.min(axis=0)) / h_far).astype(np.int64)
+    key = np.zeros(len(xy), np.int64)
+    for bit in range(20):
+        key |= ((cell[:, 0] >> bit) & 1) << (2 * bit) | ((cell[:, 1] >> bit) & 1) << (2 * bit + 1)
+    order = np.lexsort((xy[:, 1], xy[:, 0], key))
+    xy, node_type = xy[order], node_type[order]
 
     def triangulate(xy):
         dl = Delaunay(xy)
