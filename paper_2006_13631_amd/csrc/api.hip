@@ -254,6 +254,8 @@ class Case final : public CaseBase {
     HIPCHK(alloc(&dk_, sizeof(int64_t)));
     HIPCHK(alloc(&flag_, sizeof(int)));
     HIPCHK(alloc(&counts_, 2 * sizeof(unsigned long long)));
+    HIPCHK(alloc(&done_, sizeof(unsigned)));
+    HIPCHK(hipMemset(done_, 0, sizeof(unsigned)));
     HIPCHK(hipMemset(dk_, 0, sizeof(int64_t)));
     HIPCHK(hipMemset(flag_, 0, sizeof(int)));
     HIPCHK(hipMemset(counts_, 0, 2 * sizeof(unsigned long long)));
@@ -439,6 +441,8 @@ class Case final : public CaseBase {
       Kernels<T, R>::force(v, (const R *)gbuf_[cur], s_grid_, 0);
       Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
       Kernels<T, R>::advance_step(v, s_grid_);
+    } else if (timing_ != 1) {  // one launch (level 1 times the two apart)
+      Kernels<T, R>::refill_force(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], done_, s_grid_);
     } else {
       Kernels<T, R>::refill(v, (const R *)gbuf_[cur], (R *)gbuf_[1 - cur], s_grid_);
       if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][5], s_grid_));
@@ -1766,6 +1770,7 @@ class Case final : public CaseBase {
   int64_t *dk_ = nullptr;
   int *flag_ = nullptr;
   unsigned long long *counts_ = nullptr;
+  unsigned *done_ = nullptr;  // workgroups done in the fused refill-and-force launch (0 between launches)
   int k2_x0_ = 0, k2_w_ = 1, k2_h_ = 1;
   int64_t k_ = 0;
   bool use_graphs_ = true;

@@ -165,6 +165,9 @@ struct Kernels {
   static void grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
                               R *tape, R *wtape, const int *widx, int nwall, hipEvent_t start, hipEvent_t stop);
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
+  // refill and force (prescribed motion) in one launch, then the step
+  // counter advances; done: a device counter that starts at 0 and is left at 0
+  static void refill_force(const CaseView<T, R> &v, const R *fold, R *fnew, unsigned *done, hipStream_t s);
   // advance = 0: leave the step counter (a coupled-motion step then runs the
   // refill and advance_step after it)
   static void force(const CaseView<T, R> &v, const R *f, hipStream_t s, int advance = 1);

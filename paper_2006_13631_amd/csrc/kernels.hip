@@ -956,6 +956,34 @@ __global__ __launch_bounds__(256) void k_force(const R *__restrict__ f, const Wa
   force_block<R>(f, wall, n_wall_edges, nnode, dk, hist, flag, mot, P, uw, n_sub, advance);
 }
 
+// Refill and force of one case in one launch: workgroup 0 computes the
+// force of t_{k+1} on the grid before the refill, the others refill it.
+// Every workgroup reads the step counter first and counts itself done at
+// its end; the last one advances the counter (and clears the count for the
+// next launch), so no workgroup can read the advanced step.
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_refill_force(CaseView<T, R> v, const R *__restrict__ fo,
+                                                      R *__restrict__ fn, unsigned *done) {
+  __shared__ int64_t k_s;
+  if (threadIdx.x == 0) k_s = *v.dk;
+  __syncthreads();
+  const int64_t k = k_s;
+  if (blockIdx.x == 0)
+    force_block<R>(fo, v.wall, v.n_wall_edges, v.nnode, v.dk, v.hist, v.flag, MotionCtx{}, nullptr, nullptr, 0,
+                   0);
+  else
+    refill_block<T, R>(v, v.A, fo, fn, k, blockIdx.x - 1);
+  __syncthreads();
+  // the counter was read (into k) before this point; the next launch sees
+  // the advanced counter and the cleared count at the kernel boundary
+  if (threadIdx.x == 0) {
+    if (atomicAdd(done, 1u) == gridDim.x - 1) {
+      *done = 0u;
+      *v.dk = k + 1;
+    }
+  }
+}
+
 // one workgroup per case: item = (case)
 template <class T, class R>
 __global__ __launch_bounds__(256) void kb_force(const CaseView<T, R> *__restrict__ views,
@@ -1332,6 +1360,11 @@ template <class T, class R>
 void Kernels<T, R>::force(const CaseView<T, R> &v, const R *f, hipStream_t s, int advance) {
   hipLaunchKernelGGL((k_force<R>), dim3(1), dim3(256), 0, s, f, v.wall, v.n_wall_edges, v.nnode, v.dk, v.hist,
                      v.flag, v.mot, const_cast<StepParams *>(v.params), const_cast<R *>(v.uw), v.n_sub, advance);
+}
+
+template <class T, class R>
+void Kernels<T, R>::refill_force(const CaseView<T, R> &v, const R *fold, R *fnew, unsigned *done, hipStream_t s) {
+  hipLaunchKernelGGL((k_refill_force<T, R>), dim3(1 + blocks(v.nnode, 256)), dim3(256), 0, s, v, fold, fnew, done);
 }
 
 template <class T, class R>
