@@ -255,6 +255,8 @@ class Case final : public CaseBase {
     HIPCHK(alloc(&flag_, sizeof(int)));
     HIPCHK(alloc(&counts_, 2 * sizeof(unsigned long long)));
     HIPCHK(alloc(&done_, sizeof(unsigned)));
+    HIPCHK(alloc(&dk_copy_, sizeof(int64_t)));
+    HIPCHK(hipMemset(dk_copy_, 0, sizeof(int64_t)));
     HIPCHK(hipMemset(done_, 0, sizeof(unsigned)));
     HIPCHK(hipMemset(dk_, 0, sizeof(int64_t)));
     HIPCHK(hipMemset(flag_, 0, sizeof(int)));
@@ -336,7 +338,7 @@ class Case final : public CaseBase {
         HIPCHK(alloc(&ck_grid_, (size_t)nck_ * ck_grid_bytes_));
       }
     }
-    two_step_ = two_step && std::getenv("HLBM_ONE_STEP") == nullptr && s_grid_ == s_main_ && choose_band();
+    two_step_ = two_step && std::getenv("HLBM_ONE_STEP") == nullptr && choose_band();
     if (two_step_) {
       HIPCHK(alloc(&lat_[2], 9 * plane_ * sizeof(T)));
       Kernels<T, R>::fill_rest((T *)lat_[2], plane_, nullptr, 0, s_main_);
@@ -462,11 +464,29 @@ class Case final : public CaseBase {
   hipError_t enqueue_pair() {
     hipError_t e = hipSuccess;
     CaseView<T, R> v = view();
+    const bool two = s_grid_ != s_main_;  // the grid path on its own stream
+    auto fork = [&]() -> hipError_t {
+      hipError_t r = hipEventRecord(ev_fork_, s_main_);
+      return r == hipSuccess ? hipStreamWaitEvent(s_grid_, ev_fork_, 0) : r;
+    };
+    auto join = [&]() -> hipError_t {
+      hipError_t r = hipEventRecord(ev_join_, s_grid_);
+      return r == hipSuccess ? hipStreamWaitEvent(s_main_, ev_join_, 0) : r;
+    };
     if (has_grid_) Kernels<T, R>::lattice_from_grid(v, (const R *)gbuf_[gcur_], s_main_);
+    // step k's grid path reads only the lattice of t_k: it may run beside
+    // the two-step launch, which then reads a copy of the step counter (the
+    // grid path advances it)
+    if (has_grid_ && two) {
+      Kernels<T, R>::copy_step(dk_, dk_copy_, s_main_);
+      v.dkl = dk_copy_;
+      ENQ(fork());
+    }
     if (timing_ == 2) Kernels<T, R>::stream_collide2(v, s_main_, tev_[tslot_][8], tev_[tslot_][2]);
     else Kernels<T, R>::stream_collide2(v, s_main_);
     if (has_grid_) {
       ENQ(enqueue_grid_path(v));
+      if (two) ENQ(join());
       CaseView<T, R> w = view();
       w.A = (const T *)lat_[1];
       w.B = (T *)lat_[2];
@@ -475,8 +495,11 @@ class Case final : public CaseBase {
       w.wy0 = band_[2];
       w.wh = band_[3] - band_[2] + 1;
       Kernels<T, R>::lattice_from_grid(w, (const R *)gbuf_[gcur_], s_main_);
+      // step k+1's grid path and the band's second step both read t_{k+1}
+      if (two) ENQ(fork());
       Kernels<T, R>::stream_collide(w, s_main_, nullptr, nullptr, lattice_threads_, lattice_rows_, 0);
       ENQ(enqueue_grid_path(w));
+      if (two) ENQ(join());
     }
     if (timing_) ++tslot_;
     ENQ(hipGetLastError());
@@ -1309,6 +1332,7 @@ class Case final : public CaseBase {
       v.uw = uw_;
       v.params = params_;
       v.dk = dk_;
+      v.dkl = dk_;
       v.hist = hist_;
       v.counts = counts_;
       v.k2_x0 = k2_x0_;
@@ -1771,6 +1795,7 @@ class Case final : public CaseBase {
   int *flag_ = nullptr;
   unsigned long long *counts_ = nullptr;
   unsigned *done_ = nullptr;  // workgroups done in the fused refill-and-force launch (0 between launches)
+  int64_t *dk_copy_ = nullptr;  // the step counter as the two-step launch reads it beside a grid path
   int k2_x0_ = 0, k2_w_ = 1, k2_h_ = 1;
   int64_t k_ = 0;
   bool use_graphs_ = true;

@@ -71,6 +71,8 @@ struct CaseView {
   const R *uw;     // wall velocity table [max_steps][n_sub]
   const StepParams *params;  // [max_steps + 1]
   int64_t *dk;     // device step counter
+  const int64_t *dkl;  // the step the two-step lattice launch reads (dk, or a
+                       // copy taken before a grid path that runs beside it)
   double *hist;    // [max_steps][2]
   int *flag;       // non-finite force seen
   unsigned long long *counts;  // refill type 1 and type 2 counters
@@ -165,6 +167,8 @@ struct Kernels {
   static void grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
                               R *tape, R *wtape, const int *widx, int nwall, hipEvent_t start, hipEvent_t stop);
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
+  // *to = *from (one lane): a copy of the step counter
+  static void copy_step(const int64_t *from, int64_t *to, hipStream_t s);
   // refill and force (prescribed motion) in one launch, then the step
   // counter advances; done: a device counter that starts at 0 and is left at 0
   static void refill_force(const CaseView<T, R> &v, const R *fold, R *fnew, unsigned *done, hipStream_t s);

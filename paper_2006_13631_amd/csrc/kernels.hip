@@ -145,7 +145,7 @@ __global__ __launch_bounds__(512) void k_stream_collide2(CaseView<T, R> v, int t
   }
   int ix0 = 1, ix1 = 0, iy0 = 1, iy1 = 0;
   if (v.has_grid) {
-    const StepParams &P = v.params[*v.dk];
+    const StepParams &P = v.params[*v.dkl];
     ix0 = P.ix0, ix1 = P.ix1, iy0 = P.iy0, iy1 = P.iy1;
   }
 #pragma unroll
@@ -945,6 +945,10 @@ __device__ __forceinline__ void force_block(const R *__restrict__ f, const WallE
   }
 }
 
+__global__ void k_copy_step(const int64_t *from, int64_t *to) {
+  if (threadIdx.x == 0) *to = *from;
+}
+
 __global__ void k_advance_step(int64_t *dk) {
   if (threadIdx.x == 0) *dk = *dk + 1;
 }
@@ -1365,6 +1369,11 @@ void Kernels<T, R>::force(const CaseView<T, R> &v, const R *f, hipStream_t s, in
 template <class T, class R>
 void Kernels<T, R>::refill_force(const CaseView<T, R> &v, const R *fold, R *fnew, unsigned *done, hipStream_t s) {
   hipLaunchKernelGGL((k_refill_force<T, R>), dim3(1 + blocks(v.nnode, 256)), dim3(256), 0, s, v, fold, fnew, done);
+}
+
+template <class T, class R>
+void Kernels<T, R>::copy_step(const int64_t *from, int64_t *to, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_step, dim3(1), dim3(64), 0, s, from, to);
 }
 
 template <class T, class R>
