@@ -861,6 +861,12 @@ struct or_sim {
    * oscillating wall, periodic in x, in place of the lamina grid */
   int band;
   double band_U, band_omega;
+  /* a given triangulation (or_create_mesh) and its prescribed deformation
+   * (or_set_deformation): node p's local y is yref[p] + prof[p] beta_k */
+  int unstructured;
+  int deform;
+  double dB, dphi;
+  double *yref, *prof, *sx;
 };
 
 /* prescribed motion y(t) = A sin(omega t) (Sec. Problem statement), t = k */
@@ -912,6 +918,7 @@ static void free_sim(or_sim *s) {
   free(s->fA); free(s->fB); free(s->disc); or_mesh_free(s->m);
   free(s->fu); free(s->fu2); free(s->star_eq); free(s->star_neq);
   free(s->uwx); free(s->uwy); free(s->hist); free(s->mhist);
+  free(s->yref); free(s->prof); free(s->sx);
   free(s);
 }
 
@@ -1112,7 +1119,9 @@ int or_create_mesh(const or_config *c, int32_t nnode, const double *xy, const in
   m->T = body ? c->thickness : 0.0;
   m = mesh_finish(m); /* frees the mesh on failure (a triangle not counter-clockwise, ...) */
   if (!m) return OR_E_ARG;
-  return create_sim(c, NULL, NULL, m, out);
+  const int rc = create_sim(c, NULL, NULL, m, out);
+  if (rc == OR_OK) (*out)->unstructured = 1;
+  return rc;
 }
 
 /* A static grid band on a tangentially oscillating wall (see the header):
@@ -1305,6 +1314,86 @@ int or_probe_grid(const or_sim *s, double X, double Y, double out[12]) {
 }
 #endif
 
+/* Prescribed deformation (the extension to deformable bodies that Sec.
+ * Conclusions names; reading of this build): the lamina's centreline moves
+ * as Y(x, t) = A sin(omega t) + B sin(omega t + phi) s(x), with s = (2x/b)^2
+ * on the lamina, so it bends symmetrically about its centre. The grid
+ * follows: node p, at local (x, y) in the reference triangulation, sits at
+ * y + s(x) w(y) beta(t), beta = B sin(omega t + phi), in the frame that
+ * moves with A sin(omega t); s falls linearly from 1 at |x| = b/2 to 0 at
+ * the grid's side, w is 1 for |y| <= T/2 and falls linearly to 0 at its top
+ * and bottom, so the outer boundary moves rigidly and the lamina keeps its
+ * vertical thickness T. The grid is static during the sub-steps of a step
+ * (at beta_k); its matrices, wall edges and triangles are those of that
+ * configuration. Not differentiated (the complex-step build deforms with
+ * the real part of omega). */
+static double deform_s(const or_sim *s, double x) {
+  const double hb = 0.5 * s->b;
+  if (fabs(x) <= hb) return (x / hb) * (x / hb);
+  const double xr = x < 0.0 ? -s->ex0 : s->ex1;
+  const double r = 1.0 - (fabs(x) - hb) / (xr - hb);
+  return r > 0.0 ? r : 0.0;
+}
+
+static double deform_w(const or_sim *s, double y) {
+  const double ht = 0.5 * s->T;
+  if (fabs(y) <= ht) return 1.0;
+  const double r = 1.0 - (fabs(y) - ht) / (s->ey1 - ht);
+  return r > 0.0 ? r : 0.0;
+}
+
+static double deform_beta(const or_sim *s, int64_t k) {
+  return s->dB * sin(RE(s->omega) * (double)k + s->dphi);
+}
+
+/* the grid in the configuration beta: node positions, triangles, matrices
+ * and wall edges */
+static int set_geometry(or_sim *s, double beta) {
+  or_mesh *m = s->m;
+  for (int p = 0; p < m->nnode; ++p) m->y[p] = s->yref[p] + s->prof[p] * beta;
+  for (int t = 0; t < m->ntri; ++t)
+    for (int a = 0; a < 3; ++a) m->txy[6 * t + 2 * a + 1] = m->y[m->tri[3 * t + a]];
+  free(m->nk); free(m->nbr); free(m->S); free(m->C); free(m->V);
+  free(m->we); free(m->wn); free(m->wl);
+  m->nk = NULL; m->nbr = NULL; m->S = NULL; m->C = NULL; m->V = NULL;
+  m->we = NULL; m->wn = NULL; m->wl = NULL;
+  return assemble(m);
+}
+
+int or_set_deformation(or_sim *s, double B, double phi) {
+  if (!s || !s->unstructured || s->k != 0 || s->fsi || !(s->b > 0.0) || !(fabs(B) < 1.0)) return OR_E_ARG;
+  const double ht = 0.5 * s->T;
+  if (!(fabs(B) < s->ey1 - ht)) return OR_E_ARG;
+  /* the deflected lamina stays inside the fictitious rectangle, and no node
+   * moves a lattice unit per step */
+  if (!(ht + fabs(B) + 1.0 <= s->ey1 - s->margin - 1.0)) return OR_E_ARG;
+  if (!(fabs(RE(s->A * s->omega)) + fabs(B * RE(s->omega)) < 1.0)) return OR_E_ARG;
+  or_mesh *m = s->m;
+  const int N = m->nnode;
+  s->yref = malloc((size_t)N * sizeof(double));
+  s->prof = malloc((size_t)N * sizeof(double));
+  s->sx = malloc((size_t)N * sizeof(double));
+  if (!s->yref || !s->prof || !s->sx) return OR_E_NOMEM;
+  for (int p = 0; p < N; ++p) {
+    s->yref[p] = m->y[p];
+    s->sx[p] = deform_s(s, m->x[p]);
+    s->prof[p] = s->sx[p] * deform_w(s, m->y[p]);
+  }
+  /* a triangle's area is linear in beta: positive at both extremes, positive
+   * throughout */
+  for (int e = -1; e <= 1; e += 2)
+    for (int t = 0; t < m->ntri; ++t) {
+      double y[3];
+      const double *q = &m->txy[6 * t];
+      for (int a = 0; a < 3; ++a) y[a] = s->yref[m->tri[3 * t + a]] + s->prof[m->tri[3 * t + a]] * e * B;
+      if (!((q[2] - q[0]) * (y[2] - y[0]) - (q[4] - q[0]) * (y[1] - y[0]) > 0.0)) return OR_E_ARG;
+    }
+  s->dB = B;
+  s->dphi = phi;
+  s->deform = 1;
+  return set_geometry(s, deform_beta(s, 0));
+}
+
 /* Refill after the move from y_k to y_k1 (Sec. Refill procedure). */
 static void refill(or_sim *s, real yk, real yk1) {
   const or_mesh *m = s->m;
@@ -1319,8 +1408,12 @@ static void refill(or_sim *s, real yk, real yk1) {
       for (int i = 0; i < 9; ++i) out[i] = s->fu[(size_t)i * N + p];
     } else {
       const double X = s->xc + m->x[p];
-      const real Ynew = (s->yc + yk1) + m->y[p];
+      /* deformation: the node's own new local y */
+      const double ynew = s->deform ? s->yref[p] + s->prof[p] * deform_beta(s, s->k + 1) : m->y[p];
+      const real Ynew = (s->yc + yk1) + ynew;
       const real py = Ynew - (s->yc + yk);
+      /* the old lamina's centreline under the node */
+      const double yb = s->deform ? deform_beta(s, s->k) * deform_s(s, X - s->xc) : 0.0;
       double lam0[3];
       real lam[3];
       const int t = or_mesh_locate(m, X - s->xc, RE(py), lam0);
@@ -1335,7 +1428,7 @@ static void refill(or_sim *s, real yk, real yk1) {
           for (int a = 0; a < 3; ++a) out[i] += lam[a] * s->fu[(size_t)i * N + m->tri[3 * t + a]];
         }
         s->nt3++;
-      } else if (s->body_b > 0.0 && fabs(X - s->xc) < 0.5 * s->body_b && fabs(RE(py)) < 0.5 * s->T) {
+      } else if (s->body_b > 0.0 && fabs(X - s->xc) < 0.5 * s->body_b && fabs(RE(py) - yb) < 0.5 * s->T) {
         /* type 2: inside the old body, keep the previous values */
         for (int i = 0; i < 9; ++i) out[i] = s->fu[(size_t)i * N + p];
         s->nt2++;
@@ -1371,6 +1464,7 @@ int or_step(or_sim *s, int64_t nsteps) {
       const real yprev = s->fsi ? s->y_prev : ((k > 0) ? motion_y(s, k - 1) : yk);
       real yk1 = s->fsi ? 0.0 : motion_y(s, k + 1);
       const rect_t R = rect_at(s, RE(yk)), Rp = rect_at(s, RE(yprev));
+      if (s->deform && set_geometry(s, deform_beta(s, k)) != OR_OK) return OR_E_STATE;
       /* 1. lattice interpolation nodes, plus nodes the moving fictitious line
        *    has just uncovered (Sec. Refill procedure, last paragraphs), get
        *    Eq.(postcollision2_s) from the grid at y_k */
@@ -1407,6 +1501,9 @@ int or_step(or_sim *s, int64_t nsteps) {
           s->uwx[p] = 0.0;
           s->uwy[p] = uw;
         }
+        if (s->deform) /* the wall's own bending velocity */
+          for (int p = 0; p < N; ++p)
+            s->uwy[p] += s->dB * RE(s->omega) * cos(RE(s->omega) * t + s->dphi) * s->sx[p];
         if (s->band) /* the band's wall moves tangentially */
           for (int p = 0; p < N; ++p) {
             s->uwx[p] = s->band_U * cos(s->band_omega * t);

@@ -153,6 +153,11 @@ int or_create_graded(const or_config *cfg, const double *X, const double *Y, or_
  * |x| < b/2, |y| < thickness/2 (cfg->nux, nuy, h_u unused). */
 int or_create_mesh(const or_config *cfg, int32_t nnode, const double *xy, const int32_t *type, int32_t ntri,
                    const int32_t *tri, or_sim **out);
+/* a prescribed deformation of a case on a given triangulation (before the
+ * first step): the lamina bends as Y(x, t) = A sin(omega t) +
+ * B sin(omega t + phi) (2x/b)^2 and the grid follows it (see
+ * hlbm_oracle.c); |B| < 1 */
+int or_set_deformation(or_sim *s, double B, double phi);
 void or_destroy(or_sim *s);
 int or_step(or_sim *s, int64_t nsteps);
 int or_info_get(const or_sim *s, or_info *out);

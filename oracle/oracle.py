@@ -126,6 +126,7 @@ def lib():
         L.or_set_motion.argtypes = [vp] + [C.c_double] * 6
         L.or_create_graded.argtypes = [C.POINTER(Config), _D, _D, C.POINTER(vp)]
         L.or_create_mesh.argtypes = [C.POINTER(Config), C.c_int32, _D, _I, C.c_int32, _I, C.POINTER(vp)]
+        L.or_set_deformation.argtypes = [vp, C.c_double, C.c_double]
         L.or_mesh_lamina_coords.argtypes = [C.c_int32, C.c_int32, _D, _D, C.c_double]
         L.or_mesh_lamina_coords.restype = vp
         L.or_motion_history.argtypes = [vp, _D, C.c_int64]
@@ -362,6 +363,13 @@ class Sim:
         out = np.zeros((max(n, 1), 2))
         lib().or_history(self.ptr, out, n)
         return out[:n]
+
+    def set_deformation(self, B, phi=0.0):
+        """Prescribed bending B sin(omega t + phi) (2x/b)^2 of the lamina on a
+        given triangulation (before the first step)."""
+        rc = lib().or_set_deformation(self.ptr, B, phi)
+        if rc != 0:
+            raise ValueError(f"or_set_deformation rejected the arguments (code {rc})")
 
     def set_motion(self, mass, stiffness, damping=0.0, y0=0.0, v0=0.0, y_max=1.0):
         """Two-way coupled motion M y'' + C y' + K y = F_y (before the first step)."""

@@ -171,25 +171,25 @@ int main(void) {
       or_destroy(s);
     }
   }
-  /* a given triangulation: a 13 x 10 node grid with jittered interior
+  /* a given triangulation: a 13 x 12 node grid with jittered interior
    * nodes, cells split along alternating diagonals, a lamina hole */
   {
-    enum { NX = 13, NY = 10 };
+    enum { NX = 13, NY = 12 };
     double xy[2 * NX * NY];
     int32_t ty[NX * NY], tri[3 * 2 * (NX - 1) * (NY - 1)];
     for (int j = 0; j < NY; ++j)
       for (int i = 0; i < NX; ++i) {
         const int p = j * NX + i;
         const int outer = i == 0 || j == 0 || i == NX - 1 || j == NY - 1;
-        const int wall = (j == 4 || j == 5) && i >= 4 && i <= 8;
+        const int wall = (j == NY / 2 - 1 || j == NY / 2) && i >= 4 && i <= 8;
         xy[2 * p] = (i - 6) + (outer || wall ? 0.0 : 0.13 * ((i * 7 + j * 3) % 5 - 2) / 2.0);
-        xy[2 * p + 1] = (j - 4.5) + (outer || wall ? 0.0 : 0.11 * ((i * 5 + j * 11) % 5 - 2) / 2.0);
+        xy[2 * p + 1] = (j - 0.5 * (NY - 1)) + (outer || wall ? 0.0 : 0.11 * ((i * 5 + j * 11) % 5 - 2) / 2.0);
         ty[p] = wall ? OR_NODE_WALL : outer ? OR_NODE_INTERFACE : OR_NODE_INTERIOR;
       }
     int nt = 0;
     for (int cj = 0; cj + 1 < NY; ++cj)
       for (int ci = 0; ci + 1 < NX; ++ci) {
-        if (cj == 4 && ci >= 4 && ci < 8) continue; /* the lamina, x in [-2, 2], y in [-0.5, 0.5] */
+        if (cj == NY / 2 - 1 && ci >= 4 && ci < 8) continue; /* the lamina, x in [-2, 2], y in [-0.5, 0.5] */
         const int n00 = cj * NX + ci, n10 = n00 + 1, n01 = n00 + NX, n11 = n01 + 1;
         if ((ci + cj) % 2) {
           const int t[6] = {n00, n10, n11, n00, n11, n01};
@@ -204,6 +204,15 @@ int main(void) {
     or_sim *s = NULL;
     EXPECT(or_create_mesh(&c, NX * NY, xy, ty, nt, tri, &s) == OR_OK);
     if (s) {
+      EXPECT(or_step(s, 6) == OR_OK);
+      EXPECT(or_set_deformation(s, 0.2, 0.0) == OR_E_ARG); /* after the first step */
+      or_destroy(s);
+    }
+    /* the same grid bending with the lamina */
+    EXPECT(or_create_mesh(&c, NX * NY, xy, ty, nt, tri, &s) == OR_OK);
+    if (s) {
+      EXPECT(or_set_deformation(s, 1.5, 0.0) == OR_E_ARG);
+      EXPECT(or_set_deformation(s, 0.25, 0.4) == OR_OK);
       EXPECT(or_step(s, 6) == OR_OK);
       or_destroy(s);
     }

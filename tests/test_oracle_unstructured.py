@@ -167,3 +167,116 @@ def test_unstructured_uniform_flow_through_moving_grid(oracle):
     assert inf.n_type1 > 0 and inf.n_type3 > 0 and abs(inf.y) > 0.3
     assert np.abs(s.lattice() - e[:, None, None]).max() < 1e-13
     assert np.abs(s.grid() - e[:, None]).max() < 1e-13
+
+
+# ---- prescribed deformation (or_set_deformation) ------------------------------
+
+def _feq(oracle, rho, ux, uy):
+    cx, cy, w = oracle.d2q9()
+    cu = cx[:, None] * ux + cy[:, None] * uy
+    return w[:, None] * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy))
+
+
+def test_zero_deformation_is_the_rigid_case(oracle):
+    mesh = _mesh()
+    a, b = _sim(oracle, mesh, steps=40), _sim(oracle, mesh, steps=40)
+    b.set_deformation(0.0, 0.7)
+    a.step(40)
+    b.step(40)
+    for x, y in ((a.grid(), b.grid()), (a.lattice(), b.lattice()), (a.history(), b.history())):
+        assert np.array_equal(x, y)
+
+
+def test_deformed_configuration_matrices(oracle):
+    """After steps with the grid bending, the matrices of its current
+    configuration still sum as they must and are exact on linear fields."""
+    s = _sim(oracle, _mesh(), steps=25)
+    s.set_deformation(0.6, 0.4)
+    s.step(25)
+    m = s.mesh()
+    nbr, S, Cm, V = m.stencil()
+    x, y, _ = m.nodes()
+    assert np.abs(y - _mesh()[0][:, 1]).max() > 0.1  # the grid is bent
+    assert np.abs(Cm.sum(1) - 1).max() < 1e-13 and np.abs(S.sum(2)).max() < 1e-12
+    assert abs(V.sum() - (36 * 13 - 16)) < 1e-10
+    cx, cy, _ = oracle.d2q9()
+    g = np.array([0.3, -0.8, 0.5])
+    F = np.where(nbr >= 0, (g[0] + g[1] * x + g[2] * y)[np.maximum(nbr, 0)], 0.0)
+    for i in range(9):
+        assert np.abs((S[:, i, :] * F).sum(1) + cx[i] * g[1] + cy[i] * g[2]).max() < 1e-12
+
+
+def test_uniform_flow_through_deforming_grid(oracle):
+    cx, cy, w = oracle.d2q9()
+    e = _feq(oracle, np.ones(1), np.array([0.04]), np.array([-0.02]))[:, 0]
+    mesh = lamina_triangulation(23.0, 15.0, b=0.0, h_wall=1.0, h_far=1.0, seed=6)
+    s = oracle.Sim(64, 48, b=8.0, thickness=1.0, tau=0.8, kc=1.0, beta=20.0, n_sub=0,
+                   bc=oracle.BC_PERIODIC, flags=oracle.FLAG_NO_BODY, max_steps=60, mesh=mesh)
+    s.set_deformation(0.7, 1.1)
+    s.set_lattice(np.broadcast_to(e[:, None, None], (9, 48, 64)).copy())
+    s.set_grid(np.broadcast_to(e[:, None], (9, s.nnode)).copy())
+    s.step(60)
+    assert np.abs(s.lattice() - e[:, None, None]).max() < 1e-13
+    assert np.abs(s.grid() - e[:, None]).max() < 1e-13
+
+
+def _couette_deforming(oracle, gamma, tau, mesh, B, flags=0, steps=70):
+    """Plane Couette flow through a bending Delaunay grid (no body, the same
+    set-up as the interface pin). Returns the lattice's discretization nodes
+    and their expected first-order state, and the grid's non-equilibrium
+    part f - f^eq(its own moments) with its expected value -3 tau_u w_i c_ix
+    c_iy gamma (independent of where the bent grid's nodes sit)."""
+    nx, ny = 64, 48
+    cx, cy, w = oracle.d2q9()
+    s = oracle.Sim(nx, ny, 0, 0, 1.0, 8.0, 1.0, tau, 1.0, 20.0, 0, oracle.BC_PERIODIC_X_WALLS_Y,
+                   oracle.FLAG_NO_BODY | flags, steps, mesh=mesh)
+    s.set_deformation(B, 0.3)
+    yc = 0.5 * (ny - 1)
+    s.set_walls(-gamma * ny / 2, gamma * ny / 2)
+    Y, _ = np.mgrid[0:ny, 0:nx].astype(float)
+    shear = (w * cx * cy) * gamma
+    lat = (_feq(oracle, np.ones(Y.size), gamma * (Y.ravel() - yc), 0 * Y.ravel()).reshape(9, ny, nx)
+           - 3 * (tau - 1) * shear[:, None, None])
+    s.set_lattice(lat)
+    _, y, _ = s.mesh().nodes()  # the configuration of step 0
+    s.set_grid(_feq(oracle, np.ones(len(y)), gamma * y, 0 * y) - 3 * (tau - 0.5) * shear[:, None])
+    s.step(steps)
+    disc = s.status(steps) == 0
+    g = s.grid()
+    r = g.sum(0)
+    ux, uy = (cx[:, None] * g).sum(0) / r, (cy[:, None] * g).sum(0) / r
+    neq = g - _feq(oracle, r, ux, uy)
+    return s.lattice()[:, disc], lat[:, disc], neq, -3 * (tau - 0.5) * shear[:, None] + 0 * neq
+
+
+def _couette_deforming_error(oracle, gamma, tau, mesh, B, flags=0):
+    p = _couette_deforming(oracle, gamma, tau, mesh, B, flags)
+    m = _couette_deforming(oracle, -gamma, tau, mesh, B, flags)
+    return max(np.max(np.abs((p[i] - m[i]) / 2 - (p[i + 1] - m[i + 1]) / 2)) / gamma for i in (0, 2))
+
+
+def test_couette_through_deforming_unstructured_grid(oracle):
+    """The first-order Couette state crosses an oscillating and bending
+    Delaunay grid (matrices rebuilt every step, refills located in the old
+    configuration) to third order in gamma; the planted mistakes fail."""
+    mesh = lamina_triangulation(23.0, 15.0, b=0.0, h_wall=1.0, h_far=1.0, seed=5)
+    e5 = _couette_deforming_error(oracle, 1e-5, 0.8, mesh, 0.8)
+    e4 = _couette_deforming_error(oracle, 1e-4, 0.8, mesh, 0.8)
+    assert e5 < 1e-8, e5
+    assert 50 < e4 / e5 < 200, (e4, e5)
+    for plant in (oracle.PLANT_S_FACTOR, oracle.PLANT_NO_KNEQ, oracle.PLANT_BARY):
+        assert _couette_deforming_error(oracle, 1e-5, 0.8, mesh, 0.8, plant) > 1e-2, plant
+
+
+def test_deformation_rejects_bad_input(oracle):
+    s = _sim(oracle, _mesh(), steps=4)
+    for B in (1.0, -1.5):
+        with pytest.raises(ValueError):
+            s.set_deformation(B)
+    s.step(1)
+    with pytest.raises(ValueError):  # after the first step
+        s.set_deformation(0.3)
+    split = oracle.Sim(96, 48, nux=37, nuy=14, h_u=1.0, b=16.0, thickness=1.0, tau=0.7, kc=0.6, beta=40.0,
+                       n_sub=8, max_steps=4)
+    with pytest.raises(ValueError):  # split-quad grids do not deform
+        split.set_deformation(0.3)
