@@ -277,6 +277,33 @@ int hlbm_create_mesh(const hlbm_config *cfg, int32_t nnode, const double *xy,
                      const int32_t *node_type, int32_t ntri, const int32_t *tri,
                      hlbm_t **out);
 
+/* A bending lamina on a given triangulation (the extension to deformable
+ * bodies that Sec. Conclusions names; the paper's lamina is rigid). The
+ * centreline moves as A sin(omega t) + B sin(omega t + phi) (2x/b)^2 for
+ * |x| <= b/2, and the grid follows: node p, at local (x_p, y_p) in the
+ * triangulation given to hlbm_create_mesh, sits at y_p + s(x_p) w(y_p)
+ * beta_k during step k, beta_k = B sin(omega k + phi), where s is
+ * (2x/b)^2 on the lamina and falls linearly to 0 at the grid's left and
+ * right sides, and w is 1 for |y| <= thickness/2 and falls linearly to 0
+ * at its top and bottom, so the outer boundary moves rigidly and the
+ * lamina keeps its thickness. Every step first rebuilds the grid's
+ * finite-volume matrices, triangles and wall edges for the configuration
+ * beta_k (one launch); the sub-steps impose the wall velocity
+ * A omega cos(omega t) + B omega cos(omega t + phi) s(x); the refill
+ * locates a node's position of t_{k+1} in the grid of t_k and keeps f
+ * (type 2) inside the bent lamina |y - beta_k (2x/b)^2| < thickness/2;
+ * the force integrates over the bent wall edges. hlbm_stencil returns the
+ * weights of the last configuration (that of t_0 before the first step).
+ * Call before the first step of a single case from hlbm_create_mesh with
+ * the lamina. Needs |B| < 1, the bent lamina (thickness/2 + |B| + 1) at
+ * least one lattice unit inside the fictitious rectangle, |A omega| +
+ * |B omega| < 1, and every triangle keeping a positive area at beta =
+ * +-B. Errors: HLBM_E_UNSUPPORTED (not such a case), HLBM_E_STATE (steps
+ * taken, coupled motion, no lamina), HLBM_E_ARG (B or phi out of range,
+ * hlbm_last_error says which), HLBM_E_HIP. A bending case takes no
+ * coupled motion. */
+int hlbm_set_deformation(hlbm_t *h, double B, double phi);
+
 /* ---- two-way coupled motion ------------------------------------------- */
 /* The paper prescribes the lamina's motion (Sec. Problem statement: known a
  * priori). Instead, the lamina may be mounted on a spring and damper and

@@ -143,6 +143,12 @@ class CaseBase {
     err = "coupled motion applies to single cases";
     return HLBM_E_UNSUPPORTED;
   }
+  virtual int set_deformation(double B, double phi) {
+    (void)B;
+    (void)phi;
+    err = "deformation applies to single cases on a given triangulation";
+    return HLBM_E_UNSUPPORTED;
+  }
   virtual int tune(int trial_steps, hlbm_tuning *t) {
     (void)trial_steps;
     (void)t;
@@ -374,6 +380,8 @@ class Case final : public CaseBase {
     CaseView<T, R> v = view();
     if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][0], s_main_));
     if (has_grid_) {
+      // 0. a bending grid takes the configuration of t_k
+      if (deform_) Kernels<T, R>::mesh_deform(deform_view(), s_main_);
       // 1. lattice interpolation nodes from the grid at t_k, Eq.(postcollision2_s)
       Kernels<T, R>::lattice_from_grid(v, (const R *)gbuf_[gcur_], s_main_);
       if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][1], s_main_));
@@ -473,7 +481,10 @@ class Case final : public CaseBase {
       hipError_t r = hipEventRecord(ev_join_, s_grid_);
       return r == hipSuccess ? hipStreamWaitEvent(s_main_, ev_join_, 0) : r;
     };
-    if (has_grid_) Kernels<T, R>::lattice_from_grid(v, (const R *)gbuf_[gcur_], s_main_);
+    if (has_grid_) {
+      if (deform_) Kernels<T, R>::mesh_deform(deform_view(), s_main_);
+      Kernels<T, R>::lattice_from_grid(v, (const R *)gbuf_[gcur_], s_main_);
+    }
     // step k's grid path reads only the lattice of t_k: it may run beside
     // the two-step launch, which then reads a copy of the step counter (the
     // grid path advances it)
@@ -494,6 +505,8 @@ class Case final : public CaseBase {
       w.ww = band_[1] - band_[0] + 1;
       w.wy0 = band_[2];
       w.wh = band_[3] - band_[2] + 1;
+      // (step k's refill and force have read the configuration of t_k)
+      if (deform_) Kernels<T, R>::mesh_deform(deform_view(), s_main_);
       Kernels<T, R>::lattice_from_grid(w, (const R *)gbuf_[gcur_], s_main_);
       // step k+1's grid path and the band's second step both read t_{k+1}
       if (two) ENQ(fork());
@@ -805,15 +818,32 @@ class Case final : public CaseBase {
       int need = 0;
       for (int p = 0; p < grid_.nnode; ++p) need = std::max(need, grid_.row[p + 1] - grid_.row[p]);
       if (kmax < need) return fail(HLBM_E_ARG, "kmax smaller than the largest stencil");
+      const std::vector<double> *Cw = &grid_.C, *Gxw = &grid_.Gx, *Gyw = &grid_.Gy;
+      std::vector<double> dC, dGx, dGy;
+      if (deform_) {  // a bending grid: the weights of the current configuration
+        HIPCHK(hipStreamSynchronize(s_main_));
+        if (s_grid_ != s_main_) HIPCHK(hipStreamSynchronize(s_grid_));
+        const size_t ne = grid_.col.size();
+        std::vector<R> buf(ne);
+        std::vector<double> *dst[3] = {&dC, &dGx, &dGy};
+        const R *src[3] = {m_C_, m_Gx_, m_Gy_};
+        for (int a = 0; a < 3; ++a) {
+          HIPCHK(hipMemcpy(buf.data(), src[a], ne * sizeof(R), hipMemcpyDeviceToHost));
+          dst[a]->assign(buf.begin(), buf.end());
+        }
+        Cw = &dC;
+        Gxw = &dGx;
+        Gyw = &dGy;
+      }
       for (int p = 0; p < grid_.nnode; ++p) {
         const int e0 = grid_.row[p], k = grid_.row[p + 1] - e0;
         for (int u = 0; u < kmax; ++u) {
           const bool in = u < k;
           if (nbr) nbr[(size_t)p * kmax + u] = in ? grid_.col[e0 + u] : -1;
-          if (C) C[(size_t)p * kmax + u] = in ? grid_.C[e0 + u] : 0.0;
+          if (C) C[(size_t)p * kmax + u] = in ? (*Cw)[e0 + u] : 0.0;
           if (S)
             for (int r = 0; r < 9; ++r)
-              S[((size_t)p * 9 + r) * kmax + u] = in ? cx[r] * grid_.Gx[e0 + u] + cy[r] * grid_.Gy[e0 + u] : 0.0;
+              S[((size_t)p * 9 + r) * kmax + u] = in ? cx[r] * (*Gxw)[e0 + u] + cy[r] * (*Gyw)[e0 + u] : 0.0;
         }
       }
       return HLBM_OK;
@@ -872,6 +902,7 @@ class Case final : public CaseBase {
     if (!m) return fail(HLBM_E_ARG, "null argument");
     if (k_ != 0) return fail(HLBM_E_STATE, "coupled motion must be set before the first step");
     if (!has_grid_ || !body_) return fail(HLBM_E_STATE, "coupled motion needs a grid with the lamina");
+    if (deform_) return fail(HLBM_E_STATE, "a bending grid takes no coupled motion");
     if (!(m->mass > 0.0) || !(m->stiffness >= 0.0) || !(m->damping >= 0.0) || !(m->y_max > 0.0) ||
         !(std::fabs(m->y0) <= m->y_max) || !(std::fabs(m->v0) < 1.0))
       return fail(HLBM_E_ARG, "invalid coupled-motion parameters");
@@ -901,6 +932,123 @@ class Case final : public CaseBase {
     drop_graphs();
     return HLBM_OK;
   }
+
+  // Prescribed bending of the lamina on a given triangulation (the
+  // extension to deformable bodies of Sec. Conclusions). The centreline
+  // moves as A sin(omega t) + B sin(omega t + phi) s(x) with s = (2x/b)^2
+  // on the lamina; node p of the reference grid sits at local y = y_p +
+  // s(x_p) w(y_p) beta_k during step k, beta_k = B sin(omega k + phi),
+  // where s falls linearly to 0 from the lamina's ends to the grid's sides
+  // and w is 1 across the lamina's thickness and falls linearly to 0 at the
+  // grid's top and bottom: the outer boundary moves rigidly, the lamina
+  // keeps its thickness. Wall nodes move with the extra velocity
+  // B omega cos(omega t + phi) s(x). Each step starts with the geometry
+  // update (k_mesh_deform); the refill locates a node's new position in the
+  // grid of t_k and takes type 2 inside the bent lamina of t_k.
+  static double bend_s(double x, double hb, double ex0, double ex1) {
+    if (std::fabs(x) <= hb) return (x / hb) * (x / hb);
+    const double side = x < 0.0 ? -ex0 : ex1;
+    const double r = 1.0 - (std::fabs(x) - hb) / (side - hb);
+    return r > 0.0 ? r : 0.0;
+  }
+  static double bend_w(double y, double ht, double ey1) {
+    if (std::fabs(y) <= ht) return 1.0;
+    const double r = 1.0 - (std::fabs(y) - ht) / (ey1 - ht);
+    return r > 0.0 ? r : 0.0;
+  }
+
+  MeshDeformView<R> deform_view() const {
+    MeshDeformView<R> g{};
+    g.nnode = grid_.nnode;
+    g.ntri = grid_.ntri;
+    g.nwall = (int)grid_.wall.size();
+    g.x = m_x_;
+    g.yref = m_yref_;
+    g.prof = m_prof_;
+    g.tri = m_tri_;
+    g.row = m_row_;
+    g.trow = m_trow_;
+    g.tlist = m_tlist_;
+    g.tslot = m_tslot_;
+    g.wall_o = m_wo_;
+    g.C = m_C_;
+    g.Gx = m_Gx_;
+    g.Gy = m_Gy_;
+    g.txy = m_txy_;
+    g.wall = wall_;
+    g.params = params_;
+    g.dk = dk_;
+    return g;
+  }
+
+  int set_deformation(double B, double phi) override {
+    if (!has_grid_ || !grid_.mesh) return fail(HLBM_E_UNSUPPORTED, "deformation applies to cases on a given triangulation");
+    if (k_ != 0) return fail(HLBM_E_STATE, "the deformation must be set before the first step");
+    if (fsi_) return fail(HLBM_E_STATE, "a coupled case does not bend");
+    if (!body_) return fail(HLBM_E_STATE, "deformation needs the lamina");
+    if (!std::isfinite(B) || !std::isfinite(phi) || !(std::fabs(B) < 1.0))
+      return fail(HLBM_E_ARG, "|B| must be finite and below one lattice unit");
+    const double hb = 0.5 * grid_.b, ht = 0.5 * grid_.T;
+    // the bent lamina stays inside the fictitious rectangle with its donors
+    if (!(ht + std::fabs(B) + 1.0 <= gey1_ - kMargin - 1.0))
+      return fail(HLBM_E_ARG, "the bent lamina leaves the fictitious rectangle");
+    if (!(std::fabs(d_.A * d_.omega) + std::fabs(B * d_.omega) < 1.0))
+      return fail(HLBM_E_ARG, "lamina speed must stay below one lattice unit per step");
+    const int N = grid_.nnode;
+    std::vector<double> prof(N);
+    std::vector<R> sx(N);
+    for (int p = 0; p < N; ++p) {
+      const double sp = bend_s(grid_.x[p], hb, grid_.ex0, grid_.ex1);
+      sx[p] = (R)sp;
+      prof[p] = sp * bend_w(grid_.y[p], ht, grid_.ey1);
+    }
+    // a triangle's area is linear in beta: positive at beta = +-B, positive
+    // for every configuration
+    for (int sgn = -1; sgn <= 1; sgn += 2)
+      for (int t = 0; t < grid_.ntri; ++t) {
+        double x[3], y[3];
+        for (int a = 0; a < 3; ++a) {
+          const int n = grid_.tri[3 * t + a];
+          x[a] = grid_.x[n];
+          y[a] = grid_.y[n] + prof[n] * (sgn * B);
+        }
+        if (!((x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]) > 0.0))
+          return fail(HLBM_E_ARG, "the bent grid folds over (a triangle loses its area)");
+      }
+    HIPCHK(hipStreamSynchronize(s_main_));
+    if (!m_yref_) {
+      HIPCHK(upload(&m_yref_, grid_.y.data(), N * sizeof(double)));
+      HIPCHK(alloc(&m_prof_, N * sizeof(double)));
+      HIPCHK(alloc(&m_sx_, N * sizeof(R)));
+      HIPCHK(upload(&m_trow_, grid_.trow.data(), grid_.trow.size() * sizeof(int)));
+      HIPCHK(upload(&m_tlist_, grid_.tlist.data(), grid_.tlist.size() * sizeof(int)));
+      HIPCHK(upload(&m_tslot_, grid_.tslot.data(), grid_.tslot.size() * sizeof(int)));
+      HIPCHK(upload(&m_wo_, grid_.wall_o.data(), std::max<size_t>(1, grid_.wall_o.size()) * sizeof(int)));
+      HIPCHK(alloc(&uwb_, std::max<size_t>(1, uw_count()) * sizeof(R)));
+    }
+    HIPCHK(hipMemcpy(m_prof_, prof.data(), N * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(m_sx_, sx.data(), N * sizeof(R), hipMemcpyHostToDevice));
+    dB_ = B;
+    dphi_ = phi;
+    deform_ = true;
+    const int64_t cap = std::max<int64_t>(cfg_.max_steps, 1);
+    for (int64_t k = 0; k <= cap; ++k) P_host_[k] = params_at(k);
+    HIPCHK(hipMemcpy(params_, P_host_.data(), P_host_.size() * sizeof(StepParams), hipMemcpyHostToDevice));
+    std::vector<R> uwb(uw_count());
+    for (int64_t k = 0; k < cap; ++k)
+      for (int m = 0; m < d_.n; ++m) {
+        const double t = (double)k + (double)(m + 1) / (double)d_.n;
+        uwb[(size_t)k * d_.n + m] = (R)(dB_ * d_.omega * std::cos(d_.omega * t + dphi_));
+      }
+    HIPCHK(hipMemcpy(uwb_, uwb.data(), uwb.size() * sizeof(R), hipMemcpyHostToDevice));
+    // the configuration of t_0 (stencils and state reads before the first step)
+    Kernels<T, R>::mesh_deform(deform_view(), s_main_);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s_main_));
+    drop_graphs();
+    return HLBM_OK;
+  }
+  size_t uw_count() const { return (size_t)std::max<int64_t>(cfg_.max_steps, 1) * d_.n; }
 
   // Capture the graphs of every buffer arrangement the steps will pass
   // through from the current one (the arrangements form a cycle), so that
@@ -1255,6 +1403,8 @@ class Case final : public CaseBase {
     P.ybase1 = d_.yc + P.y1;
     rect(P.y, P.ix0, P.ix1, P.iy0, P.iy1);
     rect(yp, P.pix0, P.pix1, P.piy0, P.piy1);
+    P.beta = deform_ ? dB_ * std::sin(d_.omega * (double)k + dphi_) : 0.0;
+    P.beta1 = deform_ ? dB_ * std::sin(d_.omega * (double)(k + 1) + dphi_) : 0.0;
     return P;
   }
 
@@ -1323,6 +1473,13 @@ class Case final : public CaseBase {
         v.m_y = m_y_;
         v.m_type = m_type_;
         v.mg = MeshGeom{m_tri_, m_txy_, m_bstart_, m_blist_, grid_.bx0, grid_.by0, grid_.bnx, grid_.bny};
+        if (deform_) {
+          v.deform = 1;
+          v.m_yref = m_yref_;
+          v.m_prof = m_prof_;
+          v.m_sx = m_sx_;
+          v.uwb = uwb_;
+        }
       }
       v.wall = wall_;
       v.star_f = star_f_;
@@ -1788,6 +1945,12 @@ class Case final : public CaseBase {
   R *m_C_ = nullptr, *m_Gx_ = nullptr, *m_Gy_ = nullptr;
   double *m_x_ = nullptr, *m_y_ = nullptr, *m_txy_ = nullptr;
   WallEdge *wall_ = nullptr;
+  // prescribed bending of an unstructured grid (hlbm_set_deformation)
+  bool deform_ = false;
+  double dB_ = 0.0, dphi_ = 0.0;
+  double *m_yref_ = nullptr, *m_prof_ = nullptr;
+  R *m_sx_ = nullptr, *uwb_ = nullptr;
+  int *m_trow_ = nullptr, *m_tlist_ = nullptr, *m_tslot_ = nullptr, *m_wo_ = nullptr;
   StepParams *params_ = nullptr;
   R *uw_ = nullptr;
   double *hist_ = nullptr;
@@ -3005,6 +3168,11 @@ int hlbm_create_graded(const hlbm_config *cfg, const double *x_nodes, const doub
 int hlbm_set_motion(hlbm_t *h, int32_t case_id, const hlbm_motion *m) {
   if (!h) return HLBM_E_ARG;
   return h->c->set_motion(case_id, m);
+}
+
+int hlbm_set_deformation(hlbm_t *h, double B, double phi) {
+  if (!h) return HLBM_E_ARG;
+  return h->c->set_deformation(B, phi);
 }
 
 int hlbm_step(hlbm_t *h, int64_t nsteps) {

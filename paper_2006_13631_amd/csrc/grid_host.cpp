@@ -268,6 +268,7 @@ bool build_mesh(int nnode, const double *xy, const int *type, int ntri, const in
       v.push_back(o);
     }
   g->wall.clear();
+  g->wall_o.clear();
   const double tol = 1e-12 * std::max({g->ex1 - g->ex0, g->ey1 - g->ey0, 1.0});
   auto on_box = [&](int p) {
     return std::fabs(g->x[p] - g->ex0) <= tol || std::fabs(g->x[p] - g->ex1) <= tol ||
@@ -295,6 +296,7 @@ bool build_mesh(int nnode, const double *xy, const int *type, int ntri, const in
         ny = -ny;
       }
       g->wall.push_back({a, c, nx, ny, len});
+      g->wall_o.push_back(o);
     }
   }
   g->iface.clear();
@@ -317,6 +319,9 @@ bool build_mesh(int nnode, const double *xy, const int *type, int ntri, const in
   g->C.clear();
   g->Gx.clear();
   g->Gy.clear();
+  g->trow.assign(nnode + 1, 0);
+  g->tlist.clear();
+  g->tslot.clear();
   for (int p = 0; p < nnode; ++p) {
     std::vector<int> nb;
     for (int t : around[p])
@@ -342,6 +347,21 @@ bool build_mesh(int nnode, const double *xy, const int *type, int ntri, const in
         C[s] += area * (tri[3 * t + a] == p ? 11.0 / 54.0 : 7.0 / 108.0);
       }
     }
+    if (nb.size() > 1024) {
+      *err = "mesh node with more than 1023 neighbours";
+      return false;
+    }
+    for (int t : around[p]) {
+      int packed = 0;
+      for (int a = 0; a < 3; ++a) {
+        const int q = tri[3 * t + a];
+        const int s = q == p ? 0 : (int)(std::lower_bound(nb.begin() + 1, nb.end(), q) - nb.begin());
+        packed |= s << (10 * a);
+      }
+      g->tlist.push_back(t);
+      g->tslot.push_back(packed);
+    }
+    g->trow[p + 1] = (int)g->tlist.size();
     for (size_t s = 0; s < nb.size(); ++s) {
       g->col.push_back(nb[s]);
       g->C.push_back(C[s] / V);

@@ -29,6 +29,7 @@ struct StepParams {
   double ybase1; // yc + y(t_{k+1})
   int ix0, ix1, iy0, iy1;      // lattice nodes inside the fictitious rectangle at t_k
   int pix0, pix1, piy0, piy1;  // same at t_{k-1} (t_0 for k = 0)
+  double beta, beta1;  // bending amplitude of a deforming grid at t_k, t_{k+1} (0: rigid)
 };
 
 // One finite-volume stencil shared by every grid node with the same
@@ -76,6 +77,11 @@ struct HostGrid {
   std::vector<double> txy;               // [ntri][3][2] vertex coordinates
   std::vector<int> row, col;             // stencil of node p: col[row[p] .. row[p+1]), the node first
   std::vector<double> C, Gx, Gy;         // its weights, per entry
+  // triangles around node p: tlist[trow[p] .. trow[p+1]) in increasing
+  // order, with the stencil slot (entry - row[p]) of each of their three
+  // vertices in bits 10a .. 10a+9 of tslot
+  std::vector<int> trow, tlist, tslot;
+  std::vector<int> wall_o;               // third vertex of each wall edge's triangle
   double ex0 = 0, ex1 = 0, ey0 = 0, ey1 = 0;  // bounding box of the nodes
   // point location: unit buckets over the bounding box, each listing (in
   // increasing order) the triangles whose box, grown by one bucket, meets it

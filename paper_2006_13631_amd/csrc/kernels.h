@@ -65,6 +65,12 @@ struct CaseView {
   const double *m_x, *m_y;
   const int *m_type;
   MeshGeom mg;
+  // a bending unstructured grid (deform != 0): node p's local y at step k
+  // is m_yref[p] + m_prof[p] beta_k; a wall node's bending velocity is
+  // uwb[k n_sub + m] m_sx[p] on top of uw
+  int deform;
+  const double *m_yref, *m_prof;
+  const R *m_sx, *uwb;
   R *star_f;       // [9][nnode] structured-derived f* at interface nodes
   R *star_n;       // [9][nnode] structured-derived f^neq* at interface nodes
   R dt_u, dt_over_tau_u;
@@ -83,6 +89,24 @@ struct CaseView {
   T *lat[2];
   R *grid[2];
   int64_t max_steps;  // a batched case stops here
+};
+
+// What the geometry update of a bending unstructured grid writes and reads
+// (device pointers): the configuration of step *dk (node p at local x[p],
+// yref[p] + prof[p] params[*dk].beta) gives the stencil weights C, Gx, Gy
+// (entries row[p] .. row[p+1]-1), the triangles' vertex coordinates txy and
+// the wall edges' normals and lengths (wall_o: the third vertex of each
+// wall edge's triangle).
+template <class R>
+struct MeshDeformView {
+  int nnode, ntri, nwall;
+  const double *x, *yref, *prof;
+  const int *tri, *row, *trow, *tlist, *tslot, *wall_o;
+  R *C, *Gx, *Gy;
+  double *txy;
+  WallEdge *wall;
+  const StepParams *params;
+  const int64_t *dk;
 };
 
 // Population-plane stride of lattice buffers: nx * ny rounded up to 256
@@ -167,6 +191,8 @@ struct Kernels {
   static void grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout, int m0, int count, hipStream_t s,
                               R *tape, R *wtape, const int *widx, int nwall, hipEvent_t start, hipEvent_t stop);
   static void refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s);
+  // geometry of a bending unstructured grid at the current step
+  static void mesh_deform(const MeshDeformView<R> &g, hipStream_t s);
   // *to = *from (one lane): a copy of the step counter
   static void copy_step(const int64_t *from, int64_t *to, hipStream_t s);
   // refill and force (prescribed motion) in one launch, then the step

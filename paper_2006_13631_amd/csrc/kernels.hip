@@ -753,12 +753,94 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_substep(CaseView<T, R> v,
     R e[9], ew[9], r, vx, vy;
     moments<R>(out, r, vx, vy);
     equilibrium<R>(r, vx, vy, e);
-    equilibrium<R>(r, R(0), v.uw[k * v.n_sub + m], ew);
+    R uy = v.uw[k * v.n_sub + m];
+    if (v.deform) uy = uy + v.uwb[k * v.n_sub + m] * v.m_sx[p];  // the wall's own bending velocity
+    equilibrium<R>(r, R(0), uy, ew);
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = ew[q] + (out[q] - e[q]);
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) fout[q * N + p] = out[q];
+}
+
+// ---- geometry of a bending unstructured grid ---------------------------------
+// The extension to deformable bodies (Sec. Conclusions): node p of the
+// reference triangulation sits at local y = yref_p + prof_p beta_k during
+// step k. One launch at the start of the step rebuilds what depends on the
+// configuration: lanes [0, nnode) the stencil weights of one node each (the
+// median-dual C_ik and gradient weights Gx_k, Gy_k, summed over the node's
+// triangles in increasing order, as the host assembles them at set-up),
+// lanes [nnode, nnode + ntri) the vertex y of one triangle each (point
+// location), the remaining lanes one wall edge each (length and unit normal
+// toward the triangle's third vertex, out of the body). Node positions are
+// rounded as a separate product and sum.
+template <class R>
+__global__ __launch_bounds__(256) void k_mesh_deform(MeshDeformView<R> g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double beta = g.params[*g.dk].beta;
+  auto ynode = [&](int n) { return __dadd_rn(g.yref[n], __dmul_rn(g.prof[n], beta)); };
+  if (i < g.nnode) {
+    const int p = i, t0 = g.trow[p], t1 = g.trow[p + 1], e0 = g.row[p];
+    double V = 0.0;
+    for (int j = t0; j < t1; ++j) {
+      const int *v = g.tri + 3 * (size_t)g.tlist[j];
+      const double x0 = g.x[v[0]], x1 = g.x[v[1]], x2 = g.x[v[2]];
+      const double y0 = ynode(v[0]), y1 = ynode(v[1]), y2 = ynode(v[2]);
+      V += 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0)) / 3.0;
+    }
+    for (int e = e0; e < g.row[p + 1]; ++e) {
+      const int slot = e - e0;
+      double C = 0.0, Gx = 0.0, Gy = 0.0;
+      for (int j = t0; j < t1; ++j) {
+        const int packed = g.tslot[j];
+        int a = -1;
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (((packed >> (10 * u)) & 1023) == slot) a = u;
+        if (a < 0) continue;
+        const int *v = g.tri + 3 * (size_t)g.tlist[j];
+        double qx[3], qy[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          qx[u] = g.x[v[u]];
+          qy[u] = ynode(v[u]);
+        }
+        const double area = 0.5 * ((qx[1] - qx[0]) * (qy[2] - qy[0]) - (qx[2] - qx[0]) * (qy[1] - qy[0]));
+        const int ab = a == 2 ? 0 : a + 1, ac = a == 0 ? 2 : a - 1;
+        // gradient of vertex a's linear shape function on the triangle
+        const double dphx = -(qy[ac] - qy[ab]) / (2.0 * area);
+        const double dphy = (qx[ac] - qx[ab]) / (2.0 * area);
+        Gx -= (area / 3.0) * dphx;
+        Gy -= (area / 3.0) * dphy;
+        C += area * (slot == 0 ? 11.0 / 54.0 : 7.0 / 108.0);
+      }
+      g.C[e] = (R)(C / V);
+      g.Gx[e] = (R)(Gx / V);
+      g.Gy[e] = (R)(Gy / V);
+    }
+    return;
+  }
+  const int t = i - g.nnode;
+  if (t < g.ntri) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g.txy[6 * (size_t)t + 2 * a + 1] = ynode(g.tri[3 * (size_t)t + a]);
+    return;
+  }
+  const int w = t - g.ntri;
+  if (w >= g.nwall) return;
+  WallEdge &we = g.wall[w];
+  const int o = g.wall_o[w];
+  const double ya = ynode(we.a);
+  const double ex = g.x[we.b] - g.x[we.a], ey = ynode(we.b) - ya;
+  const double len = sqrt(ex * ex + ey * ey);
+  double nx = -ey / len, ny = ex / len;
+  if (nx * (g.x[o] - g.x[we.a]) + ny * (ynode(o) - ya) < 0.0) {
+    nx = -nx;
+    ny = -ny;
+  }
+  we.nx = nx;
+  we.ny = ny;
+  we.len = len;
 }
 
 // ---- K5: move the grid from y_k to y_{k+1} and refill it ---------------------
@@ -787,11 +869,18 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
   if (v.mesh) {
     // the node's new position in the grid of t_k; not in any triangle:
     // inside the old lamina (type 2) or outside the old grid (type 1)
+    // (a bending grid: the node's own new position, and the old lamina's
+    // centreline beta_k (2x/b)^2 under it)
     X = v.xc + v.m_x[p];
-    Ynew = P.ybase1 + v.m_y[p];
+    Ynew = P.ybase1 + (v.deform ? __dadd_rn(v.m_yref[p], __dmul_rn(v.m_prof[p], P.beta1)) : v.m_y[p]);
     const double xl = X - v.xc, yl = Ynew - P.ybase;
+    double yb = 0.0;
+    if (v.deform) {
+      const double r = xl / v.half_b;
+      yb = __dmul_rn(P.beta, __dmul_rn(r, r));
+    }
     rc.kind = mesh_locate(v.mg, xl, yl, node, lam) >= 0 ? 3
-              : (v.body && fabs(xl) < v.half_b && fabs(yl) < v.half_T) ? 2 : 1;
+              : (v.body && fabs(xl) < v.half_b && fabs(yl - yb) < v.half_T) ? 2 : 1;
   } else {
     const int i = p % v.nux, j = p / v.nux;
     const GridGeom gg{v.nux, v.nuy, v.h, v.xc, v.half_b, v.half_T, v.body, v.gx, v.gy};
@@ -1358,6 +1447,11 @@ void Kernels<T, R>::grid_substeps(const CaseView<T, R> &v, const R *f, R *fout, 
 template <class T, class R>
 void Kernels<T, R>::refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipStream_t s) {
   hipLaunchKernelGGL((k_refill<T, R>), dim3(blocks(v.nnode, 256)), dim3(256), 0, s, v, fold, fnew);
+}
+
+template <class T, class R>
+void Kernels<T, R>::mesh_deform(const MeshDeformView<R> &g, hipStream_t s) {
+  hipLaunchKernelGGL((k_mesh_deform<R>), dim3(blocks(g.nnode + g.ntri + g.nwall, 256)), dim3(256), 0, s, g);
 }
 
 template <class T, class R>

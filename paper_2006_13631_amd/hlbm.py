@@ -29,7 +29,7 @@ EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_s
            "hlbm_set_state", "hlbm_info_get", "hlbm_get_stencil", "hlbm_timing",
            "hlbm_timing_get", "hlbm_tune", "hlbm_destroy", "hlbm_last_error",
            "hlbm_create_multilevel", "hlbm_level_shape", "hlbm_set_motion", "hlbm_create_graded",
-           "hlbm_create_mesh",
+           "hlbm_create_mesh", "hlbm_set_deformation",
            "hlbm_get_state_noalloc")
 STATUS_RUNNING, STATUS_DONE, STATUS_UNSTABLE = 0, 1, 2
 
@@ -107,6 +107,7 @@ def load(path: str = LIB_PATH):
     L.hlbm_create_multilevel.argtypes = [C.POINTER(Config), C.POINTER(Levels), C.POINTER(vp)]
     L.hlbm_level_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), dp]
     L.hlbm_set_motion.argtypes = [vp, i32, C.POINTER(Motion)]
+    L.hlbm_set_deformation.argtypes = [vp, C.c_double, C.c_double]
     L.hlbm_create_graded.argtypes = [C.POINTER(Config), dp, dp, C.POINTER(vp)]
     L.hlbm_create_mesh.argtypes = [C.POINTER(Config), i32, dp, C.POINTER(i32), i32, C.POINTER(i32),
                                    C.POINTER(vp)]
@@ -254,6 +255,11 @@ class Case:
         """Two-way coupled motion M y'' + C y' + K y = F_y (before the first step)."""
         m = Motion(mass, stiffness, damping, y0, v0, y_max)
         self._check(load().hlbm_set_motion(self.h, 0, C.byref(m)))
+
+    def set_deformation(self, B, phi=0.0):
+        """Bending B sin(omega t + phi) (2x/b)^2 of the lamina on a given
+        triangulation, the grid following it (before the first step)."""
+        self._check(load().hlbm_set_deformation(self.h, float(B), float(phi)))
 
     def motion_history(self):
         """(y, v) after each step of a coupled case, entry k at t = k+1."""

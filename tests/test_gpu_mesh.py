@@ -166,3 +166,99 @@ def test_mesh_rejects_invalid_meshes():
         with pytest.raises(hlbm.HlbmError) as e:
             make(**kw)
         assert e.value.code == hlbm.E_ARG, kw
+
+
+# ---- a bending lamina (hlbm_set_deformation against or_set_deformation) -------
+
+def _bending_pair(oracle, name, steps, B, phi, storage=hlbm.FP64, **over):
+    o, g, mesh = _pair(oracle, name, steps, storage=storage, **over)
+    o.set_deformation(B, phi)
+    g.set_deformation(B, phi)
+    return o, g, mesh
+
+
+@pytest.mark.parametrize("name,steps,B,phi", [("lamina_96x48", 60, 0.6, 0.4), ("ragged_77x45", 40, -0.5, 1.0),
+                                              ("lamina_256x128", 40, 0.8, 0.0)])
+def test_bending_matches_oracle(oracle, name, steps, B, phi):
+    """Matrices, triangles and wall edges rebuilt on the device every step;
+    refill and force in the bent configuration."""
+    _say("bending parity", name, steps, B, phi)
+    o, g, _ = _bending_pair(oracle, name, steps, B, phi)
+    o.step(steps)
+    g.step(steps)
+    io, ig = o.info(), g.info()
+    assert ig.n_type1 == io.n_type1 and ig.n_type2 == io.n_type2 and ig.n_type3 == io.n_type3
+    _check(o, g)
+
+
+def test_bending_in_chunks_with_graphs(oracle):
+    """Graph replays, pairs of steps and single steps of a bending grid end
+    where one call ends."""
+    o, g, _ = _bending_pair(oracle, "lamina_96x48", 90, 0.7, 2.0)
+    o.step(90)
+    for n in (1, 2, 17, 8, 30, 32):
+        g.step(n)
+    _check(o, g)
+
+
+def test_bending_stencil_follows_the_configuration(oracle):
+    """The weights hlbm_stencil returns are those of the last configuration:
+    that of t_0 before the first step, of t_{k-1} after k steps."""
+    o, g, mesh = _bending_pair(oracle, "ragged_77x45", 12, 0.5, 0.9)
+    N = len(mesh[0])
+
+    def sparse(nbr, M):
+        rows = np.repeat(np.arange(N), nbr.shape[1])
+        cols = nbr.ravel()
+        keep = cols >= 0
+        return sp.csr_matrix((M.ravel()[keep], (rows[keep], cols[keep])), shape=(N, N))
+
+    def compare():
+        nbr_g, S_g, C_g = g.stencil(16)
+        nbr_o, S_o, C_o, _ = o.mesh().stencil()
+        assert abs(sparse(nbr_g, C_g) - sparse(nbr_o, C_o)).max() < 1e-13
+        smax = np.abs(S_o).max()
+        for q in (1, 2, 5):
+            assert abs(sparse(nbr_g, S_g[:, q, :]) - sparse(nbr_o, S_o[:, q, :])).max() < 1e-13 * smax
+        return C_g
+    c0 = compare()
+    o.step(12)
+    g.step(12)
+    c1 = compare()
+    assert np.abs(c1 - c0).max() > 1e-4  # the weights did change
+
+
+def test_bending_reduced_precision(oracle):
+    o, g, _ = _bending_pair(oracle, "lamina_96x48", 20, 0.6, 0.4, storage=hlbm.FP32)
+    o.step(20)
+    g.step(20)
+    errs = {"lattice": _rel(g.lattice(), o.lattice()), "grid": _rel(g.grid(), o.grid())}
+    _say("bending errors, FP32", errs)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_bending_rejects():
+    nx, ny, margs, cargs = CASES["lamina_96x48"]
+    mesh = lamina_triangulation(**margs)
+
+    def code(fn):
+        with pytest.raises(hlbm.HlbmError) as e:
+            fn()
+        return e.value.code
+    g = hlbm.Case(nx, ny, max_steps=4, mesh=mesh, **cargs)
+    assert code(lambda: g.set_deformation(1.0)) == hlbm.E_ARG           # |B| >= 1
+    assert code(lambda: g.set_deformation(float("nan"))) == hlbm.E_ARG
+    g.set_deformation(0.5)
+    assert code(lambda: g.set_motion(mass=400.0, stiffness=0.05)) == hlbm.E_STATE
+    g.step(1)
+    assert code(lambda: g.set_deformation(0.3)) == hlbm.E_STATE         # after the first step
+    # a grid too low for the bent lamina inside the fictitious rectangle
+    low = lamina_triangulation(36.0, 9.6, b=16.0, T=1.0, h_wall=0.7, h_far=1.0, seed=1)
+    g = hlbm.Case(nx, ny, max_steps=4, mesh=low, **cargs)
+    assert code(lambda: g.set_deformation(0.6)) == hlbm.E_ARG
+    nb = CASES["no_body_80x40"]
+    g = hlbm.Case(nb[0], nb[1], max_steps=4, mesh=lamina_triangulation(**nb[2]), **nb[3])
+    assert code(lambda: g.set_deformation(0.3)) == hlbm.E_STATE         # no lamina
+    split = hlbm.Case(96, 48, nux=37, nuy=14, h_u=1.0, b=16.0, thickness=1.0, tau=0.7, kc=0.6, beta=40.0,
+                      n_sub=8, max_steps=4)
+    assert code(lambda: split.set_deformation(0.3)) == hlbm.E_UNSUPPORTED
