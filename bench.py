@@ -755,14 +755,17 @@ def graded_leg(workload="lamina_1024", storage="f64"):
     return out
 
 
-def mesh_leg(workload="lamina_2048", storage="f64", steps=200, warmup=20, timing_steps=40, h_wall=1.0, seed=1):
+def mesh_leg(workload="lamina_2048", storage="f64", steps=200, warmup=20, timing_steps=40, h_wall=1.0, seed=1,
+             bend=0.0):
     """The workload's lamina on an unstructured Delaunay grid of the same
     extent (spacing h_wall on the lamina growing to 1, seeded) against its
     split-quad grid: time per step, the CSR sub-step kernel's mean launch
     time (its own events, one sub-step per launch) against its algorithmic
     bytes (the stencil's neighbours read and the node written, 9 values
     each), and the lattice MLUPS. The mesh grid is L2-resident, so the
-    achieved rate is not an HBM fraction."""
+    achieved rate is not an HBM fraction. bend != 0: also the unstructured
+    grid with its lamina bending at amplitude `bend` (the grid's weights,
+    triangles and wall edges rebuilt every step)."""
     import torch
     from paper_2006_13631_amd import hlbm as H
     from paper_2006_13631_amd.meshes import lamina_triangulation
@@ -784,11 +787,13 @@ def mesh_leg(workload="lamina_2048", storage="f64", steps=200, warmup=20, timing
                     "triangles": int(len(tri)), "mean_stencil": round(entries / len(mesh[0]), 3),
                     "generate_s": round(t_mesh, 2)}}
     total = warmup + steps + timing_steps
-    for kind in ("split_quad", "unstructured"):
+    for kind in ("split_quad", "unstructured") + (("bending",) if bend else ()):
         kw = dict(cfg, storage=H.STORAGE[storage], max_steps=total)
-        if kind == "unstructured":
+        if kind != "split_quad":
             kw["mesh"] = mesh
         c = H.Case(**kw)
+        if kind == "bending":
+            c.set_deformation(bend, 0.0)
         c.step(warmup)
         sched = c.tune(trial_steps=4)
         torch.cuda.synchronize()
@@ -806,7 +811,7 @@ def mesh_leg(workload="lamina_2048", storage="f64", steps=200, warmup=20, timing
                "mlups": round(cfg["nx"] * cfg["ny"] * steps / dt / 1e6, 1),
                "substep_launch_us": round(avg_g * 1e6, 3), "launches_timed": n_g,
                "schedule": {k: sched[k] for k in ("lattice_threads", "lattice_rows", "substep_variant", "order")}}
-        if kind == "unstructured":
+        if kind != "split_quad":
             byts = (entries + inf.nnode) * 9 * s_b  # stencil reads + one write per node
             rec.update({"substeps_per_launch": 1, "bytes_per_launch": byts,
                         "achieved_gbs": round(byts / avg_g / 1e9, 1), "kernel": f"k_mesh_substep<{storage}>"})
@@ -914,6 +919,8 @@ def main():
                     help="run only the main workload on an unstructured Delaunay grid against its split-quad grid "
                          "and print their line")
     ap.add_argument("--mesh-steps", type=int, default=200)
+    ap.add_argument("--mesh-bend", type=float, default=0.0,
+                    help="with --mesh: also run the unstructured grid with the lamina bending at this amplitude")
     ap.add_argument("--coupled", action="store_true",
                     help="run only the main workload with the lamina elastically mounted (two-way coupled) and "
                          "print its line")
@@ -948,7 +955,7 @@ def main():
         return
     if args.mesh:
         torch.cuda.set_device(0)
-        print(json.dumps(mesh_leg(args.workload, args.storage, steps=args.mesh_steps)), flush=True)
+        print(json.dumps(mesh_leg(args.workload, args.storage, steps=args.mesh_steps, bend=args.mesh_bend)), flush=True)
         return
     if args.coupled:
         torch.cuda.set_device(0)

@@ -767,20 +767,59 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_substep(CaseView<T, R> v,
 // The extension to deformable bodies (Sec. Conclusions): node p of the
 // reference triangulation sits at local y = yref_p + prof_p beta_k during
 // step k. One launch at the start of the step rebuilds what depends on the
-// configuration: lanes [0, nnode) the stencil weights of one node each (the
-// median-dual C_ik and gradient weights Gx_k, Gy_k, summed over the node's
-// triangles in increasing order, as the host assembles them at set-up),
+// configuration: lanes [0, nnode) the stencil weights of one node each,
 // lanes [nnode, nnode + ntri) the vertex y of one triangle each (point
 // location), the remaining lanes one wall edge each (length and unit normal
 // toward the triangle's third vertex, out of the body). Node positions are
 // rounded as a separate product and sum.
+//
+// A node's weights are the median-dual ones of the host assembly: over the
+// triangles around it, V = sum |T|/3, C gains |T| 11/54 for the node itself
+// and |T| 7/108 for each other vertex, and the gradient weight of vertex a,
+// -(|T|/3) grad(phi_a), is the edge opposite a turned by 90 degrees over 6
+// (no division). Each lane sums into its own column of LDS, one slot per
+// stencil entry; a node with more than kDeformSlots entries takes the
+// per-entry loop instead.
+constexpr int kDeformThreads = 64, kDeformSlots = 16;
 template <class R>
-__global__ __launch_bounds__(256) void k_mesh_deform(MeshDeformView<R> g) {
+__global__ __launch_bounds__(kDeformThreads) void k_mesh_deform(MeshDeformView<R> g) {
+  __shared__ double acc[kDeformSlots * 3][kDeformThreads];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x;
   const double beta = g.params[*g.dk].beta;
   auto ynode = [&](int n) { return __dadd_rn(g.yref[n], __dmul_rn(g.prof[n], beta)); };
   if (i < g.nnode) {
-    const int p = i, t0 = g.trow[p], t1 = g.trow[p + 1], e0 = g.row[p];
+    const int p = i, t0 = g.trow[p], t1 = g.trow[p + 1], e0 = g.row[p], ne = g.row[p + 1] - e0;
+    if (ne <= kDeformSlots) {
+      for (int u = 0; u < ne; ++u) acc[3 * u][lane] = acc[3 * u + 1][lane] = acc[3 * u + 2][lane] = 0.0;
+      double V = 0.0;
+      for (int j = t0; j < t1; ++j) {
+        const int packed = g.tslot[j];
+        const int *v = g.tri + 3 * (size_t)g.tlist[j];
+        double qx[3], qy[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          qx[u] = g.x[v[u]];
+          qy[u] = ynode(v[u]);
+        }
+        const double area = 0.5 * ((qx[1] - qx[0]) * (qy[2] - qy[0]) - (qx[2] - qx[0]) * (qy[1] - qy[0]));
+        V += area / 3.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int ab = a == 2 ? 0 : a + 1, ac = a == 0 ? 2 : a - 1;
+          const int slot = (packed >> (10 * a)) & 1023;
+          acc[3 * slot][lane] += area * (slot == 0 ? 11.0 / 54.0 : 7.0 / 108.0);
+          acc[3 * slot + 1][lane] += (qy[ac] - qy[ab]) / 6.0;
+          acc[3 * slot + 2][lane] += (qx[ab] - qx[ac]) / 6.0;
+        }
+      }
+      for (int u = 0; u < ne; ++u) {
+        g.C[e0 + u] = (R)(acc[3 * u][lane] / V);
+        g.Gx[e0 + u] = (R)(acc[3 * u + 1][lane] / V);
+        g.Gy[e0 + u] = (R)(acc[3 * u + 2][lane] / V);
+      }
+      return;
+    }
     double V = 0.0;
     for (int j = t0; j < t1; ++j) {
       const int *v = g.tri + 3 * (size_t)g.tlist[j];
@@ -788,8 +827,7 @@ __global__ __launch_bounds__(256) void k_mesh_deform(MeshDeformView<R> g) {
       const double y0 = ynode(v[0]), y1 = ynode(v[1]), y2 = ynode(v[2]);
       V += 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0)) / 3.0;
     }
-    for (int e = e0; e < g.row[p + 1]; ++e) {
-      const int slot = e - e0;
+    for (int slot = 0; slot < ne; ++slot) {
       double C = 0.0, Gx = 0.0, Gy = 0.0;
       for (int j = t0; j < t1; ++j) {
         const int packed = g.tslot[j];
@@ -807,16 +845,13 @@ __global__ __launch_bounds__(256) void k_mesh_deform(MeshDeformView<R> g) {
         }
         const double area = 0.5 * ((qx[1] - qx[0]) * (qy[2] - qy[0]) - (qx[2] - qx[0]) * (qy[1] - qy[0]));
         const int ab = a == 2 ? 0 : a + 1, ac = a == 0 ? 2 : a - 1;
-        // gradient of vertex a's linear shape function on the triangle
-        const double dphx = -(qy[ac] - qy[ab]) / (2.0 * area);
-        const double dphy = (qx[ac] - qx[ab]) / (2.0 * area);
-        Gx -= (area / 3.0) * dphx;
-        Gy -= (area / 3.0) * dphy;
         C += area * (slot == 0 ? 11.0 / 54.0 : 7.0 / 108.0);
+        Gx += (qy[ac] - qy[ab]) / 6.0;
+        Gy += (qx[ab] - qx[ac]) / 6.0;
       }
-      g.C[e] = (R)(C / V);
-      g.Gx[e] = (R)(Gx / V);
-      g.Gy[e] = (R)(Gy / V);
+      g.C[e0 + slot] = (R)(C / V);
+      g.Gx[e0 + slot] = (R)(Gx / V);
+      g.Gy[e0 + slot] = (R)(Gy / V);
     }
     return;
   }
@@ -1451,7 +1486,8 @@ void Kernels<T, R>::refill(const CaseView<T, R> &v, const R *fold, R *fnew, hipS
 
 template <class T, class R>
 void Kernels<T, R>::mesh_deform(const MeshDeformView<R> &g, hipStream_t s) {
-  hipLaunchKernelGGL((k_mesh_deform<R>), dim3(blocks(g.nnode + g.ntri + g.nwall, 256)), dim3(256), 0, s, g);
+  hipLaunchKernelGGL((k_mesh_deform<R>), dim3(blocks(g.nnode + g.ntri + g.nwall, kDeformThreads)),
+                     dim3(kDeformThreads), 0, s, g);
 }
 
 template <class T, class R>
