@@ -150,8 +150,10 @@ typedef struct hlbm_tuning {
                               (large grids)                                */
   int32_t order;           /* batch work lists: 0 case by case, 1 dealt to
                               the 8 XCDs in contiguous chunks; single
-                              case: 1 gives each XCD a contiguous band of
-                              stream-collide rows                          */
+                              case: bit 0 gives each XCD a contiguous band
+                              of stream-collide rows, bit 1 deals the
+                              two-step tiles to the XCDs in contiguous
+                              runs, each XCD starting at its own offset    */
   int32_t tail_variant;    /* batch: sub-step variant once at most
                               max(1, ncases/8) cases still run (-1: the
                               same as substep_variant); single case: -1    */
@@ -450,9 +452,10 @@ int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count)
  * longest-running max(1, ncases/8) cases alone (tail_variant, persistent
  * 2), keep the fastest and restore the initial state. Single case (any
  * time, state untouched): time trial_steps launches of the stream-collide
- * in each shape and order and of one step's sub-steps in each variant, reading the
- * current lattice and grid and writing only their free buffers, and keep
- * the fastest (ms_per_step: the two chosen kernels' time per step).
+ * in each shape and order, of the two-step stream-collide in each tile
+ * order (where the case takes two steps per launch) and of one step's
+ * sub-steps in each variant, reading the current lattice and grid and
+ * writing only their free buffers, and keep the fastest (ms_per_step: the two chosen kernels' time per step).
  * trial_steps = 0 applies *t as given instead (single case: lattice_threads
  * = lattice_rows = 0 keeps the stream-collide shape). A single case then
  * captures the HIP graphs its next steps replay, so later hlbm_step calls

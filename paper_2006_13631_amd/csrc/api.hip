@@ -493,8 +493,8 @@ class Case final : public CaseBase {
       v.dkl = dk_copy_;
       ENQ(fork());
     }
-    if (timing_ == 2) Kernels<T, R>::stream_collide2(v, s_main_, tev_[tslot_][8], tev_[tslot_][2]);
-    else Kernels<T, R>::stream_collide2(v, s_main_);
+    if (timing_ == 2) Kernels<T, R>::stream_collide2(v, s_main_, tev_[tslot_][8], tev_[tslot_][2], two_step_order_);
+    else Kernels<T, R>::stream_collide2(v, s_main_, nullptr, nullptr, two_step_order_);
     if (has_grid_) {
       ENQ(enqueue_grid_path(v));
       if (two) ENQ(join());
@@ -1093,18 +1093,19 @@ class Case final : public CaseBase {
     if (trial_steps == 0) {
       const bool keep_shape = t->lattice_threads == 0 && t->lattice_rows == 0;
       if ((!keep_shape && !valid_lattice_shape(*t)) || t->substep_variant < -1 ||
-          t->substep_variant >= kSubstepVariantsSingle || t->order < 0 || t->order > 1)
+          t->substep_variant >= kSubstepVariantsSingle || t->order < 0 || t->order > 3)
         return fail(HLBM_E_ARG, "invalid schedule");
       if (!keep_shape) {
         lattice_threads_ = t->lattice_threads;
         lattice_rows_ = t->lattice_rows;
       }
       substep_variant_ = t->substep_variant;
-      lattice_order_ = t->order;
+      lattice_order_ = t->order & 1;
+      two_step_order_ = (t->order >> 1) & 1;
       HIPCHK(hipStreamSynchronize(s_main_));
       drop_graphs();
       HIPCHK(prime_graphs());
-      *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, -1, 0, 0, 0.0};
+      *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, order_code(), -1, 0, 0, 0.0};
       return HLBM_OK;
     }
     HIPCHK(hipDeviceSynchronize());
@@ -1141,6 +1142,16 @@ class Case final : public CaseBase {
             lattice_order_ = ord;
           }
         }
+    if (two_step_) {  // the two-step kernel's tile order (writes B and C, both free between pairs)
+      float best2 = 3e38f;
+      for (int ord : {0, 1}) {
+        const float ms = timed(s_main_, [&] { Kernels<T, R>::stream_collide2(v, s_main_, nullptr, nullptr, ord); });
+        if (e == hipSuccess && ms < best2) {
+          best2 = ms;
+          two_step_order_ = ord;
+        }
+      }
+    }
     total += best_ms;
     if (has_grid_ && grid_.mesh) {  // one sub-step kernel: timed, nothing to choose
       total += timed(s_grid_, [&] {
@@ -1170,7 +1181,7 @@ class Case final : public CaseBase {
     HIPCHK(e);
     drop_graphs();
     HIPCHK(prime_graphs());
-    *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, lattice_order_, -1, 0, 0,
+    *t = hlbm_tuning{0, lattice_threads_, lattice_rows_, substep_variant_, order_code(), -1, 0, 0,
                       total / trial_steps};
     return HLBM_OK;
   }
@@ -1915,6 +1926,8 @@ class Case final : public CaseBase {
   int substep_variant_ = -1;  // grid sub-step kernel variant (-1: the default for R)
   int lattice_threads_ = kLatticeThreads, lattice_rows_ = kLatticeRows;  // stream-collide launch shape
   int lattice_order_ = 0;  // 1: stream-collide rows banded by XCD
+  int two_step_order_ = 1;  // 1: two-step tiles in staggered runs per XCD (0: in turn)
+  int order_code() const { return lattice_order_ | (two_step_order_ << 1); }
   static constexpr int kTimedKernels = 9;  // HLBM_K_* ids
   double tms_[kTimedKernels] = {};
   int64_t tcount_[kTimedKernels] = {};

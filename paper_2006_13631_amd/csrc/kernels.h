@@ -169,9 +169,11 @@ struct Kernels {
                              hipEvent_t stop = nullptr, int threads = 0, int rows = 0, int order = 0);
   // two steps t_k -> t_{k+2} in one launch (tile of kTwoStepTX x kTwoStepTY
   // nodes, the first step on the tile and a one-node ring kept in LDS);
-  // needs nx >= kTwoStepTX + 2 and ny >= kTwoStepTY + 2
+  // needs nx >= kTwoStepTX + 2 and ny >= kTwoStepTY + 2; order 1: the
+  // tiles are dealt to the XCDs in contiguous runs of rows, each XCD
+  // starting at a different offset (0: in turn, row by row)
   static void stream_collide2(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start = nullptr,
-                              hipEvent_t stop = nullptr);
+                              hipEvent_t stop = nullptr, int order = 0);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
   static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
   // one sub-step m of an unstructured grid (Eq.(ulbe), Eq.(postcollision2_u)),

@@ -221,13 +221,15 @@ class Case:
         """Pick the stream-collide launch shape and order and the grid
         sub-step kernel variant by timing each (state untouched), or apply
         ``variant`` (-1 = default), ``lattice`` = (threads, rows) and
-        ``order`` (1: rows banded by XCD) as given. Returns the schedule."""
+        ``order`` (bit 0: single-step rows banded by XCD; bit 1: two-step
+        tiles in staggered runs per XCD; default 2) as given. Returns the
+        schedule."""
         t = Tuning()
         if variant is not None or lattice is not None or order is not None:
             t.substep_variant = -1 if variant is None else variant
             if lattice is not None:
                 t.lattice_threads, t.lattice_rows = lattice
-            t.order = 0 if order is None else order
+            t.order = 2 if order is None else order
             trial_steps = 0
         self._check(load().hlbm_tune(self.h, trial_steps, C.byref(t)))
         return t.as_dict()

@@ -158,7 +158,7 @@ def test_single_case_tune_leaves_state_alone():
     a.step(n - n // 2)
     b.step(n - n // 2)
     _same(a, b)
-    for bad in (dict(variant=11), dict(lattice=(96, 1)), dict(lattice=(128, 3)), dict(order=2)):
+    for bad in (dict(variant=11), dict(lattice=(96, 1)), dict(lattice=(128, 3)), dict(order=4)):
         with pytest.raises(hlbm.HlbmError) as e:
             a.tune(**bad)
         assert e.value.code == hlbm.E_ARG

@@ -205,9 +205,9 @@ def _host_threads():
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("name,steps,schedule", [
     # the schedule the autotuner picks for the 2048^2 FP64 benchmark line
-    ("lamina_2048", 202, dict(variant=1, lattice=(128, 1), order=1)),
+    ("lamina_2048", 202, dict(variant=1, lattice=(128, 1), order=3)),
     # and for the 4096^2 FP64 precision line
-    ("lamina_4096", 26, dict(variant=9, lattice=(256, 1), order=0)),
+    ("lamina_4096", 26, dict(variant=9, lattice=(256, 1), order=2)),
 ])
 def test_full_size_in_benchmark_configuration(oracle, name, steps, schedule):
     """The benchmark workloads at full size in the launch configuration the
