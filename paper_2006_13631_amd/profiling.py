@@ -3,7 +3,7 @@
     python -m paper_2006_13631_amd.profiling stats KERNEL_STATS_CSV --out FILE --command CMD \
         [--trace KERNEL_TRACE_CSV --kernel NAME --windows A:B,C:D]
     python -m paper_2006_13631_amd.profiling traffic --fetch PMC_CSV --write PMC_CSV \
-        --kernel k_stream_collide --copy-bytes N --out FILE --command CMD
+        --kernel k_stream_collide --copy-bytes N --out FILE --command CMD [--skip N]
 
 `traffic` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch) of
 a kernel into bytes per launch, each scaled by what the same counter reads
@@ -74,8 +74,8 @@ def _per_dispatch(path: str, counter: str):
         acc[d] += float(r["Counter_Value"])
         names[d] = r["Kernel_Name"]
     out = collections.defaultdict(list)
-    for d, v in acc.items():
-        out[names[d]].append(v)
+    for d in sorted(acc, key=lambda x: int(x) if str(x).isdigit() else x):  # in dispatch order
+        out[names[d]].append(acc[d])
     return out
 
 
@@ -84,19 +84,22 @@ def kernel_file(kernel: str) -> str:
     return re.sub(r"[^A-Za-z0-9_]+", "_", kernel).strip("_")
 
 
-def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dict:
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, skip: int = 0) -> dict:
+    """skip: leave out the kernel's first `skip` dispatches of each run (in
+    dispatch order), e.g. launches in a configuration the benchmark does
+    not time."""
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         per = _per_dispatch(path, counter)
         # the kernel, not a longer name; with template arguments, that instance only
         match = (lambda n: kernel + "(" in n) if "<" in kernel else (lambda n: kernel + "<" in n)
-        kv = [v for n, vs in per.items() if match(n) for v in vs]
+        kv = [v for n, vs in per.items() if match(n) for v in vs][skip:]
         cv = [v for n, vs in per.items() if COPY_KERNEL in n for v in vs]
         if not kv or not cv:
             raise SystemExit(f"{counter}: no dispatch of {kernel!r} or of the copy kernel in {path}")
         copy_kib = max(cv)  # the calibration copy is the largest copy of the run
         scale = (copy_bytes / 1024.0) / copy_kib
-        res[counter] = {"kernel_kib_per_dispatch": sum(kv) / len(kv), "dispatches": len(kv),
+        res[counter] = {"kernel_kib_per_dispatch": sum(kv) / len(kv), "dispatches": len(kv), "skipped": skip,
                         "copy_kib": copy_kib, "copy_scale": scale,
                         "bytes_per_launch": sum(kv) / len(kv) * 1024.0 * scale}
     res["bytes_per_launch"] = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
@@ -157,6 +160,8 @@ def main(argv=None):
     t.add_argument("--write", required=True)
     t.add_argument("--kernel", required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--skip", type=int, default=0, help="leave out the kernel's first N dispatches")
+    t.add_argument("--note", default="")
     t.add_argument("--workload", required=True)
     t.add_argument("--storage", required=True)
     t.add_argument("--out", required=True)
@@ -179,9 +184,11 @@ def main(argv=None):
         open(a.out, "w").write(text)
         print(text)
     else:
-        res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes)
+        res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.skip)
         res.update({"kernel": a.kernel, "workload": a.workload, "storage": a.storage,
                     "source_sha256": source_sha256(), "command": a.command})
+        if a.note:
+            res["note"] = a.note
         json.dump(res, open(a.out, "w"), indent=1)
         print(json.dumps(res, indent=1))
 

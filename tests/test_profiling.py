@@ -46,6 +46,19 @@ def test_traffic_scaled_by_the_copy(tmp_path):
     assert r["FETCH_SIZE"]["dispatches"] == 2  # the longer name is another kernel
 
 
+def test_traffic_skips_leading_dispatches(tmp_path):
+    copy = P.COPY_KERNEL
+    # dispatch ids out of order in the file: the skip follows dispatch order
+    f = _csv(tmp_path / "f.csv", [(3, KERNEL, "FETCH_SIZE", 100.0), (1, copy, "FETCH_SIZE", 512.0),
+                                  (2, KERNEL, "FETCH_SIZE", 900.0), (4, KERNEL, "FETCH_SIZE", 300.0)])
+    w = _csv(tmp_path / "w.csv", [(1, copy, "WRITE_SIZE", 1024.0), (2, KERNEL, "WRITE_SIZE", 70.0),
+                                  (3, KERNEL, "WRITE_SIZE", 50.0), (4, KERNEL, "WRITE_SIZE", 50.0)])
+    r = P.traffic(f, w, "k_stream_collide2", 1 << 20, skip=1)
+    assert r["FETCH_SIZE"]["dispatches"] == 2 and r["FETCH_SIZE"]["skipped"] == 1
+    assert r["FETCH_SIZE"]["bytes_per_launch"] == pytest.approx(200.0 * 1024 * 2.0)
+    assert r["WRITE_SIZE"]["bytes_per_launch"] == pytest.approx(50.0 * 1024)
+
+
 def test_traffic_needs_both_kernels(tmp_path):
     f = _csv(tmp_path / "f.csv", [(2, KERNEL, "FETCH_SIZE", 100.0)])
     with pytest.raises(SystemExit):
