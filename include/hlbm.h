@@ -344,6 +344,23 @@ int hlbm_set_motion(hlbm_t *h, int32_t case_id, const hlbm_motion *m);
  * max_steps; HLBM_E_UNSTABLE if a non-finite force appeared. */
 int hlbm_step(hlbm_t *h, int64_t nsteps);
 
+/* The steps of hlbm_step (Sec. HLBM and Sec. Refill procedure), enqueued on
+ * the handle's stream without waiting for them: the call returns once they
+ * are launched. The status it returns covers the steps known to have
+ * finished (the device flag as copied after an earlier hlbm_step_async, if
+ * that copy is done): HLBM_E_UNSTABLE as hlbm_step reports it; a flag raised
+ * by steps still running is reported by a later hlbm_step_async, hlbm_sync or
+ * hlbm_step. Every other call on the handle first waits for the enqueued
+ * steps. HLBM_E_ARG as hlbm_step (nothing is enqueued then). Single cases;
+ * a batched or multi-level handle, and a single case with timing on, step
+ * as hlbm_step does (blocking). */
+int hlbm_step_async(hlbm_t *h, int64_t nsteps);
+
+/* Wait for every step enqueued on the handle; returns what hlbm_step would
+ * have returned for them (0, or HLBM_E_UNSTABLE with the cause in
+ * hlbm_last_error). */
+int hlbm_sync(hlbm_t *h);
+
 /* Force history and hydrodynamic function (Sec. 2.1, Eq.(force_phasor)).
  * hist_xy (may be NULL) receives up to cap (Fx, Fy) pairs, entry k at
  * t = k+1; *n_out (may be NULL) gets the number of entries. If theta is not

@@ -118,6 +118,14 @@ class CaseBase {
  public:
   virtual ~CaseBase() = default;
   virtual int step(int64_t n) = 0;
+  // enqueue n steps and return without waiting for them (single cases;
+  // other handles step as hlbm_step does)
+  virtual int step_async(int64_t n) { return step(n); }
+  // wait for the enqueued steps; their status as step() reports it
+  virtual int sync() { return 0; }
+  // wait for the enqueued steps before another call reads or writes the
+  // state (their status stays on the device flag for the next step or sync)
+  virtual void drain() {}
   virtual int get_state(int which, void *buf, size_t bytes) = 0;
   virtual int set_state(int which, const void *buf, size_t bytes) = 0;
   // get_state of the lattice and grid states through the static staging
@@ -251,6 +259,9 @@ class Case final : public CaseBase {
     else s_grid_ = s_main_;
     HIPCHK(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_flag_, hipEventDisableTiming));
+    HIPCHK(hipHostMalloc((void **)&hflag_, sizeof(int), hipHostMallocDefault));
+    *hflag_ = 0;
     HIPCHK(alloc(&lat_[0], 9 * plane_ * sizeof(T)));
     HIPCHK(alloc(&lat_[1], 9 * plane_ * sizeof(T)));
     lat_base_ = lat_[0];
@@ -592,6 +603,52 @@ class Case final : public CaseBase {
   }
 
   int step(int64_t nsteps) override {
+    const int rc = enqueue_run(nsteps);
+    if (rc != HLBM_OK) return rc;
+    return sync();
+  }
+
+  // the steps enqueued; the flag of those that have finished (read from the
+  // copy a previous call enqueued, if it is done) is checked without waiting
+  int step_async(int64_t nsteps) override {
+    if (timing_) return step(nsteps);  // timed steps are harvested on the host
+    const int rc = enqueue_run(nsteps);
+    if (rc != HLBM_OK) return rc;
+    pending_ = true;
+    int seen = 0;
+    if (flag_copied_) {
+      const hipError_t q = hipEventQuery(ev_flag_);
+      if (q == hipSuccess) seen = *hflag_;
+      else if (q != hipErrorNotReady) HIPCHK(q);
+    }
+    HIPCHK(hipMemcpyAsync(hflag_, flag_, sizeof(int), hipMemcpyDeviceToHost, s_main_));
+    HIPCHK(hipEventRecord(ev_flag_, s_main_));
+    flag_copied_ = true;
+    return flag_status(seen);
+  }
+
+  int sync() override {
+    HIPCHK(hipStreamSynchronize(s_main_));
+    pending_ = false;
+    int flag = 0;
+    HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
+    return flag_status(flag);
+  }
+
+  void drain() override {
+    if (pending_) (void)hipStreamSynchronize(s_main_);
+    pending_ = false;
+  }
+
+  int flag_status(int flag) {
+    if (flag & 4) return fail(HLBM_E_UNSTABLE, "a lattice node to interpolate lies outside the grid");
+    if (flag & 2) return fail(HLBM_E_UNSTABLE, "a density became non-positive or not a number");
+    if (flag) return fail(HLBM_E_UNSTABLE, has_grid_ ? "non-finite force on the lamina" : "unstable");
+    return HLBM_OK;
+  }
+
+  // enqueue nsteps steps (graphs, pairs or single steps) on the main stream
+  int enqueue_run(int64_t nsteps) {
     if (nsteps < 0) return fail(HLBM_E_ARG, "nsteps < 0");
     if (has_grid_ && k_ + nsteps > cfg_.max_steps) return fail(HLBM_E_ARG, "force history would exceed max_steps");
     int64_t done = 0;
@@ -627,12 +684,6 @@ class Case final : public CaseBase {
       }
     }
     if (timing_ && tslot_ > 0) HIPCHK(harvest());
-    HIPCHK(hipStreamSynchronize(s_main_));
-    int flag = 0;
-    HIPCHK(hipMemcpy(&flag, flag_, sizeof(int), hipMemcpyDeviceToHost));
-    if (flag & 4) return fail(HLBM_E_UNSTABLE, "a lattice node to interpolate lies outside the grid");
-    if (flag & 2) return fail(HLBM_E_UNSTABLE, "a density became non-positive or not a number");
-    if (flag) return fail(HLBM_E_UNSTABLE, has_grid_ ? "non-finite force on the lamina" : "unstable");
     return HLBM_OK;
   }
 
@@ -1335,6 +1386,9 @@ class Case final : public CaseBase {
         if (e) (void)hipEventDestroy(e);
     if (ev_fork_) (void)hipEventDestroy(ev_fork_);
     if (ev_join_) (void)hipEventDestroy(ev_join_);
+    if (ev_flag_) (void)hipEventDestroy(ev_flag_);
+    if (hflag_) (void)hipHostFree(hflag_);
+    hflag_ = nullptr;
     for (auto &e : ev_rec_)
       if (e) (void)hipEventDestroy(e);
     for (auto &e : ev_rev_)
@@ -1969,6 +2023,10 @@ class Case final : public CaseBase {
   double *hist_ = nullptr;
   int64_t *dk_ = nullptr;
   int *flag_ = nullptr;
+  int *hflag_ = nullptr;          // pinned: the flag as last copied by step_async
+  hipEvent_t ev_flag_ = nullptr;  // recorded after that copy
+  bool flag_copied_ = false;      // a copy has been enqueued
+  bool pending_ = false;          // steps enqueued by step_async not yet waited for
   unsigned long long *counts_ = nullptr;
   unsigned *done_ = nullptr;  // workgroups done in the fused refill-and-force launch (0 between launches)
   int64_t *dk_copy_ = nullptr;  // the step counter as the two-step launch reads it beside a grid path
@@ -3180,17 +3238,29 @@ int hlbm_create_graded(const hlbm_config *cfg, const double *x_nodes, const doub
 
 int hlbm_set_motion(hlbm_t *h, int32_t case_id, const hlbm_motion *m) {
   if (!h) return HLBM_E_ARG;
+  h->c->drain();
   return h->c->set_motion(case_id, m);
 }
 
 int hlbm_set_deformation(hlbm_t *h, double B, double phi) {
   if (!h) return HLBM_E_ARG;
+  h->c->drain();
   return h->c->set_deformation(B, phi);
 }
 
 int hlbm_step(hlbm_t *h, int64_t nsteps) {
   if (!h) return HLBM_E_ARG;
   return h->c->step(nsteps);
+}
+
+int hlbm_step_async(hlbm_t *h, int64_t nsteps) {
+  if (!h) return HLBM_E_ARG;
+  return h->c->step_async(nsteps);
+}
+
+int hlbm_sync(hlbm_t *h) {
+  if (!h) return HLBM_E_ARG;
+  return h->c->sync();
 }
 
 static mghlbm::CaseBase *pick(hlbm_t *h, int32_t case_id) {
@@ -3202,6 +3272,7 @@ static mghlbm::CaseBase *pick(hlbm_t *h, int32_t case_id) {
 int hlbm_force(hlbm_t *h, int32_t case_id, double *hist_xy, int64_t cap, int64_t *n_out, double win_t0,
                double win_t1, double theta[2]) {
   if (!h || cap < 0) return HLBM_E_ARG;
+  h->c->drain();
   mghlbm::CaseBase *c = pick(h, case_id);
   if (!c) return HLBM_E_ARG;
   const int rc = c->force(hist_xy, cap, n_out, win_t0, win_t1, theta);
@@ -3211,6 +3282,7 @@ int hlbm_force(hlbm_t *h, int32_t case_id, double *hist_xy, int64_t cap, int64_t
 
 int hlbm_adjoint(hlbm_t *h, int32_t case_id, const double *dJ_dF, int64_t n, double grad[3]) {
   if (!h) return HLBM_E_ARG;
+  h->c->drain();
   if (h->c->sub(1)) return h->c->adjoint(dJ_dF, n, grad);  // a batch: unsupported
   if (case_id != 0) return HLBM_E_ARG;
   return h->c->adjoint(dJ_dF, n, grad);
@@ -3218,6 +3290,7 @@ int hlbm_adjoint(hlbm_t *h, int32_t case_id, const double *dJ_dF, int64_t n, dou
 
 int hlbm_get_state(hlbm_t *h, int32_t case_id, int32_t which, void *buf, size_t bytes) {
   if (!h || !buf) return HLBM_E_ARG;
+  h->c->drain();
   mghlbm::CaseBase *c = pick(h, case_id);
   if (!c) return HLBM_E_ARG;
   const int rc = c->get_state(which, buf, bytes);
@@ -3227,6 +3300,7 @@ int hlbm_get_state(hlbm_t *h, int32_t case_id, int32_t which, void *buf, size_t 
 
 int hlbm_get_state_noalloc(hlbm_t *h, int32_t case_id, int32_t which, void *host_buf, size_t bytes) {
   if (!h || !host_buf) return HLBM_E_ARG;
+  h->c->drain();
   mghlbm::CaseBase *c = pick(h, case_id);
   if (!c) return HLBM_E_ARG;
   const int rc = c->get_state_noalloc(which, host_buf, bytes);
@@ -3236,6 +3310,7 @@ int hlbm_get_state_noalloc(hlbm_t *h, int32_t case_id, int32_t which, void *host
 
 int hlbm_set_state(hlbm_t *h, int32_t case_id, int32_t which, const void *buf, size_t bytes) {
   if (!h || !buf) return HLBM_E_ARG;
+  h->c->drain();
   mghlbm::CaseBase *c = pick(h, case_id);
   if (!c) return HLBM_E_ARG;
   const int rc = c->set_state(which, buf, bytes);
@@ -3245,6 +3320,7 @@ int hlbm_set_state(hlbm_t *h, int32_t case_id, int32_t which, const void *buf, s
 
 int hlbm_info_get(hlbm_t *h, int32_t case_id, hlbm_info *out) {
   if (!h || !out) return HLBM_E_ARG;
+  h->c->drain();
   mghlbm::CaseBase *c = pick(h, case_id);
   if (!c) return HLBM_E_ARG;
   const int rc = c->info(out);
@@ -3254,21 +3330,25 @@ int hlbm_info_get(hlbm_t *h, int32_t case_id, hlbm_info *out) {
 
 int hlbm_tune(hlbm_t *h, int32_t trial_steps, hlbm_tuning *t) {
   if (!h) return HLBM_E_ARG;
+  h->c->drain();
   return h->c->tune(trial_steps, t);
 }
 
 int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S, double *C) {
   if (!h || kmax <= 0) return HLBM_E_ARG;
+  h->c->drain();
   return h->c->stencil(kmax, nbr, S, C);
 }
 
 int hlbm_timing(hlbm_t *h, int32_t on) {
   if (!h) return HLBM_E_ARG;
+  h->c->drain();
   return h->c->timing(on);
 }
 
 int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count) {
   if (!h) return HLBM_E_ARG;
+  h->c->drain();
   return h->c->timing_get(kernel, total_ms, count);
 }
 

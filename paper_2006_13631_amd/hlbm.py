@@ -30,7 +30,7 @@ EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_s
            "hlbm_timing_get", "hlbm_tune", "hlbm_destroy", "hlbm_last_error",
            "hlbm_create_multilevel", "hlbm_level_shape", "hlbm_set_motion", "hlbm_create_graded",
            "hlbm_create_mesh", "hlbm_set_deformation",
-           "hlbm_get_state_noalloc")
+           "hlbm_get_state_noalloc", "hlbm_step_async", "hlbm_sync")
 STATUS_RUNNING, STATUS_DONE, STATUS_UNSTABLE = 0, 1, 2
 
 
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
     dp = C.POINTER(C.c_double)
     L.hlbm_create.argtypes = [C.POINTER(Config), i32, C.POINTER(vp)]
     L.hlbm_step.argtypes = [vp, i64]
+    L.hlbm_step_async.argtypes = [vp, i64]
+    L.hlbm_sync.argtypes = [vp]
     L.hlbm_force.argtypes = [vp, i32, dp, i64, C.POINTER(i64), d, d, dp]
     L.hlbm_adjoint.argtypes = [vp, i32, dp, i64, dp]
     L.hlbm_get_state.argtypes = [vp, i32, i32, vp, C.c_size_t]
@@ -174,6 +176,14 @@ class Case:
 
     def step(self, n=1):
         self._check(load().hlbm_step(self.h, n))
+
+    def step_async(self, n=1):
+        """Enqueue n steps without waiting (hlbm_step_async)."""
+        self._check(load().hlbm_step_async(self.h, n))
+
+    def sync(self):
+        """Wait for the enqueued steps (hlbm_sync)."""
+        self._check(load().hlbm_sync(self.h))
 
     def info(self) -> Info:
         i = Info()
