@@ -505,6 +505,18 @@ def precision_leg(workload="lamina_4096", steps=None, chunk=1000):
     return out
 
 
+def paper_theta(eps, beta):
+    """The paper's own MG-HLBM Theta for one of its (epsilon, beta) cases
+    (Figs. aggregate_re and aggregate_im, 4 decimals; tests/golden), or
+    None for a pair it did not run."""
+    path = os.path.join(ROOT, "tests", "golden", "paper_mg_hlbm_theta.txt")
+    for line in open(path):
+        f = line.split("#")[0].split()
+        if len(f) == 4 and abs(float(f[0]) - eps) < 1e-12 and int(f[1]) == int(round(beta)):
+            return complex(float(f[2]), -float(f[3]))
+    return None
+
+
 def study_leg(b=64, storage="f64", tune_steps=8, chunk=2000):
     """The paper's (epsilon, beta) study (35 pairs under Eq.(betalimit), 5L x 5L
     domain, the paper's outer boundaries) as one batch; Theta of each case
@@ -532,6 +544,7 @@ def study_leg(b=64, storage="f64", tune_steps=8, chunk=2000):
     t2 = time.perf_counter()
     rows = []
     devs_re, devs_im = [], []
+    pdev_re, pdev_im = [], []
     for i, c in enumerate(cases):
         inf = batch[i].info()
         th = batch[i].theta() if inf.status == H.STATUS_DONE else None
@@ -539,11 +552,19 @@ def study_leg(b=64, storage="f64", tune_steps=8, chunk=2000):
         row = {"eps": c["eps"], "beta": c["beta_p"], "steps": c["max_steps"], "status": int(inf.status),
                "theta": None if th is None else [round(th.real, 5), round(th.imag, 5)],
                "semianalytical": [round(ref.real, 5), round(ref.imag, 5)]}
+        pap = paper_theta(c["eps"], c["beta_p"])
+        if pap is not None:
+            row["paper_mg_hlbm"] = [pap.real, pap.imag]
         if th is not None:
             row["dev_re"] = round((th.real - ref.real) / ref.real, 4)
             row["dev_im"] = round((th.imag - ref.imag) / ref.imag, 4)
             devs_re.append(abs(row["dev_re"]))
             devs_im.append(abs(row["dev_im"]))
+            if pap is not None:
+                row["dev_paper_re"] = round((th.real - pap.real) / pap.real, 4)
+                row["dev_paper_im"] = round((th.imag - pap.imag) / pap.imag, 4)
+                pdev_re.append(abs(row["dev_paper_re"]))
+                pdev_im.append(abs(row["dev_paper_im"]))
         rows.append(row)
     import statistics
     return {"metric": "the paper's (epsilon, beta) study: Theta per case, cases/hour", "unit": "cases/hour",
@@ -552,7 +573,9 @@ def study_leg(b=64, storage="f64", tune_steps=8, chunk=2000):
             "tau": [round(min(c["tau"] for c in cases), 4), round(max(c["tau"] for c in cases), 4)], "schedule": sched, "setup_s": round(t1 - t0, 2), "run_s": round(t2 - t1, 2),
             "value": round(len(cases) / ((t2 - t0) / 3600.0), 1),
             "median_abs_dev_re": statistics.median(devs_re) if devs_re else None,
-            "median_abs_dev_im": statistics.median(devs_im) if devs_im else None, "per_case": rows}
+            "median_abs_dev_im": statistics.median(devs_im) if devs_im else None,
+            "median_abs_dev_paper_re": statistics.median(pdev_re) if pdev_re else None,
+            "median_abs_dev_paper_im": statistics.median(pdev_im) if pdev_im else None, "per_case": rows}
 
 
 def levels_leg(b=800, nlevels=4, storage="f64", steps=40, warmup=4, uniform=True):
@@ -606,23 +629,27 @@ def levels_leg(b=800, nlevels=4, storage="f64", steps=40, warmup=4, uniform=True
     return out
 
 
-def levels_theta_leg(b=256, nlevels=4, eps=0.1, beta=20.0, tau=0.8, storage="f64", periods=4.2, chunk=2048):
+def levels_theta_leg(b=256, nlevels=4, eps=0.1, beta=20.0, tau=0.8, storage="f64", periods=4.2, chunk=2048,
+                     uniform=True, n_sub=0):
     """Theta of the lamina on the finest of the paper's refinement levels
     against one uniform lattice at the finest resolution over the same
     5L x 5L domain (same grid, tau, boundaries), and the time each takes;
     the semianalytical value of the paper's Eqs. (hydro_gamma),(hydro_delta)
-    beside them as context."""
+    and, for one of its cases, the paper's own MG-HLBM value beside them as
+    context."""
     import torch
     from paper_2006_13631_amd import hlbm as H
     from paper_2006_13631_amd.theory import theta_semianalytical
     from paper_2006_13631_amd.workloads import paper_levels
     d = paper_levels(b=b, nlevels=nlevels, eps=eps, beta=beta, tau=tau, margin=8)
+    if n_sub:
+        d["fine"]["n_sub"] = n_sub  # grid sub-steps per step (0: the smallest stable count)
     per = 2 ** (nlevels - 1)
     nu = (tau - 0.5) / 3.0
     period = b * b / (nu * beta)  # finest steps
     n0 = int(math.ceil(periods * period / per))
     runs = {}
-    for kind in ("levels", "uniform"):
+    for kind in ("levels", "uniform") if uniform else ("levels",):
         if kind == "levels":
             c = H.MultiLevel(d["nx0"], d["ny0"], d["boxes"], bc0=d["bc0"], storage=H.STORAGE[storage],
                              max_steps=n0 * per, **d["fine"])
@@ -645,20 +672,27 @@ def levels_theta_leg(b=256, nlevels=4, eps=0.1, beta=20.0, tau=0.8, storage="f64
         th = c.theta(1.0, 4.0)
         runs[kind] = {"theta": [th.real, th.imag], "s": round(dt, 3),
                       "ms_per_finest_step": round(dt / (total * unit) * 1e3, 4)}
+        runs[kind]["n_sub"] = int(c.info().n_sub)
         if kind == "levels":
             runs[kind]["levels"] = [list(sh) for sh in c.shapes]
         else:
             runs[kind]["lattice"] = [5 * b + 1, 5 * b + 1]
         c.close()
     tl = complex(*runs["levels"]["theta"])
-    tu = complex(*runs["uniform"]["theta"])
     ts = theta_semianalytical(beta, eps)
-    return {"workload": f"paper_levels_{b}_theta", "storage": storage, "nlevels": nlevels, "eps": eps,
-            "beta": beta, "tau_finest": tau, "grid": [4 * b, b], "finest_steps": n0 * per,
-            "period_steps": round(period, 1), **runs,
-            "theta_rel_diff_levels_vs_uniform": abs(tl - tu) / abs(tu),
-            "speedup_vs_uniform": round(runs["uniform"]["s"] / runs["levels"]["s"], 3),
-            "theta_semianalytical": [ts.real, ts.imag]}
+    out = {"workload": f"paper_levels_{b}_theta", "storage": storage, "nlevels": nlevels, "eps": eps,
+           "beta": beta, "tau_finest": tau, "grid": [4 * b, b],
+           "finest_steps": n0 * per, "period_steps": round(period, 1), **runs,
+           "theta_semianalytical": [ts.real, ts.imag]}
+    if uniform:
+        tu = complex(*runs["uniform"]["theta"])
+        out["theta_rel_diff_levels_vs_uniform"] = abs(tl - tu) / abs(tu)
+        out["speedup_vs_uniform"] = round(runs["uniform"]["s"] / runs["levels"]["s"], 3)
+    pap = paper_theta(eps, beta)
+    if pap is not None:
+        out["theta_paper_mg_hlbm"] = [pap.real, pap.imag]
+        out["theta_rel_diff_levels_vs_paper"] = abs(tl - pap) / abs(pap)
+    return out
 
 
 def coupled_leg(workload="lamina_2048", storage="f64", periods=2.5, mass_ratio=1.0, chunk=1000):
@@ -931,6 +965,13 @@ def main():
     ap.add_argument("--levels-theta", action="store_true",
                     help="run only Theta on 4 refinement levels (L = 256 at the finest) against a uniform "
                          "finest lattice over the same domain and print its line")
+    ap.add_argument("--lt-b", type=int, default=256, help="--levels-theta: L at the finest level")
+    ap.add_argument("--lt-eps", type=float, default=0.1)
+    ap.add_argument("--lt-beta", type=float, default=20.0)
+    ap.add_argument("--lt-tau", type=float, default=0.8, help="--levels-theta: tau at the finest level")
+    ap.add_argument("--lt-periods", type=float, default=4.2)
+    ap.add_argument("--lt-no-uniform", action="store_true")
+    ap.add_argument("--lt-n-sub", type=int, default=0, help="--levels-theta: grid sub-steps per step (0: auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
@@ -963,7 +1004,9 @@ def main():
         return
     if args.levels_theta:
         torch.cuda.set_device(0)
-        print(json.dumps(levels_theta_leg(storage=args.levels_storage)), flush=True)
+        print(json.dumps(levels_theta_leg(b=args.lt_b, eps=args.lt_eps, beta=args.lt_beta, tau=args.lt_tau,
+                                          storage=args.levels_storage, periods=args.lt_periods,
+                                          uniform=not args.lt_no_uniform, n_sub=args.lt_n_sub)), flush=True)
         return
     if args.levels:
         torch.cuda.set_device(0)
