@@ -46,7 +46,7 @@ struct AdjCtx {
   // grid
   dev::GridGeom gg;
   int nnode, n_iface, n_wall;
-  const int *cls;
+  const int *ncode;  // per node: 16 class + 4 zero_diag + type (-1: no class)
   const GridClass<R> *tab;
   const int *iface;
   const int *wall_nodes;    // ids of the wall nodes

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(NG) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
   double pA = 0.0, pW = 0.0, pT = 0.0;
   if (q < c.nnode) {
     const int i = q % g.nux, j = q / g.nux;
-    const int tq = c.tab[c.cls[q]].type;
+    const int tq = c.ncode[q] & 3;
     // (a) this node's own type-1 refill: adjoint of the interpolated moments
     R z[12];
 #pragma unroll
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(NG) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
     for (int jj = jlo; jj <= jhi; ++jj) {
       for (int ii = max(i - 1, 0); ii <= min(i + 1, g.nux - 1); ++ii) {
         const int p = jj * g.nux + ii;
-        if (c.tab[c.cls[p]].type == NODE_WALL) continue;
+        if ((c.ncode[p] & 3) == NODE_WALL) continue;
         const RefillCell r = refill_cell(g, c.P.ybase, c.P.ybase1, ii, jj);
         if (r.kind != 3) continue;
         int node[3];

@@ -318,7 +318,13 @@ class Case final : public CaseBase {
       }
       if (!grid_.mesh) {
         HIPCHK(upload(&tab_, tab.data(), tab.size() * sizeof(GridClass<R>)));
-        HIPCHK(upload(&cls_, grid_.cls.data(), grid_.cls.size() * sizeof(int)));
+        // node codes: 16 class + 4 zero_diag + type (static: the grid moves rigidly)
+        std::vector<int> code(grid_.cls.size());
+        for (size_t p = 0; p < code.size(); ++p) {
+          const int k = grid_.cls[p];
+          code[p] = k >= 0 ? 16 * k + 4 * tab[k].zero_diag + tab[k].type : -1;
+        }
+        HIPCHK(upload(&ncode_, code.data(), code.size() * sizeof(int)));
       }
       HIPCHK(upload(&iface_, grid_.iface.data(), grid_.iface.size() * sizeof(int)));
       HIPCHK(upload(&wall_, grid_.wall.data(), grid_.wall.size() * sizeof(WallEdge)));
@@ -1523,7 +1529,7 @@ class Case final : public CaseBase {
       v.body = body_;
       v.gx = dgx_;
       v.gy = dgy_;
-      v.cls = cls_;
+      v.ncode = ncode_;
       v.tab = tab_;
       v.iface = iface_;
       if (grid_.mesh) {
@@ -1822,7 +1828,7 @@ class Case final : public CaseBase {
     c.nnode = N;
     c.n_iface = (int)grid_.iface.size();
     c.n_wall = (int)wn.size();
-    c.cls = cls_;
+    c.ncode = ncode_;
     c.tab = tab_;
     c.iface = iface_;
     c.wall_nodes = wall_nodes_;
@@ -2005,7 +2011,7 @@ class Case final : public CaseBase {
   int gcur_ = 0;
   R *star_f_ = nullptr, *star_n_ = nullptr;
   GridClass<R> *tab_ = nullptr;
-  int *cls_ = nullptr, *iface_ = nullptr;
+  int *ncode_ = nullptr, *iface_ = nullptr;
   // unstructured grid (device copies of the HostGrid mesh fields)
   int *m_row_ = nullptr, *m_col_ = nullptr, *m_type_ = nullptr, *m_tri_ = nullptr;
   int *m_bstart_ = nullptr, *m_blist_ = nullptr;

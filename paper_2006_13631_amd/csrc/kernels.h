@@ -51,7 +51,9 @@ struct CaseView {
   double h, xc, yc, half_b, half_T;
   int body;
   const double *gx, *gy;  // graded grid: local x of each column, y of each row (null: uniform)
-  const int *cls;
+  // per grid node: 16 class + 4 zero_diag + type of its stencil class
+  // (-1: no class), so a kernel learns a node's type and stencil in one load
+  const int *ncode;
   const GridClass<R> *tab;
   const int *iface;
   const WallEdge *wall;

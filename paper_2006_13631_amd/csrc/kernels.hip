@@ -399,7 +399,7 @@ constexpr bool substeps_double_buffer() {
 template <class R, class G, int H, int NT, bool DB = false>
 __device__ __forceinline__ void grid_substeps_block(
     const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
-    const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int t,
+    const int *__restrict__ ncode, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int t,
     R dt, R dt_tau, const R *__restrict__ uw, int64_t k, int n_sub, int m0, int count,
     R *__restrict__ tape, R *__restrict__ wtape, const int *__restrict__ widx, int nwall) {
   constexpr int TX = G::TX, TY = G::TY, RX = G::RX, RN = G::RN;
@@ -432,10 +432,7 @@ __device__ __forceinline__ void grid_substeps_block(
       const size_t p = in ? (size_t)gj * nux + gi : 0;
 #pragma unroll
       for (int q = 0; q < 9; ++q) v[u][q] = in ? f[q * N + p] : R(0);
-      if (idx < RN) {
-        const int c = in ? cls[p] : -1;
-        scode[idx] = c >= 0 ? 16 * c + 4 * tab[c].zero_diag + tab[c].type : -1;
-      }
+      if (idx < RN) scode[idx] = in ? ncode[p] : -1;
       if (touches_ring && in) {
         const int rs = ring_slot<G>(gi, gj, idx % RX, idx / RX, nux, nuy);
         if (rs >= 0) {
@@ -668,14 +665,14 @@ template <> struct SubstepVariant<10> : SubstepShape<32, 8, 384, 2> {};
 template <class R, int V>
 __global__ __launch_bounds__(SubstepVariant<V>::NT) void k_grid_substeps(
     const R *__restrict__ f, R *__restrict__ fout, const R *__restrict__ star_f, const R *__restrict__ star_n,
-    const int *__restrict__ cls, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int ntiles,
+    const int *__restrict__ ncode, const GridClass<R> *__restrict__ tab, int nux, int nuy, int tiles_x, int ntiles,
     R dt, R dt_tau, const R *__restrict__ uw, const int64_t *__restrict__ dk, int n_sub, int m0, int count,
     R *__restrict__ tape, R *__restrict__ wtape, const int *__restrict__ widx, int nwall) {
   using SV = SubstepVariant<V>;
   const int b = blockIdx.x;  // tiles are dealt to the eight XCDs in contiguous bands
   const int t = (ntiles % 8 == 0) ? (b % 8) * (ntiles / 8) + (b / 8) : b;
   grid_substeps_block<R, typename SV::G, SV::H, SV::NT, substeps_double_buffer<R, typename SV::G>()>(
-      f, fout, star_f, star_n, cls, tab, nux, nuy, tiles_x, t, dt, dt_tau, uw, *dk, n_sub, m0, count, tape, wtape,
+      f, fout, star_f, star_n, ncode, tab, nux, nuy, tiles_x, t, dt, dt_tau, uw, *dk, n_sub, m0, count, tape, wtape,
       widx, nwall);
 }
 
@@ -691,7 +688,7 @@ __global__ __launch_bounds__(SubstepVariant<V>::NT) void kb_grid_substeps(const 
   const int cur = grid_cur(v, k), i = m0 / kSubstepBlock;
   const int tiles_x = (v.nux + SV::G::TX - 1) / SV::G::TX;
   grid_substeps_block<R, typename SV::G, kSubstepBlock, SV::NT>(
-      v.grid[cur ^ (i & 1)], v.grid[cur ^ ((i + 1) & 1)], v.star_f, v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x,
+      v.grid[cur ^ (i & 1)], v.grid[cur ^ ((i + 1) & 1)], v.star_f, v.star_n, v.ncode, v.tab, v.nux, v.nuy, tiles_x,
       it.y, v.dt_u, v.dt_over_tau_u, v.uw, k, v.n_sub, m0, min(kSubstepBlock, v.n_sub - m0), nullptr, nullptr,
       nullptr, 0);
 }
@@ -903,7 +900,7 @@ __device__ __forceinline__ void refill_block(const CaseView<T, R> &v, const T *_
   if (p >= v.nnode) return;
   const size_t N = (size_t)v.nnode;
   R out[9];
-  if ((v.mesh ? v.m_type[p] : v.tab[v.cls[p]].type) == NODE_WALL) {
+  if ((v.mesh ? v.m_type[p] : (v.ncode[p] & 3)) == NODE_WALL) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) fn[q * N + p] = fo[q * N + p];
     return;
@@ -1165,7 +1162,7 @@ __device__ __forceinline__ void batch_item(const CaseView<T, R> *__restrict__ vi
       const int i = m0 / kSubstepBlock;
       const int tiles_x = (v.nux + SV::G::TX - 1) / SV::G::TX;
       grid_substeps_block<R, typename SV::G, kSubstepBlock, SV::NT>(
-          v.grid[cur ^ (i & 1)], v.grid[cur ^ ((i + 1) & 1)], v.star_f, v.star_n, v.cls, v.tab, v.nux, v.nuy,
+          v.grid[cur ^ (i & 1)], v.grid[cur ^ ((i + 1) & 1)], v.star_f, v.star_n, v.ncode, v.tab, v.nux, v.nuy,
           tiles_x, it.y, v.dt_u, v.dt_over_tau_u, v.uw, k, v.n_sub, m0, min(kSubstepBlock, v.n_sub - m0), nullptr,
           nullptr, nullptr, 0);
       break;
@@ -1472,13 +1469,13 @@ void Kernels<T, R>::grid_substeps_v(const CaseView<T, R> &v, const R *f, R *fout
   if (start || stop)
     hipExtLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT), lds, s, start, stop, 0,
                           f, fout,
-                          (const R *)v.star_f, (const R *)v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x,
+                          (const R *)v.star_f, (const R *)v.star_n, v.ncode, v.tab, v.nux, v.nuy, tiles_x,
                           tiles_x * tiles_y, v.dt_u, v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m0,
                           count, tape, wtape, widx, nwall);
   else
     hipLaunchKernelGGL((k_grid_substeps<R, V>), dim3(tiles_x * tiles_y), dim3(SV::NT), lds, s, f, fout,
                        (const R *)v.star_f,
-                       (const R *)v.star_n, v.cls, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u,
+                       (const R *)v.star_n, v.ncode, v.tab, v.nux, v.nuy, tiles_x, tiles_x * tiles_y, v.dt_u,
                        v.dt_over_tau_u, v.uw, (const int64_t *)v.dk, v.n_sub, m0, count, tape, wtape, widx, nwall);
 }
 
