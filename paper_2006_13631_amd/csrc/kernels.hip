@@ -539,16 +539,26 @@ __device__ __forceinline__ void grid_substeps_block(
   // copy a sub-step reads (offset into the LDS values); DB: the other copy
   // receives its results
   auto copy_of = [&](int sub) { return DB ? (sub & 1) * NS * RN : 0; };
+  // the node codes never change within a launch: each sub-step's are read
+  // before the barrier that ends the previous one
+  int nidx[PER], ncd[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) lane_node(0, u, nidx[u], ncd[u]);
 #pragma unroll
   for (int sub = 0; sub < H; ++sub) {
     if (sub >= count) break;
     const R uw_now = uwv[sub];
     const int cur = copy_of(sub), nxt = copy_of(sub + 1);
     R out[PER][9];
+    int sidx[PER], scd[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      int idx, code;
-      lane_node(sub, u, idx, code);
+      sidx[u] = nidx[u];
+      scd[u] = ncd[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = sidx[u], code = scd[u];
 #pragma unroll
       for (int q = 0; q < 9; ++q) out[u][q] = R(0);
       if (__ballot(code >= 0) == 0) continue;  // nothing to update in this wave
@@ -599,8 +609,7 @@ __device__ __forceinline__ void grid_substeps_block(
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
-        int idx, code;
-        lane_node(sub, u, idx, code);
+        const int idx = sidx[u], code = scd[u];
         if (code < 0) continue;
         R P[3];
         quad_moments<R>(out[u], P);
@@ -610,6 +619,9 @@ __device__ __forceinline__ void grid_substeps_block(
         for (int a = 0; a < 3; ++a) sl[idx * NS + 9 + a] = P[a];
       }
     }
+    if (sub + 1 < count)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) lane_node(sub + 1, u, nidx[u], ncd[u]);
     __syncthreads();
     // the tile is exact after every sub-step: a tape keeps the intermediate ones
     if (tape && sub + 1 < count) {
