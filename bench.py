@@ -228,6 +228,7 @@ def adjoint_leg(workload, storage, W_ckpt, fd_step, steps=None):
     case.timing(True)
     case.adjoint(w)
     ms, cnt = case.timing_get(H.K_ADJ_STREAM_COLLIDE)
+    ms_sub, cnt_sub = case.timing_get(H.K_ADJ_SUBSTEPS)
     case.timing(False)
     sT = BYTES[{H.FP64: "f64", H.FP32: "f32", H.FP16_DEV: "f16dev"}[storage]]
     sR = 8 if storage == H.FP64 else 4
@@ -312,6 +313,8 @@ def adjoint_leg(workload, storage, W_ckpt, fd_step, steps=None):
         "fd_rel_err": {k: float(abs(fd[k] - adj_cfg[k]) / abs(adj_cfg[k])) for k in fd},
         "kernel": "k_adj_stream_collide", "kernel_avg_us": round(k1_avg * 1e6, 3),
         "kernel_bytes_per_launch": k1_bytes, "kernel_gbs": round(k1_bytes / k1_avg / 1e9, 1),
+        "substeps_kernel": "k_adj_substeps", "substeps_launch_us": round(ms_sub * 1e3 / max(cnt_sub, 1), 3),
+        "substeps_per_launch": min(4, info.n_sub),
     }
 
 

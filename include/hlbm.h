@@ -457,6 +457,10 @@ int hlbm_get_stencil(hlbm_t *h, int32_t kmax, int32_t *nbr, double *S,
 #define HLBM_K_SUBSTEP_LAUNCH 8 /* level 3: each grid sub-step launch of a step
                                    (up to 16 per step; up to 4 sub-steps each,
                                    Eq.(ulbe)), count = launches timed        */
+#define HLBM_K_ADJ_SUBSTEPS 9   /* hlbm_adjoint with timing on: the first
+                                   reverse grid sub-step launch of every step
+                                   (up to 4 sub-steps backwards), by events at
+                                   its own start and end; count = launches  */
 int hlbm_timing(hlbm_t *h, int32_t on);
 int hlbm_timing_get(hlbm_t *h, int32_t kernel, double *total_ms, int64_t *count);
 

@@ -93,8 +93,10 @@ struct AdjKernels {
   // its A, omega derivatives in sc, index m_hi - m), then the transposed
   // stencil; ub -> ub_out; tape0: the step's taped grid states, sub-step m
   // at tape0 + 9 m nnode; first/last: the launch holds m = n-1 / m = 0
+  // start, stop (optional): events taken at the launch's own start and end
   static void substeps(const AdjCtx<T, R> &c, const R *tape0, const R *ub, R *ub_out, int m_hi, int count,
-                       const AdjSubScal<R> &sc, int first, int last, int slot0, hipStream_t s);
+                       const AdjSubScal<R> &sc, int first, int last, int slot0, hipStream_t s,
+                       hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
   // lattice side: donor gather E, stream-collide adjoint, grid-to-lattice adjoint
   static void donor_gather(const AdjCtx<T, R> &c, int slot0, hipStream_t s);
   static void stream_collide(const AdjCtx<T, R> &c, int slot0, hipStream_t s, hipEvent_t start = nullptr,

@@ -785,9 +785,14 @@ int AdjKernels<T, R>::substep_slots(const AdjCtx<T, R> &c) {
 }
 template <class T, class R>
 void AdjKernels<T, R>::substeps(const AdjCtx<T, R> &c, const R *tape0, const R *ub, R *ub_out, int m_hi, int count,
-                                const AdjSubScal<R> &sc, int first, int last, int slot0, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_substeps<T, R>), dim3(substep_slots(c)), dim3(ANT), 0, s, c, tape0, ub, ub_out, m_hi,
-                     count, sc, first, last, slot0);
+                                const AdjSubScal<R> &sc, int first, int last, int slot0, hipStream_t s,
+                                hipEvent_t start, hipEvent_t stop) {
+  if (start || stop)
+    hipExtLaunchKernelGGL((k_adj_substeps<T, R>), dim3(substep_slots(c)), dim3(ANT), 0, s, start, stop, 0, c, tape0,
+                          ub, ub_out, m_hi, count, sc, first, last, slot0);
+  else
+    hipLaunchKernelGGL((k_adj_substeps<T, R>), dim3(substep_slots(c)), dim3(ANT), 0, s, c, tape0, ub, ub_out, m_hi,
+                       count, sc, first, last, slot0);
 }
 
 template <class T, class R>

@@ -1637,6 +1637,10 @@ class Case final : public CaseBase {
         tms_[HLBM_K_ADJ_STREAM_COLLIDE] += ms;
         tcount_[HLBM_K_ADJ_STREAM_COLLIDE] += 1;
       }
+      if (has_grid_ && hipEventElapsedTime(&ms, tev_adj_ring_[i][2], tev_adj_ring_[i][3]) == hipSuccess) {
+        tms_[HLBM_K_ADJ_SUBSTEPS] += ms;
+        tcount_[HLBM_K_ADJ_SUBSTEPS] += 1;
+      }
     }
     aslot_ = 0;
     return hipSuccess;
@@ -1942,8 +1946,10 @@ class Case final : public CaseBase {
         sc.duwA[i] = om * std::cos(om * tm);
         sc.duwW[i] = A * std::cos(om * tm) - A * om * tm * std::sin(om * tm);
       }
+      const bool timed = timing_ && m_hi == d_.n - 1;  // the step's first reverse launch
       AK::substeps(c, tape_grid(tape, j, 0), agrid_[gin], agrid_[1 - gin], m_hi, count, sc, m_hi == d_.n - 1,
-                   m_hi - count + 1 == 0, slot_sub_, s_main_);
+                   m_hi - count + 1 == 0, slot_sub_, s_main_, timed ? tev_adj_ring_[aslot_][2] : nullptr,
+                   timed ? tev_adj_ring_[aslot_][3] : nullptr);
       gin = 1 - gin;
     }
     AK::donor_gather(c, slot_eg_, s_main_);
@@ -1988,7 +1994,7 @@ class Case final : public CaseBase {
   int lattice_order_ = 0;  // 1: stream-collide rows banded by XCD
   int two_step_order_ = 1;  // 1: two-step tiles in staggered runs per XCD (0: in turn)
   int order_code() const { return lattice_order_ | (two_step_order_ << 1); }
-  static constexpr int kTimedKernels = 9;  // HLBM_K_* ids
+  static constexpr int kTimedKernels = 10;  // HLBM_K_* ids
   double tms_[kTimedKernels] = {};
   int64_t tcount_[kTimedKernels] = {};
   int sub_mark_ = -1;  // timing slot whose first sub-step launch is timed (level 3)
@@ -2073,7 +2079,7 @@ class Case final : public CaseBase {
   int slot_refill_ = 0, slot_sub_ = 0, slot_eg_ = 0, slot_sc_ = 0, slot_fg_ = 0, slot_fgg_ = 0,
       nslots_ = 0;
   hipEvent_t tev_adj_[4] = {};
-  hipEvent_t tev_adj_ring_[kTimingRing][2] = {};
+  hipEvent_t tev_adj_ring_[kTimingRing][4] = {};  // lattice adjoint, first sub-step launch
   int aslot_ = 0;
 };
 

@@ -22,7 +22,7 @@ STATE_MOTION = 4
 STATE_LEVEL = 16
 MAX_LEVELS = 8
 (K_STREAM_COLLIDE, K_LATTICE_FROM_GRID, K_GRID_SUBSTEPS, K_REFILL, K_FORCE, K_STEP,
- K_ADJ_STREAM_COLLIDE, K_ADJOINT, K_SUBSTEP_LAUNCH) = range(9)
+ K_ADJ_STREAM_COLLIDE, K_ADJOINT, K_SUBSTEP_LAUNCH, K_ADJ_SUBSTEPS) = range(10)
 STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV}
 
 EXPORTS = ("hlbm_create", "hlbm_step", "hlbm_force", "hlbm_adjoint", "hlbm_get_state",

@@ -231,6 +231,25 @@ def test_adjoint_is_reproducible_and_leaves_forward_state():
     assert np.array_equal(g.lattice(), ref.lattice())
 
 
+def test_adjoint_timing_records_substep_launches():
+    """With timing on, hlbm_adjoint times the lattice adjoint and the first
+    reverse sub-step launch of every step by their own events, and the
+    gradient is the untimed one bit for bit."""
+    _say("adjoint timing")
+    c = _cfg("tiny_adjoint")
+    w = _weights(30, 17)
+    g = hlbm.Case(max_steps=30, ckpt_every=8, **c)
+    g.step(30)
+    a0 = g.adjoint(w)
+    g.timing(1)
+    a1 = g.adjoint(w)
+    ms, n = g.timing_get(hlbm.K_ADJ_SUBSTEPS)
+    ms_l, n_l = g.timing_get(hlbm.K_ADJ_STREAM_COLLIDE)
+    g.timing(0)
+    assert np.array_equal(a0, a1)
+    assert n == 30 and n_l == 30 and ms > 0 and ms_l > 0
+
+
 def test_adjoint_errors():
     c = _cfg("tiny_adjoint")
     g = hlbm.Case(max_steps=10, **c)
