@@ -52,7 +52,8 @@ struct AdjCtx {
   const int *wall_nodes;    // ids of the wall nodes
   const int *widx;          // per grid node: its index among the wall nodes, -1 otherwise
   const unsigned char *ntype;  // per grid node: NodeType
-  const int *acls;          // per grid node: transposed stencil class
+  const int *acls;          // per grid node: 4 transposed stencil class + the diagonal slot
+                            // pairs it lacks (bit 0: slots 2 and 6, bit 1: 0 and 8)
   const AdjClass<R> *atab;
   const double *wall_nrm;   // [2][nnode]: sum over a wall node's edges of (len/2) n
   const R *wt;              // [n][3][n_wall] wall-node moments before the velocity is imposed

@@ -33,6 +33,8 @@
 // fixed slots and reduced once at the end.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "adjoint.h"
 
 namespace mghlbm {
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(ANT) void k_adj_substeps(AdjCtx<T, R> c, const R *_
   constexpr int SPER = (RN + ANT - 1) / ANT;
   constexpr int PER = ((ATX + 2 * (H - 1)) * (ATY + 2 * (H - 1)) + ANT - 1) / ANT;
   __shared__ R sob[RN * 9];              // adjoint of the region's grid state
-  __shared__ int scls[RN];               // transposed stencil class, -1 outside the grid
+  __shared__ int scls[RN];               // acls of the node, -1 outside the grid
   __shared__ R acc[ATX * ATY * 18];      // running sums (sf, sn) of the tile's interface nodes
   const GridGeom &g = c.gg;
   const size_t N = (size_t)c.nnode;
@@ -325,23 +327,30 @@ __global__ __launch_bounds__(ANT) void k_adj_substeps(AdjCtx<T, R> c, const R *_
       const int j = threadIdx.x + u * ANT;
       const int rx = o + j % W, ry = o + j / W;
       const int ci = j < NA ? ry * RX + rx : 0;
-      const int cls = j < NA ? scls[ci] : -1;
+      const int acode = j < NA ? scls[ci] : -1;  // 4 class + zero slot pairs
       at[u] = ci;
-      upd[u] = cls >= 0;
+      upd[u] = acode >= 0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) out[u][k] = R(0);
+      // a wave whose nodes all lack the same two diagonal neighbours skips
+      // those slots (zero weights: the sums are the same)
+      const int zl = acode >= 0 ? acode & 3 : 3;
+      const int zd = __ballot(!(zl & 1)) == 0 ? 1 : (__ballot(!(zl & 2)) == 0 ? 2 : 0);
       if (!upd[u]) continue;
       const size_t q = (size_t)(y0 + ry) * g.nux + (x0 + rx);
       R f[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) f[k] = Um[k * N + q];
-      const AdjClass<R> &cl = c.atab[cls];
+      const AdjClass<R> &cl = c.atab[acode >> 2];
       const int tq = cl.type, star = cl.star;
       R accF[9], accN[9], sf[9], sn[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) accF[k] = accN[k] = sf[k] = sn[k] = R(0);
+      auto gather = [&](auto mask) {
+        constexpr int M = decltype(mask)::value;
 #pragma unroll
       for (int s = 0; s < NSLOT; ++s) {
+        if (!((M >> s) & 1)) continue;
         const int ri = ci + (s / 3 - 1) * RX + (s % 3 - 1);
         const R gx = cl.Gx[s], gy = cl.Gy[s], cc = cl.C[s];
         const bool st_s = (star >> s) & 1;
@@ -359,6 +368,13 @@ __global__ __launch_bounds__(ANT) void k_adj_substeps(AdjCtx<T, R> c, const R *_
           }
         }
       }
+      };
+      if (zd == 1)
+        gather(std::integral_constant<int, 0x1FF & ~(1 << 2 | 1 << 6)>{});
+      else if (zd == 2)
+        gather(std::integral_constant<int, 0x1FF & ~(1 << 0 | 1 << 8)>{});
+      else
+        gather(std::integral_constant<int, 0x1FF>{});
       // the node's own value: its f, or f* at an interface node
 #pragma unroll
       for (int k = 0; k < 9; ++k) {

@@ -1810,6 +1810,13 @@ class Case final : public CaseBase {
         at[k].type = atab[k].type;
       }
       HIPCHK(upload(&atab_, at.data(), at.size() * sizeof(AdjClass<R>)));
+      // per node: 4 class + the diagonal slot pairs its class lacks (bit 0:
+      // slots 2 and 6, bit 1: slots 0 and 8), which a wave may skip
+      for (int q = 0; q < N; ++q) {
+        const AdjClass<R> &a = at[acls[q]];
+        auto zero = [&](int s) { return a.C[s] == R(0) && a.Gx[s] == R(0) && a.Gy[s] == R(0); };
+        acls[q] = 4 * acls[q] + (zero(2) && zero(6) ? 1 : 0) + (zero(0) && zero(8) ? 2 : 0);
+      }
       HIPCHK(upload(&acls_, acls.data(), acls.size() * sizeof(int)));
       n_adj_classes_ = (int)at.size();
     }
