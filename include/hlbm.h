@@ -250,8 +250,8 @@ int hlbm_level_shape(hlbm_t *h, int32_t level, int32_t *nx, int32_t *ny,
  * finite-volume matrices follow the cells' own sizes; the fictitious
  * rectangle is the grid's bounding box inset by 2. Otherwise as
  * hlbm_create with ncases = 1 (the geometric checks use the grid's
- * extents). ckpt_every must be 0: hlbm_adjoint of a graded case returns
- * HLBM_E_UNSUPPORTED. */
+ * extents), checkpoints and hlbm_adjoint included: the derivatives of the
+ * interpolation weights in y_k follow each cell's own height. */
 int hlbm_create_graded(const hlbm_config *cfg, const double *x_nodes,
                        const double *y_nodes, hlbm_t **out);
 

@@ -158,6 +158,7 @@ def lib_cs():
         L = C.CDLL(_LIB_CS)
         vp = C.c_void_p
         L.or_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.or_create_graded.argtypes = [C.POINTER(Config), _D, _D, C.POINTER(vp)]
         L.or_destroy.argtypes = [vp]
         L.or_step.argtypes = [vp, C.c_int64]
         L.or_info_get.argtypes = [vp, C.POINTER(Info)]
@@ -517,15 +518,23 @@ class SimCS:
     ``SimCS(h_A, h_omega, h_tau, **cfg)`` adds i*h to A, omega and tau_s
     (tau_u = tau_s - 1/2 follows). After ``step``, ``history()`` returns the
     real force history and its imaginary part; divided by h the latter is
-    the exact derivative of the history along that direction."""
+    the exact derivative of the history along that direction. ``x_nodes``
+    and ``y_nodes`` give a graded grid, as for :class:`Sim`."""
 
     def __init__(self, h_A=0.0, h_omega=0.0, h_tau=0.0, *, nx, ny, nux=0, nuy=0, h_u=1.0,
                  b=0.0, thickness=1.0, tau=0.8, kc=0.0, beta=0.0, n_sub=0,
-                 bc=BC_PERIODIC_X_WALLS_Y, flags=0, max_steps=0):
+                 bc=BC_PERIODIC_X_WALLS_Y, flags=0, max_steps=0, x_nodes=None, y_nodes=None):
         self.cfg = Config(nx, ny, nux, nuy, h_u, b, thickness, tau, kc, beta, n_sub, bc, flags,
                           max_steps)
         h = C.c_void_p()
-        rc = lib_cs().or_create(C.byref(self.cfg), C.byref(h))
+        if x_nodes is not None or y_nodes is not None:  # graded grid
+            gx = np.ascontiguousarray(x_nodes, dtype=np.float64)
+            gy = np.ascontiguousarray(y_nodes, dtype=np.float64)
+            if gx.shape != (nux,) or gy.shape != (nuy,):
+                raise ValueError("x_nodes and y_nodes need nux and nuy entries")
+            rc = lib_cs().or_create_graded(C.byref(self.cfg), gx, gy, C.byref(h))
+        else:
+            rc = lib_cs().or_create(C.byref(self.cfg), C.byref(h))
         if rc != 0:
             raise ValueError(f"or_create rejected the configuration (code {rc})")
         self.ptr = h

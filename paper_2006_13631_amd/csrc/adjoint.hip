@@ -89,9 +89,23 @@ __device__ __forceinline__ double dot12(const R z[12], R rho, R ux, R uy, const 
 }
 
 // x coordinate of grid column i and y coordinate of grid row j at base yb
-__device__ __forceinline__ double grid_x(const GridGeom &g, int i) { return g.xc + (double)(i - g.nux / 2) * g.h; }
+// (the same expressions as the forward kernels, graded or uniform)
+__device__ __forceinline__ double grid_x(const GridGeom &g, int i) {
+  return g.gx ? g.xc + g.gx[i] : g.xc + (double)(i - g.nux / 2) * g.h;
+}
 __device__ __forceinline__ double grid_y(const GridGeom &g, double yb, int j) {
-  return yb + ((double)j - 0.5 * (double)(g.nuy - 1)) * g.h;
+  return g.gy ? yb + g.gy[j] : yb + ((double)j - 0.5 * (double)(g.nuy - 1)) * g.h;
+}
+// height of grid cell row cj (rows cj, cj + 1)
+__device__ __forceinline__ double cell_height(const GridGeom &g, int cj) {
+  return g.gy ? g.gy[cj + 1] - g.gy[cj] : g.h;
+}
+// first and last of the graded rows (columns) whose local coordinate lies in
+// [lo, hi], widened by `pad` on either side and clamped to the grid
+__device__ __forceinline__ void graded_span(const double *v, int n, double lo, double hi, int pad, int &first,
+                                            int &last) {
+  first = max(graded_cell(v, n, lo) - pad, 0);
+  last = min(graded_cell(v, n, hi) + 1 + pad, n - 1);
 }
 
 // ---- star: f*, f^neq* of step k and the interpolated moments ----------------
@@ -175,9 +189,15 @@ __global__ __launch_bounds__(NG) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
     double dsum = 0.0;
     // a new node jj lands near old row jj + delta; its triangle's rows are
     // within one (two next to the lamina) of that
-    const double delta = (c.P.ybase1 - c.P.ybase) / g.h;
-    const int jlo = max((int)ceil((double)j - 2.0 - delta) - 1, 0);
-    const int jhi = min((int)ceil((double)j + 2.0 - delta), g.nuy - 1);
+    int jlo, jhi;
+    if (g.gy) {  // graded: new rows whose position lies within old rows j - 2 .. j + 2
+      const double dy = c.P.ybase1 - c.P.ybase;
+      graded_span(g.gy, g.nuy, g.gy[max(j - 2, 0)] - dy, g.gy[min(j + 2, g.nuy - 1)] - dy, 1, jlo, jhi);
+    } else {
+      const double delta = (c.P.ybase1 - c.P.ybase) / g.h;
+      jlo = max((int)ceil((double)j - 2.0 - delta) - 1, 0);
+      jhi = min((int)ceil((double)j + 2.0 - delta), g.nuy - 1);
+    }
     for (int jj = jlo; jj <= jhi; ++jj) {
       for (int ii = max(i - 1, 0); ii <= min(i + 1, g.nux - 1); ++ii) {
         const int p = jj * g.nux + ii;
@@ -198,13 +218,15 @@ __global__ __launch_bounds__(NG) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
             acc[s] += l * u;
             d += (double)u * (double)un[s];
           }
-          dsum += dl[a] * d;
+          // graded: the cell coordinate b = (y_{k+1} - y_k + const)/(cell height)
+          dsum += g.gy ? dl[a] * d / cell_height(g, r.cj) : dl[a] * d;
         }
       }
     }
-    // the new node's old-grid coordinate t = (y_{k+1} - y_k)/h + const
-    pA += dsum * (c.dyA1 - c.dyA) / g.h;
-    pW += dsum * (c.dyW1 - c.dyW) / g.h;
+    // uniform: the new node's old-grid coordinate t = (y_{k+1} - y_k)/h + const
+    const double hs = g.gy ? 1.0 : g.h;
+    pA += dsum * (c.dyA1 - c.dyA) / hs;
+    pW += dsum * (c.dyW1 - c.dyW) / hs;
     // (c) force on the lamina at t_{k+1}
     if (tq == NODE_WALL) {
       const double nx = c.wall_nrm[q], ny = c.wall_nrm[N + q];
@@ -492,8 +514,13 @@ __global__ __launch_bounds__(NG) void k_adj_donor_gather(AdjCtx<T, R> c, int slo
 #pragma unroll
       for (int k = 0; k < 12; ++k) zs[k] = zA[k] = zW[k] = R(0);
       bool any = false;
-      const int ilo = max(0, (int)floor(((double)x - 1.0 - g.xc) / g.h) + g.nux / 2 - 1);
-      const int ihi = min(g.nux - 1, (int)ceil(((double)x + 1.0 - g.xc) / g.h) + g.nux / 2 + 1);
+      int ilo, ihi;
+      if (g.gx) {
+        graded_span(g.gx, g.nux, (double)x - 1.0 - g.xc, (double)x + 1.0 - g.xc, 1, ilo, ihi);
+      } else {
+        ilo = max(0, (int)floor(((double)x - 1.0 - g.xc) / g.h) + g.nux / 2 - 1);
+        ihi = min(g.nux - 1, (int)ceil(((double)x + 1.0 - g.xc) / g.h) + g.nux / 2 + 1);
+      }
       for (int i = ilo; i <= ihi; ++i) {
         const double X = grid_x(g, i);
         const int fx = (int)floor(X);
@@ -501,8 +528,14 @@ __global__ __launch_bounds__(NG) void k_adj_donor_gather(AdjCtx<T, R> c, int slo
         for (int pos = 0; pos < 2; ++pos) {  // 0: interface donors at y_k, 1: type-1 refill at y_{k+1}
           const double yb = pos ? c.P.ybase1 : c.P.ybase;
           const double dyA = pos ? c.dyA1 : c.dyA, dyW = pos ? c.dyW1 : c.dyW;
-          const double j0 = ((double)y - yb) / g.h + 0.5 * (double)(g.nuy - 1);
-          const int jlo = max(0, (int)floor(j0 - 1.0 / g.h) - 1), jhi = min(g.nuy - 1, (int)ceil(j0 + 1.0 / g.h) + 1);
+          int jlo, jhi;
+          if (g.gy) {
+            graded_span(g.gy, g.nuy, (double)y - 1.0 - yb, (double)y + 1.0 - yb, 1, jlo, jhi);
+          } else {
+            const double j0 = ((double)y - yb) / g.h + 0.5 * (double)(g.nuy - 1);
+            jlo = max(0, (int)floor(j0 - 1.0 / g.h) - 1);
+            jhi = min(g.nuy - 1, (int)ceil(j0 + 1.0 / g.h) + 1);
+          }
           const unsigned char need = pos ? 1 : 2;
           const R *Z = pos ? c.Z1 : c.Z2;
           for (int j = jlo; j <= jhi; ++j) {
@@ -702,12 +735,26 @@ __global__ __launch_bounds__(NG) void k_adj_from_grid_gather(AdjCtx<T, R> c, R *
   double pA = 0.0, pW = 0.0;
   if (q < c.nnode) {
     const int i = q % g.nux, j = q / g.nux;
-    const double X0 = grid_x(g, 0), Y0 = grid_y(g, c.P.ybase, 0);
     const int ybot = min(c.P.iy0, c.P.piy0), ytop = min(max(c.P.iy1, c.P.piy1), ybot + c.k2_h - 1);
-    const int xlo = max((int)floor(X0 + (double)(i - 1) * g.h) - 1, c.k2_x0);
-    const int xhi = min((int)ceil(X0 + (double)(i + 1) * g.h) + 1, c.k2_x0 + c.k2_w - 1);
-    const int ylo = max((int)floor(Y0 + (double)(j - 1) * g.h) - 1, ybot);
-    const int yhi = min((int)ceil(Y0 + (double)(j + 1) * g.h) + 1, ytop);
+    // lattice nodes in the cells around the node: between its neighbouring
+    // columns and rows, one lattice node wider
+    double xa, xb, ya, yb;
+    if (g.gx) {
+      xa = grid_x(g, max(i - 1, 0));
+      xb = grid_x(g, min(i + 1, g.nux - 1));
+      ya = grid_y(g, c.P.ybase, max(j - 1, 0));
+      yb = grid_y(g, c.P.ybase, min(j + 1, g.nuy - 1));
+    } else {
+      const double X0 = grid_x(g, 0), Y0 = grid_y(g, c.P.ybase, 0);
+      xa = X0 + (double)(i - 1) * g.h;
+      xb = X0 + (double)(i + 1) * g.h;
+      ya = Y0 + (double)(j - 1) * g.h;
+      yb = Y0 + (double)(j + 1) * g.h;
+    }
+    const int xlo = max((int)floor(xa) - 1, c.k2_x0);
+    const int xhi = min((int)ceil(xb) + 1, c.k2_x0 + c.k2_w - 1);
+    const int ylo = max((int)floor(ya) - 1, ybot);
+    const int yhi = min((int)ceil(yb) + 1, ytop);
     R zs[12], zd[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) zs[k] = zd[k] = R(0);
@@ -730,7 +777,8 @@ __global__ __launch_bounds__(NG) void k_adj_from_grid_gather(AdjCtx<T, R> c, R *
 #pragma unroll
         for (int n = 0; n < 3; ++n) {
           if (node[n] != q) continue;
-          const R l = R(lam[n]), d = R(dl[n]);
+          // graded: d b/d y_k = -1/(cell height) per cell (uniform: -1/h, below)
+          const R l = R(lam[n]), d = R(g.gy ? dl[n] / cell_height(g, cj) : dl[n]);
 #pragma unroll
           for (int k = 0; k < 12; ++k) {
             const R z = c.Z3[k * zp + at];
@@ -752,10 +800,11 @@ __global__ __launch_bounds__(NG) void k_adj_from_grid_gather(AdjCtx<T, R> c, R *
       node_chain<R>(rho, ux, uy, zs[0], zs[1], zs[2], zs + 3, fb);
 #pragma unroll
       for (int k = 0; k < 9; ++k) ub[k * N + q] += fb[k];
-      // the lattice node's grid coordinate t = (y - y_k)/h + const
+      // uniform: the lattice node's grid coordinate t = (y - y_k)/h + const
       const double dsum = dot12<R>(zd, rho, ux, uy, fneq);
-      pA += dsum * (-c.dyA / g.h);
-      pW += dsum * (-c.dyW / g.h);
+      const double hs = g.gy ? 1.0 : g.h;
+      pA += dsum * (-c.dyA / hs);
+      pW += dsum * (-c.dyW / hs);
     }
   }
   block_accum3<NG>(pA, pW, 0.0, c.part + 3 * (size_t)(slot0 + blockIdx.x));

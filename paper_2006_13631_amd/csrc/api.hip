@@ -1259,7 +1259,6 @@ class Case final : public CaseBase {
     if (ckW_ <= 0) return fail(HLBM_E_STATE, "case was created with ckpt_every = 0");
     if (!ck_valid_) return fail(HLBM_E_STATE, "state was replaced after step 0; the checkpoints no longer hold");
     if (fsi_) return fail(HLBM_E_UNSUPPORTED, "adjoint of a case with coupled motion");
-    if (!gx_.empty()) return fail(HLBM_E_UNSUPPORTED, "adjoint of a graded grid");
     if (n != k_ || n <= 0) return fail(HLBM_E_ARG, "the cotangent must cover every step taken (n = steps)");
     HIPCHK(hipStreamSynchronize(s_main_));
     int rc = adjoint_setup();
@@ -1696,8 +1695,11 @@ class Case final : public CaseBase {
     const int N = grid_.nnode;
     // lattice rows and columns that can be bilinear donors: the grid's
     // bounding box over the whole motion, one node wider
-    const double hx0 = (double)(0 - cfg_.nux / 2) * h_, hx1 = (double)(cfg_.nux - 1 - cfg_.nux / 2) * h_;
-    const double hy = 0.5 * (double)(cfg_.nuy - 1) * h_;
+    // (graded: the first and last column and row of the given spacing)
+    const bool graded = !gx_.empty();
+    const double hx0 = graded ? gx_.front() : (double)(0 - cfg_.nux / 2) * h_;
+    const double hx1 = graded ? gx_.back() : (double)(cfg_.nux - 1 - cfg_.nux / 2) * h_;
+    const double hy = graded ? std::max(-gy_.front(), gy_.back()) : 0.5 * (double)(cfg_.nuy - 1) * h_;
     double ymin = 1e300, ymax = -1e300;
     for (const StepParams &P : P_host_) {
       ymin = std::min(ymin, std::min(P.ybase, P.ybase1));
@@ -1835,7 +1837,7 @@ class Case final : public CaseBase {
     c.k_neq = v.k_neq;
     c.dt = v.dt_u;
     c.dt_tau = v.dt_over_tau_u;
-    c.gg = dev::GridGeom{cfg_.nux, cfg_.nuy, h_, d_.xc, v.half_b, v.half_T, (int)body_};
+    c.gg = dev::GridGeom{cfg_.nux, cfg_.nuy, h_, d_.xc, v.half_b, v.half_T, (int)body_, v.gx, v.gy};
     c.nnode = N;
     c.n_iface = (int)grid_.iface.size();
     c.n_wall = (int)wn.size();
@@ -3221,7 +3223,6 @@ int hlbm_create_graded(const hlbm_config *cfg, const double *x_nodes, const doub
   if (out) *out = nullptr;
   if (!cfg || !x_nodes || !y_nodes || !out) { g_create_error = "null argument"; return HLBM_E_ARG; }
   if (cfg->nux <= 0 || cfg->nuy <= 0) { g_create_error = "a graded case needs a grid"; return HLBM_E_ARG; }
-  if (cfg->ckpt_every != 0) { g_create_error = "a graded case takes no checkpoints (no adjoint)"; return HLBM_E_ARG; }
   std::string e;
   int rc = validate(*cfg, &e, false, x_nodes, y_nodes);
   if (rc != HLBM_OK) { g_create_error = e; return rc; }

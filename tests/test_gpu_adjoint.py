@@ -138,6 +138,41 @@ def test_adjoint_fine_grid_type2(oracle):
     _compare(gpu, ref)
 
 
+def _graded_cfg():
+    """A lamina on a grid refined toward it (spacing 0.5 near the lamina,
+    several grid rows per lattice cell, growing to 1.5)."""
+    from paper_2006_13631_amd.workloads import graded_nodes
+    return dict(nx=64, ny=48, nux=31, nuy=16, b=8.0, thickness=0.5, tau=0.8, kc=1.0, beta=20.0,
+                x_nodes=graded_nodes(31, 0.5, 1.25, 1.5, fine=5.0), y_nodes=graded_nodes(16, 0.5, 1.3, 1.5))
+
+
+@pytest.mark.parametrize("bc", [hlbm.BC_PERIODIC_X_WALLS_Y, hlbm.BC_PAPER])
+def test_adjoint_graded_grid(oracle, bc):
+    """Graded grid, random start: parameters and both initial-state
+    directions over several checkpoint windows (the derivatives of the
+    interpolation weights in y_k follow each cell's own height)."""
+    _say("adjoint graded grid, bc", bc)
+    c = dict(_graded_cfg(), bc=bc)
+    n = 24
+    f0, g0, dirs = _random_state(oracle, c, 71)
+    w = _weights(n, 15)
+    ref = _oracle_derivatives(oracle, c, n, w, f0, g0, dirs)
+    gpu, _ = _gpu_derivatives(c, n, w, f0, g0, dirs, ckpt=7)
+    _compare(gpu, ref)
+
+
+def test_adjoint_graded_grid_from_rest(oracle):
+    """Graded grid from rest over 150 steps (the grid moves through its
+    fine rows and the lamina sheds vorticity)."""
+    _say("adjoint graded grid from rest")
+    c = _graded_cfg()
+    n = 150
+    w = _weights(n, 16)
+    ref = _oracle_derivatives(oracle, c, n, w)
+    gpu, _ = _gpu_derivatives(c, n, w, ckpt=32)
+    _compare(gpu, ref)
+
+
 def test_adjoint_periodic_bc(oracle):
     _say("adjoint periodic bc")
     c = _cfg("tiny_adjoint", bc=hlbm.BC_PERIODIC)

@@ -74,9 +74,6 @@ def test_graded_refusals():
     with pytest.raises(hlbm.HlbmError) as e:  # thickness is the slot rows' spacing
         hlbm.Case(max_steps=4, x_nodes=GX, y_nodes=GY, **dict(CASE, thickness=1.0))
     assert e.value.code == hlbm.E_ARG
-    with pytest.raises(hlbm.HlbmError) as e:  # no checkpoints: no adjoint on graded grids
-        hlbm.Case(max_steps=4, ckpt_every=2, x_nodes=GX, y_nodes=GY, **CASE)
-    assert e.value.code == hlbm.E_ARG
 
 
 def test_fp32_graded_tracks_fp64(oracle):
