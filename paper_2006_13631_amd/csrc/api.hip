@@ -383,12 +383,14 @@ class Case final : public CaseBase {
   // Enqueue one structured step t_k -> t_{k+1} (host bookkeeping included).
   // Stream-collide with its own start and end events when timing is on
   // (the events are taken at the kernel's own start and end on its stream).
-  void stream_collide_timed(const CaseView<T, R> &v) {
+  // donors: the launch also computes the grid path's interface donors
+  void stream_collide_timed(const CaseView<T, R> &v, bool donors = false) {
     if (timing_ == 1 || timing_ == 2) {
       Kernels<T, R>::stream_collide(v, s_main_, tev_[tslot_][8], tev_[tslot_][2], lattice_threads_, lattice_rows_,
-                                    lattice_order_);
+                                    lattice_order_, donors);
     } else {
-      Kernels<T, R>::stream_collide(v, s_main_, nullptr, nullptr, lattice_threads_, lattice_rows_, lattice_order_);
+      Kernels<T, R>::stream_collide(v, s_main_, nullptr, nullptr, lattice_threads_, lattice_rows_, lattice_order_,
+                                    donors);
     }
   }
 
@@ -406,10 +408,13 @@ class Case final : public CaseBase {
         ENQ(hipEventRecord(ev_fork_, s_main_));
         ENQ(hipStreamWaitEvent(s_grid_, ev_fork_, 0));
       }
-      // 2. lattice stream-collide, Eq.(LBE)
-      stream_collide_timed(v);
+      // 2. lattice stream-collide, Eq.(LBE); on one stream (and unless the
+      // donors are timed apart) it also computes step 3's donors, which
+      // read the same source lattice
+      const bool fuse = s_grid_ == s_main_ && timing_ != 1;
+      stream_collide_timed(v, fuse);
       // 3.-6. grid path: donors, n sub-steps, refill, force
-      ENQ(enqueue_grid_path(v));
+      ENQ(enqueue_grid_path(v, fuse));
       if (s_grid_ != s_main_) {
         ENQ(hipEventRecord(ev_join_, s_grid_));
         ENQ(hipStreamWaitEvent(s_main_, ev_join_, 0));
@@ -427,11 +432,12 @@ class Case final : public CaseBase {
   }
 
   // Grid path of the step whose lattice (post-collision at t_k) v.A holds:
-  // donors, n sub-steps, refill, force (steps 3-6 of the step).
-  hipError_t enqueue_grid_path(const CaseView<T, R> &v) {
+  // donors (unless the lattice launch computed them), n sub-steps, refill,
+  // force (steps 3-6 of the step).
+  hipError_t enqueue_grid_path(const CaseView<T, R> &v, bool donors_done = false) {
     hipError_t e = hipSuccess;
     if (timing_ == 1) ENQ(hipEventRecord(tev_[tslot_][3], s_grid_));
-    Kernels<T, R>::interface_donors(v, s_grid_);
+    if (!donors_done) Kernels<T, R>::interface_donors(v, s_grid_);
     int cur = gcur_;
     const int blk = substep_block(substep_variant_);
     // level 3: every sub-step launch of the step (up to kTimedLaunches),
@@ -510,10 +516,14 @@ class Case final : public CaseBase {
       v.dkl = dk_copy_;
       ENQ(fork());
     }
-    if (timing_ == 2) Kernels<T, R>::stream_collide2(v, s_main_, tev_[tslot_][8], tev_[tslot_][2], two_step_order_);
-    else Kernels<T, R>::stream_collide2(v, s_main_, nullptr, nullptr, two_step_order_);
+    // on one stream the lattice launches also compute the donors of the grid
+    // path that follows them (both read only the lattice of t_k or t_{k+1})
+    const bool fuse = has_grid_ && !two;
+    if (timing_ == 2)
+      Kernels<T, R>::stream_collide2(v, s_main_, tev_[tslot_][8], tev_[tslot_][2], two_step_order_, fuse);
+    else Kernels<T, R>::stream_collide2(v, s_main_, nullptr, nullptr, two_step_order_, fuse);
     if (has_grid_) {
-      ENQ(enqueue_grid_path(v));
+      ENQ(enqueue_grid_path(v, fuse));
       if (two) ENQ(join());
       CaseView<T, R> w = view();
       w.A = (const T *)lat_[1];
@@ -527,8 +537,8 @@ class Case final : public CaseBase {
       Kernels<T, R>::lattice_from_grid(w, (const R *)gbuf_[gcur_], s_main_);
       // step k+1's grid path and the band's second step both read t_{k+1}
       if (two) ENQ(fork());
-      Kernels<T, R>::stream_collide(w, s_main_, nullptr, nullptr, lattice_threads_, lattice_rows_, 0);
-      ENQ(enqueue_grid_path(w));
+      Kernels<T, R>::stream_collide(w, s_main_, nullptr, nullptr, lattice_threads_, lattice_rows_, 0, fuse);
+      ENQ(enqueue_grid_path(w, fuse));
       if (two) ENQ(join());
     }
     if (timing_) ++tslot_;
@@ -1906,8 +1916,8 @@ class Case final : public CaseBase {
       v.B = tape_lat(t, j + 1);
       v.counts = counts_scratch_;
       Kernels<T, R>::lattice_from_grid(v, tape_grid(t, j, 0), st);
-      Kernels<T, R>::stream_collide(v, st, nullptr, nullptr, lattice_threads_, lattice_rows_, lattice_order_);
-      Kernels<T, R>::interface_donors(v, st);
+      // (the stream-collide launch also computes the interface donors)
+      Kernels<T, R>::stream_collide(v, st, nullptr, nullptr, lattice_threads_, lattice_rows_, lattice_order_, true);
       for (int m = 0; m < d_.n; m += kSubstepBlock) {
         const int cnt = std::min(kSubstepBlock, d_.n - m);
         // the tape is written in blocks of kSubstepBlock sub-steps

@@ -166,16 +166,20 @@ struct Kernels {
   // start/stop (optional): events recorded at the kernel's own start and end
   // threads x rows: workgroup width and lattice rows per lane (1, 2 or 4);
   // <= 0 takes kLatticeThreads / kLatticeRows; order 1: each XCD takes a
-  // contiguous band of rows
+  // contiguous band of rows; donors: the same launch also computes the
+  // grid's interface donors from v.A (as interface_donors), in workgroups of
+  // its own
   static void stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start = nullptr,
-                             hipEvent_t stop = nullptr, int threads = 0, int rows = 0, int order = 0);
+                             hipEvent_t stop = nullptr, int threads = 0, int rows = 0, int order = 0,
+                             bool donors = false);
   // two steps t_k -> t_{k+2} in one launch (tile of kTwoStepTX x kTwoStepTY
   // nodes, the first step on the tile and a one-node ring kept in LDS);
   // needs nx >= kTwoStepTX + 2 and ny >= kTwoStepTY + 2; order 1: the
   // tiles are dealt to the XCDs in contiguous runs of rows, each XCD
-  // starting at a different offset (0: in turn, row by row)
+  // starting at a different offset (0: in turn, row by row); donors: as
+  // for stream_collide
   static void stream_collide2(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start = nullptr,
-                              hipEvent_t stop = nullptr, int order = 0);
+                              hipEvent_t stop = nullptr, int order = 0, bool donors = false);
   static void lattice_from_grid(const CaseView<T, R> &v, const R *grid, hipStream_t s);
   static void interface_donors(const CaseView<T, R> &v, hipStream_t s);
   // one sub-step m of an unstructured grid (Eq.(ulbe), Eq.(postcollision2_u)),

@@ -91,12 +91,25 @@ __device__ __forceinline__ void stream_collide_block(const CaseView<T, R> &v, co
   }
 }
 
+template <class T, class R>
+__device__ __forceinline__ void interface_donors_block(const CaseView<T, R> &v, const T *__restrict__ A, int64_t k,
+                                                       int bx);
+
 // banded: workgroups are dealt to the eight XCDs in turn, so give each XCD
 // a contiguous band of rows and the rows a pull shares with its neighbours
-// stay in that XCD's L2 (less HBM traffic, though not less time here)
+// stay in that XCD's L2 (less HBM traffic, though not less time here).
+// ndon (a multiple of 8) leading workgroups compute the grid's interface
+// donors from the same source lattice A instead (they read A only, which
+// the stream-collide does not write), so the small donor pass hides in the
+// HBM-bound one; the lattice workgroups keep their XCD assignment.
 template <class T, class R, int RPT>
-__global__ __launch_bounds__(256) void k_stream_collide(CaseView<T, R> v, int nbx, int nblocks, int banded) {
-  const int b = blockIdx.x;
+__global__ __launch_bounds__(256) void k_stream_collide(CaseView<T, R> v, int nbx, int nblocks, int banded,
+                                                        int ndon) {
+  const int b = (int)blockIdx.x - ndon;
+  if (b < 0) {
+    interface_donors_block<T, R>(v, v.A, *v.dk, blockIdx.x);
+    return;
+  }
   const int t = (banded && nblocks % 8 == 0) ? (b % 8) * (nblocks / 8) + (b / 8) : b;
   stream_collide_block<T, R, RPT>(v, v.A, v.B, v.dk, t % nbx, t / nbx);
 }
@@ -130,17 +143,23 @@ template <class T, class R>
 // runs of rows, so the rows a tile's ring shares with the tiles above and
 // below are fetched into that XCD's L2 once; each XCD starts its run
 // `stagger` tiles further along, so the eight XCDs do not stream from
-// addresses a power of two apart (which share HBM channels).
-__global__ __launch_bounds__(512) void k_stream_collide2(CaseView<T, R> v, int tiles_x, int stagger) {
+// addresses a power of two apart (which share HBM channels). ndon leading
+// workgroups compute the interface donors, as in k_stream_collide.
+__global__ __launch_bounds__(512) void k_stream_collide2(CaseView<T, R> v, int tiles_x, int stagger, int ndon) {
   constexpr int TX = kTwoStepTX, TY = kTwoStepTY, NT = 512, LX = TX + 2, LY = TY + 2, LN = LX * LY;
   constexpr int P1 = (LN + NT - 1) / NT;
   static_assert(TX * TY == NT, "one output node per lane");
   __shared__ R s[9 * LN];
   const int nx = v.nx, ny = v.ny;
   const size_t plane = v.plane;
-  int t = blockIdx.x;
-  if (stagger >= 0 && gridDim.x % 8 == 0) {
-    const int per = gridDim.x / 8, xcd = t % 8, i = t / 8;
+  int t = (int)blockIdx.x - ndon;
+  if (t < 0) {
+    interface_donors_block<T, R>(v, v.A, *v.dk, blockIdx.x);
+    return;
+  }
+  const int ntiles = (int)gridDim.x - ndon;
+  if (stagger >= 0 && ntiles % 8 == 0) {
+    const int per = ntiles / 8, xcd = t % 8, i = t / 8;
     t = xcd * per + (i + xcd * stagger) % per;
   }
   const int tx0 = (t % tiles_x) * TX, ty0 = (t / tiles_x) * TY;
@@ -1424,20 +1443,31 @@ void Kernels<T, R>::fill_rest(T *lat, size_t plane, R *grid, int nnode, hipStrea
   hipLaunchKernelGGL((k_fill_rest<T, R>), dim3(blocks(n, 256)), dim3(256), 0, s, lat, plane, grid, nnode);
 }
 
+// workgroups for the interface donors of a grid in a launch of nt lanes
+// (four lanes per node), rounded up to a multiple of the eight XCDs
+static int donor_groups(int n_iface, int nt) {
+  const int n = (int)blocks((size_t)4 * n_iface, nt);
+  return (n + 7) / 8 * 8;
+}
+
 template <class T, class R>
 void Kernels<T, R>::stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start, hipEvent_t stop,
-                                   int threads, int rows, int order) {
+                                   int threads, int rows, int order, bool donors) {
   const int nt = threads > 0 ? threads : kLatticeThreads, rpt = rows > 0 ? rows : kLatticeRows;
-  if (v.ww <= 0 || v.wh <= 0) return;
+  if (v.ww <= 0 || v.wh <= 0) {
+    if (donors) interface_donors(v, s);
+    return;
+  }
   const int nbx = (int)blocks(v.ww, nt), nblocks = nbx * ((v.wh + rpt - 1) / rpt);
-  const dim3 g(nblocks);
+  const int ndon = donors && v.n_iface > 0 ? donor_groups(v.n_iface, nt) : 0;
+  const dim3 g(nblocks + ndon);
   const int band = order & 1;
 #define HLBM_K1(RPT)                                                                                            \
   if (start) /* events taken by the command processor at the kernel's own start and end */                    \
     hipExtLaunchKernelGGL((k_stream_collide<T, R, RPT>), g, dim3(nt), 0, s, start, stop, 0, v, nbx, nblocks,     \
-                          band);                                                                               \
+                          band, ndon);                                                                         \
   else                                                                                                         \
-    hipLaunchKernelGGL((k_stream_collide<T, R, RPT>), g, dim3(nt), 0, s, v, nbx, nblocks, band)
+    hipLaunchKernelGGL((k_stream_collide<T, R, RPT>), g, dim3(nt), 0, s, v, nbx, nblocks, band, ndon)
   switch (rpt) {
     case 4: HLBM_K1(4); break;
     case 2: HLBM_K1(2); break;
@@ -1448,16 +1478,17 @@ void Kernels<T, R>::stream_collide(const CaseView<T, R> &v, hipStream_t s, hipEv
 
 template <class T, class R>
 void Kernels<T, R>::stream_collide2(const CaseView<T, R> &v, hipStream_t s, hipEvent_t start, hipEvent_t stop,
-                                    int order) {
+                                    int order, bool donors) {
   const int tiles_x = (int)blocks(v.nx, kTwoStepTX), tiles = tiles_x * (int)blocks(v.ny, kTwoStepTY);
   // three tile rows and five tiles: measured on 2048^2 against other offsets
   const int segments = order == 1 ? 3 * tiles_x + 5 : -1;
+  constexpr int nt = kTwoStepTX * kTwoStepTY;
+  const int ndon = donors && v.n_iface > 0 ? donor_groups(v.n_iface, nt) : 0;
   if (start || stop)
-    hipExtLaunchKernelGGL((k_stream_collide2<T, R>), dim3(tiles), dim3(kTwoStepTX * kTwoStepTY), 0, s, start, stop, 0,
-                          v, tiles_x, segments);
+    hipExtLaunchKernelGGL((k_stream_collide2<T, R>), dim3(tiles + ndon), dim3(nt), 0, s, start, stop, 0, v, tiles_x,
+                          segments, ndon);
   else
-    hipLaunchKernelGGL((k_stream_collide2<T, R>), dim3(tiles), dim3(kTwoStepTX * kTwoStepTY), 0, s, v, tiles_x,
-                       segments);
+    hipLaunchKernelGGL((k_stream_collide2<T, R>), dim3(tiles + ndon), dim3(nt), 0, s, v, tiles_x, segments, ndon);
 }
 
 template <class T, class R>
