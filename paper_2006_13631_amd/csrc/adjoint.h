@@ -85,10 +85,10 @@ struct AdjSubScal {
 
 template <class T, class R>
 struct AdjKernels {
-  // recompute f*, f^neq* and the interpolated moments of the interface nodes
-  static void star(const AdjCtx<T, R> &c, hipStream_t s);
-  // refill and force adjoints: Ubn from Ub_next; Z1 and zf
-  static void refill(const AdjCtx<T, R> &c, int slot0, hipStream_t s);
+  // one launch: recompute f*, f^neq* and the interpolated moments of the
+  // interface nodes; refill and force adjoints (Ubn from Ub_next; Z1 and zf,
+  // partial sums from slot0 on)
+  static void star_refill(const AdjCtx<T, R> &c, int slot0, hipStream_t s);
   // sub-steps m_hi, m_hi-1, ..., m_hi-count+1 backwards (count <= 4): per
   // sub-step the wall-velocity adjoint (lamina velocity of that sub-step and
   // its A, omega derivatives in sc, index m_hi - m), then the transposed

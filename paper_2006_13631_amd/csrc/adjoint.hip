@@ -110,8 +110,8 @@ __device__ __forceinline__ void graded_span(const double *v, int n, double lo, d
 
 // ---- star: f*, f^neq* of step k and the interpolated moments ----------------
 template <class T, class R>
-__global__ __launch_bounds__(NG) void k_adj_star(AdjCtx<T, R> c) {
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void adj_star_block(const AdjCtx<T, R> &c, int bx) {
+  const int gt = bx * NG + threadIdx.x;
   const int t = gt >> 2, d = gt & 3;
   const bool valid = t < c.n_iface;
   R acc[12];
@@ -144,8 +144,8 @@ __global__ __launch_bounds__(NG) void k_adj_star(AdjCtx<T, R> c) {
 
 // ---- refill and force adjoint -------------------------------------------------
 template <class T, class R>
-__global__ __launch_bounds__(NG) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
-  const int q = blockIdx.x * NG + threadIdx.x;
+__device__ __forceinline__ void adj_refill_block(const AdjCtx<T, R> &c, int slot0, int bx) {
+  const int q = bx * NG + threadIdx.x;
   const size_t N = (size_t)c.nnode;
   const GridGeom &g = c.gg;
   double pA = 0.0, pW = 0.0, pT = 0.0;
@@ -246,7 +246,16 @@ __global__ __launch_bounds__(NG) void k_adj_refill(AdjCtx<T, R> c, int slot0) {
 #pragma unroll
     for (int s = 0; s < 9; ++s) c.Ubn[s * N + q] = acc[s];
   }
-  block_accum3<NG>(pA, pW, pT, c.part + 3 * (size_t)(slot0 + blockIdx.x));
+  block_accum3<NG>(pA, pW, pT, c.part + 3 * (size_t)(slot0 + bx));
+}
+
+// The star recomputation and the refill adjoint share a launch: neither
+// reads what the other writes (star: f*, f^neq*, moments of the interface
+// nodes from the taped lattice; refill: Z1, zf, Ubn and its partial sums).
+template <class T, class R>
+__global__ __launch_bounds__(NG) void k_adj_star_refill(AdjCtx<T, R> c, int slot0, int nstar) {
+  if ((int)blockIdx.x < nstar) adj_star_block<T, R>(c, blockIdx.x);
+  else adj_refill_block<T, R>(c, slot0, (int)blockIdx.x - nstar);
 }
 
 // ---- one sub-step backwards -----------------------------------------------------
@@ -831,17 +840,14 @@ __global__ void k_set_counter(int64_t *dk, int64_t k) { *dk = k; }
 }  // namespace
 
 template <class T, class R>
-void AdjKernels<T, R>::star(const AdjCtx<T, R> &c, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_star<T, R>), dim3(blocks((size_t)4 * c.n_iface, NG)), dim3(NG), 0, s, c);
+void AdjKernels<T, R>::star_refill(const AdjCtx<T, R> &c, int slot0, hipStream_t s) {
+  const int nstar = (int)blocks((size_t)4 * c.n_iface, NG);
+  hipLaunchKernelGGL((k_adj_star_refill<T, R>), dim3(nstar + refill_slots(c)), dim3(NG), 0, s, c, slot0, nstar);
 }
 
 template <class T, class R>
 int AdjKernels<T, R>::refill_slots(const AdjCtx<T, R> &c) {
   return (int)blocks(c.nnode, NG);
-}
-template <class T, class R>
-void AdjKernels<T, R>::refill(const AdjCtx<T, R> &c, int slot0, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_refill<T, R>), dim3(refill_slots(c)), dim3(NG), 0, s, c, slot0);
 }
 
 template <class T, class R>

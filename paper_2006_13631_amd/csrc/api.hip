@@ -1953,8 +1953,7 @@ class Case final : public CaseBase {
     c.wt = tape_wall(tape, j);
     c.Ub_next = agrid_[gc];
     c.Ubn = agrid_[1 - gc];
-    AK::star(c, s_main_);
-    AK::refill(c, slot_refill_, s_main_);
+    AK::star_refill(c, slot_refill_, s_main_);
     int gin = 1 - gc;  // holds the adjoint of the grid after sub-step m_hi + 1
     for (int m_hi = d_.n - 1; m_hi >= 0; m_hi -= 4) {
       const int count = std::min(4, m_hi + 1);
